@@ -1,0 +1,209 @@
+/* gpa.h -- C-ABI of the MI355X GPA hot-path library (libgpa.so).
+ *
+ * The library implements, as hand-written HIP kernels for gfx950, the
+ * data-parallel hot path of GPA, the instruction-sampling GPU performance
+ * advisor of Zhou, Meng, Sai and Mellor-Crummey:
+ *   - aggregation of PC samples into per-instruction stall-reason counts
+ *     (Sec. 2.1, the "raw PC sampling report" of Sec. 2.3);
+ *   - reaching definitions over each function's CFG with predicates and
+ *     virtual barrier registers (Sec. 4, backward slicing);
+ *   - the instruction blamer: dependency graph, opcode / dominator / latency
+ *     pruning and the apportioning rule Eq. (1) (Sec. 4);
+ *   - the code-optimization estimators of Table 2 with Eqs. (2), (4) and (5),
+ *     rolled up the line -> loop -> function scope tree (Sec. 5).
+ *
+ * Conventions for every call:
+ *   - Return value: GPA_OK (0) or a negative gpa_status; the thread-local
+ *     message of the last failure is returned by gpa_last_error().
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls are
+ *     synchronous with respect to the host unless stated otherwise: on
+ *     return, results are complete and host inputs may be reused.
+ *   - Inputs are borrowed for the duration of the call and copied; handles
+ *     own their device memory until the matching *_free call.  A program is
+ *     read-only after loading and may back any number of blame handles.
+ *   - Copy-out getters write to host buffers; passing NULL for an optional
+ *     buffer skips it.
+ */
+#ifndef GPA_H
+#define GPA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gpa_status;
+#define GPA_OK 0
+#define GPA_E_INVALID (-1)      /* malformed argument or descriptor */
+#define GPA_E_NOMEM (-2)        /* device or host allocation failed */
+#define GPA_E_DEVICE (-3)       /* a HIP runtime call failed */
+#define GPA_E_STATE (-4)        /* handle used with a mismatching program */
+#define GPA_E_UNSUPPORTED (-6)  /* input beyond the limits documented below */
+
+/* ---------------------------------------------------------------------
+ * Encodings shared by inputs and outputs.
+ * ------------------------------------------------------------------- */
+/* opcode classes */
+enum { GPA_OP_ALU = 0, GPA_OP_FP64, GPA_OP_LONG_ALU, GPA_OP_GLOBAL_LOAD, GPA_OP_SHARED_LOAD,
+       GPA_OP_LOCAL_LOAD, GPA_OP_CONST_LOAD, GPA_OP_GLOBAL_STORE, GPA_OP_SHARED_STORE,
+       GPA_OP_LOCAL_STORE, GPA_OP_BRANCH, GPA_OP_BARRIER, GPA_OP_CALL, GPA_N_OP_CLASSES };
+/* stall reasons (Sec. 2.1; the blamed ones are listed in Sec. 4) */
+enum { GPA_ST_SELECTED = 0, GPA_ST_INST_FETCH, GPA_ST_EXEC_DEP, GPA_ST_MEM_DEP, GPA_ST_TEXTURE,
+       GPA_ST_SYNC, GPA_ST_CONST_MEM_DEP, GPA_ST_PIPE_BUSY, GPA_ST_MEM_THROTTLE,
+       GPA_ST_NOT_SELECTED, GPA_ST_OTHER, GPA_ST_SLEEPING, GPA_N_STALLS };
+/* def kinds: register, predicate, write barrier, read barrier (Sec. 4) */
+enum { GPA_DEF_REG = 0, GPA_DEF_PRED, GPA_DEF_WBAR, GPA_DEF_RBAR };
+/* use kinds: operand (carries the instruction's guard), guard read, wait mask */
+enum { GPA_USE_OPND = 0, GPA_USE_GUARD, GPA_USE_WAIT };
+enum { GPA_SCOPE_FUNCTION = 0, GPA_SCOPE_LOOP, GPA_SCOPE_LINE };
+enum { GPA_SF_KERNEL_ENTRY = 1, GPA_SF_DEVICE_FN = 2, GPA_SF_MATH_FN = 4, GPA_SF_HAS_CFG = 8 };
+/* fine classes of blamed stalls (Sec. 4, Fig. 5) */
+enum { GPA_F_MEM_GLOBAL = 0, GPA_F_MEM_LOCAL, GPA_F_MEM_CONST, GPA_F_EXEC_SHARED,
+       GPA_F_EXEC_ARITH, GPA_F_EXEC_WAR, GPA_F_SYNC, GPA_F_OTHER, GPA_N_FINE };
+/* the nine code optimizers of Table 2 */
+enum { GPA_O_REGISTER_REUSE = 0, GPA_O_STRENGTH_REDUCTION, GPA_O_FUNCTION_SPLIT,
+       GPA_O_FAST_MATH, GPA_O_WARP_BALANCE, GPA_O_MEM_TRANSACTION_REDUCTION,
+       GPA_O_LOOP_UNROLLING, GPA_O_CODE_REORDERING, GPA_O_FUNCTION_INLINING, GPA_N_OPT };
+/* edge flags */
+enum { GPA_E_DOM_KEEP = 1, GPA_E_LAT_KEEP = 2, GPA_E_WAR = 4 };
+#define GPA_NONE 0xFFFFFFFFu
+
+/* One PC sample (8 bytes, little endian).  flags bit 0: latency sample
+ * (the warp scheduler issued nothing, Sec. 2.1).  A record with
+ * pc >= n_instr, stall >= 12, any other flag bit or reserved != 0 is not
+ * counted; it is counted as dropped instead. */
+typedef struct {
+  uint32_t pc;
+  uint8_t stall;
+  uint8_t flags;
+  uint16_t reserved;
+} gpa_sample;
+
+/* Architectural features (Sec. 3, static analyzer). */
+typedef struct {
+  uint16_t lat[16];      /* per opcode class: latency in instruction slots (pruning rule 3) */
+  uint16_t allowed[12];  /* per stall reason: bitmask of opcode classes that may cause it (rule 1) */
+  uint16_t blamable;     /* bitmask of stall reasons attributed to source instructions */
+  uint16_t pad;
+} gpa_arch;
+
+/* A program: instructions, basic blocks, one CFG per function, and the
+ * scope tree (Sec. 3, "Control flow graphs" and "Program structure").
+ * All arrays are borrowed for the call.  If on_device != 0 every array
+ * pointer is a device pointer, otherwise a host pointer.
+ *
+ *  locations : [0,n_regs) registers, then n_preds predicates, then n_bars
+ *              virtual barrier registers;
+ *  guard     : 0 = unpredicated ("_"), 1+2k = Pk, 2+2k = !Pk (k < n_preds);
+ *  def/use   : CSR over instructions (def_ptr[n_instr+1] etc.); a location
+ *              appears at most once in an instruction's def list;
+ *  blocks    : block b holds instructions [block_begin[b], block_begin[b+1]),
+ *              block_begin[0] = 0, block_begin[n_blocks] = n_instr, no block
+ *              is empty; successors are a CSR over blocks (succ_ptr, succ);
+ *  functions : function f holds blocks [func_block_begin[f],
+ *              func_block_begin[f+1]); its first block is the entry; every
+ *              successor stays inside its function; func_scope[f] is a
+ *              FUNCTION scope with GPA_SF_HAS_CFG;
+ *  scopes    : numbered in preorder (scope_parent[s] < s, GPA_NONE for a
+ *              root); roots are kernels (FUNCTION with GPA_SF_KERNEL_ENTRY);
+ *              instr_scope[i] is a LINE scope inside func_scope of i's
+ *              function and below no other CFG function.
+ * Limits: n_instr < 2^31, n_preds <= 16, n_regs+n_preds+n_bars <= 1024,
+ * at most 4096 blocks in one function. */
+typedef struct {
+  uint32_t n_instr, n_blocks, n_funcs, n_scopes;
+  uint32_t n_regs, n_preds, n_bars;
+  int32_t on_device;
+  const uint8_t *op_class;         /* [n_instr] */
+  const uint8_t *guard;            /* [n_instr] */
+  const uint32_t *def_ptr;         /* [n_instr+1] */
+  const uint32_t *def_loc;         /* [n_defs] */
+  const uint8_t *def_kind;         /* [n_defs] */
+  const uint32_t *use_ptr;         /* [n_instr+1] */
+  const uint32_t *use_loc;         /* [n_uses] */
+  const uint8_t *use_kind;         /* [n_uses] */
+  const uint32_t *block_begin;     /* [n_blocks+1] */
+  const uint32_t *succ_ptr;        /* [n_blocks+1] */
+  const uint32_t *succ;            /* [n_succ] */
+  const uint32_t *func_block_begin;/* [n_funcs+1] */
+  const uint32_t *func_scope;      /* [n_funcs] */
+  const uint32_t *instr_scope;     /* [n_instr] */
+  const uint32_t *scope_parent;    /* [n_scopes] */
+  const uint8_t *scope_kind;       /* [n_scopes] */
+  const uint8_t *scope_flags;      /* [n_scopes] */
+  gpa_arch arch;
+} gpa_program_desc;
+
+typedef struct gpa_program gpa_program;
+typedef struct gpa_blame gpa_blame;
+typedef struct gpa_advice gpa_advice;
+
+typedef struct {
+  uint64_t n_instr, n_blocks, n_funcs, n_scopes, n_defs, n_uses;
+  uint64_t n_rd;       /* total size of the per-use source lists */
+  uint64_t n_edges;    /* dependency-graph edges (i, j) */
+  uint32_t n_blamable; /* popcount(arch.blamable) */
+  uint32_t pad;
+} gpa_program_info;
+
+/* Load a program and build its static analysis on the device: reaching
+ * definitions per use site with and without the use-blocked variant
+ * (dominator pruning, Sec. 4 rule 2), the dependency-graph edges (Sec. 4,
+ * Fig. 4b) with their flags, the shortest and longest instruction distance
+ * of every edge (rules 2 and 3, heuristic 2), and the static target scopes
+ * used by the estimators.  Errors: GPA_E_INVALID on a malformed descriptor
+ * (details in gpa_last_error), GPA_E_UNSUPPORTED beyond the limits. */
+gpa_status gpa_load_program(const gpa_program_desc *desc, void *stream, gpa_program **out);
+void gpa_program_free(gpa_program *p);
+gpa_status gpa_program_get_info(const gpa_program *p, gpa_program_info *info);
+
+/* Per use site (in def/use CSR order) the sorted source instructions:
+ * rd_ptr[n_uses+1], rd_src[n_rd], rd_blocked[n_rd] (1 if the source also
+ * survives the use-blocked search). */
+gpa_status gpa_program_rd(const gpa_program *p, uint32_t *rd_ptr, uint32_t *rd_src,
+                          uint8_t *rd_blocked);
+/* Edges sorted by (dst, src): src, dst, flags (GPA_E_*), dmin, dmax [n_edges]. */
+gpa_status gpa_program_edges(const gpa_program *p, uint32_t *src, uint32_t *dst, uint8_t *flags,
+                             uint32_t *dmin, uint32_t *dmax);
+
+/* Attribute one profile (one kernel launch context, Sec. 3) of n samples.
+ * samples_on_device != 0: `samples` is a device pointer that must stay
+ * valid until the call returns.  Counts the samples (Sec. 2.1) and runs
+ * the instruction blamer (Sec. 4, Eq. 1). */
+gpa_status gpa_attribute(gpa_program *p, const gpa_sample *samples, uint64_t n,
+                         int samples_on_device, void *stream, gpa_blame **out);
+void gpa_blame_free(gpa_blame *b);
+/* counts[n_instr*24] (index (pc*12+stall)*2+latency); totals[4] =
+ * {valid samples, latency samples, dropped records, 0}. */
+gpa_status gpa_blame_counts(const gpa_blame *b, uint32_t *counts, uint64_t *totals);
+/* Per edge, per blamable reason (ascending) and latency bit: the share of
+ * the destination's samples attributed along the edge, Eq. (1).
+ * share[n_edges * n_blamable * 2]. */
+gpa_status gpa_blame_shares(const gpa_blame *b, double *share);
+/* blamed[n_instr*24]: samples attributed to i as a source; self_[n_instr*24]:
+ * samples kept by the sampled instruction; fine[n_instr*GPA_N_FINE*2]. */
+gpa_status gpa_blame_table(const gpa_blame *b, double *blamed, double *self_, double *fine);
+
+/* Estimate the speedup of each code optimizer at each scope: Eq. (2) for
+ * stall elimination, Eq. (5) for latency hiding (Eq. (4) at a kernel). */
+gpa_status gpa_advise(const gpa_blame *b, void *stream, gpa_advice **out);
+void gpa_advice_free(gpa_advice *a);
+/* active[n_scopes], matched[n_scopes*9], speedup[n_scopes*9],
+ * kernel_T / kernel_L [n_scopes] (set at roots, 0 elsewhere),
+ * eq3[n_scopes*3] (kernel-level Eq. (3) for the three hiding optimizers). */
+gpa_status gpa_advice_get(const gpa_advice *a, double *active, double *matched, double *speedup,
+                          double *kernel_T, double *kernel_L, double *eq3);
+/* Top-k (k <= 16) per kernel root, speedup descending then optimizer then
+ * scope ascending: arrays of n_scopes*k, GPA_NONE padded, indexed by root. */
+gpa_status gpa_advice_topk(const gpa_advice *a, uint32_t k, uint32_t *opt, uint32_t *scope,
+                           double *speedup);
+
+/* Thread-local description of the last failure on this thread. */
+const char *gpa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,418 @@
+// The C-ABI entry points of libgpa (declared in include/gpa.h): argument
+// checks, descriptor upload, the order of the device steps, copy-out.
+#include <cstdarg>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <unordered_map>
+
+#include "common.h"
+
+namespace gpa {
+
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...) {
+  char buf[2048];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+void fail(gpa_status code, const char *fmt, ...) {
+  char buf[2048];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  throw Error{code};
+}
+
+// ------------------------------------------------------------------ pool
+namespace {
+std::mutex g_mu;
+std::map<size_t, std::vector<void *>> g_free;   // size class -> cached blocks
+std::unordered_map<void *, size_t> g_class;     // block -> size class
+
+size_t size_class(size_t b) {
+  if (b <= 4096) return 4096;
+  if (b <= (size_t)1 << 24) {
+    size_t r = 4096;
+    while (r < b) r <<= 1;
+    return r;
+  }
+  const size_t mb = (size_t)1 << 20;
+  return (b + mb - 1) / mb * mb;
+}
+
+void release_cached_locked() {
+  for (auto &kv : g_free)
+    for (void *p : kv.second) {
+      (void)hipFree(p);
+      g_class.erase(p);
+    }
+  g_free.clear();
+}
+}  // namespace
+
+void *dev_alloc(size_t bytes) {
+  const size_t c = size_class(bytes);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_free.find(c);
+  if (it != g_free.end() && !it->second.empty()) {
+    void *p = it->second.back();
+    it->second.pop_back();
+    return p;
+  }
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, c);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    release_cached_locked();
+    e = hipMalloc(&p, c);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("device allocation of %zu bytes failed: %s", c, hipGetErrorString(e));
+    throw Error{GPA_E_NOMEM};
+  }
+  g_class[p] = c;
+  return p;
+}
+
+void dev_free(void *p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_class.find(p);
+  if (it == g_class.end()) return;
+  g_free[it->second].push_back(p);
+}
+
+template <typename T>
+static void upload(DBuf<T> &dst, const T *src, size_t n, bool on_device, hipStream_t s) {
+  dst.alloc(n);
+  if (n == 0) return;
+  if (!src) fail(GPA_E_INVALID, "a descriptor array is NULL");
+  GPA_HIP(hipMemcpyAsync(dst.p, src, n * sizeof(T),
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+}
+
+static uint32_t read_u32(const uint32_t *p, bool on_device, hipStream_t s) {
+  if (!p) fail(GPA_E_INVALID, "a descriptor array is NULL");
+  if (!on_device) return *p;
+  uint32_t v = 0;
+  GPA_HIP(hipMemcpyAsync(&v, p, 4, hipMemcpyDeviceToHost, s));
+  GPA_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+template <typename F>
+static gpa_status guarded(F &&body) {
+  try {
+    body();
+    return GPA_OK;
+  } catch (const Error &e) {
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    set_error("host allocation failed");
+    return GPA_E_NOMEM;
+  } catch (...) {
+    set_error("unexpected failure");
+    return GPA_E_DEVICE;
+  }
+}
+
+template <typename T>
+static void copy_out(T *host, const DBuf<T> &src, size_t n, hipStream_t s) {
+  if (!host || n == 0) return;
+  GPA_HIP(hipMemcpyAsync(host, src.p, n * sizeof(T), hipMemcpyDeviceToHost, s));
+}
+
+}  // namespace gpa
+
+using namespace gpa;
+
+extern "C" {
+
+const char *gpa_last_error(void) { return g_err.c_str(); }
+
+gpa_status gpa_load_program(const gpa_program_desc *d, void *stream, gpa_program **out) {
+  if (!d || !out) {
+    set_error("gpa_load_program: NULL argument");
+    return GPA_E_INVALID;
+  }
+  *out = nullptr;
+  gpa_program *p = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  gpa_status st = guarded([&] {
+    if (d->n_instr == 0 || d->n_blocks == 0 || d->n_funcs == 0 || d->n_scopes == 0)
+      fail(GPA_E_INVALID, "empty program: n_instr, n_blocks, n_funcs and n_scopes must be > 0");
+    if (d->n_instr >= 0x80000000u) fail(GPA_E_UNSUPPORTED, "n_instr must be below 2^31");
+    if (d->n_preds > 16) fail(GPA_E_UNSUPPORTED, "n_preds must be at most 16");
+    const uint64_t n_loc = (uint64_t)d->n_regs + d->n_preds + d->n_bars;
+    if (n_loc == 0 || n_loc > 1024)
+      fail(GPA_E_UNSUPPORTED, "n_regs + n_preds + n_bars must be in [1, 1024]");
+    if (d->arch.blamable & ~0xFFFu) fail(GPA_E_INVALID, "arch.blamable has bits above 11");
+    if (d->n_blocks > d->n_instr) fail(GPA_E_INVALID, "more blocks than instructions");
+    if (d->n_funcs > d->n_blocks) fail(GPA_E_INVALID, "more functions than blocks");
+    const bool dev = d->on_device != 0;
+    p = new gpa_program();
+    p->n_instr = d->n_instr;
+    p->n_blocks = d->n_blocks;
+    p->n_funcs = d->n_funcs;
+    p->n_scopes = d->n_scopes;
+    p->n_regs = d->n_regs;
+    p->n_preds = d->n_preds;
+    p->n_bars = d->n_bars;
+    p->n_loc = (uint32_t)n_loc;
+    p->arch = d->arch;
+    p->n_blamable = (uint32_t)__builtin_popcount(d->arch.blamable & 0xFFFu);
+    p->n_defs = read_u32(d->def_ptr + d->n_instr, dev, s);
+    p->n_uses = read_u32(d->use_ptr + d->n_instr, dev, s);
+    p->n_succ = read_u32(d->succ_ptr + d->n_blocks, dev, s);
+    const uint32_t n = p->n_instr, nb = p->n_blocks;
+    upload(p->op_class, d->op_class, n, dev, s);
+    upload(p->guard, d->guard, n, dev, s);
+    upload(p->def_ptr, d->def_ptr, (size_t)n + 1, dev, s);
+    upload(p->def_loc, d->def_loc, p->n_defs, dev, s);
+    upload(p->def_kind, d->def_kind, p->n_defs, dev, s);
+    upload(p->use_ptr, d->use_ptr, (size_t)n + 1, dev, s);
+    upload(p->use_loc, d->use_loc, p->n_uses, dev, s);
+    upload(p->use_kind, d->use_kind, p->n_uses, dev, s);
+    upload(p->block_begin, d->block_begin, (size_t)nb + 1, dev, s);
+    upload(p->succ_ptr, d->succ_ptr, (size_t)nb + 1, dev, s);
+    upload(p->succ, d->succ, p->n_succ, dev, s);
+    upload(p->func_block_begin, d->func_block_begin, (size_t)p->n_funcs + 1, dev, s);
+    upload(p->func_scope, d->func_scope, p->n_funcs, dev, s);
+    upload(p->instr_scope, d->instr_scope, n, dev, s);
+    upload(p->scope_parent, d->scope_parent, p->n_scopes, dev, s);
+    upload(p->scope_kind, d->scope_kind, p->n_scopes, dev, s);
+    upload(p->scope_flags, d->scope_flags, p->n_scopes, dev, s);
+    Arena ar;
+    validate_and_build_structure(*p, s, ar);
+    build_reaching_defs(*p, s, ar);
+    build_edges(*p, s, ar);
+    build_distances(*p, s, ar);
+    build_scope_targets(*p, s, ar);
+    GPA_HIP(hipStreamSynchronize(s));
+  });
+  if (st != GPA_OK) {
+    if (s) (void)hipStreamSynchronize(s);
+    else (void)hipDeviceSynchronize();
+    delete p;
+    return st;
+  }
+  p->stream = s;
+  *out = p;
+  return GPA_OK;
+}
+
+void gpa_program_free(gpa_program *p) { delete p; }
+
+gpa_status gpa_program_get_info(const gpa_program *p, gpa_program_info *info) {
+  if (!p || !info) {
+    set_error("gpa_program_get_info: NULL argument");
+    return GPA_E_INVALID;
+  }
+  info->n_instr = p->n_instr;
+  info->n_blocks = p->n_blocks;
+  info->n_funcs = p->n_funcs;
+  info->n_scopes = p->n_scopes;
+  info->n_defs = p->n_defs;
+  info->n_uses = p->n_uses;
+  info->n_rd = p->n_rd;
+  info->n_edges = p->n_edges;
+  info->n_blamable = p->n_blamable;
+  info->pad = 0;
+  return GPA_OK;
+}
+
+gpa_status gpa_program_rd(const gpa_program *p, uint32_t *rd_ptr, uint32_t *rd_src,
+                          uint8_t *rd_blocked) {
+  if (!p) {
+    set_error("gpa_program_rd: NULL program");
+    return GPA_E_INVALID;
+  }
+  return guarded([&] {
+    hipStream_t s = nullptr;
+    copy_out(rd_ptr, p->rd_ptr, (size_t)p->n_uses + 1, s);
+    copy_out(rd_src, p->rd_src, p->n_rd, s);
+    copy_out(rd_blocked, p->rd_blk, p->n_rd, s);
+    GPA_HIP(hipStreamSynchronize(s));
+  });
+}
+
+gpa_status gpa_program_edges(const gpa_program *p, uint32_t *src, uint32_t *dst, uint8_t *flags,
+                             uint32_t *dmin, uint32_t *dmax) {
+  if (!p) {
+    set_error("gpa_program_edges: NULL program");
+    return GPA_E_INVALID;
+  }
+  return guarded([&] {
+    hipStream_t s = nullptr;
+    copy_out(src, p->e_src, p->n_edges, s);
+    copy_out(dst, p->e_dst, p->n_edges, s);
+    copy_out(flags, p->e_flags, p->n_edges, s);
+    copy_out(dmin, p->e_dmin, p->n_edges, s);
+    copy_out(dmax, p->e_dmax, p->n_edges, s);
+    GPA_HIP(hipStreamSynchronize(s));
+  });
+}
+
+gpa_status gpa_attribute(gpa_program *p, const gpa_sample *samples, uint64_t n,
+                         int samples_on_device, void *stream, gpa_blame **out) {
+  if (!p || !out || (n && !samples)) {
+    set_error("gpa_attribute: NULL argument");
+    return GPA_E_INVALID;
+  }
+  *out = nullptr;
+  gpa_blame *b = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  gpa_status st = guarded([&] {
+    b = new gpa_blame();
+    b->prog = p;
+    Arena ar;
+    const gpa_sample *dsamp = samples;
+    if (n && !samples_on_device) {
+      gpa_sample *tmp = ar.get<gpa_sample>(n);
+      GPA_HIP(hipMemcpyAsync(tmp, samples, n * sizeof(gpa_sample), hipMemcpyHostToDevice, s));
+      dsamp = tmp;
+    }
+    b->counts.alloc((size_t)p->n_instr * 24);
+    b->dtotals.alloc(4);
+    run_hist(*p, dsamp, n, b->counts.p, b->dtotals.p, s, ar);
+    run_blame(*p, *b, s, ar);
+    GPA_HIP(hipMemcpyAsync(b->totals, b->dtotals.p, sizeof(b->totals), hipMemcpyDeviceToHost, s));
+    GPA_HIP(hipStreamSynchronize(s));
+  });
+  if (st != GPA_OK) {
+    if (s) (void)hipStreamSynchronize(s);
+    else (void)hipDeviceSynchronize();
+    delete b;
+    return st;
+  }
+  *out = b;
+  return GPA_OK;
+}
+
+void gpa_blame_free(gpa_blame *b) { delete b; }
+
+gpa_status gpa_blame_counts(const gpa_blame *b, uint32_t *counts, uint64_t *totals) {
+  if (!b) {
+    set_error("gpa_blame_counts: NULL blame");
+    return GPA_E_INVALID;
+  }
+  return guarded([&] {
+    hipStream_t s = nullptr;
+    copy_out(counts, b->counts, (size_t)b->prog->n_instr * 24, s);
+    if (totals) memcpy(totals, b->totals, sizeof(b->totals));
+    GPA_HIP(hipStreamSynchronize(s));
+  });
+}
+
+gpa_status gpa_blame_shares(const gpa_blame *b, double *share) {
+  if (!b) {
+    set_error("gpa_blame_shares: NULL blame");
+    return GPA_E_INVALID;
+  }
+  return guarded([&] {
+    hipStream_t s = nullptr;
+    copy_out(share, b->share, b->prog->n_edges * b->prog->n_blamable * 2, s);
+    GPA_HIP(hipStreamSynchronize(s));
+  });
+}
+
+gpa_status gpa_blame_table(const gpa_blame *b, double *blamed, double *self_, double *fine) {
+  if (!b) {
+    set_error("gpa_blame_table: NULL blame");
+    return GPA_E_INVALID;
+  }
+  return guarded([&] {
+    hipStream_t s = nullptr;
+    const size_t n = b->prog->n_instr;
+    copy_out(blamed, b->blamed, n * 24, s);
+    copy_out(self_, b->self_, n * 24, s);
+    copy_out(fine, b->fine, n * GPA_N_FINE * 2, s);
+    GPA_HIP(hipStreamSynchronize(s));
+  });
+}
+
+gpa_status gpa_advise(const gpa_blame *b, void *stream, gpa_advice **out) {
+  if (!b || !out) {
+    set_error("gpa_advise: NULL argument");
+    return GPA_E_INVALID;
+  }
+  *out = nullptr;
+  gpa_advice *a = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  gpa_status st = guarded([&] {
+    a = new gpa_advice();
+    a->prog = b->prog;
+    Arena ar;
+    run_estimate(*b->prog, *b, *a, 16, s, ar);
+    GPA_HIP(hipStreamSynchronize(s));
+  });
+  if (st != GPA_OK) {
+    if (s) (void)hipStreamSynchronize(s);
+    else (void)hipDeviceSynchronize();
+    delete a;
+    return st;
+  }
+  *out = a;
+  return GPA_OK;
+}
+
+void gpa_advice_free(gpa_advice *a) { delete a; }
+
+gpa_status gpa_advice_get(const gpa_advice *a, double *active, double *matched, double *speedup,
+                          double *kernel_T, double *kernel_L, double *eq3) {
+  if (!a) {
+    set_error("gpa_advice_get: NULL advice");
+    return GPA_E_INVALID;
+  }
+  return guarded([&] {
+    hipStream_t s = nullptr;
+    const size_t ns = a->prog->n_scopes;
+    copy_out(active, a->active, ns, s);
+    copy_out(matched, a->matched, ns * GPA_N_OPT, s);
+    copy_out(speedup, a->speedup, ns * GPA_N_OPT, s);
+    copy_out(kernel_T, a->kernel_T, ns, s);
+    copy_out(kernel_L, a->kernel_L, ns, s);
+    copy_out(eq3, a->eq3, ns * 3, s);
+    GPA_HIP(hipStreamSynchronize(s));
+  });
+}
+
+gpa_status gpa_advice_topk(const gpa_advice *a, uint32_t k, uint32_t *opt, uint32_t *scope,
+                           double *speedup) {
+  if (!a) {
+    set_error("gpa_advice_topk: NULL advice");
+    return GPA_E_INVALID;
+  }
+  if (k == 0 || k > a->k) {
+    set_error("gpa_advice_topk: k must be in [1, %u]", a->k);
+    return GPA_E_INVALID;
+  }
+  return guarded([&] {
+    hipStream_t s = nullptr;
+    const size_t ns = a->prog->n_scopes;
+    std::vector<uint32_t> o(ns * a->k), sc(ns * a->k);
+    std::vector<double> sp(ns * a->k);
+    GPA_HIP(hipMemcpyAsync(o.data(), a->top_opt.p, 4 * o.size(), hipMemcpyDeviceToHost, s));
+    GPA_HIP(hipMemcpyAsync(sc.data(), a->top_scope.p, 4 * sc.size(), hipMemcpyDeviceToHost, s));
+    GPA_HIP(hipMemcpyAsync(sp.data(), a->top_speed.p, 8 * sp.size(), hipMemcpyDeviceToHost, s));
+    GPA_HIP(hipStreamSynchronize(s));
+    for (size_t r = 0; r < ns; ++r)
+      for (uint32_t t = 0; t < k; ++t) {
+        if (opt) opt[r * k + t] = o[r * a->k + t];
+        if (scope) scope[r * k + t] = sc[r * a->k + t];
+        if (speedup) speedup[r * k + t] = sp[r * a->k + t];
+      }
+  });
+}
+
+}  // extern "C"

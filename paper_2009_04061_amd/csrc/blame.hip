@@ -1,0 +1,173 @@
+// The instruction blamer's attribution step (Sec. 4, "Attribute stalls").
+//
+// For a sampled instruction j, a blamable reason r and a latency bit l with
+// S = C[j][r][l] > 0, the candidates are j's incoming edges that survived
+// dominator and latency pruning and whose source opcode class may cause r
+// (opcode pruning).  Eq. (1) splits S over them with weights
+//   R_issue(i) * R_path(i)  ~  issued(i) / (dmax(i, j) + 1)
+// (more issued samples, more blame; longer longest path, less blame); when
+// no candidate issued anything the path term alone decides.  Without a
+// candidate the samples stay on j, as do all samples of other reasons; the
+// rule applies the same way to latency samples.
+//
+// k_blame_dst owns one destination and writes its edges' shares; k_blame_src
+// owns one source and sums its outgoing shares in edge order, so every FP64
+// sum has a fixed order and no floating-point atomics are used.
+#include "common.h"
+#include "devutil.h"
+
+namespace gpa {
+
+struct ArchDev {
+  uint16_t allowed[12];
+  uint16_t blamable;
+  uint16_t pad;
+};
+
+__global__ void k_blame_dst(uint32_t n_instr, uint32_t nbl, ArchDev arch, const uint32_t *counts,
+                            const uint32_t *in_ptr, const uint32_t *e_src, const uint8_t *e_flags,
+                            const uint32_t *e_dmax, const uint8_t *op_class, double *share,
+                            double *self_) {
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_instr;
+       j += gridDim.x * blockDim.x) {
+    const uint32_t *C = counts + (size_t)j * 24;
+    const uint32_t e0 = in_ptr[j], e1 = in_ptr[j + 1];
+    for (uint32_t e = e0; e < e1; ++e)
+      for (uint32_t q = 0; q < 2 * nbl; ++q) share[(size_t)e * 2 * nbl + q] = 0.0;
+    for (uint32_t r = 0; r < 12; ++r) {
+      for (uint32_t l = 0; l < 2; ++l) {
+        const uint32_t S = C[r * 2 + l];
+        double kept = 0.0;
+        if (S != 0) {
+          if (!((arch.blamable >> r) & 1u)) {
+            kept = (double)S;
+          } else {
+            const uint32_t slot = __popc((uint32_t)arch.blamable & ((1u << r) - 1u));
+            double W = 0.0;
+            uint32_t ncand = 0;
+            for (uint32_t e = e0; e < e1; ++e) {
+              const uint32_t i = e_src[e];
+              const uint8_t fl = e_flags[e];
+              if (!(fl & GPA_E_DOM_KEEP) || !(fl & GPA_E_LAT_KEEP)) continue;
+              if (!((arch.allowed[r] >> op_class[i]) & 1u)) continue;
+              ++ncand;
+              const double issued = (double)counts[(size_t)i * 24] + (double)counts[(size_t)i * 24 + 1];
+              W += issued / ((double)e_dmax[e] + 1.0);
+            }
+            if (ncand == 0) {
+              kept = (double)S;
+            } else {
+              const bool by_path = (W == 0.0);
+              if (by_path) {
+                for (uint32_t e = e0; e < e1; ++e) {
+                  const uint32_t i = e_src[e];
+                  const uint8_t fl = e_flags[e];
+                  if (!(fl & GPA_E_DOM_KEEP) || !(fl & GPA_E_LAT_KEEP)) continue;
+                  if (!((arch.allowed[r] >> op_class[i]) & 1u)) continue;
+                  W += 1.0 / ((double)e_dmax[e] + 1.0);
+                }
+              }
+              for (uint32_t e = e0; e < e1; ++e) {
+                const uint32_t i = e_src[e];
+                const uint8_t fl = e_flags[e];
+                if (!(fl & GPA_E_DOM_KEEP) || !(fl & GPA_E_LAT_KEEP)) continue;
+                if (!((arch.allowed[r] >> op_class[i]) & 1u)) continue;
+                const double issued = (double)counts[(size_t)i * 24] + (double)counts[(size_t)i * 24 + 1];
+                const double w = by_path ? 1.0 / ((double)e_dmax[e] + 1.0)
+                                         : issued / ((double)e_dmax[e] + 1.0);
+                share[((size_t)e * nbl + slot) * 2 + l] = (double)S * w / W;
+              }
+            }
+          }
+        }
+        self_[(size_t)j * 24 + r * 2 + l] = kept;
+      }
+    }
+  }
+}
+
+// Sums in edge order; the fine class of a memory dependency or a non-WAR
+// execution dependency depends only on the source's opcode class, so each
+// fine class is one accumulator (no run-time indexing of private arrays).
+__global__ void k_blame_src(uint32_t n_instr, uint32_t nbl, uint32_t blamable,
+                            const uint32_t *out_ptr, const uint32_t *out_perm,
+                            const uint8_t *e_flags, const uint8_t *op_class, const double *share,
+                            double *blamed, double *fine) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_instr;
+       i += gridDim.x * blockDim.x) {
+    double acc[24];
+#pragma unroll
+    for (int q = 0; q < 24; ++q) acc[q] = 0.0;
+    double war0 = 0.0, war1 = 0.0, nwar0 = 0.0, nwar1 = 0.0, oth0 = 0.0, oth1 = 0.0;
+    const uint32_t cls = op_class[i];
+    for (uint32_t k = out_ptr[i]; k < out_ptr[i + 1]; ++k) {
+      const uint32_t e = out_perm[k];
+      const bool war = (e_flags[e] & GPA_E_WAR) != 0;
+      uint32_t slot = 0;
+#pragma unroll
+      for (uint32_t r = 0; r < 12; ++r) {
+        if (!((blamable >> r) & 1u)) continue;
+        const double s0 = share[((size_t)e * nbl + slot) * 2];
+        const double s1 = share[((size_t)e * nbl + slot) * 2 + 1];
+        acc[r * 2] += s0;
+        acc[r * 2 + 1] += s1;
+        if (r == GPA_ST_EXEC_DEP) {
+          if (war) {
+            war0 += s0;
+            war1 += s1;
+          } else {
+            nwar0 += s0;
+            nwar1 += s1;
+          }
+        } else if (r != GPA_ST_MEM_DEP && r != GPA_ST_SYNC) {
+          oth0 += s0;
+          oth1 += s1;
+        }
+        ++slot;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 24; ++q) blamed[(size_t)i * 24 + q] = acc[q];
+    const uint32_t fm = (cls == GPA_OP_LOCAL_LOAD || cls == GPA_OP_LOCAL_STORE) ? GPA_F_MEM_LOCAL
+                        : (cls == GPA_OP_CONST_LOAD)                           ? GPA_F_MEM_CONST
+                                                                               : GPA_F_MEM_GLOBAL;
+    const uint32_t fx = (cls == GPA_OP_SHARED_LOAD) ? GPA_F_EXEC_SHARED : GPA_F_EXEC_ARITH;
+    double *dst = fine + (size_t)i * GPA_N_FINE * 2;
+#pragma unroll
+    for (int q = 0; q < GPA_N_FINE * 2; ++q) dst[q] = 0.0;
+    dst[fm * 2] = acc[GPA_ST_MEM_DEP * 2];
+    dst[fm * 2 + 1] = acc[GPA_ST_MEM_DEP * 2 + 1];
+    dst[GPA_F_EXEC_WAR * 2] = war0;
+    dst[GPA_F_EXEC_WAR * 2 + 1] = war1;
+    dst[fx * 2] = nwar0;
+    dst[fx * 2 + 1] = nwar1;
+    dst[GPA_F_SYNC * 2] = acc[GPA_ST_SYNC * 2];
+    dst[GPA_F_SYNC * 2 + 1] = acc[GPA_ST_SYNC * 2 + 1];
+    dst[GPA_F_OTHER * 2] = oth0;
+    dst[GPA_F_OTHER * 2 + 1] = oth1;
+  }
+}
+
+void run_blame(const gpa_program &p, gpa_blame &b, hipStream_t s, Arena &ar) {
+  (void)ar;
+  const uint32_t n = p.n_instr;
+  const uint32_t nbl = p.n_blamable;
+  b.share.alloc(p.n_edges * nbl * 2);
+  b.blamed.alloc((size_t)n * 24);
+  b.self_.alloc((size_t)n * 24);
+  b.fine.alloc((size_t)n * GPA_N_FINE * 2);
+  ArchDev a;
+  for (int r = 0; r < 12; ++r) a.allowed[r] = p.arch.allowed[r];
+  a.blamable = p.arch.blamable;
+  a.pad = 0;
+  hipLaunchKernelGGL(k_blame_dst, dim3(grid_for(n, 128, 8192)), dim3(128), 0, s, n, nbl, a,
+                     b.counts.p, p.in_ptr.p, p.e_src.p, p.e_flags.p, p.e_dmax.p, p.op_class.p,
+                     b.share.p, b.self_.p);
+  GPA_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_blame_src, dim3(grid_for(n, 128, 8192)), dim3(128), 0, s, n, nbl,
+                     (uint32_t)p.arch.blamable, p.out_ptr.p, p.out_perm.p, p.e_flags.p,
+                     p.op_class.p, b.share.p, b.blamed.p, b.fine.p);
+  GPA_LAUNCH_CHECK();
+}
+
+}  // namespace gpa

@@ -1,0 +1,187 @@
+// Internal declarations of libgpa: handle layouts, error reporting, the
+// device memory pool and the launch helpers shared by the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/gpa.h"
+
+namespace gpa {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char *fmt, ...);
+
+struct Error {
+  gpa_status code;
+};
+
+#define GPA_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      ::gpa::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),      \
+                       __FILE__, __LINE__);                                        \
+      throw ::gpa::Error{e_ == hipErrorOutOfMemory ? GPA_E_NOMEM : GPA_E_DEVICE};  \
+    }                                                                              \
+  } while (0)
+
+#define GPA_LAUNCH_CHECK() GPA_HIP(hipGetLastError())
+
+[[noreturn]] void fail(gpa_status code, const char *fmt, ...);
+
+// ------------------------------------------------------------ device memory
+// A caching allocator: freed blocks go back to a per-size-class free list and
+// are reused by later allocations; nothing is returned to the runtime before
+// process exit.  Blocks are 256-byte aligned.
+void *dev_alloc(size_t bytes);
+void dev_free(void *p);
+
+template <typename T>
+struct DBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+  ~DBuf() { release(); }
+  void alloc(size_t count) {
+    release();
+    n = count;
+    p = static_cast<T *>(dev_alloc((count ? count : 1) * sizeof(T)));
+  }
+  void release() {
+    if (p) dev_free(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+// Per-call scratch: every block is returned to the pool when the arena is
+// destroyed, which the API calls do only after synchronizing their stream.
+struct Arena {
+  std::vector<void *> blocks;
+  Arena() = default;
+  Arena(const Arena &) = delete;
+  Arena &operator=(const Arena &) = delete;
+  ~Arena() {
+    for (void *b : blocks) dev_free(b);
+  }
+  template <typename T>
+  T *get(size_t count) {
+    void *b = dev_alloc((count ? count : 1) * sizeof(T));
+    blocks.push_back(b);
+    return static_cast<T *>(b);
+  }
+};
+
+// ------------------------------------------------------------------ handles
+}  // namespace gpa
+
+struct gpa_program {
+  // sizes
+  uint32_t n_instr = 0, n_blocks = 0, n_funcs = 0, n_scopes = 0;
+  uint32_t n_regs = 0, n_preds = 0, n_bars = 0, n_loc = 0;
+  uint32_t n_defs = 0, n_uses = 0, n_succ = 0;
+  uint32_t max_func_blocks = 0;
+  gpa_arch arch{};
+  uint32_t n_blamable = 0;
+  // device copies of the descriptor
+  gpa::DBuf<uint8_t> op_class, guard, def_kind, use_kind, scope_kind, scope_flags;
+  gpa::DBuf<uint32_t> def_ptr, def_loc, use_ptr, use_loc, block_begin, succ_ptr, succ;
+  gpa::DBuf<uint32_t> func_block_begin, func_scope, instr_scope, scope_parent;
+  // derived structure
+  gpa::DBuf<uint32_t> block_of, func_of_block, pred_ptr, pred;
+  gpa::DBuf<uint32_t> def_site_sorted, fl_def_ptr;   // def sites by (function, location, instr)
+  gpa::DBuf<uint32_t> use_site_sorted, fl_use_ptr;   // use sites by (function, location, instr)
+  gpa::DBuf<uint32_t> def_instr, use_instr;          // site -> instruction
+  gpa::DBuf<uint32_t> def_rank, use_rank;            // site -> position in the sorted array
+  gpa::DBuf<uint64_t> fl_def_guards;                 // (function, location) -> guards on defs
+  gpa::DBuf<uint8_t> use_cond;                       // use site -> effective condition
+  // reaching definitions
+  uint64_t n_rd = 0;
+  gpa::DBuf<uint32_t> rd_ptr, rd_src;
+  gpa::DBuf<uint8_t> rd_blk, rd_nonrbar;
+  // dependency graph
+  uint64_t n_edges = 0;
+  gpa::DBuf<uint32_t> in_ptr;                  // [n_instr+1] edges into j
+  gpa::DBuf<uint32_t> e_src, e_dst, e_dmin, e_dmax;
+  gpa::DBuf<uint8_t> e_flags;
+  gpa::DBuf<uint32_t> out_ptr, out_perm;       // edges by source instruction
+  gpa::DBuf<uint32_t> rpo_pos, rpo_order;      // per block: topological position in G'
+  gpa::DBuf<uint8_t> retreat;                  // per successor edge
+  // scope structure for the estimators
+  gpa::DBuf<uint32_t> scope_end, root_of, scope_depth;
+  gpa::DBuf<uint32_t> e_lca, e_icl;            // per edge target scopes
+  gpa::DBuf<uint8_t> instr_tags;               // bit0 in math fn, bit1 in device fn with CFG
+  gpa::DBuf<uint32_t> lca_ptr, lca_perm, icl_ptr, icl_perm, line_ptr, line_perm;
+  gpa::DBuf<uint32_t> roots;                   // kernel root scope ids
+  uint32_t n_roots = 0;
+  hipStream_t stream = nullptr;
+};
+
+struct gpa_blame {
+  const gpa_program *prog = nullptr;
+  uint64_t totals[4] = {0, 0, 0, 0};
+  gpa::DBuf<uint32_t> counts;          // [n_instr*24]
+  gpa::DBuf<unsigned long long> dtotals;
+  gpa::DBuf<double> share;             // [n_edges*n_blamable*2]
+  gpa::DBuf<double> blamed, self_;     // [n_instr*24]
+  gpa::DBuf<double> fine;              // [n_instr*GPA_N_FINE*2]
+};
+
+struct gpa_advice {
+  const gpa_program *prog = nullptr;
+  gpa::DBuf<double> active, matched, speedup, kernel_T, kernel_L, eq3;
+  gpa::DBuf<uint32_t> top_opt, top_scope;
+  gpa::DBuf<double> top_speed;
+  uint32_t k = 0;
+};
+
+namespace gpa {
+
+// ------------------------------------------------------------ device steps
+// scan.hip: exclusive prefix sum of n u32 values into out (out may alias
+// in); returns the total through *total_dev (a device u64) when not null.
+void exclusive_scan_u32(const uint32_t *in, uint32_t *out, size_t n, hipStream_t s, Arena &ar,
+                        unsigned long long *total_dev = nullptr);
+
+// hist.hip
+void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint32_t *counts,
+              unsigned long long *totals, hipStream_t s, Arena &ar);
+
+// load.hip
+void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar);
+// dataflow.hip
+void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar);
+void build_edges(gpa_program &p, hipStream_t s, Arena &ar);
+// dist.hip
+void build_distances(gpa_program &p, hipStream_t s, Arena &ar);
+void build_scope_targets(gpa_program &p, hipStream_t s, Arena &ar);
+// blame.hip
+void run_blame(const gpa_program &p, gpa_blame &b, hipStream_t s, Arena &ar);
+// estimate.hip
+void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint32_t k,
+                  hipStream_t s, Arena &ar);
+
+// read a few device words synchronously
+template <typename T>
+T read_scalar(const T *dev, hipStream_t s) {
+  T v{};
+  GPA_HIP(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, s));
+  GPA_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+inline unsigned grid_for(size_t n, unsigned block, unsigned cap = 1u << 20) {
+  size_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace gpa

@@ -1,0 +1,604 @@
+// Program loading: descriptor validation and the derived structure every
+// later step reads (Sec. 3: CFGs, program structure, architecture table).
+//   - block -> function, instruction -> block, predecessor lists;
+//   - def and use sites sorted by (function, location, instruction): the
+//     per-location views the reaching-definitions tiles work on;
+//   - per (function, location) the guards met on its defs, and per use site
+//     the condition its search must cover (Sec. 4, predicated instructions);
+//   - scope tree: kernel root, depth and preorder subtree end per scope.
+#include "common.h"
+#include "devutil.h"
+
+namespace gpa {
+
+enum : uint32_t {
+  kErrOpClass = 1u << 0,
+  kErrGuard = 1u << 1,
+  kErrCsr = 1u << 2,
+  kErrDef = 1u << 3,
+  kErrUse = 1u << 4,
+  kErrDupDef = 1u << 5,
+  kErrBlocks = 1u << 6,
+  kErrSucc = 1u << 7,
+  kErrFuncs = 1u << 8,
+  kErrFuncScope = 1u << 9,
+  kErrScopes = 1u << 10,
+  kErrInstrScope = 1u << 11,
+};
+
+static const char *kErrText[] = {
+    "op_class out of range",
+    "guard out of range (0, 1+2k or 2+2k with k < n_preds)",
+    "def_ptr/use_ptr not a valid CSR",
+    "def location or kind out of range",
+    "use location or kind out of range",
+    "a location appears twice in one instruction's def list",
+    "block_begin not strictly increasing from 0 to n_instr",
+    "successor out of range or outside its function",
+    "func_block_begin not strictly increasing from 0 to n_blocks",
+    "func_scope is not a FUNCTION scope with GPA_SF_HAS_CFG",
+    "scope tree not in preorder with FUNCTION kernel roots",
+    "instr_scope is not a LINE scope inside its own CFG function",
+};
+
+// ------------------------------------------------------------ validation
+__global__ void k_val_instr(uint32_t n_instr, uint32_t n_preds, uint32_t n_scopes, uint32_t n_defs,
+                            uint32_t n_uses, const uint8_t *op_class, const uint8_t *guard,
+                            const uint32_t *def_ptr, const uint32_t *use_ptr,
+                            const uint32_t *def_loc, const uint32_t *instr_scope,
+                            const uint8_t *scope_kind, uint32_t *err) {
+  uint32_t e = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_instr;
+       i += gridDim.x * blockDim.x) {
+    if (op_class[i] >= GPA_N_OP_CLASSES) e |= kErrOpClass;
+    if (guard[i] > 2 * n_preds) e |= kErrGuard;
+    if (def_ptr[i] > def_ptr[i + 1] || use_ptr[i] > use_ptr[i + 1] || def_ptr[i + 1] > n_defs ||
+        use_ptr[i + 1] > n_uses) {
+      e |= kErrCsr;
+      continue;
+    }
+    for (uint32_t a = def_ptr[i]; a < def_ptr[i + 1]; ++a)
+      for (uint32_t b = a + 1; b < def_ptr[i + 1]; ++b)
+        if (def_loc[a] == def_loc[b]) e |= kErrDupDef;
+    const uint32_t sc = instr_scope[i];
+    if (sc >= n_scopes || scope_kind[sc] != GPA_SCOPE_LINE) e |= kErrInstrScope;
+  }
+  if (e) atomicOr(err, e);
+}
+
+__global__ void k_val_sites(uint32_t n, const uint32_t *loc, const uint8_t *kind, uint32_t n_loc,
+                            uint32_t max_kind, uint32_t bit, uint32_t *err) {
+  uint32_t e = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    if (loc[i] >= n_loc || kind[i] > max_kind) e = bit;
+  if (e) atomicOr(err, e);
+}
+
+__global__ void k_val_ends(uint32_t n_instr, uint32_t n_blocks, uint32_t n_funcs,
+                           const uint32_t *def_ptr, const uint32_t *use_ptr,
+                           const uint32_t *block_begin, const uint32_t *succ_ptr,
+                           const uint32_t *fbb, uint32_t *err) {
+  uint32_t e = 0;
+  if (def_ptr[0] != 0 || use_ptr[0] != 0) e |= kErrCsr;
+  if (block_begin[0] != 0 || block_begin[n_blocks] != n_instr) e |= kErrBlocks;
+  if (succ_ptr[0] != 0) e |= kErrSucc;
+  if (fbb[0] != 0 || fbb[n_funcs] != n_blocks) e |= kErrFuncs;
+  if (e) atomicOr(err, e);
+}
+
+__global__ void k_val_funcs(uint32_t n_funcs, uint32_t n_scopes, const uint32_t *fbb,
+                            const uint32_t *func_scope, const uint8_t *scope_kind,
+                            const uint8_t *scope_flags, uint32_t *err) {
+  uint32_t e = 0;
+  for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < n_funcs;
+       f += gridDim.x * blockDim.x) {
+    if (fbb[f] >= fbb[f + 1]) e |= kErrFuncs;
+    const uint32_t s = func_scope[f];
+    if (s >= n_scopes || scope_kind[s] != GPA_SCOPE_FUNCTION || !(scope_flags[s] & GPA_SF_HAS_CFG))
+      e |= kErrFuncScope;
+  }
+  if (e) atomicOr(err, e);
+}
+
+__global__ void k_val_scopes(uint32_t n_scopes, const uint32_t *parent, const uint8_t *kind,
+                             const uint8_t *flags, uint32_t *err) {
+  uint32_t e = 0;
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_scopes;
+       s += gridDim.x * blockDim.x) {
+    const uint32_t p = parent[s];
+    if (kind[s] > GPA_SCOPE_LINE) e |= kErrScopes;
+    if (p == GPA_NONE) {
+      if (kind[s] != GPA_SCOPE_FUNCTION || !(flags[s] & GPA_SF_KERNEL_ENTRY)) e |= kErrScopes;
+    } else if (p >= s || kind[p] == GPA_SCOPE_LINE) {
+      e |= kErrScopes;
+    }
+  }
+  if (e) atomicOr(err, e);
+}
+
+// block structure: instruction ranges, block -> function, successors inside the function
+__global__ void k_blocks(uint32_t n_funcs, uint32_t n_instr, const uint32_t *fbb,
+                         const uint32_t *block_begin,
+                         uint32_t *block_of, uint32_t *func_of_block, uint32_t *err) {
+  for (uint32_t f = blockIdx.x; f < n_funcs; f += gridDim.x) {
+    for (uint32_t b = fbb[f] + threadIdx.x; b < fbb[f + 1]; b += blockDim.x) {
+      func_of_block[b] = f;
+      const uint32_t i0 = block_begin[b], i1 = block_begin[b + 1];
+      if (i0 >= i1 || i1 > n_instr) {
+        atomicOr(err, kErrBlocks);
+        continue;
+      }
+      for (uint32_t i = i0; i < i1; ++i) block_of[i] = b;
+    }
+  }
+}
+
+__global__ void k_val_succ(uint32_t n_blocks, const uint32_t *succ_ptr, const uint32_t *succ,
+                           uint32_t n_succ, const uint32_t *func_of_block, uint32_t *pred_cnt,
+                           uint32_t *err) {
+  uint32_t e = 0;
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_blocks;
+       b += gridDim.x * blockDim.x) {
+    const uint32_t e0 = succ_ptr[b], e1 = succ_ptr[b + 1];
+    if (e0 > e1 || e1 > n_succ) {
+      e |= kErrSucc;
+      continue;
+    }
+    for (uint32_t k = e0; k < e1; ++k) {
+      const uint32_t t = succ[k];
+      if (t >= n_blocks || func_of_block[t] != func_of_block[b]) {
+        e |= kErrSucc;
+        continue;
+      }
+      atomicAdd(&pred_cnt[t], 1u);
+    }
+  }
+  if (e) atomicOr(err, e);
+}
+
+__global__ void k_fill_pred(uint32_t n_blocks, const uint32_t *succ_ptr, const uint32_t *succ,
+                            uint32_t *cursor, uint32_t *pred) {
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_blocks;
+       b += gridDim.x * blockDim.x)
+    for (uint32_t k = succ_ptr[b]; k < succ_ptr[b + 1]; ++k) pred[atomicAdd(&cursor[succ[k]], 1u)] = b;
+}
+
+// Each pred list in ascending order, so that everything downstream is
+// independent of the order in which the atomics above were served.
+__global__ void k_sort_pred(uint32_t n_blocks, const uint32_t *pred_ptr, uint32_t *pred) {
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_blocks;
+       b += gridDim.x * blockDim.x) {
+    const uint32_t p0 = pred_ptr[b], p1 = pred_ptr[b + 1];
+    for (uint32_t i = p0 + 1; i < p1; ++i) {
+      uint32_t v = pred[i], j = i;
+      while (j > p0 && pred[j - 1] > v) {
+        pred[j] = pred[j - 1];
+        --j;
+      }
+      pred[j] = v;
+    }
+  }
+}
+
+// every instruction's LINE scope lies under its function's scope and under no
+// other CFG function
+__global__ void k_val_instr_scope(uint32_t n_instr, const uint32_t *instr_scope,
+                                  const uint32_t *block_of, const uint32_t *func_of_block,
+                                  const uint32_t *func_scope, const uint32_t *parent,
+                                  const uint8_t *kind, const uint8_t *flags, uint32_t *err) {
+  uint32_t e = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_instr;
+       i += gridDim.x * blockDim.x) {
+    const uint32_t want = func_scope[func_of_block[block_of[i]]];
+    uint32_t s = instr_scope[i];
+    uint32_t guard = 0;
+    while (s != GPA_NONE && !(kind[s] == GPA_SCOPE_FUNCTION && (flags[s] & GPA_SF_HAS_CFG)) &&
+           guard < 4096) {
+      s = parent[s];
+      ++guard;
+    }
+    if (s != want) e |= kErrInstrScope;
+  }
+  if (e) atomicOr(err, e);
+}
+
+// ------------------------------------------------- sites by (func, location)
+// Sites (defs or uses) of function f occupy [site_ptr[i0], site_ptr[i1]) for
+// its instruction range [i0, i1); they are processed in chunks of kChunk.
+constexpr int kSortThreads = 256;
+constexpr int kChunk = 2048;
+
+struct SiteChunk {
+  uint32_t func, begin, end, pad;
+};
+
+__global__ void k_chunk_count(uint32_t n_funcs, const uint32_t *fbb, const uint32_t *block_begin,
+                              const uint32_t *site_ptr, uint32_t *nchunks) {
+  for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < n_funcs;
+       f += gridDim.x * blockDim.x) {
+    const uint32_t s0 = site_ptr[block_begin[fbb[f]]], s1 = site_ptr[block_begin[fbb[f + 1]]];
+    nchunks[f] = (s1 - s0 + kChunk - 1) / kChunk;
+  }
+}
+
+__global__ void k_chunk_fill(uint32_t n_funcs, const uint32_t *fbb, const uint32_t *block_begin,
+                             const uint32_t *site_ptr, const uint32_t *chunk_start,
+                             SiteChunk *chunks) {
+  for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < n_funcs;
+       f += gridDim.x * blockDim.x) {
+    const uint32_t s0 = site_ptr[block_begin[fbb[f]]], s1 = site_ptr[block_begin[fbb[f + 1]]];
+    uint32_t c = chunk_start[f];
+    for (uint32_t a = s0; a < s1; a += kChunk, ++c) {
+      SiteChunk ch;
+      ch.func = f;
+      ch.begin = a;
+      ch.end = min(a + kChunk, s1);
+      ch.pad = 0;
+      chunks[c] = ch;
+    }
+  }
+}
+
+// per chunk, the number of sites of each location
+__global__ void __launch_bounds__(kSortThreads)
+k_chunk_hist(const SiteChunk *chunks, const uint32_t *key, uint32_t n_loc, uint32_t *chunk_cnt) {
+  extern __shared__ uint32_t cnt[];
+  const SiteChunk ch = chunks[blockIdx.x];
+  for (uint32_t x = threadIdx.x; x < n_loc; x += kSortThreads) cnt[x] = 0;
+  __syncthreads();
+  for (uint32_t s = ch.begin + threadIdx.x; s < ch.end; s += kSortThreads) atomicAdd(&cnt[key[s]], 1u);
+  __syncthreads();
+  for (uint32_t x = threadIdx.x; x < n_loc; x += kSortThreads)
+    chunk_cnt[(size_t)blockIdx.x * n_loc + x] = cnt[x];
+}
+
+// per function: start of each (function, location) list (fl_ptr) and each
+// chunk's base inside it (written over the per-chunk counts)
+__global__ void __launch_bounds__(kSortThreads)
+k_chunk_bases(uint32_t n_funcs, const uint32_t *fbb, const uint32_t *block_begin,
+              const uint32_t *site_ptr, const uint32_t *chunk_start, const uint32_t *nchunks,
+              uint32_t n_loc, uint32_t *chunk_cnt, uint32_t *fl_ptr) {
+  __shared__ uint32_t tmp[kSortThreads / kWave + 1];
+  const uint32_t f = blockIdx.x;
+  const uint32_t s0 = site_ptr[block_begin[fbb[f]]];
+  const uint32_t c0 = chunk_start[f], nc = nchunks[f];
+  const uint32_t per = (n_loc + kSortThreads - 1) / kSortThreads;   // <= 4
+  const uint32_t x0 = min(threadIdx.x * per, n_loc), x1 = min(x0 + per, n_loc);
+  uint32_t tot[4] = {0, 0, 0, 0};
+  uint32_t mytot = 0;
+  for (uint32_t x = x0; x < x1; ++x) {
+    uint32_t run = 0;
+    for (uint32_t c = 0; c < nc; ++c) {
+      uint32_t *q = &chunk_cnt[(size_t)(c0 + c) * n_loc + x];
+      const uint32_t v = *q;
+      *q = run;
+      run += v;
+    }
+    tot[x - x0] = run;
+    mytot += run;
+  }
+  uint32_t total;
+  uint32_t base = block_excl_scan<kSortThreads>(mytot, tmp, &total) + s0;
+  for (uint32_t x = x0; x < x1; ++x) {
+    fl_ptr[(size_t)f * (n_loc + 1) + x] = base;
+    for (uint32_t c = 0; c < nc; ++c) chunk_cnt[(size_t)(c0 + c) * n_loc + x] += base;
+    base += tot[x - x0];
+  }
+}
+
+// Stable scatter: rounds of kSortThreads consecutive sites; the rank of a
+// site among equal keys of its round comes from ballot matching inside the
+// wave plus per-wave counts in LDS; per-location cursors carry across rounds.
+__global__ void __launch_bounds__(kSortThreads)
+k_chunk_scatter(const SiteChunk *chunks, const uint32_t *key, uint32_t n_loc, uint32_t key_bits,
+                const uint32_t *chunk_base, uint32_t *sorted, uint32_t *rank_of) {
+  extern __shared__ uint32_t sh[];
+  uint32_t *cursor = sh;                        // [n_loc]
+  uint32_t *wcnt = sh + n_loc;                  // [4][n_loc]
+  constexpr int NW = kSortThreads / kWave;
+  const SiteChunk ch = chunks[blockIdx.x];
+  const unsigned tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+  for (uint32_t x = tid; x < n_loc; x += kSortThreads) {
+    cursor[x] = chunk_base[(size_t)blockIdx.x * n_loc + x];
+    for (int k = 0; k < NW; ++k) wcnt[k * n_loc + x] = 0;
+  }
+  __syncthreads();
+  for (uint32_t r0 = ch.begin; r0 < ch.end; r0 += kSortThreads) {
+    const uint32_t s = r0 + tid;
+    const bool active = s < ch.end;
+    const uint32_t k = active ? key[s] : 0xFFFFFFFFu;
+    // lanes of this wave holding the same key
+    uint64_t peers = __ballot(active);
+    for (uint32_t bit = 0; bit < key_bits; ++bit) {
+      const uint64_t m = __ballot(active && ((k >> bit) & 1u));
+      peers &= ((k >> bit) & 1u) ? m : ~m;
+    }
+    const uint64_t lower = peers & ((1ull << lane) - 1ull);
+    const uint32_t in_wave = __popcll(lower);
+    if (active && lower == 0) wcnt[w * n_loc + k] = __popcll(peers);
+    __syncthreads();
+    if (active) {
+      uint32_t before = 0;
+      for (unsigned v = 0; v < w; ++v) before += wcnt[v * n_loc + k];
+      const uint32_t pos = cursor[k] + before + in_wave;
+      sorted[pos] = s;
+      rank_of[s] = pos;
+    }
+    __syncthreads();
+    if (active && lower == 0) {
+      uint32_t tot = 0;
+      for (int v = 0; v < NW; ++v) tot += wcnt[v * n_loc + k];
+      // only the first wave holding this key advances the cursor
+      bool first = true;
+      for (unsigned v = 0; v < w; ++v)
+        if (wcnt[v * n_loc + k]) first = false;
+      if (first) cursor[k] += tot;
+    }
+    __syncthreads();
+    if (active && lower == 0) wcnt[w * n_loc + k] = 0;
+    __syncthreads();
+  }
+}
+
+// (function, location) -> bitmask of the guards on its defs
+__global__ void k_def_guards(uint32_t n_funcs, uint32_t n_loc, const uint32_t *fl_def_ptr,
+                             const uint32_t *def_site_sorted, const uint32_t *def_instr,
+                             const uint8_t *guard, uint64_t *mask) {
+  const size_t total = (size_t)n_funcs * n_loc;
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < total;
+       q += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t f = (uint32_t)(q / n_loc), x = (uint32_t)(q % n_loc);
+    const uint32_t a = fl_def_ptr[(size_t)f * (n_loc + 1) + x];
+    const uint32_t b = fl_def_ptr[(size_t)f * (n_loc + 1) + x + 1];
+    uint64_t m = 0;
+    for (uint32_t k = a; k < b; ++k) m |= 1ull << guard[def_instr[def_site_sorted[k]]];
+    mask[q] = m;
+  }
+}
+
+// site -> instruction
+__global__ void k_site_instr(uint32_t n_instr, const uint32_t *site_ptr, uint32_t *site_instr) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_instr; i += gridDim.x * blockDim.x)
+    for (uint32_t s = site_ptr[i]; s < site_ptr[i + 1]; ++s) site_instr[s] = i;
+}
+
+// A use's search must cover its condition: the instruction's guard for an
+// operand use, `_` for a guard read or a wait.  A guard that no def of the
+// location carries is covered exactly by the defs that cover `_`, so such
+// uses share the `_` problem.
+__global__ void k_use_cond(uint32_t n_uses, const uint32_t *use_instr, const uint32_t *use_loc,
+                           const uint8_t *use_kind, const uint8_t *guard, const uint32_t *block_of,
+                           const uint32_t *func_of_block, uint32_t n_loc, const uint64_t *dmask,
+                           uint8_t *cond) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n_uses; u += gridDim.x * blockDim.x) {
+    const uint32_t j = use_instr[u];
+    uint32_t c = use_kind[u] == GPA_USE_OPND ? guard[j] : 0u;
+    const uint32_t f = func_of_block[block_of[j]];
+    if (c && !((dmask[(size_t)f * n_loc + use_loc[u]] >> c) & 1ull)) c = 0;
+    cond[u] = (uint8_t)c;
+  }
+}
+
+// ------------------------------------------------------------------ scopes
+__global__ void k_scope_info(uint32_t n_scopes, const uint32_t *parent, uint32_t *root_of,
+                             uint32_t *depth) {
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_scopes;
+       s += gridDim.x * blockDim.x) {
+    uint32_t a = s, d = 0;
+    while (parent[a] != GPA_NONE) {
+      a = parent[a];
+      ++d;
+    }
+    root_of[s] = a;
+    depth[s] = d;
+  }
+}
+
+// Preorder subtree ends: index t closes scope t-1 and every ancestor of it
+// whose depth is at least depth[t] (t = n_scopes closes everything left);
+// every scope is closed exactly once.
+__global__ void k_scope_end(uint32_t n_scopes, const uint32_t *parent, const uint32_t *depth,
+                            uint32_t *scope_end) {
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x + 1; t <= n_scopes;
+       t += gridDim.x * blockDim.x) {
+    uint32_t cur = t - 1;
+    while (cur != GPA_NONE && (t == n_scopes || depth[cur] >= depth[t])) {
+      scope_end[cur] = t;
+      cur = parent[cur];
+    }
+  }
+}
+
+// bit0: some FUNCTION scope above the instruction is a math function;
+// bit1: some FUNCTION scope above it is a device function with its own CFG
+__global__ void k_instr_tags(uint32_t n_instr, const uint32_t *instr_scope, const uint32_t *parent,
+                             const uint8_t *kind, const uint8_t *flags, uint8_t *tags) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_instr;
+       i += gridDim.x * blockDim.x) {
+    uint8_t t = 0;
+    for (uint32_t s = instr_scope[i]; s != GPA_NONE; s = parent[s]) {
+      if (kind[s] != GPA_SCOPE_FUNCTION) continue;
+      if (flags[s] & GPA_SF_MATH_FN) t |= 1;
+      if ((flags[s] & GPA_SF_DEVICE_FN) && (flags[s] & GPA_SF_HAS_CFG)) t |= 2;
+    }
+    tags[i] = t;
+  }
+}
+
+__global__ void k_roots(uint32_t n_scopes, const uint32_t *parent, uint32_t *roots, uint32_t *n) {
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_scopes;
+       s += gridDim.x * blockDim.x)
+    if (parent[s] == GPA_NONE) roots[atomicAdd(n, 1u)] = s;
+}
+
+__global__ void k_max_func_blocks(uint32_t n_funcs, const uint32_t *fbb, uint32_t *mx) {
+  uint32_t m = 0;
+  for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < n_funcs;
+       f += gridDim.x * blockDim.x)
+    m = max(m, fbb[f + 1] - fbb[f]);
+  atomicMax(mx, m);
+}
+
+static void raise_validation(uint32_t err) {
+  std::string msg = "invalid program descriptor:";
+  for (int b = 0; b < 12; ++b)
+    if (err & (1u << b)) {
+      msg += " ";
+      msg += kErrText[b];
+      msg += ";";
+    }
+  fail(GPA_E_INVALID, "%s", msg.c_str());
+}
+
+static void sort_sites(gpa_program &p, hipStream_t s, Arena &ar, const uint32_t *site_ptr,
+                       const uint32_t *key, uint32_t n_sites, DBuf<uint32_t> &sorted,
+                       DBuf<uint32_t> &fl_ptr, uint32_t *rank_of) {
+  const uint32_t nf = p.n_funcs, nl = p.n_loc;
+  uint32_t *nchunks = ar.get<uint32_t>(nf);
+  uint32_t *cstart = ar.get<uint32_t>(nf);
+  unsigned long long *ntot = ar.get<unsigned long long>(1);
+  hipLaunchKernelGGL(k_chunk_count, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf,
+                     p.func_block_begin.p, p.block_begin.p, site_ptr, nchunks);
+  GPA_LAUNCH_CHECK();
+  exclusive_scan_u32(nchunks, cstart, nf, s, ar, ntot);
+  const uint32_t n_chunks = (uint32_t)read_scalar(ntot, s);
+  sorted.alloc(n_sites);
+  fl_ptr.alloc((size_t)nf * (nl + 1));
+  // the end of every (function, location) list is the start of the next one
+  GPA_HIP(hipMemsetAsync(fl_ptr.p, 0, sizeof(uint32_t) * fl_ptr.n, s));
+  if (n_chunks == 0) return;
+  SiteChunk *chunks = ar.get<SiteChunk>(n_chunks);
+  hipLaunchKernelGGL(k_chunk_fill, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf,
+                     p.func_block_begin.p, p.block_begin.p, site_ptr, cstart, chunks);
+  GPA_LAUNCH_CHECK();
+  uint32_t *ccnt = ar.get<uint32_t>((size_t)n_chunks * nl);
+  hipLaunchKernelGGL(k_chunk_hist, dim3(n_chunks), dim3(kSortThreads), nl * 4, s, chunks, key, nl,
+                     ccnt);
+  GPA_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_chunk_bases, dim3(nf), dim3(kSortThreads), 0, s, nf, p.func_block_begin.p,
+                     p.block_begin.p, site_ptr, cstart, nchunks, nl, ccnt, fl_ptr.p);
+  GPA_LAUNCH_CHECK();
+  uint32_t key_bits = 1;
+  while ((1u << key_bits) < nl) ++key_bits;
+  const size_t lds = (size_t)nl * 4 * (1 + kSortThreads / kWave);
+  hipLaunchKernelGGL(k_chunk_scatter, dim3(n_chunks), dim3(kSortThreads), lds, s, chunks, key, nl,
+                     key_bits, ccnt, sorted.p, rank_of);
+  GPA_LAUNCH_CHECK();
+}
+
+__global__ void k_fl_close(uint32_t n_funcs, uint32_t n_loc, const uint32_t *fbb,
+                           const uint32_t *block_begin, const uint32_t *site_ptr, uint32_t *fl_ptr) {
+  for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < n_funcs;
+       f += gridDim.x * blockDim.x)
+    fl_ptr[(size_t)f * (n_loc + 1) + n_loc] = site_ptr[block_begin[fbb[f + 1]]];
+}
+
+void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar) {
+  const uint32_t n = p.n_instr, nb = p.n_blocks, nf = p.n_funcs, ns = p.n_scopes;
+  uint32_t *err = ar.get<uint32_t>(1);
+  GPA_HIP(hipMemsetAsync(err, 0, 4, s));
+  hipLaunchKernelGGL(k_val_ends, dim3(1), dim3(1), 0, s, n, nb, nf, p.def_ptr.p, p.use_ptr.p,
+                     p.block_begin.p, p.succ_ptr.p, p.func_block_begin.p, err);
+  hipLaunchKernelGGL(k_val_instr, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, n, p.n_preds, ns,
+                     p.n_defs, p.n_uses, p.op_class.p, p.guard.p, p.def_ptr.p, p.use_ptr.p, p.def_loc.p,
+                     p.instr_scope.p, p.scope_kind.p, err);
+  hipLaunchKernelGGL(k_val_sites, dim3(grid_for(p.n_defs, 256, 2048)), dim3(256), 0, s, p.n_defs,
+                     p.def_loc.p, p.def_kind.p, p.n_loc, (uint32_t)GPA_DEF_RBAR, kErrDef, err);
+  hipLaunchKernelGGL(k_val_sites, dim3(grid_for(p.n_uses, 256, 2048)), dim3(256), 0, s, p.n_uses,
+                     p.use_loc.p, p.use_kind.p, p.n_loc, (uint32_t)GPA_USE_WAIT, kErrUse, err);
+  hipLaunchKernelGGL(k_val_funcs, dim3(grid_for(nf, 256, 2048)), dim3(256), 0, s, nf, ns,
+                     p.func_block_begin.p, p.func_scope.p, p.scope_kind.p, p.scope_flags.p, err);
+  hipLaunchKernelGGL(k_val_scopes, dim3(grid_for(ns, 256, 2048)), dim3(256), 0, s, ns,
+                     p.scope_parent.p, p.scope_kind.p, p.scope_flags.p, err);
+  GPA_LAUNCH_CHECK();
+  uint32_t e = read_scalar(err, s);
+  if (e) raise_validation(e);
+  // function and block maps (ranges are known to be sane from here on)
+  p.block_of.alloc(n);
+  p.func_of_block.alloc(nb);
+  hipLaunchKernelGGL(k_blocks, dim3(grid_for(nf, 1, 4096)), dim3(64), 0, s, nf, n,
+                     p.func_block_begin.p, p.block_begin.p, p.block_of.p, p.func_of_block.p, err);
+  GPA_LAUNCH_CHECK();
+  e = read_scalar(err, s);
+  if (e) raise_validation(e);
+  uint32_t *pcnt = ar.get<uint32_t>(nb + 1);
+  GPA_HIP(hipMemsetAsync(pcnt, 0, 4 * (nb + 1), s));
+  hipLaunchKernelGGL(k_val_succ, dim3(grid_for(nb, 256, 2048)), dim3(256), 0, s, nb, p.succ_ptr.p,
+                     p.succ.p, p.n_succ, p.func_of_block.p, pcnt, err);
+  hipLaunchKernelGGL(k_val_instr_scope, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, n,
+                     p.instr_scope.p, p.block_of.p, p.func_of_block.p, p.func_scope.p,
+                     p.scope_parent.p, p.scope_kind.p, p.scope_flags.p, err);
+  GPA_LAUNCH_CHECK();
+  e = read_scalar(err, s);
+  if (e) raise_validation(e);
+  // predecessor lists
+  p.pred_ptr.alloc(nb + 1);
+  p.pred.alloc(p.n_succ);
+  exclusive_scan_u32(pcnt, p.pred_ptr.p, nb + 1, s, ar);
+  uint32_t *cursor = ar.get<uint32_t>(nb + 1);
+  GPA_HIP(hipMemcpyAsync(cursor, p.pred_ptr.p, 4 * (nb + 1), hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_fill_pred, dim3(grid_for(nb, 256, 2048)), dim3(256), 0, s, nb, p.succ_ptr.p,
+                     p.succ.p, cursor, p.pred.p);
+  hipLaunchKernelGGL(k_sort_pred, dim3(grid_for(nb, 256, 2048)), dim3(256), 0, s, nb,
+                     p.pred_ptr.p, p.pred.p);
+  GPA_LAUNCH_CHECK();
+  // largest function, in blocks
+  uint32_t *mx = ar.get<uint32_t>(1);
+  GPA_HIP(hipMemsetAsync(mx, 0, 4, s));
+  hipLaunchKernelGGL(k_max_func_blocks, dim3(grid_for(nf, 256, 1024)), dim3(256), 0, s, nf,
+                     p.func_block_begin.p, mx);
+  GPA_LAUNCH_CHECK();
+  p.max_func_blocks = read_scalar(mx, s);
+  if (p.max_func_blocks > 4096)
+    fail(GPA_E_UNSUPPORTED, "a function has %u blocks; at most 4096 are supported",
+         p.max_func_blocks);
+  // sites by (function, location, instruction)
+  p.def_instr.alloc(p.n_defs);
+  p.use_instr.alloc(p.n_uses);
+  hipLaunchKernelGGL(k_site_instr, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, n, p.def_ptr.p,
+                     p.def_instr.p);
+  hipLaunchKernelGGL(k_site_instr, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, n, p.use_ptr.p,
+                     p.use_instr.p);
+  GPA_LAUNCH_CHECK();
+  p.def_rank.alloc(p.n_defs);
+  p.use_rank.alloc(p.n_uses);
+  sort_sites(p, s, ar, p.def_ptr.p, p.def_loc.p, p.n_defs, p.def_site_sorted, p.fl_def_ptr,
+             p.def_rank.p);
+  sort_sites(p, s, ar, p.use_ptr.p, p.use_loc.p, p.n_uses, p.use_site_sorted, p.fl_use_ptr,
+             p.use_rank.p);
+  hipLaunchKernelGGL(k_fl_close, dim3(grid_for(nf, 256, 1024)), dim3(256), 0, s, nf, p.n_loc,
+                     p.func_block_begin.p, p.block_begin.p, p.def_ptr.p, p.fl_def_ptr.p);
+  hipLaunchKernelGGL(k_fl_close, dim3(grid_for(nf, 256, 1024)), dim3(256), 0, s, nf, p.n_loc,
+                     p.func_block_begin.p, p.block_begin.p, p.use_ptr.p, p.fl_use_ptr.p);
+  GPA_LAUNCH_CHECK();
+  p.fl_def_guards.alloc((size_t)nf * p.n_loc);
+  hipLaunchKernelGGL(k_def_guards, dim3(grid_for((size_t)nf * p.n_loc, 256, 4096)), dim3(256), 0,
+                     s, nf, p.n_loc, p.fl_def_ptr.p, p.def_site_sorted.p, p.def_instr.p, p.guard.p,
+                     p.fl_def_guards.p);
+  p.use_cond.alloc(p.n_uses);
+  hipLaunchKernelGGL(k_use_cond, dim3(grid_for(p.n_uses, 256, 4096)), dim3(256), 0, s, p.n_uses,
+                     p.use_instr.p, p.use_loc.p, p.use_kind.p, p.guard.p, p.block_of.p,
+                     p.func_of_block.p, p.n_loc, p.fl_def_guards.p, p.use_cond.p);
+  GPA_LAUNCH_CHECK();
+  // scope tree
+  p.root_of.alloc(ns);
+  p.scope_depth.alloc(ns);
+  p.scope_end.alloc(ns);
+  hipLaunchKernelGGL(k_scope_info, dim3(grid_for(ns, 256, 4096)), dim3(256), 0, s, ns,
+                     p.scope_parent.p, p.root_of.p, p.scope_depth.p);
+  hipLaunchKernelGGL(k_scope_end, dim3(grid_for(ns, 256, 4096)), dim3(256), 0, s, ns,
+                     p.scope_parent.p, p.scope_depth.p, p.scope_end.p);
+  p.instr_tags.alloc(n);
+  hipLaunchKernelGGL(k_instr_tags, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n,
+                     p.instr_scope.p, p.scope_parent.p, p.scope_kind.p, p.scope_flags.p,
+                     p.instr_tags.p);
+  p.roots.alloc(ns);
+  uint32_t *nr = ar.get<uint32_t>(1);
+  GPA_HIP(hipMemsetAsync(nr, 0, 4, s));
+  hipLaunchKernelGGL(k_roots, dim3(grid_for(ns, 256, 4096)), dim3(256), 0, s, ns, p.scope_parent.p,
+                     p.roots.p, nr);
+  GPA_LAUNCH_CHECK();
+  p.n_roots = read_scalar(nr, s);
+}
+
+}  // namespace gpa

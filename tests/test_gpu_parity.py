@@ -1,0 +1,115 @@
+"""GPU parity: the HIP path through the C-ABI against the oracle, element by
+element on the same seeded inputs."""
+import numpy as np
+import pytest
+
+import brute as B
+from asm import assemble, samples
+from oracle import oracle as O
+from paper_2009_04061_amd import synth as S
+from parity import compare, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _both(prog, rec, **kw):
+    g = run_gpu(prog, rec, **kw)
+    o = O.run_all(prog, rec)
+    compare(prog, g, o)
+    return g, o
+
+
+def test_small_workload_full_parity():
+    prog, rec = S.workload_small(seed=0)
+    g, o = _both(prog, rec)
+    assert g["info"]["n_edges"] > 1000
+
+
+def test_host_inputs_match_device_inputs():
+    prog, rec = S.workload_small(seed=11, n_samples=50_000)
+    g = run_gpu(prog, rec, device_inputs=False)
+    o = O.run_all(prog, rec)
+    compare(prog, g, o)
+
+
+def test_multi_kernel_device_and_math_functions():
+    prog, rec = S.workload_multi(seed=7, n_samples=150_000)
+    _both(prog, rec)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_arbitrary_cfgs(seed):
+    """Arbitrary (irreducible, partly unreachable) tiny CFGs with random
+    guards, complementary pairs, barriers and read barriers."""
+    prog = B.random_cfg_program(seed, n_blocks=int(3 + seed % 6), max_block=5, n_locs=4)
+    n = len(prog["op_class"])
+    rec = S.gen_samples(5000, n, 0.8, S.stall_mix_small(), seed=seed)
+    _both(prog, rec)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_structured_programs(seed):
+    prog = S.gen_program(seed=100 + seed, functions=[
+        dict(n_instr=300 + 50 * seed, n_blocks=20 + 3 * seed, n_loops=4, max_depth=3, kind="kernel"),
+        dict(n_instr=80, n_blocks=6, n_loops=1, max_depth=1, kind="device")],
+        n_regs=12, n_preds=3, n_bars=4, guard_frac=0.3, pair_frac=0.15, inline_frac=0.1)
+    n = len(prog["op_class"])
+    rec = S.gen_samples(40_000, n, 1.0, S.stall_mix_small(), seed=seed)
+    _both(prog, rec)
+
+
+def test_dropped_records_and_ragged_tail():
+    prog, rec = S.workload_small(seed=4, n_samples=3 * 16384 + 77)
+    bad = S.corrupt_samples(rec, 0.03, 2000, seed=9)
+    g, o = _both(prog, bad)
+    assert g["totals"][2] > 0
+
+
+def test_empty_and_single_sample():
+    prog, _ = S.workload_small(seed=5, n_samples=10)
+    _both(prog, np.zeros(0, S.SAMPLE_DTYPE))
+    _both(prog, samples([(17, S.ST_MEM_DEP, 1, 1)]))
+
+
+def test_worked_examples_on_gpu():
+    prog = assemble("block 0 ->\n  @!P0 LDC R0 <- R5\n  MOV R7 <- R8\n  @P0 LDG R0 <- R2 R3\n"
+                    "  MOV R9 <- R8\n  IADD R1 <- R0 R6\n")
+    rec = samples([(0, S.ST_SELECTED, 0, 8), (2, S.ST_SELECTED, 0, 4), (4, S.ST_MEM_DEP, 1, 10)])
+    g, _ = _both(prog, rec)
+    assert g["table"]["blamed"][0, S.ST_MEM_DEP, 1] == 5.0
+    assert g["table"]["blamed"][2, S.ST_MEM_DEP, 1] == 5.0
+
+
+def test_deterministic_bitwise():
+    prog, rec = S.workload_multi(seed=3, n_samples=60_000)
+    a = run_gpu(prog, rec)
+    b = run_gpu(prog, rec)
+    for key in ("shares",):
+        assert np.array_equal(a[key], b[key])
+    for key in ("blamed", "self", "fine"):
+        assert np.array_equal(a["table"][key], b["table"][key])
+    for key in ("matched", "speedup", "active"):
+        assert np.array_equal(a["est"][key], b["est"][key])
+
+
+def test_large_workload_full_parity():
+    """The 60k-instruction, 1,500-block profile with 20M samples, compared
+    in full (the oracle finishes it in seconds)."""
+    prog, rec = S.workload_large(seed=1)
+    g, o = _both(prog, rec)
+    assert g["info"]["n_edges"] > 100_000
+
+
+def test_function_at_block_limit_and_beyond():
+    from paper_2009_04061_amd import gpa
+    ok = S.gen_program(seed=8, functions=[dict(n_instr=4096 * 2, n_blocks=4096, n_loops=20,
+                                               max_depth=3, kind="kernel")],
+                       n_regs=32, n_preds=4, n_bars=4)
+    rec = S.gen_samples(100_000, 8192, 1.1, S.stall_mix_small(), seed=8)
+    _both(ok, rec)
+    big = S.gen_program(seed=9, functions=[dict(n_instr=4097 * 2, n_blocks=4097, n_loops=5,
+                                                max_depth=2, kind="kernel")],
+                        n_regs=32, n_preds=4, n_bars=4)
+    with pytest.raises(gpa.GpaError) as ei:
+        gpa.Program(big)
+    assert ei.value.status == -6
