@@ -150,6 +150,13 @@ namespace gpa {
 void exclusive_scan_u32(const uint32_t *in, uint32_t *out, size_t n, hipStream_t s, Arena &ar,
                         unsigned long long *total_dev = nullptr);
 
+// sort.hip: stable radix sort of (key, value) pairs over the low key_bits
+// bits, and grouping of n items by key (GPA_NONE keys left out).
+void sort_pairs_u32(uint32_t *keys, uint32_t *vals, size_t n, uint32_t key_bits, hipStream_t s,
+                    Arena &ar);
+void group_by_key(const uint32_t *key, size_t n, uint32_t n_keys, DBuf<uint32_t> &ptr,
+                  DBuf<uint32_t> &perm, hipStream_t s, Arena &ar);
+
 // hist.hip
 void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint32_t *counts,
               unsigned long long *totals, hipStream_t s, Arena &ar);

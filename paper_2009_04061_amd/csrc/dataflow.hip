@@ -424,35 +424,6 @@ __global__ void k_edge_fill(uint32_t n_instr, const uint32_t *use_ptr, const uin
   }
 }
 
-// edges grouped by source instruction, each group in edge order
-__global__ void k_out_count(uint64_t n_edges, const uint32_t *e_src, uint32_t *cnt) {
-  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < n_edges;
-       e += (uint64_t)gridDim.x * blockDim.x)
-    atomicAdd(&cnt[e_src[e]], 1u);
-}
-
-__global__ void k_out_fill(uint64_t n_edges, const uint32_t *e_src, uint32_t *cursor,
-                           uint32_t *perm) {
-  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < n_edges;
-       e += (uint64_t)gridDim.x * blockDim.x)
-    perm[atomicAdd(&cursor[e_src[e]], 1u)] = (uint32_t)e;
-}
-
-__global__ void k_segment_sort(uint32_t n_seg, const uint32_t *ptr, uint32_t *v) {
-  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_seg; s += gridDim.x * blockDim.x) {
-    const uint32_t a = ptr[s], b = ptr[s + 1];
-    for (uint32_t i = a + 1; i < b; ++i) {
-      const uint32_t x = v[i];
-      uint32_t j = i;
-      while (j > a && v[j - 1] > x) {
-        v[j] = v[j - 1];
-        --j;
-      }
-      v[j] = x;
-    }
-  }
-}
-
 // ------------------------------------------------------------------ host
 void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar) {
   const uint32_t nf = p.n_funcs, nl = p.n_loc;
@@ -538,24 +509,8 @@ void build_edges(gpa_program &p, hipStream_t s, Arena &ar) {
   hipLaunchKernelGGL(k_edge_fill, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, p.use_ptr.p,
                      p.rd_ptr.p, items, p.in_ptr.p, p.e_src.p, p.e_dst.p, p.e_flags.p);
   GPA_LAUNCH_CHECK();
-  // by source
-  uint32_t *ocnt = ar.get<uint32_t>(n + 1);
-  GPA_HIP(hipMemsetAsync(ocnt, 0, 4 * (size_t)(n + 1), s));
-  if (ne)
-    hipLaunchKernelGGL(k_out_count, dim3(grid_for(ne, 256, 8192)), dim3(256), 0, s, ne, p.e_src.p,
-                       ocnt);
-  GPA_LAUNCH_CHECK();
-  p.out_ptr.alloc(n + 1);
-  exclusive_scan_u32(ocnt, p.out_ptr.p, n + 1, s, ar);
-  uint32_t *cursor = ar.get<uint32_t>(n + 1);
-  GPA_HIP(hipMemcpyAsync(cursor, p.out_ptr.p, 4 * (size_t)(n + 1), hipMemcpyDeviceToDevice, s));
-  p.out_perm.alloc(ne);
-  if (ne)
-    hipLaunchKernelGGL(k_out_fill, dim3(grid_for(ne, 256, 8192)), dim3(256), 0, s, ne, p.e_src.p,
-                       cursor, p.out_perm.p);
-  hipLaunchKernelGGL(k_segment_sort, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n,
-                     p.out_ptr.p, p.out_perm.p);
-  GPA_LAUNCH_CHECK();
+  // by source instruction, in edge order inside each source
+  group_by_key(p.e_src.p, ne, n, p.out_ptr, p.out_perm, s, ar);
 }
 
 }  // namespace gpa

@@ -299,56 +299,6 @@ __global__ void k_edge_scopes(uint64_t n_edges, const uint32_t *e_src, const uin
   }
 }
 
-__global__ void k_key_count(uint64_t n, const uint32_t *key, uint32_t *cnt) {
-  for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n;
-       k += (uint64_t)gridDim.x * blockDim.x)
-    if (key[k] != GPA_NONE) atomicAdd(&cnt[key[k]], 1u);
-}
-
-__global__ void k_key_fill(uint64_t n, const uint32_t *key, uint32_t *cursor, uint32_t *perm) {
-  for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n;
-       k += (uint64_t)gridDim.x * blockDim.x)
-    if (key[k] != GPA_NONE) perm[atomicAdd(&cursor[key[k]], 1u)] = (uint32_t)k;
-}
-
-__global__ void k_segment_sort2(uint32_t n_seg, const uint32_t *ptr, uint32_t *v) {
-  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_seg; s += gridDim.x * blockDim.x) {
-    const uint32_t a = ptr[s], b = ptr[s + 1];
-    for (uint32_t i = a + 1; i < b; ++i) {
-      const uint32_t x = v[i];
-      uint32_t j = i;
-      while (j > a && v[j - 1] > x) {
-        v[j] = v[j - 1];
-        --j;
-      }
-      v[j] = x;
-    }
-  }
-}
-
-// items grouped by a key in [0, n_keys) (GPA_NONE keys left out), each group
-// in item order
-static void group_by(const uint32_t *key, uint64_t n, uint32_t n_keys, DBuf<uint32_t> &ptr,
-                     DBuf<uint32_t> &perm, hipStream_t s, Arena &ar) {
-  uint32_t *cnt = ar.get<uint32_t>(n_keys + 1);
-  GPA_HIP(hipMemsetAsync(cnt, 0, 4 * (size_t)(n_keys + 1), s));
-  if (n)
-    hipLaunchKernelGGL(k_key_count, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, key, cnt);
-  GPA_LAUNCH_CHECK();
-  ptr.alloc(n_keys + 1);
-  unsigned long long *tot = ar.get<unsigned long long>(1);
-  exclusive_scan_u32(cnt, ptr.p, n_keys + 1, s, ar, tot);
-  uint32_t *cursor = ar.get<uint32_t>(n_keys + 1);
-  GPA_HIP(hipMemcpyAsync(cursor, ptr.p, 4 * (size_t)(n_keys + 1), hipMemcpyDeviceToDevice, s));
-  perm.alloc(n ? n : 1);
-  if (n)
-    hipLaunchKernelGGL(k_key_fill, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, key, cursor,
-                       perm.p);
-  hipLaunchKernelGGL(k_segment_sort2, dim3(grid_for(n_keys, 256, 8192)), dim3(256), 0, s, n_keys,
-                     ptr.p, perm.p);
-  GPA_LAUNCH_CHECK();
-}
-
 void build_scope_targets(gpa_program &p, hipStream_t s, Arena &ar) {
   const uint64_t ne = p.n_edges;
   p.e_lca.alloc(ne);
@@ -359,9 +309,9 @@ void build_scope_targets(gpa_program &p, hipStream_t s, Arena &ar) {
                        p.scope_kind.p, p.block_of.p, p.func_of_block.p, p.func_scope.p, p.e_lca.p,
                        p.e_icl.p);
   GPA_LAUNCH_CHECK();
-  group_by(p.e_lca.p, ne, p.n_scopes, p.lca_ptr, p.lca_perm, s, ar);
-  group_by(p.e_icl.p, ne, p.n_scopes, p.icl_ptr, p.icl_perm, s, ar);
-  group_by(p.instr_scope.p, p.n_instr, p.n_scopes, p.line_ptr, p.line_perm, s, ar);
+  group_by_key(p.e_lca.p, ne, p.n_scopes, p.lca_ptr, p.lca_perm, s, ar);
+  group_by_key(p.e_icl.p, ne, p.n_scopes, p.icl_ptr, p.icl_perm, s, ar);
+  group_by_key(p.instr_scope.p, p.n_instr, p.n_scopes, p.line_ptr, p.line_perm, s, ar);
 }
 
 }  // namespace gpa

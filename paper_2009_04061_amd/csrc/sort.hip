@@ -1,0 +1,141 @@
+// Stable LSD radix sort of (key, value) u32 pairs, 8-bit digits.
+// Each pass: per-chunk digit histograms in LDS (digit-major counts), one
+// exclusive scan over them, and a stable scatter that ranks equal digits
+// inside each wave by ballot matching and across waves by LDS counts.
+// Used to group items by a key while keeping item order inside each group.
+#include "common.h"
+#include "devutil.h"
+
+namespace gpa {
+
+constexpr int kRsThreads = 256;
+constexpr int kRsChunk = 2048;
+constexpr int kRsDigits = 256;
+
+__global__ void __launch_bounds__(kRsThreads)
+k_rs_hist(const uint32_t *keys, size_t n, uint32_t shift, uint32_t n_chunks, uint32_t *counts) {
+  __shared__ uint32_t h[kRsDigits];
+  for (int d = threadIdx.x; d < kRsDigits; d += kRsThreads) h[d] = 0;
+  __syncthreads();
+  const size_t a = (size_t)blockIdx.x * kRsChunk, b = min(a + kRsChunk, n);
+  for (size_t i = a + threadIdx.x; i < b; i += kRsThreads) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  __syncthreads();
+  for (int d = threadIdx.x; d < kRsDigits; d += kRsThreads)
+    counts[(size_t)d * n_chunks + blockIdx.x] = h[d];
+}
+
+__global__ void __launch_bounds__(kRsThreads)
+k_rs_scatter(const uint32_t *keys, const uint32_t *vals, size_t n, uint32_t shift,
+             uint32_t n_chunks, const uint32_t *offsets, uint32_t *keys_out, uint32_t *vals_out) {
+  constexpr int NW = kRsThreads / kWave;
+  __shared__ uint32_t cursor[kRsDigits];
+  __shared__ uint32_t wcnt[NW][kRsDigits];
+  const unsigned tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+  for (int d = tid; d < kRsDigits; d += kRsThreads) {
+    cursor[d] = offsets[(size_t)d * n_chunks + blockIdx.x];
+    for (int v = 0; v < NW; ++v) wcnt[v][d] = 0;
+  }
+  __syncthreads();
+  const size_t a = (size_t)blockIdx.x * kRsChunk, b = min(a + kRsChunk, n);
+  for (size_t r0 = a; r0 < b; r0 += kRsThreads) {
+    const size_t i = r0 + tid;
+    const bool active = i < b;
+    const uint32_t key = active ? keys[i] : 0u;
+    const uint32_t dg = (key >> shift) & 255u;
+    uint64_t peers = __ballot(active);
+#pragma unroll
+    for (uint32_t bit = 0; bit < 8; ++bit) {
+      const uint64_t m = __ballot(active && ((dg >> bit) & 1u));
+      peers &= ((dg >> bit) & 1u) ? m : ~m;
+    }
+    const uint64_t lower = peers & ((1ull << lane) - 1ull);
+    if (active && lower == 0) wcnt[w][dg] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (active) {
+      uint32_t before = 0;
+      for (unsigned v = 0; v < w; ++v) before += wcnt[v][dg];
+      const uint32_t pos = cursor[dg] + before + (uint32_t)__popcll(lower);
+      keys_out[pos] = key;
+      vals_out[pos] = vals[i];
+    }
+    __syncthreads();
+    if (active && lower == 0) {
+      bool first = true;
+      uint32_t tot = 0;
+      for (int v = 0; v < NW; ++v) {
+        tot += wcnt[v][dg];
+        if ((unsigned)v < w && wcnt[v][dg]) first = false;
+      }
+      if (first) cursor[dg] += tot;
+    }
+    __syncthreads();
+    if (active && lower == 0) wcnt[w][dg] = 0;
+    __syncthreads();
+  }
+}
+
+void sort_pairs_u32(uint32_t *keys, uint32_t *vals, size_t n, uint32_t key_bits, hipStream_t s,
+                    Arena &ar) {
+  if (n <= 1 || key_bits == 0) return;
+  const uint32_t n_chunks = (uint32_t)((n + kRsChunk - 1) / kRsChunk);
+  uint32_t *k2 = ar.get<uint32_t>(n), *v2 = ar.get<uint32_t>(n);
+  uint32_t *counts = ar.get<uint32_t>((size_t)kRsDigits * n_chunks);
+  uint32_t *ka = keys, *va = vals, *kb = k2, *vb = v2;
+  const uint32_t passes = (key_bits + 7) / 8;
+  for (uint32_t p = 0; p < passes; ++p) {
+    const uint32_t shift = 8 * p;
+    hipLaunchKernelGGL(k_rs_hist, dim3(n_chunks), dim3(kRsThreads), 0, s, ka, n, shift, n_chunks,
+                       counts);
+    GPA_LAUNCH_CHECK();
+    exclusive_scan_u32(counts, counts, (size_t)kRsDigits * n_chunks, s, ar);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(n_chunks), dim3(kRsThreads), 0, s, ka, va, n, shift,
+                       n_chunks, counts, kb, vb);
+    GPA_LAUNCH_CHECK();
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  if (ka != keys) {
+    GPA_HIP(hipMemcpyAsync(keys, ka, n * 4, hipMemcpyDeviceToDevice, s));
+    GPA_HIP(hipMemcpyAsync(vals, va, n * 4, hipMemcpyDeviceToDevice, s));
+  }
+}
+
+__global__ void k_iota_keys(const uint32_t *key, size_t n, uint32_t none_key, uint32_t *k,
+                            uint32_t *v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t x = key[i];
+    k[i] = (x == GPA_NONE) ? none_key : x;
+    v[i] = (uint32_t)i;
+  }
+}
+
+__global__ void k_key_count(size_t n, const uint32_t *key, uint32_t *cnt) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    if (key[i] != GPA_NONE) atomicAdd(&cnt[key[i]], 1u);
+}
+
+// ptr[n_keys+1] and perm: items with key k are perm[ptr[k] .. ptr[k+1]) in
+// item order; items whose key is GPA_NONE are left out (they sort last).
+void group_by_key(const uint32_t *key, size_t n, uint32_t n_keys, DBuf<uint32_t> &ptr,
+                  DBuf<uint32_t> &perm, hipStream_t s, Arena &ar) {
+  uint32_t *cnt = ar.get<uint32_t>((size_t)n_keys + 1);
+  GPA_HIP(hipMemsetAsync(cnt, 0, 4 * ((size_t)n_keys + 1), s));
+  if (n)
+    hipLaunchKernelGGL(k_key_count, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, key, cnt);
+  GPA_LAUNCH_CHECK();
+  ptr.alloc((size_t)n_keys + 1);
+  exclusive_scan_u32(cnt, ptr.p, (size_t)n_keys + 1, s, ar);
+  perm.alloc(n ? n : 1);
+  if (!n) return;
+  uint32_t *k = ar.get<uint32_t>(n);
+  hipLaunchKernelGGL(k_iota_keys, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, key, n, n_keys,
+                     k, perm.p);
+  GPA_LAUNCH_CHECK();
+  uint32_t bits = 1;
+  while (bits < 32 && (1ull << bits) <= n_keys) ++bits;
+  sort_pairs_u32(k, perm.p, n, bits, s, ar);
+}
+
+}  // namespace gpa

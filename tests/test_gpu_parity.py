@@ -95,8 +95,15 @@ def test_deterministic_bitwise():
 def test_large_workload_full_parity():
     """The 60k-instruction, 1,500-block profile with 20M samples, compared
     in full (the oracle finishes it in seconds)."""
+    import time
+    t = time.time()
     prog, rec = S.workload_large(seed=1)
-    g, o = _both(prog, rec)
+    print(f"\n  generated in {time.time() - t:.1f}s", flush=True)
+    g = run_gpu(prog, rec)
+    print(f"  gpu done at {time.time() - t:.1f}s", flush=True)
+    o = O.run_all(prog, rec)
+    print(f"  oracle done at {time.time() - t:.1f}s", flush=True)
+    compare(prog, g, o)
     assert g["info"]["n_edges"] > 100_000
 
 
