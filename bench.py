@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Throughput of the GPA hot path on one MI355X.
+
+One step is one pass of the whole path over one profile of the large
+single-kernel workload (60,000 instructions in 1,500 blocks, loop depth up to
+5, 255 registers + 7 predicates + 16 barriers, 20M PC-sample records with
+Zipf(1.2) PCs and a memory-dependency-heavy stall mix):
+
+  load     gpa_load_program: validation, reaching definitions, def-use
+           edges, CFG distances, static pruning and target scopes (Sec. 4);
+  attribute gpa_attribute: sample histogram (Sec. 2.1) and blame with
+           apportioning (Sec. 4.2, Eq. 1);
+  advise   gpa_advise: scope roll-up, estimated speedups (Eqs. 2-5) and the
+           ranked top-k, copied to the host.
+
+Inputs are resident in HBM before timing starts.  Three copies of the sample
+records (3 x 160 MB) are used in turn so that no step reads records another
+step left in the 256 MB last-level cache.  `value` is records per second of
+the whole step.  The roofline object is for the sample histogram, timed with
+hipEvents on the stream it runs on; its traffic field comes from the
+rocprofv3 counter summary under profiles/ when that summary was taken on the
+current source of the histogram kernels.  The CPU baseline is the oracle (test
+infrastructure) run on the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+HBM_PEAK_GBS = 8000.0
+HIST_SOURCE = os.path.join(HERE, "paper_2009_04061_amd", "csrc", "hist.hip")
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "hist_large_traffic.json")
+
+
+def _source_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic(n_launches_ref=None):
+    """HBM bytes per histogram pass from the committed counter summary, or
+    None when it is absent or was taken on another version of the kernels."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256_16") != _source_hash(HIST_SOURCE):
+        return None
+    return t.get("bytes_per_pass")
+
+
+def cpu_baseline(prog, rec, seconds):
+    """The oracle on the host: whole steps over the same workload until at
+    least `seconds` of CPU work has been done (at least one step)."""
+    from oracle import oracle
+    oracle.build(force=False)
+    times = []
+    out = None
+    t_all = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        out = oracle.run_all(prog, rec, 5)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_all >= seconds:
+            break
+    med = statistics.median(times)
+    n = len(rec)
+    return {"value": n / med, "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"the whole large workload ({n} records, {len(prog['op_class'])} "
+                      f"instructions), {len(times)} single-thread oracle steps, median "
+                      f"{med:.3f} s"}, out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="minimum CPU time spent on the oracle baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the comparison of one step with the oracle")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path has no multi-GPU code: one profile is processed by one GPU)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2009_04061_amd import gpa, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    gpa.lib()   # fails loudly when the library is not built
+
+    t0 = time.perf_counter()
+    prog, rec = synth.workload_large(seed=1)
+    gen_s = time.perf_counter() - t0
+    n_rec = len(rec)
+    n_instr = len(prog["op_class"])
+    print(f"# workload generated in {gen_s:.1f} s: {n_instr} instructions, {n_rec} records",
+          file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    dprog = gpa.program_to_device(prog, dev)
+    raw = np.ascontiguousarray(rec).view(np.uint8)
+    copies = [torch.from_numpy(raw).to(dev) for _ in range(3)]
+    torch.cuda.synchronize()
+
+    def step(k):
+        with torch.cuda.stream(stream):
+            P = gpa.Program(dprog, stream=stream)
+            B = P.attribute(copies[k % len(copies)], stream=stream)
+            A = B.advise(stream=stream)
+            top = A.topk(5)
+        return P, B, A, top
+
+    lat_adv = []
+    for k in range(args.warmup):
+        P, B, A, _ = step(k)
+        A.close(); B.close(); P.close()
+    torch.cuda.synchronize()
+
+    gpa.timing_enable(True)
+    gpa.timing_read(reset=True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        P, B, A, _ = step(k)
+        A.close(); B.close(); P.close()
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    ph = gpa.timing_read(reset=True)
+    gpa.timing_enable(False)
+
+    # per-call advise latency (host clock, call to advice on the host)
+    for k in range(args.steps):
+        P = gpa.Program(dprog, stream=stream)
+        B = P.attribute(copies[k % len(copies)], stream=stream)
+        t_a = time.perf_counter()
+        A = B.advise(stream=stream)
+        A.topk(5)
+        lat_adv.append(time.perf_counter() - t_a)
+        A.close(); B.close(); P.close()
+
+    ms_step = 1e3 * t_total / args.steps
+    value = n_rec * args.steps / t_total
+
+    phase_ms = {name: (ms / c if c else None) for name, (ms, c) in ph.items()}
+    hist_ms = phase_ms["hist"]
+    alg_bytes = 8.0 * n_rec + 96.0 * n_instr
+    achieved = alg_bytes / (hist_ms * 1e-3) / 1e9
+    traffic = _traffic()
+    roofline = {"bound": "hbm", "kernel": "gpa_hist (sample histogram pass)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "algorithmic_bytes": alg_bytes,
+                "avg_ms": round(hist_ms, 5)}
+
+    checked = None
+    base = None
+    if not args.no_cpu_baseline:
+        base, oracle_out = cpu_baseline(prog, rec, args.cpu_seconds)
+        if not args.no_check:
+            sys.path.insert(0, os.path.join(HERE, "tests"))
+            from parity import compare, run_gpu   # noqa: E402
+            g = run_gpu(prog, rec, device_inputs=True, k=5)
+            compare(prog, g, oracle_out, k=5)
+            checked = True
+
+    a_sorted = sorted(lat_adv)
+    p = lambda q: 1e3 * a_sorted[min(len(a_sorted) - 1, int(q * len(a_sorted)))]
+    line = {
+        "metric": "PC samples blamed/s, batched vs per-profile (oracle-exact); p99 advise latency",
+        "value": round(value, 1), "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32+f64", "data": "synthetic",
+        "config": {"workload": "large single kernel: 60k instructions, 1.5k blocks, loop depth "
+                               "<= 5, 255 R + 7 P + 16 B, 20M records, Zipf 1.2, seed 1",
+                   "records": n_rec, "instructions": n_instr, "path": "per-profile"},
+        "phase_ms": {k: (round(v, 4) if v is not None else None) for k, v in phase_ms.items()},
+        "advise_latency_ms": {"p50": round(p(0.5), 4), "p99": round(p(0.99), 4)},
+        "samples_per_s_resident_program": round(
+            n_rec / (1e-3 * (phase_ms["hist"] + phase_ms["blame"] + phase_ms["advise"])), 1),
+        "oracle_exact": checked,
+        "roofline": roofline,
+        "cpu_baseline": base,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

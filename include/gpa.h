@@ -200,6 +200,16 @@ gpa_status gpa_advice_get(const gpa_advice *a, double *active, double *matched, 
 gpa_status gpa_advice_topk(const gpa_advice *a, uint32_t k, uint32_t *opt, uint32_t *scope,
                            double *speedup);
 
+/* Instrumentation (for benchmarks and profiling tools).  When enabled, the
+ * library records a hipEvent pair on the caller's stream around each phase
+ * and accumulates the elapsed device time once the call has synchronized.
+ * Phases: 0 sample aggregation, 1 blame, 2 whole program load, 3 advise,
+ * 4 reaching definitions and edges, 5 distances.  gpa_timing_read copies
+ * up to max_phases accumulated milliseconds and call counts (either pointer
+ * may be NULL), optionally resets them, and returns the number of phases. */
+void gpa_timing_enable(int on);
+uint32_t gpa_timing_read(double *ms, uint64_t *calls, uint32_t max_phases, int reset);
+
 /* Thread-local description of the last failure on this thread. */
 const char *gpa_last_error(void);
 

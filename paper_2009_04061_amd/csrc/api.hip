@@ -92,6 +92,46 @@ void dev_free(void *p) {
   g_free[it->second].push_back(p);
 }
 
+// ------------------------------------------------------------- timing
+namespace {
+std::mutex g_tmu;
+bool g_timing = false;
+double g_ms[kNumPhases] = {0};
+uint64_t g_calls[kNumPhases] = {0};
+}  // namespace
+
+void PhaseTimer::begin(int ph, hipStream_t s) {
+  {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (!g_timing) return;
+  }
+  phase = ph;
+  GPA_HIP(hipEventCreate(&a));
+  GPA_HIP(hipEventCreate(&b));
+  GPA_HIP(hipEventRecord(a, s));
+}
+
+void PhaseTimer::end(hipStream_t s) {
+  if (phase < 0) return;
+  GPA_HIP(hipEventRecord(b, s));
+}
+
+void PhaseTimer::collect() {
+  if (phase < 0) return;
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) == hipSuccess) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_ms[phase] += ms;
+    g_calls[phase] += 1;
+  }
+  phase = -1;
+}
+
+PhaseTimer::~PhaseTimer() {
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+}
+
 template <typename T>
 static void upload(DBuf<T> &dst, const T *src, size_t n, bool on_device, hipStream_t s) {
   dst.alloc(n);
@@ -139,6 +179,26 @@ using namespace gpa;
 extern "C" {
 
 const char *gpa_last_error(void) { return g_err.c_str(); }
+
+void gpa_timing_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_timing = on != 0;
+}
+
+uint32_t gpa_timing_read(double *ms, uint64_t *calls, uint32_t max_phases, int reset) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  const uint32_t n = max_phases < (uint32_t)kNumPhases ? max_phases : (uint32_t)kNumPhases;
+  for (uint32_t k = 0; k < n; ++k) {
+    if (ms) ms[k] = g_ms[k];
+    if (calls) calls[k] = g_calls[k];
+  }
+  if (reset)
+    for (int k = 0; k < kNumPhases; ++k) {
+      g_ms[k] = 0.0;
+      g_calls[k] = 0;
+    }
+  return (uint32_t)kNumPhases;
+}
 
 gpa_status gpa_load_program(const gpa_program_desc *d, void *stream, gpa_program **out) {
   if (!d || !out) {
@@ -193,12 +253,22 @@ gpa_status gpa_load_program(const gpa_program_desc *d, void *stream, gpa_program
     upload(p->scope_kind, d->scope_kind, p->n_scopes, dev, s);
     upload(p->scope_flags, d->scope_flags, p->n_scopes, dev, s);
     Arena ar;
+    PhaseTimer t_load, t_rd, t_dist;
+    t_load.begin(kPhaseLoad, s);
     validate_and_build_structure(*p, s, ar);
+    t_rd.begin(kPhaseRd, s);
     build_reaching_defs(*p, s, ar);
     build_edges(*p, s, ar);
+    t_rd.end(s);
+    t_dist.begin(kPhaseDist, s);
     build_distances(*p, s, ar);
+    t_dist.end(s);
     build_scope_targets(*p, s, ar);
+    t_load.end(s);
     GPA_HIP(hipStreamSynchronize(s));
+    t_load.collect();
+    t_rd.collect();
+    t_dist.collect();
   });
   if (st != GPA_OK) {
     if (s) (void)hipStreamSynchronize(s);
@@ -284,10 +354,17 @@ gpa_status gpa_attribute(gpa_program *p, const gpa_sample *samples, uint64_t n,
     }
     b->counts.alloc((size_t)p->n_instr * 24);
     b->dtotals.alloc(4);
+    PhaseTimer t_hist, t_blame;
+    t_hist.begin(kPhaseHist, s);
     run_hist(*p, dsamp, n, b->counts.p, b->dtotals.p, s, ar);
+    t_hist.end(s);
+    t_blame.begin(kPhaseBlame, s);
     run_blame(*p, *b, s, ar);
+    t_blame.end(s);
     GPA_HIP(hipMemcpyAsync(b->totals, b->dtotals.p, sizeof(b->totals), hipMemcpyDeviceToHost, s));
     GPA_HIP(hipStreamSynchronize(s));
+    t_hist.collect();
+    t_blame.collect();
   });
   if (st != GPA_OK) {
     if (s) (void)hipStreamSynchronize(s);
@@ -353,8 +430,12 @@ gpa_status gpa_advise(const gpa_blame *b, void *stream, gpa_advice **out) {
     a = new gpa_advice();
     a->prog = b->prog;
     Arena ar;
+    PhaseTimer t_adv;
+    t_adv.begin(kPhaseAdvise, s);
     run_estimate(*b->prog, *b, *a, 16, s, ar);
+    t_adv.end(s);
     GPA_HIP(hipStreamSynchronize(s));
+    t_adv.collect();
   });
   if (st != GPA_OK) {
     if (s) (void)hipStreamSynchronize(s);

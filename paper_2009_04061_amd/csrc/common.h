@@ -87,7 +87,7 @@ struct gpa_program {
   uint32_t n_instr = 0, n_blocks = 0, n_funcs = 0, n_scopes = 0;
   uint32_t n_regs = 0, n_preds = 0, n_bars = 0, n_loc = 0;
   uint32_t n_defs = 0, n_uses = 0, n_succ = 0;
-  uint32_t max_func_blocks = 0;
+  uint32_t max_func_blocks = 0, max_func_edges = 0;
   gpa_arch arch{};
   uint32_t n_blamable = 0;
   // device copies of the descriptor
@@ -119,6 +119,7 @@ struct gpa_program {
   gpa::DBuf<uint32_t> e_lca, e_icl;            // per edge target scopes
   gpa::DBuf<uint8_t> instr_tags;               // bit0 in math fn, bit1 in device fn with CFG
   gpa::DBuf<uint32_t> lca_ptr, lca_perm, icl_ptr, icl_perm, line_ptr, line_perm;
+  uint64_t n_icl = 0;                          // edges with a common loop
   gpa::DBuf<uint32_t> roots;                   // kernel root scope ids
   uint32_t n_roots = 0;
   hipStream_t stream = nullptr;
@@ -174,6 +175,19 @@ void run_blame(const gpa_program &p, gpa_blame &b, hipStream_t s, Arena &ar);
 // estimate.hip
 void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint32_t k,
                   hipStream_t s, Arena &ar);
+
+// Opt-in phase timing with hipEvents on the caller's stream (gpa_timing_*):
+// a phase records an event pair; the pair's elapsed time is accumulated when
+// the API call that launched it has synchronized its stream.
+enum Phase { kPhaseHist = 0, kPhaseBlame, kPhaseLoad, kPhaseAdvise, kPhaseRd, kPhaseDist, kNumPhases };
+struct PhaseTimer {
+  hipEvent_t a = nullptr, b = nullptr;
+  int phase = -1;
+  void begin(int ph, hipStream_t s);
+  void end(hipStream_t s);
+  void collect();   // after the stream has been synchronized
+  ~PhaseTimer();
+};
 
 // read a few device words synchronously
 template <typename T>

@@ -74,41 +74,75 @@ __global__ void k_edge_contrib(uint64_t n_edges, uint32_t nbl, int s_mem, int s_
   }
 }
 
-// own sums of each scope: its instructions, then the edges targeting it
-__global__ void k_scope_own(uint32_t n_scopes, const uint32_t *line_ptr, const uint32_t *line_perm,
-                            const uint32_t *icl_ptr, const uint32_t *icl_perm,
-                            const uint32_t *lca_ptr, const uint32_t *lca_perm, const double *iv,
-                            const double *ev, double *own) {
-  for (uint32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < n_scopes;
-       l += gridDim.x * blockDim.x) {
-    double v[kNV];
-    for (int q = 0; q < kNV; ++q) v[q] = 0.0;
-    for (uint32_t k = line_ptr[l]; k < line_ptr[l + 1]; ++k) {
-      const double *x = iv + (size_t)line_perm[k] * kNV;
-      for (int q = 0; q < kNV; ++q) v[q] += x[q];
-    }
-    for (uint32_t k = icl_ptr[l]; k < icl_ptr[l + 1]; ++k) v[GPA_O_LOOP_UNROLLING] += ev[icl_perm[k]];
-    for (uint32_t k = lca_ptr[l]; k < lca_ptr[l + 1]; ++k) v[GPA_O_CODE_REORDERING] += ev[lca_perm[k]];
-    for (int q = 0; q < kNV; ++q) own[(size_t)l * kNV + q] = v[q];
+// values gathered into group order, so every group is a contiguous range
+template <int W>
+__global__ void k_gather(size_t n, const uint32_t *perm, const double *src, double *dst) {
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * blockDim.x) {
+    const double *x = src + (size_t)perm[k] * W;
+#pragma unroll
+    for (int q = 0; q < W; ++q) dst[k * W + q] = x[q];
   }
 }
 
-// one wave per scope: sum of `own` over the preorder range [l, end(l))
+// Segmented sums over contiguous ranges: one workgroup per segment l,
+// range [begin(l), end(l)) given either by ptr[l], ptr[l+1] (ptr mode) or by
+// l, end[l] (subtree mode).  Each thread owns a fixed stride of the range and
+// the block reduction has a fixed shape, so the result is deterministic.
+template <int W>
 __global__ void __launch_bounds__(256)
-k_subtree(uint32_t n_scopes, const uint32_t *scope_end, const double *own, double *sub) {
-  const uint32_t l = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (l >= n_scopes) return;
-  const unsigned lane = lane_id();
-  const uint32_t end = scope_end[l];
-  double v[kNV];
-  for (int q = 0; q < kNV; ++q) v[q] = 0.0;
-  for (uint32_t s = l + lane; s < end; s += kWave) {
-    const double *x = own + (size_t)s * kNV;
-    for (int q = 0; q < kNV; ++q) v[q] += x[q];
+k_seg_sum(uint32_t n_seg, const uint32_t *ptr, const uint32_t *end, const double *data,
+          double *out, int accumulate) {
+  __shared__ double red[4][W];
+  const uint32_t l = blockIdx.x;
+  if (l >= n_seg) return;
+  const uint32_t a = ptr ? ptr[l] : l;
+  const uint32_t b = ptr ? ptr[l + 1] : end[l];
+  double v[W];
+#pragma unroll
+  for (int q = 0; q < W; ++q) v[q] = 0.0;
+  uint32_t i = a + threadIdx.x;
+  for (; i + 3 * 256 < b; i += 4 * 256) {
+    double t0[W], t1[W], t2[W], t3[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      t0[q] = data[(size_t)i * W + q];
+      t1[q] = data[(size_t)(i + 256) * W + q];
+      t2[q] = data[(size_t)(i + 512) * W + q];
+      t3[q] = data[(size_t)(i + 768) * W + q];
+    }
+#pragma unroll
+    for (int q = 0; q < W; ++q) v[q] += ((t0[q] + t1[q]) + (t2[q] + t3[q]));
   }
-  for (int q = 0; q < kNV; ++q) v[q] = wave_sum(v[q]);
-  if (lane == 0)
-    for (int q = 0; q < kNV; ++q) sub[(size_t)l * kNV + q] = v[q];
+  for (; i < b; i += 256) {
+#pragma unroll
+    for (int q = 0; q < W; ++q) v[q] += data[(size_t)i * W + q];
+  }
+#pragma unroll
+  for (int q = 0; q < W; ++q) v[q] = wave_sum(v[q]);
+  const unsigned w = threadIdx.x / kWave;
+  if (lane_id() == 0)
+#pragma unroll
+    for (int q = 0; q < W; ++q) red[w][q] = v[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      const double s = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+      if (accumulate) out[(size_t)l * W + q] += s;
+      else out[(size_t)l * W + q] = s;
+    }
+  }
+}
+
+// own sums of the two edge optimizers, merged into the per-scope vectors
+__global__ void k_merge_edge_own(uint32_t n_scopes, const double *own_icl, const double *own_lca,
+                                 double *own) {
+  for (uint32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < n_scopes;
+       l += gridDim.x * blockDim.x) {
+    own[(size_t)l * kNV + GPA_O_LOOP_UNROLLING] = own_icl[l];
+    own[(size_t)l * kNV + GPA_O_CODE_REORDERING] = own_lca[l];
+  }
 }
 
 __global__ void k_speedup(uint32_t n_scopes, const uint32_t *parent, const uint32_t *root_of,
@@ -136,6 +170,10 @@ __global__ void k_speedup(uint32_t n_scopes, const uint32_t *parent, const uint3
 }
 
 // ------------------------------------------------------------------ top-k
+// Two stages: chunks of one kernel's (scope, optimizer) items each keep a
+// top-16 per thread in registers and merge it across the workgroup; one
+// workgroup per kernel then merges its chunks' candidates.  Order: speedup
+// descending, then optimizer, then scope ascending (a total order).
 struct Cand {
   double s;
   uint32_t o, l;
@@ -147,39 +185,35 @@ __device__ __forceinline__ bool better(const Cand &a, const Cand &b) {
   return a.l < b.l;
 }
 
-constexpr int kTopMax = 16;
+constexpr int kTopK = 16;
 constexpr int kTopThreads = 256;
+constexpr uint32_t kTopChunk = 16384;   // items per stage-1 workgroup
 
-__global__ void __launch_bounds__(kTopThreads)
-k_topk(const uint32_t *roots, const uint32_t *scope_end, const double *speedup, uint32_t k,
-       uint32_t *top_opt, uint32_t *top_scope, double *top_speed) {
-  __shared__ Cand red[kTopThreads];
-  const uint32_t r = roots[blockIdx.x];
-  const uint32_t end = scope_end[r];
-  const uint64_t n_items = (uint64_t)(end - r) * GPA_N_OPT;
-  Cand mine[kTopMax];
-  uint32_t nm = 0;
-  for (uint64_t it = threadIdx.x; it < n_items; it += kTopThreads) {
-    Cand c;
-    c.l = r + (uint32_t)(it / GPA_N_OPT);
-    c.o = (uint32_t)(it % GPA_N_OPT);
-    c.s = speedup[(size_t)c.l * GPA_N_OPT + c.o];
-    if (nm == k && !better(c, mine[k - 1])) continue;
-    uint32_t p = (nm < k) ? nm++ : k - 1;
-    while (p > 0 && better(c, mine[p - 1])) {
-      mine[p] = mine[p - 1];
-      --p;
+__device__ __forceinline__ Cand cand_none() {
+  Cand c;
+  c.s = -1.0;
+  c.o = 0xFFFFFFFFu;
+  c.l = 0xFFFFFFFFu;
+  return c;
+}
+
+__device__ __forceinline__ void top_insert(Cand (&top)[kTopK], const Cand &c) {
+  if (!better(c, top[kTopK - 1])) return;
+  top[kTopK - 1] = c;
+#pragma unroll
+  for (int i = kTopK - 1; i > 0; --i) {
+    if (better(top[i], top[i - 1])) {
+      const Cand t = top[i];
+      top[i] = top[i - 1];
+      top[i - 1] = t;
     }
-    mine[p] = c;
   }
-  uint32_t head = 0;
-  for (uint32_t t = 0; t < k; ++t) {
-    Cand c;
-    c.s = -1.0;
-    c.o = 0xFFFFFFFFu;
-    c.l = 0xFFFFFFFFu;
-    if (head < nm) c = mine[head];
-    red[threadIdx.x] = c;
+}
+
+// the workgroup's best 16 in order into out[0..16)
+__device__ void block_merge(Cand (&top)[kTopK], Cand *red, Cand *out) {
+  for (int t = 0; t < kTopK; ++t) {
+    red[threadIdx.x] = top[0];
     __syncthreads();
     for (int w = kTopThreads / 2; w > 0; w >>= 1) {
       if ((int)threadIdx.x < w && better(red[threadIdx.x + w], red[threadIdx.x]))
@@ -188,13 +222,71 @@ k_topk(const uint32_t *roots, const uint32_t *scope_end, const double *speedup, 
     }
     const Cand best = red[0];
     __syncthreads();
-    if (best.o == 0xFFFFFFFFu) break;
-    if (head < nm && mine[head].o == best.o && mine[head].l == best.l) ++head;
-    if (threadIdx.x == 0) {
-      top_opt[(size_t)r * k + t] = best.o;
-      top_scope[(size_t)r * k + t] = best.l;
-      top_speed[(size_t)r * k + t] = best.s;
+    if (threadIdx.x == 0) out[t] = best;
+    if (best.o != 0xFFFFFFFFu && top[0].o == best.o && top[0].l == best.l) {
+#pragma unroll
+      for (int i = 0; i < kTopK - 1; ++i) top[i] = top[i + 1];
+      top[kTopK - 1] = cand_none();
     }
+  }
+}
+
+__global__ void k_topk_plan(uint32_t n_roots, const uint32_t *roots, const uint32_t *scope_end,
+                            uint32_t *nchunks) {
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n_roots; r += gridDim.x * blockDim.x) {
+    const uint64_t items = (uint64_t)(scope_end[roots[r]] - roots[r]) * GPA_N_OPT;
+    nchunks[r] = (uint32_t)((items + kTopChunk - 1) / kTopChunk);
+  }
+}
+
+__global__ void __launch_bounds__(kTopThreads)
+k_topk_chunks(uint32_t n_roots, const uint32_t *roots, const uint32_t *nchunks,
+              const uint32_t *chunk_start, const uint32_t *scope_end, const double *speedup,
+              Cand *cand) {
+  __shared__ Cand red[kTopThreads];
+  const uint32_t c = blockIdx.x;
+  const uint32_t total = chunk_start[n_roots - 1] + nchunks[n_roots - 1];
+  if (c >= total) return;
+  const uint32_t ri = upper_index_u32(chunk_start, 0, n_roots, c);
+  const uint32_t r = roots[ri];
+  const uint64_t n_items = (uint64_t)(scope_end[r] - r) * GPA_N_OPT;
+  const uint64_t a = (uint64_t)(c - chunk_start[ri]) * kTopChunk;
+  const uint64_t b = min(a + kTopChunk, n_items);
+  Cand top[kTopK];
+#pragma unroll
+  for (int i = 0; i < kTopK; ++i) top[i] = cand_none();
+  const double *base = speedup + (size_t)r * GPA_N_OPT;
+  for (uint64_t it = a + threadIdx.x; it < b; it += kTopThreads) {
+    Cand x;
+    x.s = base[it];
+    x.l = r + (uint32_t)(it / GPA_N_OPT);
+    x.o = (uint32_t)(it % GPA_N_OPT);
+    top_insert(top, x);
+  }
+  block_merge(top, red, cand + (size_t)c * kTopK);
+}
+
+__global__ void __launch_bounds__(kTopThreads)
+k_topk_final(const uint32_t *roots, const uint32_t *nchunks, const uint32_t *chunk_start,
+             const Cand *cand, uint32_t k, uint32_t *top_opt, uint32_t *top_scope,
+             double *top_speed) {
+  __shared__ Cand red[kTopThreads];
+  __shared__ Cand best[kTopK];
+  const uint32_t ri = blockIdx.x, r = roots[ri];
+  const uint32_t n = nchunks[ri] * kTopK;
+  const Cand *src = cand + (size_t)chunk_start[ri] * kTopK;
+  Cand top[kTopK];
+#pragma unroll
+  for (int i = 0; i < kTopK; ++i) top[i] = cand_none();
+  for (uint32_t it = threadIdx.x; it < n; it += kTopThreads)
+    if (src[it].o != 0xFFFFFFFFu) top_insert(top, src[it]);
+  block_merge(top, red, best);
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < k; t += kTopThreads) {
+    const Cand c = best[t];
+    top_opt[(size_t)r * k + t] = c.o;
+    top_scope[(size_t)r * k + t] = c.l;
+    top_speed[(size_t)r * k + t] = c.o == 0xFFFFFFFFu ? 0.0 : c.s;
   }
 }
 
@@ -221,15 +313,32 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint3
   double *ev = ar.get<double>(p.n_edges);
   double *own = ar.get<double>((size_t)ns * kNV);
   double *sub = ar.get<double>((size_t)ns * kNV);
+  double *iv_g = ar.get<double>((size_t)n * kNV);
+  double *ev_icl = ar.get<double>(p.n_edges), *ev_lca = ar.get<double>(p.n_edges);
+  double *own_icl = ar.get<double>(ns), *own_lca = ar.get<double>(ns);
   hipLaunchKernelGGL(k_instr_contrib, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, nbl, bl,
                      b.counts.p, b.blamed.p, b.self_.p, p.op_class.p, p.instr_tags.p, iv);
-  if (p.n_edges)
+  hipLaunchKernelGGL(k_gather<kNV>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, (size_t)n,
+                     p.line_perm.p, iv, iv_g);
+  hipLaunchKernelGGL(k_seg_sum<kNV>, dim3(ns), dim3(256), 0, s, ns, p.line_ptr.p, nullptr, iv_g,
+                     own, 0);
+  if (p.n_edges) {
     hipLaunchKernelGGL(k_edge_contrib, dim3(grid_for(p.n_edges, 256, 8192)), dim3(256), 0, s,
                        p.n_edges, nbl, s_mem, s_exec, p.e_src.p, p.op_class.p, b.share.p, ev);
-  hipLaunchKernelGGL(k_scope_own, dim3(grid_for(ns, 256, 8192)), dim3(256), 0, s, ns, p.line_ptr.p,
-                     p.line_perm.p, p.icl_ptr.p, p.icl_perm.p, p.lca_ptr.p, p.lca_perm.p, iv, ev,
-                     own);
-  hipLaunchKernelGGL(k_subtree, dim3((ns + 3) / 4), dim3(256), 0, s, ns, p.scope_end.p, own, sub);
+    // edges without a common loop are not in the icl grouping: its size is icl_ptr[ns]
+    hipLaunchKernelGGL(k_gather<1>, dim3(grid_for(p.n_edges, 256, 8192)), dim3(256), 0, s,
+                       (size_t)p.n_icl, p.icl_perm.p, ev, ev_icl);
+    hipLaunchKernelGGL(k_gather<1>, dim3(grid_for(p.n_edges, 256, 8192)), dim3(256), 0, s,
+                       (size_t)p.n_edges, p.lca_perm.p, ev, ev_lca);
+  }
+  hipLaunchKernelGGL(k_seg_sum<1>, dim3(ns), dim3(256), 0, s, ns, p.icl_ptr.p, nullptr, ev_icl,
+                     own_icl, 0);
+  hipLaunchKernelGGL(k_seg_sum<1>, dim3(ns), dim3(256), 0, s, ns, p.lca_ptr.p, nullptr, ev_lca,
+                     own_lca, 0);
+  hipLaunchKernelGGL(k_merge_edge_own, dim3(grid_for(ns, 256, 8192)), dim3(256), 0, s, ns, own_icl,
+                     own_lca, own);
+  hipLaunchKernelGGL(k_seg_sum<kNV>, dim3(ns), dim3(256), 0, s, ns, nullptr, p.scope_end.p, own,
+                     sub, 0);
   GPA_LAUNCH_CHECK();
   a.active.alloc(ns);
   a.matched.alloc((size_t)ns * GPA_N_OPT);
@@ -252,10 +361,19 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint3
                        a.top_scope.p, (size_t)ns * k, GPA_NONE);
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((size_t)ns * k, 256, 4096)), dim3(256), 0, s,
                        a.top_speed.p, (size_t)ns * k, 0.0);
-    if (p.n_roots)
-      hipLaunchKernelGGL(k_topk, dim3(p.n_roots), dim3(kTopThreads), 0, s, p.roots.p,
-                         p.scope_end.p, a.speedup.p, k, a.top_opt.p, a.top_scope.p,
-                         a.top_speed.p);
+    if (p.n_roots) {
+      uint32_t *nch = ar.get<uint32_t>(p.n_roots), *cst = ar.get<uint32_t>(p.n_roots);
+      hipLaunchKernelGGL(k_topk_plan, dim3(grid_for(p.n_roots, 256, 1024)), dim3(256), 0, s,
+                         p.n_roots, p.roots.p, p.scope_end.p, nch);
+      exclusive_scan_u32(nch, cst, p.n_roots, s, ar);
+      // every scope is in exactly one kernel's subtree: chunks <= items/chunk + roots
+      const uint64_t max_chunks = ((uint64_t)ns * GPA_N_OPT) / kTopChunk + p.n_roots + 1;
+      Cand *cand = ar.get<Cand>(max_chunks * kTopK);
+      hipLaunchKernelGGL(k_topk_chunks, dim3((unsigned)max_chunks), dim3(kTopThreads), 0, s,
+                         p.n_roots, p.roots.p, nch, cst, p.scope_end.p, a.speedup.p, cand);
+      hipLaunchKernelGGL(k_topk_final, dim3(p.n_roots), dim3(kTopThreads), 0, s, p.roots.p, nch,
+                         cst, cand, k, a.top_opt.p, a.top_scope.p, a.top_speed.p);
+    }
     GPA_LAUNCH_CHECK();
   }
 }

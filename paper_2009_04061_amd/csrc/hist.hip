@@ -2,16 +2,19 @@
 //
 // Device-wide atomics on MI355X retire far slower than HBM streams records,
 // and Zipf-distributed PCs serialize them on hot bins, so the histogram is
-// built without them:
-//   k_partition   one workgroup per tile of kTile records: validity check,
-//                 LDS counting sort by PC bucket (kBucketPCs consecutive PCs),
-//                 the tile's valid records written back as 2-byte payloads
-//                 (pc offset in bucket, stall, latency bit) grouped by bucket,
-//                 plus the tile's bucket offsets and its totals;
-//   k_bucket_plan per bucket: records over all tiles, number of work items;
-//   k_count       one workgroup per work item (a bucket and a range of tiles):
-//                 LDS histogram of the bucket's 512 x 24 bins, written once to
-//                 the output (single item) or to a partial slot;
+// built without them, in two passes over the records and one over 2-byte
+// payloads:
+//   k_bcount      per tile of kTile records: LDS histogram of PC buckets
+//                 (kBucketPCs consecutive PCs) and the tile's totals;
+//   scan          bucket-major over (bucket, tile): where each tile's run of
+//                 each bucket goes, so that every bucket is one contiguous
+//                 range of payloads;
+//   k_partition   per tile: the records again, an LDS counting sort by bucket
+//                 and the runs written as payloads (pc offset in bucket,
+//                 stall, latency bit) at their positions;
+//   k_count       per work item (a contiguous range of one bucket): LDS
+//                 histogram of the bucket's 512 x 24 bins, written once to
+//                 the output (whole bucket) or to a partial slot;
 //   k_merge       per split bucket: sum of its partial slots.
 // Every output bin is written exactly once; integer sums are exact in any order.
 #include "common.h"
@@ -20,92 +23,90 @@
 namespace gpa {
 
 constexpr int kHistThreads = 256;
-constexpr int kTile = 16384;                    // records per partition tile (u16 offsets)
-constexpr int kPerThread = kTile / kHistThreads;
+constexpr int kTile = 16384;                    // records per tile
+constexpr int kBatch = 16;                      // records per thread per batch (8 x 16 B loads)
+constexpr int kBatches = kTile / (kHistThreads * kBatch);
 constexpr int kBucketShift = 9;
 constexpr int kBucketPCs = 1 << kBucketShift;   // 512 PCs -> 12288 bins = 48 KiB of LDS
 constexpr int kBucketBins = kBucketPCs * 24;
 constexpr int kMaxBuckets = 8192;
-constexpr uint32_t kItemRecords = 1u << 16;     // target records per counting work item
+constexpr uint32_t kItemRecords = 1u << 16;     // records per counting work item
+
+typedef unsigned long u64x2 __attribute__((ext_vector_type(2)));
 
 struct TileTotals {
   uint32_t valid, latency, dropped, pad;
 };
 
+__device__ __forceinline__ bool rec_valid(uint64_t r, uint32_t n_instr) {
+  const uint32_t pc = (uint32_t)r, hi = (uint32_t)(r >> 32);
+  return pc < n_instr && (hi & 0xFFu) < 12u && ((hi >> 8) & 0xFEu) == 0u && (hi >> 16) == 0u;
+}
+
+// The tile's records in batches of kBatch per thread: record q of a batch
+// sits at local index bt*4096 + (q/2)*512 + 2*tid + (q&1); two records per
+// 16-byte load, 1 KiB contiguous per wave instruction.
+template <bool VEC>
+__device__ __forceinline__ void load_batch(const uint64_t *__restrict__ rec, uint64_t n,
+                                           uint64_t base, int bt, uint64_t (&v)[kBatch]) {
+  const unsigned tid = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < kBatch / 2; ++j) {
+    const uint64_t idx = base + (uint64_t)bt * 4096 + (uint64_t)j * 512 + 2 * tid;
+    if (VEC && idx + 1 < n) {
+      const u64x2 x = __builtin_nontemporal_load((const u64x2 *)(rec + idx));
+      v[2 * j] = x.x;
+      v[2 * j + 1] = x.y;
+    } else {
+      v[2 * j] = idx < n ? rec[idx] : 0ull;
+      v[2 * j + 1] = idx + 1 < n ? rec[idx + 1] : 0ull;
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t local_index(int bt, int q) {
+  return (uint32_t)bt * 4096u + (uint32_t)(q / 2) * 512u + 2u * threadIdx.x + (uint32_t)(q & 1);
+}
+
+template <bool VEC>
 __global__ void __launch_bounds__(kHistThreads)
-k_partition(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint32_t n_buckets,
-            uint16_t *__restrict__ payload, uint16_t *__restrict__ tile_off,
-            TileTotals *__restrict__ tile_tot) {
-  extern __shared__ uint32_t smem[];
-  uint32_t *cnt = smem;                                   // [n_buckets + 1]
-  uint16_t *arrival = (uint16_t *)(smem + ((n_buckets + 4) & ~3u));
-  uint16_t *sorted = arrival + kTile;
-  __shared__ uint32_t scan_tmp[kHistThreads / kWave + 1];
+k_bcount(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint32_t n_buckets,
+         uint32_t n_tiles, uint32_t *__restrict__ tile_cnt, TileTotals *__restrict__ tile_tot) {
+  extern __shared__ uint32_t cnt[];   // [n_buckets]
   __shared__ uint32_t red[3];
   const unsigned tid = threadIdx.x;
   const uint64_t base = (uint64_t)blockIdx.x * kTile;
-  for (uint32_t b = tid; b <= n_buckets; b += kHistThreads) cnt[b] = 0;
+  for (uint32_t b = tid; b < n_buckets; b += kHistThreads) cnt[b] = 0;
   if (tid < 3) red[tid] = 0;
   __syncthreads();
-  uint32_t rank[kPerThread];
   uint32_t my_valid = 0, my_lat = 0, my_drop = 0;
 #pragma unroll
-  for (int k = 0; k < kPerThread; ++k) {
-    const uint64_t idx = base + (uint64_t)k * kHistThreads + tid;
-    rank[k] = 0xFFFFFFFFu;
-    if (idx < n) {
-      const uint64_t r = __builtin_nontemporal_load(&rec[idx]);
-      const uint32_t lo = (uint32_t)r, hi = (uint32_t)(r >> 32);
-      const uint32_t pc = lo, stall = hi & 0xFFu, flags = (hi >> 8) & 0xFFu, resv = hi >> 16;
-      if (pc < n_instr && stall < 12u && (flags & ~1u) == 0u && resv == 0u) {
-        const uint32_t b = pc >> kBucketShift;
-        const uint32_t pl = ((pc & (kBucketPCs - 1)) << 5) | (stall * 2u + flags);
-        const uint32_t rk = atomicAdd(&cnt[b], 1u);
-        arrival[k * kHistThreads + tid] = (uint16_t)pl;
-        rank[k] = (b << 16) | rk;
-        my_valid += 1;
-        my_lat += flags;
+  for (int bt = 0; bt < kBatches; ++bt) {
+    uint64_t v[kBatch];
+    load_batch<VEC>(rec, n, base, bt, v);
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      if (base + local_index(bt, q) >= n) continue;
+      if (rec_valid(v[q], n_instr)) {
+        atomicAdd(&cnt[(uint32_t)v[q] >> kBucketShift], 1u);
+        ++my_valid;
+        my_lat += (uint32_t)(v[q] >> 40) & 1u;
       } else {
-        my_drop += 1;
+        ++my_drop;
       }
     }
   }
-  // exclusive scan of the bucket counts (n_buckets <= kMaxBuckets)
-  __syncthreads();
-  {
-    const uint32_t per = (n_buckets + kHistThreads - 1) / kHistThreads;
-    const uint32_t b0 = tid * per, b1 = min(b0 + per, n_buckets);
-    uint32_t s = 0;
-    for (uint32_t b = b0; b < b1; ++b) s += cnt[b];
-    uint32_t total;
-    uint32_t run = block_excl_scan<kHistThreads>(s, scan_tmp, &total);
-    for (uint32_t b = b0; b < b1; ++b) {
-      uint32_t c = cnt[b];
-      cnt[b] = run;
-      run += c;
-    }
-    if (tid == 0) cnt[n_buckets] = total;
+  my_valid = wave_sum(my_valid);
+  my_lat = wave_sum(my_lat);
+  my_drop = wave_sum(my_drop);
+  if (lane_id() == 0) {
+    atomicAdd(&red[0], my_valid);
+    atomicAdd(&red[1], my_lat);
+    atomicAdd(&red[2], my_drop);
   }
   __syncthreads();
-  uint16_t *toff = tile_off + (size_t)blockIdx.x * (n_buckets + 1);
-  for (uint32_t b = tid; b <= n_buckets; b += kHistThreads) toff[b] = (uint16_t)cnt[b];
-#pragma unroll
-  for (int k = 0; k < kPerThread; ++k) {
-    if (rank[k] != 0xFFFFFFFFu) {
-      const uint32_t b = rank[k] >> 16, rk = rank[k] & 0xFFFFu;
-      sorted[cnt[b] + rk] = arrival[k * kHistThreads + tid];
-    }
-  }
-  atomicAdd(&red[0], my_valid);
-  atomicAdd(&red[1], my_lat);
-  atomicAdd(&red[2], my_drop);
-  __syncthreads();
-  const uint32_t nvalid = cnt[n_buckets];
-  uint16_t *out = payload + base;
-  // coalesced write-back of the grouped payloads, two per 32-bit word
-  const uint32_t *s32 = (const uint32_t *)sorted;
-  uint32_t *o32 = (uint32_t *)out;
-  for (uint32_t w = tid; w < (nvalid + 1) / 2; w += kHistThreads) o32[w] = s32[w];
+  for (uint32_t b = tid; b < n_buckets; b += kHistThreads)
+    tile_cnt[(size_t)b * n_tiles + blockIdx.x] = cnt[b];
   if (tid == 0) {
     TileTotals t;
     t.valid = red[0];
@@ -116,27 +117,76 @@ k_partition(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint
   }
 }
 
-// per bucket: records over all tiles and the number of counting items
+template <bool VEC>
 __global__ void __launch_bounds__(kHistThreads)
-k_bucket_plan(const uint16_t *__restrict__ tile_off, uint32_t n_tiles, uint32_t n_buckets,
-              uint32_t *__restrict__ items) {
-  __shared__ uint32_t red[kHistThreads / kWave];
-  const uint32_t b = blockIdx.x;
-  uint32_t s = 0;
-  for (uint32_t t = threadIdx.x; t < n_tiles; t += kHistThreads) {
-    const uint16_t *o = tile_off + (size_t)t * (n_buckets + 1);
-    s += (uint32_t)o[b + 1] - (uint32_t)o[b];
-  }
-  s = wave_sum(s);
-  if (lane_id() == 0) red[threadIdx.x / kWave] = s;
+k_partition(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint32_t n_buckets,
+            uint32_t n_tiles, const uint32_t *__restrict__ tile_pos, uint16_t *__restrict__ payload) {
+  extern __shared__ uint32_t smem[];
+  uint32_t *cnt = smem;                                   // [n_buckets + 1]
+  uint32_t *staged = smem + n_buckets + 1;                // [kTile]: bucket << 16 | payload
+  __shared__ uint32_t scan_tmp[kHistThreads / kWave + 1];
+  const unsigned tid = threadIdx.x;
+  const uint64_t base = (uint64_t)blockIdx.x * kTile;
+  for (uint32_t b = tid; b <= n_buckets; b += kHistThreads) cnt[b] = 0;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t tot = 0;
-    for (int w = 0; w < kHistThreads / kWave; ++w) tot += red[w];
-    uint32_t r = (tot + kItemRecords - 1) / kItemRecords;
-    if (r < 1) r = 1;
-    if (r > n_tiles) r = n_tiles > 0 ? n_tiles : 1;
-    items[b] = r;
+  uint32_t rank[kTile / kHistThreads];
+#pragma unroll
+  for (int bt = 0; bt < kBatches; ++bt) {
+    uint64_t v[kBatch];
+    load_batch<VEC>(rec, n, base, bt, v);
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      uint32_t rk = 0xFFFFFFFFu;
+      if (base + local_index(bt, q) < n && rec_valid(v[q], n_instr)) {
+        const uint32_t pc = (uint32_t)v[q], hi = (uint32_t)(v[q] >> 32);
+        const uint32_t b = pc >> kBucketShift;
+        const uint32_t pl = ((pc & (kBucketPCs - 1)) << 5) | ((hi & 0xFFu) * 2u + ((hi >> 8) & 1u));
+        rk = (b << 16) | atomicAdd(&cnt[b], 1u);
+        staged[local_index(bt, q)] = pl;   // parked; moved to its sorted slot below
+      }
+      rank[bt * kBatch + q] = rk;
+    }
+  }
+  __syncthreads();
+  // exclusive scan of the bucket counts
+  {
+    const uint32_t per = (n_buckets + kHistThreads - 1) / kHistThreads;
+    const uint32_t b0 = min(tid * per, n_buckets), b1 = min(b0 + per, n_buckets);
+    uint32_t s = 0;
+    for (uint32_t b = b0; b < b1; ++b) s += cnt[b];
+    uint32_t total;
+    uint32_t run = block_excl_scan<kHistThreads>(s, scan_tmp, &total);
+    for (uint32_t b = b0; b < b1; ++b) {
+      const uint32_t c = cnt[b];
+      cnt[b] = run;
+      run += c;
+    }
+    if (tid == 0) cnt[n_buckets] = total;
+  }
+  __syncthreads();
+  // move every parked payload to its sorted slot; parked and sorted slots
+  // share [0, kTile), so every parked value is read before any is moved
+  uint32_t val[kTile / kHistThreads];
+#pragma unroll
+  for (int bt = 0; bt < kBatches; ++bt)
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q)
+      val[bt * kBatch + q] = (rank[bt * kBatch + q] != 0xFFFFFFFFu) ? staged[local_index(bt, q)] : 0u;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kTile / kHistThreads; ++k) {
+    if (rank[k] != 0xFFFFFFFFu) {
+      const uint32_t b = rank[k] >> 16;
+      staged[cnt[b] + (rank[k] & 0xFFFFu)] = (b << 16) | val[k];
+    }
+  }
+  __syncthreads();
+  // runs to their global positions (bucket-major layout)
+  const uint32_t nvalid = cnt[n_buckets];
+  for (uint32_t k = tid; k < nvalid; k += kHistThreads) {
+    const uint32_t x = staged[k];
+    const uint32_t b = x >> 16;
+    payload[tile_pos[(size_t)b * n_tiles + blockIdx.x] + (k - cnt[b])] = (uint16_t)x;
   }
 }
 
@@ -172,10 +222,24 @@ __global__ void k_hist_totals(const TileTotals *__restrict__ tt, uint32_t n_tile
   }
 }
 
+// per bucket: its start in the payload array and its number of work items
+__global__ void k_bucket_plan(const uint32_t *tile_pos, uint32_t n_tiles, uint32_t n_buckets,
+                              const unsigned long long *totals, uint32_t *bstart, uint32_t *items) {
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_buckets;
+       b += gridDim.x * blockDim.x) {
+    const uint32_t s0 = tile_pos[(size_t)b * n_tiles];
+    const uint32_t s1 = (b + 1 < n_buckets) ? tile_pos[(size_t)(b + 1) * n_tiles]
+                                            : (uint32_t)totals[0];
+    bstart[b] = s0;
+    const uint32_t r = (s1 - s0 + kItemRecords - 1) / kItemRecords;
+    items[b] = r < 1 ? 1 : r;
+  }
+}
+
 // work item -> (bucket, part) via the prefix of items per bucket
 __global__ void __launch_bounds__(kHistThreads)
-k_count(const uint16_t *__restrict__ payload, const uint16_t *__restrict__ tile_off,
-        uint32_t n_tiles, uint32_t n_buckets, uint32_t n_instr,
+k_count(const uint16_t *__restrict__ payload, const uint32_t *__restrict__ bstart,
+        uint32_t n_buckets, uint32_t n_instr, const unsigned long long *totals,
         const uint32_t *__restrict__ items, const uint32_t *__restrict__ item_start,
         uint32_t *__restrict__ counts, uint32_t *__restrict__ partial) {
   __shared__ uint32_t bins[kBucketBins];
@@ -184,20 +248,24 @@ k_count(const uint16_t *__restrict__ payload, const uint16_t *__restrict__ tile_
   if (it >= total_items) return;
   const uint32_t b = upper_index_u32(item_start, 0, n_buckets, it);
   const uint32_t parts = items[b], part = it - item_start[b];
-  const uint32_t t0 = (uint32_t)((uint64_t)n_tiles * part / parts);
-  const uint32_t t1 = (uint32_t)((uint64_t)n_tiles * (part + 1) / parts);
+  const uint32_t s0 = bstart[b];
+  const uint32_t s1 = (b + 1 < n_buckets) ? bstart[b + 1] : (uint32_t)totals[0];
+  const uint32_t q0 = s0 + (uint32_t)((uint64_t)(s1 - s0) * part / parts);
+  const uint32_t q1 = s0 + (uint32_t)((uint64_t)(s1 - s0) * (part + 1) / parts);
   for (uint32_t k = threadIdx.x; k < kBucketBins; k += kHistThreads) bins[k] = 0;
   __syncthreads();
-  const unsigned w = threadIdx.x / kWave, lane = lane_id();
-  constexpr unsigned kWaves = kHistThreads / kWave;
-  for (uint32_t t = t0 + w; t < t1; t += kWaves) {
-    const uint16_t *o = tile_off + (size_t)t * (n_buckets + 1);
-    const uint32_t lo = o[b], hi = o[b + 1];
-    const uint16_t *src = payload + (size_t)t * kTile;
-    for (uint32_t q = lo + lane; q < hi; q += kWave) {
-      const uint32_t pl = src[q];
-      atomicAdd(&bins[(pl >> 5) * 24u + (pl & 31u)], 1u);
-    }
+  uint32_t q = q0 + threadIdx.x;
+  for (; q + 3 * kHistThreads < q1; q += 4 * kHistThreads) {
+    const uint32_t p0 = payload[q], p1 = payload[q + kHistThreads];
+    const uint32_t p2 = payload[q + 2 * kHistThreads], p3 = payload[q + 3 * kHistThreads];
+    atomicAdd(&bins[(p0 >> 5) * 24u + (p0 & 31u)], 1u);
+    atomicAdd(&bins[(p1 >> 5) * 24u + (p1 & 31u)], 1u);
+    atomicAdd(&bins[(p2 >> 5) * 24u + (p2 & 31u)], 1u);
+    atomicAdd(&bins[(p3 >> 5) * 24u + (p3 & 31u)], 1u);
+  }
+  for (; q < q1; q += kHistThreads) {
+    const uint32_t pl = payload[q];
+    atomicAdd(&bins[(pl >> 5) * 24u + (pl & 31u)], 1u);
   }
   __syncthreads();
   if (parts == 1) {
@@ -211,6 +279,8 @@ k_count(const uint16_t *__restrict__ payload, const uint16_t *__restrict__ tile_
   }
 }
 
+// grid (bucket, slice of kHistThreads bins): each thread sums one bin over
+// the bucket's parts, four loads in flight
 __global__ void __launch_bounds__(kHistThreads)
 k_merge(const uint32_t *__restrict__ partial, const uint32_t *__restrict__ items,
         const uint32_t *__restrict__ item_start, uint32_t n_instr, uint32_t *__restrict__ counts) {
@@ -219,12 +289,19 @@ k_merge(const uint32_t *__restrict__ partial, const uint32_t *__restrict__ items
   if (parts == 1) return;
   const uint32_t pc0 = b * kBucketPCs;
   const uint32_t npc = min((uint32_t)kBucketPCs, n_instr - pc0);
-  const uint32_t *src = partial + (size_t)item_start[b] * kBucketBins;
-  for (uint32_t k = threadIdx.x; k < npc * 24u; k += kHistThreads) {
-    uint32_t s = 0;
-    for (uint32_t p = 0; p < parts; ++p) s += src[(size_t)p * kBucketBins + k];
-    counts[(size_t)pc0 * 24u + k] = s;
+  const uint32_t k = blockIdx.y * kHistThreads + threadIdx.x;
+  if (k >= npc * 24u) return;
+  const uint32_t *src = partial + (size_t)item_start[b] * kBucketBins + k;
+  uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  uint32_t p = 0;
+  for (; p + 3 < parts; p += 4) {
+    s0 += src[(size_t)p * kBucketBins];
+    s1 += src[(size_t)(p + 1) * kBucketBins];
+    s2 += src[(size_t)(p + 2) * kBucketBins];
+    s3 += src[(size_t)(p + 3) * kBucketBins];
   }
+  for (; p < parts; ++p) s0 += src[(size_t)p * kBucketBins];
+  counts[(size_t)pc0 * 24u + k] = (s0 + s1) + (s2 + s3);
 }
 
 __global__ void k_hist_empty(uint32_t *counts, size_t nbins, unsigned long long *totals) {
@@ -246,34 +323,54 @@ void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint3
     GPA_LAUNCH_CHECK();
     return;
   }
-  const uint64_t n_tiles64 = (n + kTile - 1) / kTile;
-  if (n_tiles64 > 0x7FFFFFFFull) fail(GPA_E_UNSUPPORTED, "too many samples in one call");
-  const uint32_t n_tiles = (uint32_t)n_tiles64;
-  uint16_t *payload = ar.get<uint16_t>(n_tiles64 * kTile);
-  uint16_t *tile_off = ar.get<uint16_t>((size_t)n_tiles * (n_buckets + 1));
+  if (n >= 0xFFFFFFFFull) fail(GPA_E_UNSUPPORTED, "at most 2^32-1 samples in one call");
+  const uint32_t n_tiles = (uint32_t)((n + kTile - 1) / kTile);
+  if ((uint64_t)n_tiles * n_buckets >= 0xFFFFFFFFull)
+    fail(GPA_E_UNSUPPORTED, "too many (tile, bucket) pairs in one call");
+  const uint64_t *rec = (const uint64_t *)samples;
+  const bool vec = ((uintptr_t)samples % 16) == 0;
+  uint32_t *tile_cnt = ar.get<uint32_t>((size_t)n_buckets * n_tiles);
+  uint32_t *tile_pos = ar.get<uint32_t>((size_t)n_buckets * n_tiles);
   TileTotals *tt = ar.get<TileTotals>(n_tiles);
-  const size_t lds = (size_t)((n_buckets + 4) & ~3u) * 4 + 2 * (size_t)kTile * 2;
-  GPA_HIP(hipFuncSetAttribute((const void *)k_partition, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds));
-  hipLaunchKernelGGL(k_partition, dim3(n_tiles), dim3(kHistThreads), lds, s,
-                     (const uint64_t *)samples, n, n_instr, n_buckets, payload, tile_off, tt);
-  GPA_LAUNCH_CHECK();
-  uint32_t *items = ar.get<uint32_t>(n_buckets);
-  uint32_t *item_start = ar.get<uint32_t>(n_buckets);
-  hipLaunchKernelGGL(k_bucket_plan, dim3(n_buckets), dim3(kHistThreads), 0, s, tile_off, n_tiles,
-                     n_buckets, items);
+  const size_t lds_count = (size_t)n_buckets * 4;
+  if (vec)
+    hipLaunchKernelGGL(k_bcount<true>, dim3(n_tiles), dim3(kHistThreads), lds_count, s, rec, n,
+                       n_instr, n_buckets, n_tiles, tile_cnt, tt);
+  else
+    hipLaunchKernelGGL(k_bcount<false>, dim3(n_tiles), dim3(kHistThreads), lds_count, s, rec, n,
+                       n_instr, n_buckets, n_tiles, tile_cnt, tt);
   GPA_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_hist_totals, dim3(1), dim3(kHistThreads), 0, s, tt, n_tiles, totals);
+  exclusive_scan_u32(tile_cnt, tile_pos, (size_t)n_buckets * n_tiles, s, ar);
+  uint16_t *payload = ar.get<uint16_t>(n);
+  const size_t lds_part = ((size_t)n_buckets + 1) * 4 + (size_t)kTile * 4;
+  if (vec) {
+    GPA_HIP(hipFuncSetAttribute((const void *)k_partition<true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_part));
+    hipLaunchKernelGGL(k_partition<true>, dim3(n_tiles), dim3(kHistThreads), lds_part, s, rec, n,
+                       n_instr, n_buckets, n_tiles, tile_pos, payload);
+  } else {
+    GPA_HIP(hipFuncSetAttribute((const void *)k_partition<false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_part));
+    hipLaunchKernelGGL(k_partition<false>, dim3(n_tiles), dim3(kHistThreads), lds_part, s, rec, n,
+                       n_instr, n_buckets, n_tiles, tile_pos, payload);
+  }
+  GPA_LAUNCH_CHECK();
+  uint32_t *bstart = ar.get<uint32_t>(n_buckets);
+  uint32_t *items = ar.get<uint32_t>(n_buckets);
+  uint32_t *item_start = ar.get<uint32_t>(n_buckets);
+  hipLaunchKernelGGL(k_bucket_plan, dim3(grid_for(n_buckets, 256, 64)), dim3(256), 0, s, tile_pos,
+                     n_tiles, n_buckets, totals, bstart, items);
   GPA_LAUNCH_CHECK();
   exclusive_scan_u32(items, item_start, n_buckets, s, ar);
-  // upper bound on the number of items: one per bucket plus one per kItemRecords records
+  // items <= one per bucket plus one per kItemRecords records
   const uint64_t max_items = n_buckets + n / kItemRecords + 1;
   uint32_t *partial = ar.get<uint32_t>((size_t)max_items * kBucketBins);
-  hipLaunchKernelGGL(k_count, dim3((unsigned)max_items), dim3(kHistThreads), 0, s, payload,
-                     tile_off, n_tiles, n_buckets, n_instr, items, item_start, counts, partial);
+  hipLaunchKernelGGL(k_count, dim3((unsigned)max_items), dim3(kHistThreads), 0, s, payload, bstart,
+                     n_buckets, n_instr, totals, items, item_start, counts, partial);
   GPA_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_merge, dim3(n_buckets), dim3(kHistThreads), 0, s, partial, items,
-                     item_start, n_instr, counts);
+  hipLaunchKernelGGL(k_merge, dim3(n_buckets, kBucketBins / kHistThreads), dim3(kHistThreads), 0,
+                     s, partial, items, item_start, n_instr, counts);
   GPA_LAUNCH_CHECK();
 }
 

@@ -340,19 +340,15 @@ k_chunk_scatter(const SiteChunk *chunks, const uint32_t *key, uint32_t n_loc, ui
   }
 }
 
-// (function, location) -> bitmask of the guards on its defs
-__global__ void k_def_guards(uint32_t n_funcs, uint32_t n_loc, const uint32_t *fl_def_ptr,
-                             const uint32_t *def_site_sorted, const uint32_t *def_instr,
-                             const uint8_t *guard, uint64_t *mask) {
-  const size_t total = (size_t)n_funcs * n_loc;
-  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < total;
-       q += (size_t)gridDim.x * blockDim.x) {
-    const uint32_t f = (uint32_t)(q / n_loc), x = (uint32_t)(q % n_loc);
-    const uint32_t a = fl_def_ptr[(size_t)f * (n_loc + 1) + x];
-    const uint32_t b = fl_def_ptr[(size_t)f * (n_loc + 1) + x + 1];
-    uint64_t m = 0;
-    for (uint32_t k = a; k < b; ++k) m |= 1ull << guard[def_instr[def_site_sorted[k]]];
-    mask[q] = m;
+// (function, location) -> bitmask of the guards on its defs (guard bytes <= 32)
+__global__ void k_def_guards(uint32_t n_defs, uint32_t n_loc, const uint32_t *def_instr,
+                             const uint32_t *def_loc, const uint32_t *block_of,
+                             const uint32_t *func_of_block, const uint8_t *guard,
+                             unsigned long long *mask) {
+  for (uint32_t d = blockIdx.x * blockDim.x + threadIdx.x; d < n_defs; d += gridDim.x * blockDim.x) {
+    const uint32_t i = def_instr[d];
+    const size_t q = (size_t)func_of_block[block_of[i]] * n_loc + def_loc[d];
+    atomicOr(&mask[q], 1ull << guard[i]);
   }
 }
 
@@ -431,12 +427,17 @@ __global__ void k_roots(uint32_t n_scopes, const uint32_t *parent, uint32_t *roo
     if (parent[s] == GPA_NONE) roots[atomicAdd(n, 1u)] = s;
 }
 
-__global__ void k_max_func_blocks(uint32_t n_funcs, const uint32_t *fbb, uint32_t *mx) {
-  uint32_t m = 0;
+// largest function: blocks, and CFG edges
+__global__ void k_max_func_blocks(uint32_t n_funcs, const uint32_t *fbb, const uint32_t *succ_ptr,
+                                  uint32_t *mx) {
+  uint32_t m = 0, e = 0;
   for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < n_funcs;
-       f += gridDim.x * blockDim.x)
+       f += gridDim.x * blockDim.x) {
     m = max(m, fbb[f + 1] - fbb[f]);
-  atomicMax(mx, m);
+    e = max(e, succ_ptr[fbb[f + 1]] - succ_ptr[fbb[f]]);
+  }
+  atomicMax(&mx[0], m);
+  atomicMax(&mx[1], e);
 }
 
 static void raise_validation(uint32_t err) {
@@ -543,12 +544,13 @@ void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar) {
                      p.pred_ptr.p, p.pred.p);
   GPA_LAUNCH_CHECK();
   // largest function, in blocks
-  uint32_t *mx = ar.get<uint32_t>(1);
-  GPA_HIP(hipMemsetAsync(mx, 0, 4, s));
+  uint32_t *mx = ar.get<uint32_t>(2);
+  GPA_HIP(hipMemsetAsync(mx, 0, 8, s));
   hipLaunchKernelGGL(k_max_func_blocks, dim3(grid_for(nf, 256, 1024)), dim3(256), 0, s, nf,
-                     p.func_block_begin.p, mx);
+                     p.func_block_begin.p, p.succ_ptr.p, mx);
   GPA_LAUNCH_CHECK();
   p.max_func_blocks = read_scalar(mx, s);
+  p.max_func_edges = read_scalar(mx + 1, s);
   if (p.max_func_blocks > 4096)
     fail(GPA_E_UNSUPPORTED, "a function has %u blocks; at most 4096 are supported",
          p.max_func_blocks);
@@ -572,9 +574,10 @@ void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar) {
                      p.func_block_begin.p, p.block_begin.p, p.use_ptr.p, p.fl_use_ptr.p);
   GPA_LAUNCH_CHECK();
   p.fl_def_guards.alloc((size_t)nf * p.n_loc);
-  hipLaunchKernelGGL(k_def_guards, dim3(grid_for((size_t)nf * p.n_loc, 256, 4096)), dim3(256), 0,
-                     s, nf, p.n_loc, p.fl_def_ptr.p, p.def_site_sorted.p, p.def_instr.p, p.guard.p,
-                     p.fl_def_guards.p);
+  GPA_HIP(hipMemsetAsync(p.fl_def_guards.p, 0, 8 * (size_t)nf * p.n_loc, s));
+  hipLaunchKernelGGL(k_def_guards, dim3(grid_for(p.n_defs, 256, 8192)), dim3(256), 0, s, p.n_defs,
+                     p.n_loc, p.def_instr.p, p.def_loc.p, p.block_of.p, p.func_of_block.p,
+                     p.guard.p, (unsigned long long *)p.fl_def_guards.p);
   p.use_cond.alloc(p.n_uses);
   hipLaunchKernelGGL(k_use_cond, dim3(grid_for(p.n_uses, 256, 4096)), dim3(256), 0, s, p.n_uses,
                      p.use_instr.p, p.use_loc.p, p.use_kind.p, p.guard.p, p.block_of.p,

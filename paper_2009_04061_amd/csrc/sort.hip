@@ -110,32 +110,34 @@ __global__ void k_iota_keys(const uint32_t *key, size_t n, uint32_t none_key, ui
   }
 }
 
-__global__ void k_key_count(size_t n, const uint32_t *key, uint32_t *cnt) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x)
-    if (key[i] != GPA_NONE) atomicAdd(&cnt[key[i]], 1u);
+// ptr[k] = first position of the sorted keys holding a key >= k, k <= n_keys
+__global__ void k_key_bounds(size_t n, const uint32_t *sk, uint32_t n_keys, uint32_t *ptr) {
+  for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p <= n;
+       p += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t lo = (p == 0) ? 0u : sk[p - 1] + 1u;
+    const uint32_t hi = (p == n) ? n_keys : sk[p];
+    for (uint32_t k = lo; k <= hi && k <= n_keys; ++k) ptr[k] = (uint32_t)p;
+  }
 }
 
 // ptr[n_keys+1] and perm: items with key k are perm[ptr[k] .. ptr[k+1]) in
 // item order; items whose key is GPA_NONE are left out (they sort last).
 void group_by_key(const uint32_t *key, size_t n, uint32_t n_keys, DBuf<uint32_t> &ptr,
                   DBuf<uint32_t> &perm, hipStream_t s, Arena &ar) {
-  uint32_t *cnt = ar.get<uint32_t>((size_t)n_keys + 1);
-  GPA_HIP(hipMemsetAsync(cnt, 0, 4 * ((size_t)n_keys + 1), s));
-  if (n)
-    hipLaunchKernelGGL(k_key_count, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, key, cnt);
-  GPA_LAUNCH_CHECK();
   ptr.alloc((size_t)n_keys + 1);
-  exclusive_scan_u32(cnt, ptr.p, (size_t)n_keys + 1, s, ar);
   perm.alloc(n ? n : 1);
-  if (!n) return;
-  uint32_t *k = ar.get<uint32_t>(n);
-  hipLaunchKernelGGL(k_iota_keys, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, key, n, n_keys,
-                     k, perm.p);
+  uint32_t *k = ar.get<uint32_t>(n ? n : 1);
+  if (n) {
+    hipLaunchKernelGGL(k_iota_keys, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, key, n, n_keys,
+                       k, perm.p);
+    GPA_LAUNCH_CHECK();
+    uint32_t bits = 1;
+    while (bits < 32 && (1ull << bits) <= n_keys) ++bits;
+    sort_pairs_u32(k, perm.p, n, bits, s, ar);
+  }
+  hipLaunchKernelGGL(k_key_bounds, dim3(grid_for(n + 1, 256, 8192)), dim3(256), 0, s, n, k,
+                     n_keys, ptr.p);
   GPA_LAUNCH_CHECK();
-  uint32_t bits = 1;
-  while (bits < 32 && (1ull << bits) <= n_keys) ++bits;
-  sort_pairs_u32(k, perm.p, n, bits, s, ar);
 }
 
 }  // namespace gpa

@@ -59,7 +59,9 @@ class ProgramInfo(ct.Structure):
 EXPORTS = ["gpa_load_program", "gpa_program_free", "gpa_program_get_info", "gpa_program_rd",
            "gpa_program_edges", "gpa_attribute", "gpa_blame_free", "gpa_blame_counts",
            "gpa_blame_shares", "gpa_blame_table", "gpa_advise", "gpa_advice_free",
-           "gpa_advice_get", "gpa_advice_topk", "gpa_last_error"]
+           "gpa_advice_get", "gpa_advice_topk", "gpa_last_error", "gpa_timing_enable",
+           "gpa_timing_read"]
+PHASES = ["hist", "blame", "load", "advise", "rd_edges", "dist"]
 
 _lib = None
 
@@ -91,6 +93,10 @@ def lib():
         L.gpa_advice_free.restype = None
         L.gpa_advice_get.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.gpa_advice_topk.argtypes = [vp, u32, vp, vp, vp]
+        L.gpa_timing_enable.argtypes = [i32]
+        L.gpa_timing_enable.restype = None
+        L.gpa_timing_read.argtypes = [vp, vp, u32, i32]
+        L.gpa_timing_read.restype = u32
         L.gpa_last_error.argtypes = []
         L.gpa_last_error.restype = ct.c_char_p
         for name in ("gpa_load_program", "gpa_program_get_info", "gpa_program_rd",
@@ -142,6 +148,18 @@ def program_to_device(prog: dict, device="cuda"):
             a = a.view(np.int32)
         out[k] = torch.from_numpy(a.copy()).to(device)
     return out
+
+
+def timing_enable(on: bool = True):
+    """Device-time accounting per phase, with hipEvents on the caller's stream."""
+    lib().gpa_timing_enable(int(bool(on)))
+
+
+def timing_read(reset: bool = False) -> dict:
+    ms = np.zeros(len(PHASES))
+    calls = np.zeros(len(PHASES), np.uint64)
+    lib().gpa_timing_read(ms.ctypes.data, calls.ctypes.data, len(PHASES), int(bool(reset)))
+    return {name: (float(ms[k]), int(calls[k])) for k, name in enumerate(PHASES)}
 
 
 class Program:
