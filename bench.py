@@ -58,6 +58,60 @@ def _traffic(n_launches_ref=None):
     return t.get("bytes_per_pass")
 
 
+HIST_KERNELS = ("k_bcount", "k_hist_totals", "k_partition", "k_bucket_plan", "k_count",
+                "k_merge", "k_hist_empty")
+
+
+def _counter_rows(d):
+    """Rows of the rocprofv3 counter CSV files under directory d."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def summarize_traffic(fetch_dir, write_dir, copy_mb, out_path):
+    """HBM bytes per histogram pass from two rocprofv3 --pmc runs (FETCH_SIZE,
+    then WRITE_SIZE, KiB per dispatch), each scaled by what the same counter
+    reads for the plain device copy of copy_mb MiB in the same run."""
+    res = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _counter_rows(d) if r.get("Counter_Name") == counter]
+        if not rows:
+            raise SystemExit(f"no {counter} rows under {d}")
+        per_kernel = {}
+        copy_vals = []
+        for r in rows:
+            name = r.get("Kernel_Name", "")
+            v = float(r["Counter_Value"])
+            if "copyBuffer" in name:
+                copy_vals.append(v)
+            for k in HIST_KERNELS:
+                if ("gpa::" + k + "(") in name or ("gpa::" + k + "<") in name:
+                    per_kernel.setdefault(k, []).append(v)
+        if not copy_vals:
+            raise SystemExit(f"no copy kernel in the {counter} run")
+        copy_kib = max(copy_vals)   # the large calibration copy
+        factor = (copy_mb * 1024.0) / copy_kib
+        n_pass = max(len(v) for k, v in per_kernel.items() if k in ("k_bcount", "k_count"))
+        kib = sum(sum(v) for v in per_kernel.values()) / n_pass
+        res[counter] = {"kib_per_pass_raw": kib, "copy_kib_raw": copy_kib,
+                        "scale": factor, "bytes_per_pass": kib * 1024.0 * factor,
+                        "per_kernel_kib_raw": {k: sum(v) / len(v) for k, v in per_kernel.items()}}
+    out = {"kernel": "gpa_hist (sample histogram pass)",
+           "workload": "large single kernel, 20M records",
+           "source_sha256_16": _source_hash(HIST_SOURCE),
+           "bytes_per_pass": res["FETCH_SIZE"]["bytes_per_pass"] +
+                             res["WRITE_SIZE"]["bytes_per_pass"],
+           "fetch": res["FETCH_SIZE"], "write": res["WRITE_SIZE"], "copy_mib": copy_mb}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def cpu_baseline(prog, rec, seconds):
     """The oracle on the host: whole steps over the same workload until at
     least `seconds` of CPU work has been done (at least one step)."""
@@ -90,7 +144,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true",
                     help="skip the comparison of one step with the oracle")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="after the timed steps, run a plain device copy of this many MiB "
+                         "(calibrates the HBM byte counters of a profiling run)")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no benchmark: turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) "
+                         "of this script with --copy-mb into the traffic summary")
     args = ap.parse_args()
+
+    if args.traffic_summary:
+        summarize_traffic(args.traffic_summary[0], args.traffic_summary[1],
+                          args.copy_mb or 512, TRAFFIC_FILE)
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -157,6 +222,14 @@ def main():
         A.topk(5)
         lat_adv.append(time.perf_counter() - t_a)
         A.close(); B.close(); P.close()
+
+    if args.copy_mb:
+        a = torch.empty(args.copy_mb << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     ms_step = 1e3 * t_total / args.steps
     value = n_rec * args.steps / t_total

@@ -6,6 +6,7 @@ leg of the benchmark use this module; the HIP library never does.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as ct
 import os
 import subprocess
@@ -27,6 +28,29 @@ def build(force: bool = True) -> str:
                                "-o", tmp, os.path.join(HERE, "gpa_oracle.c"), "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
+
+
+def build_variant(source: str, out_path: str) -> str:
+    """Compile C source text (a modified copy of the oracle, for the tests
+    that plant mistakes in it) into out_path with the same flags."""
+    src = out_path + ".c"
+    with open(src, "w") as f:
+        f.write(source)
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-w", "-shared", "-fPIC", "-I", HERE,
+                           "-o", out_path, src, "-lm"])
+    return out_path
+
+
+@contextlib.contextmanager
+def use_library(path: str):
+    """Route every oracle call to another build of the oracle for a while."""
+    global _lib
+    saved = _lib
+    _lib = _load(path)
+    try:
+        yield
+    finally:
+        _lib = saved
 
 
 class _Prog(ct.Structure):
@@ -51,26 +75,30 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build(force=False)
-        L = ct.CDLL(LIB_PATH)
-        vp, u32, u64 = ct.c_void_p, ct.c_uint32, ct.c_uint64
-        L.orc_count.argtypes = [u32, vp, u64, vp, vp]
-        L.orc_ctx_new.argtypes = [ct.POINTER(_Prog)]
-        L.orc_ctx_new.restype = vp
-        L.orc_ctx_free.argtypes = [vp]
-        L.orc_sources.argtypes = [vp, u32, ct.c_int, vp, u32]
-        L.orc_sources.restype = u32
-        L.orc_dist.argtypes = [vp, u32, u32, vp, vp]
-        L.orc_dist.restype = ct.c_int
-        L.orc_analyze.argtypes = [vp]
-        L.orc_analyze.restype = vp
-        L.orc_analysis_free.argtypes = [vp]
-        L.orc_analysis_sizes.argtypes = [vp, vp, vp]
-        L.orc_analysis_rd.argtypes = [vp, vp, vp, vp]
-        L.orc_analysis_edges.argtypes = [vp, vp, vp, vp, vp, vp]
-        L.orc_blame.argtypes = [vp, vp, vp, vp, vp, vp]
-        L.orc_estimate.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, u32, vp, vp, vp]
-        _lib = L
+        _lib = _load(LIB_PATH)
     return _lib
+
+
+def _load(path):
+    L = ct.CDLL(path)
+    vp, u32, u64 = ct.c_void_p, ct.c_uint32, ct.c_uint64
+    L.orc_count.argtypes = [u32, vp, u64, vp, vp]
+    L.orc_ctx_new.argtypes = [ct.POINTER(_Prog)]
+    L.orc_ctx_new.restype = vp
+    L.orc_ctx_free.argtypes = [vp]
+    L.orc_sources.argtypes = [vp, u32, ct.c_int, vp, u32]
+    L.orc_sources.restype = u32
+    L.orc_dist.argtypes = [vp, u32, u32, vp, vp]
+    L.orc_dist.restype = ct.c_int
+    L.orc_analyze.argtypes = [vp]
+    L.orc_analyze.restype = vp
+    L.orc_analysis_free.argtypes = [vp]
+    L.orc_analysis_sizes.argtypes = [vp, vp, vp]
+    L.orc_analysis_rd.argtypes = [vp, vp, vp, vp]
+    L.orc_analysis_edges.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.orc_blame.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.orc_estimate.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, u32, vp, vp, vp]
+    return L
 
 
 def _p(a):

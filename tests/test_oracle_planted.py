@@ -1,0 +1,113 @@
+"""Planted mistakes: the pins must catch plausible errors in the oracle.
+
+Each case copies the oracle's C source, turns one expression into a plausible
+mistake (a dropped rule, a wrong sign, index or bound, a transposed operand),
+compiles the copy with the oracle's flags and reruns the pins chosen to catch
+it; at least one of them must fail.  The committed oracle is never touched:
+the copy lives in a temporary directory and is loaded only inside the test.
+"""
+import os
+
+import pytest
+
+import test_oracle_bruteforce as TB
+import test_oracle_worked_examples as TW
+from oracle import oracle as O
+
+SRC = os.path.join(os.path.dirname(O.__file__), "gpa_oracle.c")
+
+
+def _pins_for_sources():
+    for tag, prog in TB.PROGS[::5]:
+        TB.test_sources_match_simple_path_enumeration(tag, prog)
+
+
+def _pins_for_distances():
+    for seed in range(0, 25, 3):
+        TB.test_distances_match_bfs_and_path_enumeration(seed)
+
+
+# (name, original text, planted text, pins expected to catch it)
+MUTANTS = [
+    ("latency bit swapped in counting",
+     "C[((size_t)pc * 12 + stall) * 2 + (flags & 1u)] += 1;",
+     "C[((size_t)pc * 12 + stall) * 2 + (1u - (flags & 1u))] += 1;",
+     [TB.test_counts_are_bincount_and_drop_invalid, TW.test_fig1_sampling_ratios]),
+    ("reserved field not checked",
+     "(flags & ~1u) == 0 && reserved == 0)",
+     "(flags & ~1u) == 0)",
+     [TB.test_counts_are_bincount_and_drop_invalid]),
+    ("coverage ignores a matching guard",
+     "static int covers(uint8_t g, uint8_t c) { return g == 0 || g == c; }",
+     "static int covers(uint8_t g, uint8_t c) { return g == 0; }",
+     [_pins_for_sources]),
+    ("complementary pair rule dropped",
+     "if (partner >= 0) {",
+     "if (0 && partner >= 0) {",
+     [TW.test_fig4a_predicate_coverage]),
+    ("dominator stop also at predicated uses",
+     "if (blocked && p->guard[k] == 0 && uses_loc(p, k, x)) continue;",
+     "if (blocked && uses_loc(p, k, x)) continue;",
+     [TW.test_dominator_pruning_hand_case, _pins_for_sources]),
+    ("shortest distance counts an endpoint",
+     "dmin[t] = d - 1;",
+     "dmin[t] = d;",
+     [TW.test_latency_pruning_hand_case, _pins_for_distances]),
+    ("longest path keeps retreating edges",
+     "        if (c->retreat[e]) continue;\n",
+     "",
+     [_pins_for_distances]),
+    ("latency rule off by one",
+     "if (d0[k - k0] <= p->lat[p->op_class[i]])",
+     "if (d0[k - k0] < p->lat[p->op_class[i]])",
+     [TW.test_latency_pruning_hand_case]),
+    ("Eq. 1 path weight inverted",
+     "issued / ((double)a->e_dmax[e] + 1.0)",
+     "issued * ((double)a->e_dmax[e] + 1.0)",
+     [TW.test_fig4d_equal_apportioning]),
+    ("share credited to the destination",
+     "blamed[((size_t)i * 12 + r) * 2 + l] += s;",
+     "blamed[((size_t)j * 12 + r) * 2 + l] += s;",
+     [TW.test_load_use_chain_takes_all_stalls, TW.test_fig3_barrier_dependency]),
+    ("active and latency samples swapped",
+     "      act += CNT(j, r, 0);\n      lat += CNT(j, r, 1);",
+     "      act += CNT(j, r, 1);\n      lat += CNT(j, r, 0);",
+     # Fig. 1 alone cannot see this one: its example has A = L = 3
+     [TW.test_nested_scope_actives, lambda: TW.test_theorem_latency_hiding_bound(1)]),
+    ("Eq. 5 without the active-sample bound",
+     "double x = (o >= ORC_O_LOOP_UNROLL) ? (active[s] < M ? active[s] : M) : M;",
+     "double x = M;",
+     [lambda: TW.test_theorem_latency_hiding_bound(1)]),
+    ("Eq. 2 sign",
+     "double sp = (T == 0.0) ? 1.0 : T / (T - x);",
+     "double sp = (T == 0.0) ? 1.0 : T / (T + x);",
+     [TW.test_eq2_stall_elimination_closed_form]),
+    ("subtree sums stop at the scope itself",
+     "    if (p->scope_parent[s] == ORC_NONE) return;\n    s = p->scope_parent[s];",
+     "    return;",
+     [TW.test_nested_scope_actives]),
+]
+
+
+def test_every_planted_text_is_in_the_oracle():
+    with open(SRC) as f:
+        src = f.read()
+    for name, old, _, _ in MUTANTS:
+        assert src.count(old) >= 1, name
+
+
+@pytest.mark.parametrize("case", range(len(MUTANTS)), ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(case, tmp_path):
+    name, old, new, pins = MUTANTS[case]
+    with open(SRC) as f:
+        src = f.read()
+    assert old in src
+    lib = O.build_variant(src.replace(old, new), str(tmp_path / "libmutant.so"))
+    caught = []
+    with O.use_library(lib):
+        for pin in pins:
+            try:
+                pin()
+            except AssertionError:
+                caught.append(getattr(pin, "__name__", "pin"))
+    assert caught, f"no pin caught the planted mistake: {name}"
