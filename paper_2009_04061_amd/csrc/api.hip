@@ -132,6 +132,32 @@ PhaseTimer::~PhaseTimer() {
   if (b) (void)hipEventDestroy(b);
 }
 
+// ------------------------------------------------------- side streams
+namespace {
+std::mutex g_smu;
+std::vector<hipStream_t> g_side;   // per device
+}  // namespace
+
+hipStream_t side_stream() {
+  int dev = 0;
+  GPA_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_smu);
+  if ((size_t)dev >= g_side.size()) g_side.resize((size_t)dev + 1, nullptr);
+  if (!g_side[dev]) GPA_HIP(hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking));
+  return g_side[dev];
+}
+
+// a synchronization-only event, destroyed with its scope
+struct Event {
+  hipEvent_t e = nullptr;
+  Event() { GPA_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming)); }
+  ~Event() {
+    if (e) (void)hipEventDestroy(e);
+  }
+  Event(const Event &) = delete;
+  Event &operator=(const Event &) = delete;
+};
+
 template <typename T>
 static void upload(DBuf<T> &dst, const T *src, size_t n, bool on_device, hipStream_t s) {
   dst.alloc(n);
@@ -252,16 +278,27 @@ gpa_status gpa_load_program(const gpa_program_desc *d, void *stream, gpa_program
     upload(p->scope_parent, d->scope_parent, p->n_scopes, dev, s);
     upload(p->scope_kind, d->scope_kind, p->n_scopes, dev, s);
     upload(p->scope_flags, d->scope_flags, p->n_scopes, dev, s);
-    Arena ar;
-    PhaseTimer t_load, t_rd, t_dist;
+    const hipStream_t side = side_stream();
+    Event ev_struct, ev_order;   // outlive the arena, whose end waits for both streams
+    Arena ar(s);
+    ar.add_stream(side);
+    PhaseTimer t_load, t_rd, t_dist, t_dfs, t_search;
     t_load.begin(kPhaseLoad, s);
     validate_and_build_structure(*p, s, ar);
+    // the DFS order and the sweep streams need only the CFG: they run on the
+    // side stream while the reaching definitions and edges are built
+    GPA_HIP(hipEventRecord(ev_struct.e, s));
+    GPA_HIP(hipStreamWaitEvent(side, ev_struct.e, 0));
+    SweepPlan plan;
+    build_cfg_order(*p, side, ar, plan, t_dfs);
+    GPA_HIP(hipEventRecord(ev_order.e, side));
     t_rd.begin(kPhaseRd, s);
-    build_reaching_defs(*p, s, ar);
+    build_reaching_defs(*p, s, ar, t_search);
     build_edges(*p, s, ar);
     t_rd.end(s);
+    GPA_HIP(hipStreamWaitEvent(s, ev_order.e, 0));
     t_dist.begin(kPhaseDist, s);
-    build_distances(*p, s, ar);
+    build_distances(*p, s, ar, plan);
     t_dist.end(s);
     build_scope_targets(*p, s, ar);
     t_load.end(s);
@@ -269,6 +306,8 @@ gpa_status gpa_load_program(const gpa_program_desc *d, void *stream, gpa_program
     t_load.collect();
     t_rd.collect();
     t_dist.collect();
+    t_dfs.collect();
+    t_search.collect();
   });
   if (st != GPA_OK) {
     if (s) (void)hipStreamSynchronize(s);
@@ -345,7 +384,7 @@ gpa_status gpa_attribute(gpa_program *p, const gpa_sample *samples, uint64_t n,
   gpa_status st = guarded([&] {
     b = new gpa_blame();
     b->prog = p;
-    Arena ar;
+    Arena ar(s);
     const gpa_sample *dsamp = samples;
     if (n && !samples_on_device) {
       gpa_sample *tmp = ar.get<gpa_sample>(n);
@@ -429,7 +468,7 @@ gpa_status gpa_advise(const gpa_blame *b, void *stream, gpa_advice **out) {
   gpa_status st = guarded([&] {
     a = new gpa_advice();
     a->prog = b->prog;
-    Arena ar;
+    Arena ar(s);
     PhaseTimer t_adv;
     t_adv.begin(kPhaseAdvise, s);
     run_estimate(*b->prog, *b, *a, 16, s, ar);

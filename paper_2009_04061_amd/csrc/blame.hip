@@ -24,6 +24,11 @@ struct ArchDev {
   uint16_t pad;
 };
 
+// One thread per destination j.  A first pass over j's incoming edges sums,
+// per blamable reason, the issued-based and the path-only weights of the
+// candidates (in edge order, as Eq. (1) is written); a second pass writes
+// every share slot of those edges.  Reasons are unrolled, so the per-reason
+// sums stay in registers.
 __global__ void k_blame_dst(uint32_t n_instr, uint32_t nbl, ArchDev arch, const uint32_t *counts,
                             const uint32_t *in_ptr, const uint32_t *e_src, const uint8_t *e_flags,
                             const uint32_t *e_dmax, const uint8_t *op_class, double *share,
@@ -32,55 +37,61 @@ __global__ void k_blame_dst(uint32_t n_instr, uint32_t nbl, ArchDev arch, const 
        j += gridDim.x * blockDim.x) {
     const uint32_t *C = counts + (size_t)j * 24;
     const uint32_t e0 = in_ptr[j], e1 = in_ptr[j + 1];
-    for (uint32_t e = e0; e < e1; ++e)
-      for (uint32_t q = 0; q < 2 * nbl; ++q) share[(size_t)e * 2 * nbl + q] = 0.0;
-    for (uint32_t r = 0; r < 12; ++r) {
-      for (uint32_t l = 0; l < 2; ++l) {
-        const uint32_t S = C[r * 2 + l];
-        double kept = 0.0;
-        if (S != 0) {
-          if (!((arch.blamable >> r) & 1u)) {
-            kept = (double)S;
-          } else {
-            const uint32_t slot = __popc((uint32_t)arch.blamable & ((1u << r) - 1u));
-            double W = 0.0;
-            uint32_t ncand = 0;
-            for (uint32_t e = e0; e < e1; ++e) {
-              const uint32_t i = e_src[e];
-              const uint8_t fl = e_flags[e];
-              if (!(fl & GPA_E_DOM_KEEP) || !(fl & GPA_E_LAT_KEEP)) continue;
-              if (!((arch.allowed[r] >> op_class[i]) & 1u)) continue;
-              ++ncand;
-              const double issued = (double)counts[(size_t)i * 24] + (double)counts[(size_t)i * 24 + 1];
-              W += issued / ((double)e_dmax[e] + 1.0);
-            }
-            if (ncand == 0) {
-              kept = (double)S;
-            } else {
-              const bool by_path = (W == 0.0);
-              if (by_path) {
-                for (uint32_t e = e0; e < e1; ++e) {
-                  const uint32_t i = e_src[e];
-                  const uint8_t fl = e_flags[e];
-                  if (!(fl & GPA_E_DOM_KEEP) || !(fl & GPA_E_LAT_KEEP)) continue;
-                  if (!((arch.allowed[r] >> op_class[i]) & 1u)) continue;
-                  W += 1.0 / ((double)e_dmax[e] + 1.0);
-                }
-              }
-              for (uint32_t e = e0; e < e1; ++e) {
-                const uint32_t i = e_src[e];
-                const uint8_t fl = e_flags[e];
-                if (!(fl & GPA_E_DOM_KEEP) || !(fl & GPA_E_LAT_KEEP)) continue;
-                if (!((arch.allowed[r] >> op_class[i]) & 1u)) continue;
-                const double issued = (double)counts[(size_t)i * 24] + (double)counts[(size_t)i * 24 + 1];
-                const double w = by_path ? 1.0 / ((double)e_dmax[e] + 1.0)
-                                         : issued / ((double)e_dmax[e] + 1.0);
-                share[((size_t)e * nbl + slot) * 2 + l] = (double)S * w / W;
-              }
-            }
-          }
+    double Wi[12], Wp[12];
+    bool any[12];
+#pragma unroll
+    for (int r = 0; r < 12; ++r) {
+      Wi[r] = 0.0;
+      Wp[r] = 0.0;
+      any[r] = false;
+    }
+    for (uint32_t e = e0; e < e1; ++e) {
+      const uint8_t fl = e_flags[e];
+      if (!(fl & GPA_E_DOM_KEEP) || !(fl & GPA_E_LAT_KEEP)) continue;
+      const uint32_t i = e_src[e];
+      const uint32_t cls = op_class[i];
+      const double len = (double)e_dmax[e] + 1.0;
+      const double issued = (double)counts[(size_t)i * 24] + (double)counts[(size_t)i * 24 + 1];
+      const double wi = issued / len, wp = 1.0 / len;
+#pragma unroll
+      for (int r = 0; r < 12; ++r) {
+        if (!((arch.blamable >> r) & 1u) || !((arch.allowed[r] >> cls) & 1u)) continue;
+        Wi[r] += wi;
+        Wp[r] += wp;
+        any[r] = true;
+      }
+    }
+    for (uint32_t e = e0; e < e1; ++e) {
+      const uint8_t fl = e_flags[e];
+      const bool kept = (fl & GPA_E_DOM_KEEP) && (fl & GPA_E_LAT_KEEP);
+      const uint32_t i = e_src[e];
+      const uint32_t cls = op_class[i];
+      const double len = (double)e_dmax[e] + 1.0;
+      const double issued = (double)counts[(size_t)i * 24] + (double)counts[(size_t)i * 24 + 1];
+      double *sh = share + (size_t)e * 2 * nbl;
+      uint32_t slot = 0;
+#pragma unroll
+      for (int r = 0; r < 12; ++r) {
+        if (!((arch.blamable >> r) & 1u)) continue;
+        const bool cand = kept && ((arch.allowed[r] >> cls) & 1u);
+        const bool by_path = (Wi[r] == 0.0);
+        const double w = by_path ? 1.0 / len : issued / len;
+        const double W = by_path ? Wp[r] : Wi[r];
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+          const uint32_t S = C[r * 2 + l];
+          sh[slot * 2 + l] = (cand && S != 0) ? (double)S * w / W : 0.0;
         }
-        self_[(size_t)j * 24 + r * 2 + l] = kept;
+        ++slot;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 12; ++r) {
+      const bool blam = (arch.blamable >> r) & 1u;
+#pragma unroll
+      for (int l = 0; l < 2; ++l) {
+        const uint32_t S = C[r * 2 + l];
+        self_[(size_t)j * 24 + r * 2 + l] = (S != 0 && (!blam || !any[r])) ? (double)S : 0.0;
       }
     }
   }

@@ -62,13 +62,17 @@ struct DBuf {
 };
 
 // Per-call scratch: every block is returned to the pool when the arena is
-// destroyed, which the API calls do only after synchronizing their stream.
+// destroyed, after the streams the call launched work on have finished (also
+// when the call fails part-way through).
 struct Arena {
   std::vector<void *> blocks;
-  Arena() = default;
+  std::vector<hipStream_t> streams;
+  explicit Arena(hipStream_t s) { streams.push_back(s); }
   Arena(const Arena &) = delete;
   Arena &operator=(const Arena &) = delete;
+  void add_stream(hipStream_t s) { streams.push_back(s); }
   ~Arena() {
+    for (hipStream_t s : streams) (void)hipStreamSynchronize(s);
     for (void *b : blocks) dev_free(b);
   }
   template <typename T>
@@ -100,7 +104,6 @@ struct gpa_program {
   gpa::DBuf<uint32_t> use_site_sorted, fl_use_ptr;   // use sites by (function, location, instr)
   gpa::DBuf<uint32_t> def_instr, use_instr;          // site -> instruction
   gpa::DBuf<uint32_t> def_rank, use_rank;            // site -> position in the sorted array
-  gpa::DBuf<uint64_t> fl_def_guards;                 // (function, location) -> guards on defs
   gpa::DBuf<uint8_t> use_cond;                       // use site -> effective condition
   // reaching definitions
   uint64_t n_rd = 0;
@@ -120,6 +123,10 @@ struct gpa_program {
   gpa::DBuf<uint8_t> instr_tags;               // bit0 in math fn, bit1 in device fn with CFG
   gpa::DBuf<uint32_t> lca_ptr, lca_perm, icl_ptr, icl_perm, line_ptr, line_perm;
   uint64_t n_icl = 0;                          // edges with a common loop
+  // segments longer than a thread sums alone, per grouping (own sums by
+  // scope, edges by common loop, edges by common scope, subtrees), each list
+  // n_scopes long, counts in big_n[4]
+  gpa::DBuf<uint32_t> big_list, big_n;
   gpa::DBuf<uint32_t> roots;                   // kernel root scope ids
   uint32_t n_roots = 0;
   hipStream_t stream = nullptr;
@@ -165,10 +172,23 @@ void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint3
 // load.hip
 void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar);
 // dataflow.hip
-void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar);
+struct PhaseTimer;
+void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar, PhaseTimer &t_search);
 void build_edges(gpa_program &p, hipStream_t s, Arena &ar);
 // dist.hip
-void build_distances(gpa_program &p, hipStream_t s, Arena &ar);
+// Per device, a second stream (default priority, non-blocking) for load work
+// that only needs the CFG and can overlap the reaching definitions.
+hipStream_t side_stream();
+
+// The G' sweep streams the distance kernel reads (built with the DFS order).
+struct SweepPlan {
+  uint32_t *ent_ptr = nullptr, *ent = nullptr, *ent_w = nullptr;
+  uint32_t *ret_ptr = nullptr, *rent = nullptr, *rent_w = nullptr;
+};
+void build_cfg_order(gpa_program &p, hipStream_t s, Arena &ar, SweepPlan &plan,
+                     PhaseTimer &t_dfs);
+void build_distances(gpa_program &p, hipStream_t s, Arena &ar, const SweepPlan &plan);
+constexpr uint32_t kSmallSeg = 64;   // longest segment one thread sums alone
 void build_scope_targets(gpa_program &p, hipStream_t s, Arena &ar);
 // blame.hip
 void run_blame(const gpa_program &p, gpa_blame &b, hipStream_t s, Arena &ar);
@@ -179,7 +199,10 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint3
 // Opt-in phase timing with hipEvents on the caller's stream (gpa_timing_*):
 // a phase records an event pair; the pair's elapsed time is accumulated when
 // the API call that launched it has synchronized its stream.
-enum Phase { kPhaseHist = 0, kPhaseBlame, kPhaseLoad, kPhaseAdvise, kPhaseRd, kPhaseDist, kNumPhases };
+enum Phase {
+  kPhaseHist = 0, kPhaseBlame, kPhaseLoad, kPhaseAdvise, kPhaseRd, kPhaseDist, kPhaseDfs,
+  kPhaseRdSearch, kNumPhases
+};
 struct PhaseTimer {
   hipEvent_t a = nullptr, b = nullptr;
   int phase = -1;

@@ -1,28 +1,26 @@
 // Reaching definitions and the dependency graph (Sec. 4, "Backward slicing",
 // "Construct a dependency graph", dominator pruning).
 //
-// The backward slice of a use reaches exactly the defs from which a path to
-// the use exists with no intermediate instruction that stops the search, so
-// the same relation is computed forward as bit-vector reaching definitions:
+// The immediate sources of a use are found as the paper finds them, by a
+// backward search from the use that stops on every path at the first def
+// that settles it, run in parallel over all uses:
 //
-//   * RD separates by location x and by the condition c the use must cover
-//     (its guard for an operand use, `_` for a guard read or a wait): a def
-//     covers c iff its guard is `_` or c.  Within one (x, c) the transfer of
-//     a def is  S := {d}  if it covers c,  S := {d, partner} if it completes
-//     a complementary pair with the previous def of x in the block
-//     ({Pi} with {!Pi} covers `_`), and  S := S + {d}  otherwise.
-//   * The use-blocked variant (dominator pruning) also empties S at every
-//     unpredicated instruction that uses x, before that instruction's defs.
-//   * Bits are the defs of x in instruction order (ordinals), split into
-//     chunks of 64*W so that one chunk's OUT bitsets for every block of the
-//     function fit in LDS.  A workgroup owns one (function, x, c, chunk) tile
-//     and iterates OUT[b] = GEN[b] | (KILL[b] ? 0 : OR_{p in pred(b)} OUT[p])
-//     to the least fixed point, each thread sweeping a contiguous run of
-//     blocks in order (chaotic iteration; it stops after a sweep that changes
-//     nothing anywhere, when every block satisfies its equation).
-//   * Inside one block the effect of the defs (and blocking uses) is a
-//     single range of ordinals that survives to the end, plus a kill flag;
-//     these block summaries are computed once per (function, x, c).
+//   * a search is keyed by location x and the condition c the use must cover
+//     (its guard for an operand use, `_` for a guard read or a wait); a def
+//     covers c iff its guard is `_` or c; a def that completes a
+//     complementary pair with the previous def of x in its block ({Pi} with
+//     {!Pi} covers `_`) stops the search after its partner;
+//   * the use-blocked variant (dominator pruning) also stops at every
+//     unpredicated instruction that uses x;
+//   * the search runs over blocks: inside one whole block the defs that
+//     survive to its end are one range of def ordinals (the defs of x in
+//     instruction order), plus a flag saying whether the block stops the
+//     search; a dense (location, block) index gives each block's def and use
+//     ranges in one load;
+//   * one thread follows one use (both variants) and ORs the surviving
+//     ranges of the blocks it reaches into that use's IN bitsets; a search
+//     that reaches more blocks than a thread keeps track of is handed to a
+//     whole workgroup, which repeats it breadth-first with LDS bitsets.
 // The per-use source lists then combine IN of the use's block (if nothing in
 // the block before the use stops the search) with the in-block survivors.
 #include "common.h"
@@ -30,27 +28,17 @@
 
 namespace gpa {
 
-constexpr int kTileThreads = 256;
-constexpr uint32_t kLdsBudget = 96 * 1024;
-constexpr uint32_t kMaxWords = 16;
-constexpr uint32_t kStageMax = 4096;     // defs / uses of one (function, x) staged in LDS
 constexpr uint32_t kUnpred = 0x80000000u;
-
-struct RdTile {
-  uint32_t func, loc, chunk, cond;   // cond: guard byte the tile's uses must cover
-  uint32_t words, n_blocks, block0, summ;   // summ: first block summary of its problem
-};
-
-struct BlockSumm {
-  uint32_t gF, gB, hi, kill;   // survivor ranges [gF, hi), [gB, hi); kill bit0 full, bit1 blocked
-};
+constexpr int kSearchThreads = 256;
+constexpr uint32_t kSearchCap = 32;      // blocks one thread tracks per search
+constexpr uint32_t kLongGrid = 512;      // workgroups that take the long searches
 
 __device__ __forceinline__ bool covers(uint32_t g, uint32_t c) { return g == 0 || g == c; }
 __device__ __forceinline__ uint32_t complement(uint32_t g) { return (g & 1u) ? g + 1 : g - 1; }
 
-// first index in [0, n) whose instruction (low 31 bits) is >= key
-__device__ __forceinline__ uint32_t lower_instr(const uint32_t *a, uint32_t n, uint32_t key) {
-  uint32_t lo = 0, hi = n;
+// first position in [lo, hi) whose instruction (low 31 bits) is >= key
+__device__ __forceinline__ uint32_t lower_pos(const uint32_t *a, uint32_t lo, uint32_t hi,
+                                              uint32_t key) {
   while (lo < hi) {
     const uint32_t mid = (lo + hi) / 2;
     if ((a[mid] & ~kUnpred) < key) lo = mid + 1;
@@ -80,86 +68,28 @@ __global__ void k_sorted_views(uint32_t n_defs, uint32_t n_uses, const uint32_t 
 }
 
 // ------------------------------------------------------------------ plan
-// conditions the uses of each (function, location) must cover
-__global__ void k_use_condmask(uint32_t n_uses, uint32_t n_loc, const uint32_t *use_instr,
-                               const uint32_t *use_loc, const uint32_t *block_of,
-                               const uint32_t *func_of_block, const uint8_t *use_cond,
-                               unsigned long long *mask) {
-  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n_uses; u += gridDim.x * blockDim.x) {
-    const size_t q = (size_t)func_of_block[block_of[use_instr[u]]] * n_loc + use_loc[u];
-    atomicOr(&mask[q], 1ull << use_cond[u]);
-  }
-}
-
-// tile LDS: nb*(16W + 12) + 2*npred + 4 bytes (bitsets, summaries, pred CSR)
-__device__ __host__ __forceinline__ uint32_t tile_words(uint32_t nb, uint32_t npred) {
-  const uint32_t fixed = nb * 12u + 2u * npred + 8u;
-  uint32_t w = fixed < kLdsBudget ? (kLdsBudget - fixed) / (16u * nb) : 0u;
-  if (w < 1) w = 1;
-  if (w > kMaxWords) w = kMaxWords;
-  return w;
-}
-
-__global__ void k_fl_plan(uint32_t n_funcs, uint32_t n_loc, const uint32_t *fbb,
-                          const uint32_t *succ_ptr, const uint32_t *fl_def_ptr,
-                          const uint32_t *fl_use_ptr, uint32_t *fl_words, uint32_t *fl_chunks,
-                          uint64_t *fl_condmask, uint32_t *fl_tiles, uint32_t *fl_summ) {
+// IN bitset words per use site of (function, x): one word per 64 defs of x,
+// twice (plain, use-blocked); the largest word count sizes the LDS of the
+// workgroup search.
+__global__ void k_rd_plan(uint32_t n_funcs, uint32_t n_loc, const uint32_t *fl_def_ptr,
+                          uint32_t *fl_words, uint32_t *fl_chunks, uint32_t *max_words) {
   const size_t total = (size_t)n_funcs * n_loc;
+  uint32_t mx = 0;
   for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < total;
        q += (size_t)gridDim.x * blockDim.x) {
     const uint32_t f = (uint32_t)(q / n_loc), x = (uint32_t)(q % n_loc);
     const size_t fi = (size_t)f * (n_loc + 1) + x;
     const uint32_t nd = fl_def_ptr[fi + 1] - fl_def_ptr[fi];
-    const uint32_t nu = fl_use_ptr[fi + 1] - fl_use_ptr[fi];
-    const uint32_t nb = fbb[f + 1] - fbb[f];
-    uint32_t w = tile_words(nb, succ_ptr[fbb[f + 1]] - succ_ptr[fbb[f]]);
-    const uint32_t need = (nd + 63) / 64;
-    if (w > need) w = need ? need : 1;
-    const uint64_t mask = fl_condmask[q];   // guard bytes go up to 32
-    const uint32_t chunks = (nd + 64 * w - 1) / (64 * w);
-    const bool live = nd && nu;
-    fl_words[q] = w;
-    fl_chunks[q] = chunks;
-    if (!live) fl_condmask[q] = 0ull;
-    fl_tiles[q] = live ? chunks * (uint32_t)__popcll(mask) : 0u;
-    fl_summ[q] = live ? nb * (uint32_t)__popcll(mask) : 0u;
+    const uint32_t nw = (nd + 63) / 64;
+    fl_words[q] = 1;
+    fl_chunks[q] = nw;
+    mx = max(mx, nw);
   }
+  mx = wave_max_u32(mx);
+  if (lane_id() == 0 && mx) atomicMax(max_words, mx);
 }
 
-__global__ void k_fl_tiles(uint32_t n_funcs, uint32_t n_loc, const uint32_t *fbb,
-                           const uint32_t *fl_words, const uint32_t *fl_chunks,
-                           const uint64_t *fl_condmask, const uint32_t *fl_tile_start,
-                           const uint32_t *fl_summ_start, RdTile *tiles) {
-  const size_t total = (size_t)n_funcs * n_loc;
-  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < total;
-       q += (size_t)gridDim.x * blockDim.x) {
-    uint64_t mask = fl_condmask[q];
-    if (!mask) continue;
-    const uint32_t f = (uint32_t)(q / n_loc), x = (uint32_t)(q % n_loc);
-    const uint32_t nb = fbb[f + 1] - fbb[f];
-    uint32_t t = fl_tile_start[q];
-    uint32_t summ = fl_summ_start[q];
-    while (mask) {
-      const uint32_t c = (uint32_t)__ffsll((long long)mask) - 1;
-      mask &= mask - 1;
-      for (uint32_t k = 0; k < fl_chunks[q]; ++k) {
-        RdTile d;
-        d.func = f;
-        d.loc = x;
-        d.chunk = k;
-        d.cond = c;
-        d.words = fl_words[q];
-        d.block0 = fbb[f];
-        d.n_blocks = nb;
-        d.summ = summ;
-        tiles[t++] = d;
-      }
-      summ += nb;
-    }
-  }
-}
-
-// IN words each use site receives: chunks * 2 * words (full, blocked)
+// IN words each use site receives: chunks * 2 * words (plain, blocked)
 __global__ void k_use_slots(uint32_t n_uses, const uint32_t *use_instr, const uint32_t *use_loc,
                             const uint32_t *block_of, const uint32_t *func_of_block,
                             uint32_t n_loc, const uint32_t *fl_words, const uint32_t *fl_chunks,
@@ -172,21 +102,19 @@ __global__ void k_use_slots(uint32_t n_uses, const uint32_t *use_instr, const ui
 }
 
 // --------------------------------------------------- block and prefix rules
-// Survivors of the defs of x among instructions [i_begin, i_end) of one
-// block, for condition c: the first surviving ordinal g (survivors are
-// [g, ord_end)) and whether something in the range stops everything before
-// it (kill).  With `blocked`, unpredicated uses of x also stop the search.
-// dI/dG: instruction and guard per def ordinal; uI: use instructions with
-// the unpredicated flag, sorted.
+// Survivors of the defs of x at positions [lo, hi) of one block (all defs of
+// x in an instruction range of the block), for condition c: the first
+// surviving position g (survivors are [g, hi)) and whether something in the
+// range stops everything before it (kill).  With `blocked`, unpredicated
+// uses of x (positions [ulo, uhi) of the sorted uses) also stop the search.
 struct Survive {
   uint32_t g, hi;
   bool kill;
 };
 
-__device__ Survive survivors(const uint32_t *dI, const uint8_t *dG, uint32_t nd, const uint32_t *uI,
-                             uint32_t nu, uint32_t i_begin, uint32_t i_end, uint32_t c,
-                             bool blocked) {
-  const uint32_t lo = lower_instr(dI, nd, i_begin), hi = lower_instr(dI, nd, i_end);
+__device__ Survive survivors_range(const uint32_t *dI, const uint8_t *dG, const uint32_t *uI,
+                                   uint32_t lo, uint32_t hi, uint32_t ulo, uint32_t uhi,
+                                   uint32_t c, bool blocked) {
   // last def in the range that stops the search, and its kind
   uint32_t qk = 0xFFFFFFFFu;
   bool pair = false;
@@ -205,7 +133,6 @@ __device__ Survive survivors(const uint32_t *dI, const uint8_t *dG, uint32_t nd,
   // last unpredicated use of x in the range
   uint32_t qb = 0xFFFFFFFFu;
   if (blocked) {
-    const uint32_t ulo = lower_instr(uI, nu, i_begin), uhi = lower_instr(uI, nu, i_end);
     for (uint32_t q = uhi; q-- > ulo;) {
       if (uI[q] & kUnpred) {
         qb = uI[q] & ~kUnpred;
@@ -219,7 +146,7 @@ __device__ Survive survivors(const uint32_t *dI, const uint8_t *dG, uint32_t nd,
     const uint32_t ik = dI[qk];
     if (qb != 0xFFFFFFFFu && qb > ik) {
       // a use after the last stopping def: only defs at or after the use survive
-      r.g = lower_instr(dI, nd, qb);
+      r.g = lower_pos(dI, qk, hi, qb);
       r.kill = true;
       return r;
     }
@@ -234,13 +161,27 @@ __device__ Survive survivors(const uint32_t *dI, const uint8_t *dG, uint32_t nd,
     return r;
   }
   if (qb != 0xFFFFFFFFu) {
-    r.g = lower_instr(dI, nd, qb);
+    r.g = lower_pos(dI, lo, hi, qb);
     r.kill = true;
     return r;
   }
   r.g = lo;
   r.kill = false;
   return r;
+}
+
+// The same for the instructions [i_begin, i_end) of one block, given the
+// (function, x) arrays: dI/dG per def ordinal, uI per sorted use.
+__device__ Survive survivors(const uint32_t *dI, const uint8_t *dG, uint32_t nd, const uint32_t *uI,
+                             uint32_t nu, uint32_t i_begin, uint32_t i_end, uint32_t c,
+                             bool blocked) {
+  const uint32_t lo = lower_pos(dI, 0, nd, i_begin), hi = lower_pos(dI, lo, nd, i_end);
+  uint32_t ulo = 0, uhi = 0;
+  if (blocked) {
+    ulo = lower_pos(uI, 0, nu, i_begin);
+    uhi = lower_pos(uI, ulo, nu, i_end);
+  }
+  return survivors_range(dI, dG, uI, lo, hi, ulo, uhi, c, blocked);
 }
 
 __device__ __forceinline__ uint64_t range_word(uint32_t lo, uint32_t hi, uint32_t w0) {
@@ -252,133 +193,175 @@ __device__ __forceinline__ uint64_t range_word(uint32_t lo, uint32_t hi, uint32_
   return m << (a - w0);
 }
 
-// ------------------------------------------------------- block summaries
-// One workgroup per (function, x, c): the def and use views of (function, x)
-// staged in LDS, then one summary per block.
-__global__ void __launch_bounds__(kTileThreads)
-k_rd_summ(const RdTile *tiles, const uint32_t *block_begin, const uint32_t *fl_def_ptr,
-          const uint32_t *fl_use_ptr, uint32_t n_loc, const uint32_t *dsi, const uint8_t *dsg,
-          const uint32_t *usi, BlockSumm *summ) {
-  __shared__ uint32_t sI[kStageMax];
-  __shared__ uint32_t sU[kStageMax];
-  __shared__ uint8_t sG[kStageMax];
-  const RdTile t = tiles[blockIdx.x];
-  if (t.chunk != 0) return;
-  const size_t fi = (size_t)t.func * (n_loc + 1) + t.loc;
-  const uint32_t d0 = fl_def_ptr[fi], nd = fl_def_ptr[fi + 1] - d0;
-  const uint32_t u0 = fl_use_ptr[fi], nu = fl_use_ptr[fi + 1] - u0;
-  const uint32_t *dI = dsi + d0;
-  const uint8_t *dG = dsg + d0;
-  const uint32_t *uI = usi + u0;
-  if (nd <= kStageMax) {
-    for (uint32_t k = threadIdx.x; k < nd; k += kTileThreads) {
-      sI[k] = dI[k];
-      sG[k] = dG[k];
-    }
-    dI = sI;
-    dG = sG;
-  }
-  if (nu <= kStageMax) {
-    for (uint32_t k = threadIdx.x; k < nu; k += kTileThreads) sU[k] = uI[k];
-    uI = sU;
-  }
-  __syncthreads();
-  for (uint32_t b = threadIdx.x; b < t.n_blocks; b += kTileThreads) {
-    const uint32_t i0 = block_begin[t.block0 + b], i1 = block_begin[t.block0 + b + 1];
-    const Survive sF = survivors(dI, dG, nd, uI, nu, i0, i1, t.cond, false);
-    const Survive sB = survivors(dI, dG, nd, uI, nu, i0, i1, t.cond, true);
-    BlockSumm m;
-    m.gF = sF.g;
-    m.gB = sB.g;
-    m.hi = sF.hi;
-    m.kill = (sF.kill ? 1u : 0u) | (sB.kill ? 2u : 0u);
-    summ[t.summ + b] = m;
+// ------------------------------------------------ (location, block) index
+// For location x and block b: the positions of x's defs and uses inside b in
+// the sorted def and use arrays (absolute positions, empty ranges where x
+// does not occur).  Row-major by location, so a search over one location
+// reads one row.
+__global__ void k_loc_block_index(uint32_t n_blocks, uint32_t n_loc, const uint32_t *func_of_block,
+                                  const uint32_t *block_begin, const uint32_t *fl_def_ptr,
+                                  const uint32_t *fl_use_ptr, const uint32_t *dsi,
+                                  const uint32_t *usi, uint4 *tab) {
+  const size_t total = (size_t)n_loc * n_blocks;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < total;
+       k += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t x = (uint32_t)(k / n_blocks), b = (uint32_t)(k % n_blocks);
+    const size_t fi = (size_t)func_of_block[b] * (n_loc + 1) + x;
+    const uint32_t d0 = fl_def_ptr[fi], d1 = fl_def_ptr[fi + 1];
+    const uint32_t u0 = fl_use_ptr[fi], u1 = fl_use_ptr[fi + 1];
+    const uint32_t i0 = block_begin[b], i1 = block_begin[b + 1];
+    uint4 r;
+    r.x = lower_pos(dsi, d0, d1, i0);
+    r.y = lower_pos(dsi, r.x, d1, i1);
+    r.z = lower_pos(usi, u0, u1, i0);
+    r.w = lower_pos(usi, r.z, u1, i1);
+    tab[k] = r;
   }
 }
 
-// ------------------------------------------------------------- the tiles
-__global__ void __launch_bounds__(kTileThreads)
-k_rd_tile(const RdTile *tiles, const uint32_t *pred_ptr, const uint32_t *pred,
-          const BlockSumm *summ, const uint32_t *use_site_sorted, const uint32_t *use_instr,
-          const uint32_t *fl_use_ptr, uint32_t n_loc, const uint8_t *use_cond,
-          const uint32_t *block_of, const uint32_t *slot_start, uint64_t *rd_in) {
+// OR the def positions [g, hi) (absolute; the bitset starts at d0) into the
+// words of one IN bitset whose word w sits at in[2 * w]
+__device__ __forceinline__ void or_range(uint64_t *in, uint32_t d0, uint32_t g, uint32_t hi) {
+  if (g >= hi) return;
+  const uint32_t a = g - d0, b = hi - d0;
+  for (uint32_t w = a / 64; w * 64 < b; ++w) in[2 * w] |= range_word(a, b, w * 64);
+}
+
+// ------------------------------------------------------- the searches
+// One thread per use site (sorted order, so a wave's uses share a location):
+// for each variant, a breadth-first search backwards from the use's block
+// over whole predecessor blocks.  The blocks met are kept in a per-thread
+// list in LDS (also the queue), with a 64-bit filter in a register to skip
+// most list scans; a search that would meet more than kSearchCap blocks is
+// left to k_rd_search_long.
+__global__ void __launch_bounds__(kSearchThreads)
+k_rd_search(uint32_t n_uses, uint32_t n_blocks, uint32_t n_loc, const uint32_t *use_site_sorted,
+            const uint32_t *use_instr, const uint32_t *use_loc, const uint8_t *use_cond,
+            const uint32_t *block_of, const uint32_t *func_of_block, const uint32_t *fbb,
+            const uint32_t *pred_ptr, const uint32_t *pred, const uint32_t *fl_def_ptr,
+            const uint32_t *dsi, const uint8_t *dsg, const uint32_t *usi, const uint4 *tab,
+            const uint32_t *slot_start, uint64_t *rd_in, uint32_t *long_list, uint32_t *n_long) {
+  __shared__ uint16_t seen[kSearchCap][kSearchThreads];
+  const unsigned tid = threadIdx.x;
+  for (uint32_t k = blockIdx.x * blockDim.x + tid; k < n_uses; k += gridDim.x * blockDim.x) {
+    const uint32_t u = use_site_sorted[k];
+    const uint32_t j = use_instr[u], x = use_loc[u];
+    const uint32_t b = block_of[j], f = func_of_block[b], b0 = fbb[f];
+    const size_t fi = (size_t)f * (n_loc + 1) + x;
+    const uint32_t d0 = fl_def_ptr[fi];
+    if (fl_def_ptr[fi + 1] == d0) continue;
+    const uint32_t c = use_cond[u];
+    const uint4 *row = tab + (size_t)x * n_blocks;
+    uint64_t *in = rd_in + slot_start[k];
+    bool ok = true;
+    for (int var = 0; var < 2 && ok; ++var) {
+      const bool blocked = var == 1;
+      uint32_t n_seen = 0, head = 0;
+      uint64_t filter = 0;
+      auto visit = [&](uint32_t p) {
+        const uint32_t pl = p - b0;
+        const uint64_t bit = 1ull << ((pl * 0x9E3779B1u) >> 26);
+        if (filter & bit) {
+          for (uint32_t t = 0; t < n_seen; ++t)
+            if (seen[t][tid] == pl) return;
+        }
+        if (n_seen == kSearchCap) {
+          ok = false;
+          return;
+        }
+        filter |= bit;
+        seen[n_seen++][tid] = (uint16_t)pl;
+      };
+      for (uint32_t q = pred_ptr[b]; q < pred_ptr[b + 1] && ok; ++q) visit(pred[q]);
+      while (ok && head < n_seen) {
+        const uint32_t p = seen[head++][tid] + b0;
+        const uint4 r = row[p];
+        const Survive s = survivors_range(dsi, dsg, usi, r.x, r.y, r.z, r.w, c, blocked);
+        or_range(in + var, d0, s.g, r.y);
+        if (!s.kill)
+          for (uint32_t q = pred_ptr[p]; q < pred_ptr[p + 1] && ok; ++q) visit(pred[q]);
+      }
+    }
+    if (!ok) long_list[atomicAdd(n_long, 1u)] = k;
+  }
+}
+
+// The searches one thread could not hold: one workgroup per use, level by
+// level, with the blocks met and the IN bits in LDS.
+__global__ void __launch_bounds__(kSearchThreads)
+k_rd_search_long(uint32_t n_blocks, uint32_t n_loc, uint32_t max_nb, uint32_t max_words,
+                 const uint32_t *use_site_sorted, const uint32_t *use_instr,
+                 const uint32_t *use_loc, const uint8_t *use_cond, const uint32_t *block_of,
+                 const uint32_t *func_of_block, const uint32_t *fbb, const uint32_t *pred_ptr,
+                 const uint32_t *pred, const uint32_t *fl_def_ptr, const uint32_t *dsi,
+                 const uint8_t *dsg, const uint32_t *usi, const uint4 *tab,
+                 const uint32_t *slot_start, uint64_t *rd_in, const uint32_t *long_list,
+                 const uint32_t *n_long) {
   extern __shared__ uint64_t lds[];
-  const RdTile t = tiles[blockIdx.x];
-  const uint32_t nb = t.n_blocks, W = t.words, b0 = t.block0;
-  uint64_t *outF = lds;                        // [nb][W]
-  uint64_t *outB = lds + (size_t)nb * W;       // [nb][W]
-  uint64_t *sm = lds + 2 * (size_t)nb * W;     // [nb] clipped summaries
-  uint32_t *lptr = (uint32_t *)(sm + nb);      // [nb+1] predecessor CSR, local ids
-  uint16_t *lpred = (uint16_t *)(lptr + nb + 1);
-  const uint32_t p_base = pred_ptr[b0];
-  const uint32_t c0 = t.chunk * 64u * W, c1 = c0 + 64u * W;
-  auto clip = [&](uint32_t v) { return v < c0 ? 0u : (v > c1 ? c1 - c0 : v - c0); };
-  for (uint32_t b = threadIdx.x; b < nb; b += kTileThreads) {
-    const BlockSumm m = summ[t.summ + b];
-    sm[b] = (uint64_t)clip(m.gF) | ((uint64_t)clip(m.hi) << 14) | ((uint64_t)clip(m.gB) << 28) |
-            ((uint64_t)(m.kill & 1u) << 62) | ((uint64_t)((m.kill >> 1) & 1u) << 63);
-    lptr[b] = pred_ptr[b0 + b] - p_base;
-    for (uint32_t w = 0; w < W; ++w) {
-      outF[(size_t)b * W + w] = 0ull;
-      outB[(size_t)b * W + w] = 0ull;
-    }
-  }
-  const uint32_t np = pred_ptr[b0 + nb] - p_base;
-  if (threadIdx.x == 0) lptr[nb] = np;
-  for (uint32_t k = threadIdx.x; k < np; k += kTileThreads) lpred[k] = (uint16_t)(pred[p_base + k] - b0);
-  __syncthreads();
-  // each thread sweeps a contiguous run of blocks, in block order
-  const uint32_t per = (nb + kTileThreads - 1) / kTileThreads;
-  const uint32_t bb0 = min(threadIdx.x * per, nb), bb1 = min(bb0 + per, nb);
-  for (;;) {
-    int changed = 0;
-    for (uint32_t b = bb0; b < bb1; ++b) {
-      const uint64_t m = sm[b];
-      const uint32_t gF = (uint32_t)(m & 0x3FFF), gE = (uint32_t)((m >> 14) & 0x3FFF);
-      const uint32_t gB = (uint32_t)((m >> 28) & 0x3FFF);
-      const bool kF = (m >> 62) & 1ull, kB = (m >> 63) & 1ull;
-      const uint32_t p0 = lptr[b], p1 = lptr[b + 1];
-      for (uint32_t w = 0; w < W; ++w) {
-        uint64_t inF = 0, inB = 0;
-        if (!kF || !kB) {
-          for (uint32_t k = p0; k < p1; ++k) {
-            const uint32_t pb = lpred[k];
-            inF |= outF[(size_t)pb * W + w];
-            inB |= outB[(size_t)pb * W + w];
+  const uint32_t vis_words = (max_nb + 31) / 32;
+  uint64_t *bits = lds;                                  // [max_words]
+  uint32_t *vis = (uint32_t *)(bits + max_words);        // [vis_words]
+  uint16_t *q0 = (uint16_t *)(vis + vis_words);          // [max_nb]
+  uint16_t *q1 = q0 + max_nb;                            // [max_nb]
+  __shared__ uint32_t n_cur, n_next;
+  const unsigned tid = threadIdx.x;
+  const uint32_t nl = *n_long;
+  for (uint32_t i = blockIdx.x; i < nl; i += gridDim.x) {
+    const uint32_t k = long_list[i];
+    const uint32_t u = use_site_sorted[k];
+    const uint32_t j = use_instr[u], x = use_loc[u];
+    const uint32_t b = block_of[j], f = func_of_block[b], b0 = fbb[f];
+    const uint32_t nb = fbb[f + 1] - b0;
+    const size_t fi = (size_t)f * (n_loc + 1) + x;
+    const uint32_t d0 = fl_def_ptr[fi], nd = fl_def_ptr[fi + 1] - d0;
+    const uint32_t nw = (nd + 63) / 64;
+    const uint32_t c = use_cond[u];
+    const uint4 *row = tab + (size_t)x * n_blocks;
+    uint64_t *in = rd_in + slot_start[k];
+    for (int var = 0; var < 2; ++var) {
+      const bool blocked = var == 1;
+      __syncthreads();
+      for (uint32_t w = tid; w < nw; w += kSearchThreads) bits[w] = 0ull;
+      for (uint32_t w = tid; w < (nb + 31) / 32; w += kSearchThreads) vis[w] = 0u;
+      if (tid == 0) n_cur = 0;
+      __syncthreads();
+      for (uint32_t q = pred_ptr[b] + tid; q < pred_ptr[b + 1]; q += kSearchThreads) {
+        const uint32_t pl = pred[q] - b0;
+        if (!(atomicOr(&vis[pl / 32], 1u << (pl % 32)) & (1u << (pl % 32))))
+          q0[atomicAdd(&n_cur, 1u)] = (uint16_t)pl;
+      }
+      __syncthreads();
+      uint16_t *cur = q0, *nxt = q1;
+      for (;;) {
+        const uint32_t nc = n_cur;
+        if (nc == 0) break;
+        __syncthreads();
+        if (tid == 0) n_next = 0;
+        __syncthreads();
+        for (uint32_t t = tid; t < nc; t += kSearchThreads) {
+          const uint32_t p = cur[t] + b0;
+          const uint4 r = row[p];
+          const Survive s = survivors_range(dsi, dsg, usi, r.x, r.y, r.z, r.w, c, blocked);
+          if (s.g < r.y) {
+            const uint32_t a = s.g - d0, e = r.y - d0;
+            for (uint32_t w = a / 64; w * 64 < e; ++w)
+              atomicOr((unsigned long long *)&bits[w], (unsigned long long)range_word(a, e, w * 64));
           }
+          if (!s.kill)
+            for (uint32_t q = pred_ptr[p]; q < pred_ptr[p + 1]; ++q) {
+              const uint32_t pl = pred[q] - b0;
+              if (!(atomicOr(&vis[pl / 32], 1u << (pl % 32)) & (1u << (pl % 32))))
+                nxt[atomicAdd(&n_next, 1u)] = (uint16_t)pl;
+            }
         }
-        const uint64_t nF = (kF ? 0ull : inF) | range_word(gF, gE, 64u * w);
-        const uint64_t nB = (kB ? 0ull : inB) | range_word(gB, gE, 64u * w);
-        if (nF != outF[(size_t)b * W + w]) {
-          outF[(size_t)b * W + w] = nF;
-          changed = 1;
-        }
-        if (nB != outB[(size_t)b * W + w]) {
-          outB[(size_t)b * W + w] = nB;
-          changed = 1;
-        }
+        __syncthreads();
+        if (tid == 0) n_cur = n_next;
+        uint16_t *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+        __syncthreads();
       }
-    }
-    if (!__syncthreads_or(changed)) break;
-  }
-  // IN of each use's block, for the uses of x whose condition is this tile's
-  const size_t fi = (size_t)t.func * (n_loc + 1) + t.loc;
-  const uint32_t ub = fl_use_ptr[fi], un = fl_use_ptr[fi + 1] - ub;
-  for (uint32_t k = threadIdx.x; k < un; k += kTileThreads) {
-    const uint32_t site = use_site_sorted[ub + k];
-    if (use_cond[site] != t.cond) continue;
-    const uint32_t b = block_of[use_instr[site]] - b0;
-    const uint32_t p0 = lptr[b], p1 = lptr[b + 1];
-    uint64_t *dst = rd_in + slot_start[ub + k] + (size_t)t.chunk * 2u * W;
-    for (uint32_t w = 0; w < W; ++w) {
-      uint64_t inF = 0, inB = 0;
-      for (uint32_t q = p0; q < p1; ++q) {
-        const uint32_t pb = lpred[q];
-        inF |= outF[(size_t)pb * W + w];
-        inB |= outB[(size_t)pb * W + w];
-      }
-      dst[w] = inF;
-      dst[W + w] = inB;
+      for (uint32_t w = tid; w < nw; w += kSearchThreads) in[2 * w + var] = bits[w];
     }
   }
 }
@@ -492,30 +475,21 @@ __global__ void k_edge_fill(uint32_t n_instr, const uint32_t *use_ptr, const uin
 }
 
 // ------------------------------------------------------------------ host
-void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar) {
-  const uint32_t nf = p.n_funcs, nl = p.n_loc;
+void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar, PhaseTimer &t_search) {
+  const uint32_t nf = p.n_funcs, nl = p.n_loc, nb = p.n_blocks;
   const size_t nfl = (size_t)nf * nl;
   uint32_t *dsi = ar.get<uint32_t>(p.n_defs), *usi = ar.get<uint32_t>(p.n_uses);
   uint8_t *dsg = ar.get<uint8_t>(p.n_defs);
   hipLaunchKernelGGL(k_sorted_views, dim3(grid_for((size_t)p.n_defs + p.n_uses, 256, 8192)),
                      dim3(256), 0, s, p.n_defs, p.n_uses, p.def_site_sorted.p, p.def_instr.p,
                      p.use_site_sorted.p, p.use_instr.p, p.guard.p, dsi, dsg, usi);
-  uint32_t *fl_words = ar.get<uint32_t>(nfl), *fl_chunks = ar.get<uint32_t>(nfl);
-  uint64_t *fl_mask = ar.get<uint64_t>(nfl);
-  uint32_t *fl_tiles = ar.get<uint32_t>(nfl), *fl_summ = ar.get<uint32_t>(nfl);
-  uint32_t *fl_tstart = ar.get<uint32_t>(nfl), *fl_sstart = ar.get<uint32_t>(nfl);
-  GPA_HIP(hipMemsetAsync(fl_mask, 0, 8 * nfl, s));
-  hipLaunchKernelGGL(k_use_condmask, dim3(grid_for(p.n_uses, 256, 8192)), dim3(256), 0, s,
-                     p.n_uses, nl, p.use_instr.p, p.use_loc.p, p.block_of.p, p.func_of_block.p,
-                     p.use_cond.p, (unsigned long long *)fl_mask);
-  hipLaunchKernelGGL(k_fl_plan, dim3(grid_for(nfl, 256, 4096)), dim3(256), 0, s, nf, nl,
-                     p.func_block_begin.p, p.succ_ptr.p, p.fl_def_ptr.p, p.fl_use_ptr.p, fl_words,
-                     fl_chunks, fl_mask, fl_tiles, fl_summ);
   GPA_LAUNCH_CHECK();
-  unsigned long long *ntiles_d = ar.get<unsigned long long>(1);
-  unsigned long long *nsumm_d = ar.get<unsigned long long>(1);
-  exclusive_scan_u32(fl_tiles, fl_tstart, nfl, s, ar, ntiles_d);
-  exclusive_scan_u32(fl_summ, fl_sstart, nfl, s, ar, nsumm_d);
+  uint32_t *fl_words = ar.get<uint32_t>(nfl), *fl_chunks = ar.get<uint32_t>(nfl);
+  uint32_t *scal = ar.get<uint32_t>(2);   // [0] largest IN bitset in words, [1] long searches
+  GPA_HIP(hipMemsetAsync(scal, 0, 8, s));
+  hipLaunchKernelGGL(k_rd_plan, dim3(grid_for(nfl, 256, 4096)), dim3(256), 0, s, nf, nl,
+                     p.fl_def_ptr.p, fl_words, fl_chunks, scal);
+  GPA_LAUNCH_CHECK();
   // IN slots per use site, in sorted-use order
   uint32_t *slot_words = ar.get<uint32_t>(p.n_uses);
   uint32_t *slot_start = ar.get<uint32_t>(p.n_uses);
@@ -525,27 +499,38 @@ void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar) {
                      fl_chunks, p.use_rank.p, slot_words);
   GPA_LAUNCH_CHECK();
   exclusive_scan_u32(slot_words, slot_start, p.n_uses, s, ar, nslot_d);
-  const uint64_t ntiles = read_scalar(ntiles_d, s);
-  const uint64_t nsumm = read_scalar(nsumm_d, s);
   const uint64_t nslot = read_scalar(nslot_d, s);
-  uint64_t *rd_in = ar.get<uint64_t>(nslot);
-  if (ntiles) {
-    RdTile *tiles = ar.get<RdTile>(ntiles);
-    BlockSumm *summ = ar.get<BlockSumm>(nsumm);
-    hipLaunchKernelGGL(k_fl_tiles, dim3(grid_for(nfl, 256, 4096)), dim3(256), 0, s, nf, nl,
-                       p.func_block_begin.p, fl_words, fl_chunks, fl_mask, fl_tstart, fl_sstart,
-                       tiles);
-    hipLaunchKernelGGL(k_rd_summ, dim3((unsigned)ntiles), dim3(kTileThreads), 0, s, tiles,
-                       p.block_begin.p, p.fl_def_ptr.p, p.fl_use_ptr.p, nl, dsi, dsg, usi, summ);
+  const uint32_t max_words = read_scalar(scal, s);
+  uint64_t *rd_in = ar.get<uint64_t>(nslot ? nslot : 1);
+  if (nslot) {
+    const size_t lds_long = 8u * (size_t)max_words + 4u * ((p.max_func_blocks + 31) / 32) +
+                            4u * (size_t)p.max_func_blocks + 16u;
+    if (lds_long > 160 * 1024)
+      fail(GPA_E_UNSUPPORTED, "a location has %u defs in one function (at most %u supported)",
+           64u * max_words, 64u * (uint32_t)((120u * 1024u) / 8u));
+    GPA_HIP(hipMemsetAsync(rd_in, 0, 8 * nslot, s));
+    uint4 *tab = ar.get<uint4>((size_t)nl * nb);
+    hipLaunchKernelGGL(k_loc_block_index, dim3(grid_for((size_t)nl * nb, 256, 8192)), dim3(256),
+                       0, s, nb, nl, p.func_of_block.p, p.block_begin.p, p.fl_def_ptr.p,
+                       p.fl_use_ptr.p, dsi, usi, tab);
     GPA_LAUNCH_CHECK();
-    const size_t lds = std::max<size_t>(kLdsBudget, (size_t)p.max_func_blocks * 28u +
-                                                        2u * p.max_func_edges + 16u);
-    GPA_HIP(hipFuncSetAttribute((const void *)k_rd_tile, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds));
-    hipLaunchKernelGGL(k_rd_tile, dim3((unsigned)ntiles), dim3(kTileThreads), lds, s, tiles,
-                       p.pred_ptr.p, p.pred.p, summ, p.use_site_sorted.p, p.use_instr.p,
-                       p.fl_use_ptr.p, nl, p.use_cond.p, p.block_of.p, slot_start, rd_in);
+    uint32_t *long_list = ar.get<uint32_t>(p.n_uses);
+    t_search.begin(kPhaseRdSearch, s);
+    hipLaunchKernelGGL(k_rd_search, dim3(grid_for(p.n_uses, kSearchThreads, 8192)),
+                       dim3(kSearchThreads), 0, s, p.n_uses, nb, nl, p.use_site_sorted.p,
+                       p.use_instr.p, p.use_loc.p, p.use_cond.p, p.block_of.p, p.func_of_block.p,
+                       p.func_block_begin.p, p.pred_ptr.p, p.pred.p, p.fl_def_ptr.p, dsi, dsg, usi,
+                       tab, slot_start, rd_in, long_list, scal + 1);
     GPA_LAUNCH_CHECK();
+    GPA_HIP(hipFuncSetAttribute((const void *)k_rd_search_long,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_long));
+    hipLaunchKernelGGL(k_rd_search_long, dim3(kLongGrid), dim3(kSearchThreads), lds_long, s, nb,
+                       nl, p.max_func_blocks, max_words, p.use_site_sorted.p, p.use_instr.p,
+                       p.use_loc.p, p.use_cond.p, p.block_of.p, p.func_of_block.p,
+                       p.func_block_begin.p, p.pred_ptr.p, p.pred.p, p.fl_def_ptr.p, dsi, dsg, usi,
+                       tab, slot_start, rd_in, long_list, scal + 1);
+    GPA_LAUNCH_CHECK();
+    t_search.end(s);
   }
   // per-use source lists
   uint32_t *rd_cnt = ar.get<uint32_t>(p.n_uses + 1);

@@ -31,6 +31,12 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, d, kWave));
+  return v;
+}
+
 // Exclusive scan across a workgroup of NT threads (NT a multiple of 64);
 // `smem` holds NT/64 + 1 elements.  Returns the exclusive prefix of this
 // thread and writes the workgroup total to *total.

@@ -17,68 +17,113 @@
 namespace gpa {
 
 // ------------------------------------------------------------------ DFS
-// One workgroup per function; its successor lists are staged in LDS and one
-// lane walks them (the visiting order is sequential by definition).
+// One wave per function walks its CFG depth-first (the visiting order is
+// sequential by definition).  Every lane executes the same walk, so the
+// walk's values are wave-uniform; the visited and finished sets are bitsets
+// spread over the lanes of two VGPRs each (bit v in word v/32, word w in
+// lane w%64 of register w/64), so a membership test is one readlane instead
+// of an LDS round trip.  Each block's edge range and first two successors
+// are staged together, so most tree edges cost one LDS read and most other
+// edges none; the stack holds (block, next edge, end, next successor).
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ bool bit_test(uint32_t r0, uint32_t r1, uint32_t v) {
+  const uint32_t w = v >> 5;
+  const uint32_t word = (w >> 6) ? __builtin_amdgcn_readlane(r1, w & 63)
+                                 : __builtin_amdgcn_readlane(r0, w & 63);
+  return (word >> (v & 31)) & 1u;
+}
+
+__device__ __forceinline__ void bit_set(uint32_t &r0, uint32_t &r1, uint32_t v) {
+  const uint32_t w = v >> 5;
+  const uint32_t m = (lane_id() == (w & 63)) ? (1u << (v & 31)) : 0u;
+  if (w >> 6) r1 |= m;
+  else r0 |= m;
+}
+
+constexpr uint32_t kNoSucc = 0xFFFFu;
+
 __global__ void __launch_bounds__(64)
 k_dfs(const uint32_t *fbb, const uint32_t *succ_ptr, const uint32_t *succ, uint8_t *retreat,
       uint32_t *rpo_pos, uint32_t *rpo_order) {
-  extern __shared__ uint32_t sh[];
+  extern __shared__ uint4 shq[];
   const uint32_t f = blockIdx.x;
   const uint32_t b0 = fbb[f], nb = fbb[f + 1] - b0;
   const uint32_t e0 = succ_ptr[b0], ne = succ_ptr[b0 + nb] - e0;
-  uint32_t *lptr = sh;                       // [nb+1]
-  uint32_t *sk = lptr + nb + 1;              // [nb] saved edge cursors
-  uint16_t *lsucc = (uint16_t *)(sk + nb);   // [ne]
-  uint16_t *stk = lsucc + ne;                // [nb] saved blocks
-  uint16_t *post = stk + nb;                 // [nb]
-  uint8_t *state = (uint8_t *)(post + nb);   // [nb] 0 new, 1 on the stack, 2 done
-  uint8_t *ret = state + nb;                 // [ne]
-  for (uint32_t b = threadIdx.x; b <= nb; b += 64) lptr[b] = succ_ptr[b0 + b] - e0;
-  for (uint32_t e = threadIdx.x; e < ne; e += 64) {
+  const unsigned lane = lane_id();
+  uint4 *stk = shq;                            // [nb] (block, next edge, end, next successor)
+  uint2 *rng = (uint2 *)(stk + nb);            // [nb] edge range
+  uint32_t *s01 = (uint32_t *)(rng + nb);      // [nb] first two successors
+  uint16_t *lsucc = (uint16_t *)(s01 + nb);    // [ne]
+  uint16_t *post = lsucc + ne;                 // [nb]
+  uint8_t *ret = (uint8_t *)(post + nb);       // [ne]
+  for (uint32_t b = lane; b < nb; b += 64) {
+    const uint32_t lo = succ_ptr[b0 + b] - e0, hi = succ_ptr[b0 + b + 1] - e0;
+    rng[b] = make_uint2(lo, hi);
+    const uint32_t a0 = lo < hi ? succ[e0 + lo] - b0 : kNoSucc;
+    const uint32_t a1 = lo + 1 < hi ? succ[e0 + lo + 1] - b0 : kNoSucc;
+    s01[b] = a0 | (a1 << 16);
+  }
+  for (uint32_t e = lane; e < ne; e += 64) {
     lsucc[e] = (uint16_t)(succ[e0 + e] - b0);
     ret[e] = 0;
   }
-  for (uint32_t b = threadIdx.x; b < nb; b += 64) state[b] = 0;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    // the block on top of the stack and its edge cursor live in registers;
-    // the stack holds the blocks below it with their cursors
-    uint32_t npost = 0;
-    for (uint32_t root = 0; root < nb; ++root) {
-      if (state[root]) continue;
-      uint32_t sp = 0, u = root, k = lptr[root], end = lptr[root + 1];
-      state[root] = 1;
-      while (true) {
-        if (k < end) {
-          const uint32_t v = lsucc[k];
-          const uint8_t sv = state[v];
-          if (sv == 0) {
-            stk[sp] = (uint16_t)u;
-            sk[sp] = k + 1;
-            ++sp;
-            state[v] = 1;
-            u = v;
-            k = lptr[v];
-            end = lptr[v + 1];
-          } else {
-            if (sv == 1) ret[k] = 1;
-            ++k;
-          }
+  uint32_t vis0 = 0, vis1 = 0, fin0 = 0, fin1 = 0;
+  uint32_t npost = 0;
+  for (uint32_t root = 0; root < nb; ++root) {
+    if (bit_test(vis0, vis1, root)) continue;
+    bit_set(vis0, vis1, root);
+    uint32_t sp = 0, u = root;
+    uint2 r = rng[root];
+    uint32_t pair = uni(s01[root]);
+    uint32_t k = uni(r.x), end = uni(r.y);
+    // the successor at edge k when it is known without a read; `fresh` while
+    // k is the first edge of u, whose second successor is staged too
+    uint32_t nextv = k < end ? (pair & 0xFFFFu) : kNoSucc;
+    uint32_t second = pair >> 16;
+    bool fresh = true;
+    for (;;) {
+      if (k < end) {
+        const uint32_t v = nextv != kNoSucc ? nextv : uni(lsucc[k]);
+        const uint32_t k1 = k + 1;
+        const uint32_t after = (fresh && k1 < end) ? second : kNoSucc;
+        fresh = false;
+        if (!bit_test(vis0, vis1, v)) {
+          if (lane == 0) stk[sp] = make_uint4(u, k1, end, after);
+          ++sp;
+          bit_set(vis0, vis1, v);
+          u = v;
+          r = rng[v];
+          pair = uni(s01[v]);
+          k = uni(r.x);
+          end = uni(r.y);
+          nextv = k < end ? (pair & 0xFFFFu) : kNoSucc;
+          second = pair >> 16;
+          fresh = true;
         } else {
-          state[u] = 2;
-          post[npost++] = (uint16_t)u;
-          if (sp == 0) break;
-          --sp;
-          u = stk[sp];
-          k = sk[sp];
-          end = lptr[u + 1];
+          if (!bit_test(fin0, fin1, v) && lane == 0) ret[k] = 1;
+          k = k1;
+          nextv = after;
         }
+      } else {
+        bit_set(fin0, fin1, u);
+        if (lane == 0) post[npost] = (uint16_t)u;
+        ++npost;
+        if (sp == 0) break;
+        --sp;
+        const uint4 t = stk[sp];
+        u = uni(t.x);
+        k = uni(t.y);
+        end = uni(t.z);
+        nextv = uni(t.w);
+        fresh = false;
       }
     }
   }
   __syncthreads();
-  for (uint32_t e = threadIdx.x; e < ne; e += 64) retreat[e0 + e] = ret[e];
-  for (uint32_t k = threadIdx.x; k < nb; k += 64) {
+  for (uint32_t e = lane; e < ne; e += 64) retreat[e0 + e] = ret[e];
+  for (uint32_t k = lane; k < nb; k += 64) {
     const uint32_t b = post[nb - 1 - k];   // reverse postorder
     rpo_pos[b0 + b] = k;
     rpo_order[b0 + k] = b0 + b;
@@ -157,28 +202,48 @@ __global__ void k_sweep_fill(uint32_t n_blocks, const uint32_t *fbb,
 //   shortest:  E[w] = min over edges v -> w of (v == s ? 0 : E[v]) + |w|
 //   longest:   the same maximum over edges that are not retreating, -1 for
 //              blocks no G' walk from s reaches.
-// The value of the block swept just before stays in a register, so a chain
-// of single-predecessor blocks never waits on LDS.
+// Table reads run kPD entries ahead of their use, so they are issued before
+// the writes of the kPD entries in between; those writes are kept in a
+// register ring and forwarded (a block is written once per sweep, so at most
+// one ring slot matches).
+constexpr int kPD = 4;
+
 template <bool kLongest>
 __device__ void dist_sweep(uint32_t *D, uint32_t L, uint32_t li, bool writer, uint32_t s,
                            const uint32_t *ent, const uint32_t *ent_w, uint32_t e_begin,
                            uint32_t e_end) {
   const unsigned lane = threadIdx.x;
-  uint32_t prev_w = kLocalNone, prev_e = kInf;
+  uint32_t rw[kPD], re[kPD];
+#pragma unroll
+  for (int r = 0; r < kPD; ++r) {
+    rw[r] = kLocalNone;
+    re[r] = kInf;
+  }
   uint32_t best = kInf;
   for (uint32_t base = e_begin; base < e_end; base += 64) {
     const uint32_t idx = base + lane;
     const uint32_t vp = idx < e_end ? ent[idx] : kLocalNone;
     const uint32_t vw = idx < e_end ? ent_w[idx] : 0u;
-#pragma unroll 16
+    uint32_t pre[kPD];
+#pragma unroll
+    for (int i = 0; i < kPD; ++i) {
+      const uint32_t v = __builtin_amdgcn_readlane(vp, i) & kLocalNone;
+      pre[i] = D[(v == kLocalNone ? 0u : v) * L + li];
+    }
+#pragma unroll
     for (int i = 0; i < 64; ++i) {
       const uint32_t pk = __builtin_amdgcn_readlane(vp, i);
       const uint32_t v = pk & kLocalNone;
+      uint32_t c = pre[i % kPD];
+      if (i + kPD < 64) {
+        const uint32_t vn = __builtin_amdgcn_readlane(vp, i + kPD) & kLocalNone;
+        pre[i % kPD] = D[(vn == kLocalNone ? 0u : vn) * L + li];
+      }
       if (pk & kEntFirst) best = kInf;
       if (v != kLocalNone && !(kLongest && (pk & kEntRet))) {
-        uint32_t c;
-        if (v == prev_w) c = prev_e;
-        else c = D[v * L + li];
+#pragma unroll
+        for (int r = 0; r < kPD; ++r)
+          if (v == rw[r]) c = re[r];
         if (v == s) c = 0;
         // kInf reads as -1 for longest walks: no walk
         best = kLongest ? (uint32_t)max((int32_t)best, (int32_t)c) : min(best, c);
@@ -188,8 +253,13 @@ __device__ void dist_sweep(uint32_t *D, uint32_t L, uint32_t li, bool writer, ui
         const uint32_t bw = __builtin_amdgcn_readlane(vw, i);
         const uint32_t e = (best == kInf) ? kInf : best + bw;
         if (writer) D[w * L + li] = e;
-        prev_w = w;
-        prev_e = e;
+#pragma unroll
+        for (int r = kPD - 1; r > 0; --r) {
+          rw[r] = rw[r - 1];
+          re[r] = re[r - 1];
+        }
+        rw[0] = w;
+        re[0] = e;
       }
     }
   }
@@ -290,43 +360,52 @@ k_dist(uint32_t n_blocks, uint32_t n_funcs, uint32_t L, const uint32_t *fbb,
   }
 }
 
-void build_distances(gpa_program &p, hipStream_t s, Arena &ar) {
+void build_cfg_order(gpa_program &p, hipStream_t s, Arena &ar, SweepPlan &plan,
+                     PhaseTimer &t_dfs) {
   const uint32_t nf = p.n_funcs, nb = p.n_blocks;
   const uint32_t max_ne = p.max_func_edges;
   const uint32_t max_nb = p.max_func_blocks;
   p.retreat.alloc(p.n_succ);
   p.rpo_pos.alloc(nb);
   p.rpo_order.alloc(nb);
-  const size_t lds_dfs = 4u * (2 * (size_t)max_nb + 1) + 2u * max_ne + 6u * max_nb + max_nb +
-                         max_ne + 16;
+  const size_t lds_dfs = 28u * (size_t)max_nb + 2u * max_nb + 3u * (size_t)max_ne + 16;
   if (lds_dfs > 160 * 1024)
     fail(GPA_E_UNSUPPORTED, "a function's CFG (%u blocks, %u edges) exceeds the LDS staging",
          max_nb, max_ne);
   GPA_HIP(hipFuncSetAttribute((const void *)k_dfs, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds_dfs));
+  t_dfs.begin(kPhaseDfs, s);
   hipLaunchKernelGGL(k_dfs, dim3(nf), dim3(64), lds_dfs, s, p.func_block_begin.p, p.succ_ptr.p,
                      p.succ.p, p.retreat.p, p.rpo_pos.p, p.rpo_order.p);
   GPA_LAUNCH_CHECK();
-  p.e_dmin.alloc(p.n_edges);
-  p.e_dmax.alloc(p.n_edges);
-  if (p.n_edges == 0) return;
+  t_dfs.end(s);
   // sweep streams
   uint32_t *cnt = ar.get<uint32_t>((size_t)nb + 1), *rcnt = ar.get<uint32_t>((size_t)nb + 1);
-  uint32_t *ent_ptr = ar.get<uint32_t>((size_t)nb + 1), *ret_ptr = ar.get<uint32_t>((size_t)nb + 1);
+  plan.ent_ptr = ar.get<uint32_t>((size_t)nb + 1);
+  plan.ret_ptr = ar.get<uint32_t>((size_t)nb + 1);
   const size_t n_ent = (size_t)p.n_succ + nb;   // upper bound
-  uint32_t *ent = ar.get<uint32_t>(n_ent), *ent_w = ar.get<uint32_t>(n_ent);
-  uint32_t *rent = ar.get<uint32_t>(p.n_succ ? p.n_succ : 1);
-  uint32_t *rent_w = ar.get<uint32_t>(p.n_succ ? p.n_succ : 1);
+  plan.ent = ar.get<uint32_t>(n_ent);
+  plan.ent_w = ar.get<uint32_t>(n_ent);
+  plan.rent = ar.get<uint32_t>(p.n_succ ? p.n_succ : 1);
+  plan.rent_w = ar.get<uint32_t>(p.n_succ ? p.n_succ : 1);
   const uint32_t g = grid_for(nb, 256, 4096);
   hipLaunchKernelGGL(k_sweep_count, dim3(g), dim3(256), 0, s, nb, p.func_block_begin.p,
                      p.func_of_block.p, p.pred_ptr.p, p.pred.p, p.rpo_pos.p, cnt, rcnt);
   GPA_LAUNCH_CHECK();
-  exclusive_scan_u32(cnt, ent_ptr, (size_t)nb + 1, s, ar);
-  exclusive_scan_u32(rcnt, ret_ptr, (size_t)nb + 1, s, ar);
+  exclusive_scan_u32(cnt, plan.ent_ptr, (size_t)nb + 1, s, ar);
+  exclusive_scan_u32(rcnt, plan.ret_ptr, (size_t)nb + 1, s, ar);
   hipLaunchKernelGGL(k_sweep_fill, dim3(g), dim3(256), 0, s, nb, p.func_block_begin.p,
                      p.func_of_block.p, p.block_begin.p, p.pred_ptr.p, p.pred.p, p.rpo_pos.p,
-                     ent_ptr, ret_ptr, ent, ent_w, rent, rent_w);
+                     plan.ent_ptr, plan.ret_ptr, plan.ent, plan.ent_w, plan.rent, plan.rent_w);
   GPA_LAUNCH_CHECK();
+}
+
+void build_distances(gpa_program &p, hipStream_t s, Arena &ar, const SweepPlan &plan) {
+  const uint32_t nf = p.n_funcs, nb = p.n_blocks;
+  const uint32_t max_nb = p.max_func_blocks;
+  p.e_dmin.alloc(p.n_edges);
+  p.e_dmax.alloc(p.n_edges);
+  if (p.n_edges == 0) return;
   const uint32_t L = std::max<uint32_t>(1u, std::min<uint32_t>(64u, kDistLds / (4u * max_nb)));
   const size_t lds = (size_t)4 * L * max_nb;
   GPA_HIP(hipFuncSetAttribute((const void *)k_dist, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -335,9 +414,9 @@ void build_distances(gpa_program &p, hipStream_t s, Arena &ar) {
   GPA_HIP(hipMemcpyAsync(lat, p.arch.lat, sizeof(p.arch.lat), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_dist, dim3((nb + L - 1) / L), dim3(64), lds, s, nb, nf, L,
                      p.func_block_begin.p, p.func_of_block.p, p.block_begin.p, p.block_of.p,
-                     ent_ptr, ent, ent_w, ret_ptr, rent, rent_w, p.out_ptr.p, p.out_perm.p,
-                     p.e_src.p, p.e_dst.p, p.op_class.p, lat, p.e_dmin.p, p.e_dmax.p,
-                     p.e_flags.p);
+                     plan.ent_ptr, plan.ent, plan.ent_w, plan.ret_ptr, plan.rent, plan.rent_w,
+                     p.out_ptr.p, p.out_perm.p, p.e_src.p, p.e_dst.p, p.op_class.p, lat, p.e_dmin.p,
+                     p.e_dmax.p, p.e_flags.p);
   GPA_LAUNCH_CHECK();
 }
 
@@ -365,6 +444,15 @@ __global__ void k_edge_scopes(uint64_t n_edges, const uint32_t *e_src, const uin
   }
 }
 
+// segments of more than kSmallSeg elements, listed for a workgroup each
+__global__ void k_big_segments(uint32_t n_seg, const uint32_t *ptr, const uint32_t *end,
+                               uint32_t *list, uint32_t *n_list) {
+  for (uint32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < n_seg; l += gridDim.x * blockDim.x) {
+    const uint32_t a = ptr ? ptr[l] : l, b = ptr ? ptr[l + 1] : end[l];
+    if (b - a > kSmallSeg) list[atomicAdd(n_list, 1u)] = l;
+  }
+}
+
 void build_scope_targets(gpa_program &p, hipStream_t s, Arena &ar) {
   const uint64_t ne = p.n_edges;
   p.e_lca.alloc(ne);
@@ -379,6 +467,15 @@ void build_scope_targets(gpa_program &p, hipStream_t s, Arena &ar) {
   group_by_key(p.e_icl.p, ne, p.n_scopes, p.icl_ptr, p.icl_perm, s, ar);
   p.n_icl = read_scalar(p.icl_ptr.p + p.n_scopes, s);
   group_by_key(p.instr_scope.p, p.n_instr, p.n_scopes, p.line_ptr, p.line_perm, s, ar);
+  const uint32_t ns = p.n_scopes;
+  p.big_list.alloc((size_t)4 * ns);
+  p.big_n.alloc(4);
+  GPA_HIP(hipMemsetAsync(p.big_n.p, 0, 16, s));
+  const uint32_t *ptrs[4] = {p.line_ptr.p, p.icl_ptr.p, p.lca_ptr.p, nullptr};
+  for (int g = 0; g < 4; ++g)
+    hipLaunchKernelGGL(k_big_segments, dim3(grid_for(ns, 256, 4096)), dim3(256), 0, s, ns, ptrs[g],
+                       p.scope_end.p, p.big_list.p + (size_t)g * ns, p.big_n.p + g);
+  GPA_LAUNCH_CHECK();
 }
 
 }  // namespace gpa

@@ -85,54 +85,85 @@ __global__ void k_gather(size_t n, const uint32_t *perm, const double *src, doub
   }
 }
 
-// Segmented sums over contiguous ranges: one workgroup per segment l,
-// range [begin(l), end(l)) given either by ptr[l], ptr[l+1] (ptr mode) or by
-// l, end[l] (subtree mode).  Each thread owns a fixed stride of the range and
-// the block reduction has a fixed shape, so the result is deterministic.
+// Segmented sums over contiguous ranges [begin(l), end(l)), given either by
+// ptr[l], ptr[l+1] (ptr mode) or by l, end[l] (subtree mode).  A segment of
+// at most kSmallSeg elements is summed by one thread in element order; the
+// longer ones (listed once at load) by one workgroup each, every thread
+// owning a fixed stride and the reduction a fixed shape.  Either way the
+// result does not depend on scheduling.
+template <int W>
+__global__ void k_seg_small(uint32_t n_seg, const uint32_t *ptr, const uint32_t *end,
+                            const double *data, double *out) {
+  for (uint32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < n_seg;
+       l += gridDim.x * blockDim.x) {
+    const uint32_t a = ptr ? ptr[l] : l;
+    const uint32_t b = ptr ? ptr[l + 1] : end[l];
+    if (b - a > kSmallSeg) continue;
+    double v[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) v[q] = 0.0;
+    for (uint32_t i = a; i < b; ++i)
+#pragma unroll
+      for (int q = 0; q < W; ++q) v[q] += data[(size_t)i * W + q];
+#pragma unroll
+    for (int q = 0; q < W; ++q) out[(size_t)l * W + q] = v[q];
+  }
+}
+
 template <int W>
 __global__ void __launch_bounds__(256)
-k_seg_sum(uint32_t n_seg, const uint32_t *ptr, const uint32_t *end, const double *data,
-          double *out, int accumulate) {
+k_seg_big(const uint32_t *list, const uint32_t *n_list, const uint32_t *ptr, const uint32_t *end,
+          const double *data, double *out) {
   __shared__ double red[4][W];
-  const uint32_t l = blockIdx.x;
-  if (l >= n_seg) return;
-  const uint32_t a = ptr ? ptr[l] : l;
-  const uint32_t b = ptr ? ptr[l + 1] : end[l];
-  double v[W];
+  const uint32_t nl = *n_list;
+  for (uint32_t g = blockIdx.x; g < nl; g += gridDim.x) {
+    const uint32_t l = list[g];
+    const uint32_t a = ptr ? ptr[l] : l;
+    const uint32_t b = ptr ? ptr[l + 1] : end[l];
+    double v[W];
 #pragma unroll
-  for (int q = 0; q < W; ++q) v[q] = 0.0;
-  uint32_t i = a + threadIdx.x;
-  for (; i + 3 * 256 < b; i += 4 * 256) {
-    double t0[W], t1[W], t2[W], t3[W];
+    for (int q = 0; q < W; ++q) v[q] = 0.0;
+    uint32_t i = a + threadIdx.x;
+    for (; i + 3 * 256 < b; i += 4 * 256) {
+      double t0[W], t1[W], t2[W], t3[W];
 #pragma unroll
-    for (int q = 0; q < W; ++q) {
-      t0[q] = data[(size_t)i * W + q];
-      t1[q] = data[(size_t)(i + 256) * W + q];
-      t2[q] = data[(size_t)(i + 512) * W + q];
-      t3[q] = data[(size_t)(i + 768) * W + q];
+      for (int q = 0; q < W; ++q) {
+        t0[q] = data[(size_t)i * W + q];
+        t1[q] = data[(size_t)(i + 256) * W + q];
+        t2[q] = data[(size_t)(i + 512) * W + q];
+        t3[q] = data[(size_t)(i + 768) * W + q];
+      }
+#pragma unroll
+      for (int q = 0; q < W; ++q) v[q] += ((t0[q] + t1[q]) + (t2[q] + t3[q]));
+    }
+    for (; i < b; i += 256) {
+#pragma unroll
+      for (int q = 0; q < W; ++q) v[q] += data[(size_t)i * W + q];
     }
 #pragma unroll
-    for (int q = 0; q < W; ++q) v[q] += ((t0[q] + t1[q]) + (t2[q] + t3[q]));
-  }
-  for (; i < b; i += 256) {
+    for (int q = 0; q < W; ++q) v[q] = wave_sum(v[q]);
+    const unsigned w = threadIdx.x / kWave;
+    if (lane_id() == 0)
 #pragma unroll
-    for (int q = 0; q < W; ++q) v[q] += data[(size_t)i * W + q];
-  }
+      for (int q = 0; q < W; ++q) red[w][q] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
 #pragma unroll
-  for (int q = 0; q < W; ++q) v[q] = wave_sum(v[q]);
-  const unsigned w = threadIdx.x / kWave;
-  if (lane_id() == 0)
-#pragma unroll
-    for (int q = 0; q < W; ++q) red[w][q] = v[q];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < W; ++q) {
-      const double s = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
-      if (accumulate) out[(size_t)l * W + q] += s;
-      else out[(size_t)l * W + q] = s;
+      for (int q = 0; q < W; ++q)
+        out[(size_t)l * W + q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
     }
+    __syncthreads();
   }
+}
+
+template <int W>
+void seg_sum(uint32_t n_seg, const uint32_t *ptr, const uint32_t *end, const uint32_t *big_list,
+             const uint32_t *big_n, const double *data, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_small<W>, dim3(grid_for(n_seg, 256, 8192)), dim3(256), 0, s, n_seg, ptr,
+                     end, data, out);
+  hipLaunchKernelGGL(k_seg_big<W>, dim3(std::min<uint32_t>(n_seg, 512)), dim3(256), 0, s, big_list,
+                     big_n, ptr, end, data, out);
+  GPA_LAUNCH_CHECK();
 }
 
 // own sums of the two edge optimizers, merged into the per-scope vectors
@@ -170,10 +201,11 @@ __global__ void k_speedup(uint32_t n_scopes, const uint32_t *parent, const uint3
 }
 
 // ------------------------------------------------------------------ top-k
-// Two stages: chunks of one kernel's (scope, optimizer) items each keep a
-// top-16 per thread in registers and merge it across the workgroup; one
-// workgroup per kernel then merges its chunks' candidates.  Order: speedup
-// descending, then optimizer, then scope ascending (a total order).
+// Two stages of bitonic sorts in LDS: each chunk of one kernel's (scope,
+// optimizer) items is sorted and keeps its best 16; one workgroup per kernel
+// then sorts its chunks' candidates (in rounds of kTopChunk, carrying the
+// best 16 forward).  Order: speedup descending, then optimizer, then scope
+// ascending (a total order, so the result is unique).
 struct Cand {
   double s;
   uint32_t o, l;
@@ -187,7 +219,7 @@ __device__ __forceinline__ bool better(const Cand &a, const Cand &b) {
 
 constexpr int kTopK = 16;
 constexpr int kTopThreads = 256;
-constexpr uint32_t kTopChunk = 16384;   // items per stage-1 workgroup
+constexpr uint32_t kTopChunk = 2048;   // items per sort (a power of two)
 
 __device__ __forceinline__ Cand cand_none() {
   Cand c;
@@ -197,36 +229,22 @@ __device__ __forceinline__ Cand cand_none() {
   return c;
 }
 
-__device__ __forceinline__ void top_insert(Cand (&top)[kTopK], const Cand &c) {
-  if (!better(c, top[kTopK - 1])) return;
-  top[kTopK - 1] = c;
-#pragma unroll
-  for (int i = kTopK - 1; i > 0; --i) {
-    if (better(top[i], top[i - 1])) {
-      const Cand t = top[i];
-      top[i] = top[i - 1];
-      top[i - 1] = t;
-    }
-  }
-}
-
-// the workgroup's best 16 in order into out[0..16)
-__device__ void block_merge(Cand (&top)[kTopK], Cand *red, Cand *out) {
-  for (int t = 0; t < kTopK; ++t) {
-    red[threadIdx.x] = top[0];
-    __syncthreads();
-    for (int w = kTopThreads / 2; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w && better(red[threadIdx.x + w], red[threadIdx.x]))
-        red[threadIdx.x] = red[threadIdx.x + w];
+// sorts a[0..kTopChunk) best first
+__device__ void bitonic_best_first(Cand *a) {
+  for (uint32_t k = 2; k <= kTopChunk; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < kTopChunk; i += kTopThreads) {
+        const uint32_t ixj = i ^ j;
+        if (ixj > i) {
+          const Cand x = a[i], y = a[ixj];
+          const bool swap = ((i & k) == 0) ? better(y, x) : better(x, y);
+          if (swap) {
+            a[i] = y;
+            a[ixj] = x;
+          }
+        }
+      }
       __syncthreads();
-    }
-    const Cand best = red[0];
-    __syncthreads();
-    if (threadIdx.x == 0) out[t] = best;
-    if (best.o != 0xFFFFFFFFu && top[0].o == best.o && top[0].l == best.l) {
-#pragma unroll
-      for (int i = 0; i < kTopK - 1; ++i) top[i] = top[i + 1];
-      top[kTopK - 1] = cand_none();
     }
   }
 }
@@ -243,47 +261,53 @@ __global__ void __launch_bounds__(kTopThreads)
 k_topk_chunks(uint32_t n_roots, const uint32_t *roots, const uint32_t *nchunks,
               const uint32_t *chunk_start, const uint32_t *scope_end, const double *speedup,
               Cand *cand) {
-  __shared__ Cand red[kTopThreads];
+  __shared__ Cand a[kTopChunk];
   const uint32_t c = blockIdx.x;
   const uint32_t total = chunk_start[n_roots - 1] + nchunks[n_roots - 1];
   if (c >= total) return;
   const uint32_t ri = upper_index_u32(chunk_start, 0, n_roots, c);
   const uint32_t r = roots[ri];
   const uint64_t n_items = (uint64_t)(scope_end[r] - r) * GPA_N_OPT;
-  const uint64_t a = (uint64_t)(c - chunk_start[ri]) * kTopChunk;
-  const uint64_t b = min(a + kTopChunk, n_items);
-  Cand top[kTopK];
-#pragma unroll
-  for (int i = 0; i < kTopK; ++i) top[i] = cand_none();
-  const double *base = speedup + (size_t)r * GPA_N_OPT;
-  for (uint64_t it = a + threadIdx.x; it < b; it += kTopThreads) {
-    Cand x;
-    x.s = base[it];
-    x.l = r + (uint32_t)(it / GPA_N_OPT);
-    x.o = (uint32_t)(it % GPA_N_OPT);
-    top_insert(top, x);
+  const uint64_t base = (uint64_t)(c - chunk_start[ri]) * kTopChunk;
+  const double *sp = speedup + (size_t)r * GPA_N_OPT;
+  for (uint32_t i = threadIdx.x; i < kTopChunk; i += kTopThreads) {
+    const uint64_t it = base + i;
+    Cand x = cand_none();
+    if (it < n_items) {
+      x.s = sp[it];
+      x.l = r + (uint32_t)(it / GPA_N_OPT);
+      x.o = (uint32_t)(it % GPA_N_OPT);
+    }
+    a[i] = x;
   }
-  block_merge(top, red, cand + (size_t)c * kTopK);
+  __syncthreads();
+  bitonic_best_first(a);
+  if (threadIdx.x < kTopK) cand[(size_t)c * kTopK + threadIdx.x] = a[threadIdx.x];
 }
 
 __global__ void __launch_bounds__(kTopThreads)
 k_topk_final(const uint32_t *roots, const uint32_t *nchunks, const uint32_t *chunk_start,
              const Cand *cand, uint32_t k, uint32_t *top_opt, uint32_t *top_scope,
              double *top_speed) {
-  __shared__ Cand red[kTopThreads];
-  __shared__ Cand best[kTopK];
+  __shared__ Cand a[kTopChunk];
   const uint32_t ri = blockIdx.x, r = roots[ri];
   const uint32_t n = nchunks[ri] * kTopK;
   const Cand *src = cand + (size_t)chunk_start[ri] * kTopK;
-  Cand top[kTopK];
-#pragma unroll
-  for (int i = 0; i < kTopK; ++i) top[i] = cand_none();
-  for (uint32_t it = threadIdx.x; it < n; it += kTopThreads)
-    if (src[it].o != 0xFFFFFFFFu) top_insert(top, src[it]);
-  block_merge(top, red, best);
-  __syncthreads();
+  // round 0 takes kTopChunk candidates, later rounds keep the best kTopK in
+  // front and take kTopChunk - kTopK new ones
+  uint32_t next = 0;
+  for (uint32_t round = 0; round == 0 || next < n; ++round) {
+    const uint32_t keep = round == 0 ? 0u : (uint32_t)kTopK;
+    for (uint32_t i = keep + threadIdx.x; i < kTopChunk; i += kTopThreads) {
+      const uint32_t it = next + (i - keep);
+      a[i] = it < n ? src[it] : cand_none();
+    }
+    next += kTopChunk - keep;
+    __syncthreads();
+    bitonic_best_first(a);
+  }
   for (uint32_t t = threadIdx.x; t < k; t += kTopThreads) {
-    const Cand c = best[t];
+    const Cand c = t < (uint32_t)kTopK ? a[t] : cand_none();
     top_opt[(size_t)r * k + t] = c.o;
     top_scope[(size_t)r * k + t] = c.l;
     top_speed[(size_t)r * k + t] = c.o == 0xFFFFFFFFu ? 0.0 : c.s;
@@ -320,8 +344,8 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint3
                      b.counts.p, b.blamed.p, b.self_.p, p.op_class.p, p.instr_tags.p, iv);
   hipLaunchKernelGGL(k_gather<kNV>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, (size_t)n,
                      p.line_perm.p, iv, iv_g);
-  hipLaunchKernelGGL(k_seg_sum<kNV>, dim3(ns), dim3(256), 0, s, ns, p.line_ptr.p, nullptr, iv_g,
-                     own, 0);
+  const uint32_t *big = p.big_list.p;
+  seg_sum<kNV>(ns, p.line_ptr.p, nullptr, big, p.big_n.p, iv_g, own, s);
   if (p.n_edges) {
     hipLaunchKernelGGL(k_edge_contrib, dim3(grid_for(p.n_edges, 256, 8192)), dim3(256), 0, s,
                        p.n_edges, nbl, s_mem, s_exec, p.e_src.p, p.op_class.p, b.share.p, ev);
@@ -331,14 +355,11 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint3
     hipLaunchKernelGGL(k_gather<1>, dim3(grid_for(p.n_edges, 256, 8192)), dim3(256), 0, s,
                        (size_t)p.n_edges, p.lca_perm.p, ev, ev_lca);
   }
-  hipLaunchKernelGGL(k_seg_sum<1>, dim3(ns), dim3(256), 0, s, ns, p.icl_ptr.p, nullptr, ev_icl,
-                     own_icl, 0);
-  hipLaunchKernelGGL(k_seg_sum<1>, dim3(ns), dim3(256), 0, s, ns, p.lca_ptr.p, nullptr, ev_lca,
-                     own_lca, 0);
+  seg_sum<1>(ns, p.icl_ptr.p, nullptr, big + ns, p.big_n.p + 1, ev_icl, own_icl, s);
+  seg_sum<1>(ns, p.lca_ptr.p, nullptr, big + 2 * (size_t)ns, p.big_n.p + 2, ev_lca, own_lca, s);
   hipLaunchKernelGGL(k_merge_edge_own, dim3(grid_for(ns, 256, 8192)), dim3(256), 0, s, ns, own_icl,
                      own_lca, own);
-  hipLaunchKernelGGL(k_seg_sum<kNV>, dim3(ns), dim3(256), 0, s, ns, nullptr, p.scope_end.p, own,
-                     sub, 0);
+  seg_sum<kNV>(ns, nullptr, p.scope_end.p, big + 3 * (size_t)ns, p.big_n.p + 3, own, sub, s);
   GPA_LAUNCH_CHECK();
   a.active.alloc(ns);
   a.matched.alloc((size_t)ns * GPA_N_OPT);

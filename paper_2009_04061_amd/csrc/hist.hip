@@ -30,7 +30,7 @@ constexpr int kBucketShift = 9;
 constexpr int kBucketPCs = 1 << kBucketShift;   // 512 PCs -> 12288 bins = 48 KiB of LDS
 constexpr int kBucketBins = kBucketPCs * 24;
 constexpr int kMaxBuckets = 8192;
-constexpr uint32_t kItemRecords = 1u << 16;     // records per counting work item
+constexpr uint32_t kItemRecords = 1u << 17;     // records per counting work item
 
 typedef unsigned long u64x2 __attribute__((ext_vector_type(2)));
 
@@ -123,11 +123,14 @@ k_partition(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint
             uint32_t n_tiles, const uint32_t *__restrict__ tile_pos, uint16_t *__restrict__ payload) {
   extern __shared__ uint32_t smem[];
   uint32_t *cnt = smem;                                   // [n_buckets + 1]
-  uint32_t *staged = smem + n_buckets + 1;                // [kTile]: bucket << 16 | payload
+  uint32_t *gpos = cnt + n_buckets + 1;                   // [n_buckets] where each run goes
+  uint32_t *staged = gpos + n_buckets;                    // [kTile]: bucket << 16 | payload
   __shared__ uint32_t scan_tmp[kHistThreads / kWave + 1];
   const unsigned tid = threadIdx.x;
   const uint64_t base = (uint64_t)blockIdx.x * kTile;
   for (uint32_t b = tid; b <= n_buckets; b += kHistThreads) cnt[b] = 0;
+  for (uint32_t b = tid; b < n_buckets; b += kHistThreads)
+    gpos[b] = tile_pos[(size_t)b * n_tiles + blockIdx.x];
   __syncthreads();
   uint32_t rank[kTile / kHistThreads];
 #pragma unroll
@@ -186,7 +189,7 @@ k_partition(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint
   for (uint32_t k = tid; k < nvalid; k += kHistThreads) {
     const uint32_t x = staged[k];
     const uint32_t b = x >> 16;
-    payload[tile_pos[(size_t)b * n_tiles + blockIdx.x] + (k - cnt[b])] = (uint16_t)x;
+    payload[gpos[b] + (k - cnt[b])] = (uint16_t)x;
   }
 }
 
@@ -343,7 +346,7 @@ void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint3
   hipLaunchKernelGGL(k_hist_totals, dim3(1), dim3(kHistThreads), 0, s, tt, n_tiles, totals);
   exclusive_scan_u32(tile_cnt, tile_pos, (size_t)n_buckets * n_tiles, s, ar);
   uint16_t *payload = ar.get<uint16_t>(n);
-  const size_t lds_part = ((size_t)n_buckets + 1) * 4 + (size_t)kTile * 4;
+  const size_t lds_part = (2 * (size_t)n_buckets + 1) * 4 + (size_t)kTile * 4;
   if (vec) {
     GPA_HIP(hipFuncSetAttribute((const void *)k_partition<true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_part));

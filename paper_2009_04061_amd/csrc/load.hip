@@ -2,9 +2,9 @@
 // later step reads (Sec. 3: CFGs, program structure, architecture table).
 //   - block -> function, instruction -> block, predecessor lists;
 //   - def and use sites sorted by (function, location, instruction): the
-//     per-location views the reaching-definitions tiles work on;
-//   - per (function, location) the guards met on its defs, and per use site
-//     the condition its search must cover (Sec. 4, predicated instructions);
+//     per-location views the backward searches work on;
+//   - per use site the condition its search must cover (Sec. 4, predicated
+//     instructions);
 //   - scope tree: kernel root, depth and preorder subtree end per scope.
 #include "common.h"
 #include "devutil.h"
@@ -116,21 +116,25 @@ __global__ void k_val_scopes(uint32_t n_scopes, const uint32_t *parent, const ui
   if (e) atomicOr(err, e);
 }
 
-// block structure: instruction ranges, block -> function, successors inside the function
-__global__ void k_blocks(uint32_t n_funcs, uint32_t n_instr, const uint32_t *fbb,
-                         const uint32_t *block_begin,
-                         uint32_t *block_of, uint32_t *func_of_block, uint32_t *err) {
-  for (uint32_t f = blockIdx.x; f < n_funcs; f += gridDim.x) {
-    for (uint32_t b = fbb[f] + threadIdx.x; b < fbb[f + 1]; b += blockDim.x) {
-      func_of_block[b] = f;
-      const uint32_t i0 = block_begin[b], i1 = block_begin[b + 1];
-      if (i0 >= i1 || i1 > n_instr) {
-        atomicOr(err, kErrBlocks);
-        continue;
-      }
-      for (uint32_t i = i0; i < i1; ++i) block_of[i] = b;
+// block structure: block -> function and instruction -> block by binary
+// search over the range starts (always in bounds; the blocks' own check
+// rejects a block_begin that is not strictly increasing)
+__global__ void k_blocks(uint32_t n_funcs, uint32_t n_blocks, uint32_t n_instr, const uint32_t *fbb,
+                         const uint32_t *block_begin, uint32_t *block_of, uint32_t *func_of_block,
+                         uint32_t *err) {
+  uint32_t e = 0;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n_blocks + n_instr;
+       k += gridDim.x * blockDim.x) {
+    if (k < n_blocks) {
+      func_of_block[k] = upper_index_u32(fbb, 0, n_funcs, k);
+      const uint32_t i0 = block_begin[k], i1 = block_begin[k + 1];
+      if (i0 >= i1 || i1 > n_instr) e |= kErrBlocks;
+    } else {
+      const uint32_t i = k - n_blocks;
+      block_of[i] = upper_index_u32(block_begin, 0, n_blocks, i);
     }
   }
+  if (e) atomicOr(err, e);
 }
 
 __global__ void k_val_succ(uint32_t n_blocks, const uint32_t *succ_ptr, const uint32_t *succ,
@@ -340,18 +344,6 @@ k_chunk_scatter(const SiteChunk *chunks, const uint32_t *key, uint32_t n_loc, ui
   }
 }
 
-// (function, location) -> bitmask of the guards on its defs (guard bytes <= 32)
-__global__ void k_def_guards(uint32_t n_defs, uint32_t n_loc, const uint32_t *def_instr,
-                             const uint32_t *def_loc, const uint32_t *block_of,
-                             const uint32_t *func_of_block, const uint8_t *guard,
-                             unsigned long long *mask) {
-  for (uint32_t d = blockIdx.x * blockDim.x + threadIdx.x; d < n_defs; d += gridDim.x * blockDim.x) {
-    const uint32_t i = def_instr[d];
-    const size_t q = (size_t)func_of_block[block_of[i]] * n_loc + def_loc[d];
-    atomicOr(&mask[q], 1ull << guard[i]);
-  }
-}
-
 // site -> instruction
 __global__ void k_site_instr(uint32_t n_instr, const uint32_t *site_ptr, uint32_t *site_instr) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_instr; i += gridDim.x * blockDim.x)
@@ -359,20 +351,11 @@ __global__ void k_site_instr(uint32_t n_instr, const uint32_t *site_ptr, uint32_
 }
 
 // A use's search must cover its condition: the instruction's guard for an
-// operand use, `_` for a guard read or a wait.  A guard that no def of the
-// location carries is covered exactly by the defs that cover `_`, so such
-// uses share the `_` problem.
-__global__ void k_use_cond(uint32_t n_uses, const uint32_t *use_instr, const uint32_t *use_loc,
-                           const uint8_t *use_kind, const uint8_t *guard, const uint32_t *block_of,
-                           const uint32_t *func_of_block, uint32_t n_loc, const uint64_t *dmask,
-                           uint8_t *cond) {
-  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n_uses; u += gridDim.x * blockDim.x) {
-    const uint32_t j = use_instr[u];
-    uint32_t c = use_kind[u] == GPA_USE_OPND ? guard[j] : 0u;
-    const uint32_t f = func_of_block[block_of[j]];
-    if (c && !((dmask[(size_t)f * n_loc + use_loc[u]] >> c) & 1ull)) c = 0;
-    cond[u] = (uint8_t)c;
-  }
+// operand use, `_` for a guard read or a wait.
+__global__ void k_use_cond(uint32_t n_uses, const uint32_t *use_instr, const uint8_t *use_kind,
+                           const uint8_t *guard, uint8_t *cond) {
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n_uses; u += gridDim.x * blockDim.x)
+    cond[u] = use_kind[u] == GPA_USE_OPND ? guard[use_instr[u]] : (uint8_t)0;
 }
 
 // ------------------------------------------------------------------ scopes
@@ -517,8 +500,9 @@ void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar) {
   // function and block maps (ranges are known to be sane from here on)
   p.block_of.alloc(n);
   p.func_of_block.alloc(nb);
-  hipLaunchKernelGGL(k_blocks, dim3(grid_for(nf, 1, 4096)), dim3(64), 0, s, nf, n,
-                     p.func_block_begin.p, p.block_begin.p, p.block_of.p, p.func_of_block.p, err);
+  hipLaunchKernelGGL(k_blocks, dim3(grid_for((size_t)nb + n, 256, 4096)), dim3(256), 0, s, nf, nb,
+                     n, p.func_block_begin.p, p.block_begin.p, p.block_of.p, p.func_of_block.p,
+                     err);
   GPA_LAUNCH_CHECK();
   e = read_scalar(err, s);
   if (e) raise_validation(e);
@@ -573,15 +557,9 @@ void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar) {
   hipLaunchKernelGGL(k_fl_close, dim3(grid_for(nf, 256, 1024)), dim3(256), 0, s, nf, p.n_loc,
                      p.func_block_begin.p, p.block_begin.p, p.use_ptr.p, p.fl_use_ptr.p);
   GPA_LAUNCH_CHECK();
-  p.fl_def_guards.alloc((size_t)nf * p.n_loc);
-  GPA_HIP(hipMemsetAsync(p.fl_def_guards.p, 0, 8 * (size_t)nf * p.n_loc, s));
-  hipLaunchKernelGGL(k_def_guards, dim3(grid_for(p.n_defs, 256, 8192)), dim3(256), 0, s, p.n_defs,
-                     p.n_loc, p.def_instr.p, p.def_loc.p, p.block_of.p, p.func_of_block.p,
-                     p.guard.p, (unsigned long long *)p.fl_def_guards.p);
   p.use_cond.alloc(p.n_uses);
   hipLaunchKernelGGL(k_use_cond, dim3(grid_for(p.n_uses, 256, 4096)), dim3(256), 0, s, p.n_uses,
-                     p.use_instr.p, p.use_loc.p, p.use_kind.p, p.guard.p, p.block_of.p,
-                     p.func_of_block.p, p.n_loc, p.fl_def_guards.p, p.use_cond.p);
+                     p.use_instr.p, p.use_kind.p, p.guard.p, p.use_cond.p);
   GPA_LAUNCH_CHECK();
   // scope tree
   p.root_of.alloc(ns);

@@ -80,6 +80,43 @@ def test_worked_examples_on_gpu():
     assert g["table"]["blamed"][2, S.ST_MEM_DEP, 1] == 5.0
 
 
+def _long_search_program(n=120):
+    """A loop of n blocks where every block branches to the next two: a use
+    at the latch reaches back over the whole loop to the defs before it, so
+    its backward search meets far more blocks than one thread keeps track of
+    (the workgroup search takes it).  R0 has one plain and one guarded def,
+    R2 a complementary pair, R10 a def after the loop only; one block in the
+    middle reads R0 unpredicated (dominator pruning cuts there)."""
+    lines = ["block 0 -> 1", "  MOV R0 <- R1", "  @P0 MOV R2 <- R1", "  @!P0 MOV R2 <- R3"]
+    for b in range(1, n):
+        succ = [b + 1] if b + 1 < n else [1, n]
+        if b + 2 < n:
+            succ.append(b + 2)
+        lines.append(f"block {b} -> " + " ".join(map(str, succ)))
+        if b == n // 2:
+            lines.append("  IADD R4 <- R0 R5")
+        elif b % 7 == 0:
+            lines.append("  @P1 MOV R0 <- R6")
+        else:
+            lines.append(f"  IADD R{7 + b % 3} <- R{11 + b % 3}")
+        if b == n - 1:
+            lines.append("  IADD R5 <- R0 R2")
+            lines.append("  @P1 IADD R6 <- R10 R0")
+        lines.append("  BRA")
+    lines += [f"block {n} ->", "  MOV R10 <- R0", f"loop 1 {n - 1}"]
+    return assemble("\n".join(lines) + "\n")
+
+
+def test_long_backward_searches():
+    prog = _long_search_program()
+    o = O.Program(prog)
+    # some use is reached by defs from all around the loop
+    assert max(len(o.sources(u)) for u in range(o.n_uses)) >= 10
+    n = len(prog["op_class"])
+    rec = S.gen_samples(20_000, n, 0.7, S.stall_mix_small(), seed=21)
+    _both(prog, rec)
+
+
 def test_deterministic_bitwise():
     prog, rec = S.workload_multi(seed=3, n_samples=60_000)
     a = run_gpu(prog, rec)
