@@ -286,12 +286,14 @@ gpa_status gpa_load_program(const gpa_program_desc *d, void *stream, gpa_program
     t_load.begin(kPhaseLoad, s);
     validate_and_build_structure(*p, s, ar);
     // the DFS order and the sweep streams need only the CFG: they run on the
-    // side stream while the reaching definitions and edges are built
+    // side stream while the sites are sorted and the reaching definitions
+    // and edges are built
     GPA_HIP(hipEventRecord(ev_struct.e, s));
     GPA_HIP(hipStreamWaitEvent(side, ev_struct.e, 0));
     SweepPlan plan;
     build_cfg_order(*p, side, ar, plan, t_dfs);
     GPA_HIP(hipEventRecord(ev_order.e, side));
+    build_sites_and_scopes(*p, s, ar);
     t_rd.begin(kPhaseRd, s);
     build_reaching_defs(*p, s, ar, t_search);
     build_edges(*p, s, ar);

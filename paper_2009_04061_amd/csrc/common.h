@@ -171,6 +171,7 @@ void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint3
 
 // load.hip
 void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar);
+void build_sites_and_scopes(gpa_program &p, hipStream_t s, Arena &ar);
 // dataflow.hip
 struct PhaseTimer;
 void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar, PhaseTimer &t_search);

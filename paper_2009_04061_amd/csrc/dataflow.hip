@@ -29,9 +29,13 @@
 namespace gpa {
 
 constexpr uint32_t kUnpred = 0x80000000u;
-constexpr int kSearchThreads = 256;
-constexpr uint32_t kSearchCap = 32;      // blocks one thread tracks per search
+constexpr int kSearchThreads = 256;      // (use, variant) searches per workgroup
+constexpr int kLongThreads = 256;
+constexpr uint32_t kSearchCap = 64;      // blocks one thread tracks per search
 constexpr uint32_t kLongGrid = 512;      // workgroups that take the long searches
+constexpr uint32_t kStagePred = 16 * 1024;   // LDS for a function's predecessor lists
+constexpr uint32_t kStageRows = 48 * 1024;   // LDS for (location, block) index rows
+constexpr uint32_t kKill = 0x80000000u;
 
 __device__ __forceinline__ bool covers(uint32_t g, uint32_t c) { return g == 0 || g == c; }
 __device__ __forceinline__ uint32_t complement(uint32_t g) { return (g & 1u) ? g + 1 : g - 1; }
@@ -194,14 +198,17 @@ __device__ __forceinline__ uint64_t range_word(uint32_t lo, uint32_t hi, uint32_
 }
 
 // ------------------------------------------------ (location, block) index
-// For location x and block b: the positions of x's defs and uses inside b in
-// the sorted def and use arrays (absolute positions, empty ranges where x
-// does not occur).  Row-major by location, so a search over one location
-// reads one row.
+// For location x and block b (row-major by location, so a search over one
+// location reads one row):
+//   t0 = (g plain | kill << 31, g blocked | kill << 31, def end, def begin)
+//        where the g are the block's survivors for condition `_` (the
+//        condition of most uses), so such a visit is a single load;
+//   t1 = (use begin, use end) for the other conditions, which rescan.
+// Positions are absolute in the sorted def and use arrays.
 __global__ void k_loc_block_index(uint32_t n_blocks, uint32_t n_loc, const uint32_t *func_of_block,
                                   const uint32_t *block_begin, const uint32_t *fl_def_ptr,
                                   const uint32_t *fl_use_ptr, const uint32_t *dsi,
-                                  const uint32_t *usi, uint4 *tab) {
+                                  const uint8_t *dsg, const uint32_t *usi, uint4 *t0, uint2 *t1) {
   const size_t total = (size_t)n_loc * n_blocks;
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < total;
        k += (size_t)gridDim.x * blockDim.x) {
@@ -210,13 +217,29 @@ __global__ void k_loc_block_index(uint32_t n_blocks, uint32_t n_loc, const uint3
     const uint32_t d0 = fl_def_ptr[fi], d1 = fl_def_ptr[fi + 1];
     const uint32_t u0 = fl_use_ptr[fi], u1 = fl_use_ptr[fi + 1];
     const uint32_t i0 = block_begin[b], i1 = block_begin[b + 1];
-    uint4 r;
-    r.x = lower_pos(dsi, d0, d1, i0);
-    r.y = lower_pos(dsi, r.x, d1, i1);
-    r.z = lower_pos(usi, u0, u1, i0);
-    r.w = lower_pos(usi, r.z, u1, i1);
-    tab[k] = r;
+    const uint32_t dlo = lower_pos(dsi, d0, d1, i0), dhi = lower_pos(dsi, dlo, d1, i1);
+    const uint32_t ulo = lower_pos(usi, u0, u1, i0), uhi = lower_pos(usi, ulo, u1, i1);
+    const Survive f = survivors_range(dsi, dsg, usi, dlo, dhi, ulo, uhi, 0, false);
+    const Survive g = survivors_range(dsi, dsg, usi, dlo, dhi, ulo, uhi, 0, true);
+    t0[k] = make_uint4(f.g | (f.kill ? kKill : 0u), g.g | (g.kill ? kKill : 0u), dhi, dlo);
+    t1[k] = make_uint2(ulo, uhi);
   }
+}
+
+// survivors of a whole block for a use of condition c, from the index
+__device__ __forceinline__ Survive block_step(const uint4 &r, const uint2 *t1, size_t k,
+                                              const uint32_t *dsi, const uint8_t *dsg,
+                                              const uint32_t *usi, uint32_t c, bool blocked) {
+  if (c == 0) {
+    const uint32_t v = blocked ? r.y : r.x;
+    Survive s;
+    s.g = v & ~kKill;
+    s.hi = r.z;
+    s.kill = (v & kKill) != 0;
+    return s;
+  }
+  const uint2 u = t1[k];
+  return survivors_range(dsi, dsg, usi, r.w, r.z, u.x, u.y, c, blocked);
 }
 
 // OR the def positions [g, hi) (absolute; the bitset starts at d0) into the
@@ -228,86 +251,121 @@ __device__ __forceinline__ void or_range(uint64_t *in, uint32_t d0, uint32_t g, 
 }
 
 // ------------------------------------------------------- the searches
-// One thread per use site (sorted order, so a wave's uses share a location):
-// for each variant, a breadth-first search backwards from the use's block
-// over whole predecessor blocks.  The blocks met are kept in a per-thread
-// list in LDS (also the queue), with a 64-bit filter in a register to skip
-// most list scans; a search that would meet more than kSearchCap blocks is
-// left to k_rd_search_long.
+// One thread per (use site, variant): threads [0, n) take the plain search
+// of the sorted use sites, threads [n, 2n) the use-blocked one, so a wave's
+// uses share a location.  A breadth-first search backwards from the use's
+// block over whole predecessor blocks; the blocks met are kept in a
+// per-thread list in LDS (also the queue), with a 128-bit filter in
+// registers to skip most list scans.  IN bitsets of up to kRegWords words
+// are accumulated in registers and written once; longer ones are OR-ed in
+// place.  A search that would meet more than kSearchCap blocks is left to
+// k_rd_search_long.
+constexpr uint32_t kRegWords = 8;
+
 __global__ void __launch_bounds__(kSearchThreads)
 k_rd_search(uint32_t n_uses, uint32_t n_blocks, uint32_t n_loc, const uint32_t *use_site_sorted,
             const uint32_t *use_instr, const uint32_t *use_loc, const uint8_t *use_cond,
             const uint32_t *block_of, const uint32_t *func_of_block, const uint32_t *fbb,
             const uint32_t *pred_ptr, const uint32_t *pred, const uint32_t *fl_def_ptr,
-            const uint32_t *dsi, const uint8_t *dsg, const uint32_t *usi, const uint4 *tab,
-            const uint32_t *slot_start, uint64_t *rd_in, uint32_t *long_list, uint32_t *n_long) {
-  __shared__ uint16_t seen[kSearchCap][kSearchThreads];
+            const uint32_t *dsi, const uint8_t *dsg, const uint32_t *usi, const uint4 *t0,
+            const uint2 *t1, const uint32_t *slot_start, uint64_t *rd_in, uint32_t *long_list,
+            uint32_t *n_long) {
+  __shared__ uint16_t seen[kSearchCap * kSearchThreads];
   const unsigned tid = threadIdx.x;
-  for (uint32_t k = blockIdx.x * blockDim.x + tid; k < n_uses; k += gridDim.x * blockDim.x) {
-    const uint32_t u = use_site_sorted[k];
-    const uint32_t j = use_instr[u], x = use_loc[u];
-    const uint32_t b = block_of[j], f = func_of_block[b], b0 = fbb[f];
-    const size_t fi = (size_t)f * (n_loc + 1) + x;
-    const uint32_t d0 = fl_def_ptr[fi];
-    if (fl_def_ptr[fi + 1] == d0) continue;
-    const uint32_t c = use_cond[u];
-    const uint4 *row = tab + (size_t)x * n_blocks;
-    uint64_t *in = rd_in + slot_start[k];
-    bool ok = true;
-    for (int var = 0; var < 2 && ok; ++var) {
-      const bool blocked = var == 1;
-      uint32_t n_seen = 0, head = 0;
-      uint64_t filter = 0;
-      auto visit = [&](uint32_t p) {
-        const uint32_t pl = p - b0;
-        const uint64_t bit = 1ull << ((pl * 0x9E3779B1u) >> 26);
-        if (filter & bit) {
-          for (uint32_t t = 0; t < n_seen; ++t)
-            if (seen[t][tid] == pl) return;
-        }
-        if (n_seen == kSearchCap) {
-          ok = false;
-          return;
-        }
-        filter |= bit;
-        seen[n_seen++][tid] = (uint16_t)pl;
-      };
-      for (uint32_t q = pred_ptr[b]; q < pred_ptr[b + 1] && ok; ++q) visit(pred[q]);
-      while (ok && head < n_seen) {
-        const uint32_t p = seen[head++][tid] + b0;
-        const uint4 r = row[p];
-        const Survive s = survivors_range(dsi, dsg, usi, r.x, r.y, r.z, r.w, c, blocked);
-        or_range(in + var, d0, s.g, r.y);
-        if (!s.kill)
-          for (uint32_t q = pred_ptr[p]; q < pred_ptr[p + 1] && ok; ++q) visit(pred[q]);
+  const uint32_t t = blockIdx.x * kSearchThreads + tid;
+  if (t >= 2 * n_uses) return;
+  const uint32_t var = t >= n_uses ? 1u : 0u;
+  const uint32_t k = t - var * n_uses;
+  const bool blocked = var == 1;
+  const uint32_t u = use_site_sorted[k];
+  const uint32_t j = use_instr[u], x = use_loc[u];
+  const uint32_t b = block_of[j], f = func_of_block[b], b0 = fbb[f];
+  const size_t fi = (size_t)f * (n_loc + 1) + x;
+  const uint32_t d0 = fl_def_ptr[fi];
+  const uint32_t nd = fl_def_ptr[fi + 1] - d0;
+  if (nd == 0) return;
+  const uint32_t nw = (nd + 63) / 64;
+  const uint32_t c = use_cond[u];
+  const size_t row = (size_t)x * n_blocks + b0;
+  uint64_t *in = rd_in + slot_start[k] + var;
+  uint64_t acc[kRegWords];
+#pragma unroll
+  for (uint32_t w = 0; w < kRegWords; ++w) acc[w] = 0ull;
+  uint32_t n_seen = 0, head = 0;
+  uint64_t fl0 = 0, fl1 = 0;
+  bool ok = true;
+  auto visit = [&](uint32_t pl) {
+    const uint32_t h = (pl * 0x9E3779B1u) >> 25;
+    const uint64_t bit = 1ull << (h & 63);
+    const uint64_t fl = (h & 64) ? fl1 : fl0;
+    if (fl & bit) {
+      for (uint32_t q = 0; q < n_seen; ++q)
+        if (seen[q * kSearchThreads + tid] == pl) return;
+    }
+    if (n_seen == kSearchCap) {
+      ok = false;
+      return;
+    }
+    if (h & 64) fl1 |= bit;
+    else fl0 |= bit;
+    seen[(n_seen++) * kSearchThreads + tid] = (uint16_t)pl;
+  };
+  for (uint32_t q = pred_ptr[b]; q < pred_ptr[b + 1] && ok; ++q) visit(pred[q] - b0);
+  while (ok && head < n_seen) {
+    const uint32_t pl = seen[(head++) * kSearchThreads + tid];
+    const uint4 r = t0[row + pl];
+    const uint32_t qa = pred_ptr[b0 + pl], qb = pred_ptr[b0 + pl + 1];
+    const Survive sv = block_step(r, t1, row + pl, dsi, dsg, usi, c, blocked);
+    if (sv.g < r.z) {
+      const uint32_t lo = sv.g - d0, hi = r.z - d0;
+      if (nw <= kRegWords) {
+#pragma unroll
+        for (uint32_t w = 0; w < kRegWords; ++w) acc[w] |= range_word(lo, hi, 64 * w);
+      } else {
+        for (uint32_t w = lo / 64; w * 64 < hi; ++w) in[2 * w] |= range_word(lo, hi, 64 * w);
       }
     }
-    if (!ok) long_list[atomicAdd(n_long, 1u)] = k;
+    if (!sv.kill)
+      for (uint32_t q = qa; q < qb && ok; ++q) visit(pred[q] - b0);
+  }
+  if (!ok) {
+    long_list[atomicAdd(n_long, 1u)] = k | (var << 31);
+    return;
+  }
+  if (nw <= kRegWords) {
+#pragma unroll
+    for (uint32_t w = 0; w < kRegWords; ++w)
+      if (w < nw) in[2 * w] = acc[w];
   }
 }
 
 // The searches one thread could not hold: one workgroup per use, level by
-// level, with the blocks met and the IN bits in LDS.
-__global__ void __launch_bounds__(kSearchThreads)
+// level, with the blocks met and the IN bits in LDS (and the function's
+// predecessor lists and the use's index row staged there when they fit).
+__global__ void __launch_bounds__(kLongThreads)
 k_rd_search_long(uint32_t n_blocks, uint32_t n_loc, uint32_t max_nb, uint32_t max_words,
                  const uint32_t *use_site_sorted, const uint32_t *use_instr,
                  const uint32_t *use_loc, const uint8_t *use_cond, const uint32_t *block_of,
                  const uint32_t *func_of_block, const uint32_t *fbb, const uint32_t *pred_ptr,
                  const uint32_t *pred, const uint32_t *fl_def_ptr, const uint32_t *dsi,
-                 const uint8_t *dsg, const uint32_t *usi, const uint4 *tab,
+                 const uint8_t *dsg, const uint32_t *usi, const uint4 *t0, const uint2 *t1,
                  const uint32_t *slot_start, uint64_t *rd_in, const uint32_t *long_list,
                  const uint32_t *n_long) {
-  extern __shared__ uint64_t lds[];
+  extern __shared__ uint4 lds_l[];
   const uint32_t vis_words = (max_nb + 31) / 32;
-  uint64_t *bits = lds;                                  // [max_words]
-  uint32_t *vis = (uint32_t *)(bits + max_words);        // [vis_words]
-  uint16_t *q0 = (uint16_t *)(vis + vis_words);          // [max_nb]
-  uint16_t *q1 = q0 + max_nb;                            // [max_nb]
+  uint4 *s_row = lds_l;                                          // kStageRows bytes
+  uint64_t *bits = (uint64_t *)(s_row + kStageRows / 16);        // [max_words]
+  uint32_t *s_ptr = (uint32_t *)(bits + max_words);               // kStagePred bytes
+  uint16_t *s_predl = nullptr;
+  uint32_t *vis = (uint32_t *)((char *)s_ptr + kStagePred);       // [vis_words]
+  uint16_t *q0 = (uint16_t *)(vis + vis_words);                   // [max_nb]
+  uint16_t *q1 = q0 + max_nb;                                     // [max_nb]
   __shared__ uint32_t n_cur, n_next;
   const unsigned tid = threadIdx.x;
   const uint32_t nl = *n_long;
   for (uint32_t i = blockIdx.x; i < nl; i += gridDim.x) {
-    const uint32_t k = long_list[i];
+    const uint32_t k = long_list[i] & 0x7FFFFFFFu;
+    const int var = (int)(long_list[i] >> 31);
     const uint32_t u = use_site_sorted[k];
     const uint32_t j = use_instr[u], x = use_loc[u];
     const uint32_t b = block_of[j], f = func_of_block[b], b0 = fbb[f];
@@ -316,20 +374,35 @@ k_rd_search_long(uint32_t n_blocks, uint32_t n_loc, uint32_t max_nb, uint32_t ma
     const uint32_t d0 = fl_def_ptr[fi], nd = fl_def_ptr[fi + 1] - d0;
     const uint32_t nw = (nd + 63) / 64;
     const uint32_t c = use_cond[u];
-    const uint4 *row = tab + (size_t)x * n_blocks;
+    const size_t row = (size_t)x * n_blocks;
     uint64_t *in = rd_in + slot_start[k];
-    for (int var = 0; var < 2; ++var) {
+    const uint32_t p0 = pred_ptr[b0], np = pred_ptr[b0 + nb] - p0;
+    const bool sp = (nb + 1) * 4u + np * 2u <= kStagePred;
+    const bool sr = nb * 16u <= kStageRows;
+    __syncthreads();
+    s_predl = (uint16_t *)(s_ptr + nb + 1);
+    if (sp) {
+      for (uint32_t q = tid; q <= nb; q += kLongThreads) s_ptr[q] = pred_ptr[b0 + q] - p0;
+      for (uint32_t q = tid; q < np; q += kLongThreads) s_predl[q] = (uint16_t)(pred[p0 + q] - b0);
+    }
+    if (sr)
+      for (uint32_t q = tid; q < nb; q += kLongThreads) s_row[q] = t0[row + b0 + q];
+    {
       const bool blocked = var == 1;
       __syncthreads();
-      for (uint32_t w = tid; w < nw; w += kSearchThreads) bits[w] = 0ull;
-      for (uint32_t w = tid; w < (nb + 31) / 32; w += kSearchThreads) vis[w] = 0u;
+      for (uint32_t w = tid; w < nw; w += kLongThreads) bits[w] = 0ull;
+      for (uint32_t w = tid; w < (nb + 31) / 32; w += kLongThreads) vis[w] = 0u;
       if (tid == 0) n_cur = 0;
       __syncthreads();
-      for (uint32_t q = pred_ptr[b] + tid; q < pred_ptr[b + 1]; q += kSearchThreads) {
-        const uint32_t pl = pred[q] - b0;
+      auto claim = [&](uint32_t pl, uint16_t *queue, uint32_t *count) {
         if (!(atomicOr(&vis[pl / 32], 1u << (pl % 32)) & (1u << (pl % 32))))
-          q0[atomicAdd(&n_cur, 1u)] = (uint16_t)pl;
-      }
+          queue[atomicAdd(count, 1u)] = (uint16_t)pl;
+      };
+      const uint32_t bl = b - b0;
+      const uint32_t qa = sp ? s_ptr[bl] : pred_ptr[b] - p0;
+      const uint32_t qb = sp ? s_ptr[bl + 1] : pred_ptr[b + 1] - p0;
+      for (uint32_t q = qa + tid; q < qb; q += kLongThreads)
+        claim(sp ? s_predl[q] : pred[p0 + q] - b0, q0, &n_cur);
       __syncthreads();
       uint16_t *cur = q0, *nxt = q1;
       for (;;) {
@@ -338,21 +411,20 @@ k_rd_search_long(uint32_t n_blocks, uint32_t n_loc, uint32_t max_nb, uint32_t ma
         __syncthreads();
         if (tid == 0) n_next = 0;
         __syncthreads();
-        for (uint32_t t = tid; t < nc; t += kSearchThreads) {
-          const uint32_t p = cur[t] + b0;
-          const uint4 r = row[p];
-          const Survive s = survivors_range(dsi, dsg, usi, r.x, r.y, r.z, r.w, c, blocked);
-          if (s.g < r.y) {
-            const uint32_t a = s.g - d0, e = r.y - d0;
+        for (uint32_t t = tid; t < nc; t += kLongThreads) {
+          const uint32_t pl = cur[t];
+          const uint4 r = sr ? s_row[pl] : t0[row + b0 + pl];
+          const Survive s = block_step(r, t1, row + b0 + pl, dsi, dsg, usi, c, blocked);
+          if (s.g < r.z) {
+            const uint32_t a = s.g - d0, e = r.z - d0;
             for (uint32_t w = a / 64; w * 64 < e; ++w)
               atomicOr((unsigned long long *)&bits[w], (unsigned long long)range_word(a, e, w * 64));
           }
-          if (!s.kill)
-            for (uint32_t q = pred_ptr[p]; q < pred_ptr[p + 1]; ++q) {
-              const uint32_t pl = pred[q] - b0;
-              if (!(atomicOr(&vis[pl / 32], 1u << (pl % 32)) & (1u << (pl % 32))))
-                nxt[atomicAdd(&n_next, 1u)] = (uint16_t)pl;
-            }
+          if (!s.kill) {
+            const uint32_t ra = sp ? s_ptr[pl] : pred_ptr[b0 + pl] - p0;
+            const uint32_t rb = sp ? s_ptr[pl + 1] : pred_ptr[b0 + pl + 1] - p0;
+            for (uint32_t q = ra; q < rb; ++q) claim(sp ? s_predl[q] : pred[p0 + q] - b0, nxt, &n_next);
+          }
         }
         __syncthreads();
         if (tid == 0) n_cur = n_next;
@@ -361,7 +433,7 @@ k_rd_search_long(uint32_t n_blocks, uint32_t n_loc, uint32_t max_nb, uint32_t ma
         nxt = tmp;
         __syncthreads();
       }
-      for (uint32_t w = tid; w < nw; w += kSearchThreads) in[2 * w + var] = bits[w];
+      for (uint32_t w = tid; w < nw; w += kLongThreads) in[2 * w + var] = bits[w];
     }
   }
 }
@@ -503,32 +575,33 @@ void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar, PhaseTimer &t
   const uint32_t max_words = read_scalar(scal, s);
   uint64_t *rd_in = ar.get<uint64_t>(nslot ? nslot : 1);
   if (nslot) {
-    const size_t lds_long = 8u * (size_t)max_words + 4u * ((p.max_func_blocks + 31) / 32) +
-                            4u * (size_t)p.max_func_blocks + 16u;
+    const size_t lds_long = kStageRows + 8u * (size_t)max_words + kStagePred +
+                            4u * ((p.max_func_blocks + 31) / 32) + 4u * (size_t)p.max_func_blocks;
     if (lds_long > 160 * 1024)
-      fail(GPA_E_UNSUPPORTED, "a location has %u defs in one function (at most %u supported)",
-           64u * max_words, 64u * (uint32_t)((120u * 1024u) / 8u));
+      fail(GPA_E_UNSUPPORTED, "a location has %u defs in one function (too many for one search)",
+           64u * max_words);
     GPA_HIP(hipMemsetAsync(rd_in, 0, 8 * nslot, s));
-    uint4 *tab = ar.get<uint4>((size_t)nl * nb);
+    uint4 *t0 = ar.get<uint4>((size_t)nl * nb);
+    uint2 *t1 = ar.get<uint2>((size_t)nl * nb);
     hipLaunchKernelGGL(k_loc_block_index, dim3(grid_for((size_t)nl * nb, 256, 8192)), dim3(256),
                        0, s, nb, nl, p.func_of_block.p, p.block_begin.p, p.fl_def_ptr.p,
-                       p.fl_use_ptr.p, dsi, usi, tab);
+                       p.fl_use_ptr.p, dsi, dsg, usi, t0, t1);
     GPA_LAUNCH_CHECK();
     uint32_t *long_list = ar.get<uint32_t>(p.n_uses);
     t_search.begin(kPhaseRdSearch, s);
-    hipLaunchKernelGGL(k_rd_search, dim3(grid_for(p.n_uses, kSearchThreads, 8192)),
+    hipLaunchKernelGGL(k_rd_search, dim3((2 * p.n_uses + kSearchThreads - 1) / kSearchThreads),
                        dim3(kSearchThreads), 0, s, p.n_uses, nb, nl, p.use_site_sorted.p,
                        p.use_instr.p, p.use_loc.p, p.use_cond.p, p.block_of.p, p.func_of_block.p,
                        p.func_block_begin.p, p.pred_ptr.p, p.pred.p, p.fl_def_ptr.p, dsi, dsg, usi,
-                       tab, slot_start, rd_in, long_list, scal + 1);
+                       t0, t1, slot_start, rd_in, long_list, scal + 1);
     GPA_LAUNCH_CHECK();
     GPA_HIP(hipFuncSetAttribute((const void *)k_rd_search_long,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_long));
-    hipLaunchKernelGGL(k_rd_search_long, dim3(kLongGrid), dim3(kSearchThreads), lds_long, s, nb,
+    hipLaunchKernelGGL(k_rd_search_long, dim3(kLongGrid), dim3(kLongThreads), lds_long, s, nb,
                        nl, p.max_func_blocks, max_words, p.use_site_sorted.p, p.use_instr.p,
                        p.use_loc.p, p.use_cond.p, p.block_of.p, p.func_of_block.p,
                        p.func_block_begin.p, p.pred_ptr.p, p.pred.p, p.fl_def_ptr.p, dsi, dsg, usi,
-                       tab, slot_start, rd_in, long_list, scal + 1);
+                       t0, t1, slot_start, rd_in, long_list, scal + 1);
     GPA_LAUNCH_CHECK();
     t_search.end(s);
   }

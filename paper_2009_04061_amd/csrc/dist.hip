@@ -220,64 +220,107 @@ __device__ void dist_sweep(uint32_t *D, uint32_t L, uint32_t li, bool writer, ui
     re[r] = kInf;
   }
   uint32_t best = kInf;
+  // the next batch of entries is loaded while the current one is swept
+  uint32_t idx = e_begin + lane;
+  uint32_t vp = idx < e_end ? ent[idx] : kLocalNone;
+  uint32_t vw = idx < e_end ? ent_w[idx] : 0u;
   for (uint32_t base = e_begin; base < e_end; base += 64) {
-    const uint32_t idx = base + lane;
-    const uint32_t vp = idx < e_end ? ent[idx] : kLocalNone;
-    const uint32_t vw = idx < e_end ? ent_w[idx] : 0u;
+    const uint32_t nidx = base + 64 + lane;
+    const uint32_t vp_next = nidx < e_end ? ent[nidx] : kLocalNone;
+    const uint32_t vw_next = nidx < e_end ? ent_w[nidx] : 0u;
     uint32_t pre[kPD];
 #pragma unroll
     for (int i = 0; i < kPD; ++i) {
       const uint32_t v = __builtin_amdgcn_readlane(vp, i) & kLocalNone;
       pre[i] = D[(v == kLocalNone ? 0u : v) * L + li];
     }
+    // 16 entries per unrolled body keeps the code small; ring slots stay
+    // compile-time indices because 16 is a multiple of kPD
+    for (int i0 = 0; i0 < 64; i0 += 16) {
 #pragma unroll
-    for (int i = 0; i < 64; ++i) {
-      const uint32_t pk = __builtin_amdgcn_readlane(vp, i);
-      const uint32_t v = pk & kLocalNone;
-      uint32_t c = pre[i % kPD];
-      if (i + kPD < 64) {
-        const uint32_t vn = __builtin_amdgcn_readlane(vp, i + kPD) & kLocalNone;
-        pre[i % kPD] = D[(vn == kLocalNone ? 0u : vn) * L + li];
-      }
-      if (pk & kEntFirst) best = kInf;
-      if (v != kLocalNone && !(kLongest && (pk & kEntRet))) {
-#pragma unroll
-        for (int r = 0; r < kPD; ++r)
-          if (v == rw[r]) c = re[r];
-        if (v == s) c = 0;
-        // kInf reads as -1 for longest walks: no walk
-        best = kLongest ? (uint32_t)max((int32_t)best, (int32_t)c) : min(best, c);
-      }
-      if (pk & kEntLast) {
-        const uint32_t w = (pk >> 13) & kLocalNone;
-        const uint32_t bw = __builtin_amdgcn_readlane(vw, i);
-        const uint32_t e = (best == kInf) ? kInf : best + bw;
-        if (writer) D[w * L + li] = e;
-#pragma unroll
-        for (int r = kPD - 1; r > 0; --r) {
-          rw[r] = rw[r - 1];
-          re[r] = re[r - 1];
+      for (int j = 0; j < 16; ++j) {
+        const int i = i0 + j;
+        const uint32_t pk = __builtin_amdgcn_readlane(vp, i);
+        const uint32_t v = pk & kLocalNone;
+        uint32_t c = pre[j % kPD];
+        if (i + kPD < 64) {
+          const uint32_t vn = __builtin_amdgcn_readlane(vp, i + kPD) & kLocalNone;
+          pre[j % kPD] = D[(vn == kLocalNone ? 0u : vn) * L + li];
         }
-        rw[0] = w;
-        re[0] = e;
+        if (pk & kEntFirst) best = kInf;
+        if (v != kLocalNone && !(kLongest && (pk & kEntRet))) {
+#pragma unroll
+          for (int r = 0; r < kPD; ++r)
+            if (v == rw[r]) c = re[r];
+          if (v == s) c = 0;
+          // kInf reads as -1 for longest walks: no walk
+          best = kLongest ? (uint32_t)max((int32_t)best, (int32_t)c) : min(best, c);
+        }
+        if (pk & kEntLast) {
+          const uint32_t w = (pk >> 13) & kLocalNone;
+          const uint32_t bw = __builtin_amdgcn_readlane(vw, i);
+          const uint32_t e = (best == kInf) ? kInf : best + bw;
+          if (writer) D[w * L + li] = e;
+#pragma unroll
+          for (int r = kPD - 1; r > 0; --r) {
+            rw[r] = rw[r - 1];
+            re[r] = re[r - 1];
+          }
+          rw[0] = w;
+          re[0] = e;
+        }
       }
     }
+    vp = vp_next;
+    vw = vw_next;
   }
+}
+
+// Per edge, in source order (the order k_dist walks them), everything its
+// distances need besides the table values:
+//   q = (edge, target block (local) | same-block flag << 31, addend, source block)
+// where dmin = addend for a same-block pair with the source first, else
+// table value of the target + addend, with addend = (|B_i| - o_i - 1) + o_j - |B_j|;
+// ql = the latency bound of the source's opcode class.
+__global__ void k_dist_queries(uint64_t n_edges, const uint32_t *out_perm, const uint32_t *e_src,
+                               const uint32_t *e_dst, const uint32_t *block_of,
+                               const uint32_t *func_of_block, const uint32_t *fbb,
+                               const uint32_t *block_begin, const uint8_t *op_class,
+                               const uint16_t *lat_tab, uint4 *q, uint32_t *ql) {
+  for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n_edges;
+       k += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t e = out_perm[k];
+    const uint32_t src = e_src[e], j = e_dst[e];
+    const uint32_t sb = block_of[src], tb = block_of[j];
+    const uint32_t b0 = fbb[func_of_block[sb]];
+    const uint32_t i0 = block_begin[sb], ss = block_begin[sb + 1] - i0;
+    const uint32_t tj0 = block_begin[tb], bt = block_begin[tb + 1] - tj0;
+    const uint32_t oi = src - i0, oj = j - tj0;
+    const bool same = tb == sb && oi < oj;
+    const uint32_t add = same ? oj - oi - 1 : (ss - oi - 1) + oj - bt;   // mod 2^32
+    q[k] = make_uint4(e, (tb - b0) | (same ? 0x80000000u : 0u), add, sb);
+    ql[k] = lat_tab[op_class[src]];
+  }
+}
+
+// the latency rule's bit, set by k_dist beside the other flags
+__global__ void k_merge_lat(uint64_t n_edges, const uint8_t *e_lat, uint8_t *e_flags) {
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < n_edges;
+       e += (uint64_t)gridDim.x * blockDim.x)
+    if (e_lat[e]) e_flags[e] |= GPA_E_LAT_KEEP;
 }
 
 // Distances of every edge out of a group of L consecutive source blocks, one
 // lane per source.  Shortest walks repeat the sweep until no retreating edge
 // can shorten a walk (the sweep order settles every other edge); longest G'
-// walks take one sweep.  The workgroup is one wave.
+// walks take one sweep into a second table.  The workgroup is one wave.
 __global__ void __launch_bounds__(64)
 k_dist(uint32_t n_blocks, uint32_t n_funcs, uint32_t L, const uint32_t *fbb,
-       const uint32_t *func_of_block, const uint32_t *block_begin, const uint32_t *block_of,
-       const uint32_t *ent_ptr, const uint32_t *ent, const uint32_t *ent_w,
-       const uint32_t *ret_ptr, const uint32_t *rent, const uint32_t *rent_w,
-       const uint32_t *out_ptr, const uint32_t *out_perm, const uint32_t *e_src,
-       const uint32_t *e_dst, const uint8_t *op_class, const uint16_t *lat_tab,
-       uint32_t *e_dmin, uint32_t *e_dmax, uint8_t *e_flags) {
-  extern __shared__ uint32_t D[];   // [blocks of the function][L]
+       const uint32_t *func_of_block, const uint32_t *block_begin, const uint32_t *ent_ptr,
+       const uint32_t *ent, const uint32_t *ent_w, const uint32_t *ret_ptr, const uint32_t *rent,
+       const uint32_t *rent_w, const uint32_t *out_ptr, const uint4 *q, const uint32_t *ql,
+       uint32_t *e_dmin, uint32_t *e_dmax, uint8_t *e_lat) {
+  extern __shared__ uint32_t D[];   // [2][blocks of the function][L]
   const unsigned lane = threadIdx.x;
   const uint32_t c0 = blockIdx.x * L, c1 = min(c0 + L, n_blocks);
   if (c0 >= n_blocks) return;
@@ -288,6 +331,7 @@ k_dist(uint32_t n_blocks, uint32_t n_funcs, uint32_t L, const uint32_t *fbb,
     if (g0 >= g1) continue;
     const uint32_t ea = out_ptr[block_begin[g0]], eb = out_ptr[block_begin[g1]];
     if (ea == eb) continue;
+    uint32_t *Dsp = D, *Dlp = D + (size_t)nb * L;
     const uint32_t sb = c0 + lane;
     const bool writer = lane < L;
     const bool mine = writer && sb >= g0 && sb < g1 &&
@@ -297,10 +341,10 @@ k_dist(uint32_t n_blocks, uint32_t n_funcs, uint32_t L, const uint32_t *fbb,
     const uint32_t r_begin = ret_ptr[b0], r_end = ret_ptr[b1];
     // shortest walks
     __syncthreads();
-    for (uint32_t k = lane; k < nb * L; k += 64) D[k] = kInf;
+    for (uint32_t k = lane; k < nb * L; k += 64) Dsp[k] = kInf;
     __syncthreads();
     for (uint32_t sweep = 0; sweep <= nb; ++sweep) {
-      dist_sweep<false>(D, L, li, writer, s, ent, ent_w, e_begin, e_end);
+      dist_sweep<false>(Dsp, L, li, writer, s, ent, ent_w, e_begin, e_end);
       bool changed = false;
       for (uint32_t base = r_begin; base < r_end; base += 64) {
         const uint32_t idx = base + lane;
@@ -310,52 +354,33 @@ k_dist(uint32_t n_blocks, uint32_t n_funcs, uint32_t L, const uint32_t *fbb,
         for (uint32_t i = 0; i < cnt; ++i) {
           const uint32_t pk = __builtin_amdgcn_readlane(rp, i);
           const uint32_t u = pk & kLocalNone, h = (pk >> 13) & kLocalNone;
-          const uint32_t cu = (u == s) ? 0u : D[u * L + li];
+          const uint32_t cu = (u == s) ? 0u : Dsp[u * L + li];
           const uint32_t bh = __builtin_amdgcn_readlane(rw, i);
-          if (mine && cu != kInf && cu + bh < D[h * L + li]) changed = true;
+          if (mine && cu != kInf && cu + bh < Dsp[h * L + li]) changed = true;
         }
       }
       if (__ballot(changed) == 0) break;
     }
-    __syncthreads();
-    for (uint32_t k = ea + lane; k < eb; k += 64) {
-      const uint32_t e = out_perm[k];
-      const uint32_t src = e_src[e], j = e_dst[e];
-      const uint32_t sbk = block_of[src], tb = block_of[j];
-      const uint32_t sl = sbk - c0, t = tb - b0;
-      const uint32_t i0 = block_begin[sbk], ss = block_begin[sbk + 1] - i0;
-      const uint32_t tj0 = block_begin[tb], bt = block_begin[tb + 1] - tj0;
-      const uint32_t oi = src - i0, oj = j - tj0;
-      uint32_t dmin;
-      if (tb == sbk && oi < oj) {
-        dmin = oj - oi - 1;
-      } else {
-        const uint32_t Et = D[t * L + sl];
-        dmin = (Et == kInf) ? kInf : (ss - oi - 1) + (Et - bt) + oj;
-      }
-      e_dmin[e] = dmin;
-      if (dmin <= lat_tab[op_class[src]]) e_flags[e] |= GPA_E_LAT_KEEP;
-    }
     // longest G' walks; every block is written before any later block reads it
-    __syncthreads();
-    dist_sweep<true>(D, L, li, writer, s, ent, ent_w, e_begin, e_end);
+    dist_sweep<true>(Dlp, L, li, writer, s, ent, ent_w, e_begin, e_end);
     __syncthreads();
     for (uint32_t k = ea + lane; k < eb; k += 64) {
-      const uint32_t e = out_perm[k];
-      const uint32_t src = e_src[e], j = e_dst[e];
-      const uint32_t sbk = block_of[src], tb = block_of[j];
-      const uint32_t sl = sbk - c0, t = tb - b0;
-      const uint32_t i0 = block_begin[sbk], ss = block_begin[sbk + 1] - i0;
-      const uint32_t tj0 = block_begin[tb], bt = block_begin[tb + 1] - tj0;
-      const uint32_t oi = src - i0, oj = j - tj0;
-      uint32_t dmax;
-      if (tb == sbk && oi < oj) {
-        dmax = oj - oi - 1;
+      const uint4 r = q[k];
+      const uint32_t lat = ql[k];
+      const uint32_t t = r.y & 0x7FFFFFFFu;
+      const uint32_t sl = r.w - c0;
+      uint32_t dmin, dmax;
+      if (r.y & 0x80000000u) {
+        dmin = dmax = r.z;
       } else {
-        const int32_t Et = (int32_t)D[t * L + sl];
-        dmax = (tb != sbk && Et >= 0) ? (ss - oi - 1) + ((uint32_t)Et - bt) + oj : e_dmin[e];
+        const uint32_t Es = Dsp[t * L + sl];
+        const int32_t El = (int32_t)Dlp[t * L + sl];
+        dmin = (Es == kInf) ? kInf : Es + r.z;
+        dmax = (r.w - b0 != t && El >= 0) ? (uint32_t)El + r.z : dmin;
       }
-      e_dmax[e] = dmax;
+      e_dmin[r.x] = dmin;
+      e_dmax[r.x] = dmax;
+      e_lat[r.x] = dmin <= lat ? 1 : 0;
     }
   }
 }
@@ -403,20 +428,31 @@ void build_cfg_order(gpa_program &p, hipStream_t s, Arena &ar, SweepPlan &plan,
 void build_distances(gpa_program &p, hipStream_t s, Arena &ar, const SweepPlan &plan) {
   const uint32_t nf = p.n_funcs, nb = p.n_blocks;
   const uint32_t max_nb = p.max_func_blocks;
-  p.e_dmin.alloc(p.n_edges);
-  p.e_dmax.alloc(p.n_edges);
-  if (p.n_edges == 0) return;
-  const uint32_t L = std::max<uint32_t>(1u, std::min<uint32_t>(64u, kDistLds / (4u * max_nb)));
-  const size_t lds = (size_t)4 * L * max_nb;
-  GPA_HIP(hipFuncSetAttribute((const void *)k_dist, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds));
+  const uint64_t ne = p.n_edges;
+  p.e_dmin.alloc(ne);
+  p.e_dmax.alloc(ne);
+  if (ne == 0) return;
   uint16_t *lat = ar.get<uint16_t>(16);
   GPA_HIP(hipMemcpyAsync(lat, p.arch.lat, sizeof(p.arch.lat), hipMemcpyHostToDevice, s));
+  uint4 *q = ar.get<uint4>(ne);
+  uint32_t *ql = ar.get<uint32_t>(ne);
+  uint8_t *e_lat = ar.get<uint8_t>(ne);
+  hipLaunchKernelGGL(k_dist_queries, dim3(grid_for(ne, 256, 8192)), dim3(256), 0, s, ne,
+                     p.out_perm.p, p.e_src.p, p.e_dst.p, p.block_of.p, p.func_of_block.p,
+                     p.func_block_begin.p, p.block_begin.p, p.op_class.p, lat, q, ql);
+  GPA_LAUNCH_CHECK();
+  const uint32_t L =
+      std::max<uint32_t>(1u, std::min<uint32_t>(64u, kDistLds / (8u * max_nb)));
+  const size_t lds = (size_t)8 * L * max_nb;
+  GPA_HIP(hipFuncSetAttribute((const void *)k_dist, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds));
   hipLaunchKernelGGL(k_dist, dim3((nb + L - 1) / L), dim3(64), lds, s, nb, nf, L,
-                     p.func_block_begin.p, p.func_of_block.p, p.block_begin.p, p.block_of.p,
-                     plan.ent_ptr, plan.ent, plan.ent_w, plan.ret_ptr, plan.rent, plan.rent_w,
-                     p.out_ptr.p, p.out_perm.p, p.e_src.p, p.e_dst.p, p.op_class.p, lat, p.e_dmin.p,
-                     p.e_dmax.p, p.e_flags.p);
+                     p.func_block_begin.p, p.func_of_block.p, p.block_begin.p, plan.ent_ptr,
+                     plan.ent, plan.ent_w, plan.ret_ptr, plan.rent, plan.rent_w, p.out_ptr.p, q, ql,
+                     p.e_dmin.p, p.e_dmax.p, e_lat);
+  GPA_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_merge_lat, dim3(grid_for(ne, 256, 8192)), dim3(256), 0, s, ne, e_lat,
+                     p.e_flags.p);
   GPA_LAUNCH_CHECK();
 }
 

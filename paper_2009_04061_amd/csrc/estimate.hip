@@ -201,11 +201,14 @@ __global__ void k_speedup(uint32_t n_scopes, const uint32_t *parent, const uint3
 }
 
 // ------------------------------------------------------------------ top-k
-// Two stages of bitonic sorts in LDS: each chunk of one kernel's (scope,
-// optimizer) items is sorted and keeps its best 16; one workgroup per kernel
-// then sorts its chunks' candidates (in rounds of kTopChunk, carrying the
-// best 16 forward).  Order: speedup descending, then optimizer, then scope
-// ascending (a total order, so the result is unique).
+// Two stages: a workgroup takes kTopChunk of one kernel's (scope, optimizer)
+// items, 8 per thread kept sorted in registers, and picks its best 16 in 16
+// rounds, each round selecting the best head over the workgroup (wave
+// shuffles, then one exchange of the 4 wave winners in LDS) and popping it
+// from its owner; one workgroup per kernel then does the same over its
+// chunks' winners, carrying the best 16 across rounds of kTopChunk.  Order:
+// speedup descending, then optimizer, then scope ascending (a total order,
+// so the result is unique).
 struct Cand {
   double s;
   uint32_t o, l;
@@ -219,7 +222,8 @@ __device__ __forceinline__ bool better(const Cand &a, const Cand &b) {
 
 constexpr int kTopK = 16;
 constexpr int kTopThreads = 256;
-constexpr uint32_t kTopChunk = 2048;   // items per sort (a power of two)
+constexpr int kPerThread = 8;
+constexpr uint32_t kTopChunk = kTopThreads * kPerThread;
 
 __device__ __forceinline__ Cand cand_none() {
   Cand c;
@@ -229,22 +233,69 @@ __device__ __forceinline__ Cand cand_none() {
   return c;
 }
 
-// sorts a[0..kTopChunk) best first
-__device__ void bitonic_best_first(Cand *a) {
-  for (uint32_t k = 2; k <= kTopChunk; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t i = threadIdx.x; i < kTopChunk; i += kTopThreads) {
-        const uint32_t ixj = i ^ j;
+__device__ __forceinline__ void cswap(Cand &a, Cand &b) {
+  if (better(b, a)) {
+    const Cand t = a;
+    a = b;
+    b = t;
+  }
+}
+
+// best first; a bitonic network on 8 with fixed register indices
+__device__ __forceinline__ void sort8(Cand (&a)[kPerThread]) {
+#pragma unroll
+  for (int k = 2; k <= kPerThread; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+      for (int i = 0; i < kPerThread; ++i) {
+        const int ixj = i ^ j;
         if (ixj > i) {
-          const Cand x = a[i], y = a[ixj];
-          const bool swap = ((i & k) == 0) ? better(y, x) : better(x, y);
-          if (swap) {
-            a[i] = y;
-            a[ixj] = x;
-          }
+          if ((i & k) == 0) cswap(a[i], a[ixj]);
+          else cswap(a[ixj], a[i]);
         }
       }
-      __syncthreads();
+}
+
+// the workgroup's best kTopK of the threads' sorted lists, in order, into out
+__device__ void select_top(Cand (&my)[kPerThread], Cand *out, Cand (*xch)[kTopThreads / kWave],
+                           uint32_t (*xwho)[kTopThreads / kWave]) {
+  const unsigned tid = threadIdx.x, w = tid / kWave;
+  for (int r = 0; r < kTopK; ++r) {
+    Cand c = my[0];
+    uint32_t who = tid;
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+      Cand o;
+      o.s = __shfl_xor(c.s, d, kWave);
+      o.o = (uint32_t)__shfl_xor((int)c.o, d, kWave);
+      o.l = (uint32_t)__shfl_xor((int)c.l, d, kWave);
+      const uint32_t ow = (uint32_t)__shfl_xor((int)who, d, kWave);
+      if (better(o, c) || (!better(c, o) && ow < who)) {
+        c = o;
+        who = ow;
+      }
+    }
+    if (lane_id() == 0) {
+      xch[r & 1][w] = c;
+      xwho[r & 1][w] = who;
+    }
+    __syncthreads();
+    Cand best = xch[r & 1][0];
+    uint32_t bw = xwho[r & 1][0];
+#pragma unroll
+    for (int v = 1; v < kTopThreads / kWave; ++v) {
+      const Cand o = xch[r & 1][v];
+      if (better(o, best) || (!better(best, o) && xwho[r & 1][v] < bw)) {
+        best = o;
+        bw = xwho[r & 1][v];
+      }
+    }
+    if (tid == 0) out[r] = best;
+    if (tid == bw) {
+#pragma unroll
+      for (int i = 0; i < kPerThread - 1; ++i) my[i] = my[i + 1];
+      my[kPerThread - 1] = cand_none();
     }
   }
 }
@@ -261,7 +312,8 @@ __global__ void __launch_bounds__(kTopThreads)
 k_topk_chunks(uint32_t n_roots, const uint32_t *roots, const uint32_t *nchunks,
               const uint32_t *chunk_start, const uint32_t *scope_end, const double *speedup,
               Cand *cand) {
-  __shared__ Cand a[kTopChunk];
+  __shared__ Cand xch[2][kTopThreads / kWave];
+  __shared__ uint32_t xwho[2][kTopThreads / kWave];
   const uint32_t c = blockIdx.x;
   const uint32_t total = chunk_start[n_roots - 1] + nchunks[n_roots - 1];
   if (c >= total) return;
@@ -270,44 +322,56 @@ k_topk_chunks(uint32_t n_roots, const uint32_t *roots, const uint32_t *nchunks,
   const uint64_t n_items = (uint64_t)(scope_end[r] - r) * GPA_N_OPT;
   const uint64_t base = (uint64_t)(c - chunk_start[ri]) * kTopChunk;
   const double *sp = speedup + (size_t)r * GPA_N_OPT;
-  for (uint32_t i = threadIdx.x; i < kTopChunk; i += kTopThreads) {
-    const uint64_t it = base + i;
+  Cand my[kPerThread];
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const uint64_t it = base + (uint64_t)i * kTopThreads + threadIdx.x;
     Cand x = cand_none();
     if (it < n_items) {
       x.s = sp[it];
       x.l = r + (uint32_t)(it / GPA_N_OPT);
       x.o = (uint32_t)(it % GPA_N_OPT);
     }
-    a[i] = x;
+    my[i] = x;
   }
-  __syncthreads();
-  bitonic_best_first(a);
-  if (threadIdx.x < kTopK) cand[(size_t)c * kTopK + threadIdx.x] = a[threadIdx.x];
+  sort8(my);
+  select_top(my, cand + (size_t)c * kTopK, xch, xwho);
 }
 
 __global__ void __launch_bounds__(kTopThreads)
 k_topk_final(const uint32_t *roots, const uint32_t *nchunks, const uint32_t *chunk_start,
              const Cand *cand, uint32_t k, uint32_t *top_opt, uint32_t *top_scope,
              double *top_speed) {
-  __shared__ Cand a[kTopChunk];
+  __shared__ Cand xch[2][kTopThreads / kWave];
+  __shared__ uint32_t xwho[2][kTopThreads / kWave];
+  __shared__ Cand best[kTopK];
   const uint32_t ri = blockIdx.x, r = roots[ri];
   const uint32_t n = nchunks[ri] * kTopK;
   const Cand *src = cand + (size_t)chunk_start[ri] * kTopK;
-  // round 0 takes kTopChunk candidates, later rounds keep the best kTopK in
-  // front and take kTopChunk - kTopK new ones
+  // round 0 takes kTopChunk candidates; later rounds carry the best kTopK in
+  // slots 0 .. kTopK-1 (item 0 of threads 0 .. 15) and take the rest anew
   uint32_t next = 0;
   for (uint32_t round = 0; round == 0 || next < n; ++round) {
     const uint32_t keep = round == 0 ? 0u : (uint32_t)kTopK;
-    for (uint32_t i = keep + threadIdx.x; i < kTopChunk; i += kTopThreads) {
-      const uint32_t it = next + (i - keep);
-      a[i] = it < n ? src[it] : cand_none();
+    Cand my[kPerThread];
+#pragma unroll
+    for (int i = 0; i < kPerThread; ++i) {
+      const uint32_t slot = (uint32_t)i * kTopThreads + threadIdx.x;
+      if (slot < keep) {
+        my[i] = best[slot];
+      } else {
+        const uint32_t it = next + (slot - keep);
+        my[i] = it < n ? src[it] : cand_none();
+      }
     }
     next += kTopChunk - keep;
     __syncthreads();
-    bitonic_best_first(a);
+    sort8(my);
+    select_top(my, best, xch, xwho);
+    __syncthreads();
   }
   for (uint32_t t = threadIdx.x; t < k; t += kTopThreads) {
-    const Cand c = t < (uint32_t)kTopK ? a[t] : cand_none();
+    const Cand c = t < (uint32_t)kTopK ? best[t] : cand_none();
     top_opt[(size_t)r * k + t] = c.o;
     top_scope[(size_t)r * k + t] = c.l;
     top_speed[(size_t)r * k + t] = c.o == 0xFFFFFFFFu ? 0.0 : c.s;

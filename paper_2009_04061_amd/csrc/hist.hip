@@ -2,21 +2,24 @@
 //
 // Device-wide atomics on MI355X retire far slower than HBM streams records,
 // and Zipf-distributed PCs serialize them on hot bins, so the histogram is
-// built without them, in two passes over the records and one over 2-byte
-// payloads:
-//   k_bcount      per tile of kTile records: LDS histogram of PC buckets
-//                 (kBucketPCs consecutive PCs) and the tile's totals;
-//   scan          bucket-major over (bucket, tile): where each tile's run of
-//                 each bucket goes, so that every bucket is one contiguous
-//                 range of payloads;
-//   k_partition   per tile: the records again, an LDS counting sort by bucket
-//                 and the runs written as payloads (pc offset in bucket,
-//                 stall, latency bit) at their positions;
-//   k_count       per work item (a contiguous range of one bucket): LDS
-//                 histogram of the bucket's 512 x 24 bins, written once to
-//                 the output (whole bucket) or to a partial slot;
-//   k_merge       per split bucket: sum of its partial slots.
-// Every output bin is written exactly once; integer sums are exact in any order.
+// built by partitioning the records into buckets of kBucketPCs consecutive
+// PCs whose 512 x 24 bins fit in LDS, reading the records once:
+//   k_hsample     every kSampleStride-th tile: bucket sizes, scaled up, give
+//                 each bucket a region of the payload array (capacity with
+//                 head-room and slack; k_hregions lays them out);
+//   k_partition   per tile of kTile records: an LDS counting sort by bucket,
+//                 one device atomic per (tile, bucket) reserving room in the
+//                 bucket's region, and the runs written as 2-byte payloads
+//                 (pc offset in bucket, stall, latency bit); a run that does
+//                 not fit goes to an overflow area as 4-byte keys;
+//   k_count       per work item (a contiguous range of one bucket's region):
+//                 LDS histogram of the bucket's bins, written once to the
+//                 output (whole bucket) or to a partial slot;
+//   k_merge       per split bucket: sum of its partial slots;
+//   k_hoverflow   overflow keys added with integer atomics (only when a
+//                 bucket outgrew its estimate).
+// Integer sums are exact in any order, so the result does not depend on
+// where runs land.
 #include "common.h"
 #include "devutil.h"
 
@@ -31,6 +34,8 @@ constexpr int kBucketPCs = 1 << kBucketShift;   // 512 PCs -> 12288 bins = 48 Ki
 constexpr int kBucketBins = kBucketPCs * 24;
 constexpr int kMaxBuckets = 8192;
 constexpr uint32_t kItemRecords = 1u << 17;     // records per counting work item
+constexpr uint32_t kSampleStride = 32;          // one sampled tile in this many
+constexpr uint32_t kBucketSlack = 4 * kTile;    // region slack per bucket, records
 
 typedef unsigned long u64x2 __attribute__((ext_vector_type(2)));
 
@@ -68,71 +73,74 @@ __device__ __forceinline__ uint32_t local_index(int bt, int q) {
   return (uint32_t)bt * 4096u + (uint32_t)(q / 2) * 512u + 2u * threadIdx.x + (uint32_t)(q & 1);
 }
 
+// bucket sizes of every kSampleStride-th tile, added into est[]
 template <bool VEC>
 __global__ void __launch_bounds__(kHistThreads)
-k_bcount(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint32_t n_buckets,
-         uint32_t n_tiles, uint32_t *__restrict__ tile_cnt, TileTotals *__restrict__ tile_tot) {
+k_hsample(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint32_t n_buckets,
+          uint32_t *__restrict__ est) {
   extern __shared__ uint32_t cnt[];   // [n_buckets]
-  __shared__ uint32_t red[3];
   const unsigned tid = threadIdx.x;
-  const uint64_t base = (uint64_t)blockIdx.x * kTile;
+  const uint64_t base = (uint64_t)blockIdx.x * kSampleStride * kTile;
   for (uint32_t b = tid; b < n_buckets; b += kHistThreads) cnt[b] = 0;
-  if (tid < 3) red[tid] = 0;
   __syncthreads();
-  uint32_t my_valid = 0, my_lat = 0, my_drop = 0;
 #pragma unroll
   for (int bt = 0; bt < kBatches; ++bt) {
     uint64_t v[kBatch];
     load_batch<VEC>(rec, n, base, bt, v);
 #pragma unroll
-    for (int q = 0; q < kBatch; ++q) {
-      if (base + local_index(bt, q) >= n) continue;
-      if (rec_valid(v[q], n_instr)) {
+    for (int q = 0; q < kBatch; ++q)
+      if (base + local_index(bt, q) < n && rec_valid(v[q], n_instr))
         atomicAdd(&cnt[(uint32_t)v[q] >> kBucketShift], 1u);
-        ++my_valid;
-        my_lat += (uint32_t)(v[q] >> 40) & 1u;
-      } else {
-        ++my_drop;
-      }
-    }
-  }
-  my_valid = wave_sum(my_valid);
-  my_lat = wave_sum(my_lat);
-  my_drop = wave_sum(my_drop);
-  if (lane_id() == 0) {
-    atomicAdd(&red[0], my_valid);
-    atomicAdd(&red[1], my_lat);
-    atomicAdd(&red[2], my_drop);
   }
   __syncthreads();
   for (uint32_t b = tid; b < n_buckets; b += kHistThreads)
-    tile_cnt[(size_t)b * n_tiles + blockIdx.x] = cnt[b];
-  if (tid == 0) {
-    TileTotals t;
-    t.valid = red[0];
-    t.latency = red[1];
-    t.dropped = red[2];
-    t.pad = 0;
-    tile_tot[blockIdx.x] = t;
+    if (cnt[b]) atomicAdd(&est[b], cnt[b]);
+}
+
+// regions: capacity = estimate * 5/4 + slack per bucket, laid out in bucket
+// order by one workgroup; cursors start at zero
+__global__ void __launch_bounds__(kHistThreads)
+k_hregions(uint32_t n_buckets, const uint32_t *__restrict__ est, uint32_t *__restrict__ cap,
+           uint32_t *__restrict__ region, uint32_t *__restrict__ cursor) {
+  __shared__ uint32_t tmp[kHistThreads / kWave + 1];
+  const uint32_t per = (n_buckets + kHistThreads - 1) / kHistThreads;
+  const uint32_t b0 = min(threadIdx.x * per, n_buckets), b1 = min(b0 + per, n_buckets);
+  uint32_t sum = 0;
+  for (uint32_t b = b0; b < b1; ++b) {
+    const uint64_t e = (uint64_t)est[b] * kSampleStride;
+    const uint32_t c = (uint32_t)min<uint64_t>(e + e / 4 + kBucketSlack, 0x40000000ull);
+    cap[b] = c;
+    sum += c;
+  }
+  uint32_t total;
+  uint32_t run = block_excl_scan<kHistThreads>(sum, tmp, &total);
+  for (uint32_t b = b0; b < b1; ++b) {
+    region[b] = run;
+    run += cap[b];
+    cursor[b] = 0;
   }
 }
 
 template <bool VEC>
 __global__ void __launch_bounds__(kHistThreads)
 k_partition(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint32_t n_buckets,
-            uint32_t n_tiles, const uint32_t *__restrict__ tile_pos, uint16_t *__restrict__ payload) {
+            const uint32_t *__restrict__ cap, const uint32_t *__restrict__ region,
+            uint32_t *__restrict__ cursor, uint16_t *__restrict__ payload,
+            uint32_t *__restrict__ ov_keys, uint32_t *__restrict__ ov_count,
+            TileTotals *__restrict__ tile_tot) {
   extern __shared__ uint32_t smem[];
   uint32_t *cnt = smem;                                   // [n_buckets + 1]
-  uint32_t *gpos = cnt + n_buckets + 1;                   // [n_buckets] where each run goes
-  uint32_t *staged = gpos + n_buckets;                    // [kTile]: bucket << 16 | payload
+  uint32_t *dst = cnt + n_buckets + 1;                    // [n_buckets] where each run goes
+  uint32_t *staged = dst + n_buckets;                     // [kTile]: bucket << 16 | payload
   __shared__ uint32_t scan_tmp[kHistThreads / kWave + 1];
+  __shared__ uint32_t red[3];
   const unsigned tid = threadIdx.x;
   const uint64_t base = (uint64_t)blockIdx.x * kTile;
   for (uint32_t b = tid; b <= n_buckets; b += kHistThreads) cnt[b] = 0;
-  for (uint32_t b = tid; b < n_buckets; b += kHistThreads)
-    gpos[b] = tile_pos[(size_t)b * n_tiles + blockIdx.x];
+  if (tid < 3) red[tid] = 0;
   __syncthreads();
   uint32_t rank[kTile / kHistThreads];
+  uint32_t my_lat = 0, my_drop = 0;
 #pragma unroll
   for (int bt = 0; bt < kBatches; ++bt) {
     uint64_t v[kBatch];
@@ -140,25 +148,48 @@ k_partition(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint
 #pragma unroll
     for (int q = 0; q < kBatch; ++q) {
       uint32_t rk = 0xFFFFFFFFu;
-      if (base + local_index(bt, q) < n && rec_valid(v[q], n_instr)) {
-        const uint32_t pc = (uint32_t)v[q], hi = (uint32_t)(v[q] >> 32);
-        const uint32_t b = pc >> kBucketShift;
-        const uint32_t pl = ((pc & (kBucketPCs - 1)) << 5) | ((hi & 0xFFu) * 2u + ((hi >> 8) & 1u));
-        rk = (b << 16) | atomicAdd(&cnt[b], 1u);
-        staged[local_index(bt, q)] = pl;   // parked; moved to its sorted slot below
+      if (base + local_index(bt, q) < n) {
+        if (rec_valid(v[q], n_instr)) {
+          const uint32_t pc = (uint32_t)v[q], hi = (uint32_t)(v[q] >> 32);
+          const uint32_t b = pc >> kBucketShift;
+          const uint32_t pl = ((pc & (kBucketPCs - 1)) << 5) | ((hi & 0xFFu) * 2u + ((hi >> 8) & 1u));
+          rk = (b << 16) | atomicAdd(&cnt[b], 1u);
+          staged[local_index(bt, q)] = pl;   // parked; moved to its sorted slot below
+          my_lat += (hi >> 8) & 1u;
+        } else {
+          ++my_drop;
+        }
       }
       rank[bt * kBatch + q] = rk;
     }
+  }
+  my_lat = wave_sum(my_lat);
+  my_drop = wave_sum(my_drop);
+  if (lane_id() == 0) {
+    atomicAdd(&red[1], my_lat);
+    atomicAdd(&red[2], my_drop);
+  }
+  __syncthreads();
+  // room for each run: a device atomic per non-empty bucket of the tile
+  for (uint32_t b = tid; b < n_buckets; b += kHistThreads) {
+    const uint32_t c = cnt[b];
+    uint32_t d = 0;
+    if (c) {
+      const uint32_t pos = atomicAdd(&cursor[b], c);
+      if (pos + c <= cap[b]) d = region[b] + pos;
+      else d = 0x80000000u | atomicAdd(ov_count, c);   // overflow area, 4-byte keys
+    }
+    dst[b] = d;
   }
   __syncthreads();
   // exclusive scan of the bucket counts
   {
     const uint32_t per = (n_buckets + kHistThreads - 1) / kHistThreads;
     const uint32_t b0 = min(tid * per, n_buckets), b1 = min(b0 + per, n_buckets);
-    uint32_t s = 0;
-    for (uint32_t b = b0; b < b1; ++b) s += cnt[b];
+    uint32_t sum = 0;
+    for (uint32_t b = b0; b < b1; ++b) sum += cnt[b];
     uint32_t total;
-    uint32_t run = block_excl_scan<kHistThreads>(s, scan_tmp, &total);
+    uint32_t run = block_excl_scan<kHistThreads>(sum, scan_tmp, &total);
     for (uint32_t b = b0; b < b1; ++b) {
       const uint32_t c = cnt[b];
       cnt[b] = run;
@@ -184,12 +215,21 @@ k_partition(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint
     }
   }
   __syncthreads();
-  // runs to their global positions (bucket-major layout)
   const uint32_t nvalid = cnt[n_buckets];
   for (uint32_t k = tid; k < nvalid; k += kHistThreads) {
     const uint32_t x = staged[k];
     const uint32_t b = x >> 16;
-    payload[gpos[b] + (k - cnt[b])] = (uint16_t)x;
+    const uint32_t d = dst[b];
+    if (!(d & 0x80000000u)) payload[d + (k - cnt[b])] = (uint16_t)x;
+    else ov_keys[(d & 0x7FFFFFFFu) + (k - cnt[b])] = x;
+  }
+  if (tid == 0) {
+    TileTotals t;
+    t.valid = nvalid;
+    t.latency = red[1];
+    t.dropped = red[2];
+    t.pad = 0;
+    tile_tot[blockIdx.x] = t;
   }
 }
 
@@ -225,16 +265,16 @@ __global__ void k_hist_totals(const TileTotals *__restrict__ tt, uint32_t n_tile
   }
 }
 
-// per bucket: its start in the payload array and its number of work items
-__global__ void k_bucket_plan(const uint32_t *tile_pos, uint32_t n_tiles, uint32_t n_buckets,
-                              const unsigned long long *totals, uint32_t *bstart, uint32_t *items) {
+// per bucket: its start and fill in the payload array, and its work items
+__global__ void k_bucket_plan(uint32_t n_buckets, const uint32_t *region, const uint32_t *cursor,
+                              const uint32_t *cap, uint32_t *bstart, uint32_t *bfill,
+                              uint32_t *items) {
   for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_buckets;
        b += gridDim.x * blockDim.x) {
-    const uint32_t s0 = tile_pos[(size_t)b * n_tiles];
-    const uint32_t s1 = (b + 1 < n_buckets) ? tile_pos[(size_t)(b + 1) * n_tiles]
-                                            : (uint32_t)totals[0];
-    bstart[b] = s0;
-    const uint32_t r = (s1 - s0 + kItemRecords - 1) / kItemRecords;
+    const uint32_t fill = min(cursor[b], cap[b]);
+    bstart[b] = region[b];
+    bfill[b] = fill;
+    const uint32_t r = (fill + kItemRecords - 1) / kItemRecords;
     items[b] = r < 1 ? 1 : r;
   }
 }
@@ -242,7 +282,7 @@ __global__ void k_bucket_plan(const uint32_t *tile_pos, uint32_t n_tiles, uint32
 // work item -> (bucket, part) via the prefix of items per bucket
 __global__ void __launch_bounds__(kHistThreads)
 k_count(const uint16_t *__restrict__ payload, const uint32_t *__restrict__ bstart,
-        uint32_t n_buckets, uint32_t n_instr, const unsigned long long *totals,
+        const uint32_t *__restrict__ bfill, uint32_t n_buckets, uint32_t n_instr,
         const uint32_t *__restrict__ items, const uint32_t *__restrict__ item_start,
         uint32_t *__restrict__ counts, uint32_t *__restrict__ partial) {
   __shared__ uint32_t bins[kBucketBins];
@@ -252,9 +292,9 @@ k_count(const uint16_t *__restrict__ payload, const uint32_t *__restrict__ bstar
   const uint32_t b = upper_index_u32(item_start, 0, n_buckets, it);
   const uint32_t parts = items[b], part = it - item_start[b];
   const uint32_t s0 = bstart[b];
-  const uint32_t s1 = (b + 1 < n_buckets) ? bstart[b + 1] : (uint32_t)totals[0];
-  const uint32_t q0 = s0 + (uint32_t)((uint64_t)(s1 - s0) * part / parts);
-  const uint32_t q1 = s0 + (uint32_t)((uint64_t)(s1 - s0) * (part + 1) / parts);
+  const uint32_t fill = bfill[b];
+  const uint32_t q0 = s0 + (uint32_t)((uint64_t)fill * part / parts);
+  const uint32_t q1 = s0 + (uint32_t)((uint64_t)fill * (part + 1) / parts);
   for (uint32_t k = threadIdx.x; k < kBucketBins; k += kHistThreads) bins[k] = 0;
   __syncthreads();
   uint32_t q = q0 + threadIdx.x;
@@ -307,6 +347,17 @@ k_merge(const uint32_t *__restrict__ partial, const uint32_t *__restrict__ items
   counts[(size_t)pc0 * 24u + k] = (s0 + s1) + (s2 + s3);
 }
 
+// keys of runs that did not fit their bucket's region (bucket << 16 | payload)
+__global__ void k_hoverflow(const uint32_t *__restrict__ ov_keys, const uint32_t *__restrict__ ov_count,
+                            uint32_t *__restrict__ counts) {
+  const uint32_t n = *ov_count;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const uint32_t x = ov_keys[k];
+    const uint32_t pc = (x >> 16) * kBucketPCs + ((x & 0xFFFFu) >> 5);
+    atomicAdd(&counts[(size_t)pc * 24u + (x & 31u)], 1u);
+  }
+}
+
 __global__ void k_hist_empty(uint32_t *counts, size_t nbins, unsigned long long *totals) {
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < nbins;
        k += (size_t)gridDim.x * blockDim.x)
@@ -326,54 +377,66 @@ void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint3
     GPA_LAUNCH_CHECK();
     return;
   }
-  if (n >= 0xFFFFFFFFull) fail(GPA_E_UNSUPPORTED, "at most 2^32-1 samples in one call");
+  if (n >= 0x40000000ull) fail(GPA_E_UNSUPPORTED, "at most 2^30 samples in one call");
   const uint32_t n_tiles = (uint32_t)((n + kTile - 1) / kTile);
-  if ((uint64_t)n_tiles * n_buckets >= 0xFFFFFFFFull)
-    fail(GPA_E_UNSUPPORTED, "too many (tile, bucket) pairs in one call");
   const uint64_t *rec = (const uint64_t *)samples;
   const bool vec = ((uintptr_t)samples % 16) == 0;
-  uint32_t *tile_cnt = ar.get<uint32_t>((size_t)n_buckets * n_tiles);
-  uint32_t *tile_pos = ar.get<uint32_t>((size_t)n_buckets * n_tiles);
-  TileTotals *tt = ar.get<TileTotals>(n_tiles);
+  // bucket regions from a sample of the tiles
+  const uint32_t n_samp = (n_tiles + kSampleStride - 1) / kSampleStride;
+  uint32_t *est = ar.get<uint32_t>(n_buckets), *cap = ar.get<uint32_t>(n_buckets);
+  uint32_t *region = ar.get<uint32_t>(n_buckets), *cursor = ar.get<uint32_t>(n_buckets);
+  uint32_t *ov_count = ar.get<uint32_t>(1);
+  GPA_HIP(hipMemsetAsync(est, 0, 4 * (size_t)n_buckets, s));
+  GPA_HIP(hipMemsetAsync(ov_count, 0, 4, s));
   const size_t lds_count = (size_t)n_buckets * 4;
   if (vec)
-    hipLaunchKernelGGL(k_bcount<true>, dim3(n_tiles), dim3(kHistThreads), lds_count, s, rec, n,
-                       n_instr, n_buckets, n_tiles, tile_cnt, tt);
+    hipLaunchKernelGGL(k_hsample<true>, dim3(n_samp), dim3(kHistThreads), lds_count, s, rec, n,
+                       n_instr, n_buckets, est);
   else
-    hipLaunchKernelGGL(k_bcount<false>, dim3(n_tiles), dim3(kHistThreads), lds_count, s, rec, n,
-                       n_instr, n_buckets, n_tiles, tile_cnt, tt);
+    hipLaunchKernelGGL(k_hsample<false>, dim3(n_samp), dim3(kHistThreads), lds_count, s, rec, n,
+                       n_instr, n_buckets, est);
   GPA_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_hist_totals, dim3(1), dim3(kHistThreads), 0, s, tt, n_tiles, totals);
-  exclusive_scan_u32(tile_cnt, tile_pos, (size_t)n_buckets * n_tiles, s, ar);
-  uint16_t *payload = ar.get<uint16_t>(n);
+  hipLaunchKernelGGL(k_hregions, dim3(1), dim3(kHistThreads), 0, s, n_buckets, est, cap, region,
+                     cursor);
+  GPA_LAUNCH_CHECK();
+  // the regions hold at most 5/4 of the scaled sample plus the slack
+  const uint64_t max_region = (uint64_t)n_samp * kTile * kSampleStride * 5 / 4 +
+                              (uint64_t)n_buckets * (kBucketSlack + 1);
+  uint16_t *payload = ar.get<uint16_t>(max_region);
+  uint32_t *ov_keys = ar.get<uint32_t>(n);
+  TileTotals *tt = ar.get<TileTotals>(n_tiles);
   const size_t lds_part = (2 * (size_t)n_buckets + 1) * 4 + (size_t)kTile * 4;
   if (vec) {
     GPA_HIP(hipFuncSetAttribute((const void *)k_partition<true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_part));
     hipLaunchKernelGGL(k_partition<true>, dim3(n_tiles), dim3(kHistThreads), lds_part, s, rec, n,
-                       n_instr, n_buckets, n_tiles, tile_pos, payload);
+                       n_instr, n_buckets, cap, region, cursor, payload, ov_keys, ov_count, tt);
   } else {
     GPA_HIP(hipFuncSetAttribute((const void *)k_partition<false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_part));
     hipLaunchKernelGGL(k_partition<false>, dim3(n_tiles), dim3(kHistThreads), lds_part, s, rec, n,
-                       n_instr, n_buckets, n_tiles, tile_pos, payload);
+                       n_instr, n_buckets, cap, region, cursor, payload, ov_keys, ov_count, tt);
   }
   GPA_LAUNCH_CHECK();
-  uint32_t *bstart = ar.get<uint32_t>(n_buckets);
+  hipLaunchKernelGGL(k_hist_totals, dim3(1), dim3(kHistThreads), 0, s, tt, n_tiles, totals);
+  uint32_t *bstart = ar.get<uint32_t>(n_buckets), *bfill = ar.get<uint32_t>(n_buckets);
   uint32_t *items = ar.get<uint32_t>(n_buckets);
   uint32_t *item_start = ar.get<uint32_t>(n_buckets);
-  hipLaunchKernelGGL(k_bucket_plan, dim3(grid_for(n_buckets, 256, 64)), dim3(256), 0, s, tile_pos,
-                     n_tiles, n_buckets, totals, bstart, items);
+  hipLaunchKernelGGL(k_bucket_plan, dim3(grid_for(n_buckets, 256, 64)), dim3(256), 0, s,
+                     n_buckets, region, cursor, cap, bstart, bfill, items);
   GPA_LAUNCH_CHECK();
   exclusive_scan_u32(items, item_start, n_buckets, s, ar);
   // items <= one per bucket plus one per kItemRecords records
   const uint64_t max_items = n_buckets + n / kItemRecords + 1;
   uint32_t *partial = ar.get<uint32_t>((size_t)max_items * kBucketBins);
   hipLaunchKernelGGL(k_count, dim3((unsigned)max_items), dim3(kHistThreads), 0, s, payload, bstart,
-                     n_buckets, n_instr, totals, items, item_start, counts, partial);
+                     bfill, n_buckets, n_instr, items, item_start, counts, partial);
   GPA_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_merge, dim3(n_buckets, kBucketBins / kHistThreads), dim3(kHistThreads), 0,
                      s, partial, items, item_start, n_instr, counts);
+  GPA_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_hoverflow, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, ov_keys, ov_count,
+                     counts);
   GPA_LAUNCH_CHECK();
 }
 

@@ -538,6 +538,10 @@ void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar) {
   if (p.max_func_blocks > 4096)
     fail(GPA_E_UNSUPPORTED, "a function has %u blocks; at most 4096 are supported",
          p.max_func_blocks);
+}
+
+void build_sites_and_scopes(gpa_program &p, hipStream_t s, Arena &ar) {
+  const uint32_t n = p.n_instr, nf = p.n_funcs, ns = p.n_scopes;
   // sites by (function, location, instruction)
   p.def_instr.alloc(p.n_defs);
   p.use_instr.alloc(p.n_uses);
