@@ -167,15 +167,6 @@ static void upload(DBuf<T> &dst, const T *src, size_t n, bool on_device, hipStre
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
 }
 
-static uint32_t read_u32(const uint32_t *p, bool on_device, hipStream_t s) {
-  if (!p) fail(GPA_E_INVALID, "a descriptor array is NULL");
-  if (!on_device) return *p;
-  uint32_t v = 0;
-  GPA_HIP(hipMemcpyAsync(&v, p, 4, hipMemcpyDeviceToHost, s));
-  GPA_HIP(hipStreamSynchronize(s));
-  return v;
-}
-
 template <typename F>
 static gpa_status guarded(F &&body) {
   try {
@@ -257,9 +248,21 @@ gpa_status gpa_load_program(const gpa_program_desc *d, void *stream, gpa_program
     p->n_loc = (uint32_t)n_loc;
     p->arch = d->arch;
     p->n_blamable = (uint32_t)__builtin_popcount(d->arch.blamable & 0xFFFu);
-    p->n_defs = read_u32(d->def_ptr + d->n_instr, dev, s);
-    p->n_uses = read_u32(d->use_ptr + d->n_instr, dev, s);
-    p->n_succ = read_u32(d->succ_ptr + d->n_blocks, dev, s);
+    if (!d->def_ptr || !d->use_ptr || !d->succ_ptr) fail(GPA_E_INVALID, "a descriptor array is NULL");
+    if (dev) {
+      uint32_t sizes[3];
+      GPA_HIP(hipMemcpyAsync(&sizes[0], d->def_ptr + d->n_instr, 4, hipMemcpyDeviceToHost, s));
+      GPA_HIP(hipMemcpyAsync(&sizes[1], d->use_ptr + d->n_instr, 4, hipMemcpyDeviceToHost, s));
+      GPA_HIP(hipMemcpyAsync(&sizes[2], d->succ_ptr + d->n_blocks, 4, hipMemcpyDeviceToHost, s));
+      GPA_HIP(hipStreamSynchronize(s));
+      p->n_defs = sizes[0];
+      p->n_uses = sizes[1];
+      p->n_succ = sizes[2];
+    } else {
+      p->n_defs = d->def_ptr[d->n_instr];
+      p->n_uses = d->use_ptr[d->n_instr];
+      p->n_succ = d->succ_ptr[d->n_blocks];
+    }
     const uint32_t n = p->n_instr, nb = p->n_blocks;
     upload(p->op_class, d->op_class, n, dev, s);
     upload(p->guard, d->guard, n, dev, s);

@@ -122,7 +122,6 @@ struct gpa_program {
   gpa::DBuf<uint32_t> e_lca, e_icl;            // per edge target scopes
   gpa::DBuf<uint8_t> instr_tags;               // bit0 in math fn, bit1 in device fn with CFG
   gpa::DBuf<uint32_t> lca_ptr, lca_perm, icl_ptr, icl_perm, line_ptr, line_perm;
-  uint64_t n_icl = 0;                          // edges with a common loop
   // segments longer than a thread sums alone, per grouping (own sums by
   // scope, edges by common loop, edges by common scope, subtrees), each list
   // n_scopes long, counts in big_n[4]
@@ -184,7 +183,7 @@ hipStream_t side_stream();
 // The G' sweep streams the distance kernel reads (built with the DFS order).
 struct SweepPlan {
   uint32_t *ent_ptr = nullptr, *ent = nullptr, *ent_w = nullptr;
-  uint32_t *ret_ptr = nullptr, *rent = nullptr, *rent_w = nullptr;
+  uint32_t *ret_ptr = nullptr, *rent = nullptr, *rent_w = nullptr, *rent_e = nullptr;
 };
 void build_cfg_order(gpa_program &p, hipStream_t s, Arena &ar, SweepPlan &plan,
                      PhaseTimer &t_dfs);
@@ -220,6 +219,14 @@ T read_scalar(const T *dev, hipStream_t s) {
   GPA_HIP(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, s));
   GPA_HIP(hipStreamSynchronize(s));
   return v;
+}
+
+// read two device values with one synchronization
+template <typename A, typename B>
+void read_scalars(const A *da, A &a, const B *db, B &b, hipStream_t s) {
+  GPA_HIP(hipMemcpyAsync(&a, da, sizeof(A), hipMemcpyDeviceToHost, s));
+  GPA_HIP(hipMemcpyAsync(&b, db, sizeof(B), hipMemcpyDeviceToHost, s));
+  GPA_HIP(hipStreamSynchronize(s));
 }
 
 inline unsigned grid_for(size_t n, unsigned block, unsigned cap = 1u << 20) {

@@ -257,8 +257,8 @@ __device__ __forceinline__ void or_range(uint64_t *in, uint32_t d0, uint32_t g, 
 // block over whole predecessor blocks; the blocks met are kept in a
 // per-thread list in LDS (also the queue), with a 128-bit filter in
 // registers to skip most list scans.  IN bitsets of up to kRegWords words
-// are accumulated in registers and written once; longer ones are OR-ed in
-// place.  A search that would meet more than kSearchCap blocks is left to
+// are accumulated in LDS (thread-private words, OR without return) and
+// written once; longer ones are OR-ed in place.  A search that would meet more than kSearchCap blocks is left to
 // k_rd_search_long.
 constexpr uint32_t kRegWords = 8;
 
@@ -271,6 +271,7 @@ k_rd_search(uint32_t n_uses, uint32_t n_blocks, uint32_t n_loc, const uint32_t *
             const uint2 *t1, const uint32_t *slot_start, uint64_t *rd_in, uint32_t *long_list,
             uint32_t *n_long) {
   __shared__ uint16_t seen[kSearchCap * kSearchThreads];
+  __shared__ unsigned long long inw[kRegWords * kSearchThreads];   // [word][thread]
   const unsigned tid = threadIdx.x;
   const uint32_t t = blockIdx.x * kSearchThreads + tid;
   if (t >= 2 * n_uses) return;
@@ -285,12 +286,12 @@ k_rd_search(uint32_t n_uses, uint32_t n_blocks, uint32_t n_loc, const uint32_t *
   const uint32_t nd = fl_def_ptr[fi + 1] - d0;
   if (nd == 0) return;
   const uint32_t nw = (nd + 63) / 64;
+  const bool local = nw <= kRegWords;
   const uint32_t c = use_cond[u];
   const size_t row = (size_t)x * n_blocks + b0;
   uint64_t *in = rd_in + slot_start[k] + var;
-  uint64_t acc[kRegWords];
-#pragma unroll
-  for (uint32_t w = 0; w < kRegWords; ++w) acc[w] = 0ull;
+  if (local)
+    for (uint32_t w = 0; w < nw; ++w) inw[w * kSearchThreads + tid] = 0ull;
   uint32_t n_seen = 0, head = 0;
   uint64_t fl0 = 0, fl1 = 0;
   bool ok = true;
@@ -318,11 +319,10 @@ k_rd_search(uint32_t n_uses, uint32_t n_blocks, uint32_t n_loc, const uint32_t *
     const Survive sv = block_step(r, t1, row + pl, dsi, dsg, usi, c, blocked);
     if (sv.g < r.z) {
       const uint32_t lo = sv.g - d0, hi = r.z - d0;
-      if (nw <= kRegWords) {
-#pragma unroll
-        for (uint32_t w = 0; w < kRegWords; ++w) acc[w] |= range_word(lo, hi, 64 * w);
-      } else {
-        for (uint32_t w = lo / 64; w * 64 < hi; ++w) in[2 * w] |= range_word(lo, hi, 64 * w);
+      for (uint32_t w = lo / 64; w * 64 < hi; ++w) {
+        const uint64_t m = range_word(lo, hi, 64 * w);
+        if (local) atomicOr(&inw[w * kSearchThreads + tid], (unsigned long long)m);
+        else in[2 * w] |= m;
       }
     }
     if (!sv.kill)
@@ -332,11 +332,8 @@ k_rd_search(uint32_t n_uses, uint32_t n_blocks, uint32_t n_loc, const uint32_t *
     long_list[atomicAdd(n_long, 1u)] = k | (var << 31);
     return;
   }
-  if (nw <= kRegWords) {
-#pragma unroll
-    for (uint32_t w = 0; w < kRegWords; ++w)
-      if (w < nw) in[2 * w] = acc[w];
-  }
+  if (local)
+    for (uint32_t w = 0; w < nw; ++w) in[2 * w] = inw[w * kSearchThreads + tid];
 }
 
 // The searches one thread could not hold: one workgroup per use, level by
@@ -571,8 +568,9 @@ void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar, PhaseTimer &t
                      fl_chunks, p.use_rank.p, slot_words);
   GPA_LAUNCH_CHECK();
   exclusive_scan_u32(slot_words, slot_start, p.n_uses, s, ar, nslot_d);
-  const uint64_t nslot = read_scalar(nslot_d, s);
-  const uint32_t max_words = read_scalar(scal, s);
+  unsigned long long nslot = 0;
+  uint32_t max_words = 0;
+  read_scalars(nslot_d, nslot, scal, max_words, s);
   uint64_t *rd_in = ar.get<uint64_t>(nslot ? nslot : 1);
   if (nslot) {
     const size_t lds_long = kStageRows + 8u * (size_t)max_words + kStagePred +

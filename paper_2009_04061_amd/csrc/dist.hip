@@ -43,36 +43,61 @@ __device__ __forceinline__ void bit_set(uint32_t &r0, uint32_t &r1, uint32_t v) 
 
 constexpr uint32_t kNoSucc = 0xFFFFu;
 
+// Chains: a block v whose only predecessor p has v as its only successor and
+// comes before it (p < v) is a chain member behind p.  The walk enters such a
+// v from p at once (v cannot be a root: p is reached no later than the root
+// loop reaches v), no other edge leads to v, and v finishes right after
+// everything behind it, so the walk only needs the chain heads, each with
+// the edges of its chain's last block; the postorder is expanded afterwards.
 __global__ void __launch_bounds__(64)
-k_dfs(const uint32_t *fbb, const uint32_t *succ_ptr, const uint32_t *succ, uint8_t *retreat,
-      uint32_t *rpo_pos, uint32_t *rpo_order) {
+k_dfs(const uint32_t *fbb, const uint32_t *succ_ptr, const uint32_t *succ,
+      const uint32_t *pred_ptr, const uint32_t *pred, uint8_t *retreat, uint32_t *rpo_pos,
+      uint32_t *rpo_order) {
   extern __shared__ uint4 shq[];
   const uint32_t f = blockIdx.x;
   const uint32_t b0 = fbb[f], nb = fbb[f + 1] - b0;
   const uint32_t e0 = succ_ptr[b0], ne = succ_ptr[b0 + nb] - e0;
   const unsigned lane = lane_id();
-  uint4 *stk = shq;                            // [nb] (block, next edge, end, next successor)
-  uint2 *rng = (uint2 *)(stk + nb);            // [nb] edge range
-  uint32_t *s01 = (uint32_t *)(rng + nb);      // [nb] first two successors
-  uint16_t *lsucc = (uint16_t *)(s01 + nb);    // [ne]
-  uint16_t *post = lsucc + ne;                 // [nb]
-  uint8_t *ret = (uint8_t *)(post + nb);       // [ne]
-  for (uint32_t b = lane; b < nb; b += 64) {
-    const uint32_t lo = succ_ptr[b0 + b] - e0, hi = succ_ptr[b0 + b + 1] - e0;
-    rng[b] = make_uint2(lo, hi);
-    const uint32_t a0 = lo < hi ? succ[e0 + lo] - b0 : kNoSucc;
-    const uint32_t a1 = lo + 1 < hi ? succ[e0 + lo + 1] - b0 : kNoSucc;
-    s01[b] = a0 | (a1 << 16);
-  }
+  uint4 *stk = shq;                            // [nb] (head, next edge, end, next successor)
+  uint2 *rng = (uint2 *)(stk + nb);            // [nb] edge range of the head's chain end
+  uint32_t *s01 = (uint32_t *)(rng + nb);      // [nb] its first two successors
+  uint16_t *nxt = (uint16_t *)(s01 + nb);      // [nb] next chain member or kNoSucc
+  uint16_t *posth = nxt + nb;                  // [nb] heads in postorder
+  uint16_t *lsucc = posth + nb;                // [ne]
+  uint8_t *ret = (uint8_t *)(lsucc + ne);      // [ne]
+  uint8_t *head = ret + ne;                    // [nb]
+  for (uint32_t b = lane; b < nb; b += 64) nxt[b] = (uint16_t)kNoSucc;
   for (uint32_t e = lane; e < ne; e += 64) {
     lsucc[e] = (uint16_t)(succ[e0 + e] - b0);
     ret[e] = 0;
   }
   __syncthreads();
+  for (uint32_t v = lane; v < nb; v += 64) {
+    const uint32_t q0 = pred_ptr[b0 + v], q1 = pred_ptr[b0 + v + 1];
+    bool member = false;
+    if (q1 - q0 == 1) {
+      const uint32_t pb = pred[q0] - b0;
+      member = pb < v && succ_ptr[b0 + pb + 1] - succ_ptr[b0 + pb] == 1;
+      if (member) nxt[pb] = (uint16_t)v;
+    }
+    head[v] = member ? 0 : 1;
+  }
+  __syncthreads();
+  for (uint32_t h = lane; h < nb; h += 64) {
+    if (!head[h]) continue;
+    uint32_t t = h;
+    while (nxt[t] != kNoSucc) t = nxt[t];
+    const uint32_t lo = succ_ptr[b0 + t] - e0, hi = succ_ptr[b0 + t + 1] - e0;
+    rng[h] = make_uint2(lo, hi);
+    const uint32_t a0 = lo < hi ? succ[e0 + lo] - b0 : kNoSucc;
+    const uint32_t a1 = lo + 1 < hi ? succ[e0 + lo + 1] - b0 : kNoSucc;
+    s01[h] = a0 | (a1 << 16);
+  }
+  __syncthreads();
   uint32_t vis0 = 0, vis1 = 0, fin0 = 0, fin1 = 0;
   uint32_t npost = 0;
   for (uint32_t root = 0; root < nb; ++root) {
-    if (bit_test(vis0, vis1, root)) continue;
+    if (!head[root] || bit_test(vis0, vis1, root)) continue;
     bit_set(vis0, vis1, root);
     uint32_t sp = 0, u = root;
     uint2 r = rng[root];
@@ -108,7 +133,7 @@ k_dfs(const uint32_t *fbb, const uint32_t *succ_ptr, const uint32_t *succ, uint8
         }
       } else {
         bit_set(fin0, fin1, u);
-        if (lane == 0) post[npost] = (uint16_t)u;
+        if (lane == 0) posth[npost] = (uint16_t)u;
         ++npost;
         if (sp == 0) break;
         --sp;
@@ -123,10 +148,28 @@ k_dfs(const uint32_t *fbb, const uint32_t *succ_ptr, const uint32_t *succ, uint8
   }
   __syncthreads();
   for (uint32_t e = lane; e < ne; e += 64) retreat[e0 + e] = ret[e];
-  for (uint32_t k = lane; k < nb; k += 64) {
-    const uint32_t b = post[nb - 1 - k];   // reverse postorder
-    rpo_pos[b0 + b] = k;
-    rpo_order[b0 + k] = b0 + b;
+  // postorder: a finished head is followed by its chain's members from the
+  // last to the head itself; positions by a running sum of chain lengths
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < npost; base += 64) {
+    const uint32_t i = base + lane;
+    uint32_t h = 0, len = 0;
+    if (i < npost) {
+      h = posth[i];
+      for (uint32_t t = h; t != kNoSucc; t = nxt[t]) ++len;
+    }
+    const uint32_t incl = wave_incl_scan(len);
+    const uint32_t first = carry + incl - len;   // postorder index of the chain's last block
+    if (i < npost) {
+      uint32_t o = 0;
+      for (uint32_t t = h; t != kNoSucc; t = nxt[t], ++o) {
+        const uint32_t post = first + (len - 1 - o);
+        const uint32_t rp = nb - 1 - post;
+        rpo_pos[b0 + t] = rp;
+        rpo_order[b0 + rp] = b0 + t;
+      }
+    }
+    carry += __shfl(incl, 63, 64);
   }
 }
 
@@ -168,7 +211,7 @@ __global__ void k_sweep_fill(uint32_t n_blocks, const uint32_t *fbb,
                              const uint32_t *pred_ptr, const uint32_t *pred,
                              const uint32_t *rpo_pos, const uint32_t *ent_ptr,
                              const uint32_t *ret_ptr, uint32_t *ent, uint32_t *ent_w,
-                             uint32_t *rent, uint32_t *rent_w) {
+                             uint32_t *rent, uint32_t *rent_w, uint32_t *rent_e) {
   for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_blocks;
        b += gridDim.x * blockDim.x) {
     const uint32_t b0 = fbb[func_of_block[b]];
@@ -190,6 +233,7 @@ __global__ void k_sweep_fill(uint32_t n_blocks, const uint32_t *fbb,
       if (ret) {
         rent[roff] = (v - b0) | (bl << 13);
         rent_w[roff] = bs;
+        rent_e[roff] = off;   // where the header's entries start
         ++roff;
       }
     }
@@ -199,28 +243,32 @@ __global__ void k_sweep_fill(uint32_t n_blocks, const uint32_t *fbb,
 // One sweep over a function's stream in G' order.  Every lane follows its
 // own source block s with the same (uniform) control flow; the table holds,
 // per block w and lane, the walk length up to and including w:
-//   shortest:  E[w] = min over edges v -> w of (v == s ? 0 : E[v]) + |w|
-//   longest:   the same maximum over edges that are not retreating, -1 for
-//              blocks no G' walk from s reaches.
-// Table reads run kPD entries ahead of their use, so they are issued before
-// the writes of the kPD entries in between; those writes are kept in a
-// register ring and forwarded (a block is written once per sweep, so at most
-// one ring slot matches).
+//   shortest:  E[w] = min over edges v -> w of (v == s ? 0 : E[v]) + |w|,
+//              saturating at kInf (no walk);
+//   longest:   the same maximum over edges that are not retreating, stored
+//              plus one so that 0 means no G' walk from s reaches w.
+// The table has a spare row (written by entries that are not the last of
+// their block) and a spare column (written by lanes without a source), so
+// every entry is the same straight-line code.  Table reads run kPD entries
+// ahead of their use and are issued before the writes of the kPD entries in
+// between; those writes sit in a ring (slot = entry index mod kPD) and are
+// forwarded (a block is written once per sweep, so at most one slot matches).
 constexpr int kPD = 4;
 
 template <bool kLongest>
-__device__ void dist_sweep(uint32_t *D, uint32_t L, uint32_t li, bool writer, uint32_t s,
+__device__ void dist_sweep(uint32_t *D, uint32_t Lc, uint32_t col, uint32_t s, uint32_t spare_row,
                            const uint32_t *ent, const uint32_t *ent_w, uint32_t e_begin,
                            uint32_t e_end) {
   const unsigned lane = threadIdx.x;
+  const uint32_t none = kLongest ? 0u : kInf;     // "no walk"
+  const uint32_t at_s = kLongest ? 1u : 0u;       // a walk that starts at s
   uint32_t rw[kPD], re[kPD];
 #pragma unroll
   for (int r = 0; r < kPD; ++r) {
     rw[r] = kLocalNone;
-    re[r] = kInf;
+    re[r] = none;
   }
-  uint32_t best = kInf;
-  // the next batch of entries is loaded while the current one is swept
+  uint32_t best = none;
   uint32_t idx = e_begin + lane;
   uint32_t vp = idx < e_end ? ent[idx] : kLocalNone;
   uint32_t vw = idx < e_end ? ent_w[idx] : 0u;
@@ -232,43 +280,35 @@ __device__ void dist_sweep(uint32_t *D, uint32_t L, uint32_t li, bool writer, ui
 #pragma unroll
     for (int i = 0; i < kPD; ++i) {
       const uint32_t v = __builtin_amdgcn_readlane(vp, i) & kLocalNone;
-      pre[i] = D[(v == kLocalNone ? 0u : v) * L + li];
+      pre[i] = D[(v == kLocalNone ? spare_row : v) * Lc + col];
     }
-    // 16 entries per unrolled body keeps the code small; ring slots stay
-    // compile-time indices because 16 is a multiple of kPD
     for (int i0 = 0; i0 < 64; i0 += 16) {
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int i = i0 + j;
         const uint32_t pk = __builtin_amdgcn_readlane(vp, i);
+        const uint32_t bw = __builtin_amdgcn_readlane(vw, i);
         const uint32_t v = pk & kLocalNone;
         uint32_t c = pre[j % kPD];
         if (i + kPD < 64) {
           const uint32_t vn = __builtin_amdgcn_readlane(vp, i + kPD) & kLocalNone;
-          pre[j % kPD] = D[(vn == kLocalNone ? 0u : vn) * L + li];
+          pre[j % kPD] = D[(vn == kLocalNone ? spare_row : vn) * Lc + col];
         }
-        if (pk & kEntFirst) best = kInf;
-        if (v != kLocalNone && !(kLongest && (pk & kEntRet))) {
 #pragma unroll
-          for (int r = 0; r < kPD; ++r)
-            if (v == rw[r]) c = re[r];
-          if (v == s) c = 0;
-          // kInf reads as -1 for longest walks: no walk
-          best = kLongest ? (uint32_t)max((int32_t)best, (int32_t)c) : min(best, c);
-        }
-        if (pk & kEntLast) {
-          const uint32_t w = (pk >> 13) & kLocalNone;
-          const uint32_t bw = __builtin_amdgcn_readlane(vw, i);
-          const uint32_t e = (best == kInf) ? kInf : best + bw;
-          if (writer) D[w * L + li] = e;
-#pragma unroll
-          for (int r = kPD - 1; r > 0; --r) {
-            rw[r] = rw[r - 1];
-            re[r] = re[r - 1];
-          }
-          rw[0] = w;
-          re[0] = e;
-        }
+        for (int r = 0; r < kPD; ++r) c = (v == rw[r]) ? re[r] : c;
+        c = (v == s) ? at_s : c;
+        const bool use = v != kLocalNone && !(kLongest && (pk & kEntRet));
+        best = (pk & kEntFirst) ? none : best;
+        const uint32_t nb_ = kLongest ? max(best, c) : min(best, c);
+        best = use ? nb_ : best;
+        uint32_t e;
+        if (kLongest) e = best ? best + bw : 0u;
+        else e = __builtin_elementwise_add_sat(best, bw);
+        const bool last = (pk & kEntLast) != 0;
+        const uint32_t w = last ? (pk >> 13) & kLocalNone : spare_row;
+        D[w * Lc + col] = e;
+        rw[j % kPD] = last ? w : kLocalNone;
+        re[j % kPD] = e;
       }
     }
     vp = vp_next;
@@ -318,51 +358,76 @@ __global__ void __launch_bounds__(64)
 k_dist(uint32_t n_blocks, uint32_t n_funcs, uint32_t L, const uint32_t *fbb,
        const uint32_t *func_of_block, const uint32_t *block_begin, const uint32_t *ent_ptr,
        const uint32_t *ent, const uint32_t *ent_w, const uint32_t *ret_ptr, const uint32_t *rent,
-       const uint32_t *rent_w, const uint32_t *out_ptr, const uint4 *q, const uint32_t *ql,
-       uint32_t *e_dmin, uint32_t *e_dmax, uint8_t *e_lat) {
-  extern __shared__ uint32_t D[];   // [2][blocks of the function][L]
+       const uint32_t *rent_w, const uint32_t *rent_e, const uint32_t *rpo_pos,
+       const uint32_t *out_ptr, const uint4 *q, const uint32_t *ql, uint32_t *e_dmin,
+       uint32_t *e_dmax, uint8_t *e_lat) {
+  extern __shared__ uint32_t D[];   // [2][blocks of the function + 1][L + 1]
   const unsigned lane = threadIdx.x;
   const uint32_t c0 = blockIdx.x * L, c1 = min(c0 + L, n_blocks);
   if (c0 >= n_blocks) return;
-  const uint32_t li = lane < L ? lane : 0u;
+  const uint32_t Lc = L + 1;
+  const uint32_t col = lane < L ? lane : L;   // lanes without a source use the spare column
   for (uint32_t f = func_of_block[c0]; f < n_funcs && fbb[f] < c1; ++f) {
     const uint32_t b0 = fbb[f], b1 = fbb[f + 1], nb = b1 - b0;
     const uint32_t g0 = max(c0, b0), g1 = min(c1, b1);
     if (g0 >= g1) continue;
     const uint32_t ea = out_ptr[block_begin[g0]], eb = out_ptr[block_begin[g1]];
     if (ea == eb) continue;
-    uint32_t *Dsp = D, *Dlp = D + (size_t)nb * L;
+    uint32_t *Dsp = D, *Dlp = D + (size_t)(nb + 1) * Lc;
     const uint32_t sb = c0 + lane;
-    const bool writer = lane < L;
-    const bool mine = writer && sb >= g0 && sb < g1 &&
+    const bool mine = lane < L && sb >= g0 && sb < g1 &&
                       out_ptr[block_begin[sb]] < out_ptr[block_begin[sb + 1]];
     const uint32_t s = mine ? sb - b0 : 0xFFFFu;
-    const uint32_t e_begin = ent_ptr[b0], e_end = ent_ptr[b1];
+    const uint32_t e_end = ent_ptr[b1];
     const uint32_t r_begin = ret_ptr[b0], r_end = ret_ptr[b1];
+    // The sweeps cover only what can change: the first shortest-walk sweep
+    // starts at the earliest source (nothing before it is reached without a
+    // retreating edge), a later one at the earliest header whose retreating
+    // edge improved (nothing before it changed); the longest-walk sweep runs
+    // from the earliest source to the last target (G' walks only go forward).
+    uint32_t pmin = mine ? rpo_pos[sb] : 0xFFFFFFFFu;
+    uint32_t tmax = 0;
+    for (uint32_t k = ea + lane; k < eb; k += 64)
+      tmax = max(tmax, rpo_pos[b0 + (q[k].y & 0x7FFFFFFFu)]);
+    for (int d = 32; d > 0; d >>= 1) {
+      pmin = min(pmin, (uint32_t)__shfl_xor((int)pmin, d, 64));
+      tmax = max(tmax, (uint32_t)__shfl_xor((int)tmax, d, 64));
+    }
+    const uint32_t e_src_start = ent_ptr[b0 + pmin];
+    const uint32_t e_lp_end = ent_ptr[b0 + tmax + 1];
     // shortest walks
     __syncthreads();
-    for (uint32_t k = lane; k < nb * L; k += 64) Dsp[k] = kInf;
+    for (uint32_t k = lane; k < (nb + 1) * Lc; k += 64) {
+      Dsp[k] = kInf;
+      Dlp[k] = 0u;
+    }
     __syncthreads();
+    uint32_t start = e_src_start;
     for (uint32_t sweep = 0; sweep <= nb; ++sweep) {
-      dist_sweep<false>(Dsp, L, li, writer, s, ent, ent_w, e_begin, e_end);
-      bool changed = false;
+      dist_sweep<false>(Dsp, Lc, col, s, nb, ent, ent_w, start, e_end);
+      uint32_t restart = 0xFFFFFFFFu;
       for (uint32_t base = r_begin; base < r_end; base += 64) {
         const uint32_t idx = base + lane;
         const uint32_t rp = idx < r_end ? rent[idx] : kLocalNone;
         const uint32_t rw = idx < r_end ? rent_w[idx] : 0u;
+        const uint32_t re = idx < r_end ? rent_e[idx] : 0u;
         const uint32_t cnt = min(64u, r_end - base);
         for (uint32_t i = 0; i < cnt; ++i) {
           const uint32_t pk = __builtin_amdgcn_readlane(rp, i);
           const uint32_t u = pk & kLocalNone, h = (pk >> 13) & kLocalNone;
-          const uint32_t cu = (u == s) ? 0u : Dsp[u * L + li];
+          const uint32_t cu = (u == s) ? 0u : Dsp[u * Lc + col];
           const uint32_t bh = __builtin_amdgcn_readlane(rw, i);
-          if (mine && cu != kInf && cu + bh < Dsp[h * L + li]) changed = true;
+          if (mine && cu != kInf && cu + bh < Dsp[h * Lc + col])
+            restart = min(restart, __builtin_amdgcn_readlane(re, i));
         }
       }
-      if (__ballot(changed) == 0) break;
+      for (int d = 32; d > 0; d >>= 1)
+        restart = min(restart, (uint32_t)__shfl_xor((int)restart, d, 64));
+      if (restart == 0xFFFFFFFFu) break;
+      start = restart;
     }
     // longest G' walks; every block is written before any later block reads it
-    dist_sweep<true>(Dlp, L, li, writer, s, ent, ent_w, e_begin, e_end);
+    dist_sweep<true>(Dlp, Lc, col, s, nb, ent, ent_w, e_src_start, e_lp_end);
     __syncthreads();
     for (uint32_t k = ea + lane; k < eb; k += 64) {
       const uint4 r = q[k];
@@ -373,10 +438,10 @@ k_dist(uint32_t n_blocks, uint32_t n_funcs, uint32_t L, const uint32_t *fbb,
       if (r.y & 0x80000000u) {
         dmin = dmax = r.z;
       } else {
-        const uint32_t Es = Dsp[t * L + sl];
-        const int32_t El = (int32_t)Dlp[t * L + sl];
+        const uint32_t Es = Dsp[t * Lc + sl];
+        const uint32_t El = Dlp[t * Lc + sl];   // longest walk + 1, 0: none
         dmin = (Es == kInf) ? kInf : Es + r.z;
-        dmax = (r.w - b0 != t && El >= 0) ? (uint32_t)El + r.z : dmin;
+        dmax = (r.w - b0 != t && El != 0) ? (El - 1) + r.z : dmin;
       }
       e_dmin[r.x] = dmin;
       e_dmax[r.x] = dmax;
@@ -393,7 +458,7 @@ void build_cfg_order(gpa_program &p, hipStream_t s, Arena &ar, SweepPlan &plan,
   p.retreat.alloc(p.n_succ);
   p.rpo_pos.alloc(nb);
   p.rpo_order.alloc(nb);
-  const size_t lds_dfs = 28u * (size_t)max_nb + 2u * max_nb + 3u * (size_t)max_ne + 16;
+  const size_t lds_dfs = 33u * (size_t)max_nb + 3u * (size_t)max_ne + 16;
   if (lds_dfs > 160 * 1024)
     fail(GPA_E_UNSUPPORTED, "a function's CFG (%u blocks, %u edges) exceeds the LDS staging",
          max_nb, max_ne);
@@ -401,7 +466,7 @@ void build_cfg_order(gpa_program &p, hipStream_t s, Arena &ar, SweepPlan &plan,
                               (int)lds_dfs));
   t_dfs.begin(kPhaseDfs, s);
   hipLaunchKernelGGL(k_dfs, dim3(nf), dim3(64), lds_dfs, s, p.func_block_begin.p, p.succ_ptr.p,
-                     p.succ.p, p.retreat.p, p.rpo_pos.p, p.rpo_order.p);
+                     p.succ.p, p.pred_ptr.p, p.pred.p, p.retreat.p, p.rpo_pos.p, p.rpo_order.p);
   GPA_LAUNCH_CHECK();
   t_dfs.end(s);
   // sweep streams
@@ -413,6 +478,7 @@ void build_cfg_order(gpa_program &p, hipStream_t s, Arena &ar, SweepPlan &plan,
   plan.ent_w = ar.get<uint32_t>(n_ent);
   plan.rent = ar.get<uint32_t>(p.n_succ ? p.n_succ : 1);
   plan.rent_w = ar.get<uint32_t>(p.n_succ ? p.n_succ : 1);
+  plan.rent_e = ar.get<uint32_t>(p.n_succ ? p.n_succ : 1);
   const uint32_t g = grid_for(nb, 256, 4096);
   hipLaunchKernelGGL(k_sweep_count, dim3(g), dim3(256), 0, s, nb, p.func_block_begin.p,
                      p.func_of_block.p, p.pred_ptr.p, p.pred.p, p.rpo_pos.p, cnt, rcnt);
@@ -421,7 +487,8 @@ void build_cfg_order(gpa_program &p, hipStream_t s, Arena &ar, SweepPlan &plan,
   exclusive_scan_u32(rcnt, plan.ret_ptr, (size_t)nb + 1, s, ar);
   hipLaunchKernelGGL(k_sweep_fill, dim3(g), dim3(256), 0, s, nb, p.func_block_begin.p,
                      p.func_of_block.p, p.block_begin.p, p.pred_ptr.p, p.pred.p, p.rpo_pos.p,
-                     plan.ent_ptr, plan.ret_ptr, plan.ent, plan.ent_w, plan.rent, plan.rent_w);
+                     plan.ent_ptr, plan.ret_ptr, plan.ent, plan.ent_w, plan.rent, plan.rent_w,
+                     plan.rent_e);
   GPA_LAUNCH_CHECK();
 }
 
@@ -441,15 +508,16 @@ void build_distances(gpa_program &p, hipStream_t s, Arena &ar, const SweepPlan &
                      p.out_perm.p, p.e_src.p, p.e_dst.p, p.block_of.p, p.func_of_block.p,
                      p.func_block_begin.p, p.block_begin.p, p.op_class.p, lat, q, ql);
   GPA_LAUNCH_CHECK();
-  const uint32_t L =
-      std::max<uint32_t>(1u, std::min<uint32_t>(64u, kDistLds / (8u * max_nb)));
-  const size_t lds = (size_t)8 * L * max_nb;
+  // two tables of (blocks + 1) x (L + 1) words
+  const uint32_t L = std::max<uint32_t>(
+      1u, std::min<uint32_t>(63u, kDistLds / (8u * (max_nb + 1)) - 1u));
+  const size_t lds = (size_t)8 * (L + 1) * (max_nb + 1);
   GPA_HIP(hipFuncSetAttribute((const void *)k_dist, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds));
   hipLaunchKernelGGL(k_dist, dim3((nb + L - 1) / L), dim3(64), lds, s, nb, nf, L,
                      p.func_block_begin.p, p.func_of_block.p, p.block_begin.p, plan.ent_ptr,
-                     plan.ent, plan.ent_w, plan.ret_ptr, plan.rent, plan.rent_w, p.out_ptr.p, q, ql,
-                     p.e_dmin.p, p.e_dmax.p, e_lat);
+                     plan.ent, plan.ent_w, plan.ret_ptr, plan.rent, plan.rent_w, plan.rent_e,
+                     p.rpo_pos.p, p.out_ptr.p, q, ql, p.e_dmin.p, p.e_dmax.p, e_lat);
   GPA_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_merge_lat, dim3(grid_for(ne, 256, 8192)), dim3(256), 0, s, ne, e_lat,
                      p.e_flags.p);
@@ -501,7 +569,6 @@ void build_scope_targets(gpa_program &p, hipStream_t s, Arena &ar) {
   GPA_LAUNCH_CHECK();
   group_by_key(p.e_lca.p, ne, p.n_scopes, p.lca_ptr, p.lca_perm, s, ar);
   group_by_key(p.e_icl.p, ne, p.n_scopes, p.icl_ptr, p.icl_perm, s, ar);
-  p.n_icl = read_scalar(p.icl_ptr.p + p.n_scopes, s);
   group_by_key(p.instr_scope.p, p.n_instr, p.n_scopes, p.line_ptr, p.line_perm, s, ar);
   const uint32_t ns = p.n_scopes;
   p.big_list.alloc((size_t)4 * ns);

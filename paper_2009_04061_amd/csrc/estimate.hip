@@ -74,9 +74,13 @@ __global__ void k_edge_contrib(uint64_t n_edges, uint32_t nbl, int s_mem, int s_
   }
 }
 
-// values gathered into group order, so every group is a contiguous range
+// values gathered into group order, so every group is a contiguous range;
+// the grouped count is n, or *n_dev when given (items without a group are
+// left out of the grouping)
 template <int W>
-__global__ void k_gather(size_t n, const uint32_t *perm, const double *src, double *dst) {
+__global__ void k_gather(size_t n, const uint32_t *n_dev, const uint32_t *perm, const double *src,
+                         double *dst) {
+  if (n_dev) n = min(n, (size_t)*n_dev);
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
        k += (size_t)gridDim.x * blockDim.x) {
     const double *x = src + (size_t)perm[k] * W;
@@ -407,7 +411,7 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint3
   hipLaunchKernelGGL(k_instr_contrib, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, nbl, bl,
                      b.counts.p, b.blamed.p, b.self_.p, p.op_class.p, p.instr_tags.p, iv);
   hipLaunchKernelGGL(k_gather<kNV>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, (size_t)n,
-                     p.line_perm.p, iv, iv_g);
+                     nullptr, p.line_perm.p, iv, iv_g);
   const uint32_t *big = p.big_list.p;
   seg_sum<kNV>(ns, p.line_ptr.p, nullptr, big, p.big_n.p, iv_g, own, s);
   if (p.n_edges) {
@@ -415,9 +419,9 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint3
                        p.n_edges, nbl, s_mem, s_exec, p.e_src.p, p.op_class.p, b.share.p, ev);
     // edges without a common loop are not in the icl grouping: its size is icl_ptr[ns]
     hipLaunchKernelGGL(k_gather<1>, dim3(grid_for(p.n_edges, 256, 8192)), dim3(256), 0, s,
-                       (size_t)p.n_icl, p.icl_perm.p, ev, ev_icl);
+                       (size_t)p.n_edges, p.icl_ptr.p + ns, p.icl_perm.p, ev, ev_icl);
     hipLaunchKernelGGL(k_gather<1>, dim3(grid_for(p.n_edges, 256, 8192)), dim3(256), 0, s,
-                       (size_t)p.n_edges, p.lca_perm.p, ev, ev_lca);
+                       (size_t)p.n_edges, nullptr, p.lca_perm.p, ev, ev_lca);
   }
   seg_sum<1>(ns, p.icl_ptr.p, nullptr, big + ns, p.big_n.p + 1, ev_icl, own_icl, s);
   seg_sum<1>(ns, p.lca_ptr.p, nullptr, big + 2 * (size_t)ns, p.big_n.p + 2, ev_lca, own_lca, s);

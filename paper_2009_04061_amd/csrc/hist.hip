@@ -4,15 +4,16 @@
 // and Zipf-distributed PCs serialize them on hot bins, so the histogram is
 // built by partitioning the records into buckets of kBucketPCs consecutive
 // PCs whose 512 x 24 bins fit in LDS, reading the records once:
-//   k_hsample     every kSampleStride-th tile: bucket sizes, scaled up, give
-//                 each bucket a region of the payload array (capacity with
-//                 head-room and slack; k_hregions lays them out);
+//   k_hsample     every kSampleStride-th slice of records: bucket sizes, scaled up, give
+//                 each bucket kSubs sub-regions of the payload array (capacity
+//                 with head-room and slack; k_hregions lays them out);
 //   k_partition   per tile of kTile records: an LDS counting sort by bucket,
-//                 one device atomic per (tile, bucket) reserving room in the
-//                 bucket's region, and the runs written as 2-byte payloads
+//                 one device atomic per (tile, bucket) reserving room in one
+//                 of the bucket's sub-regions, and the runs written as 2-byte payloads
 //                 (pc offset in bucket, stall, latency bit); a run that does
 //                 not fit goes to an overflow area as 4-byte keys;
-//   k_count       per work item (a contiguous range of one bucket's region):
+//   k_count       per work item (a range of one bucket's filled sub-regions,
+//                 taken end to end):
 //                 LDS histogram of the bucket's bins, written once to the
 //                 output (whole bucket) or to a partial slot;
 //   k_merge       per split bucket: sum of its partial slots;
@@ -26,7 +27,7 @@
 namespace gpa {
 
 constexpr int kHistThreads = 256;
-constexpr int kTile = 16384;                    // records per tile
+constexpr int kTile = 8192;                     // records per tile
 constexpr int kBatch = 16;                      // records per thread per batch (8 x 16 B loads)
 constexpr int kBatches = kTile / (kHistThreads * kBatch);
 constexpr int kBucketShift = 9;
@@ -34,10 +35,18 @@ constexpr int kBucketPCs = 1 << kBucketShift;   // 512 PCs -> 12288 bins = 48 Ki
 constexpr int kBucketBins = kBucketPCs * 24;
 constexpr int kMaxBuckets = 8192;
 constexpr uint32_t kItemRecords = 1u << 17;     // records per counting work item
-constexpr uint32_t kSampleStride = 32;          // one sampled tile in this many
-constexpr uint32_t kBucketSlack = 4 * kTile;    // region slack per bucket, records
+constexpr uint32_t kSampleStride = 32;          // one sampled slice in this many
+constexpr uint32_t kSampleSlice = 512;          // records per sampled slice
+constexpr int kCountThreads = 1024;
+// Each bucket's region is split into kSubs sub-regions, tile t reserving in
+// sub-region t % kSubs, so that no cursor takes more than 1/kSubs of the
+// tiles' device atomics; cursors sit kCursorStride words apart (one line each).
+constexpr uint32_t kSubs = 8;
+constexpr uint32_t kCursorStride = 32;
+constexpr uint32_t kSubSlack = kTile;           // region slack per sub-region, records
 
 typedef unsigned long u64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 struct TileTotals {
   uint32_t valid, latency, dropped, pad;
@@ -50,15 +59,16 @@ __device__ __forceinline__ bool rec_valid(uint64_t r, uint32_t n_instr) {
 
 // The tile's records in batches of kBatch per thread: record q of a batch
 // sits at local index bt*4096 + (q/2)*512 + 2*tid + (q&1); two records per
-// 16-byte load, 1 KiB contiguous per wave instruction.
-template <bool VEC>
+// 16-byte load, 1 KiB contiguous per wave instruction.  FULL: the whole tile
+// is in range and 16-byte aligned; otherwise every record is bounds-checked.
+template <bool FULL>
 __device__ __forceinline__ void load_batch(const uint64_t *__restrict__ rec, uint64_t n,
                                            uint64_t base, int bt, uint64_t (&v)[kBatch]) {
   const unsigned tid = threadIdx.x;
 #pragma unroll
   for (int j = 0; j < kBatch / 2; ++j) {
     const uint64_t idx = base + (uint64_t)bt * 4096 + (uint64_t)j * 512 + 2 * tid;
-    if (VEC && idx + 1 < n) {
+    if (FULL) {
       const u64x2 x = __builtin_nontemporal_load((const u64x2 *)(rec + idx));
       v[2 * j] = x.x;
       v[2 * j + 1] = x.y;
@@ -73,32 +83,39 @@ __device__ __forceinline__ uint32_t local_index(int bt, int q) {
   return (uint32_t)bt * 4096u + (uint32_t)(q / 2) * 512u + 2u * threadIdx.x + (uint32_t)(q & 1);
 }
 
-// bucket sizes of every kSampleStride-th tile, added into est[]
-template <bool VEC>
+// where record (bt, q) of a thread is parked in LDS before the sort: any
+// one-to-one map onto [0, kTile) serves; consecutive lanes take consecutive
+// words, so the parking stores and loads are free of bank conflicts
+__device__ __forceinline__ uint32_t park_index(int bt, int q) {
+  return (uint32_t)(bt * kBatch + q) * kHistThreads + threadIdx.x;
+}
+
+// bucket sizes of every kSampleStride-th slice of kSampleSlice records
+// (two records per thread), added into the workgroup's copy of est[] (one of
+// kSubs copies, kCursorStride words apart, so that the atomics spread)
 __global__ void __launch_bounds__(kHistThreads)
 k_hsample(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint32_t n_buckets,
           uint32_t *__restrict__ est) {
   extern __shared__ uint32_t cnt[];   // [n_buckets]
   const unsigned tid = threadIdx.x;
-  const uint64_t base = (uint64_t)blockIdx.x * kSampleStride * kTile;
+  const uint64_t base = (uint64_t)blockIdx.x * kSampleStride * kSampleSlice;
   for (uint32_t b = tid; b < n_buckets; b += kHistThreads) cnt[b] = 0;
   __syncthreads();
 #pragma unroll
-  for (int bt = 0; bt < kBatches; ++bt) {
-    uint64_t v[kBatch];
-    load_batch<VEC>(rec, n, base, bt, v);
-#pragma unroll
-    for (int q = 0; q < kBatch; ++q)
-      if (base + local_index(bt, q) < n && rec_valid(v[q], n_instr))
-        atomicAdd(&cnt[(uint32_t)v[q] >> kBucketShift], 1u);
+  for (int q = 0; q < 2; ++q) {
+    const uint64_t i = base + 2 * tid + q;
+    if (i < n) {
+      const uint64_t v = rec[i];
+      if (rec_valid(v, n_instr)) atomicAdd(&cnt[(uint32_t)v >> kBucketShift], 1u);
+    }
   }
   __syncthreads();
   for (uint32_t b = tid; b < n_buckets; b += kHistThreads)
-    if (cnt[b]) atomicAdd(&est[b], cnt[b]);
+    if (cnt[b]) atomicAdd(&est[(b * kSubs + blockIdx.x % kSubs) * kCursorStride], cnt[b]);
 }
 
-// regions: capacity = estimate * 5/4 + slack per bucket, laid out in bucket
-// order by one workgroup; cursors start at zero
+// sub-regions: capacity = estimate / kSubs * 5/4 + slack, laid out in
+// (bucket, sub-region) order by one workgroup; cursors start at zero
 __global__ void __launch_bounds__(kHistThreads)
 k_hregions(uint32_t n_buckets, const uint32_t *__restrict__ est, uint32_t *__restrict__ cap,
            uint32_t *__restrict__ region, uint32_t *__restrict__ cursor) {
@@ -107,18 +124,26 @@ k_hregions(uint32_t n_buckets, const uint32_t *__restrict__ est, uint32_t *__res
   const uint32_t b0 = min(threadIdx.x * per, n_buckets), b1 = min(b0 + per, n_buckets);
   uint32_t sum = 0;
   for (uint32_t b = b0; b < b1; ++b) {
-    const uint64_t e = (uint64_t)est[b] * kSampleStride;
-    const uint32_t c = (uint32_t)min<uint64_t>(e + e / 4 + kBucketSlack, 0x40000000ull);
-    cap[b] = c;
-    sum += c;
+    uint64_t e = 0;
+    for (uint32_t u = 0; u < kSubs; ++u) e += est[(b * kSubs + u) * kCursorStride];
+    e = e * kSampleStride / kSubs;
+    const uint32_t c = (uint32_t)min<uint64_t>(e + e / 4 + kSubSlack, 0x10000000ull);
+    for (uint32_t u = 0; u < kSubs; ++u) cap[b * kSubs + u] = c;
+    sum += c * kSubs;
   }
   uint32_t total;
   uint32_t run = block_excl_scan<kHistThreads>(sum, tmp, &total);
-  for (uint32_t b = b0; b < b1; ++b) {
-    region[b] = run;
-    run += cap[b];
-    cursor[b] = 0;
-  }
+  for (uint32_t b = b0; b < b1; ++b)
+    for (uint32_t u = 0; u < kSubs; ++u) {
+      region[b * kSubs + u] = run;
+      run += cap[b * kSubs + u];
+      cursor[(b * kSubs + u) * kCursorStride] = 0;
+    }
+}
+
+// LDS words k_partition needs beyond its static arrays
+__host__ __device__ constexpr size_t partition_lds_words(uint32_t n_buckets) {
+  return 2 * (size_t)n_buckets + 2 + kTile + kWave;
 }
 
 template <bool VEC>
@@ -129,60 +154,75 @@ k_partition(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint
             uint32_t *__restrict__ ov_keys, uint32_t *__restrict__ ov_count,
             TileTotals *__restrict__ tile_tot) {
   extern __shared__ uint32_t smem[];
-  uint32_t *cnt = smem;                                   // [n_buckets + 1]
-  uint32_t *dst = cnt + n_buckets + 1;                    // [n_buckets] where each run goes
-  uint32_t *staged = dst + n_buckets;                     // [kTile]: bucket << 16 | payload
+  // cnt: one counter per bucket, then two sink counters: records that fail
+  // validation (bucket n_buckets) and records past the end (n_buckets + 1)
+  uint32_t *cnt = smem;                                   // [n_buckets + 2]
+  uint32_t *dst = cnt + n_buckets + 2;                    // [n_buckets] run destination - run start
+  uint32_t *staged = dst + n_buckets;                     // [kTile + kWave], tail = sink slots
   __shared__ uint32_t scan_tmp[kHistThreads / kWave + 1];
-  __shared__ uint32_t red[3];
+  __shared__ uint32_t s_lat, s_ovf, s_total;
   const unsigned tid = threadIdx.x;
   const uint64_t base = (uint64_t)blockIdx.x * kTile;
-  for (uint32_t b = tid; b <= n_buckets; b += kHistThreads) cnt[b] = 0;
-  if (tid < 3) red[tid] = 0;
+  const uint32_t lim = (uint32_t)min<uint64_t>(n - base, (uint64_t)kTile);
+  for (uint32_t b = tid; b < n_buckets + 2; b += kHistThreads) cnt[b] = 0;
+  if (tid == 0) {
+    s_lat = 0;
+    s_ovf = 0;
+  }
   __syncthreads();
+  // every load of the tile is issued before any record is ranked
+  uint64_t vb[kBatches][kBatch];
+  if (VEC && lim == (uint32_t)kTile) {
+#pragma unroll
+    for (int bt = 0; bt < kBatches; ++bt) load_batch<true>(rec, n, base, bt, vb[bt]);
+  } else {
+#pragma unroll
+    for (int bt = 0; bt < kBatches; ++bt) load_batch<false>(rec, n, base, bt, vb[bt]);
+  }
+  // rank of each record within its bucket (or sink); branch-free per record
   uint32_t rank[kTile / kHistThreads];
-  uint32_t my_lat = 0, my_drop = 0;
+  uint32_t my_lat = 0;
 #pragma unroll
   for (int bt = 0; bt < kBatches; ++bt) {
-    uint64_t v[kBatch];
-    load_batch<VEC>(rec, n, base, bt, v);
 #pragma unroll
     for (int q = 0; q < kBatch; ++q) {
-      uint32_t rk = 0xFFFFFFFFu;
-      if (base + local_index(bt, q) < n) {
-        if (rec_valid(v[q], n_instr)) {
-          const uint32_t pc = (uint32_t)v[q], hi = (uint32_t)(v[q] >> 32);
-          const uint32_t b = pc >> kBucketShift;
-          const uint32_t pl = ((pc & (kBucketPCs - 1)) << 5) | ((hi & 0xFFu) * 2u + ((hi >> 8) & 1u));
-          rk = (b << 16) | atomicAdd(&cnt[b], 1u);
-          staged[local_index(bt, q)] = pl;   // parked; moved to its sorted slot below
-          my_lat += (hi >> 8) & 1u;
-        } else {
-          ++my_drop;
-        }
-      }
-      rank[bt * kBatch + q] = rk;
+      const uint64_t r = vb[bt][q];
+      const uint32_t pc = (uint32_t)r, hi = (uint32_t)(r >> 32);
+      const bool in = local_index(bt, q) < lim;
+      const bool ok = in & rec_valid(r, n_instr);
+      const uint32_t b = ok ? (pc >> kBucketShift) : (in ? n_buckets : n_buckets + 1);
+      rank[bt * kBatch + q] = (b << 16) | atomicAdd(&cnt[b], 1u);
+      // parked; moved to its sorted slot below
+      staged[park_index(bt, q)] = ((pc & (kBucketPCs - 1)) << 5) | ((hi & 0xFFu) * 2u + ((hi >> 8) & 1u));
+      my_lat += ok ? (hi >> 8) & 1u : 0u;
     }
   }
   my_lat = wave_sum(my_lat);
-  my_drop = wave_sum(my_drop);
-  if (lane_id() == 0) {
-    atomicAdd(&red[1], my_lat);
-    atomicAdd(&red[2], my_drop);
-  }
+  if (lane_id() == 0) atomicAdd(&s_lat, my_lat);
   __syncthreads();
-  // room for each run: a device atomic per non-empty bucket of the tile
+  // room for each run: a device atomic per non-empty bucket of the tile, in
+  // the tile's sub-region of the bucket
+  const uint32_t sub = blockIdx.x % kSubs;
+  uint32_t any_ovf = 0;
   for (uint32_t b = tid; b < n_buckets; b += kHistThreads) {
     const uint32_t c = cnt[b];
     uint32_t d = 0;
     if (c) {
-      const uint32_t pos = atomicAdd(&cursor[b], c);
-      if (pos + c <= cap[b]) d = region[b] + pos;
-      else d = 0x80000000u | atomicAdd(ov_count, c);   // overflow area, 4-byte keys
+      const uint32_t slot = b * kSubs + sub;
+      const uint32_t pos = atomicAdd(&cursor[slot * kCursorStride], c);
+      if (pos + c <= cap[slot]) {
+        d = region[slot] + pos;
+      } else {
+        d = 0x80000000u | atomicAdd(ov_count, c);   // overflow area, 4-byte keys
+        any_ovf = 1;
+      }
     }
     dst[b] = d;
   }
-  __syncthreads();
-  // exclusive scan of the bucket counts
+  if (any_ovf) s_ovf = 1;
+  __syncthreads();   // the scan below rewrites cnt[] and dst[] of other threads' buckets
+  // exclusive scan of the bucket counts; dst[] becomes destination minus
+  // run start, so that tile slot k of bucket b goes to dst[b] + k
   {
     const uint32_t per = (n_buckets + kHistThreads - 1) / kHistThreads;
     const uint32_t b0 = min(tid * per, n_buckets), b1 = min(b0 + per, n_buckets);
@@ -193,41 +233,57 @@ k_partition(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint
     for (uint32_t b = b0; b < b1; ++b) {
       const uint32_t c = cnt[b];
       cnt[b] = run;
+      dst[b] -= run;
       run += c;
     }
-    if (tid == 0) cnt[n_buckets] = total;
+    if (tid == 0) s_total = total;
   }
   __syncthreads();
   // move every parked payload to its sorted slot; parked and sorted slots
-  // share [0, kTile), so every parked value is read before any is moved
+  // share [0, kTile), so every parked value is read before any is moved;
+  // sink records go to the spare slots past kTile
   uint32_t val[kTile / kHistThreads];
 #pragma unroll
   for (int bt = 0; bt < kBatches; ++bt)
 #pragma unroll
-    for (int q = 0; q < kBatch; ++q)
-      val[bt * kBatch + q] = (rank[bt * kBatch + q] != 0xFFFFFFFFu) ? staged[local_index(bt, q)] : 0u;
+    for (int q = 0; q < kBatch; ++q) val[bt * kBatch + q] = staged[park_index(bt, q)];
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kTile / kHistThreads; ++k) {
-    if (rank[k] != 0xFFFFFFFFu) {
-      const uint32_t b = rank[k] >> 16;
-      staged[cnt[b] + (rank[k] & 0xFFFFu)] = (b << 16) | val[k];
-    }
+    const uint32_t b = rank[k] >> 16;
+    const uint32_t slot = b < n_buckets ? cnt[b] + (rank[k] & 0xFFFFu) : (uint32_t)kTile + lane_id();
+    staged[slot] = (b << 16) | val[k];
   }
   __syncthreads();
-  const uint32_t nvalid = cnt[n_buckets];
-  for (uint32_t k = tid; k < nvalid; k += kHistThreads) {
-    const uint32_t x = staged[k];
-    const uint32_t b = x >> 16;
-    const uint32_t d = dst[b];
-    if (!(d & 0x80000000u)) payload[d + (k - cnt[b])] = (uint16_t)x;
-    else ov_keys[(d & 0x7FFFFFFFu) + (k - cnt[b])] = x;
+  const uint32_t nvalid = s_total;
+  if (!s_ovf) {
+    uint32_t k = tid;
+    for (; k + 3 * kHistThreads < nvalid; k += 4 * kHistThreads) {
+      const uint32_t x0 = staged[k], x1 = staged[k + kHistThreads];
+      const uint32_t x2 = staged[k + 2 * kHistThreads], x3 = staged[k + 3 * kHistThreads];
+      payload[dst[x0 >> 16] + k] = (uint16_t)x0;
+      payload[dst[x1 >> 16] + k + kHistThreads] = (uint16_t)x1;
+      payload[dst[x2 >> 16] + k + 2 * kHistThreads] = (uint16_t)x2;
+      payload[dst[x3 >> 16] + k + 3 * kHistThreads] = (uint16_t)x3;
+    }
+    for (; k < nvalid; k += kHistThreads) {
+      const uint32_t x = staged[k];
+      payload[dst[x >> 16] + k] = (uint16_t)x;
+    }
+  } else {
+    for (uint32_t k = tid; k < nvalid; k += kHistThreads) {
+      const uint32_t x = staged[k];
+      const uint32_t b = x >> 16;
+      const uint32_t d = dst[b] + cnt[b];   // the run's destination
+      if (!(d & 0x80000000u)) payload[d + (k - cnt[b])] = (uint16_t)x;
+      else ov_keys[(d & 0x7FFFFFFFu) + (k - cnt[b])] = x;
+    }
   }
   if (tid == 0) {
     TileTotals t;
     t.valid = nvalid;
-    t.latency = red[1];
-    t.dropped = red[2];
+    t.latency = s_lat;
+    t.dropped = cnt[n_buckets];
     t.pad = 0;
     tile_tot[blockIdx.x] = t;
   }
@@ -265,60 +321,130 @@ __global__ void k_hist_totals(const TileTotals *__restrict__ tt, uint32_t n_tile
   }
 }
 
-// per bucket: its start and fill in the payload array, and its work items
-__global__ void k_bucket_plan(uint32_t n_buckets, const uint32_t *region, const uint32_t *cursor,
-                              const uint32_t *cap, uint32_t *bstart, uint32_t *bfill,
-                              uint32_t *items) {
+// per sub-region: how far it is filled; per bucket: the total fill and the
+// number of work items
+__global__ void k_bucket_plan(uint32_t n_buckets, const uint32_t *cursor, const uint32_t *cap,
+                              uint32_t *sfill, uint32_t *bfill, uint32_t *items) {
   for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_buckets;
        b += gridDim.x * blockDim.x) {
-    const uint32_t fill = min(cursor[b], cap[b]);
-    bstart[b] = region[b];
+    uint32_t fill = 0;
+    for (uint32_t u = 0; u < kSubs; ++u) {
+      const uint32_t slot = b * kSubs + u;
+      const uint32_t f = min(cursor[slot * kCursorStride], cap[slot]);
+      sfill[slot] = f;
+      fill += f;
+    }
     bfill[b] = fill;
     const uint32_t r = (fill + kItemRecords - 1) / kItemRecords;
     items[b] = r < 1 ? 1 : r;
   }
 }
 
+// k_count's LDS bins: each 16-lane group of a wave adds into its own copy,
+// so that a hot bin takes at most 16 same-address atomics per instruction;
+// a copy holds the 12288 bins as 16-bit counters, bin k in the low half of
+// word k when k < 6144, else in the high half of word k - 6144 (the two
+// latency bins of a stall reason land in different words); copies start 16
+// banks apart.  A copy receives a quarter of a work item's vector loads plus
+// at most one partial round of them and the unaligned ends per sub-region,
+// which stays below 2^16.
+constexpr uint32_t kCountCopies = 4;
+constexpr uint32_t kHalfWords = kBucketBins / 2;
+constexpr uint32_t kCopyStride = kHalfWords + 16;
+static_assert(kItemRecords / kCountCopies + kSubs * (2 * kCountThreads + 16) < 65536u,
+              "16-bit counters of a copy must not carry");
+
+__device__ __forceinline__ void count_one(uint32_t pl, uint32_t *bins) {
+  const uint32_t k = (pl >> 5) * 24u + (pl & 31u);
+  const bool hi = k >= kHalfWords;
+  atomicAdd(&bins[hi ? k - kHalfWords : k], hi ? 0x10000u : 1u);
+}
+
+__device__ __forceinline__ void count_word(uint32_t w, uint32_t *bins) {
+  count_one(w & 0xFFFFu, bins);
+  count_one(w >> 16, bins);
+}
+
+// payload[q0, q1) into the thread's copy of the bins: the unaligned head and
+// tail one by one, the rest as 16-byte loads (eight payloads), two per
+// thread in flight
+__device__ __forceinline__ void count_range(const uint16_t *__restrict__ payload, uint32_t q0,
+                                            uint32_t q1, uint32_t *bins) {
+  const uint32_t a = min(q1, (q0 + 7u) & ~7u);
+  const uint32_t z = max(a, q1 & ~7u);
+  for (uint32_t q = q0 + threadIdx.x; q < a; q += kCountThreads) count_one(payload[q], bins);
+  for (uint32_t q = z + threadIdx.x; q < q1; q += kCountThreads) count_one(payload[q], bins);
+  const u32x4 *vec = (const u32x4 *)(payload + a);
+  const uint32_t nv = (z - a) / 8u;
+  uint32_t k = threadIdx.x;
+  for (; k + kCountThreads < nv; k += 2 * kCountThreads) {
+    const u32x4 x = __builtin_nontemporal_load(vec + k);
+    const u32x4 y = __builtin_nontemporal_load(vec + k + kCountThreads);
+    count_word(x.x, bins);
+    count_word(x.y, bins);
+    count_word(x.z, bins);
+    count_word(x.w, bins);
+    count_word(y.x, bins);
+    count_word(y.y, bins);
+    count_word(y.z, bins);
+    count_word(y.w, bins);
+  }
+  if (k < nv) {
+    const u32x4 x = __builtin_nontemporal_load(vec + k);
+    count_word(x.x, bins);
+    count_word(x.y, bins);
+    count_word(x.z, bins);
+    count_word(x.w, bins);
+  }
+}
+
 // work item -> (bucket, part) via the prefix of items per bucket
-__global__ void __launch_bounds__(kHistThreads)
-k_count(const uint16_t *__restrict__ payload, const uint32_t *__restrict__ bstart,
-        const uint32_t *__restrict__ bfill, uint32_t n_buckets, uint32_t n_instr,
+__global__ void __launch_bounds__(kCountThreads)
+k_count(const uint16_t *__restrict__ payload, const uint32_t *__restrict__ region,
+        const uint32_t *__restrict__ sfill, const uint32_t *__restrict__ bfill,
+        uint32_t n_buckets, uint32_t n_instr,
         const uint32_t *__restrict__ items, const uint32_t *__restrict__ item_start,
         uint32_t *__restrict__ counts, uint32_t *__restrict__ partial) {
-  __shared__ uint32_t bins[kBucketBins];
+  __shared__ uint32_t bins[kCountCopies * kCopyStride];
   const uint32_t it = blockIdx.x;
   const uint32_t total_items = item_start[n_buckets - 1] + items[n_buckets - 1];
   if (it >= total_items) return;
   const uint32_t b = upper_index_u32(item_start, 0, n_buckets, it);
   const uint32_t parts = items[b], part = it - item_start[b];
-  const uint32_t s0 = bstart[b];
+  // the item's share [q0, q1) of the bucket's sub-regions taken end to end
   const uint32_t fill = bfill[b];
-  const uint32_t q0 = s0 + (uint32_t)((uint64_t)fill * part / parts);
-  const uint32_t q1 = s0 + (uint32_t)((uint64_t)fill * (part + 1) / parts);
-  for (uint32_t k = threadIdx.x; k < kBucketBins; k += kHistThreads) bins[k] = 0;
+  const uint32_t q0 = (uint32_t)((uint64_t)fill * part / parts);
+  const uint32_t q1 = (uint32_t)((uint64_t)fill * (part + 1) / parts);
+  for (uint32_t k = threadIdx.x; k < kCountCopies * kCopyStride; k += kCountThreads) bins[k] = 0;
   __syncthreads();
-  uint32_t q = q0 + threadIdx.x;
-  for (; q + 3 * kHistThreads < q1; q += 4 * kHistThreads) {
-    const uint32_t p0 = payload[q], p1 = payload[q + kHistThreads];
-    const uint32_t p2 = payload[q + 2 * kHistThreads], p3 = payload[q + 3 * kHistThreads];
-    atomicAdd(&bins[(p0 >> 5) * 24u + (p0 & 31u)], 1u);
-    atomicAdd(&bins[(p1 >> 5) * 24u + (p1 & 31u)], 1u);
-    atomicAdd(&bins[(p2 >> 5) * 24u + (p2 & 31u)], 1u);
-    atomicAdd(&bins[(p3 >> 5) * 24u + (p3 & 31u)], 1u);
-  }
-  for (; q < q1; q += kHistThreads) {
-    const uint32_t pl = payload[q];
-    atomicAdd(&bins[(pl >> 5) * 24u + (pl & 31u)], 1u);
+  uint32_t *mine = bins + ((threadIdx.x >> 4) & (kCountCopies - 1)) * kCopyStride;
+  uint32_t v = 0;
+  for (uint32_t u = 0; u < kSubs; ++u) {
+    const uint32_t slot = b * kSubs + u;
+    const uint32_t f = sfill[slot];
+    const uint32_t lo = max(q0, v), hi = min(q1, v + f);
+    if (lo < hi) count_range(payload, region[slot] + (lo - v), region[slot] + (hi - v), mine);
+    v += f;
   }
   __syncthreads();
+  // bin k = sum over the copies of its 16-bit counter
+  uint32_t *dst;
+  uint32_t nbins;
   if (parts == 1) {
     const uint32_t pc0 = b * kBucketPCs;
-    const uint32_t npc = min((uint32_t)kBucketPCs, n_instr - pc0);
-    uint32_t *dst = counts + (size_t)pc0 * 24u;
-    for (uint32_t k = threadIdx.x; k < npc * 24u; k += kHistThreads) dst[k] = bins[k];
+    nbins = min((uint32_t)kBucketPCs, n_instr - pc0) * 24u;
+    dst = counts + (size_t)pc0 * 24u;
   } else {
-    uint32_t *dst = partial + (size_t)it * kBucketBins;
-    for (uint32_t k = threadIdx.x; k < kBucketBins; k += kHistThreads) dst[k] = bins[k];
+    nbins = kBucketBins;
+    dst = partial + (size_t)it * kBucketBins;
+  }
+  for (uint32_t k = threadIdx.x; k < nbins; k += kCountThreads) {
+    const bool hi = k >= kHalfWords;
+    const uint32_t w = hi ? k - kHalfWords : k, sh = hi ? 16u : 0u;
+    uint32_t t = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < kCountCopies; ++c) t += (bins[c * kCopyStride + w] >> sh) & 0xFFFFu;
+    dst[k] = t;
   }
 }
 
@@ -381,31 +507,35 @@ void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint3
   const uint32_t n_tiles = (uint32_t)((n + kTile - 1) / kTile);
   const uint64_t *rec = (const uint64_t *)samples;
   const bool vec = ((uintptr_t)samples % 16) == 0;
-  // bucket regions from a sample of the tiles
-  const uint32_t n_samp = (n_tiles + kSampleStride - 1) / kSampleStride;
-  uint32_t *est = ar.get<uint32_t>(n_buckets), *cap = ar.get<uint32_t>(n_buckets);
-  uint32_t *region = ar.get<uint32_t>(n_buckets), *cursor = ar.get<uint32_t>(n_buckets);
+  // bucket regions from a sample of the records
+  const uint64_t n_samp =
+      (n + (uint64_t)kSampleStride * kSampleSlice - 1) / ((uint64_t)kSampleStride * kSampleSlice);
+  const uint32_t n_slots = n_buckets * kSubs;
+  uint32_t *est = ar.get<uint32_t>((size_t)n_slots * kCursorStride);
+  uint32_t *cap = ar.get<uint32_t>(n_slots);
+  uint32_t *region = ar.get<uint32_t>(n_slots);
+  uint32_t *cursor = ar.get<uint32_t>((size_t)n_slots * kCursorStride);
   uint32_t *ov_count = ar.get<uint32_t>(1);
-  GPA_HIP(hipMemsetAsync(est, 0, 4 * (size_t)n_buckets, s));
+  GPA_HIP(hipMemsetAsync(est, 0, 4 * (size_t)n_slots * kCursorStride, s));
   GPA_HIP(hipMemsetAsync(ov_count, 0, 4, s));
   const size_t lds_count = (size_t)n_buckets * 4;
-  if (vec)
-    hipLaunchKernelGGL(k_hsample<true>, dim3(n_samp), dim3(kHistThreads), lds_count, s, rec, n,
-                       n_instr, n_buckets, est);
-  else
-    hipLaunchKernelGGL(k_hsample<false>, dim3(n_samp), dim3(kHistThreads), lds_count, s, rec, n,
-                       n_instr, n_buckets, est);
+  hipLaunchKernelGGL(k_hsample, dim3((unsigned)n_samp), dim3(kHistThreads), lds_count, s, rec, n,
+                     n_instr, n_buckets, est);
   GPA_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_hregions, dim3(1), dim3(kHistThreads), 0, s, n_buckets, est, cap, region,
                      cursor);
   GPA_LAUNCH_CHECK();
-  // the regions hold at most 5/4 of the scaled sample plus the slack
-  const uint64_t max_region = (uint64_t)n_samp * kTile * kSampleStride * 5 / 4 +
-                              (uint64_t)n_buckets * (kBucketSlack + 1);
+  // the sub-regions hold at most 5/4 of the scaled sample plus the slack;
+  // payload offsets stay below 2^31 (bit 31 marks the overflow area)
+  const uint64_t max_region = n_samp * kSampleSlice * kSampleStride * 5 / 4 +
+                              (uint64_t)n_slots * (kSubSlack + 1);
+  if (max_region >= 0x80000000ull)
+    fail(GPA_E_UNSUPPORTED, "histogram payload of %llu records exceeds 2^31",
+         (unsigned long long)max_region);
   uint16_t *payload = ar.get<uint16_t>(max_region);
   uint32_t *ov_keys = ar.get<uint32_t>(n);
   TileTotals *tt = ar.get<TileTotals>(n_tiles);
-  const size_t lds_part = (2 * (size_t)n_buckets + 1) * 4 + (size_t)kTile * 4;
+  const size_t lds_part = partition_lds_words(n_buckets) * 4;
   if (vec) {
     GPA_HIP(hipFuncSetAttribute((const void *)k_partition<true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_part));
@@ -419,24 +549,23 @@ void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint3
   }
   GPA_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_hist_totals, dim3(1), dim3(kHistThreads), 0, s, tt, n_tiles, totals);
-  uint32_t *bstart = ar.get<uint32_t>(n_buckets), *bfill = ar.get<uint32_t>(n_buckets);
+  uint32_t *sfill = ar.get<uint32_t>(n_slots), *bfill = ar.get<uint32_t>(n_buckets);
   uint32_t *items = ar.get<uint32_t>(n_buckets);
   uint32_t *item_start = ar.get<uint32_t>(n_buckets);
   hipLaunchKernelGGL(k_bucket_plan, dim3(grid_for(n_buckets, 256, 64)), dim3(256), 0, s,
-                     n_buckets, region, cursor, cap, bstart, bfill, items);
+                     n_buckets, cursor, cap, sfill, bfill, items);
   GPA_LAUNCH_CHECK();
   exclusive_scan_u32(items, item_start, n_buckets, s, ar);
   // items <= one per bucket plus one per kItemRecords records
   const uint64_t max_items = n_buckets + n / kItemRecords + 1;
   uint32_t *partial = ar.get<uint32_t>((size_t)max_items * kBucketBins);
-  hipLaunchKernelGGL(k_count, dim3((unsigned)max_items), dim3(kHistThreads), 0, s, payload, bstart,
-                     bfill, n_buckets, n_instr, items, item_start, counts, partial);
+  hipLaunchKernelGGL(k_count, dim3((unsigned)max_items), dim3(kCountThreads), 0, s, payload, region,
+                     sfill, bfill, n_buckets, n_instr, items, item_start, counts, partial);
   GPA_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_merge, dim3(n_buckets, kBucketBins / kHistThreads), dim3(kHistThreads), 0,
                      s, partial, items, item_start, n_instr, counts);
   GPA_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_hoverflow, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, ov_keys, ov_count,
-                     counts);
+  hipLaunchKernelGGL(k_hoverflow, dim3(256), dim3(256), 0, s, ov_keys, ov_count, counts);
   GPA_LAUNCH_CHECK();
 }
 

@@ -245,8 +245,10 @@ __global__ void k_chunk_fill(uint32_t n_funcs, const uint32_t *fbb, const uint32
 
 // per chunk, the number of sites of each location
 __global__ void __launch_bounds__(kSortThreads)
-k_chunk_hist(const SiteChunk *chunks, const uint32_t *key, uint32_t n_loc, uint32_t *chunk_cnt) {
+k_chunk_hist(const SiteChunk *chunks, const unsigned long long *n_chunks, const uint32_t *key,
+             uint32_t n_loc, uint32_t *chunk_cnt) {
   extern __shared__ uint32_t cnt[];
+  if (blockIdx.x >= *n_chunks) return;
   const SiteChunk ch = chunks[blockIdx.x];
   for (uint32_t x = threadIdx.x; x < n_loc; x += kSortThreads) cnt[x] = 0;
   __syncthreads();
@@ -294,12 +296,14 @@ k_chunk_bases(uint32_t n_funcs, const uint32_t *fbb, const uint32_t *block_begin
 // site among equal keys of its round comes from ballot matching inside the
 // wave plus per-wave counts in LDS; per-location cursors carry across rounds.
 __global__ void __launch_bounds__(kSortThreads)
-k_chunk_scatter(const SiteChunk *chunks, const uint32_t *key, uint32_t n_loc, uint32_t key_bits,
-                const uint32_t *chunk_base, uint32_t *sorted, uint32_t *rank_of) {
+k_chunk_scatter(const SiteChunk *chunks, const unsigned long long *n_chunks, const uint32_t *key,
+                uint32_t n_loc, uint32_t key_bits, const uint32_t *chunk_base, uint32_t *sorted,
+                uint32_t *rank_of) {
   extern __shared__ uint32_t sh[];
   uint32_t *cursor = sh;                        // [n_loc]
   uint32_t *wcnt = sh + n_loc;                  // [4][n_loc]
   constexpr int NW = kSortThreads / kWave;
+  if (blockIdx.x >= *n_chunks) return;
   const SiteChunk ch = chunks[blockIdx.x];
   const unsigned tid = threadIdx.x, w = tid / kWave, lane = lane_id();
   for (uint32_t x = tid; x < n_loc; x += kSortThreads) {
@@ -445,19 +449,21 @@ static void sort_sites(gpa_program &p, hipStream_t s, Arena &ar, const uint32_t 
                      p.func_block_begin.p, p.block_begin.p, site_ptr, nchunks);
   GPA_LAUNCH_CHECK();
   exclusive_scan_u32(nchunks, cstart, nf, s, ar, ntot);
-  const uint32_t n_chunks = (uint32_t)read_scalar(ntot, s);
+  // chunks <= sites / kChunk + one partial chunk per function; the kernels
+  // read the exact count from device memory
+  const uint32_t n_chunks = (uint32_t)(n_sites / kChunk + nf);
   sorted.alloc(n_sites);
   fl_ptr.alloc((size_t)nf * (nl + 1));
   // the end of every (function, location) list is the start of the next one
   GPA_HIP(hipMemsetAsync(fl_ptr.p, 0, sizeof(uint32_t) * fl_ptr.n, s));
-  if (n_chunks == 0) return;
+  if (n_sites == 0) return;
   SiteChunk *chunks = ar.get<SiteChunk>(n_chunks);
   hipLaunchKernelGGL(k_chunk_fill, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf,
                      p.func_block_begin.p, p.block_begin.p, site_ptr, cstart, chunks);
   GPA_LAUNCH_CHECK();
   uint32_t *ccnt = ar.get<uint32_t>((size_t)n_chunks * nl);
-  hipLaunchKernelGGL(k_chunk_hist, dim3(n_chunks), dim3(kSortThreads), nl * 4, s, chunks, key, nl,
-                     ccnt);
+  hipLaunchKernelGGL(k_chunk_hist, dim3(n_chunks), dim3(kSortThreads), nl * 4, s, chunks, ntot, key,
+                     nl, ccnt);
   GPA_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_chunk_bases, dim3(nf), dim3(kSortThreads), 0, s, nf, p.func_block_begin.p,
                      p.block_begin.p, site_ptr, cstart, nchunks, nl, ccnt, fl_ptr.p);
@@ -465,8 +471,8 @@ static void sort_sites(gpa_program &p, hipStream_t s, Arena &ar, const uint32_t 
   uint32_t key_bits = 1;
   while ((1u << key_bits) < nl) ++key_bits;
   const size_t lds = (size_t)nl * 4 * (1 + kSortThreads / kWave);
-  hipLaunchKernelGGL(k_chunk_scatter, dim3(n_chunks), dim3(kSortThreads), lds, s, chunks, key, nl,
-                     key_bits, ccnt, sorted.p, rank_of);
+  hipLaunchKernelGGL(k_chunk_scatter, dim3(n_chunks), dim3(kSortThreads), lds, s, chunks, ntot, key,
+                     nl, key_bits, ccnt, sorted.p, rank_of);
   GPA_LAUNCH_CHECK();
 }
 
@@ -533,8 +539,7 @@ void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar) {
   hipLaunchKernelGGL(k_max_func_blocks, dim3(grid_for(nf, 256, 1024)), dim3(256), 0, s, nf,
                      p.func_block_begin.p, p.succ_ptr.p, mx);
   GPA_LAUNCH_CHECK();
-  p.max_func_blocks = read_scalar(mx, s);
-  p.max_func_edges = read_scalar(mx + 1, s);
+  read_scalars(mx, p.max_func_blocks, mx + 1, p.max_func_edges, s);
   if (p.max_func_blocks > 4096)
     fail(GPA_E_UNSUPPORTED, "a function has %u blocks; at most 4096 are supported",
          p.max_func_blocks);
