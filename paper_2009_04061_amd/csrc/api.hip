@@ -288,13 +288,17 @@ gpa_status gpa_load_program(const gpa_program_desc *d, void *stream, gpa_program
     PhaseTimer t_load, t_rd, t_dist, t_dfs, t_search;
     t_load.begin(kPhaseLoad, s);
     validate_and_build_structure(*p, s, ar);
-    // the DFS order and the sweep streams need only the CFG: they run on the
-    // side stream while the sites are sorted and the reaching definitions
-    // and edges are built
+    // the DFS order, the sweep streams and the walk tables need only the
+    // CFG: they run on the side stream while the sites are sorted and the
+    // reaching definitions and edges are built
     GPA_HIP(hipEventRecord(ev_struct.e, s));
     GPA_HIP(hipStreamWaitEvent(side, ev_struct.e, 0));
     SweepPlan plan;
+    DistTables tables;
     build_cfg_order(*p, side, ar, plan, t_dfs);
+    t_dist.begin(kPhaseDist, side);
+    build_dist_tables(*p, side, ar, plan, tables);
+    t_dist.end(side);
     GPA_HIP(hipEventRecord(ev_order.e, side));
     build_sites_and_scopes(*p, s, ar);
     t_rd.begin(kPhaseRd, s);
@@ -302,9 +306,7 @@ gpa_status gpa_load_program(const gpa_program_desc *d, void *stream, gpa_program
     build_edges(*p, s, ar);
     t_rd.end(s);
     GPA_HIP(hipStreamWaitEvent(s, ev_order.e, 0));
-    t_dist.begin(kPhaseDist, s);
-    build_distances(*p, s, ar, plan);
-    t_dist.end(s);
+    build_distances(*p, s, ar, tables);
     build_scope_targets(*p, s, ar);
     t_load.end(s);
     GPA_HIP(hipStreamSynchronize(s));

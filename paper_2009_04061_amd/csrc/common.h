@@ -92,6 +92,7 @@ struct gpa_program {
   uint32_t n_regs = 0, n_preds = 0, n_bars = 0, n_loc = 0;
   uint32_t n_defs = 0, n_uses = 0, n_succ = 0;
   uint32_t max_func_blocks = 0, max_func_edges = 0;
+  uint64_t dist_entries = 0;   // sum over functions of (blocks)^2
   gpa_arch arch{};
   uint32_t n_blamable = 0;
   // device copies of the descriptor
@@ -187,7 +188,17 @@ struct SweepPlan {
 };
 void build_cfg_order(gpa_program &p, hipStream_t s, Arena &ar, SweepPlan &plan,
                      PhaseTimer &t_dfs);
-void build_distances(gpa_program &p, hipStream_t s, Arena &ar, const SweepPlan &plan);
+// Block-to-block walk tables of every function (shortest and longest G'
+// walks from each block to each block of its function), from the CFG alone.
+struct DistTables {
+  uint32_t *off = nullptr;   // [n_funcs] first entry of the function's tables
+  uint32_t *sp = nullptr;    // shortest walk lengths, kInf-saturated
+  uint32_t *lp = nullptr;    // longest G' walk lengths + 1, 0 = none
+};
+void build_dist_tables(gpa_program &p, hipStream_t s, Arena &ar, const SweepPlan &plan,
+                       DistTables &t);
+// per edge: dmin, dmax and the latency rule's flag from the tables
+void build_distances(gpa_program &p, hipStream_t s, Arena &ar, const DistTables &t);
 constexpr uint32_t kSmallSeg = 64;   // longest segment one thread sums alone
 void build_scope_targets(gpa_program &p, hipStream_t s, Arena &ar);
 // blame.hip

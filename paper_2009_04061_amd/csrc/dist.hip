@@ -316,53 +316,22 @@ __device__ void dist_sweep(uint32_t *D, uint32_t Lc, uint32_t col, uint32_t s, u
   }
 }
 
-// Per edge, in source order (the order k_dist walks them), everything its
-// distances need besides the table values:
-//   q = (edge, target block (local) | same-block flag << 31, addend, source block)
-// where dmin = addend for a same-block pair with the source first, else
-// table value of the target + addend, with addend = (|B_i| - o_i - 1) + o_j - |B_j|;
-// ql = the latency bound of the source's opcode class.
-__global__ void k_dist_queries(uint64_t n_edges, const uint32_t *out_perm, const uint32_t *e_src,
-                               const uint32_t *e_dst, const uint32_t *block_of,
-                               const uint32_t *func_of_block, const uint32_t *fbb,
-                               const uint32_t *block_begin, const uint8_t *op_class,
-                               const uint16_t *lat_tab, uint4 *q, uint32_t *ql) {
-  for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n_edges;
-       k += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t e = out_perm[k];
-    const uint32_t src = e_src[e], j = e_dst[e];
-    const uint32_t sb = block_of[src], tb = block_of[j];
-    const uint32_t b0 = fbb[func_of_block[sb]];
-    const uint32_t i0 = block_begin[sb], ss = block_begin[sb + 1] - i0;
-    const uint32_t tj0 = block_begin[tb], bt = block_begin[tb + 1] - tj0;
-    const uint32_t oi = src - i0, oj = j - tj0;
-    const bool same = tb == sb && oi < oj;
-    const uint32_t add = same ? oj - oi - 1 : (ss - oi - 1) + oj - bt;   // mod 2^32
-    q[k] = make_uint4(e, (tb - b0) | (same ? 0x80000000u : 0u), add, sb);
-    ql[k] = lat_tab[op_class[src]];
-  }
-}
-
-// the latency rule's bit, set by k_dist beside the other flags
-__global__ void k_merge_lat(uint64_t n_edges, const uint8_t *e_lat, uint8_t *e_flags) {
-  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < n_edges;
-       e += (uint64_t)gridDim.x * blockDim.x)
-    if (e_lat[e]) e_flags[e] |= GPA_E_LAT_KEEP;
-}
-
-// Distances of every edge out of a group of L consecutive source blocks, one
-// lane per source.  Shortest walks repeat the sweep until no retreating edge
-// can shorten a walk (the sweep order settles every other edge); longest G'
-// walks take one sweep into a second table.  The workgroup is one wave.
+// Walk tables of a group of L consecutive blocks, one lane per source block:
+// for every block w of the source's function, the shortest walk (y = 0) or
+// the longest G' walk (y = 1) from the source to w, in the sweep table's
+// terms (including |w|).  Shortest walks repeat the sweep until no
+// retreating edge can shorten a walk (the sweep order settles every other
+// edge); longest G' walks take one sweep.  The workgroup is one wave; the
+// table is copied out to the source's row of the function's table.
 __global__ void __launch_bounds__(64)
-k_dist(uint32_t n_blocks, uint32_t n_funcs, uint32_t L, const uint32_t *fbb,
-       const uint32_t *func_of_block, const uint32_t *block_begin, const uint32_t *ent_ptr,
-       const uint32_t *ent, const uint32_t *ent_w, const uint32_t *ret_ptr, const uint32_t *rent,
-       const uint32_t *rent_w, const uint32_t *rent_e, const uint32_t *rpo_pos,
-       const uint32_t *out_ptr, const uint4 *q, const uint32_t *ql, uint32_t *e_dmin,
-       uint32_t *e_dmax, uint8_t *e_lat) {
-  extern __shared__ uint32_t D[];   // [2][blocks of the function + 1][L + 1]
+k_dist_tables(uint32_t n_blocks, uint32_t n_funcs, uint32_t L, const uint32_t *fbb,
+              const uint32_t *func_of_block, const uint32_t *ent_ptr, const uint32_t *ent,
+              const uint32_t *ent_w, const uint32_t *ret_ptr, const uint32_t *rent,
+              const uint32_t *rent_w, const uint32_t *rent_e, const uint32_t *rpo_pos,
+              const uint32_t *tab_off, uint32_t *t_sp, uint32_t *t_lp) {
+  extern __shared__ uint32_t D[];   // [blocks of the function + 1][L + 1]
   const unsigned lane = threadIdx.x;
+  const bool longest = blockIdx.y != 0;
   const uint32_t c0 = blockIdx.x * L, c1 = min(c0 + L, n_blocks);
   if (c0 >= n_blocks) return;
   const uint32_t Lc = L + 1;
@@ -371,82 +340,104 @@ k_dist(uint32_t n_blocks, uint32_t n_funcs, uint32_t L, const uint32_t *fbb,
     const uint32_t b0 = fbb[f], b1 = fbb[f + 1], nb = b1 - b0;
     const uint32_t g0 = max(c0, b0), g1 = min(c1, b1);
     if (g0 >= g1) continue;
-    const uint32_t ea = out_ptr[block_begin[g0]], eb = out_ptr[block_begin[g1]];
-    if (ea == eb) continue;
-    uint32_t *Dsp = D, *Dlp = D + (size_t)(nb + 1) * Lc;
     const uint32_t sb = c0 + lane;
-    const bool mine = lane < L && sb >= g0 && sb < g1 &&
-                      out_ptr[block_begin[sb]] < out_ptr[block_begin[sb + 1]];
+    const bool mine = lane < L && sb >= g0 && sb < g1;
     const uint32_t s = mine ? sb - b0 : 0xFFFFu;
     const uint32_t e_end = ent_ptr[b1];
-    const uint32_t r_begin = ret_ptr[b0], r_end = ret_ptr[b1];
-    // The sweeps cover only what can change: the first shortest-walk sweep
-    // starts at the earliest source (nothing before it is reached without a
-    // retreating edge), a later one at the earliest header whose retreating
-    // edge improved (nothing before it changed); the longest-walk sweep runs
-    // from the earliest source to the last target (G' walks only go forward).
+    // Nothing before the earliest source (in G' order) is reached without a
+    // retreating edge: the sweeps start there, a later shortest-walk sweep
+    // at the earliest header whose retreating edge improved a walk.
     uint32_t pmin = mine ? rpo_pos[sb] : 0xFFFFFFFFu;
-    uint32_t tmax = 0;
-    for (uint32_t k = ea + lane; k < eb; k += 64)
-      tmax = max(tmax, rpo_pos[b0 + (q[k].y & 0x7FFFFFFFu)]);
-    for (int d = 32; d > 0; d >>= 1) {
-      pmin = min(pmin, (uint32_t)__shfl_xor((int)pmin, d, 64));
-      tmax = max(tmax, (uint32_t)__shfl_xor((int)tmax, d, 64));
-    }
+    for (int d = 32; d > 0; d >>= 1) pmin = min(pmin, (uint32_t)__shfl_xor((int)pmin, d, 64));
     const uint32_t e_src_start = ent_ptr[b0 + pmin];
-    const uint32_t e_lp_end = ent_ptr[b0 + tmax + 1];
-    // shortest walks
     __syncthreads();
-    for (uint32_t k = lane; k < (nb + 1) * Lc; k += 64) {
-      Dsp[k] = kInf;
-      Dlp[k] = 0u;
-    }
+    const uint32_t none = longest ? 0u : kInf;
+    for (uint32_t k = lane; k < (nb + 1) * Lc; k += 64) D[k] = none;
     __syncthreads();
-    uint32_t start = e_src_start;
-    for (uint32_t sweep = 0; sweep <= nb; ++sweep) {
-      dist_sweep<false>(Dsp, Lc, col, s, nb, ent, ent_w, start, e_end);
-      uint32_t restart = 0xFFFFFFFFu;
-      for (uint32_t base = r_begin; base < r_end; base += 64) {
-        const uint32_t idx = base + lane;
-        const uint32_t rp = idx < r_end ? rent[idx] : kLocalNone;
-        const uint32_t rw = idx < r_end ? rent_w[idx] : 0u;
-        const uint32_t re = idx < r_end ? rent_e[idx] : 0u;
-        const uint32_t cnt = min(64u, r_end - base);
-        for (uint32_t i = 0; i < cnt; ++i) {
-          const uint32_t pk = __builtin_amdgcn_readlane(rp, i);
-          const uint32_t u = pk & kLocalNone, h = (pk >> 13) & kLocalNone;
-          const uint32_t cu = (u == s) ? 0u : Dsp[u * Lc + col];
-          const uint32_t bh = __builtin_amdgcn_readlane(rw, i);
-          if (mine && cu != kInf && cu + bh < Dsp[h * Lc + col])
-            restart = min(restart, __builtin_amdgcn_readlane(re, i));
+    if (longest) {
+      // every block is written before any later block reads it
+      dist_sweep<true>(D, Lc, col, s, nb, ent, ent_w, e_src_start, e_end);
+    } else {
+      const uint32_t r_begin = ret_ptr[b0], r_end = ret_ptr[b1];
+      uint32_t start = e_src_start;
+      for (uint32_t sweep = 0; sweep <= nb; ++sweep) {
+        dist_sweep<false>(D, Lc, col, s, nb, ent, ent_w, start, e_end);
+        uint32_t restart = 0xFFFFFFFFu;
+        for (uint32_t base = r_begin; base < r_end; base += 64) {
+          const uint32_t idx = base + lane;
+          const uint32_t rp = idx < r_end ? rent[idx] : kLocalNone;
+          const uint32_t rw = idx < r_end ? rent_w[idx] : 0u;
+          const uint32_t re = idx < r_end ? rent_e[idx] : 0u;
+          const uint32_t cnt = min(64u, r_end - base);
+          for (uint32_t i = 0; i < cnt; ++i) {
+            const uint32_t pk = __builtin_amdgcn_readlane(rp, i);
+            const uint32_t u = pk & kLocalNone, h = (pk >> 13) & kLocalNone;
+            const uint32_t cu = (u == s) ? 0u : D[u * Lc + col];
+            const uint32_t bh = __builtin_amdgcn_readlane(rw, i);
+            if (mine && cu != kInf && cu + bh < D[h * Lc + col])
+              restart = min(restart, __builtin_amdgcn_readlane(re, i));
+          }
         }
+        for (int d = 32; d > 0; d >>= 1)
+          restart = min(restart, (uint32_t)__shfl_xor((int)restart, d, 64));
+        if (restart == 0xFFFFFFFFu) break;
+        start = restart;
       }
-      for (int d = 32; d > 0; d >>= 1)
-        restart = min(restart, (uint32_t)__shfl_xor((int)restart, d, 64));
-      if (restart == 0xFFFFFFFFu) break;
-      start = restart;
     }
-    // longest G' walks; every block is written before any later block reads it
-    dist_sweep<true>(Dlp, Lc, col, s, nb, ent, ent_w, e_src_start, e_lp_end);
     __syncthreads();
-    for (uint32_t k = ea + lane; k < eb; k += 64) {
-      const uint4 r = q[k];
-      const uint32_t lat = ql[k];
-      const uint32_t t = r.y & 0x7FFFFFFFu;
-      const uint32_t sl = r.w - c0;
-      uint32_t dmin, dmax;
-      if (r.y & 0x80000000u) {
-        dmin = dmax = r.z;
-      } else {
-        const uint32_t Es = Dsp[t * Lc + sl];
-        const uint32_t El = Dlp[t * Lc + sl];   // longest walk + 1, 0: none
-        dmin = (Es == kInf) ? kInf : Es + r.z;
-        dmax = (r.w - b0 != t && El != 0) ? (El - 1) + r.z : dmin;
-      }
-      e_dmin[r.x] = dmin;
-      e_dmax[r.x] = dmax;
-      e_lat[r.x] = dmin <= lat ? 1 : 0;
+    // rows (source - b0) of the function's table, nb entries each
+    uint32_t *T = (longest ? t_lp : t_sp) + tab_off[f] + (size_t)(g0 - b0) * nb;
+    const uint32_t l0 = g0 - c0, n_out = (g1 - g0) * nb;
+    for (uint32_t k = lane; k < n_out; k += 64) {
+      const uint32_t r = k / nb, w = k - r * nb;
+      T[k] = D[w * Lc + l0 + r];
     }
+  }
+}
+
+// Per edge i -> j: distances count the instructions strictly between them.
+// Same block with i first: j - i - 1 both.  Otherwise, with the tables'
+// walk lengths E (shortest) and E' (longest G', plus one) from B_i to B_j,
+// which include |B_j|: dmin = E + (|B_i| - o_i - 1) + o_j - |B_j|, and dmax
+// the same with E' - 1 when B_i != B_j and G' has such a walk, else dmin.
+// The latency rule's flag is set when dmin is within the source's bound.
+__global__ void k_edge_dist(uint64_t n_edges, const uint32_t *e_src, const uint32_t *e_dst,
+                            const uint32_t *block_of, const uint32_t *func_of_block,
+                            const uint32_t *fbb, const uint32_t *block_begin,
+                            const uint8_t *op_class, const uint16_t *lat_tab,
+                            const uint32_t *tab_off, const uint32_t *t_sp, const uint32_t *t_lp,
+                            uint32_t *e_dmin, uint32_t *e_dmax, uint8_t *e_flags) {
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < n_edges;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t src = e_src[e], j = e_dst[e];
+    const uint32_t sb = block_of[src], tb = block_of[j];
+    const uint32_t oi = src - block_begin[sb], oj = j - block_begin[tb];
+    uint32_t dmin, dmax;
+    if (tb == sb && oi < oj) {
+      dmin = dmax = oj - oi - 1;
+    } else {
+      const uint32_t f = func_of_block[sb];
+      const uint32_t b0 = fbb[f], nb = fbb[f + 1] - b0;
+      const uint32_t ss = block_begin[sb + 1] - block_begin[sb];
+      const uint32_t bt = block_begin[tb + 1] - block_begin[tb];
+      const uint32_t add = (ss - oi - 1) + oj - bt;   // mod 2^32; E >= |B_j|
+      const size_t at = tab_off[f] + (size_t)(sb - b0) * nb + (tb - b0);
+      const uint32_t Es = t_sp[at], El = t_lp[at];
+      dmin = (Es == kInf) ? kInf : Es + add;
+      dmax = (sb != tb && El != 0) ? (El - 1) + add : dmin;
+    }
+    e_dmin[e] = dmin;
+    e_dmax[e] = dmax;
+    if (dmin <= lat_tab[op_class[src]]) e_flags[e] |= GPA_E_LAT_KEEP;
+  }
+}
+
+// per function: its squared block count (the size of each of its tables)
+__global__ void k_func_sq(uint32_t n_funcs, const uint32_t *fbb, uint32_t *sq) {
+  for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < n_funcs;
+       f += gridDim.x * blockDim.x) {
+    const uint32_t nb = fbb[f + 1] - fbb[f];
+    sq[f] = nb * nb;
   }
 }
 
@@ -492,35 +483,45 @@ void build_cfg_order(gpa_program &p, hipStream_t s, Arena &ar, SweepPlan &plan,
   GPA_LAUNCH_CHECK();
 }
 
-void build_distances(gpa_program &p, hipStream_t s, Arena &ar, const SweepPlan &plan) {
+void build_dist_tables(gpa_program &p, hipStream_t s, Arena &ar, const SweepPlan &plan,
+                       DistTables &t) {
   const uint32_t nf = p.n_funcs, nb = p.n_blocks;
   const uint32_t max_nb = p.max_func_blocks;
+  if (p.dist_entries >= (1ull << 32))
+    fail(GPA_E_UNSUPPORTED, "walk tables of %llu entries; the sum over functions of the squared "
+         "block count must stay below 2^32", (unsigned long long)p.dist_entries);
+  t.off = ar.get<uint32_t>(nf);
+  t.sp = ar.get<uint32_t>(p.dist_entries);
+  t.lp = ar.get<uint32_t>(p.dist_entries);
+  uint32_t *sq = ar.get<uint32_t>(nf);
+  hipLaunchKernelGGL(k_func_sq, dim3(grid_for(nf, 256, 1024)), dim3(256), 0, s, nf,
+                     p.func_block_begin.p, sq);
+  GPA_LAUNCH_CHECK();
+  exclusive_scan_u32(sq, t.off, nf, s, ar);
+  // one table of (blocks + 1) x (L + 1) words per workgroup
+  const uint32_t L = std::max<uint32_t>(
+      1u, std::min<uint32_t>(63u, kDistLds / (4u * (max_nb + 1)) - 1u));
+  const size_t lds = (size_t)4 * (L + 1) * (max_nb + 1);
+  GPA_HIP(hipFuncSetAttribute((const void *)k_dist_tables,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_dist_tables, dim3((nb + L - 1) / L, 2), dim3(64), lds, s, nb, nf, L,
+                     p.func_block_begin.p, p.func_of_block.p, plan.ent_ptr, plan.ent, plan.ent_w,
+                     plan.ret_ptr, plan.rent, plan.rent_w, plan.rent_e, p.rpo_pos.p, t.off, t.sp,
+                     t.lp);
+  GPA_LAUNCH_CHECK();
+}
+
+void build_distances(gpa_program &p, hipStream_t s, Arena &ar, const DistTables &t) {
   const uint64_t ne = p.n_edges;
   p.e_dmin.alloc(ne);
   p.e_dmax.alloc(ne);
   if (ne == 0) return;
   uint16_t *lat = ar.get<uint16_t>(16);
   GPA_HIP(hipMemcpyAsync(lat, p.arch.lat, sizeof(p.arch.lat), hipMemcpyHostToDevice, s));
-  uint4 *q = ar.get<uint4>(ne);
-  uint32_t *ql = ar.get<uint32_t>(ne);
-  uint8_t *e_lat = ar.get<uint8_t>(ne);
-  hipLaunchKernelGGL(k_dist_queries, dim3(grid_for(ne, 256, 8192)), dim3(256), 0, s, ne,
-                     p.out_perm.p, p.e_src.p, p.e_dst.p, p.block_of.p, p.func_of_block.p,
-                     p.func_block_begin.p, p.block_begin.p, p.op_class.p, lat, q, ql);
-  GPA_LAUNCH_CHECK();
-  // two tables of (blocks + 1) x (L + 1) words
-  const uint32_t L = std::max<uint32_t>(
-      1u, std::min<uint32_t>(63u, kDistLds / (8u * (max_nb + 1)) - 1u));
-  const size_t lds = (size_t)8 * (L + 1) * (max_nb + 1);
-  GPA_HIP(hipFuncSetAttribute((const void *)k_dist, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds));
-  hipLaunchKernelGGL(k_dist, dim3((nb + L - 1) / L), dim3(64), lds, s, nb, nf, L,
-                     p.func_block_begin.p, p.func_of_block.p, p.block_begin.p, plan.ent_ptr,
-                     plan.ent, plan.ent_w, plan.ret_ptr, plan.rent, plan.rent_w, plan.rent_e,
-                     p.rpo_pos.p, p.out_ptr.p, q, ql, p.e_dmin.p, p.e_dmax.p, e_lat);
-  GPA_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_merge_lat, dim3(grid_for(ne, 256, 8192)), dim3(256), 0, s, ne, e_lat,
-                     p.e_flags.p);
+  hipLaunchKernelGGL(k_edge_dist, dim3(grid_for(ne, 256, 8192)), dim3(256), 0, s, ne, p.e_src.p,
+                     p.e_dst.p, p.block_of.p, p.func_of_block.p, p.func_block_begin.p,
+                     p.block_begin.p, p.op_class.p, lat, t.off, t.sp, t.lp, p.e_dmin.p,
+                     p.e_dmax.p, p.e_flags.p);
   GPA_LAUNCH_CHECK();
 }
 

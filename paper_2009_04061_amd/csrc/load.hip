@@ -415,16 +415,22 @@ __global__ void k_roots(uint32_t n_scopes, const uint32_t *parent, uint32_t *roo
 }
 
 // largest function: blocks, and CFG edges
+// mx = (largest block count, largest edge count, sum over functions of the
+// squared block count as a 64-bit value in words 2-3)
 __global__ void k_max_func_blocks(uint32_t n_funcs, const uint32_t *fbb, const uint32_t *succ_ptr,
                                   uint32_t *mx) {
   uint32_t m = 0, e = 0;
+  unsigned long long sq = 0;
   for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < n_funcs;
        f += gridDim.x * blockDim.x) {
-    m = max(m, fbb[f + 1] - fbb[f]);
+    const uint32_t nb = fbb[f + 1] - fbb[f];
+    m = max(m, nb);
     e = max(e, succ_ptr[fbb[f + 1]] - succ_ptr[fbb[f]]);
+    sq += (unsigned long long)nb * nb;
   }
   atomicMax(&mx[0], m);
   atomicMax(&mx[1], e);
+  if (sq) atomicAdd((unsigned long long *)(mx + 2), sq);
 }
 
 static void raise_validation(uint32_t err) {
@@ -534,12 +540,17 @@ void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar) {
                      p.pred_ptr.p, p.pred.p);
   GPA_LAUNCH_CHECK();
   // largest function, in blocks
-  uint32_t *mx = ar.get<uint32_t>(2);
-  GPA_HIP(hipMemsetAsync(mx, 0, 8, s));
+  uint32_t *mx = ar.get<uint32_t>(4);
+  GPA_HIP(hipMemsetAsync(mx, 0, 16, s));
   hipLaunchKernelGGL(k_max_func_blocks, dim3(grid_for(nf, 256, 1024)), dim3(256), 0, s, nf,
                      p.func_block_begin.p, p.succ_ptr.p, mx);
   GPA_LAUNCH_CHECK();
-  read_scalars(mx, p.max_func_blocks, mx + 1, p.max_func_edges, s);
+  uint32_t mxh[4];
+  GPA_HIP(hipMemcpyAsync(mxh, mx, sizeof(mxh), hipMemcpyDeviceToHost, s));
+  GPA_HIP(hipStreamSynchronize(s));
+  p.max_func_blocks = mxh[0];
+  p.max_func_edges = mxh[1];
+  p.dist_entries = (uint64_t)mxh[2] | ((uint64_t)mxh[3] << 32);
   if (p.max_func_blocks > 4096)
     fail(GPA_E_UNSUPPORTED, "a function has %u blocks; at most 4096 are supported",
          p.max_func_blocks);
