@@ -37,8 +37,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0
-# 32-bit integer vector issue: 256 CUs x 64 lanes x 2.4 GHz
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# 32-bit integer vector issue: 256 CUs x 64 lanes x 2.4 GHz, in Gops/s
+ALU_PEAK_GOPS = 256 * 64 * 2.4e9 / 1e9
 HIST_SOURCE = os.path.join(HERE, "paper_2009_04061_amd", "csrc", "hist.hip")
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "hist_large_traffic.json")
 
@@ -61,8 +61,8 @@ def _traffic(n_launches_ref=None):
     return t.get("bytes_per_pass")
 
 
-HIST_KERNELS = ("k_bcount", "k_hist_totals", "k_partition", "k_bucket_plan", "k_count",
-                "k_merge", "k_hist_empty")
+HIST_KERNELS = ("k_hsample", "k_hregions", "k_partition", "k_hist_totals", "k_bucket_plan",
+                "k_count", "k_merge", "k_hoverflow")
 
 
 def _counter_rows(d):
@@ -99,7 +99,7 @@ def summarize_traffic(fetch_dir, write_dir, copy_mb, out_path):
             raise SystemExit(f"no copy kernel in the {counter} run")
         copy_kib = max(copy_vals)   # the large calibration copy
         factor = (copy_mb * 1024.0) / copy_kib
-        n_pass = max(len(v) for k, v in per_kernel.items() if k in ("k_bcount", "k_count"))
+        n_pass = max(len(v) for k, v in per_kernel.items() if k in ("k_partition", "k_count"))
         kib = sum(sum(v) for v in per_kernel.values()) / n_pass
         res[counter] = {"kib_per_pass_raw": kib, "copy_kib_raw": copy_kib,
                         "scale": factor, "bytes_per_pass": kib * 1024.0 * factor,
@@ -248,17 +248,28 @@ def main():
     rooflines = {}
     n_edges, n_scopes, n_blocks = info["n_edges"], info["n_scopes"], info["n_blocks"]
     n_succ = int(len(prog["succ"]))
+    # walk-table relaxations: every source block against every sweep entry of
+    # its function (one per predecessor edge, one per block without any),
+    # once for shortest and once for longest walks
+    fbb = np.asarray(prog["func_block_begin"], np.int64)
+    n_pred = np.bincount(np.asarray(prog["succ"], np.int64), minlength=n_blocks)
+    ent_per_block = np.maximum(n_pred, 1)
+    ent_cum = np.concatenate([[0], np.cumsum(ent_per_block)])
+    relax = 0
+    for f in range(len(fbb) - 1):
+        nb_f = int(fbb[f + 1] - fbb[f])
+        relax += 2 * nb_f * int(ent_cum[fbb[f + 1]] - ent_cum[fbb[f]])
     # per-unit algorithmic work of each kernel family
     work = {
         "hist": ("hbm", 8.0 * n_rec + 96.0 * n_instr,
-                 "gpa_hist: sample histogram pass (k_bcount, scan, k_partition, k_count, k_merge)"),
+                 "gpa_hist: sample histogram pass (k_hsample, k_partition, k_count, k_merge)"),
         "blame": ("hbm", 60.0 * n_edges + 288.0 * n_instr, "gpa_blame: k_blame_dst + k_blame_src"),
         "advise": ("hbm", 72.0 * n_scopes + 88.0 * n_instr + 8.0 * n_edges,
                    "gpa_estimate: contributions, scope sums, speedups, top-k"),
         "rd_search": ("hbm", 30.0 * n_instr, "gpa_dataflow: per-use backward searches"),
         "dfs": ("alu", float(n_blocks + n_succ), "CFG depth-first order (k_dfs)"),
-        "dist": ("alu", float(n_blocks) * float(n_blocks + n_succ) * 3.0,
-                 "edge distances (k_dist): source blocks x sweep entries x sweeps"),
+        "dist": ("alu", float(relax),
+                 "walk tables (k_dist_tables): source blocks x sweep entries, shortest + longest"),
     }
     for name, (bound, amount, label) in work.items():
         t = phase_ms.get(name)
@@ -267,9 +278,10 @@ def main():
         if bound == "hbm":
             achieved, peak, unit = amount / (t * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s"
         else:
-            achieved, peak, unit = amount / (t * 1e-3) / 1e12, ALU_PEAK_TOPS, "Tops/s"
-        rooflines[name] = {"bound": bound, "kernel": label, "achieved": round(achieved, 4),
-                           "peak": peak, "unit": unit, "frac": round(achieved / peak, 6),
+            achieved, peak, unit = amount / (t * 1e-3) / 1e9, ALU_PEAK_GOPS, "Gops/s"
+        rooflines[name] = {"bound": bound, "kernel": label,
+                           "achieved": float(f"{achieved:.6g}"),
+                           "peak": peak, "unit": unit, "frac": float(f"{achieved / peak:.6g}"),
                            "traffic": _traffic() if name == "hist" else None,
                            "algorithmic": amount, "avg_ms": round(t, 5)}
     dominant = max(rooflines, key=lambda k: rooflines[k]["avg_ms"])

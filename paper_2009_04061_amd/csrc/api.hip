@@ -158,14 +158,79 @@ struct Event {
   Event &operator=(const Event &) = delete;
 };
 
-template <typename T>
-static void upload(DBuf<T> &dst, const T *src, size_t n, bool on_device, hipStream_t s) {
-  dst.alloc(n);
-  if (n == 0) return;
-  if (!src) fail(GPA_E_INVALID, "a descriptor array is NULL");
-  GPA_HIP(hipMemcpyAsync(dst.p, src, n * sizeof(T),
-                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+// Device-resident descriptor arrays are copied by one kernel launch for all
+// of them (a job per array, a row of workgroups per job); host arrays go
+// through the runtime's copies.
+constexpr int kMaxCopyJobs = 24;
+struct CopyJobs {
+  void *dst[kMaxCopyJobs];
+  const void *src[kMaxCopyJobs];
+  uint64_t bytes[kMaxCopyJobs];
+  uint32_t n;
+};
+
+__global__ void __launch_bounds__(256) k_multi_copy(CopyJobs jobs) {
+  const uint32_t j = blockIdx.y;
+  const uint64_t nb = jobs.bytes[j];
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uintptr_t a = (uintptr_t)jobs.dst[j] | (uintptr_t)jobs.src[j];
+  if ((a & 3) == 0) {
+    const uint32_t *src = (const uint32_t *)jobs.src[j];
+    uint32_t *dst = (uint32_t *)jobs.dst[j];
+    for (uint64_t k = t; k < nb / 4; k += stride) dst[k] = src[k];
+    for (uint64_t k = (nb & ~3ull) + t; k < nb; k += stride)
+      ((uint8_t *)dst)[k] = ((const uint8_t *)src)[k];
+  } else {
+    const uint8_t *src = (const uint8_t *)jobs.src[j];
+    uint8_t *dst = (uint8_t *)jobs.dst[j];
+    for (uint64_t k = t; k < nb; k += stride) dst[k] = src[k];
+  }
 }
+
+struct Uploader {
+  bool on_device;
+  hipStream_t s;
+  CopyJobs jobs{};
+  uint64_t max_bytes = 0;
+  template <typename T>
+  void operator()(DBuf<T> &dst, const T *src, size_t n) {
+    dst.alloc(n);
+    if (n == 0) return;
+    if (!src) fail(GPA_E_INVALID, "a descriptor array is NULL");
+    if (!on_device) {
+      GPA_HIP(hipMemcpyAsync(dst.p, src, n * sizeof(T), hipMemcpyHostToDevice, s));
+      return;
+    }
+    // only memory the runtime knows as device memory of this device is read
+    // by the kernel; anything else goes through the runtime's copy
+    hipPointerAttribute_t at{};
+    int cur = -1;
+    const bool known = hipPointerGetAttributes(&at, src) == hipSuccess &&
+                       hipGetDevice(&cur) == hipSuccess && at.device == cur &&
+                       (at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged ||
+                        at.type == hipMemoryTypeUnified);
+    (void)hipGetLastError();   // a failed attribute query must not linger
+    if (!known) {
+      GPA_HIP(hipMemcpyAsync(dst.p, src, n * sizeof(T), hipMemcpyDefault, s));
+      return;
+    }
+    if (jobs.n == kMaxCopyJobs) flush();
+    jobs.dst[jobs.n] = dst.p;
+    jobs.src[jobs.n] = src;
+    jobs.bytes[jobs.n] = n * sizeof(T);
+    max_bytes = std::max<uint64_t>(max_bytes, n * sizeof(T));
+    ++jobs.n;
+  }
+  void flush() {
+    if (jobs.n == 0) return;
+    const unsigned gx = grid_for(max_bytes / 4 + 1, 256, 256);
+    hipLaunchKernelGGL(k_multi_copy, dim3(gx, jobs.n), dim3(256), 0, s, jobs);
+    GPA_LAUNCH_CHECK();
+    jobs.n = 0;
+    max_bytes = 0;
+  }
+};
 
 template <typename F>
 static gpa_status guarded(F &&body) {
@@ -264,30 +329,34 @@ gpa_status gpa_load_program(const gpa_program_desc *d, void *stream, gpa_program
       p->n_succ = d->succ_ptr[d->n_blocks];
     }
     const uint32_t n = p->n_instr, nb = p->n_blocks;
-    upload(p->op_class, d->op_class, n, dev, s);
-    upload(p->guard, d->guard, n, dev, s);
-    upload(p->def_ptr, d->def_ptr, (size_t)n + 1, dev, s);
-    upload(p->def_loc, d->def_loc, p->n_defs, dev, s);
-    upload(p->def_kind, d->def_kind, p->n_defs, dev, s);
-    upload(p->use_ptr, d->use_ptr, (size_t)n + 1, dev, s);
-    upload(p->use_loc, d->use_loc, p->n_uses, dev, s);
-    upload(p->use_kind, d->use_kind, p->n_uses, dev, s);
-    upload(p->block_begin, d->block_begin, (size_t)nb + 1, dev, s);
-    upload(p->succ_ptr, d->succ_ptr, (size_t)nb + 1, dev, s);
-    upload(p->succ, d->succ, p->n_succ, dev, s);
-    upload(p->func_block_begin, d->func_block_begin, (size_t)p->n_funcs + 1, dev, s);
-    upload(p->func_scope, d->func_scope, p->n_funcs, dev, s);
-    upload(p->instr_scope, d->instr_scope, n, dev, s);
-    upload(p->scope_parent, d->scope_parent, p->n_scopes, dev, s);
-    upload(p->scope_kind, d->scope_kind, p->n_scopes, dev, s);
-    upload(p->scope_flags, d->scope_flags, p->n_scopes, dev, s);
+    Uploader up{dev, s};
+    up(p->op_class, d->op_class, n);
+    up(p->guard, d->guard, n);
+    up(p->def_ptr, d->def_ptr, (size_t)n + 1);
+    up(p->def_loc, d->def_loc, p->n_defs);
+    up(p->def_kind, d->def_kind, p->n_defs);
+    up(p->use_ptr, d->use_ptr, (size_t)n + 1);
+    up(p->use_loc, d->use_loc, p->n_uses);
+    up(p->use_kind, d->use_kind, p->n_uses);
+    up(p->block_begin, d->block_begin, (size_t)nb + 1);
+    up(p->succ_ptr, d->succ_ptr, (size_t)nb + 1);
+    up(p->succ, d->succ, p->n_succ);
+    up(p->func_block_begin, d->func_block_begin, (size_t)p->n_funcs + 1);
+    up(p->func_scope, d->func_scope, p->n_funcs);
+    up(p->instr_scope, d->instr_scope, n);
+    up(p->scope_parent, d->scope_parent, p->n_scopes);
+    up(p->scope_kind, d->scope_kind, p->n_scopes);
+    up(p->scope_flags, d->scope_flags, p->n_scopes);
+    up.flush();
     const hipStream_t side = side_stream();
     Event ev_struct, ev_order;   // outlive the arena, whose end waits for both streams
     Arena ar(s);
     ar.add_stream(side);
-    PhaseTimer t_load, t_rd, t_dist, t_dfs, t_search;
+    PhaseTimer t_load, t_rd, t_dist, t_dfs, t_search, t_val, t_sites, t_edges, t_targets;
     t_load.begin(kPhaseLoad, s);
+    t_val.begin(kPhaseValidate, s);
     validate_and_build_structure(*p, s, ar);
+    t_val.end(s);
     // the DFS order, the sweep streams and the walk tables need only the
     // CFG: they run on the side stream while the sites are sorted and the
     // reaching definitions and edges are built
@@ -300,17 +369,27 @@ gpa_status gpa_load_program(const gpa_program_desc *d, void *stream, gpa_program
     build_dist_tables(*p, side, ar, plan, tables);
     t_dist.end(side);
     GPA_HIP(hipEventRecord(ev_order.e, side));
+    t_sites.begin(kPhaseSites, s);
     build_sites_and_scopes(*p, s, ar);
+    t_sites.end(s);
     t_rd.begin(kPhaseRd, s);
     build_reaching_defs(*p, s, ar, t_search);
+    t_edges.begin(kPhaseEdges, s);
     build_edges(*p, s, ar);
+    t_edges.end(s);
     t_rd.end(s);
+    t_targets.begin(kPhaseTargets, s);
+    build_scope_targets(*p, s, ar);
     GPA_HIP(hipStreamWaitEvent(s, ev_order.e, 0));
     build_distances(*p, s, ar, tables);
-    build_scope_targets(*p, s, ar);
+    t_targets.end(s);
     t_load.end(s);
     GPA_HIP(hipStreamSynchronize(s));
     t_load.collect();
+    t_val.collect();
+    t_sites.collect();
+    t_edges.collect();
+    t_targets.collect();
     t_rd.collect();
     t_dist.collect();
     t_dfs.collect();

@@ -212,7 +212,7 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint3
 // the API call that launched it has synchronized its stream.
 enum Phase {
   kPhaseHist = 0, kPhaseBlame, kPhaseLoad, kPhaseAdvise, kPhaseRd, kPhaseDist, kPhaseDfs,
-  kPhaseRdSearch, kNumPhases
+  kPhaseRdSearch, kPhaseValidate, kPhaseSites, kPhaseEdges, kPhaseTargets, kNumPhases
 };
 struct PhaseTimer {
   hipEvent_t a = nullptr, b = nullptr;

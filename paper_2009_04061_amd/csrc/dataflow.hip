@@ -255,25 +255,81 @@ __device__ __forceinline__ void or_range(uint64_t *in, uint32_t d0, uint32_t g, 
 // of the sorted use sites, threads [n, 2n) the use-blocked one, so a wave's
 // uses share a location.  A breadth-first search backwards from the use's
 // block over whole predecessor blocks; the blocks met are kept in a
-// per-thread list in LDS (also the queue), with a 128-bit filter in
-// registers to skip most list scans.  IN bitsets of up to kRegWords words
-// are accumulated in LDS (thread-private words, OR without return) and
-// written once; longer ones are OR-ed in place.  A search that would meet more than kSearchCap blocks is left to
-// k_rd_search_long.
+// per-thread list in LDS (also the queue), with a 256-bit filter in
+// registers to skip most list scans; a thread's list is contiguous (rows
+// padded to 144 bytes, so that 16-byte reads of a wave's 16-lane groups hit
+// distinct banks) and a scan reads eight entries per load.  A workgroup stages in LDS what most of
+// its visits read: the predecessor lists of its function (the function of
+// its first use) as local ids, and the index rows (survivors for condition
+// `_` and def end, per block) of the (location, variant) of its first and of
+// its last search; other visits read the index in global memory.  IN
+// bitsets of up to kRegWords words are accumulated in registers and written
+// once; longer ones are OR-ed in place.  A search that would meet more than
+// kSearchCap blocks is left to k_rd_search_long.
 constexpr uint32_t kRegWords = 8;
+constexpr uint32_t kSeenStride = kSearchCap + 8;   // u16 entries per thread row
+constexpr uint32_t kSearchStage = 8160;   // predecessor lists, bytes
+constexpr uint32_t kRowStageBlocks = 2048;  // index rows are staged for functions up to this size
 
 __global__ void __launch_bounds__(kSearchThreads)
-k_rd_search(uint32_t n_uses, uint32_t n_blocks, uint32_t n_loc, const uint32_t *use_site_sorted,
-            const uint32_t *use_instr, const uint32_t *use_loc, const uint8_t *use_cond,
-            const uint32_t *block_of, const uint32_t *func_of_block, const uint32_t *fbb,
-            const uint32_t *pred_ptr, const uint32_t *pred, const uint32_t *fl_def_ptr,
-            const uint32_t *dsi, const uint8_t *dsg, const uint32_t *usi, const uint4 *t0,
-            const uint2 *t1, const uint32_t *slot_start, uint64_t *rd_in, uint32_t *long_list,
-            uint32_t *n_long) {
-  __shared__ uint16_t seen[kSearchCap * kSearchThreads];
-  __shared__ unsigned long long inw[kRegWords * kSearchThreads];   // [word][thread]
+k_rd_search(uint32_t n_uses, uint32_t n_blocks, uint32_t n_loc, uint32_t row_nb,
+            const uint32_t *use_site_sorted, const uint32_t *use_instr, const uint32_t *use_loc,
+            const uint8_t *use_cond, const uint32_t *block_of, const uint32_t *func_of_block,
+            const uint32_t *fbb, const uint32_t *pred_ptr, const uint32_t *pred,
+            const uint32_t *fl_def_ptr, const uint32_t *dsi, const uint8_t *dsg,
+            const uint32_t *usi, const uint4 *t0, const uint2 *t1, const uint32_t *slot_start,
+            uint64_t *rd_in, uint32_t *long_list, uint32_t *n_long) {
+  __shared__ __align__(16) uint16_t seen[kSeenStride * kSearchThreads];
+  __shared__ uint16_t stage[kSearchStage / 2];   // [nb + 1] list starts, then the lists
+  extern __shared__ uint2 s_rows[];              // [2][row_nb]: (survivor | kill, def end)
+  __shared__ uint32_t s_f, s_ok, s_key[2];
   const unsigned tid = threadIdx.x;
   const uint32_t t = blockIdx.x * kSearchThreads + tid;
+  // (location | variant << 31) of search tt, whose function is f
+  auto key_of = [&](uint32_t tt, uint32_t &f) {
+    const uint32_t v = tt >= n_uses ? 1u : 0u;
+    const uint32_t u = use_site_sorted[tt - v * n_uses];
+    f = func_of_block[block_of[use_instr[u]]];
+    return use_loc[u] | (v << 31);
+  };
+  // the workgroup's first thread is always a valid search
+  if (tid == 0) {
+    const uint32_t t_first = blockIdx.x * kSearchThreads;
+    const uint32_t t_last = min(t_first + kSearchThreads, 2 * n_uses) - 1;
+    uint32_t f, fl;
+    const uint32_t ka = key_of(t_first, f), kb = key_of(t_last, fl);
+    const uint32_t b0 = fbb[f], nb = fbb[f + 1] - b0;
+    const uint32_t np = pred_ptr[b0 + nb] - pred_ptr[b0];
+    s_f = f;
+    s_ok = (nb + 1 + np) * 2u <= kSearchStage ? 1u : 0u;
+    const bool rows = row_nb != 0 && nb <= row_nb;
+    s_key[0] = rows ? ka : 0xFFFFFFFFu;
+    s_key[1] = (rows && fl == f && kb != ka) ? kb : 0xFFFFFFFFu;
+  }
+  __syncthreads();
+  const uint32_t sf = s_f;
+  const bool staged = s_ok != 0;
+  uint16_t *s_pp = stage, *s_pr = stage;
+  {
+    const uint32_t b0 = fbb[sf], nb = fbb[sf + 1] - b0;
+    if (staged) {
+      const uint32_t p0 = pred_ptr[b0], np = pred_ptr[b0 + nb] - p0;
+      s_pr = stage + nb + 1;
+      for (uint32_t q = tid; q <= nb; q += kSearchThreads) s_pp[q] = (uint16_t)(pred_ptr[b0 + q] - p0);
+      for (uint32_t q = tid; q < np; q += kSearchThreads) s_pr[q] = (uint16_t)(pred[p0 + q] - b0);
+    }
+    for (int sl = 0; sl < 2; ++sl) {
+      const uint32_t key = s_key[sl];
+      if (key == 0xFFFFFFFFu) continue;
+      const size_t rw = (size_t)(key & 0x7FFFFFFFu) * n_blocks + b0;
+      const bool bl = (key >> 31) != 0;
+      for (uint32_t q = tid; q < nb; q += kSearchThreads) {
+        const uint4 r = t0[rw + q];
+        s_rows[sl * row_nb + q] = make_uint2(bl ? r.y : r.x, r.z);
+      }
+    }
+  }
+  __syncthreads();
   if (t >= 2 * n_uses) return;
   const uint32_t var = t >= n_uses ? 1u : 0u;
   const uint32_t k = t - var * n_uses;
@@ -287,58 +343,95 @@ k_rd_search(uint32_t n_uses, uint32_t n_blocks, uint32_t n_loc, const uint32_t *
   if (nd == 0) return;
   const uint32_t nw = (nd + 63) / 64;
   const bool local = nw <= kRegWords;
+  const bool mine = staged && f == sf;   // this thread's function is the staged one
   const uint32_t c = use_cond[u];
+  const uint32_t my_key = x | (var << 31);
+  // a staged index row serves this search when its key matches and the
+  // condition is `_` (other conditions rescan the block's defs)
+  const int slot = (c != 0 || f != sf) ? -1 : (my_key == s_key[0] ? 0 : (my_key == s_key[1] ? 1 : -1));
+  const uint2 *my_row = s_rows + (slot < 0 ? 0 : slot) * row_nb;
   const size_t row = (size_t)x * n_blocks + b0;
   uint64_t *in = rd_in + slot_start[k] + var;
-  if (local)
-    for (uint32_t w = 0; w < nw; ++w) inw[w * kSearchThreads + tid] = 0ull;
+  uint64_t acc[kRegWords];
+#pragma unroll
+  for (uint32_t w = 0; w < kRegWords; ++w) acc[w] = 0ull;
   uint32_t n_seen = 0, head = 0;
-  uint64_t fl0 = 0, fl1 = 0;
+  uint64_t fl0 = 0, fl1 = 0, fl2 = 0, fl3 = 0;
   bool ok = true;
+  uint16_t *my = seen + tid * kSeenStride;
   auto visit = [&](uint32_t pl) {
-    const uint32_t h = (pl * 0x9E3779B1u) >> 25;
+    const uint32_t h = (pl * 0x9E3779B1u) >> 24;
     const uint64_t bit = 1ull << (h & 63);
-    const uint64_t fl = (h & 64) ? fl1 : fl0;
+    const uint32_t hw = h >> 6;
+    const uint64_t fl = hw == 0 ? fl0 : hw == 1 ? fl1 : hw == 2 ? fl2 : fl3;
     if (fl & bit) {
-      for (uint32_t q = 0; q < n_seen; ++q)
-        if (seen[q * kSearchThreads + tid] == pl) return;
+      for (uint32_t q0 = 0; q0 < n_seen; q0 += 8) {
+        const uint4 v = *(const uint4 *)(my + q0);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+        bool hit = false;
+#pragma unroll
+        for (uint32_t i = 0; i < 8; ++i) {
+          const uint32_t e = (w[i / 2] >> (16 * (i & 1))) & 0xFFFFu;
+          hit |= (q0 + i < n_seen) && e == pl;
+        }
+        if (hit) return;
+      }
     }
     if (n_seen == kSearchCap) {
       ok = false;
       return;
     }
-    if (h & 64) fl1 |= bit;
-    else fl0 |= bit;
-    seen[(n_seen++) * kSearchThreads + tid] = (uint16_t)pl;
+    fl0 |= hw == 0 ? bit : 0ull;
+    fl1 |= hw == 1 ? bit : 0ull;
+    fl2 |= hw == 2 ? bit : 0ull;
+    fl3 |= hw == 3 ? bit : 0ull;
+    my[n_seen++] = (uint16_t)pl;
   };
-  for (uint32_t q = pred_ptr[b]; q < pred_ptr[b + 1] && ok; ++q) visit(pred[q] - b0);
+  // predecessors of local block pl: staged lists or the global CSR
+  auto visit_preds = [&](uint32_t pl) {
+    if (mine) {
+      const uint32_t qa = s_pp[pl], qb = s_pp[pl + 1];
+      for (uint32_t q = qa; q < qb && ok; ++q) visit(s_pr[q]);
+    } else {
+      const uint32_t qa = pred_ptr[b0 + pl], qb = pred_ptr[b0 + pl + 1];
+      for (uint32_t q = qa; q < qb && ok; ++q) visit(pred[q] - b0);
+    }
+  };
+  visit_preds(b - b0);
   while (ok && head < n_seen) {
-    const uint32_t pl = seen[(head++) * kSearchThreads + tid];
-    const uint4 r = t0[row + pl];
-    const uint32_t qa = pred_ptr[b0 + pl], qb = pred_ptr[b0 + pl + 1];
-    const Survive sv = block_step(r, t1, row + pl, dsi, dsg, usi, c, blocked);
-    if (sv.g < r.z) {
-      const uint32_t lo = sv.g - d0, hi = r.z - d0;
-      for (uint32_t w = lo / 64; w * 64 < hi; ++w) {
-        const uint64_t m = range_word(lo, hi, 64 * w);
-        if (local) atomicOr(&inw[w * kSearchThreads + tid], (unsigned long long)m);
-        else in[2 * w] |= m;
+    const uint32_t pl = my[head++];
+    Survive sv;
+    if (slot >= 0) {
+      const uint2 e = my_row[pl];
+      sv.g = e.x & ~kKill;
+      sv.kill = (e.x & kKill) != 0;
+      sv.hi = e.y;
+    } else {
+      const uint4 r = t0[row + pl];
+      sv = block_step(r, t1, row + pl, dsi, dsg, usi, c, blocked);
+    }
+    if (sv.g < sv.hi) {
+      const uint32_t lo = sv.g - d0, hi = sv.hi - d0;
+      if (local) {
+#pragma unroll
+        for (uint32_t w = 0; w < kRegWords; ++w) acc[w] |= range_word(lo, hi, 64 * w);
+      } else {
+        for (uint32_t w = lo / 64; w * 64 < hi; ++w) in[2 * w] |= range_word(lo, hi, 64 * w);
       }
     }
-    if (!sv.kill)
-      for (uint32_t q = qa; q < qb && ok; ++q) visit(pred[q] - b0);
+    if (!sv.kill) visit_preds(pl);
   }
   if (!ok) {
     long_list[atomicAdd(n_long, 1u)] = k | (var << 31);
     return;
   }
-  if (local)
-    for (uint32_t w = 0; w < nw; ++w) in[2 * w] = inw[w * kSearchThreads + tid];
+  if (local) {
+#pragma unroll
+    for (uint32_t w = 0; w < kRegWords; ++w)
+      if (w < nw) in[2 * w] = acc[w];
+  }
 }
 
-// The searches one thread could not hold: one workgroup per use, level by
-// level, with the blocks met and the IN bits in LDS (and the function's
-// predecessor lists and the use's index row staged there when they fit).
 __global__ void __launch_bounds__(kLongThreads)
 k_rd_search_long(uint32_t n_blocks, uint32_t n_loc, uint32_t max_nb, uint32_t max_words,
                  const uint32_t *use_site_sorted, const uint32_t *use_instr,
@@ -587,8 +680,14 @@ void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar, PhaseTimer &t
     GPA_LAUNCH_CHECK();
     uint32_t *long_list = ar.get<uint32_t>(p.n_uses);
     t_search.begin(kPhaseRdSearch, s);
+    // two staged index rows per workgroup when the largest function fits
+    const uint32_t row_nb = p.max_func_blocks <= kRowStageBlocks ? p.max_func_blocks : 0u;
+    const size_t lds_rows = (size_t)2 * 8 * row_nb;
+    GPA_HIP(hipFuncSetAttribute((const void *)k_rd_search,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_rows));
     hipLaunchKernelGGL(k_rd_search, dim3((2 * p.n_uses + kSearchThreads - 1) / kSearchThreads),
-                       dim3(kSearchThreads), 0, s, p.n_uses, nb, nl, p.use_site_sorted.p,
+                       dim3(kSearchThreads), lds_rows, s, p.n_uses, nb, nl, row_nb,
+                       p.use_site_sorted.p,
                        p.use_instr.p, p.use_loc.p, p.use_cond.p, p.block_of.p, p.func_of_block.p,
                        p.func_block_begin.p, p.pred_ptr.p, p.pred.p, p.fl_def_ptr.p, dsi, dsg, usi,
                        t0, t1, slot_start, rd_in, long_list, scal + 1);

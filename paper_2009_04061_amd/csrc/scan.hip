@@ -1,5 +1,7 @@
-// Device exclusive prefix sum (u32), three phases: per-tile scan with tile
-// totals, recursive scan of the totals, add-back.
+// Device exclusive prefix sum (u32).  Up to kSingleTile elements: one
+// workgroup, one launch, the total written by the same kernel.  Beyond:
+// per-tile scans with tile totals, the scan of the totals (which also gives
+// the grand total), add-back.
 #include "common.h"
 #include "devutil.h"
 
@@ -39,14 +41,39 @@ k_scan_add(uint32_t *__restrict__ out, size_t n, const uint32_t *__restrict__ ti
     if (base + k < n) out[base + k] += add;
 }
 
-__global__ void k_copy_last(const uint32_t *in, size_t n, uint32_t *last) { *last = in[n - 1]; }
-
-__global__ void k_scan_total(const uint32_t *last, const uint32_t *out, size_t n,
-                             unsigned long long *total) {
-  *total = (unsigned long long)out[n - 1] + *last;
-}
-
 __global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
+
+constexpr int kSingleThreads = 1024;
+constexpr int kSingleItems = 16;
+constexpr int kSingleTile = kSingleThreads * kSingleItems;
+
+// in and out may be the same array: every element is read before it is
+// written, within the tile that holds it
+__global__ void __launch_bounds__(kSingleThreads)
+k_scan_single(const uint32_t *in, uint32_t *out, uint32_t n, unsigned long long *total) {
+  __shared__ uint32_t smem[kSingleThreads / kWave + 1];
+  uint32_t carry = 0;
+  for (uint32_t t0 = 0; t0 < n; t0 += kSingleTile) {
+    const uint32_t base = t0 + threadIdx.x * kSingleItems;
+    uint32_t v[kSingleItems];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kSingleItems; ++k) {
+      v[k] = (base + k < n) ? in[base + k] : 0u;
+      sum += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = carry + block_excl_scan<kSingleThreads>(sum, smem, &tot);
+#pragma unroll
+    for (int k = 0; k < kSingleItems; ++k) {
+      if (base + k < n) out[base + k] = run;
+      run += v[k];
+    }
+    carry += tot;
+    __syncthreads();   // smem is reused by the next tile's scan
+  }
+  if (total && threadIdx.x == 0) *total = carry;
+}
 
 void exclusive_scan_u32(const uint32_t *in, uint32_t *out, size_t n, hipStream_t s, Arena &ar,
                         unsigned long long *total_dev) {
@@ -57,30 +84,20 @@ void exclusive_scan_u32(const uint32_t *in, uint32_t *out, size_t n, hipStream_t
     }
     return;
   }
-  // the last input element is needed for the total after `out` overwrote it
-  uint32_t *last = nullptr;
-  if (total_dev) {
-    last = ar.get<uint32_t>(1);
-    hipLaunchKernelGGL(k_copy_last, dim3(1), dim3(1), 0, s, in, n, last);
+  if (n <= (size_t)kSingleTile) {
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kSingleThreads), 0, s, in, out, (uint32_t)n,
+                       total_dev);
     GPA_LAUNCH_CHECK();
+    return;
   }
-  size_t tiles = (n + kScanTile - 1) / kScanTile;
-  if (tiles == 1) {
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, in, out, n, nullptr);
-    GPA_LAUNCH_CHECK();
-  } else {
-    uint32_t *sums = ar.get<uint32_t>(tiles);
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, out, n,
-                       sums);
-    GPA_LAUNCH_CHECK();
-    exclusive_scan_u32(sums, sums, tiles, s, ar, nullptr);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, out, n, sums);
-    GPA_LAUNCH_CHECK();
-  }
-  if (total_dev) {
-    hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, s, last, out, n, total_dev);
-    GPA_LAUNCH_CHECK();
-  }
+  const size_t tiles = (n + kScanTile - 1) / kScanTile;
+  uint32_t *sums = ar.get<uint32_t>(tiles);
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, out, n,
+                     sums);
+  GPA_LAUNCH_CHECK();
+  exclusive_scan_u32(sums, sums, tiles, s, ar, total_dev);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, out, n, sums);
+  GPA_LAUNCH_CHECK();
 }
 
 }  // namespace gpa
