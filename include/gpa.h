@@ -111,7 +111,8 @@ typedef struct {
  *              instr_scope[i] is a LINE scope inside func_scope of i's
  *              function and below no other CFG function.
  * Limits: n_instr < 2^31, n_preds <= 16, n_regs+n_preds+n_bars <= 1024,
- * at most 4096 blocks in one function. */
+ * at most 4096 blocks in one function, and the sum over functions of the
+ * squared block count below 2^32 (the block-to-block walk tables). */
 typedef struct {
   uint32_t n_instr, n_blocks, n_funcs, n_scopes;
   uint32_t n_regs, n_preds, n_bars;
@@ -145,7 +146,7 @@ typedef struct {
   uint64_t n_rd;       /* total size of the per-use source lists */
   uint64_t n_edges;    /* dependency-graph edges (i, j) */
   uint32_t n_blamable; /* popcount(arch.blamable) */
-  uint32_t pad;
+  uint32_t n_roots;    /* kernel root scopes (scope_parent == GPA_NONE) */
 } gpa_program_info;
 
 /* Load a program and build its static analysis on the device: reaching
@@ -159,6 +160,8 @@ gpa_status gpa_load_program(const gpa_program_desc *desc, void *stream, gpa_prog
 void gpa_program_free(gpa_program *p);
 gpa_status gpa_program_get_info(const gpa_program *p, gpa_program_info *info);
 
+/* The kernel root scopes in ascending order: roots[n_roots] (host). */
+gpa_status gpa_program_roots(const gpa_program *p, uint32_t *roots);
 /* Per use site (in def/use CSR order) the sorted source instructions:
  * rd_ptr[n_uses+1], rd_src[n_rd], rd_blocked[n_rd] (1 if the source also
  * survives the use-blocked search). */
@@ -171,7 +174,8 @@ gpa_status gpa_program_edges(const gpa_program *p, uint32_t *src, uint32_t *dst,
 /* Attribute one profile (one kernel launch context, Sec. 3) of n samples.
  * samples_on_device != 0: `samples` is a device pointer that must stay
  * valid until the call returns.  Counts the samples (Sec. 2.1) and runs
- * the instruction blamer (Sec. 4, Eq. 1). */
+ * the instruction blamer (Sec. 4, Eq. 1).  At most 2^30 - 1 samples per
+ * call (GPA_E_UNSUPPORTED beyond). */
 gpa_status gpa_attribute(gpa_program *p, const gpa_sample *samples, uint64_t n,
                          int samples_on_device, void *stream, gpa_blame **out);
 void gpa_blame_free(gpa_blame *b);
@@ -196,13 +200,17 @@ void gpa_advice_free(gpa_advice *a);
 gpa_status gpa_advice_get(const gpa_advice *a, double *active, double *matched, double *speedup,
                           double *kernel_T, double *kernel_L, double *eq3);
 /* Top-k (k <= 16) per kernel root, speedup descending then optimizer then
- * scope ascending: arrays of n_scopes*k, GPA_NONE padded, indexed by root. */
+ * scope ascending: arrays of n_roots*k, row r for the r-th kernel root in
+ * ascending scope order (gpa_program_roots), GPA_NONE padded (speedup 0)
+ * where a kernel has fewer than k candidates. */
 gpa_status gpa_advice_topk(const gpa_advice *a, uint32_t k, uint32_t *opt, uint32_t *scope,
                            double *speedup);
 
 /* Instrumentation (for benchmarks and profiling tools).  When enabled, the
- * library records a hipEvent pair on the caller's stream around each phase
- * and accumulates the elapsed device time once the call has synchronized.
+ * library records a hipEvent pair around each phase on the stream the phase
+ * runs on (the caller's, or for phases 5 and 6 the library's per-device side
+ * stream) and accumulates the elapsed device time once the call has
+ * synchronized.
  * Phases: 0 sample aggregation, 1 blame, 2 whole program load, 3 advise,
  * 4 reaching definitions and edges, 5 walk tables of the CFGs, 6 depth-first
  * order of the CFGs, 7 the backward searches, 8 descriptor validation and

@@ -384,7 +384,10 @@ gpa_status gpa_load_program(const gpa_program_desc *d, void *stream, gpa_program
     build_distances(*p, s, ar, tables);
     t_targets.end(s);
     t_load.end(s);
+    if (p->n_roots_dev)   // not read by an earlier synchronization
+      GPA_HIP(hipMemcpyAsync(&p->n_roots, p->n_roots_dev, 4, hipMemcpyDeviceToHost, s));
     GPA_HIP(hipStreamSynchronize(s));
+    p->n_roots_dev = nullptr;
     t_load.collect();
     t_val.collect();
     t_sites.collect();
@@ -422,8 +425,20 @@ gpa_status gpa_program_get_info(const gpa_program *p, gpa_program_info *info) {
   info->n_rd = p->n_rd;
   info->n_edges = p->n_edges;
   info->n_blamable = p->n_blamable;
-  info->pad = 0;
+  info->n_roots = p->n_roots;
   return GPA_OK;
+}
+
+gpa_status gpa_program_roots(const gpa_program *p, uint32_t *roots) {
+  if (!p) {
+    set_error("gpa_program_roots: NULL program");
+    return GPA_E_INVALID;
+  }
+  return guarded([&] {
+    hipStream_t s = nullptr;
+    copy_out(roots, p->roots, p->n_roots, s);
+    GPA_HIP(hipStreamSynchronize(s));
+  });
 }
 
 gpa_status gpa_program_rd(const gpa_program *p, uint32_t *rd_ptr, uint32_t *rd_src,
@@ -605,7 +620,8 @@ gpa_status gpa_advice_topk(const gpa_advice *a, uint32_t k, uint32_t *opt, uint3
   }
   return guarded([&] {
     hipStream_t s = nullptr;
-    const size_t ns = a->prog->n_scopes;
+    const size_t ns = a->prog->n_roots;
+    if (ns == 0) return;
     std::vector<uint32_t> o(ns * a->k), sc(ns * a->k);
     std::vector<double> sp(ns * a->k);
     GPA_HIP(hipMemcpyAsync(o.data(), a->top_opt.p, 4 * o.size(), hipMemcpyDeviceToHost, s));

@@ -129,6 +129,7 @@ struct gpa_program {
   gpa::DBuf<uint32_t> big_list, big_n;
   gpa::DBuf<uint32_t> roots;                   // kernel root scope ids
   uint32_t n_roots = 0;
+  uint32_t *n_roots_dev = nullptr;   // during the load: device copy of n_roots
   hipStream_t stream = nullptr;
 };
 

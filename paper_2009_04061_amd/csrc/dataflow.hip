@@ -663,7 +663,12 @@ void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar, PhaseTimer &t
   exclusive_scan_u32(slot_words, slot_start, p.n_uses, s, ar, nslot_d);
   unsigned long long nslot = 0;
   uint32_t max_words = 0;
-  read_scalars(nslot_d, nslot, scal, max_words, s);
+  GPA_HIP(hipMemcpyAsync(&nslot, nslot_d, sizeof(nslot), hipMemcpyDeviceToHost, s));
+  GPA_HIP(hipMemcpyAsync(&max_words, scal, sizeof(max_words), hipMemcpyDeviceToHost, s));
+  if (p.n_roots_dev)
+    GPA_HIP(hipMemcpyAsync(&p.n_roots, p.n_roots_dev, 4, hipMemcpyDeviceToHost, s));
+  GPA_HIP(hipStreamSynchronize(s));
+  p.n_roots_dev = nullptr;
   uint64_t *rd_in = ar.get<uint64_t>(nslot ? nslot : 1);
   if (nslot) {
     const size_t lds_long = kStageRows + 8u * (size_t)max_words + kStagePred +

@@ -343,13 +343,13 @@ k_topk_chunks(uint32_t n_roots, const uint32_t *roots, const uint32_t *nchunks,
 }
 
 __global__ void __launch_bounds__(kTopThreads)
-k_topk_final(const uint32_t *roots, const uint32_t *nchunks, const uint32_t *chunk_start,
+k_topk_final(const uint32_t *nchunks, const uint32_t *chunk_start,
              const Cand *cand, uint32_t k, uint32_t *top_opt, uint32_t *top_scope,
              double *top_speed) {
   __shared__ Cand xch[2][kTopThreads / kWave];
   __shared__ uint32_t xwho[2][kTopThreads / kWave];
   __shared__ Cand best[kTopK];
-  const uint32_t ri = blockIdx.x, r = roots[ri];
+  const uint32_t ri = blockIdx.x;   // the ri-th kernel root; its row of the output
   const uint32_t n = nchunks[ri] * kTopK;
   const Cand *src = cand + (size_t)chunk_start[ri] * kTopK;
   // round 0 takes kTopChunk candidates; later rounds carry the best kTopK in
@@ -376,22 +376,10 @@ k_topk_final(const uint32_t *roots, const uint32_t *nchunks, const uint32_t *chu
   }
   for (uint32_t t = threadIdx.x; t < k; t += kTopThreads) {
     const Cand c = t < (uint32_t)kTopK ? best[t] : cand_none();
-    top_opt[(size_t)r * k + t] = c.o;
-    top_scope[(size_t)r * k + t] = c.l;
-    top_speed[(size_t)r * k + t] = c.o == 0xFFFFFFFFu ? 0.0 : c.s;
+    top_opt[(size_t)ri * k + t] = c.o;
+    top_scope[(size_t)ri * k + t] = c.l;
+    top_speed[(size_t)ri * k + t] = c.o == 0xFFFFFFFFu ? 0.0 : c.s;
   }
-}
-
-__global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x)
-    p[i] = v;
-}
-
-__global__ void k_fill_f64(double *p, size_t n, double v) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x)
-    p[i] = v;
 }
 
 void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint32_t k,
@@ -440,16 +428,11 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint3
                      a.kernel_T.p, a.kernel_L.p, a.eq3.p);
   GPA_LAUNCH_CHECK();
   a.k = k;
-  a.top_opt.alloc((size_t)ns * k);
-  a.top_scope.alloc((size_t)ns * k);
-  a.top_speed.alloc((size_t)ns * k);
+  // one row of k per kernel root, in the order of p.roots (ascending scope)
+  a.top_opt.alloc((size_t)p.n_roots * k);
+  a.top_scope.alloc((size_t)p.n_roots * k);
+  a.top_speed.alloc((size_t)p.n_roots * k);
   if (k) {
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for((size_t)ns * k, 256, 4096)), dim3(256), 0, s,
-                       a.top_opt.p, (size_t)ns * k, GPA_NONE);
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for((size_t)ns * k, 256, 4096)), dim3(256), 0, s,
-                       a.top_scope.p, (size_t)ns * k, GPA_NONE);
-    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((size_t)ns * k, 256, 4096)), dim3(256), 0, s,
-                       a.top_speed.p, (size_t)ns * k, 0.0);
     if (p.n_roots) {
       uint32_t *nch = ar.get<uint32_t>(p.n_roots), *cst = ar.get<uint32_t>(p.n_roots);
       hipLaunchKernelGGL(k_topk_plan, dim3(grid_for(p.n_roots, 256, 1024)), dim3(256), 0, s,
@@ -460,8 +443,8 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint3
       Cand *cand = ar.get<Cand>(max_chunks * kTopK);
       hipLaunchKernelGGL(k_topk_chunks, dim3((unsigned)max_chunks), dim3(kTopThreads), 0, s,
                          p.n_roots, p.roots.p, nch, cst, p.scope_end.p, a.speedup.p, cand);
-      hipLaunchKernelGGL(k_topk_final, dim3(p.n_roots), dim3(kTopThreads), 0, s, p.roots.p, nch,
-                         cst, cand, k, a.top_opt.p, a.top_scope.p, a.top_speed.p);
+      hipLaunchKernelGGL(k_topk_final, dim3(p.n_roots), dim3(kTopThreads), 0, s, nch, cst, cand,
+                         k, a.top_opt.p, a.top_scope.p, a.top_speed.p);
     }
     GPA_LAUNCH_CHECK();
   }

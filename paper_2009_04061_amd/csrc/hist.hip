@@ -503,7 +503,7 @@ void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint3
     GPA_LAUNCH_CHECK();
     return;
   }
-  if (n >= 0x40000000ull) fail(GPA_E_UNSUPPORTED, "at most 2^30 samples in one call");
+  if (n >= 0x40000000ull) fail(GPA_E_UNSUPPORTED, "fewer than 2^30 samples per call are supported");
   const uint32_t n_tiles = (uint32_t)((n + kTile - 1) / kTile);
   const uint64_t *rec = (const uint64_t *)samples;
   const bool vec = ((uintptr_t)samples % 16) == 0;

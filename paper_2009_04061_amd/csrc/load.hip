@@ -160,11 +160,16 @@ __global__ void k_val_succ(uint32_t n_blocks, const uint32_t *succ_ptr, const ui
   if (e) atomicOr(err, e);
 }
 
+// pred lists filled from their ends: the remaining count of each list is
+// its next free slot counted from the list start
 __global__ void k_fill_pred(uint32_t n_blocks, const uint32_t *succ_ptr, const uint32_t *succ,
-                            uint32_t *cursor, uint32_t *pred) {
+                            const uint32_t *pred_ptr, uint32_t *remaining, uint32_t *pred) {
   for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_blocks;
        b += gridDim.x * blockDim.x)
-    for (uint32_t k = succ_ptr[b]; k < succ_ptr[b + 1]; ++k) pred[atomicAdd(&cursor[succ[k]], 1u)] = b;
+    for (uint32_t k = succ_ptr[b]; k < succ_ptr[b + 1]; ++k) {
+      const uint32_t t = succ[k];
+      pred[pred_ptr[t] + atomicSub(&remaining[t], 1u) - 1u] = b;
+    }
 }
 
 // Each pred list in ascending order, so that everything downstream is
@@ -185,8 +190,9 @@ __global__ void k_sort_pred(uint32_t n_blocks, const uint32_t *pred_ptr, uint32_
 }
 
 // every instruction's LINE scope lies under its function's scope and under no
-// other CFG function
-__global__ void k_val_instr_scope(uint32_t n_instr, const uint32_t *instr_scope,
+// other CFG function (scope ids are range-checked here: this runs before the
+// other checks' verdict is known)
+__global__ void k_val_instr_scope(uint32_t n_instr, uint32_t n_scopes, const uint32_t *instr_scope,
                                   const uint32_t *block_of, const uint32_t *func_of_block,
                                   const uint32_t *func_scope, const uint32_t *parent,
                                   const uint8_t *kind, const uint8_t *flags, uint32_t *err) {
@@ -196,7 +202,7 @@ __global__ void k_val_instr_scope(uint32_t n_instr, const uint32_t *instr_scope,
     const uint32_t want = func_scope[func_of_block[block_of[i]]];
     uint32_t s = instr_scope[i];
     uint32_t guard = 0;
-    while (s != GPA_NONE && !(kind[s] == GPA_SCOPE_FUNCTION && (flags[s] & GPA_SF_HAS_CFG)) &&
+    while (s < n_scopes && !(kind[s] == GPA_SCOPE_FUNCTION && (flags[s] & GPA_SF_HAS_CFG)) &&
            guard < 4096) {
       s = parent[s];
       ++guard;
@@ -408,24 +414,45 @@ __global__ void k_instr_tags(uint32_t n_instr, const uint32_t *instr_scope, cons
   }
 }
 
-__global__ void k_roots(uint32_t n_scopes, const uint32_t *parent, uint32_t *roots, uint32_t *n) {
-  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_scopes;
-       s += gridDim.x * blockDim.x)
-    if (parent[s] == GPA_NONE) roots[atomicAdd(n, 1u)] = s;
+// kernel roots in ascending scope order, by one workgroup (ballot ranks
+// within a wave, a running count across the waves of each round)
+__global__ void __launch_bounds__(1024)
+k_roots(uint32_t n_scopes, const uint32_t *parent, uint32_t *roots, uint32_t *n) {
+  __shared__ uint32_t wcnt[1024 / kWave];
+  uint32_t base = 0;
+  const unsigned w = threadIdx.x / kWave, lane = lane_id();
+  for (uint32_t s0 = 0; s0 < n_scopes; s0 += 1024) {
+    const uint32_t s = s0 + threadIdx.x;
+    const bool is_root = s < n_scopes && parent[s] == GPA_NONE;
+    const uint64_t m = __ballot(is_root);
+    if (lane == 0) wcnt[w] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t before = base, total = 0;
+    for (unsigned v = 0; v < 1024 / kWave; ++v) {
+      if (v < w) before += wcnt[v];
+      total += wcnt[v];
+    }
+    if (is_root) roots[before + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = s;
+    base += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *n = base;
 }
 
 // largest function: blocks, and CFG edges
 // mx = (largest block count, largest edge count, sum over functions of the
 // squared block count as a 64-bit value in words 2-3)
-__global__ void k_max_func_blocks(uint32_t n_funcs, const uint32_t *fbb, const uint32_t *succ_ptr,
-                                  uint32_t *mx) {
+// (function bounds are clamped: this runs before the validation verdict)
+__global__ void k_max_func_blocks(uint32_t n_funcs, uint32_t n_blocks, const uint32_t *fbb,
+                                  const uint32_t *succ_ptr, uint32_t *mx) {
   uint32_t m = 0, e = 0;
   unsigned long long sq = 0;
   for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < n_funcs;
        f += gridDim.x * blockDim.x) {
-    const uint32_t nb = fbb[f + 1] - fbb[f];
+    const uint32_t a = min(fbb[f], n_blocks), b = min(fbb[f + 1], n_blocks);
+    const uint32_t nb = b - a;
     m = max(m, nb);
-    e = max(e, succ_ptr[fbb[f + 1]] - succ_ptr[fbb[f]]);
+    e = max(e, succ_ptr[b] - succ_ptr[a]);
     sq += (unsigned long long)nb * nb;
   }
   atomicMax(&mx[0], m);
@@ -491,8 +518,13 @@ __global__ void k_fl_close(uint32_t n_funcs, uint32_t n_loc, const uint32_t *fbb
 
 void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar) {
   const uint32_t n = p.n_instr, nb = p.n_blocks, nf = p.n_funcs, ns = p.n_scopes;
-  uint32_t *err = ar.get<uint32_t>(1);
-  GPA_HIP(hipMemsetAsync(err, 0, 4, s));
+  // Every check and the maps they need run before one read of the verdict;
+  // each kernel stays in bounds on any input (ranges are checked or clamped
+  // before they index).  vals: error bits, then the largest-function sizes
+  // (words 2-5, see k_max_func_blocks).
+  uint32_t *vals = ar.get<uint32_t>(8);
+  uint32_t *err = vals, *mx = vals + 2;
+  GPA_HIP(hipMemsetAsync(vals, 0, 32, s));
   hipLaunchKernelGGL(k_val_ends, dim3(1), dim3(1), 0, s, n, nb, nf, p.def_ptr.p, p.use_ptr.p,
                      p.block_begin.p, p.succ_ptr.p, p.func_block_begin.p, err);
   hipLaunchKernelGGL(k_val_instr, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, n, p.n_preds, ns,
@@ -507,53 +539,42 @@ void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar) {
   hipLaunchKernelGGL(k_val_scopes, dim3(grid_for(ns, 256, 2048)), dim3(256), 0, s, ns,
                      p.scope_parent.p, p.scope_kind.p, p.scope_flags.p, err);
   GPA_LAUNCH_CHECK();
-  uint32_t e = read_scalar(err, s);
-  if (e) raise_validation(e);
-  // function and block maps (ranges are known to be sane from here on)
+  // function and block maps (binary searches, in bounds on any input)
   p.block_of.alloc(n);
   p.func_of_block.alloc(nb);
   hipLaunchKernelGGL(k_blocks, dim3(grid_for((size_t)nb + n, 256, 4096)), dim3(256), 0, s, nf, nb,
                      n, p.func_block_begin.p, p.block_begin.p, p.block_of.p, p.func_of_block.p,
                      err);
   GPA_LAUNCH_CHECK();
-  e = read_scalar(err, s);
-  if (e) raise_validation(e);
   uint32_t *pcnt = ar.get<uint32_t>(nb + 1);
   GPA_HIP(hipMemsetAsync(pcnt, 0, 4 * (nb + 1), s));
   hipLaunchKernelGGL(k_val_succ, dim3(grid_for(nb, 256, 2048)), dim3(256), 0, s, nb, p.succ_ptr.p,
                      p.succ.p, p.n_succ, p.func_of_block.p, pcnt, err);
-  hipLaunchKernelGGL(k_val_instr_scope, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, n,
+  hipLaunchKernelGGL(k_val_instr_scope, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, n, ns,
                      p.instr_scope.p, p.block_of.p, p.func_of_block.p, p.func_scope.p,
                      p.scope_parent.p, p.scope_kind.p, p.scope_flags.p, err);
-  GPA_LAUNCH_CHECK();
-  e = read_scalar(err, s);
-  if (e) raise_validation(e);
-  // predecessor lists
-  p.pred_ptr.alloc(nb + 1);
-  p.pred.alloc(p.n_succ);
-  exclusive_scan_u32(pcnt, p.pred_ptr.p, nb + 1, s, ar);
-  uint32_t *cursor = ar.get<uint32_t>(nb + 1);
-  GPA_HIP(hipMemcpyAsync(cursor, p.pred_ptr.p, 4 * (nb + 1), hipMemcpyDeviceToDevice, s));
-  hipLaunchKernelGGL(k_fill_pred, dim3(grid_for(nb, 256, 2048)), dim3(256), 0, s, nb, p.succ_ptr.p,
-                     p.succ.p, cursor, p.pred.p);
-  hipLaunchKernelGGL(k_sort_pred, dim3(grid_for(nb, 256, 2048)), dim3(256), 0, s, nb,
-                     p.pred_ptr.p, p.pred.p);
-  GPA_LAUNCH_CHECK();
-  // largest function, in blocks
-  uint32_t *mx = ar.get<uint32_t>(4);
-  GPA_HIP(hipMemsetAsync(mx, 0, 16, s));
-  hipLaunchKernelGGL(k_max_func_blocks, dim3(grid_for(nf, 256, 1024)), dim3(256), 0, s, nf,
+  hipLaunchKernelGGL(k_max_func_blocks, dim3(grid_for(nf, 256, 1024)), dim3(256), 0, s, nf, nb,
                      p.func_block_begin.p, p.succ_ptr.p, mx);
   GPA_LAUNCH_CHECK();
-  uint32_t mxh[4];
-  GPA_HIP(hipMemcpyAsync(mxh, mx, sizeof(mxh), hipMemcpyDeviceToHost, s));
+  uint32_t h[6];
+  GPA_HIP(hipMemcpyAsync(h, vals, sizeof(h), hipMemcpyDeviceToHost, s));
   GPA_HIP(hipStreamSynchronize(s));
-  p.max_func_blocks = mxh[0];
-  p.max_func_edges = mxh[1];
-  p.dist_entries = (uint64_t)mxh[2] | ((uint64_t)mxh[3] << 32);
+  if (h[0]) raise_validation(h[0]);
+  p.max_func_blocks = h[2];
+  p.max_func_edges = h[3];
+  p.dist_entries = (uint64_t)h[4] | ((uint64_t)h[5] << 32);
   if (p.max_func_blocks > 4096)
     fail(GPA_E_UNSUPPORTED, "a function has %u blocks; at most 4096 are supported",
          p.max_func_blocks);
+  // predecessor lists (the successor lists are valid from here on)
+  p.pred_ptr.alloc(nb + 1);
+  p.pred.alloc(p.n_succ);
+  exclusive_scan_u32(pcnt, p.pred_ptr.p, nb + 1, s, ar);
+  hipLaunchKernelGGL(k_fill_pred, dim3(grid_for(nb, 256, 2048)), dim3(256), 0, s, nb, p.succ_ptr.p,
+                     p.succ.p, p.pred_ptr.p, pcnt, p.pred.p);
+  hipLaunchKernelGGL(k_sort_pred, dim3(grid_for(nb, 256, 2048)), dim3(256), 0, s, nb,
+                     p.pred_ptr.p, p.pred.p);
+  GPA_LAUNCH_CHECK();
 }
 
 void build_sites_and_scopes(gpa_program &p, hipStream_t s, Arena &ar) {
@@ -594,12 +615,11 @@ void build_sites_and_scopes(gpa_program &p, hipStream_t s, Arena &ar) {
                      p.instr_scope.p, p.scope_parent.p, p.scope_kind.p, p.scope_flags.p,
                      p.instr_tags.p);
   p.roots.alloc(ns);
-  uint32_t *nr = ar.get<uint32_t>(1);
-  GPA_HIP(hipMemsetAsync(nr, 0, 4, s));
-  hipLaunchKernelGGL(k_roots, dim3(grid_for(ns, 256, 4096)), dim3(256), 0, s, ns, p.scope_parent.p,
-                     p.roots.p, nr);
+  // the count is read with the next host synchronization of the load
+  p.n_roots_dev = ar.get<uint32_t>(1);
+  hipLaunchKernelGGL(k_roots, dim3(1), dim3(1024), 0, s, ns, p.scope_parent.p, p.roots.p,
+                     p.n_roots_dev);
   GPA_LAUNCH_CHECK();
-  p.n_roots = read_scalar(nr, s);
 }
 
 }  // namespace gpa

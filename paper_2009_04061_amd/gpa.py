@@ -52,11 +52,12 @@ class ProgramInfo(ct.Structure):
     _fields_ = [("n_instr", ct.c_uint64), ("n_blocks", ct.c_uint64), ("n_funcs", ct.c_uint64),
                 ("n_scopes", ct.c_uint64), ("n_defs", ct.c_uint64), ("n_uses", ct.c_uint64),
                 ("n_rd", ct.c_uint64), ("n_edges", ct.c_uint64), ("n_blamable", ct.c_uint32),
-                ("pad", ct.c_uint32)]
+                ("n_roots", ct.c_uint32)]
 
 
 # every entry point declared in include/gpa.h
-EXPORTS = ["gpa_load_program", "gpa_program_free", "gpa_program_get_info", "gpa_program_rd",
+EXPORTS = ["gpa_load_program", "gpa_program_free", "gpa_program_get_info", "gpa_program_roots",
+           "gpa_program_rd",
            "gpa_program_edges", "gpa_attribute", "gpa_blame_free", "gpa_blame_counts",
            "gpa_blame_shares", "gpa_blame_table", "gpa_advise", "gpa_advice_free",
            "gpa_advice_get", "gpa_advice_topk", "gpa_last_error", "gpa_timing_enable",
@@ -81,6 +82,7 @@ def lib():
         L.gpa_program_free.argtypes = [vp]
         L.gpa_program_free.restype = None
         L.gpa_program_get_info.argtypes = [vp, ct.POINTER(ProgramInfo)]
+        L.gpa_program_roots.argtypes = [vp, vp]
         L.gpa_program_rd.argtypes = [vp, vp, vp, vp]
         L.gpa_program_edges.argtypes = [vp, vp, vp, vp, vp, vp]
         L.gpa_attribute.argtypes = [vp, vp, u64, i32, vp, pp]
@@ -217,6 +219,12 @@ class Program:
         except Exception:
             pass
 
+    def roots(self):
+        """Kernel root scopes, ascending (the rows of Advice.topk)."""
+        r = np.zeros(max(self.info["n_roots"], 1), np.uint32)
+        _check(lib().gpa_program_roots(self.handle, r.ctypes.data))
+        return r[:self.info["n_roots"]]
+
     def rd(self):
         i = self.info
         rd_ptr = np.zeros(i["n_uses"] + 1, np.uint32)
@@ -322,7 +330,8 @@ class Advice:
                 "kernel_T": kT, "kernel_L": kL, "eq3": eq3.reshape(ns, 3)}
 
     def topk(self, k=5):
-        ns = self.blame.prog.info["n_scopes"]
+        """Rows in the order of Program.roots()."""
+        ns = self.blame.prog.info["n_roots"]
         o, s = np.zeros(ns * k, np.uint32), np.zeros(ns * k, np.uint32)
         v = np.zeros(ns * k)
         _check(lib().gpa_advice_topk(self.handle, k, o.ctypes.data, s.ctypes.data, v.ctypes.data))

@@ -32,7 +32,7 @@ def run_gpu(prog: dict, rec: np.ndarray, device_inputs: bool = True, k: int = 5)
     A = B.advise()
     C, tot = B.counts()
     out = {"C": C, "totals": tot, "rd": P.rd(), "edges": P.edges(), "shares": B.shares(),
-           "table": B.table(), "est": A.get(), "top": A.topk(k), "info": P.info}
+           "table": B.table(), "est": A.get(), "top": A.topk(k), "roots": P.roots(), "info": P.info}
     A.close()
     B.close()
     P.close()
@@ -90,10 +90,11 @@ def compare(prog: dict, g: dict, o: dict, k: int = 5):
     _close(est["eq3"][roots], oe["eq3"][roots], TOL_SPEEDUP, "eq3")
     top = g["top"]
     osp = oe["speedup"]
-    for r in roots:
-        _close(top["top_speed"][r], oe["top_speed"][r][:k], TOL_SPEEDUP, f"top-k speed root {r}")
+    assert np.array_equal(g["roots"], roots), "kernel roots"
+    for ri, r in enumerate(roots):
+        _close(top["top_speed"][ri], oe["top_speed"][r][:k], TOL_SPEEDUP, f"top-k speed root {r}")
         for t in range(k):
-            go, gs = int(top["top_opt"][r, t]), int(top["top_scope"][r, t])
+            go, gs = int(top["top_opt"][ri, t]), int(top["top_scope"][ri, t])
             oo, os_ = int(oe["top_opt"][r, t]), int(oe["top_scope"][r, t])
             if (go, gs) == (oo, os_):
                 continue

@@ -157,3 +157,47 @@ def test_function_at_block_limit_and_beyond():
     with pytest.raises(gpa.GpaError) as ei:
         gpa.Program(big)
     assert ei.value.status == -6
+
+
+def _corrupt(prog, kind):
+    """A copy of `prog` with one malformed field; every array keeps its
+    declared size, so only the library's own checks can reject it."""
+    q = {k: (np.array(v, copy=True) if isinstance(v, np.ndarray) else v) for k, v in prog.items()}
+    nb = len(q["block_begin"]) - 1
+    ns = len(q["scope_parent"])
+    n_loc = q["n_regs"] + q["n_preds"] + q["n_bars"]
+    if kind == "succ_target":
+        q["succ"][len(q["succ"]) // 2] = nb + 5
+    elif kind == "block_order":
+        q["block_begin"][3] = q["block_begin"][4] + 1
+    elif kind == "def_loc":
+        q["def_loc"][7] = n_loc + 2
+    elif kind == "instr_scope":
+        q["instr_scope"][11] = ns + 3
+    elif kind == "scope_parent":
+        q["scope_parent"][ns - 1] = ns - 1
+    elif kind == "guard":
+        q["guard"][5] = 2 * q["n_preds"] + 1
+    elif kind == "op_class":
+        q["op_class"][9] = 200
+    elif kind == "def_csr":
+        q["def_ptr"][20] = q["def_ptr"][21] + 1
+    elif kind == "func_bounds":
+        q["func_block_begin"][1] = q["func_block_begin"][2]
+    return q
+
+
+@pytest.mark.parametrize("kind", ["succ_target", "block_order", "def_loc", "instr_scope",
+                                  "scope_parent", "guard", "op_class", "def_csr", "func_bounds"])
+def test_malformed_descriptor_is_rejected(kind):
+    from paper_2009_04061_amd import gpa
+    prog, _ = S.workload_multi(seed=3, n_samples=10)
+    assert len(prog["func_block_begin"]) > 3
+    print(f"  malformed descriptor: {kind}", flush=True)
+    with pytest.raises(gpa.GpaError) as ei:
+        gpa.Program(_corrupt(prog, kind))
+    assert ei.value.status == -1, kind
+    # the library is still usable after a rejected load
+    P = gpa.Program(prog)
+    assert P.info["n_edges"] > 0
+    P.close()
