@@ -4,23 +4,27 @@
 // and Zipf-distributed PCs serialize them on hot bins, so the histogram is
 // built by partitioning the records into buckets of kBucketPCs consecutive
 // PCs whose 512 x 24 bins fit in LDS, reading the records once:
-//   k_hsample     every kSampleStride-th slice of records: bucket sizes, scaled up, give
-//                 each bucket kSubs sub-regions of the payload array (capacity
-//                 with head-room and slack; k_hregions lays them out);
+//   k_hsample     every kSampleStride-th slice of records: bucket sizes;
+//   k_hregions    one workgroup lays out kSubs sub-regions per bucket in the
+//                 payload array (scaled estimate with head-room and slack)
+//                 and clears their cursors;
 //   k_partition   per tile of kTile records: an LDS counting sort by bucket,
 //                 one device atomic per (tile, bucket) reserving room in one
-//                 of the bucket's sub-regions, and the runs written as 2-byte payloads
-//                 (pc offset in bucket, stall, latency bit); a run that does
-//                 not fit goes to an overflow area as 4-byte keys;
-//   k_count       per work item (a range of one bucket's filled sub-regions,
-//                 taken end to end):
-//                 LDS histogram of the bucket's bins, written once to the
-//                 output (whole bucket) or to a partial slot;
+//                 of the bucket's sub-regions, and the runs written as 2-byte
+//                 payloads (pc offset in bucket, stall, latency bit); a run
+//                 that does not fit goes to an overflow area as 4-byte keys;
+//   k_hplan       one workgroup sums the tile totals and plans the counting
+//                 work items (a range of one bucket's filled sub-regions,
+//                 taken end to end);
+//   k_count       per work item: LDS histogram of the bucket's bins, written
+//                 once to the output (whole bucket) or to a partial slot;
 //   k_merge       per split bucket: sum of its partial slots;
 //   k_hoverflow   overflow keys added with integer atomics (only when a
 //                 bucket outgrew its estimate).
 // Integer sums are exact in any order, so the result does not depend on
-// where runs land.
+// where runs land.  (A last-workgroup-does-the-rest scheme would save the
+// small launches, but the device-scope fence it needs in every workgroup
+// costs far more on this part.)
 #include "common.h"
 #include "devutil.h"
 
@@ -40,7 +44,10 @@ constexpr uint32_t kSampleSlice = 512;          // records per sampled slice
 constexpr int kCountThreads = 1024;
 // Each bucket's region is split into kSubs sub-regions, tile t reserving in
 // sub-region t % kSubs, so that no cursor takes more than 1/kSubs of the
-// tiles' device atomics; cursors sit kCursorStride words apart (one line each).
+// tiles' device atomics; cursors sit kCursorStride words apart (one line
+// each).  Word 1 of a cursor's line holds the start of the first run that
+// did not fit: runs are reserved in position order, so the sub-region is
+// written exactly up to there (or up to the cursor when nothing overflowed).
 constexpr uint32_t kSubs = 8;
 constexpr uint32_t kCursorStride = 32;
 constexpr uint32_t kSubSlack = kTile;           // region slack per sub-region, records
@@ -90,6 +97,33 @@ __device__ __forceinline__ uint32_t park_index(int bt, int q) {
   return (uint32_t)(bt * kBatch + q) * kHistThreads + threadIdx.x;
 }
 
+// sub-regions: capacity = estimate / kSubs * 5/4 + slack, laid out in
+// (bucket, sub-region) order by one workgroup; cursors start at zero
+__device__ void lay_out_regions(uint32_t n_buckets, const uint32_t *est, uint32_t *cap,
+                                uint32_t *region, uint32_t *cursor) {
+  __shared__ uint32_t tmp[kHistThreads / kWave + 1];
+  const uint32_t per = (n_buckets + kHistThreads - 1) / kHistThreads;
+  const uint32_t b0 = min(threadIdx.x * per, n_buckets), b1 = min(b0 + per, n_buckets);
+  uint32_t sum = 0;
+  for (uint32_t b = b0; b < b1; ++b) {
+    uint64_t e = 0;
+    for (uint32_t u = 0; u < kSubs; ++u) e += est[(b * kSubs + u) * kCursorStride];
+    e = e * kSampleStride / kSubs;
+    const uint32_t c = (uint32_t)min<uint64_t>(e + e / 4 + kSubSlack, 0x10000000ull);
+    for (uint32_t u = 0; u < kSubs; ++u) cap[b * kSubs + u] = c;
+    sum += c * kSubs;
+  }
+  uint32_t total;
+  uint32_t run = block_excl_scan<kHistThreads>(sum, tmp, &total);
+  for (uint32_t b = b0; b < b1; ++b)
+    for (uint32_t u = 0; u < kSubs; ++u) {
+      region[b * kSubs + u] = run;
+      run += cap[b * kSubs + u];
+      cursor[(b * kSubs + u) * kCursorStride] = 0;
+      cursor[(b * kSubs + u) * kCursorStride + 1] = 0xFFFFFFFFu;
+    }
+}
+
 // bucket sizes of every kSampleStride-th slice of kSampleSlice records
 // (two records per thread), added into the workgroup's copy of est[] (one of
 // kSubs copies, kCursorStride words apart, so that the atomics spread)
@@ -114,31 +148,74 @@ k_hsample(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint32
     if (cnt[b]) atomicAdd(&est[(b * kSubs + blockIdx.x % kSubs) * kCursorStride], cnt[b]);
 }
 
-// sub-regions: capacity = estimate / kSubs * 5/4 + slack, laid out in
-// (bucket, sub-region) order by one workgroup; cursors start at zero
 __global__ void __launch_bounds__(kHistThreads)
 k_hregions(uint32_t n_buckets, const uint32_t *__restrict__ est, uint32_t *__restrict__ cap,
            uint32_t *__restrict__ region, uint32_t *__restrict__ cursor) {
+  lay_out_regions(n_buckets, est, cap, region, cursor);
+}
+
+// totals = {valid, latency, dropped, 0} over the tiles, by one workgroup
+__device__ void sum_tile_totals(const TileTotals *tt, uint32_t n_tiles,
+                                unsigned long long *totals) {
+  __shared__ unsigned long long red[3][kHistThreads / kWave];
+  unsigned long long v = 0, l = 0, d = 0;
+  for (uint32_t t = threadIdx.x; t < n_tiles; t += kHistThreads) {
+    v += tt[t].valid;
+    l += tt[t].latency;
+    d += tt[t].dropped;
+  }
+  v = wave_sum(v);
+  l = wave_sum(l);
+  d = wave_sum(d);
+  if (lane_id() == 0) {
+    red[0][threadIdx.x / kWave] = v;
+    red[1][threadIdx.x / kWave] = l;
+    red[2][threadIdx.x / kWave] = d;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long a = 0, b = 0, c = 0;
+    for (int w = 0; w < kHistThreads / kWave; ++w) {
+      a += red[0][w];
+      b += red[1][w];
+      c += red[2][w];
+    }
+    totals[0] = a;
+    totals[1] = b;
+    totals[2] = c;
+    totals[3] = 0;
+  }
+}
+
+// per sub-region: how far it is filled; per bucket: the total fill, the
+// number of work items and the first item's index, by one workgroup
+__device__ void plan_items(uint32_t n_buckets, const uint32_t *cursor, const uint32_t *cap,
+                           uint32_t *sfill, uint32_t *bfill, uint32_t *items,
+                           uint32_t *item_start) {
   __shared__ uint32_t tmp[kHistThreads / kWave + 1];
   const uint32_t per = (n_buckets + kHistThreads - 1) / kHistThreads;
   const uint32_t b0 = min(threadIdx.x * per, n_buckets), b1 = min(b0 + per, n_buckets);
-  uint32_t sum = 0;
+  uint32_t my_items = 0;
   for (uint32_t b = b0; b < b1; ++b) {
-    uint64_t e = 0;
-    for (uint32_t u = 0; u < kSubs; ++u) e += est[(b * kSubs + u) * kCursorStride];
-    e = e * kSampleStride / kSubs;
-    const uint32_t c = (uint32_t)min<uint64_t>(e + e / 4 + kSubSlack, 0x10000000ull);
-    for (uint32_t u = 0; u < kSubs; ++u) cap[b * kSubs + u] = c;
-    sum += c * kSubs;
+    uint32_t fill = 0;
+    for (uint32_t u = 0; u < kSubs; ++u) {
+      const uint32_t slot = b * kSubs + u;
+      const uint32_t f = min(min(cursor[slot * kCursorStride], cap[slot]),
+                             cursor[slot * kCursorStride + 1]);
+      sfill[slot] = f;
+      fill += f;
+    }
+    bfill[b] = fill;
+    const uint32_t r = (fill + kItemRecords - 1) / kItemRecords;
+    items[b] = r < 1 ? 1 : r;
+    my_items += r < 1 ? 1 : r;
   }
   uint32_t total;
-  uint32_t run = block_excl_scan<kHistThreads>(sum, tmp, &total);
-  for (uint32_t b = b0; b < b1; ++b)
-    for (uint32_t u = 0; u < kSubs; ++u) {
-      region[b * kSubs + u] = run;
-      run += cap[b * kSubs + u];
-      cursor[(b * kSubs + u) * kCursorStride] = 0;
-    }
+  uint32_t run = block_excl_scan<kHistThreads>(my_items, tmp, &total);
+  for (uint32_t b = b0; b < b1; ++b) {
+    item_start[b] = run;
+    run += items[b];
+  }
 }
 
 // LDS words k_partition needs beyond its static arrays
@@ -215,6 +292,7 @@ k_partition(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint
       } else {
         d = 0x80000000u | atomicAdd(ov_count, c);   // overflow area, 4-byte keys
         any_ovf = 1;
+        atomicMin(&cursor[slot * kCursorStride + 1], pos);
       }
     }
     dst[b] = d;
@@ -289,55 +367,14 @@ k_partition(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint
   }
 }
 
-__global__ void k_hist_totals(const TileTotals *__restrict__ tt, uint32_t n_tiles,
-                              unsigned long long *__restrict__ totals) {
-  __shared__ unsigned long long red[3][kHistThreads / kWave];
-  unsigned long long v = 0, l = 0, d = 0;
-  for (uint32_t t = threadIdx.x; t < n_tiles; t += kHistThreads) {
-    v += tt[t].valid;
-    l += tt[t].latency;
-    d += tt[t].dropped;
-  }
-  v = wave_sum(v);
-  l = wave_sum(l);
-  d = wave_sum(d);
-  if (lane_id() == 0) {
-    red[0][threadIdx.x / kWave] = v;
-    red[1][threadIdx.x / kWave] = l;
-    red[2][threadIdx.x / kWave] = d;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long a = 0, b = 0, c = 0;
-    for (int w = 0; w < kHistThreads / kWave; ++w) {
-      a += red[0][w];
-      b += red[1][w];
-      c += red[2][w];
-    }
-    totals[0] = a;
-    totals[1] = b;
-    totals[2] = c;
-    totals[3] = 0;
-  }
-}
-
-// per sub-region: how far it is filled; per bucket: the total fill and the
-// number of work items
-__global__ void k_bucket_plan(uint32_t n_buckets, const uint32_t *cursor, const uint32_t *cap,
-                              uint32_t *sfill, uint32_t *bfill, uint32_t *items) {
-  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_buckets;
-       b += gridDim.x * blockDim.x) {
-    uint32_t fill = 0;
-    for (uint32_t u = 0; u < kSubs; ++u) {
-      const uint32_t slot = b * kSubs + u;
-      const uint32_t f = min(cursor[slot * kCursorStride], cap[slot]);
-      sfill[slot] = f;
-      fill += f;
-    }
-    bfill[b] = fill;
-    const uint32_t r = (fill + kItemRecords - 1) / kItemRecords;
-    items[b] = r < 1 ? 1 : r;
-  }
+// one workgroup: the totals over the tiles and the counting plan
+__global__ void __launch_bounds__(kHistThreads)
+k_hplan(const TileTotals *__restrict__ tt, uint32_t n_tiles, unsigned long long *__restrict__ totals,
+        uint32_t n_buckets, const uint32_t *__restrict__ cursor, const uint32_t *__restrict__ cap,
+        uint32_t *__restrict__ sfill, uint32_t *__restrict__ bfill, uint32_t *__restrict__ items,
+        uint32_t *__restrict__ item_start) {
+  sum_tile_totals(tt, n_tiles, totals);
+  plan_items(n_buckets, cursor, cap, sfill, bfill, items, item_start);
 }
 
 // k_count's LDS bins: each 16-lane group of a wave adds into its own copy,
@@ -511,13 +548,15 @@ void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint3
   const uint64_t n_samp =
       (n + (uint64_t)kSampleStride * kSampleSlice - 1) / ((uint64_t)kSampleStride * kSampleSlice);
   const uint32_t n_slots = n_buckets * kSubs;
-  uint32_t *est = ar.get<uint32_t>((size_t)n_slots * kCursorStride);
+  // cleared by one fill: the sampled estimates (kSubs padded copies per
+  // bucket) and the overflow count
+  const size_t n_est = (size_t)n_slots * kCursorStride;
+  uint32_t *ctl = ar.get<uint32_t>(n_est + 1);
+  uint32_t *est = ctl, *ov_count = ctl + n_est;
+  GPA_HIP(hipMemsetAsync(ctl, 0, 4 * (n_est + 1), s));
   uint32_t *cap = ar.get<uint32_t>(n_slots);
   uint32_t *region = ar.get<uint32_t>(n_slots);
   uint32_t *cursor = ar.get<uint32_t>((size_t)n_slots * kCursorStride);
-  uint32_t *ov_count = ar.get<uint32_t>(1);
-  GPA_HIP(hipMemsetAsync(est, 0, 4 * (size_t)n_slots * kCursorStride, s));
-  GPA_HIP(hipMemsetAsync(ov_count, 0, 4, s));
   const size_t lds_count = (size_t)n_buckets * 4;
   hipLaunchKernelGGL(k_hsample, dim3((unsigned)n_samp), dim3(kHistThreads), lds_count, s, rec, n,
                      n_instr, n_buckets, est);
@@ -535,6 +574,9 @@ void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint3
   uint16_t *payload = ar.get<uint16_t>(max_region);
   uint32_t *ov_keys = ar.get<uint32_t>(n);
   TileTotals *tt = ar.get<TileTotals>(n_tiles);
+  uint32_t *sfill = ar.get<uint32_t>(n_slots), *bfill = ar.get<uint32_t>(n_buckets);
+  uint32_t *items = ar.get<uint32_t>(n_buckets);
+  uint32_t *item_start = ar.get<uint32_t>(n_buckets);
   const size_t lds_part = partition_lds_words(n_buckets) * 4;
   if (vec) {
     GPA_HIP(hipFuncSetAttribute((const void *)k_partition<true>,
@@ -548,14 +590,9 @@ void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint3
                        n_instr, n_buckets, cap, region, cursor, payload, ov_keys, ov_count, tt);
   }
   GPA_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_hist_totals, dim3(1), dim3(kHistThreads), 0, s, tt, n_tiles, totals);
-  uint32_t *sfill = ar.get<uint32_t>(n_slots), *bfill = ar.get<uint32_t>(n_buckets);
-  uint32_t *items = ar.get<uint32_t>(n_buckets);
-  uint32_t *item_start = ar.get<uint32_t>(n_buckets);
-  hipLaunchKernelGGL(k_bucket_plan, dim3(grid_for(n_buckets, 256, 64)), dim3(256), 0, s,
-                     n_buckets, cursor, cap, sfill, bfill, items);
+  hipLaunchKernelGGL(k_hplan, dim3(1), dim3(kHistThreads), 0, s, tt, n_tiles, totals, n_buckets,
+                     cursor, cap, sfill, bfill, items, item_start);
   GPA_LAUNCH_CHECK();
-  exclusive_scan_u32(items, item_start, n_buckets, s, ar);
   // items <= one per bucket plus one per kItemRecords records
   const uint64_t max_items = n_buckets + n / kItemRecords + 1;
   uint32_t *partial = ar.get<uint32_t>((size_t)max_items * kBucketBins);

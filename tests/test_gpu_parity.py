@@ -201,3 +201,24 @@ def test_malformed_descriptor_is_rejected(kind):
     P = gpa.Program(prog)
     assert P.info["n_edges"] > 0
     P.close()
+
+
+def test_histogram_bucket_outgrows_its_estimate():
+    """Records of one bucket placed only where the size estimate does not look
+    (every slice of 512 records except each 32nd), so its runs overflow their
+    regions and go the overflow way; the other slices feed a bucket of their
+    own, and a few invalid records are mixed in."""
+    prog, _ = S.workload_small(seed=6, n_samples=10)
+    n = 1_500_000
+    rng = np.random.default_rng(6)
+    rec = np.zeros(n, S.SAMPLE_DTYPE)
+    pos = np.arange(n)
+    sampled = (pos // 512) % 32 == 0
+    rec["pc"][sampled] = rng.integers(0, 512, int(sampled.sum()))
+    hot = rng.random(n) < 0.6
+    rec["pc"][~sampled] = np.where(hot[~sampled], 1100, rng.integers(1024, 1536, int((~sampled).sum())))
+    rec["stall"] = rng.integers(0, 12, n)
+    rec["flags"] = (rng.random(n) < 0.5) & (rec["stall"] != S.ST_SELECTED) & (rec["stall"] != S.ST_NOT_SELECTED)
+    rec = S.corrupt_samples(rec, 0.001, len(prog["op_class"]), seed=6)
+    print(f"  records {n}, sampled slices {int(sampled.sum())}", flush=True)
+    _both(prog, rec)
