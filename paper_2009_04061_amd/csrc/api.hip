@@ -386,6 +386,8 @@ gpa_status gpa_load_program(const gpa_program_desc *d, void *stream, gpa_program
     t_load.end(s);
     if (p->n_roots_dev)   // not read by an earlier synchronization
       GPA_HIP(hipMemcpyAsync(&p->n_roots, p->n_roots_dev, 4, hipMemcpyDeviceToHost, s));
+    GPA_HIP(hipMemcpyAsync(p->seg_chunks, p->big_chunk_tot.p, sizeof(p->seg_chunks),
+                           hipMemcpyDeviceToHost, s));
     GPA_HIP(hipStreamSynchronize(s));
     p->n_roots_dev = nullptr;
     t_load.collect();

@@ -127,6 +127,11 @@ struct gpa_program {
   // scope, edges by common loop, edges by common scope, subtrees), each list
   // n_scopes long, counts in big_n[4]
   gpa::DBuf<uint32_t> big_list, big_n;
+  // their kSegChunk-element chunks: first chunk of each listed segment (4
+  // lists of n_scopes) and the chunk totals (device; host copy seg_chunks)
+  gpa::DBuf<uint32_t> big_chunk;
+  gpa::DBuf<unsigned long long> big_chunk_tot;
+  unsigned long long seg_chunks[4] = {0, 0, 0, 0};
   gpa::DBuf<uint32_t> roots;                   // kernel root scope ids
   uint32_t n_roots = 0;
   uint32_t *n_roots_dev = nullptr;   // during the load: device copy of n_roots
@@ -201,6 +206,7 @@ void build_dist_tables(gpa_program &p, hipStream_t s, Arena &ar, const SweepPlan
 // per edge: dmin, dmax and the latency rule's flag from the tables
 void build_distances(gpa_program &p, hipStream_t s, Arena &ar, const DistTables &t);
 constexpr uint32_t kSmallSeg = 64;   // longest segment one thread sums alone
+constexpr uint32_t kSegChunk = 4096; // elements of a longer segment per workgroup
 void build_scope_targets(gpa_program &p, hipStream_t s, Arena &ar);
 // blame.hip
 void run_blame(const gpa_program &p, gpa_blame &b, hipStream_t s, Arena &ar);

@@ -558,6 +558,37 @@ __global__ void k_big_segments(uint32_t n_seg, const uint32_t *ptr, const uint32
   }
 }
 
+// One workgroup: for each of the four groupings, the first chunk of every
+// listed big segment (chunks of kSegChunk elements, in list order) and the
+// number of chunks.
+__global__ void __launch_bounds__(1024)
+k_big_chunks(uint32_t n_seg, const uint32_t *list, const uint32_t *n_list, const uint32_t *ptr0,
+             const uint32_t *ptr1, const uint32_t *ptr2, const uint32_t *end,
+             uint32_t *chunk_start, unsigned long long *totals) {
+  __shared__ uint32_t tmp[1024 / kWave + 1];
+  for (int g = 0; g < 4; ++g) {
+    const uint32_t *ptr = g == 0 ? ptr0 : g == 1 ? ptr1 : g == 2 ? ptr2 : nullptr;
+    const uint32_t *lst = list + (size_t)g * n_seg;
+    const uint32_t nl = n_list[g];
+    uint32_t carry = 0;
+    for (uint32_t j0 = 0; j0 < nl; j0 += 1024) {
+      const uint32_t j = j0 + threadIdx.x;
+      uint32_t c = 0;
+      if (j < nl) {
+        const uint32_t l = lst[j];
+        const uint32_t a = ptr ? ptr[l] : l, b = ptr ? ptr[l + 1] : end[l];
+        c = (b - a + kSegChunk - 1) / kSegChunk;
+      }
+      uint32_t tot;
+      const uint32_t run = block_excl_scan<1024>(c, tmp, &tot);
+      if (j < nl) chunk_start[(size_t)g * n_seg + j] = carry + run;
+      carry += tot;
+    }
+    if (threadIdx.x == 0) totals[g] = carry;
+    __syncthreads();
+  }
+}
+
 void build_scope_targets(gpa_program &p, hipStream_t s, Arena &ar) {
   const uint64_t ne = p.n_edges;
   p.e_lca.alloc(ne);
@@ -579,6 +610,13 @@ void build_scope_targets(gpa_program &p, hipStream_t s, Arena &ar) {
   for (int g = 0; g < 4; ++g)
     hipLaunchKernelGGL(k_big_segments, dim3(grid_for(ns, 256, 4096)), dim3(256), 0, s, ns, ptrs[g],
                        p.scope_end.p, p.big_list.p + (size_t)g * ns, p.big_n.p + g);
+  GPA_LAUNCH_CHECK();
+  // the big segments' chunks: first chunk of each listed segment, and the
+  // totals (read by the host with the load's last synchronization)
+  p.big_chunk.alloc((size_t)4 * ns);
+  p.big_chunk_tot.alloc(4);
+  hipLaunchKernelGGL(k_big_chunks, dim3(1), dim3(1024), 0, s, ns, p.big_list.p, p.big_n.p, ptrs[0],
+                     ptrs[1], ptrs[2], p.scope_end.p, p.big_chunk.p, p.big_chunk_tot.p);
   GPA_LAUNCH_CHECK();
 }
 

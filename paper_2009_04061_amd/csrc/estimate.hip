@@ -92,8 +92,9 @@ __global__ void k_gather(size_t n, const uint32_t *n_dev, const uint32_t *perm, 
 // Segmented sums over contiguous ranges [begin(l), end(l)), given either by
 // ptr[l], ptr[l+1] (ptr mode) or by l, end[l] (subtree mode).  A segment of
 // at most kSmallSeg elements is summed by one thread in element order; the
-// longer ones (listed once at load) by one workgroup each, every thread
-// owning a fixed stride and the reduction a fixed shape.  Either way the
+// longer ones (listed once at load, with their chunk counts) in chunks of
+// kSegChunk by one workgroup each, every thread owning a fixed stride and the
+// reduction a fixed shape, and the chunks then in order.  Either way the
 // result does not depend on scheduling.
 template <int W>
 __global__ void k_seg_small(uint32_t n_seg, const uint32_t *ptr, const uint32_t *end,
@@ -114,16 +115,21 @@ __global__ void k_seg_small(uint32_t n_seg, const uint32_t *ptr, const uint32_t 
   }
 }
 
+// Segments longer than kSmallSeg, in chunks of kSegChunk elements: one
+// workgroup per chunk (element order within a thread's stride, then the
+// waves' sums in a fixed shape), then per segment its chunks in order.
 template <int W>
 __global__ void __launch_bounds__(256)
-k_seg_big(const uint32_t *list, const uint32_t *n_list, const uint32_t *ptr, const uint32_t *end,
-          const double *data, double *out) {
+k_seg_chunks(const uint32_t *list, const uint32_t *n_list, const uint32_t *chunk_start,
+             uint32_t n_chunks, const uint32_t *ptr, const uint32_t *end, const double *data,
+             double *partial) {
   __shared__ double red[4][W];
   const uint32_t nl = *n_list;
-  for (uint32_t g = blockIdx.x; g < nl; g += gridDim.x) {
-    const uint32_t l = list[g];
-    const uint32_t a = ptr ? ptr[l] : l;
-    const uint32_t b = ptr ? ptr[l + 1] : end[l];
+  for (uint32_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+    const uint32_t j = upper_index_u32(chunk_start, 0, nl, c);
+    const uint32_t l = list[j];
+    const uint32_t a0 = ptr ? ptr[l] : l, b0 = ptr ? ptr[l + 1] : end[l];
+    const uint32_t a = a0 + (c - chunk_start[j]) * kSegChunk, b = min(a + kSegChunk, b0);
     double v[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) v[q] = 0.0;
@@ -151,22 +157,46 @@ k_seg_big(const uint32_t *list, const uint32_t *n_list, const uint32_t *ptr, con
 #pragma unroll
       for (int q = 0; q < W; ++q) red[w][q] = v[q];
     __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int q = 0; q < W; ++q)
-        out[(size_t)l * W + q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
-    }
+    if (threadIdx.x < (unsigned)W)
+      partial[(size_t)c * W + threadIdx.x] =
+          (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
     __syncthreads();
   }
 }
 
 template <int W>
+__global__ void k_seg_combine(const uint32_t *list, const uint32_t *n_list,
+                              const uint32_t *chunk_start, uint32_t n_chunks,
+                              const double *partial, double *out) {
+  const uint32_t nl = *n_list;
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nl; j += gridDim.x * blockDim.x) {
+    const uint32_t c0 = chunk_start[j], c1 = (j + 1 < nl) ? chunk_start[j + 1] : n_chunks;
+    double v[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) v[q] = 0.0;
+    for (uint32_t c = c0; c < c1; ++c)
+#pragma unroll
+      for (int q = 0; q < W; ++q) v[q] += partial[(size_t)c * W + q];
+    const uint32_t l = list[j];
+#pragma unroll
+    for (int q = 0; q < W; ++q) out[(size_t)l * W + q] = v[q];
+  }
+}
+
+template <int W>
 void seg_sum(uint32_t n_seg, const uint32_t *ptr, const uint32_t *end, const uint32_t *big_list,
-             const uint32_t *big_n, const double *data, double *out, hipStream_t s) {
+             const uint32_t *big_n, const uint32_t *chunk_start, uint64_t n_chunks,
+             const double *data, double *out, hipStream_t s, Arena &ar) {
   hipLaunchKernelGGL(k_seg_small<W>, dim3(grid_for(n_seg, 256, 8192)), dim3(256), 0, s, n_seg, ptr,
                      end, data, out);
-  hipLaunchKernelGGL(k_seg_big<W>, dim3(std::min<uint32_t>(n_seg, 512)), dim3(256), 0, s, big_list,
-                     big_n, ptr, end, data, out);
+  if (n_chunks) {
+    double *partial = ar.get<double>((size_t)n_chunks * W);
+    hipLaunchKernelGGL(k_seg_chunks<W>, dim3((unsigned)std::min<uint64_t>(n_chunks, 4096)),
+                       dim3(256), 0, s, big_list, big_n, chunk_start, (uint32_t)n_chunks, ptr, end,
+                       data, partial);
+    hipLaunchKernelGGL(k_seg_combine<W>, dim3(grid_for(n_seg, 256, 1024)), dim3(256), 0, s,
+                       big_list, big_n, chunk_start, (uint32_t)n_chunks, partial, out);
+  }
   GPA_LAUNCH_CHECK();
 }
 
@@ -401,7 +431,8 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint3
   hipLaunchKernelGGL(k_gather<kNV>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, (size_t)n,
                      nullptr, p.line_perm.p, iv, iv_g);
   const uint32_t *big = p.big_list.p;
-  seg_sum<kNV>(ns, p.line_ptr.p, nullptr, big, p.big_n.p, iv_g, own, s);
+  const uint32_t *bch = p.big_chunk.p;
+  seg_sum<kNV>(ns, p.line_ptr.p, nullptr, big, p.big_n.p, bch, p.seg_chunks[0], iv_g, own, s, ar);
   if (p.n_edges) {
     hipLaunchKernelGGL(k_edge_contrib, dim3(grid_for(p.n_edges, 256, 8192)), dim3(256), 0, s,
                        p.n_edges, nbl, s_mem, s_exec, p.e_src.p, p.op_class.p, b.share.p, ev);
@@ -411,11 +442,14 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint3
     hipLaunchKernelGGL(k_gather<1>, dim3(grid_for(p.n_edges, 256, 8192)), dim3(256), 0, s,
                        (size_t)p.n_edges, nullptr, p.lca_perm.p, ev, ev_lca);
   }
-  seg_sum<1>(ns, p.icl_ptr.p, nullptr, big + ns, p.big_n.p + 1, ev_icl, own_icl, s);
-  seg_sum<1>(ns, p.lca_ptr.p, nullptr, big + 2 * (size_t)ns, p.big_n.p + 2, ev_lca, own_lca, s);
+  seg_sum<1>(ns, p.icl_ptr.p, nullptr, big + ns, p.big_n.p + 1, bch + ns, p.seg_chunks[1], ev_icl,
+             own_icl, s, ar);
+  seg_sum<1>(ns, p.lca_ptr.p, nullptr, big + 2 * (size_t)ns, p.big_n.p + 2, bch + 2 * (size_t)ns,
+             p.seg_chunks[2], ev_lca, own_lca, s, ar);
   hipLaunchKernelGGL(k_merge_edge_own, dim3(grid_for(ns, 256, 8192)), dim3(256), 0, s, ns, own_icl,
                      own_lca, own);
-  seg_sum<kNV>(ns, nullptr, p.scope_end.p, big + 3 * (size_t)ns, p.big_n.p + 3, own, sub, s);
+  seg_sum<kNV>(ns, nullptr, p.scope_end.p, big + 3 * (size_t)ns, p.big_n.p + 3,
+               bch + 3 * (size_t)ns, p.seg_chunks[3], own, sub, s, ar);
   GPA_LAUNCH_CHECK();
   a.active.alloc(ns);
   a.matched.alloc((size_t)ns * GPA_N_OPT);
