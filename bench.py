@@ -61,8 +61,8 @@ def _traffic(n_launches_ref=None):
     return t.get("bytes_per_pass")
 
 
-HIST_KERNELS = ("k_hsample", "k_hregions", "k_partition", "k_hist_totals", "k_bucket_plan",
-                "k_count", "k_merge", "k_hoverflow")
+HIST_KERNELS = ("k_hsample", "k_hregions", "k_partition", "k_hplan", "k_count", "k_merge",
+                "k_hoverflow")
 
 
 def _counter_rows(d):
