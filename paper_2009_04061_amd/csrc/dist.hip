@@ -43,6 +43,31 @@ __device__ __forceinline__ void bit_set(uint32_t &r0, uint32_t &r1, uint32_t v) 
 
 constexpr uint32_t kNoSucc = 0xFFFFu;
 
+// The first v >= from whose bit is set in (a & ~b), over the lane-spread
+// bitsets (two VGPRs each), or 0xFFFFFFFF: words below from's word and the
+// bits below from in that word are masked, then two ballots find the first
+// word with a bit left.
+__device__ __forceinline__ uint32_t first_set_from(uint32_t a0, uint32_t a1, uint32_t b0,
+                                                   uint32_t b1, uint32_t from) {
+  const uint32_t lane = lane_id();
+  const uint32_t fw = from >> 5, fb = from & 31u;
+  const uint32_t w0 = lane, w1 = lane + 64;
+  uint32_t c0 = a0 & ~b0, c1 = a1 & ~b1;
+  c0 = w0 < fw ? 0u : (w0 == fw ? c0 & (0xFFFFFFFFu << fb) : c0);
+  c1 = w1 < fw ? 0u : (w1 == fw ? c1 & (0xFFFFFFFFu << fb) : c1);
+  const uint64_t m0 = __ballot(c0 != 0u);
+  if (m0) {
+    const uint32_t l = (uint32_t)__builtin_ctzll(m0);
+    return l * 32u + (uint32_t)__builtin_ctz(__builtin_amdgcn_readlane(c0, l));
+  }
+  const uint64_t m1 = __ballot(c1 != 0u);
+  if (m1) {
+    const uint32_t l = (uint32_t)__builtin_ctzll(m1);
+    return (l + 64u) * 32u + (uint32_t)__builtin_ctz(__builtin_amdgcn_readlane(c1, l));
+  }
+  return 0xFFFFFFFFu;
+}
+
 // Chains: a block v whose only predecessor p has v as its only successor and
 // comes before it (p < v) is a chain member behind p.  The walk enters such a
 // v from p at once (v cannot be a root: p is reached no later than the root
@@ -95,9 +120,25 @@ k_dfs(const uint32_t *fbb, const uint32_t *succ_ptr, const uint32_t *succ,
   }
   __syncthreads();
   uint32_t vis0 = 0, vis1 = 0, fin0 = 0, fin1 = 0;
+  // the chain heads as a lane-spread bitset: 64 blocks per ballot, whose two
+  // words go to lanes w and w + 1 of the register that holds them
+  uint32_t hd0 = 0, hd1 = 0;
+  for (uint32_t v0 = 0; v0 < nb; v0 += 64) {
+    const uint32_t v = v0 + lane;
+    const uint64_t m = __ballot(v < nb && head[v] != 0);
+    const uint32_t w = v0 >> 5;   // even
+    const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+    if ((w >> 6) == 0) {
+      hd0 = lane == (w & 63) ? lo : hd0;
+      hd0 = lane == ((w + 1) & 63) ? hi : hd0;
+    } else {
+      hd1 = lane == (w & 63) ? lo : hd1;
+      hd1 = lane == ((w + 1) & 63) ? hi : hd1;
+    }
+  }
   uint32_t npost = 0;
-  for (uint32_t root = 0; root < nb; ++root) {
-    if (!head[root] || bit_test(vis0, vis1, root)) continue;
+  for (uint32_t root = first_set_from(hd0, hd1, vis0, vis1, 0); root < nb;
+       root = first_set_from(hd0, hd1, vis0, vis1, root + 1)) {
     bit_set(vis0, vis1, root);
     uint32_t sp = 0, u = root;
     uint2 r = rng[root];
