@@ -176,7 +176,7 @@ void run_blame(const gpa_program &p, gpa_blame &b, hipStream_t s, Arena &ar) {
                      b.share.p, b.self_.p);
   GPA_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_blame_src, dim3(grid_for(n, 128, 8192)), dim3(128), 0, s, n, nbl,
-                     (uint32_t)p.arch.blamable, p.out_ptr.p, p.out_perm.p, p.e_flags.p,
+                     (uint32_t)p.arch.blamable, p.out_ptr, p.out_perm, p.e_flags.p,
                      p.op_class.p, b.share.p, b.blamed.p, b.fine.p);
   GPA_LAUNCH_CHECK();
 }

@@ -115,14 +115,21 @@ struct gpa_program {
   gpa::DBuf<uint32_t> in_ptr;                  // [n_instr+1] edges into j
   gpa::DBuf<uint32_t> e_src, e_dst, e_dmin, e_dmax;
   gpa::DBuf<uint8_t> e_flags;
-  gpa::DBuf<uint32_t> out_ptr, out_perm;       // edges by source instruction
+  // stable groupings, built by one sort after the edges: edges by source
+  // instruction (out), by common scope (lca), by common loop (icl), and
+  // instructions by line scope (line); each view is laid out as if grouped
+  // alone: its ptr starts at 0 and indexes its own stretch of grp_perm
+  gpa::DBuf<uint32_t> grp_ptr, grp_perm;
+  const uint32_t *out_ptr = nullptr, *lca_ptr = nullptr, *icl_ptr = nullptr, *line_ptr = nullptr;
+  const uint32_t *out_perm = nullptr, *lca_perm = nullptr, *icl_perm = nullptr,
+                 *line_perm = nullptr;
   gpa::DBuf<uint32_t> rpo_pos, rpo_order;      // per block: topological position in G'
   gpa::DBuf<uint8_t> retreat;                  // per successor edge
   // scope structure for the estimators
   gpa::DBuf<uint32_t> scope_end, root_of, scope_depth;
   gpa::DBuf<uint32_t> e_lca, e_icl;            // per edge target scopes
   gpa::DBuf<uint8_t> instr_tags;               // bit0 in math fn, bit1 in device fn with CFG
-  gpa::DBuf<uint32_t> lca_ptr, lca_perm, icl_ptr, icl_perm, line_ptr, line_perm;
+
   // segments longer than a thread sums alone, per grouping (own sums by
   // scope, edges by common loop, edges by common scope, subtrees), each list
   // n_scopes long, counts in big_n[4]
@@ -168,6 +175,19 @@ void exclusive_scan_u32(const uint32_t *in, uint32_t *out, size_t n, hipStream_t
 // bits, and grouping of n items by key (GPA_NONE keys left out).
 void sort_pairs_u32(uint32_t *keys, uint32_t *vals, size_t n, uint32_t key_bits, hipStream_t s,
                     Arena &ar);
+// One stable sort for several groupings (see group_by_key): grouping q is
+// ptr.p + ptr_base[q] (n_keys + 1 entries) over perm.p + item_base[q], as if
+// it had been grouped alone; perm's entries are item indices inside the
+// grouping.
+constexpr uint32_t kMaxGroups = 4;
+struct GroupSpec {
+  const uint32_t *key;
+  uint64_t n;
+  uint32_t n_keys;
+};
+void group_by_keys(const GroupSpec *spec, int n_groups, DBuf<uint32_t> &ptr,
+                   DBuf<uint32_t> &perm, uint32_t *ptr_base, uint64_t *item_base,
+                   hipStream_t s, Arena &ar);
 void group_by_key(const uint32_t *key, size_t n, uint32_t n_keys, DBuf<uint32_t> &ptr,
                   DBuf<uint32_t> &perm, hipStream_t s, Arena &ar);
 

@@ -751,8 +751,7 @@ void build_edges(gpa_program &p, hipStream_t s, Arena &ar) {
   hipLaunchKernelGGL(k_edge_fill, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, p.use_ptr.p,
                      p.rd_ptr.p, items, p.in_ptr.p, p.e_src.p, p.e_dst.p, p.e_flags.p);
   GPA_LAUNCH_CHECK();
-  // by source instruction, in edge order inside each source
-  group_by_key(p.e_src.p, ne, n, p.out_ptr, p.out_perm, s, ar);
+  // (the grouping by source instruction is built with the target scopes)
 }
 
 }  // namespace gpa

@@ -640,14 +640,28 @@ void build_scope_targets(gpa_program &p, hipStream_t s, Arena &ar) {
                        p.scope_kind.p, p.block_of.p, p.func_of_block.p, p.func_scope.p, p.e_lca.p,
                        p.e_icl.p);
   GPA_LAUNCH_CHECK();
-  group_by_key(p.e_lca.p, ne, p.n_scopes, p.lca_ptr, p.lca_perm, s, ar);
-  group_by_key(p.e_icl.p, ne, p.n_scopes, p.icl_ptr, p.icl_perm, s, ar);
-  group_by_key(p.instr_scope.p, p.n_instr, p.n_scopes, p.line_ptr, p.line_perm, s, ar);
+  // one stable sort for the four groupings: edges by source instruction, by
+  // common scope and by common loop, instructions by line scope
+  const GroupSpec spec[4] = {{p.e_src.p, ne, p.n_instr},
+                             {p.e_lca.p, ne, p.n_scopes},
+                             {p.e_icl.p, ne, p.n_scopes},
+                             {p.instr_scope.p, p.n_instr, p.n_scopes}};
+  uint32_t base[4];
+  uint64_t ibase[4];
+  group_by_keys(spec, 4, p.grp_ptr, p.grp_perm, base, ibase, s, ar);
+  p.out_ptr = p.grp_ptr.p + base[0];
+  p.lca_ptr = p.grp_ptr.p + base[1];
+  p.icl_ptr = p.grp_ptr.p + base[2];
+  p.line_ptr = p.grp_ptr.p + base[3];
+  p.out_perm = p.grp_perm.p + ibase[0];
+  p.lca_perm = p.grp_perm.p + ibase[1];
+  p.icl_perm = p.grp_perm.p + ibase[2];
+  p.line_perm = p.grp_perm.p + ibase[3];
   const uint32_t ns = p.n_scopes;
   p.big_list.alloc((size_t)4 * ns);
   p.big_n.alloc(4);
   GPA_HIP(hipMemsetAsync(p.big_n.p, 0, 16, s));
-  const uint32_t *ptrs[4] = {p.line_ptr.p, p.icl_ptr.p, p.lca_ptr.p, nullptr};
+  const uint32_t *ptrs[4] = {p.line_ptr, p.icl_ptr, p.lca_ptr, nullptr};
   for (int g = 0; g < 4; ++g)
     hipLaunchKernelGGL(k_big_segments, dim3(grid_for(ns, 256, 4096)), dim3(256), 0, s, ns, ptrs[g],
                        p.scope_end.p, p.big_list.p + (size_t)g * ns, p.big_n.p + g);

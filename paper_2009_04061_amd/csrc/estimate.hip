@@ -429,22 +429,22 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint3
   hipLaunchKernelGGL(k_instr_contrib, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, nbl, bl,
                      b.counts.p, b.blamed.p, b.self_.p, p.op_class.p, p.instr_tags.p, iv);
   hipLaunchKernelGGL(k_gather<kNV>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, (size_t)n,
-                     nullptr, p.line_perm.p, iv, iv_g);
+                     nullptr, p.line_perm, iv, iv_g);
   const uint32_t *big = p.big_list.p;
   const uint32_t *bch = p.big_chunk.p;
-  seg_sum<kNV>(ns, p.line_ptr.p, nullptr, big, p.big_n.p, bch, p.seg_chunks[0], iv_g, own, s, ar);
+  seg_sum<kNV>(ns, p.line_ptr, nullptr, big, p.big_n.p, bch, p.seg_chunks[0], iv_g, own, s, ar);
   if (p.n_edges) {
     hipLaunchKernelGGL(k_edge_contrib, dim3(grid_for(p.n_edges, 256, 8192)), dim3(256), 0, s,
                        p.n_edges, nbl, s_mem, s_exec, p.e_src.p, p.op_class.p, b.share.p, ev);
     // edges without a common loop are not in the icl grouping: its size is icl_ptr[ns]
     hipLaunchKernelGGL(k_gather<1>, dim3(grid_for(p.n_edges, 256, 8192)), dim3(256), 0, s,
-                       (size_t)p.n_edges, p.icl_ptr.p + ns, p.icl_perm.p, ev, ev_icl);
+                       (size_t)p.n_edges, p.icl_ptr + ns, p.icl_perm, ev, ev_icl);
     hipLaunchKernelGGL(k_gather<1>, dim3(grid_for(p.n_edges, 256, 8192)), dim3(256), 0, s,
-                       (size_t)p.n_edges, nullptr, p.lca_perm.p, ev, ev_lca);
+                       (size_t)p.n_edges, nullptr, p.lca_perm, ev, ev_lca);
   }
-  seg_sum<1>(ns, p.icl_ptr.p, nullptr, big + ns, p.big_n.p + 1, bch + ns, p.seg_chunks[1], ev_icl,
+  seg_sum<1>(ns, p.icl_ptr, nullptr, big + ns, p.big_n.p + 1, bch + ns, p.seg_chunks[1], ev_icl,
              own_icl, s, ar);
-  seg_sum<1>(ns, p.lca_ptr.p, nullptr, big + 2 * (size_t)ns, p.big_n.p + 2, bch + 2 * (size_t)ns,
+  seg_sum<1>(ns, p.lca_ptr, nullptr, big + 2 * (size_t)ns, p.big_n.p + 2, bch + 2 * (size_t)ns,
              p.seg_chunks[2], ev_lca, own_lca, s, ar);
   hipLaunchKernelGGL(k_merge_edge_own, dim3(grid_for(ns, 256, 8192)), dim3(256), 0, s, ns, own_icl,
                      own_lca, own);
