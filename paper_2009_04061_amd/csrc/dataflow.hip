@@ -174,20 +174,6 @@ __device__ Survive survivors_range(const uint32_t *dI, const uint8_t *dG, const 
   return r;
 }
 
-// The same for the instructions [i_begin, i_end) of one block, given the
-// (function, x) arrays: dI/dG per def ordinal, uI per sorted use.
-__device__ Survive survivors(const uint32_t *dI, const uint8_t *dG, uint32_t nd, const uint32_t *uI,
-                             uint32_t nu, uint32_t i_begin, uint32_t i_end, uint32_t c,
-                             bool blocked) {
-  const uint32_t lo = lower_pos(dI, 0, nd, i_begin), hi = lower_pos(dI, lo, nd, i_end);
-  uint32_t ulo = 0, uhi = 0;
-  if (blocked) {
-    ulo = lower_pos(uI, 0, nu, i_begin);
-    uhi = lower_pos(uI, ulo, nu, i_end);
-  }
-  return survivors_range(dI, dG, uI, lo, hi, ulo, uhi, c, blocked);
-}
-
 __device__ __forceinline__ uint64_t range_word(uint32_t lo, uint32_t hi, uint32_t w0) {
   // bits [lo, hi) intersected with word [w0, w0+64), shifted to the word
   const uint32_t a = max(lo, w0), b = min(hi, w0 + 64);
@@ -542,7 +528,8 @@ __global__ void k_rd_lists(uint32_t n_uses, int fill, const uint32_t *use_instr,
                            const uint32_t *fl_chunks, const uint32_t *use_rank,
                            const uint32_t *slot_start, const uint64_t *rd_in, uint32_t *rd_cnt,
                            const uint32_t *rd_ptr, uint32_t *rd_src, uint8_t *rd_blk,
-                           uint8_t *rd_nonrbar) {
+                           uint8_t *rd_nonrbar, uint32_t n_blocks, const uint4 *t0,
+                           const uint2 *t1) {
   for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n_uses; u += gridDim.x * blockDim.x) {
     const uint32_t j = use_instr[u], x = use_loc[u];
     const uint32_t b = block_of[j], f = func_of_block[b];
@@ -552,14 +539,22 @@ __global__ void k_rd_lists(uint32_t n_uses, int fill, const uint32_t *use_instr,
       if (!fill) rd_cnt[u] = 0;
       continue;
     }
-    const uint32_t u0 = fl_use_ptr[fi], nu = fl_use_ptr[fi + 1] - u0;
     const size_t q = (size_t)f * n_loc + x;
     const uint32_t W = fl_words[q], chunks = fl_chunks[q];
     const uint64_t *in = rd_in + slot_start[use_rank[u]];
-    const uint32_t c = use_cond[u], i0 = block_begin[b];
-    const Survive sF = survivors(dsi + d0, dsg + d0, nd, usi + u0, nu, i0, j, c, false);
-    const Survive sB = survivors(dsi + d0, dsg + d0, nd, usi + u0, nu, i0, j, c, true);
-    const uint32_t pj = sF.hi;
+    const uint32_t c = use_cond[u];
+    // the defs and uses of x in j's block before j, from the block's index
+    // entry (absolute positions in the sorted arrays), then relative to d0
+    const size_t tk = (size_t)x * n_blocks + b;
+    const uint4 r = t0[tk];
+    const uint2 ur = t1[tk];
+    const uint32_t lo = r.w, hi = lower_pos(dsi, r.w, r.z, j);
+    const uint32_t ulo = ur.x, uhi = lower_pos(usi, ur.x, ur.y, j);
+    Survive sF = survivors_range(dsi, dsg, usi, lo, hi, ulo, uhi, c, false);
+    Survive sB = survivors_range(dsi, dsg, usi, lo, hi, ulo, uhi, c, true);
+    sF.g -= d0;
+    sB.g -= d0;
+    const uint32_t pj = hi - d0;
     uint32_t cnt = 0;
     uint32_t pos = fill ? rd_ptr[u] : 0;
     for (uint32_t k = 0; k < chunks; ++k) {
@@ -670,6 +665,13 @@ void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar, PhaseTimer &t
   GPA_HIP(hipStreamSynchronize(s));
   p.n_roots_dev = nullptr;
   uint64_t *rd_in = ar.get<uint64_t>(nslot ? nslot : 1);
+  // the (location, block) index: the searches and the per-use lists read it
+  uint4 *t0 = ar.get<uint4>((size_t)nl * nb);
+  uint2 *t1 = ar.get<uint2>((size_t)nl * nb);
+  hipLaunchKernelGGL(k_loc_block_index, dim3(grid_for((size_t)nl * nb, 256, 8192)), dim3(256), 0,
+                     s, nb, nl, p.func_of_block.p, p.block_begin.p, p.fl_def_ptr.p,
+                     p.fl_use_ptr.p, dsi, dsg, usi, t0, t1);
+  GPA_LAUNCH_CHECK();
   if (nslot) {
     const size_t lds_long = kStageRows + 8u * (size_t)max_words + kStagePred +
                             4u * ((p.max_func_blocks + 31) / 32) + 4u * (size_t)p.max_func_blocks;
@@ -677,12 +679,6 @@ void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar, PhaseTimer &t
       fail(GPA_E_UNSUPPORTED, "a location has %u defs in one function (too many for one search)",
            64u * max_words);
     GPA_HIP(hipMemsetAsync(rd_in, 0, 8 * nslot, s));
-    uint4 *t0 = ar.get<uint4>((size_t)nl * nb);
-    uint2 *t1 = ar.get<uint2>((size_t)nl * nb);
-    hipLaunchKernelGGL(k_loc_block_index, dim3(grid_for((size_t)nl * nb, 256, 8192)), dim3(256),
-                       0, s, nb, nl, p.func_of_block.p, p.block_begin.p, p.fl_def_ptr.p,
-                       p.fl_use_ptr.p, dsi, dsg, usi, t0, t1);
-    GPA_LAUNCH_CHECK();
     uint32_t *long_list = ar.get<uint32_t>(p.n_uses);
     t_search.begin(kPhaseRdSearch, s);
     // two staged index rows per workgroup when the largest function fits
@@ -714,7 +710,7 @@ void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar, PhaseTimer &t
                      p.use_instr.p, p.use_loc.p, p.use_cond.p, p.block_of.p, p.func_of_block.p,
                      p.block_begin.p, dsi, dsg, usi, p.def_site_sorted.p, p.def_kind.p,
                      p.fl_def_ptr.p, p.fl_use_ptr.p, nl, fl_words, fl_chunks, p.use_rank.p,
-                     slot_start, rd_in, rd_cnt, nullptr, nullptr, nullptr, nullptr);
+                     slot_start, rd_in, rd_cnt, nullptr, nullptr, nullptr, nullptr, nb, t0, t1);
   GPA_LAUNCH_CHECK();
   p.rd_ptr.alloc(p.n_uses + 1);
   unsigned long long *nrd_d = ar.get<unsigned long long>(1);
@@ -728,7 +724,7 @@ void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar, PhaseTimer &t
                      p.block_begin.p, dsi, dsg, usi, p.def_site_sorted.p, p.def_kind.p,
                      p.fl_def_ptr.p, p.fl_use_ptr.p, nl, fl_words, fl_chunks, p.use_rank.p,
                      slot_start, rd_in, nullptr, p.rd_ptr.p, p.rd_src.p, p.rd_blk.p,
-                     p.rd_nonrbar.p);
+                     p.rd_nonrbar.p, nb, t0, t1);
   GPA_LAUNCH_CHECK();
 }
 

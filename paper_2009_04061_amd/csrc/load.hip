@@ -265,7 +265,9 @@ k_chunk_hist(const SiteChunk *chunks, const unsigned long long *n_chunks, const 
 }
 
 // per function: start of each (function, location) list (fl_ptr) and each
-// chunk's base inside it (written over the per-chunk counts)
+// chunk's offset inside its location's list (written over the per-chunk
+// counts; k_chunk_scatter adds the list start).  Each thread takes up to 4
+// locations and walks their columns eight chunks per batch of loads.
 __global__ void __launch_bounds__(kSortThreads)
 k_chunk_bases(uint32_t n_funcs, const uint32_t *fbb, const uint32_t *block_begin,
               const uint32_t *site_ptr, const uint32_t *chunk_start, const uint32_t *nchunks,
@@ -278,23 +280,33 @@ k_chunk_bases(uint32_t n_funcs, const uint32_t *fbb, const uint32_t *block_begin
   const uint32_t x0 = min(threadIdx.x * per, n_loc), x1 = min(x0 + per, n_loc);
   uint32_t tot[4] = {0, 0, 0, 0};
   uint32_t mytot = 0;
-  for (uint32_t x = x0; x < x1; ++x) {
+#pragma unroll
+  for (uint32_t i = 0; i < 4; ++i) {
+    const uint32_t x = x0 + i;
+    if (x >= x1) continue;
     uint32_t run = 0;
-    for (uint32_t c = 0; c < nc; ++c) {
-      uint32_t *q = &chunk_cnt[(size_t)(c0 + c) * n_loc + x];
-      const uint32_t v = *q;
-      *q = run;
-      run += v;
+    for (uint32_t c = 0; c < nc; c += 8) {
+      uint32_t v[8];
+#pragma unroll
+      for (uint32_t j = 0; j < 8; ++j)
+        v[j] = c + j < nc ? chunk_cnt[(size_t)(c0 + c + j) * n_loc + x] : 0u;
+#pragma unroll
+      for (uint32_t j = 0; j < 8; ++j) {
+        if (c + j < nc) chunk_cnt[(size_t)(c0 + c + j) * n_loc + x] = run;
+        run += v[j];
+      }
     }
-    tot[x - x0] = run;
+    tot[i] = run;
     mytot += run;
   }
   uint32_t total;
   uint32_t base = block_excl_scan<kSortThreads>(mytot, tmp, &total) + s0;
-  for (uint32_t x = x0; x < x1; ++x) {
+#pragma unroll
+  for (uint32_t i = 0; i < 4; ++i) {
+    const uint32_t x = x0 + i;
+    if (x >= x1) continue;
     fl_ptr[(size_t)f * (n_loc + 1) + x] = base;
-    for (uint32_t c = 0; c < nc; ++c) chunk_cnt[(size_t)(c0 + c) * n_loc + x] += base;
-    base += tot[x - x0];
+    base += tot[i];
   }
 }
 
@@ -303,8 +315,8 @@ k_chunk_bases(uint32_t n_funcs, const uint32_t *fbb, const uint32_t *block_begin
 // wave plus per-wave counts in LDS; per-location cursors carry across rounds.
 __global__ void __launch_bounds__(kSortThreads)
 k_chunk_scatter(const SiteChunk *chunks, const unsigned long long *n_chunks, const uint32_t *key,
-                uint32_t n_loc, uint32_t key_bits, const uint32_t *chunk_base, uint32_t *sorted,
-                uint32_t *rank_of) {
+                uint32_t n_loc, uint32_t key_bits, const uint32_t *chunk_base,
+                const uint32_t *fl_ptr, uint32_t *sorted, uint32_t *rank_of) {
   extern __shared__ uint32_t sh[];
   uint32_t *cursor = sh;                        // [n_loc]
   uint32_t *wcnt = sh + n_loc;                  // [4][n_loc]
@@ -313,7 +325,7 @@ k_chunk_scatter(const SiteChunk *chunks, const unsigned long long *n_chunks, con
   const SiteChunk ch = chunks[blockIdx.x];
   const unsigned tid = threadIdx.x, w = tid / kWave, lane = lane_id();
   for (uint32_t x = tid; x < n_loc; x += kSortThreads) {
-    cursor[x] = chunk_base[(size_t)blockIdx.x * n_loc + x];
+    cursor[x] = chunk_base[(size_t)blockIdx.x * n_loc + x] + fl_ptr[(size_t)ch.func * (n_loc + 1) + x];
     for (int k = 0; k < NW; ++k) wcnt[k * n_loc + x] = 0;
   }
   __syncthreads();
@@ -505,7 +517,7 @@ static void sort_sites(gpa_program &p, hipStream_t s, Arena &ar, const uint32_t 
   while ((1u << key_bits) < nl) ++key_bits;
   const size_t lds = (size_t)nl * 4 * (1 + kSortThreads / kWave);
   hipLaunchKernelGGL(k_chunk_scatter, dim3(n_chunks), dim3(kSortThreads), lds, s, chunks, ntot, key,
-                     nl, key_bits, ccnt, sorted.p, rank_of);
+                     nl, key_bits, ccnt, fl_ptr.p, sorted.p, rank_of);
   GPA_LAUNCH_CHECK();
 }
 
