@@ -216,6 +216,11 @@ void build_cfg_order(gpa_program &p, hipStream_t s, Arena &ar, SweepPlan &plan,
                      PhaseTimer &t_dfs);
 // Block-to-block walk tables of every function (shortest and longest G'
 // walks from each block to each block of its function), from the CFG alone.
+// per-opcode-class latency bounds, passed to a kernel by value
+struct LatTable {
+  uint16_t v[16];
+};
+
 struct DistTables {
   uint32_t *off = nullptr;   // [n_funcs] first entry of the function's tables
   uint32_t *sp = nullptr;    // shortest walk lengths, kInf-saturated

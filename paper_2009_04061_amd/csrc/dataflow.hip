@@ -56,8 +56,10 @@ __device__ __forceinline__ uint32_t lower_pos(const uint32_t *a, uint32_t lo, ui
 __global__ void k_sorted_views(uint32_t n_defs, uint32_t n_uses, const uint32_t *def_site_sorted,
                                const uint32_t *def_instr, const uint32_t *use_site_sorted,
                                const uint32_t *use_instr, const uint8_t *guard, uint32_t *dsi,
-                               uint8_t *dsg, uint32_t *usi) {
+                               uint8_t *dsg, uint32_t *usi, uint32_t *scal) {
   const uint32_t tot = n_defs + n_uses;
+  // the plan's largest word count and the long-search counter start at zero
+  if (blockIdx.x == 0 && threadIdx.x < 2) scal[threadIdx.x] = 0;
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < tot; k += gridDim.x * blockDim.x) {
     if (k < n_defs) {
       const uint32_t i = def_instr[def_site_sorted[k]];
@@ -341,6 +343,11 @@ k_rd_search(uint32_t n_uses, uint32_t n_blocks, uint32_t n_loc, uint32_t row_nb,
   uint64_t acc[kRegWords];
 #pragma unroll
   for (uint32_t w = 0; w < kRegWords; ++w) acc[w] = 0ull;
+  // every word of the slot is written by its own search: registers for a
+  // short bitset, stored at the end; a long one is cleared here and built in
+  // place (a search that overflows is redone whole by the long kernel)
+  if (!local)
+    for (uint32_t w = 0; w < nw; ++w) in[2 * w] = 0ull;
   uint32_t n_seen = 0, head = 0;
   uint64_t fl0 = 0, fl1 = 0, fl2 = 0, fl3 = 0;
   bool ok = true;
@@ -530,6 +537,8 @@ __global__ void k_rd_lists(uint32_t n_uses, int fill, const uint32_t *use_instr,
                            const uint32_t *rd_ptr, uint32_t *rd_src, uint8_t *rd_blk,
                            uint8_t *rd_nonrbar, uint32_t n_blocks, const uint4 *t0,
                            const uint2 *t1) {
+  // the count array's extra entry, so that its exclusive scan ends in the total
+  if (!fill && blockIdx.x == 0 && threadIdx.x == 0) rd_cnt[n_uses] = 0;
   for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n_uses; u += gridDim.x * blockDim.x) {
     const uint32_t j = use_instr[u], x = use_loc[u];
     const uint32_t b = block_of[j], f = func_of_block[b];
@@ -586,6 +595,7 @@ __global__ void k_rd_lists(uint32_t n_uses, int fill, const uint32_t *use_instr,
 __global__ void k_edge_sort(uint32_t n_instr, const uint32_t *use_ptr, const uint32_t *rd_ptr,
                             const uint32_t *rd_src, const uint8_t *rd_blk,
                             const uint8_t *rd_nonrbar, uint64_t *items, uint32_t *in_cnt) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) in_cnt[n_instr] = 0;   // the scan's extra entry
   for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_instr;
        j += gridDim.x * blockDim.x) {
     const uint32_t a = rd_ptr[use_ptr[j]], b = rd_ptr[use_ptr[j + 1]];
@@ -637,13 +647,12 @@ void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar, PhaseTimer &t
   const size_t nfl = (size_t)nf * nl;
   uint32_t *dsi = ar.get<uint32_t>(p.n_defs), *usi = ar.get<uint32_t>(p.n_uses);
   uint8_t *dsg = ar.get<uint8_t>(p.n_defs);
+  uint32_t *scal = ar.get<uint32_t>(2);   // [0] largest IN bitset in words, [1] long searches
   hipLaunchKernelGGL(k_sorted_views, dim3(grid_for((size_t)p.n_defs + p.n_uses, 256, 8192)),
                      dim3(256), 0, s, p.n_defs, p.n_uses, p.def_site_sorted.p, p.def_instr.p,
-                     p.use_site_sorted.p, p.use_instr.p, p.guard.p, dsi, dsg, usi);
+                     p.use_site_sorted.p, p.use_instr.p, p.guard.p, dsi, dsg, usi, scal);
   GPA_LAUNCH_CHECK();
   uint32_t *fl_words = ar.get<uint32_t>(nfl), *fl_chunks = ar.get<uint32_t>(nfl);
-  uint32_t *scal = ar.get<uint32_t>(2);   // [0] largest IN bitset in words, [1] long searches
-  GPA_HIP(hipMemsetAsync(scal, 0, 8, s));
   hipLaunchKernelGGL(k_rd_plan, dim3(grid_for(nfl, 256, 4096)), dim3(256), 0, s, nf, nl,
                      p.fl_def_ptr.p, fl_words, fl_chunks, scal);
   GPA_LAUNCH_CHECK();
@@ -678,7 +687,6 @@ void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar, PhaseTimer &t
     if (lds_long > 160 * 1024)
       fail(GPA_E_UNSUPPORTED, "a location has %u defs in one function (too many for one search)",
            64u * max_words);
-    GPA_HIP(hipMemsetAsync(rd_in, 0, 8 * nslot, s));
     uint32_t *long_list = ar.get<uint32_t>(p.n_uses);
     t_search.begin(kPhaseRdSearch, s);
     // two staged index rows per workgroup when the largest function fits
@@ -705,7 +713,6 @@ void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar, PhaseTimer &t
   }
   // per-use source lists
   uint32_t *rd_cnt = ar.get<uint32_t>(p.n_uses + 1);
-  GPA_HIP(hipMemsetAsync(rd_cnt + p.n_uses, 0, 4, s));
   hipLaunchKernelGGL(k_rd_lists, dim3(grid_for(p.n_uses, 256, 8192)), dim3(256), 0, s, p.n_uses, 0,
                      p.use_instr.p, p.use_loc.p, p.use_cond.p, p.block_of.p, p.func_of_block.p,
                      p.block_begin.p, dsi, dsg, usi, p.def_site_sorted.p, p.def_kind.p,
@@ -732,7 +739,6 @@ void build_edges(gpa_program &p, hipStream_t s, Arena &ar) {
   const uint32_t n = p.n_instr;
   uint64_t *items = ar.get<uint64_t>(p.n_rd);
   uint32_t *in_cnt = ar.get<uint32_t>(n + 1);
-  GPA_HIP(hipMemsetAsync(in_cnt + n, 0, 4, s));
   hipLaunchKernelGGL(k_edge_sort, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, p.use_ptr.p,
                      p.rd_ptr.p, p.rd_src.p, p.rd_blk.p, p.rd_nonrbar.p, items, in_cnt);
   GPA_LAUNCH_CHECK();

@@ -11,6 +11,8 @@
 //   are retreating in a depth-first search from the entry (successors in
 //   CSR order, then from every unvisited block in index order), or dmin when
 //   G' has no such walk.
+#include <cstring>
+
 #include "common.h"
 #include "devutil.h"
 
@@ -445,7 +447,7 @@ k_dist_tables(uint32_t n_blocks, uint32_t n_funcs, uint32_t L, const uint32_t *f
 __global__ void k_edge_dist(uint64_t n_edges, const uint32_t *e_src, const uint32_t *e_dst,
                             const uint32_t *block_of, const uint32_t *func_of_block,
                             const uint32_t *fbb, const uint32_t *block_begin,
-                            const uint8_t *op_class, const uint16_t *lat_tab,
+                            const uint8_t *op_class, LatTable lat_tab,
                             const uint32_t *tab_off, const uint32_t *t_sp, const uint32_t *t_lp,
                             uint32_t *e_dmin, uint32_t *e_dmax, uint8_t *e_flags) {
   for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < n_edges;
@@ -469,7 +471,7 @@ __global__ void k_edge_dist(uint64_t n_edges, const uint32_t *e_src, const uint3
     }
     e_dmin[e] = dmin;
     e_dmax[e] = dmax;
-    if (dmin <= lat_tab[op_class[src]]) e_flags[e] |= GPA_E_LAT_KEEP;
+    if (dmin <= lat_tab.v[op_class[src] & 15]) e_flags[e] |= GPA_E_LAT_KEEP;
   }
 }
 
@@ -557,8 +559,9 @@ void build_distances(gpa_program &p, hipStream_t s, Arena &ar, const DistTables 
   p.e_dmin.alloc(ne);
   p.e_dmax.alloc(ne);
   if (ne == 0) return;
-  uint16_t *lat = ar.get<uint16_t>(16);
-  GPA_HIP(hipMemcpyAsync(lat, p.arch.lat, sizeof(p.arch.lat), hipMemcpyHostToDevice, s));
+  LatTable lat;
+  static_assert(sizeof(lat.v) == sizeof(p.arch.lat), "latency table size");
+  std::memcpy(lat.v, p.arch.lat, sizeof(lat.v));
   hipLaunchKernelGGL(k_edge_dist, dim3(grid_for(ne, 256, 8192)), dim3(256), 0, s, ne, p.e_src.p,
                      p.e_dst.p, p.block_of.p, p.func_of_block.p, p.func_block_begin.p,
                      p.block_begin.p, p.op_class.p, lat, t.off, t.sp, t.lp, p.e_dmin.p,
@@ -571,7 +574,10 @@ __global__ void k_edge_scopes(uint64_t n_edges, const uint32_t *e_src, const uin
                               const uint32_t *instr_scope, const uint32_t *parent,
                               const uint32_t *depth, const uint8_t *kind,
                               const uint32_t *block_of, const uint32_t *func_of_block,
-                              const uint32_t *func_scope, uint32_t *e_lca, uint32_t *e_icl) {
+                              const uint32_t *func_scope, uint32_t *e_lca, uint32_t *e_icl,
+                              uint32_t *big_n) {
+  // the big-segment counters of the roll-up lists, appended to later
+  if (blockIdx.x == 0 && threadIdx.x < 4) big_n[threadIdx.x] = 0;
   for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < n_edges;
        e += (uint64_t)gridDim.x * blockDim.x) {
     uint32_t a = instr_scope[e_src[e]], b = instr_scope[e_dst[e]];
@@ -590,12 +596,18 @@ __global__ void k_edge_scopes(uint64_t n_edges, const uint32_t *e_src, const uin
   }
 }
 
-// segments of more than kSmallSeg elements, listed for a workgroup each
-__global__ void k_big_segments(uint32_t n_seg, const uint32_t *ptr, const uint32_t *end,
-                               uint32_t *list, uint32_t *n_list) {
+// segments of more than kSmallSeg elements, listed for a workgroup each;
+// grid row g serves grouping g (the fourth lists scopes by their [l, end)
+// ranges)
+__global__ void k_big_segments(uint32_t n_seg, const uint32_t *ptr0, const uint32_t *ptr1,
+                               const uint32_t *ptr2, const uint32_t *end, uint32_t *list,
+                               uint32_t *n_list) {
+  const uint32_t g = blockIdx.y;
+  const uint32_t *ptr = g == 0 ? ptr0 : g == 1 ? ptr1 : g == 2 ? ptr2 : nullptr;
+  uint32_t *lst = list + (size_t)g * n_seg;
   for (uint32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < n_seg; l += gridDim.x * blockDim.x) {
     const uint32_t a = ptr ? ptr[l] : l, b = ptr ? ptr[l + 1] : end[l];
-    if (b - a > kSmallSeg) list[atomicAdd(n_list, 1u)] = l;
+    if (b - a > kSmallSeg) lst[atomicAdd(n_list + g, 1u)] = l;
   }
 }
 
@@ -634,11 +646,11 @@ void build_scope_targets(gpa_program &p, hipStream_t s, Arena &ar) {
   const uint64_t ne = p.n_edges;
   p.e_lca.alloc(ne);
   p.e_icl.alloc(ne);
-  if (ne)
-    hipLaunchKernelGGL(k_edge_scopes, dim3(grid_for(ne, 256, 8192)), dim3(256), 0, s, ne,
-                       p.e_src.p, p.e_dst.p, p.instr_scope.p, p.scope_parent.p, p.scope_depth.p,
-                       p.scope_kind.p, p.block_of.p, p.func_of_block.p, p.func_scope.p, p.e_lca.p,
-                       p.e_icl.p);
+  p.big_n.alloc(4);
+  hipLaunchKernelGGL(k_edge_scopes, dim3(grid_for(ne, 256, 8192)), dim3(256), 0, s, ne, p.e_src.p,
+                     p.e_dst.p, p.instr_scope.p, p.scope_parent.p, p.scope_depth.p,
+                     p.scope_kind.p, p.block_of.p, p.func_of_block.p, p.func_scope.p, p.e_lca.p,
+                     p.e_icl.p, p.big_n.p);
   GPA_LAUNCH_CHECK();
   // one stable sort for the four groupings: edges by source instruction, by
   // common scope and by common loop, instructions by line scope
@@ -659,12 +671,9 @@ void build_scope_targets(gpa_program &p, hipStream_t s, Arena &ar) {
   p.line_perm = p.grp_perm.p + ibase[3];
   const uint32_t ns = p.n_scopes;
   p.big_list.alloc((size_t)4 * ns);
-  p.big_n.alloc(4);
-  GPA_HIP(hipMemsetAsync(p.big_n.p, 0, 16, s));
-  const uint32_t *ptrs[4] = {p.line_ptr, p.icl_ptr, p.lca_ptr, nullptr};
-  for (int g = 0; g < 4; ++g)
-    hipLaunchKernelGGL(k_big_segments, dim3(grid_for(ns, 256, 4096)), dim3(256), 0, s, ns, ptrs[g],
-                       p.scope_end.p, p.big_list.p + (size_t)g * ns, p.big_n.p + g);
+  const uint32_t *ptrs[3] = {p.line_ptr, p.icl_ptr, p.lca_ptr};
+  hipLaunchKernelGGL(k_big_segments, dim3(grid_for(ns, 256, 4096), 4), dim3(256), 0, s, ns,
+                     ptrs[0], ptrs[1], ptrs[2], p.scope_end.p, p.big_list.p, p.big_n.p);
   GPA_LAUNCH_CHECK();
   // the big segments' chunks: first chunk of each listed segment, and the
   // totals (read by the host with the load's last synchronization)

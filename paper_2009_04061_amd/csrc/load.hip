@@ -77,13 +77,15 @@ __global__ void k_val_sites(uint32_t n, const uint32_t *loc, const uint8_t *kind
 __global__ void k_val_ends(uint32_t n_instr, uint32_t n_blocks, uint32_t n_funcs,
                            const uint32_t *def_ptr, const uint32_t *use_ptr,
                            const uint32_t *block_begin, const uint32_t *succ_ptr,
-                           const uint32_t *fbb, uint32_t *err) {
+                           const uint32_t *fbb, uint32_t *vals) {
+  // first of the checks: it also clears the verdict words the others update
   uint32_t e = 0;
   if (def_ptr[0] != 0 || use_ptr[0] != 0) e |= kErrCsr;
   if (block_begin[0] != 0 || block_begin[n_blocks] != n_instr) e |= kErrBlocks;
   if (succ_ptr[0] != 0) e |= kErrSucc;
   if (fbb[0] != 0 || fbb[n_funcs] != n_blocks) e |= kErrFuncs;
-  if (e) atomicOr(err, e);
+  vals[0] = e;
+  for (int q = 1; q < 8; ++q) vals[q] = 0;
 }
 
 __global__ void k_val_funcs(uint32_t n_funcs, uint32_t n_scopes, const uint32_t *fbb,
@@ -121,11 +123,13 @@ __global__ void k_val_scopes(uint32_t n_scopes, const uint32_t *parent, const ui
 // rejects a block_begin that is not strictly increasing)
 __global__ void k_blocks(uint32_t n_funcs, uint32_t n_blocks, uint32_t n_instr, const uint32_t *fbb,
                          const uint32_t *block_begin, uint32_t *block_of, uint32_t *func_of_block,
-                         uint32_t *err) {
+                         uint32_t *pred_cnt, uint32_t *err) {
   uint32_t e = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) pred_cnt[n_blocks] = 0;
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n_blocks + n_instr;
        k += gridDim.x * blockDim.x) {
     if (k < n_blocks) {
+      pred_cnt[k] = 0;
       func_of_block[k] = upper_index_u32(fbb, 0, n_funcs, k);
       const uint32_t i0 = block_begin[k], i1 = block_begin[k + 1];
       if (i0 >= i1 || i1 > n_instr) e |= kErrBlocks;
@@ -308,6 +312,8 @@ k_chunk_bases(uint32_t n_funcs, const uint32_t *fbb, const uint32_t *block_begin
     fl_ptr[(size_t)f * (n_loc + 1) + x] = base;
     base += tot[i];
   }
+  // the function's closing entry: one past its last site
+  if (threadIdx.x == 0) fl_ptr[(size_t)f * (n_loc + 1) + n_loc] = s0 + total;
 }
 
 // Stable scatter: rounds of kSortThreads consecutive sites; the rank of a
@@ -499,9 +505,12 @@ static void sort_sites(gpa_program &p, hipStream_t s, Arena &ar, const uint32_t 
   const uint32_t n_chunks = (uint32_t)(n_sites / kChunk + nf);
   sorted.alloc(n_sites);
   fl_ptr.alloc((size_t)nf * (nl + 1));
-  // the end of every (function, location) list is the start of the next one
-  GPA_HIP(hipMemsetAsync(fl_ptr.p, 0, sizeof(uint32_t) * fl_ptr.n, s));
-  if (n_sites == 0) return;
+  // without sites every list is empty; otherwise k_chunk_bases writes every
+  // list start and each function's closing entry
+  if (n_sites == 0) {
+    GPA_HIP(hipMemsetAsync(fl_ptr.p, 0, sizeof(uint32_t) * fl_ptr.n, s));
+    return;
+  }
   SiteChunk *chunks = ar.get<SiteChunk>(n_chunks);
   hipLaunchKernelGGL(k_chunk_fill, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf,
                      p.func_block_begin.p, p.block_begin.p, site_ptr, cstart, chunks);
@@ -521,13 +530,6 @@ static void sort_sites(gpa_program &p, hipStream_t s, Arena &ar, const uint32_t 
   GPA_LAUNCH_CHECK();
 }
 
-__global__ void k_fl_close(uint32_t n_funcs, uint32_t n_loc, const uint32_t *fbb,
-                           const uint32_t *block_begin, const uint32_t *site_ptr, uint32_t *fl_ptr) {
-  for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < n_funcs;
-       f += gridDim.x * blockDim.x)
-    fl_ptr[(size_t)f * (n_loc + 1) + n_loc] = site_ptr[block_begin[fbb[f + 1]]];
-}
-
 void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar) {
   const uint32_t n = p.n_instr, nb = p.n_blocks, nf = p.n_funcs, ns = p.n_scopes;
   // Every check and the maps they need run before one read of the verdict;
@@ -536,9 +538,8 @@ void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar) {
   // (words 2-5, see k_max_func_blocks).
   uint32_t *vals = ar.get<uint32_t>(8);
   uint32_t *err = vals, *mx = vals + 2;
-  GPA_HIP(hipMemsetAsync(vals, 0, 32, s));
   hipLaunchKernelGGL(k_val_ends, dim3(1), dim3(1), 0, s, n, nb, nf, p.def_ptr.p, p.use_ptr.p,
-                     p.block_begin.p, p.succ_ptr.p, p.func_block_begin.p, err);
+                     p.block_begin.p, p.succ_ptr.p, p.func_block_begin.p, vals);
   hipLaunchKernelGGL(k_val_instr, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, n, p.n_preds, ns,
                      p.n_defs, p.n_uses, p.op_class.p, p.guard.p, p.def_ptr.p, p.use_ptr.p, p.def_loc.p,
                      p.instr_scope.p, p.scope_kind.p, err);
@@ -554,12 +555,11 @@ void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar) {
   // function and block maps (binary searches, in bounds on any input)
   p.block_of.alloc(n);
   p.func_of_block.alloc(nb);
+  uint32_t *pcnt = ar.get<uint32_t>(nb + 1);   // predecessor counts, cleared by k_blocks
   hipLaunchKernelGGL(k_blocks, dim3(grid_for((size_t)nb + n, 256, 4096)), dim3(256), 0, s, nf, nb,
                      n, p.func_block_begin.p, p.block_begin.p, p.block_of.p, p.func_of_block.p,
-                     err);
+                     pcnt, err);
   GPA_LAUNCH_CHECK();
-  uint32_t *pcnt = ar.get<uint32_t>(nb + 1);
-  GPA_HIP(hipMemsetAsync(pcnt, 0, 4 * (nb + 1), s));
   hipLaunchKernelGGL(k_val_succ, dim3(grid_for(nb, 256, 2048)), dim3(256), 0, s, nb, p.succ_ptr.p,
                      p.succ.p, p.n_succ, p.func_of_block.p, pcnt, err);
   hipLaunchKernelGGL(k_val_instr_scope, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, n, ns,
@@ -605,11 +605,6 @@ void build_sites_and_scopes(gpa_program &p, hipStream_t s, Arena &ar) {
              p.def_rank.p);
   sort_sites(p, s, ar, p.use_ptr.p, p.use_loc.p, p.n_uses, p.use_site_sorted, p.fl_use_ptr,
              p.use_rank.p);
-  hipLaunchKernelGGL(k_fl_close, dim3(grid_for(nf, 256, 1024)), dim3(256), 0, s, nf, p.n_loc,
-                     p.func_block_begin.p, p.block_begin.p, p.def_ptr.p, p.fl_def_ptr.p);
-  hipLaunchKernelGGL(k_fl_close, dim3(grid_for(nf, 256, 1024)), dim3(256), 0, s, nf, p.n_loc,
-                     p.func_block_begin.p, p.block_begin.p, p.use_ptr.p, p.fl_use_ptr.p);
-  GPA_LAUNCH_CHECK();
   p.use_cond.alloc(p.n_uses);
   hipLaunchKernelGGL(k_use_cond, dim3(grid_for(p.n_uses, 256, 4096)), dim3(256), 0, s, p.n_uses,
                      p.use_instr.p, p.use_kind.p, p.guard.p, p.use_cond.p);
