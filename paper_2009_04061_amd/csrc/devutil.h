@@ -37,10 +37,25 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
   return v;
 }
 
+// Workgroup barrier that orders LDS accesses only: global loads already
+// issued stay in flight across it (__syncthreads waits for them as well).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <bool kLdsOnly>
+__device__ __forceinline__ void wg_barrier() {
+  if (kLdsOnly) lds_barrier();
+  else __syncthreads();
+}
+
 // Exclusive scan across a workgroup of NT threads (NT a multiple of 64);
 // `smem` holds NT/64 + 1 elements.  Returns the exclusive prefix of this
-// thread and writes the workgroup total to *total.
-template <int NT, typename T>
+// thread and writes the workgroup total to *total.  kLdsOnly: its barriers
+// order LDS only (see lds_barrier).
+template <int NT, typename T, bool kLdsOnly = false>
 __device__ __forceinline__ T block_excl_scan(T v, T *smem, T *total) {
   static_assert(NT % kWave == 0, "block must be whole waves");
   constexpr int NW = NT / kWave;
@@ -48,7 +63,7 @@ __device__ __forceinline__ T block_excl_scan(T v, T *smem, T *total) {
   const unsigned w = tid / kWave, lane = tid % kWave;
   T inc = wave_incl_scan(v);
   if (lane == kWave - 1) smem[w] = inc;
-  __syncthreads();
+  wg_barrier<kLdsOnly>();
   if (tid == 0) {
     T run = 0;
     for (int k = 0; k < NW; ++k) {
@@ -58,10 +73,10 @@ __device__ __forceinline__ T block_excl_scan(T v, T *smem, T *total) {
     }
     smem[NW] = run;
   }
-  __syncthreads();
+  wg_barrier<kLdsOnly>();
   T res = smem[w] + inc - v;
   *total = smem[NW];
-  __syncthreads();
+  wg_barrier<kLdsOnly>();
   return res;
 }
 

@@ -25,6 +25,8 @@
 // where runs land.  (A last-workgroup-does-the-rest scheme would save the
 // small launches, but the device-scope fence it needs in every workgroup
 // costs far more on this part.)
+#include <cstdlib>
+
 #include "common.h"
 #include "devutil.h"
 
@@ -521,6 +523,486 @@ __global__ void k_hoverflow(const uint32_t *__restrict__ ov_keys, const uint32_t
   }
 }
 
+// ------------------------------------------------------------ hot-set path
+// For programs of up to kHotMaxPCs instructions, a sample of the records
+// picks a hot set of at most kHotH PCs.  One read of the records adds every
+// hot record into a workgroup-private LDS copy of the hot bins and appends
+// every other (cold) record as a 4-byte key to the workgroup's own slice of
+// a key array; no device atomics.  The cold keys are then sorted by bucket
+// of kColdPCs PCs within tiles, and a last launch sums the hot copies and
+// counts each bucket's cold keys in LDS.  Hot and cold PCs are disjoint, so
+// every bin is written exactly once.
+//   k_hot_select  one workgroup: 16-bit LDS counters (one per PC, or per
+//                 pair of PCs beyond 65,536) over 64 evenly spread runs of
+//                 records; a counter that reaches kSelMin makes its PCs hot
+//                 (first come, at most kHotH), each placed in one of two
+//                 candidate slots of the lookup table;
+//   k_hot_pass    one workgroup per contiguous range of records;
+//   k_cold_sort   per tile of kColdTile cold keys: LDS counting sort by
+//                 bucket, the bucket starts recorded;
+//   k_hot_finish  cold buckets, hot-bin sums and the totals.
+constexpr int kHotThreads = 1024;
+constexpr uint32_t kHotH = 512;                  // hot PCs at most
+constexpr uint32_t kHotTBits = 11;
+constexpr uint32_t kHotT = 1u << kHotTBits;      // lookup slots (load <= 1/4)
+constexpr uint32_t kHotBins = kHotH * 24;
+constexpr uint32_t kHotMaxPCs = 1u << 17;        // cold keys pc << 5 | bin fit 22 bits
+static_assert(kHotH <= 512u && kHotMaxPCs <= (1u << 22), "table entries pc | id << 22 below 2^31");
+constexpr uint32_t kColdShift = 8;
+constexpr uint32_t kColdPCs = 1u << kColdShift;  // PCs per cold bucket
+constexpr uint32_t kColdBins = kColdPCs * 24;
+constexpr uint32_t kColdMaxBuckets = kHotMaxPCs / kColdPCs;
+constexpr uint32_t kColdTile = 8192;             // cold keys per sorted tile
+constexpr uint32_t kSelSample = 8192;            // sampled records
+constexpr uint32_t kSelRun = 128;                // records per sampled run
+constexpr uint32_t kSelCounters = 1u << 16;      // 16-bit, two per word
+constexpr uint32_t kSelMin = 3;                  // sampled count that makes a PC hot
+constexpr int kHotUnroll = 4;                    // 16-byte loads per thread per step
+constexpr uint32_t kHotStep = kHotThreads * kHotUnroll * 2;   // records per step
+constexpr uint32_t kHotGrid = 256;               // workgroups of the pass at most
+constexpr uint32_t kHotMergeCols = 64;           // hot bins per merge workgroup
+constexpr uint32_t kMaxRuns = 4096;              // cold runs listed at a time
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+static_assert(kColdMaxBuckets <= (uint32_t)kHotThreads, "one cold bucket per thread in scans");
+static_assert(kSelSample < 65536u, "16-bit sample counters");
+
+// a hot PC sits in one of its two slots (entry pc | id << 22)
+__device__ __forceinline__ uint32_t hot_slot1(uint32_t pc) {
+  return (pc * 0x9E3779B1u) >> (32 - kHotTBits);
+}
+__device__ __forceinline__ uint32_t hot_slot2(uint32_t pc) {
+  return (pc * 0x85EBCA6Bu + 0x6A09E667u) >> (32 - kHotTBits);
+}
+__device__ __forceinline__ uint32_t cold_bucket(uint32_t key) { return key >> (5 + kColdShift); }
+__device__ __forceinline__ uint32_t cold_local_bin(uint32_t key) {
+  return ((key >> 5) & (kColdPCs - 1)) * 24u + (key & 31u);
+}
+
+// LDS words of k_hot_select (dynamic): counters and the table
+constexpr size_t kSelLdsWords = kSelCounters / 2 + kHotT;
+
+// Sampled record k: k itself when n <= kSelSample, else offset k % kSelRun
+// of run k / kSelRun, the runs run_stride apart (63 run_stride + kSelRun <= n).
+__global__ void __launch_bounds__(kHotThreads)
+k_hot_select(const uint64_t *__restrict__ rec, uint64_t n, uint64_t run_stride, uint32_t n_instr,
+             uint32_t *__restrict__ hot_tab, uint32_t *__restrict__ hot_pc,
+             uint32_t *__restrict__ n_hot) {
+  extern __shared__ uint32_t sm[];
+  uint32_t *cnt = sm, *tab = cnt + kSelCounters / 2;
+  __shared__ uint32_t s_nsel;
+  const unsigned tid = threadIdx.x;
+  const uint32_t sh = n_instr > kSelCounters ? 1u : 0u;   // counter = pc >> sh
+  constexpr uint32_t kPer = kSelSample / kHotThreads;
+  uint64_t r[kPer];
+#pragma unroll
+  for (uint32_t j = 0; j < kPer; ++j) {
+    const uint32_t k = j * kHotThreads + tid;
+    const uint64_t i = n <= kSelSample ? k : (k / kSelRun) * run_stride + k % kSelRun;
+    r[j] = i < n ? rec[i] : ~0ull;
+  }
+  for (uint32_t k = tid; k < kSelCounters / 2; k += kHotThreads) cnt[k] = 0;
+  for (uint32_t k = tid; k < kHotT; k += kHotThreads) tab[k] = kEmpty;
+  if (tid == 0) s_nsel = 0;
+  __syncthreads();
+#pragma unroll
+  for (uint32_t j = 0; j < kPer; ++j) {
+    if (!rec_valid(r[j], n_instr)) continue;
+    const uint32_t c = (uint32_t)r[j] >> sh, half = 16 * (c & 1);
+    const uint32_t old = (atomicAdd(&cnt[c >> 1], 1u << half) >> half) & 0xFFFFu;
+    if (old + 1 != kSelMin) continue;
+    // this sample made counter c reach kSelMin: its PCs become hot
+    for (uint32_t pc = c << sh; pc < ((c + 1) << sh) && pc < n_instr; ++pc) {
+      const uint32_t prov = pc | (kHotH << 22);   // claimed, not yet numbered
+      uint32_t slot = hot_slot1(pc);
+      if (atomicCAS(&tab[slot], kEmpty, prov) != kEmpty) {
+        slot = hot_slot2(pc);
+        if (atomicCAS(&tab[slot], kEmpty, prov) != kEmpty) continue;   // stays cold
+      }
+      const uint32_t id = atomicAdd(&s_nsel, 1u);
+      if (id < kHotH) {
+        hot_pc[id] = pc;
+        tab[slot] = pc | (id << 22);
+      } else {
+        tab[slot] = kEmpty;   // the hot set is full: stays cold
+      }
+    }
+  }
+  __syncthreads();
+  for (uint32_t k = tid; k < kHotT; k += kHotThreads) hot_tab[k] = tab[k];
+  if (tid == 0) *n_hot = min(s_nsel, kHotH);
+}
+
+// one step's records of a thread: FULL steps lie wholly below n (16-byte
+// loads when VEC); otherwise the indices are clamped and the records past n
+// zeroed (no branches, so that the loads are issued back to back)
+template <bool VEC, bool FULL>
+__device__ __forceinline__ void hot_load(const uint64_t *__restrict__ rec, uint64_t n, uint64_t i0,
+                                         uint64_t (&v)[2 * kHotUnroll]) {
+#pragma unroll
+  for (int u = 0; u < kHotUnroll; ++u) {
+    const uint64_t i = i0 + 2 * ((uint64_t)u * kHotThreads + threadIdx.x);
+    if (FULL && VEC) {
+      const u64x2 x = __builtin_nontemporal_load((const u64x2 *)(rec + i));
+      v[2 * u] = x.x;
+      v[2 * u + 1] = x.y;
+    } else if (FULL) {
+      v[2 * u] = rec[i];
+      v[2 * u + 1] = rec[i + 1];
+    } else {
+      const uint64_t a = rec[min(i, n - 1)], b = rec[min(i + 1, n - 1)];
+      v[2 * u] = i < n ? a : 0ull;
+      v[2 * u + 1] = i + 1 < n ? b : 0ull;
+    }
+  }
+}
+
+// Workgroup w reads records [w per, min((w + 1) per, n)) in steps of
+// kHotStep (per is a multiple of kHotStep), the loads of the next two steps
+// in flight while a step is counted; its cold keys are appended to cold[]
+// from index w per on (one LDS reservation per wave and step), their number
+// to n_cold[w].
+template <bool VEC>
+__global__ void __launch_bounds__(kHotThreads)
+k_hot_pass(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint64_t per,
+           const uint32_t *__restrict__ hot_tab, uint32_t *__restrict__ partial,
+           uint32_t *__restrict__ cold, uint32_t *__restrict__ n_cold,
+           TileTotals *__restrict__ wtot) {
+  __shared__ uint32_t bins[kHotBins];
+  __shared__ uint32_t tab[kHotT];
+  __shared__ uint32_t s_cur, s_valid, s_lat;
+  const unsigned tid = threadIdx.x, lane = lane_id();
+  const uint64_t r0 = (uint64_t)blockIdx.x * per, r1 = min(r0 + per, n);
+  // full steps below rf, then at most one partial step; three register
+  // buffers in rotation (the first two issued before the set-up)
+  const uint64_t rf = r0 + (r1 - r0) / kHotStep * kHotStep;
+  uint64_t va[2 * kHotUnroll], vb[2 * kHotUnroll], vc[2 * kHotUnroll];
+  auto issue = [&](uint64_t i0, uint64_t (&v)[2 * kHotUnroll]) {
+    if (i0 < rf) hot_load<VEC, true>(rec, r1, i0, v);
+  };
+  issue(r0, va);
+  issue(r0 + kHotStep, vb);
+  for (uint32_t k = tid; k < kHotBins; k += kHotThreads) bins[k] = 0;
+  for (uint32_t k = tid; k < kHotT; k += kHotThreads) tab[k] = hot_tab[k];
+  if (tid == 0) {
+    s_cur = 0;
+    s_valid = 0;
+    s_lat = 0;
+  }
+  lds_barrier();
+  uint32_t *my_cold = cold + r0;
+  uint32_t my_valid = 0, my_lat = 0;
+  auto step = [&](uint64_t i0, const uint64_t (&cur)[2 * kHotUnroll]) {
+    uint32_t cmask = 0;
+#pragma unroll
+    for (int q = 0; q < 2 * kHotUnroll; ++q) {
+      const uint64_t i = i0 + 2 * ((uint64_t)(q / 2) * kHotThreads + tid) + (q & 1);
+      const uint64_t r = cur[q];
+      const uint32_t pc = (uint32_t)r, hi = (uint32_t)(r >> 32);
+      const bool ok = i < r1 && rec_valid(r, n_instr);
+      bool hot = false;
+      if (ok) {
+        const uint32_t e1 = tab[hot_slot1(pc)], e2 = tab[hot_slot2(pc)];
+        const uint32_t e = (e1 & 0x3FFFFFu) == pc ? e1 : e2;   // an empty slot matches no pc
+        if ((e & 0x3FFFFFu) == pc) {
+          hot = true;
+          atomicAdd(&bins[(e >> 22) * 24u + (hi & 0xFFu) * 2u + ((hi >> 8) & 1u)], 1u);
+        }
+      }
+      my_valid += ok ? 1u : 0u;
+      my_lat += ok ? (hi >> 8) & 1u : 0u;
+      cmask |= (ok && !hot) ? 1u << q : 0u;
+    }
+    // the step's cold keys: one LDS reservation per wave
+    const uint32_t c = __popc(cmask);
+    const uint32_t inc = wave_incl_scan(c);
+    const uint32_t wt = __shfl(inc, kWave - 1, kWave);
+    if (wt) {
+      uint32_t pos = 0;
+      if (lane == kWave - 1) pos = atomicAdd(&s_cur, wt);
+      pos = __shfl(pos, kWave - 1, kWave) + inc - c;
+#pragma unroll
+      for (int q = 0; q < 2 * kHotUnroll; ++q)
+        if ((cmask >> q) & 1u) {
+          const uint32_t hi = (uint32_t)(cur[q] >> 32);
+          my_cold[pos++] = ((uint32_t)cur[q] << 5) | ((hi & 0xFFu) * 2u + ((hi >> 8) & 1u));
+        }
+    }
+  };
+  for (uint64_t i0 = r0; i0 < rf;) {
+    issue(i0 + 2 * kHotStep, vc);
+    step(i0, va);
+    if ((i0 += kHotStep) >= rf) break;
+    issue(i0 + 2 * kHotStep, va);
+    step(i0, vb);
+    if ((i0 += kHotStep) >= rf) break;
+    issue(i0 + 2 * kHotStep, vb);
+    step(i0, vc);
+    i0 += kHotStep;
+  }
+  if (rf < r1) {
+    hot_load<VEC, false>(rec, r1, rf, va);
+    step(rf, va);
+  }
+  my_valid = wave_sum(my_valid);
+  my_lat = wave_sum(my_lat);
+  if (lane == 0) {
+    atomicAdd(&s_valid, my_valid);
+    atomicAdd(&s_lat, my_lat);
+  }
+  __syncthreads();
+  uint32_t *dst = partial + (size_t)blockIdx.x * kHotBins;
+  for (uint32_t k = tid; k < kHotBins; k += kHotThreads) dst[k] = bins[k];
+  if (tid == 0) {
+    TileTotals t;
+    t.valid = s_valid;
+    t.latency = s_lat;
+    t.dropped = (uint32_t)(r1 - r0) - s_valid;
+    t.pad = 0;
+    wtot[blockIdx.x] = t;
+    n_cold[blockIdx.x] = s_cur;
+  }
+}
+
+// Tile t of workgroup w's cold keys (grid G x T, tiles past the workgroup's
+// keys exit): sorted by bucket into cold_sorted at the same indices, the
+// bucket starts to tile_off[(w T + t) (n_cb + 1) + b] (entry n_cb: the end).
+__global__ void __launch_bounds__(kHotThreads)
+k_cold_sort(uint32_t n_cb, uint64_t per, uint32_t T, const uint32_t *__restrict__ n_cold,
+            const uint32_t *__restrict__ cold, uint32_t *__restrict__ cold_sorted,
+            uint32_t *__restrict__ tile_off) {
+  __shared__ uint32_t sorted[kColdTile];
+  __shared__ uint32_t bc[kColdMaxBuckets];
+  __shared__ uint32_t scan_tmp[kHotThreads / kWave + 1];
+  const unsigned tid = threadIdx.x;
+  const uint32_t w = blockIdx.x / T, t = blockIdx.x % T;
+  const uint32_t nc = n_cold[w], a = t * kColdTile;
+  if (a >= nc) return;
+  const uint32_t m = min(kColdTile, nc - a);
+  const uint64_t base = (uint64_t)w * per + a;
+  constexpr uint32_t kPer = kColdTile / kHotThreads;
+  uint32_t key[kPer];
+#pragma unroll
+  for (uint32_t j = 0; j < kPer; ++j) {
+    const uint32_t k = j * kHotThreads + tid;
+    key[j] = k < m ? cold[base + k] : kEmpty;
+  }
+  for (uint32_t b = tid; b < n_cb; b += kHotThreads) bc[b] = 0;
+  __syncthreads();
+#pragma unroll
+  for (uint32_t j = 0; j < kPer; ++j)
+    if (key[j] != kEmpty) atomicAdd(&bc[cold_bucket(key[j])], 1u);
+  __syncthreads();
+  uint32_t *off = tile_off + ((size_t)w * T + t) * (n_cb + 1);
+  {
+    const uint32_t c = tid < n_cb ? bc[tid] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_excl_scan<kHotThreads>(c, scan_tmp, &total);
+    if (tid < n_cb) {
+      bc[tid] = ex;
+      off[tid] = (uint32_t)(base + ex);
+    }
+    if (tid == 0) off[n_cb] = (uint32_t)(base + total);
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t j = 0; j < kPer; ++j)
+    if (key[j] != kEmpty) sorted[atomicAdd(&bc[cold_bucket(key[j])], 1u)] = key[j];
+  __syncthreads();
+  for (uint32_t k = tid; k < m; k += kHotThreads) cold_sorted[base + k] = sorted[k];
+}
+
+// blocks [0, n_cb): the cold bins of one bucket; the next
+// kHotBins / kHotMergeCols: hot bins summed over the pass's workgroups; the
+// last: the totals
+__global__ void __launch_bounds__(kHotThreads)
+k_hot_finish(uint32_t n_instr, uint32_t n_cb, uint32_t G, uint32_t T,
+             const uint32_t *__restrict__ hot_pc, const uint32_t *__restrict__ n_hot_p,
+             const uint32_t *__restrict__ partial, const uint32_t *__restrict__ cold_sorted,
+             const uint32_t *__restrict__ tile_off, const uint32_t *__restrict__ n_cold,
+             const TileTotals *__restrict__ wtot, uint32_t *__restrict__ counts,
+             unsigned long long *__restrict__ totals) {
+  constexpr uint32_t kWaves = kHotThreads / kWave;
+  static_assert(kHotGrid <= (uint32_t)kHotThreads, "one pass workgroup per thread");
+  __shared__ __align__(16) uint32_t bins[kColdBins];
+  __shared__ uint32_t hot_mark[kColdPCs / 32];
+  __shared__ uint32_t rs[kMaxRuns], rp[kMaxRuns + 1];
+  __shared__ uint32_t scan_tmp[kHotThreads / kWave + 1];
+  const unsigned tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
+  const uint32_t n_hot = *n_hot_p;
+  constexpr uint32_t n_merge = kHotBins / kHotMergeCols;
+  if (blockIdx.x < n_cb) {
+    const uint32_t b = blockIdx.x, pc0 = b * kColdPCs;
+    const uint32_t npc = min(kColdPCs, n_instr - pc0);
+    for (uint32_t k = tid; k < kColdBins; k += kHotThreads) bins[k] = 0;
+    if (tid < kColdPCs / 32) hot_mark[tid] = 0;
+    // the bucket's runs, one per sorted tile (w, t), numbered by a scan over w
+    const uint32_t nf = tid < G ? (n_cold[tid] + kColdTile - 1) / kColdTile : 0u;
+    uint32_t n_runs;
+    const uint32_t ex = block_excl_scan<kHotThreads>(nf, scan_tmp, &n_runs);
+    if (tid < n_hot) {
+      const uint32_t pl = hot_pc[tid] - pc0;
+      if (pl < kColdPCs) atomicOr(&hot_mark[pl / 32], 1u << (pl % 32));
+    }
+    // up to kMaxRuns runs at a time: their starts and a prefix of their
+    // lengths in LDS, then the concatenated keys walked flat, each wave a
+    // contiguous share, lane-interleaved, eight loads in flight per lane
+    for (uint32_t c0 = 0; c0 < n_runs; c0 += kMaxRuns) {
+      const uint32_t m = min(kMaxRuns, n_runs - c0);
+      for (uint32_t f = 0; f < nf; ++f)
+        if (ex + f >= c0 && ex + f < c0 + m) {
+          const uint32_t *off = tile_off + ((size_t)tid * T + f) * (n_cb + 1);
+          const uint32_t st = off[b];
+          rs[ex + f - c0] = st;
+          rp[ex + f - c0] = off[b + 1] - st;   // the length, until the scan below
+        }
+      __syncthreads();
+      {
+        static_assert(kMaxRuns == 4 * (uint32_t)kHotThreads, "four runs per thread in the scan");
+        uint32_t l[4], sum = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i) {
+          l[i] = 4 * tid + i < m ? rp[4 * tid + i] : 0u;
+          sum += l[i];
+        }
+        uint32_t total;
+        uint32_t run = block_excl_scan<kHotThreads>(sum, scan_tmp, &total);
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i) {
+          if (4 * tid + i < m) rp[4 * tid + i] = run;
+          run += l[i];
+        }
+        if (tid == 0) rp[m] = total;
+      }
+      __syncthreads();
+      const uint32_t T_keys = rp[m];
+      const uint32_t share = (T_keys + kWaves - 1) / kWaves;
+      const uint32_t lo = min(wv * share, T_keys), hi = min(lo + share, T_keys);
+      uint32_t k = lo + lane, r = 0;
+      if (k < hi) {   // the run holding k: rp[r] <= k < rp[r + 1]
+        uint32_t x = 0, z = m;
+        while (z - x > 1) {
+          const uint32_t mid = (x + z) / 2;
+          if (rp[mid] <= k) x = mid;
+          else z = mid;
+        }
+        r = x;
+      }
+      for (; k < hi; k += 8 * kWave) {
+        uint32_t key[8];
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) {
+          const uint32_t kk = k + u * kWave;
+          key[u] = kEmpty;
+          if (kk < hi) {
+            while (rp[r + 1] <= kk) ++r;   // ends: kk < rp[m]
+            key[u] = cold_sorted[rs[r] + (kk - rp[r])];
+          }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u)
+          if (key[u] != kEmpty) atomicAdd(&bins[cold_local_bin(key[u])], 1u);
+      }
+      __syncthreads();
+    }
+    __syncthreads();   // the hot marks (and the cleared bins when there are no runs)
+    for (uint32_t k = tid; k < npc * 24u; k += kHotThreads) {
+      const uint32_t pl = k / 24u;
+      if (!((hot_mark[pl / 32] >> (pl % 32)) & 1u)) counts[(size_t)pc0 * 24u + k] = bins[k];
+    }
+  } else if (blockIdx.x < n_cb + n_merge) {
+    // kHotMergeCols hot bins; the pass's workgroups split over kSlices slices
+    constexpr uint32_t kSlices = kHotThreads / kHotMergeCols;
+    const uint32_t c = tid % kHotMergeCols, sl = tid / kHotMergeCols;
+    const uint32_t col = (blockIdx.x - n_cb) * kHotMergeCols + c;
+    const bool live = col < n_hot * 24u;
+    uint32_t v[kHotGrid / kSlices];
+#pragma unroll
+    for (uint32_t u = 0; u < kHotGrid / kSlices; ++u) {
+      const uint32_t w = sl + u * kSlices;
+      v[u] = live && w < G ? partial[(size_t)w * kHotBins + col] : 0u;
+    }
+    uint32_t sum = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < kHotGrid / kSlices; ++u) sum += v[u];
+    bins[sl * kHotMergeCols + c] = sum;
+    __syncthreads();
+    if (sl == 0 && live) {
+      uint32_t t = 0;
+      for (uint32_t k = 0; k < kSlices; ++k) t += bins[k * kHotMergeCols + c];
+      counts[(size_t)hot_pc[col / 24u] * 24u + col % 24u] = t;
+    }
+  } else {
+    unsigned long long v = 0, l = 0, d = 0;
+    if (tid < G) {
+      v = wtot[tid].valid;
+      l = wtot[tid].latency;
+      d = wtot[tid].dropped;
+    }
+    v = wave_sum(v);
+    l = wave_sum(l);
+    d = wave_sum(d);
+    unsigned long long *red = (unsigned long long *)bins;   // [3][kWaves]
+    if (lane == 0) {
+      red[wv] = v;
+      red[kWaves + wv] = l;
+      red[2 * kWaves + wv] = d;
+    }
+    __syncthreads();
+    if (tid < 3) {
+      unsigned long long a = 0;
+      for (uint32_t k = 0; k < kWaves; ++k) a += red[tid * kWaves + k];
+      totals[tid] = a;
+    }
+    if (tid == 3) totals[3] = 0;
+  }
+}
+
+// The hot-set path, for programs of at most kHotMaxPCs instructions.
+static bool run_hist_hot(const gpa_program &p, const uint64_t *rec, uint64_t n, bool vec,
+                         uint32_t *counts, unsigned long long *totals, hipStream_t s, Arena &ar) {
+  const uint32_t n_instr = p.n_instr;
+  if (n_instr > kHotMaxPCs) return false;
+  const char *force = getenv("GPA_HIST_PARTITION");
+  if (force && force[0] == '1') return false;
+  const uint32_t n_cb = (n_instr + kColdPCs - 1) / kColdPCs;
+  // workgroup ranges: a multiple of kHotStep records each, kHotGrid at most
+  uint64_t per = (n + kHotGrid - 1) / kHotGrid;
+  per = (per + kHotStep - 1) / kHotStep * kHotStep;
+  const uint32_t G = (uint32_t)((n + per - 1) / per);
+  const uint32_t T = (uint32_t)((per + kColdTile - 1) / kColdTile);   // tiles per workgroup
+  const uint64_t run_stride = n > kSelSample ? (n - kSelRun) / 63 : 0;
+  uint32_t *hot_tab = ar.get<uint32_t>(kHotT);
+  uint32_t *hot_pc = ar.get<uint32_t>(kHotH);
+  uint32_t *n_hot = ar.get<uint32_t>(1);
+  uint32_t *partial = ar.get<uint32_t>((size_t)G * kHotBins);
+  uint32_t *cold = ar.get<uint32_t>(n);
+  uint32_t *cold_sorted = ar.get<uint32_t>(n);
+  uint32_t *tile_off = ar.get<uint32_t>((size_t)G * T * (n_cb + 1));
+  uint32_t *n_cold = ar.get<uint32_t>(G);
+  TileTotals *wtot = ar.get<TileTotals>(G);
+  const size_t lds_sel = kSelLdsWords * 4;
+  GPA_HIP(hipFuncSetAttribute((const void *)k_hot_select,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_sel));
+  hipLaunchKernelGGL(k_hot_select, dim3(1), dim3(kHotThreads), lds_sel, s, rec, n, run_stride,
+                     n_instr, hot_tab, hot_pc, n_hot);
+  GPA_LAUNCH_CHECK();
+  if (vec)
+    hipLaunchKernelGGL(k_hot_pass<true>, dim3(G), dim3(kHotThreads), 0, s, rec, n, n_instr, per,
+                       hot_tab, partial, cold, n_cold, wtot);
+  else
+    hipLaunchKernelGGL(k_hot_pass<false>, dim3(G), dim3(kHotThreads), 0, s, rec, n, n_instr, per,
+                       hot_tab, partial, cold, n_cold, wtot);
+  GPA_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_cold_sort, dim3(G * T), dim3(kHotThreads), 0, s, n_cb, per, T, n_cold, cold,
+                     cold_sorted, tile_off);
+  GPA_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_hot_finish, dim3(n_cb + kHotBins / kHotMergeCols + 1), dim3(kHotThreads), 0,
+                     s, n_instr, n_cb, G, T, hot_pc, n_hot, partial, cold_sorted, tile_off, n_cold,
+                     wtot, counts, totals);
+  GPA_LAUNCH_CHECK();
+  return true;
+}
+
 __global__ void k_hist_empty(uint32_t *counts, size_t nbins, unsigned long long *totals) {
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < nbins;
        k += (size_t)gridDim.x * blockDim.x)
@@ -541,9 +1023,10 @@ void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint3
     return;
   }
   if (n >= 0x40000000ull) fail(GPA_E_UNSUPPORTED, "fewer than 2^30 samples per call are supported");
-  const uint32_t n_tiles = (uint32_t)((n + kTile - 1) / kTile);
   const uint64_t *rec = (const uint64_t *)samples;
   const bool vec = ((uintptr_t)samples % 16) == 0;
+  if (run_hist_hot(p, rec, n, vec, counts, totals, s, ar)) return;
+  const uint32_t n_tiles = (uint32_t)((n + kTile - 1) / kTile);
   // bucket regions from a sample of the records
   const uint64_t n_samp =
       (n + (uint64_t)kSampleStride * kSampleSlice - 1) / ((uint64_t)kSampleStride * kSampleSlice);

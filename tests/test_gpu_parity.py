@@ -203,7 +203,70 @@ def test_malformed_descriptor_is_rejected(kind):
     P.close()
 
 
-def test_histogram_bucket_outgrows_its_estimate():
+def _hist_only(P, prog, rec, offset_bytes=0):
+    """Counts and totals of one gpa_attribute call against the oracle's
+    histogram; `offset_bytes` places the device records at that offset from
+    a 256-byte aligned allocation."""
+    import torch
+    raw = np.ascontiguousarray(rec).view(np.uint8)
+    buf = torch.zeros(raw.size + offset_bytes, dtype=torch.uint8, device="cuda")
+    buf[offset_bytes:] = torch.from_numpy(raw.copy()).cuda()
+    B = P.attribute(buf[offset_bytes:])
+    C, tot = B.counts()
+    B.close()
+    Co, dropped = O.count(len(prog["op_class"]), rec)
+    from parity import _equal
+    _equal(C, Co, "counts")
+    _equal(int(tot[0]), int(Co.sum()), "valid samples")
+    _equal(int(tot[1]), int(Co[:, :, 1].sum()), "latency samples")
+    _equal(int(tot[2]), dropped, "dropped records")
+
+
+@pytest.fixture(scope="module")
+def large_program():
+    from paper_2009_04061_amd import gpa
+    prog, rec = S.workload_large(seed=1)
+    P = gpa.Program(gpa.program_to_device(prog))
+    yield prog, rec, P
+    P.close()
+
+
+def test_histogram_hot_and_cold_extremes(large_program):
+    """The hot-set histogram: uniform PCs over 60k instructions (almost every
+    record cold: a workgroup stages and flushes its cold keys many times),
+    one PC only (all hot), a flat head of 3,000 PCs (more candidates than hot
+    slots), invalid records, and records 8 bytes off 16-byte alignment."""
+    prog, _, P = large_program
+    n_instr = len(prog["op_class"])
+    rng = np.random.default_rng(12)
+    mix = S.stall_mix_small()
+    uni = S.gen_samples(20_000_000, n_instr, 0.0, mix, seed=12)
+    uni["pc"] = rng.integers(0, n_instr, len(uni))
+    print("  uniform", flush=True)
+    _hist_only(P, prog, S.corrupt_samples(uni, 0.001, n_instr, seed=12))
+    one = S.gen_samples(1_000_003, n_instr, 0.0, mix, seed=13)
+    one["pc"] = 4242
+    print("  one pc", flush=True)
+    _hist_only(P, prog, one)
+    flat = S.gen_samples(3_000_001, n_instr, 0.0, mix, seed=14)
+    flat["pc"] = rng.permutation(n_instr)[:3000][rng.integers(0, 3000, len(flat))]
+    print("  flat head, misaligned", flush=True)
+    _hist_only(P, prog, S.corrupt_samples(flat, 0.01, n_instr, seed=14), offset_bytes=8)
+
+
+@pytest.mark.parametrize("path", ["hot", "partition"])
+def test_histogram_paths_on_the_large_profile(large_program, monkeypatch, path):
+    """The 20M-record Zipf profile through either histogram path (the
+    partition path serves programs beyond the hot path's PC range, and is
+    forced here), aligned and 8 bytes off."""
+    prog, rec, P = large_program
+    if path == "partition":
+        monkeypatch.setenv("GPA_HIST_PARTITION", "1")
+    _hist_only(P, prog, rec)
+    _hist_only(P, prog, rec[: len(rec) - 5], offset_bytes=8)
+
+
+def test_histogram_bucket_outgrows_its_estimate(monkeypatch):
     """Records of one bucket placed only where the size estimate does not look
     (every slice of 512 records except each 32nd), so its runs overflow their
     regions and go the overflow way; the other slices feed a bucket of their
@@ -221,4 +284,7 @@ def test_histogram_bucket_outgrows_its_estimate():
     rec["flags"] = (rng.random(n) < 0.5) & (rec["stall"] != S.ST_SELECTED) & (rec["stall"] != S.ST_NOT_SELECTED)
     rec = S.corrupt_samples(rec, 0.001, len(prog["op_class"]), seed=6)
     print(f"  records {n}, sampled slices {int(sampled.sum())}", flush=True)
+    monkeypatch.setenv("GPA_HIST_PARTITION", "1")   # the sizing belongs to the partition path
+    _both(prog, rec)
+    monkeypatch.delenv("GPA_HIST_PARTITION")
     _both(prog, rec)
