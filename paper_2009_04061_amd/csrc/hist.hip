@@ -528,18 +528,18 @@ __global__ void k_hoverflow(const uint32_t *__restrict__ ov_keys, const uint32_t
 // picks a hot set of at most kHotH PCs.  One read of the records adds every
 // hot record into a workgroup-private LDS copy of the hot bins and appends
 // every other (cold) record as a 4-byte key to the workgroup's own slice of
-// a key array; no device atomics.  The cold keys are then sorted by bucket
-// of kColdPCs PCs within tiles, and a last launch sums the hot copies and
+// a key array; no device atomics.  The workgroup then sorts its cold keys by
+// bucket of kColdPCs PCs within tiles, and a last launch sums the hot copies and
 // counts each bucket's cold keys in LDS.  Hot and cold PCs are disjoint, so
 // every bin is written exactly once.
 //   k_hot_select  one workgroup: 16-bit LDS counters (one per PC, or per
-//                 pair of PCs beyond 65,536) over 64 evenly spread runs of
-//                 records; a counter that reaches kSelMin makes its PCs hot
+//                 pair of PCs beyond 65,536) over kSelSample records in
+//                 evenly spread runs; a counter that reaches kSelMin makes
+//                 its PCs hot
 //                 (first come, at most kHotH), each placed in one of two
 //                 candidate slots of the lookup table;
-//   k_hot_pass    one workgroup per contiguous range of records;
-//   k_cold_sort   per tile of kColdTile cold keys: LDS counting sort by
-//                 bucket, the bucket starts recorded;
+//   k_hot_pass    one workgroup per contiguous range of records, which
+//                 then sorts its cold keys by bucket in tiles of kColdTile;
 //   k_hot_finish  cold buckets, hot-bin sums and the totals.
 constexpr int kHotThreads = 1024;
 constexpr uint32_t kHotH = 512;                  // hot PCs at most
@@ -553,7 +553,7 @@ constexpr uint32_t kColdPCs = 1u << kColdShift;  // PCs per cold bucket
 constexpr uint32_t kColdBins = kColdPCs * 24;
 constexpr uint32_t kColdMaxBuckets = kHotMaxPCs / kColdPCs;
 constexpr uint32_t kColdTile = 8192;             // cold keys per sorted tile
-constexpr uint32_t kSelSample = 8192;            // sampled records
+constexpr uint32_t kSelSample = 16384;           // sampled records
 constexpr uint32_t kSelRun = 128;                // records per sampled run
 constexpr uint32_t kSelCounters = 1u << 16;      // 16-bit, two per word
 constexpr uint32_t kSelMin = 3;                  // sampled count that makes a PC hot
@@ -582,7 +582,8 @@ __device__ __forceinline__ uint32_t cold_local_bin(uint32_t key) {
 constexpr size_t kSelLdsWords = kSelCounters / 2 + kHotT;
 
 // Sampled record k: k itself when n <= kSelSample, else offset k % kSelRun
-// of run k / kSelRun, the runs run_stride apart (63 run_stride + kSelRun <= n).
+// of run k / kSelRun, the runs run_stride apart
+// ((kSelSample / kSelRun - 1) run_stride + kSelRun <= n).
 __global__ void __launch_bounds__(kHotThreads)
 k_hot_select(const uint64_t *__restrict__ rec, uint64_t n, uint64_t run_stride, uint32_t n_instr,
              uint32_t *__restrict__ hot_tab, uint32_t *__restrict__ hot_pc,
@@ -656,19 +657,66 @@ __device__ __forceinline__ void hot_load(const uint64_t *__restrict__ rec, uint6
   }
 }
 
+// m <= kColdTile cold keys at cold[base, base + m) sorted by bucket into
+// cold_sorted at the same indices; the bucket starts (absolute indices) to
+// off[0, n_cb), the end to off[n_cb].  Every thread of the workgroup calls
+// it; it ends on a barrier.
+__device__ void sort_cold_tile(uint32_t n_cb, uint64_t base, uint32_t m,
+                               const uint32_t *__restrict__ cold, uint32_t *__restrict__ cold_sorted,
+                               uint32_t *__restrict__ off, uint32_t *sorted, uint32_t *bc,
+                               uint32_t *scan_tmp) {
+  const unsigned tid = threadIdx.x;
+  constexpr uint32_t kPer = kColdTile / kHotThreads;
+  uint32_t key[kPer];
+#pragma unroll
+  for (uint32_t j = 0; j < kPer; ++j) {
+    const uint32_t k = j * kHotThreads + tid;
+    key[j] = k < m ? cold[base + k] : kEmpty;
+  }
+  for (uint32_t b = tid; b < n_cb; b += kHotThreads) bc[b] = 0;
+  __syncthreads();
+#pragma unroll
+  for (uint32_t j = 0; j < kPer; ++j)
+    if (key[j] != kEmpty) atomicAdd(&bc[cold_bucket(key[j])], 1u);
+  __syncthreads();
+  {
+    const uint32_t c = tid < n_cb ? bc[tid] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_excl_scan<kHotThreads>(c, scan_tmp, &total);
+    if (tid < n_cb) {
+      bc[tid] = ex;
+      off[tid] = (uint32_t)(base + ex);
+    }
+    if (tid == 0) off[n_cb] = (uint32_t)(base + total);
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t j = 0; j < kPer; ++j)
+    if (key[j] != kEmpty) sorted[atomicAdd(&bc[cold_bucket(key[j])], 1u)] = key[j];
+  __syncthreads();
+  for (uint32_t k = tid; k < m; k += kHotThreads) cold_sorted[base + k] = sorted[k];
+  __syncthreads();
+}
+
 // Workgroup w reads records [w per, min((w + 1) per, n)) in steps of
 // kHotStep (per is a multiple of kHotStep), the loads of the next two steps
 // in flight while a step is counted; its cold keys are appended to cold[]
 // from index w per on (one LDS reservation per wave and step), their number
-// to n_cold[w].
+// to n_cold[w].  Then the workgroup sorts its cold keys by bucket in tiles
+// of kColdTile: tile t's bucket starts go to
+// tile_off[(w T + t) (n_cb + 1) + b] (entry n_cb: the end).
 template <bool VEC>
 __global__ void __launch_bounds__(kHotThreads)
-k_hot_pass(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint64_t per,
-           const uint32_t *__restrict__ hot_tab, uint32_t *__restrict__ partial,
-           uint32_t *__restrict__ cold, uint32_t *__restrict__ n_cold,
-           TileTotals *__restrict__ wtot) {
+k_hot_pass(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint32_t n_cb,
+           uint64_t per, uint32_t T, const uint32_t *__restrict__ hot_tab,
+           uint32_t *__restrict__ partial, uint32_t *__restrict__ cold,
+           uint32_t *__restrict__ cold_sorted, uint32_t *__restrict__ tile_off,
+           uint32_t *__restrict__ n_cold, TileTotals *__restrict__ wtot) {
   __shared__ uint32_t bins[kHotBins];
   __shared__ uint32_t tab[kHotT];
+  __shared__ uint32_t sorted[kColdTile];
+  __shared__ uint32_t bc[kColdMaxBuckets];
+  __shared__ uint32_t scan_tmp[kHotThreads / kWave + 1];
   __shared__ uint32_t s_cur, s_valid, s_lat;
   const unsigned tid = threadIdx.x, lane = lane_id();
   const uint64_t r0 = (uint64_t)blockIdx.x * per, r1 = min(r0 + per, n);
@@ -761,54 +809,11 @@ k_hot_pass(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint6
     wtot[blockIdx.x] = t;
     n_cold[blockIdx.x] = s_cur;
   }
-}
-
-// Tile t of workgroup w's cold keys (grid G x T, tiles past the workgroup's
-// keys exit): sorted by bucket into cold_sorted at the same indices, the
-// bucket starts to tile_off[(w T + t) (n_cb + 1) + b] (entry n_cb: the end).
-__global__ void __launch_bounds__(kHotThreads)
-k_cold_sort(uint32_t n_cb, uint64_t per, uint32_t T, const uint32_t *__restrict__ n_cold,
-            const uint32_t *__restrict__ cold, uint32_t *__restrict__ cold_sorted,
-            uint32_t *__restrict__ tile_off) {
-  __shared__ uint32_t sorted[kColdTile];
-  __shared__ uint32_t bc[kColdMaxBuckets];
-  __shared__ uint32_t scan_tmp[kHotThreads / kWave + 1];
-  const unsigned tid = threadIdx.x;
-  const uint32_t w = blockIdx.x / T, t = blockIdx.x % T;
-  const uint32_t nc = n_cold[w], a = t * kColdTile;
-  if (a >= nc) return;
-  const uint32_t m = min(kColdTile, nc - a);
-  const uint64_t base = (uint64_t)w * per + a;
-  constexpr uint32_t kPer = kColdTile / kHotThreads;
-  uint32_t key[kPer];
-#pragma unroll
-  for (uint32_t j = 0; j < kPer; ++j) {
-    const uint32_t k = j * kHotThreads + tid;
-    key[j] = k < m ? cold[base + k] : kEmpty;
-  }
-  for (uint32_t b = tid; b < n_cb; b += kHotThreads) bc[b] = 0;
-  __syncthreads();
-#pragma unroll
-  for (uint32_t j = 0; j < kPer; ++j)
-    if (key[j] != kEmpty) atomicAdd(&bc[cold_bucket(key[j])], 1u);
-  __syncthreads();
-  uint32_t *off = tile_off + ((size_t)w * T + t) * (n_cb + 1);
-  {
-    const uint32_t c = tid < n_cb ? bc[tid] : 0u;
-    uint32_t total;
-    const uint32_t ex = block_excl_scan<kHotThreads>(c, scan_tmp, &total);
-    if (tid < n_cb) {
-      bc[tid] = ex;
-      off[tid] = (uint32_t)(base + ex);
-    }
-    if (tid == 0) off[n_cb] = (uint32_t)(base + total);
-  }
-  __syncthreads();
-#pragma unroll
-  for (uint32_t j = 0; j < kPer; ++j)
-    if (key[j] != kEmpty) sorted[atomicAdd(&bc[cold_bucket(key[j])], 1u)] = key[j];
-  __syncthreads();
-  for (uint32_t k = tid; k < m; k += kHotThreads) cold_sorted[base + k] = sorted[k];
+  const uint32_t nc = s_cur;   // the keys were written before the barrier above
+  for (uint32_t t = 0; t * kColdTile < nc; ++t)
+    sort_cold_tile(n_cb, r0 + t * kColdTile, min(kColdTile, nc - t * kColdTile), cold,
+                   cold_sorted, tile_off + ((size_t)blockIdx.x * T + t) * (n_cb + 1), sorted, bc,
+                   scan_tmp);
 }
 
 // blocks [0, n_cb): the cold bins of one bucket; the next
@@ -970,7 +975,7 @@ static bool run_hist_hot(const gpa_program &p, const uint64_t *rec, uint64_t n, 
   per = (per + kHotStep - 1) / kHotStep * kHotStep;
   const uint32_t G = (uint32_t)((n + per - 1) / per);
   const uint32_t T = (uint32_t)((per + kColdTile - 1) / kColdTile);   // tiles per workgroup
-  const uint64_t run_stride = n > kSelSample ? (n - kSelRun) / 63 : 0;
+  const uint64_t run_stride = n > kSelSample ? (n - kSelRun) / (kSelSample / kSelRun - 1) : 0;
   uint32_t *hot_tab = ar.get<uint32_t>(kHotT);
   uint32_t *hot_pc = ar.get<uint32_t>(kHotH);
   uint32_t *n_hot = ar.get<uint32_t>(1);
@@ -987,14 +992,11 @@ static bool run_hist_hot(const gpa_program &p, const uint64_t *rec, uint64_t n, 
                      n_instr, hot_tab, hot_pc, n_hot);
   GPA_LAUNCH_CHECK();
   if (vec)
-    hipLaunchKernelGGL(k_hot_pass<true>, dim3(G), dim3(kHotThreads), 0, s, rec, n, n_instr, per,
-                       hot_tab, partial, cold, n_cold, wtot);
+    hipLaunchKernelGGL(k_hot_pass<true>, dim3(G), dim3(kHotThreads), 0, s, rec, n, n_instr, n_cb,
+                       per, T, hot_tab, partial, cold, cold_sorted, tile_off, n_cold, wtot);
   else
-    hipLaunchKernelGGL(k_hot_pass<false>, dim3(G), dim3(kHotThreads), 0, s, rec, n, n_instr, per,
-                       hot_tab, partial, cold, n_cold, wtot);
-  GPA_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_cold_sort, dim3(G * T), dim3(kHotThreads), 0, s, n_cb, per, T, n_cold, cold,
-                     cold_sorted, tile_off);
+    hipLaunchKernelGGL(k_hot_pass<false>, dim3(G), dim3(kHotThreads), 0, s, rec, n, n_instr, n_cb,
+                       per, T, hot_tab, partial, cold, cold_sorted, tile_off, n_cold, wtot);
   GPA_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_hot_finish, dim3(n_cb + kHotBins / kHotMergeCols + 1), dim3(kHotThreads), 0,
                      s, n_instr, n_cb, G, T, hot_pc, n_hot, partial, cold_sorted, tile_off, n_cold,
