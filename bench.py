@@ -61,7 +61,10 @@ def _traffic(n_launches_ref=None):
     return t.get("bytes_per_pass")
 
 
-HIST_KERNELS = ("k_hsample", "k_hregions", "k_partition", "k_hplan", "k_count", "k_merge",
+# the hot-set path (programs up to 2^17 instructions, the large workload) and
+# the partition path beyond it
+HIST_KERNELS = ("k_hot_select", "k_hot_pass", "k_hot_finish",
+                "k_hsample", "k_hregions", "k_partition", "k_hplan", "k_count", "k_merge",
                 "k_hoverflow")
 
 
@@ -99,7 +102,8 @@ def summarize_traffic(fetch_dir, write_dir, copy_mb, out_path):
             raise SystemExit(f"no copy kernel in the {counter} run")
         copy_kib = max(copy_vals)   # the large calibration copy
         factor = (copy_mb * 1024.0) / copy_kib
-        n_pass = max(len(v) for k, v in per_kernel.items() if k in ("k_partition", "k_count"))
+        n_pass = max(len(v) for k, v in per_kernel.items()
+                     if k in ("k_hot_pass", "k_partition", "k_count"))
         kib = sum(sum(v) for v in per_kernel.values()) / n_pass
         res[counter] = {"kib_per_pass_raw": kib, "copy_kib_raw": copy_kib,
                         "scale": factor, "bytes_per_pass": kib * 1024.0 * factor,
@@ -262,7 +266,7 @@ def main():
     # per-unit algorithmic work of each kernel family
     work = {
         "hist": ("hbm", 8.0 * n_rec + 96.0 * n_instr,
-                 "gpa_hist: sample histogram pass (k_hsample, k_partition, k_count, k_merge)"),
+                 "gpa_hist: sample histogram (k_hot_select, k_hot_pass, k_hot_finish)"),
         "blame": ("hbm", 60.0 * n_edges + 288.0 * n_instr, "gpa_blame: k_blame_dst + k_blame_src"),
         "advise": ("hbm", 72.0 * n_scopes + 88.0 * n_instr + 8.0 * n_edges,
                    "gpa_estimate: contributions, scope sums, speedups, top-k"),

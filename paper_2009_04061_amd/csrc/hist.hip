@@ -605,7 +605,9 @@ k_hot_select(const uint64_t *__restrict__ rec, uint64_t n, uint64_t run_stride, 
   for (uint32_t k = tid; k < kHotT; k += kHotThreads) tab[k] = kEmpty;
   if (tid == 0) s_nsel = 0;
   __syncthreads();
-#pragma unroll
+  // a rolled loop: this kernel runs once per call, so its code is fetched
+  // cold and a short body costs less than unrolled copies
+#pragma unroll 1
   for (uint32_t j = 0; j < kPer; ++j) {
     if (!rec_valid(r[j], n_instr)) continue;
     const uint32_t c = (uint32_t)r[j] >> sh, half = 16 * (c & 1);
