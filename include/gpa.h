@@ -175,7 +175,10 @@ gpa_status gpa_program_edges(const gpa_program *p, uint32_t *src, uint32_t *dst,
  * samples_on_device != 0: `samples` is a device pointer that must stay
  * valid until the call returns.  Counts the samples (Sec. 2.1) and runs
  * the instruction blamer (Sec. 4, Eq. 1).  At most 2^30 - 1 samples per
- * call and 2^22 instructions in the program (GPA_E_UNSUPPORTED beyond). */
+ * call and 2^22 instructions in the program (GPA_E_UNSUPPORTED beyond).
+ * Programs of up to 2^17 instructions are counted by a hot-set pass, larger
+ * ones by a bucket partition; the environment variable GPA_HIST_PARTITION=1
+ * selects the partition for every program (the counts are the same). */
 gpa_status gpa_attribute(gpa_program *p, const gpa_sample *samples, uint64_t n,
                          int samples_on_device, void *stream, gpa_blame **out);
 void gpa_blame_free(gpa_blame *b);
