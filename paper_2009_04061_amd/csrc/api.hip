@@ -390,6 +390,7 @@ gpa_status gpa_load_program(const gpa_program_desc *d, void *stream, gpa_program
                            hipMemcpyDeviceToHost, s));
     GPA_HIP(hipStreamSynchronize(s));
     p->n_roots_dev = nullptr;
+    p->sync_words = nullptr;   // arena memory, returned with this call
     t_load.collect();
     t_val.collect();
     t_sites.collect();

@@ -142,6 +142,9 @@ struct gpa_program {
   gpa::DBuf<uint32_t> roots;                   // kernel root scope ids
   uint32_t n_roots = 0;
   uint32_t *n_roots_dev = nullptr;   // during the load: device copy of n_roots
+  // during the load: 8 device words read back together at each host
+  // synchronization (validation verdict, then the reaching-definition sizes)
+  uint32_t *sync_words = nullptr;
   hipStream_t stream = nullptr;
 };
 

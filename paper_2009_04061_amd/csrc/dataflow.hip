@@ -647,7 +647,9 @@ void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar, PhaseTimer &t
   const size_t nfl = (size_t)nf * nl;
   uint32_t *dsi = ar.get<uint32_t>(p.n_defs), *usi = ar.get<uint32_t>(p.n_uses);
   uint8_t *dsg = ar.get<uint8_t>(p.n_defs);
-  uint32_t *scal = ar.get<uint32_t>(2);   // [0] largest IN bitset in words, [1] long searches
+  // synchronization words: [0, 2) the IN slot total, [2] the largest IN
+  // bitset in words, [3] the long searches, [4] the kernel roots (k_roots)
+  uint32_t *scal = p.sync_words + 2;
   hipLaunchKernelGGL(k_sorted_views, dim3(grid_for((size_t)p.n_defs + p.n_uses, 256, 8192)),
                      dim3(256), 0, s, p.n_defs, p.n_uses, p.def_site_sorted.p, p.def_instr.p,
                      p.use_site_sorted.p, p.use_instr.p, p.guard.p, dsi, dsg, usi, scal);
@@ -659,28 +661,28 @@ void build_reaching_defs(gpa_program &p, hipStream_t s, Arena &ar, PhaseTimer &t
   // IN slots per use site, in sorted-use order
   uint32_t *slot_words = ar.get<uint32_t>(p.n_uses);
   uint32_t *slot_start = ar.get<uint32_t>(p.n_uses);
-  unsigned long long *nslot_d = ar.get<unsigned long long>(1);
+  unsigned long long *nslot_d = (unsigned long long *)p.sync_words;
   hipLaunchKernelGGL(k_use_slots, dim3(grid_for(p.n_uses, 256, 4096)), dim3(256), 0, s, p.n_uses,
                      p.use_instr.p, p.use_loc.p, p.block_of.p, p.func_of_block.p, nl, fl_words,
                      fl_chunks, p.use_rank.p, slot_words);
   GPA_LAUNCH_CHECK();
   exclusive_scan_u32(slot_words, slot_start, p.n_uses, s, ar, nslot_d);
-  unsigned long long nslot = 0;
-  uint32_t max_words = 0;
-  GPA_HIP(hipMemcpyAsync(&nslot, nslot_d, sizeof(nslot), hipMemcpyDeviceToHost, s));
-  GPA_HIP(hipMemcpyAsync(&max_words, scal, sizeof(max_words), hipMemcpyDeviceToHost, s));
-  if (p.n_roots_dev)
-    GPA_HIP(hipMemcpyAsync(&p.n_roots, p.n_roots_dev, 4, hipMemcpyDeviceToHost, s));
-  GPA_HIP(hipStreamSynchronize(s));
-  p.n_roots_dev = nullptr;
-  uint64_t *rd_in = ar.get<uint64_t>(nslot ? nslot : 1);
-  // the (location, block) index: the searches and the per-use lists read it
+  // the (location, block) index (the searches and the per-use lists read
+  // it) is built while the host waits for the sizes
   uint4 *t0 = ar.get<uint4>((size_t)nl * nb);
   uint2 *t1 = ar.get<uint2>((size_t)nl * nb);
   hipLaunchKernelGGL(k_loc_block_index, dim3(grid_for((size_t)nl * nb, 256, 8192)), dim3(256), 0,
                      s, nb, nl, p.func_of_block.p, p.block_begin.p, p.fl_def_ptr.p,
                      p.fl_use_ptr.p, dsi, dsg, usi, t0, t1);
   GPA_LAUNCH_CHECK();
+  uint32_t h[5];
+  GPA_HIP(hipMemcpyAsync(h, p.sync_words, sizeof(h), hipMemcpyDeviceToHost, s));
+  GPA_HIP(hipStreamSynchronize(s));
+  const unsigned long long nslot = (unsigned long long)h[0] | ((unsigned long long)h[1] << 32);
+  const uint32_t max_words = h[2];
+  if (p.n_roots_dev) p.n_roots = h[4];
+  p.n_roots_dev = nullptr;
+  uint64_t *rd_in = ar.get<uint64_t>(nslot ? nslot : 1);
   if (nslot) {
     const size_t lds_long = kStageRows + 8u * (size_t)max_words + kStagePred +
                             4u * ((p.max_func_blocks + 31) / 32) + 4u * (size_t)p.max_func_blocks;

@@ -538,6 +538,7 @@ void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar) {
   // (words 2-5, see k_max_func_blocks).
   uint32_t *vals = ar.get<uint32_t>(8);
   uint32_t *err = vals, *mx = vals + 2;
+  p.sync_words = vals;
   hipLaunchKernelGGL(k_val_ends, dim3(1), dim3(1), 0, s, n, nb, nf, p.def_ptr.p, p.use_ptr.p,
                      p.block_begin.p, p.succ_ptr.p, p.func_block_begin.p, vals);
   hipLaunchKernelGGL(k_val_instr, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, n, p.n_preds, ns,
@@ -622,8 +623,9 @@ void build_sites_and_scopes(gpa_program &p, hipStream_t s, Arena &ar) {
                      p.instr_scope.p, p.scope_parent.p, p.scope_kind.p, p.scope_flags.p,
                      p.instr_tags.p);
   p.roots.alloc(ns);
-  // the count is read with the next host synchronization of the load
-  p.n_roots_dev = ar.get<uint32_t>(1);
+  // the count is read with the next host synchronization of the load (word
+  // 4 of the synchronization words, free after the validation verdict)
+  p.n_roots_dev = p.sync_words + 4;
   hipLaunchKernelGGL(k_roots, dim3(1), dim3(1024), 0, s, ns, p.scope_parent.p, p.roots.p,
                      p.n_roots_dev);
   GPA_LAUNCH_CHECK();
