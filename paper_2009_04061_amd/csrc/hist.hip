@@ -552,7 +552,7 @@ constexpr uint32_t kColdShift = 8;
 constexpr uint32_t kColdPCs = 1u << kColdShift;  // PCs per cold bucket
 constexpr uint32_t kColdBins = kColdPCs * 24;
 constexpr uint32_t kColdMaxBuckets = kHotMaxPCs / kColdPCs;
-constexpr uint32_t kColdTile = 8192;             // cold keys per sorted tile
+constexpr uint32_t kColdTile = 16384;            // cold keys per sorted tile
 constexpr uint32_t kSelSample = 16384;           // sampled records
 constexpr uint32_t kSelRun = 128;                // records per sampled run
 constexpr uint32_t kSelCounters = 1u << 16;      // 16-bit, two per word
