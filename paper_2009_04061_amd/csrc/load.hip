@@ -219,35 +219,59 @@ __global__ void k_val_instr_scope(uint32_t n_instr, uint32_t n_scopes, const uin
 // ------------------------------------------------- sites by (func, location)
 // Sites (defs or uses) of function f occupy [site_ptr[i0], site_ptr[i1]) for
 // its instruction range [i0, i1); they are processed in chunks of kChunk.
+// Defs (set 0) and uses (set 1) are sorted by the same launches: grid row y
+// or the chunk's set field picks the set.
 constexpr int kSortThreads = 256;
 constexpr int kChunk = 2048;
 
 struct SiteChunk {
-  uint32_t func, begin, end, pad;
+  uint32_t func, begin, end, set;
 };
 
+struct SiteSet {
+  const uint32_t *site_ptr;   // [n_instr + 1]
+  const uint32_t *key;        // location of each site
+  uint32_t *fl_ptr;           // [n_funcs][n_loc + 1] list starts, closing entry last
+  uint32_t *sorted;           // sites in (function, location, instruction) order
+  uint32_t *rank_of;          // site -> its position in sorted
+};
+struct SiteSets {
+  SiteSet set[2];
+};
+
+__device__ __forceinline__ void func_sites(const SiteSet &ss, const uint32_t *fbb,
+                                           const uint32_t *block_begin, uint32_t f, uint32_t &s0,
+                                           uint32_t &s1) {
+  s0 = ss.site_ptr[block_begin[fbb[f]]];
+  s1 = ss.site_ptr[block_begin[fbb[f + 1]]];
+}
+
+// nchunks[set * n_funcs + f]
 __global__ void k_chunk_count(uint32_t n_funcs, const uint32_t *fbb, const uint32_t *block_begin,
-                              const uint32_t *site_ptr, uint32_t *nchunks) {
+                              SiteSets sets, uint32_t *nchunks) {
+  const uint32_t y = blockIdx.y;
   for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < n_funcs;
        f += gridDim.x * blockDim.x) {
-    const uint32_t s0 = site_ptr[block_begin[fbb[f]]], s1 = site_ptr[block_begin[fbb[f + 1]]];
-    nchunks[f] = (s1 - s0 + kChunk - 1) / kChunk;
+    uint32_t s0, s1;
+    func_sites(sets.set[y], fbb, block_begin, f, s0, s1);
+    nchunks[y * n_funcs + f] = (s1 - s0 + kChunk - 1) / kChunk;
   }
 }
 
 __global__ void k_chunk_fill(uint32_t n_funcs, const uint32_t *fbb, const uint32_t *block_begin,
-                             const uint32_t *site_ptr, const uint32_t *chunk_start,
-                             SiteChunk *chunks) {
+                             SiteSets sets, const uint32_t *chunk_start, SiteChunk *chunks) {
+  const uint32_t y = blockIdx.y;
   for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < n_funcs;
        f += gridDim.x * blockDim.x) {
-    const uint32_t s0 = site_ptr[block_begin[fbb[f]]], s1 = site_ptr[block_begin[fbb[f + 1]]];
-    uint32_t c = chunk_start[f];
+    uint32_t s0, s1;
+    func_sites(sets.set[y], fbb, block_begin, f, s0, s1);
+    uint32_t c = chunk_start[y * n_funcs + f];
     for (uint32_t a = s0; a < s1; a += kChunk, ++c) {
       SiteChunk ch;
       ch.func = f;
       ch.begin = a;
       ch.end = min(a + kChunk, s1);
-      ch.pad = 0;
+      ch.set = y;
       chunks[c] = ch;
     }
   }
@@ -255,11 +279,12 @@ __global__ void k_chunk_fill(uint32_t n_funcs, const uint32_t *fbb, const uint32
 
 // per chunk, the number of sites of each location
 __global__ void __launch_bounds__(kSortThreads)
-k_chunk_hist(const SiteChunk *chunks, const unsigned long long *n_chunks, const uint32_t *key,
+k_chunk_hist(const SiteChunk *chunks, const unsigned long long *n_chunks, SiteSets sets,
              uint32_t n_loc, uint32_t *chunk_cnt) {
   extern __shared__ uint32_t cnt[];
   if (blockIdx.x >= *n_chunks) return;
   const SiteChunk ch = chunks[blockIdx.x];
+  const uint32_t *key = sets.set[ch.set].key;
   for (uint32_t x = threadIdx.x; x < n_loc; x += kSortThreads) cnt[x] = 0;
   __syncthreads();
   for (uint32_t s = ch.begin + threadIdx.x; s < ch.end; s += kSortThreads) atomicAdd(&cnt[key[s]], 1u);
@@ -268,18 +293,21 @@ k_chunk_hist(const SiteChunk *chunks, const unsigned long long *n_chunks, const 
     chunk_cnt[(size_t)blockIdx.x * n_loc + x] = cnt[x];
 }
 
-// per function: start of each (function, location) list (fl_ptr) and each
-// chunk's offset inside its location's list (written over the per-chunk
-// counts; k_chunk_scatter adds the list start).  Each thread takes up to 4
-// locations and walks their columns eight chunks per batch of loads.
+// per (function, set): start of each (function, location) list (fl_ptr) and
+// each chunk's offset inside its location's list (written over the
+// per-chunk counts; k_chunk_scatter adds the list start).  Each thread takes
+// up to 4 locations and walks their columns eight chunks per batch of loads.
+// Every list start is written, also for functions without sites.
 __global__ void __launch_bounds__(kSortThreads)
-k_chunk_bases(uint32_t n_funcs, const uint32_t *fbb, const uint32_t *block_begin,
-              const uint32_t *site_ptr, const uint32_t *chunk_start, const uint32_t *nchunks,
-              uint32_t n_loc, uint32_t *chunk_cnt, uint32_t *fl_ptr) {
+k_chunk_bases(uint32_t n_funcs, const uint32_t *fbb, const uint32_t *block_begin, SiteSets sets,
+              const uint32_t *chunk_start, const uint32_t *nchunks, uint32_t n_loc,
+              uint32_t *chunk_cnt) {
   __shared__ uint32_t tmp[kSortThreads / kWave + 1];
-  const uint32_t f = blockIdx.x;
-  const uint32_t s0 = site_ptr[block_begin[fbb[f]]];
-  const uint32_t c0 = chunk_start[f], nc = nchunks[f];
+  const uint32_t f = blockIdx.x, y = blockIdx.y;
+  const SiteSet &ss = sets.set[y];
+  uint32_t s0, s1;
+  func_sites(ss, fbb, block_begin, f, s0, s1);
+  const uint32_t c0 = chunk_start[y * n_funcs + f], nc = nchunks[y * n_funcs + f];
   const uint32_t per = (n_loc + kSortThreads - 1) / kSortThreads;   // <= 4
   const uint32_t x0 = min(threadIdx.x * per, n_loc), x1 = min(x0 + per, n_loc);
   uint32_t tot[4] = {0, 0, 0, 0};
@@ -309,29 +337,30 @@ k_chunk_bases(uint32_t n_funcs, const uint32_t *fbb, const uint32_t *block_begin
   for (uint32_t i = 0; i < 4; ++i) {
     const uint32_t x = x0 + i;
     if (x >= x1) continue;
-    fl_ptr[(size_t)f * (n_loc + 1) + x] = base;
+    ss.fl_ptr[(size_t)f * (n_loc + 1) + x] = base;
     base += tot[i];
   }
   // the function's closing entry: one past its last site
-  if (threadIdx.x == 0) fl_ptr[(size_t)f * (n_loc + 1) + n_loc] = s0 + total;
+  if (threadIdx.x == 0) ss.fl_ptr[(size_t)f * (n_loc + 1) + n_loc] = s0 + total;
 }
 
 // Stable scatter: rounds of kSortThreads consecutive sites; the rank of a
 // site among equal keys of its round comes from ballot matching inside the
 // wave plus per-wave counts in LDS; per-location cursors carry across rounds.
 __global__ void __launch_bounds__(kSortThreads)
-k_chunk_scatter(const SiteChunk *chunks, const unsigned long long *n_chunks, const uint32_t *key,
-                uint32_t n_loc, uint32_t key_bits, const uint32_t *chunk_base,
-                const uint32_t *fl_ptr, uint32_t *sorted, uint32_t *rank_of) {
+k_chunk_scatter(const SiteChunk *chunks, const unsigned long long *n_chunks, SiteSets sets,
+                uint32_t n_loc, uint32_t key_bits, const uint32_t *chunk_base) {
   extern __shared__ uint32_t sh[];
   uint32_t *cursor = sh;                        // [n_loc]
   uint32_t *wcnt = sh + n_loc;                  // [4][n_loc]
   constexpr int NW = kSortThreads / kWave;
   if (blockIdx.x >= *n_chunks) return;
   const SiteChunk ch = chunks[blockIdx.x];
+  const SiteSet &ss = sets.set[ch.set];
+  const uint32_t *key = ss.key;
   const unsigned tid = threadIdx.x, w = tid / kWave, lane = lane_id();
   for (uint32_t x = tid; x < n_loc; x += kSortThreads) {
-    cursor[x] = chunk_base[(size_t)blockIdx.x * n_loc + x] + fl_ptr[(size_t)ch.func * (n_loc + 1) + x];
+    cursor[x] = chunk_base[(size_t)blockIdx.x * n_loc + x] + ss.fl_ptr[(size_t)ch.func * (n_loc + 1) + x];
     for (int k = 0; k < NW; ++k) wcnt[k * n_loc + x] = 0;
   }
   __syncthreads();
@@ -353,8 +382,8 @@ k_chunk_scatter(const SiteChunk *chunks, const unsigned long long *n_chunks, con
       uint32_t before = 0;
       for (unsigned v = 0; v < w; ++v) before += wcnt[v * n_loc + k];
       const uint32_t pos = cursor[k] + before + in_wave;
-      sorted[pos] = s;
-      rank_of[s] = pos;
+      ss.sorted[pos] = s;
+      ss.rank_of[s] = pos;
     }
     __syncthreads();
     if (active && lower == 0) {
@@ -372,8 +401,11 @@ k_chunk_scatter(const SiteChunk *chunks, const unsigned long long *n_chunks, con
   }
 }
 
-// site -> instruction
-__global__ void k_site_instr(uint32_t n_instr, const uint32_t *site_ptr, uint32_t *site_instr) {
+// site -> instruction, grid row 0 for the defs, 1 for the uses
+__global__ void k_site_instr(uint32_t n_instr, const uint32_t *def_ptr, uint32_t *def_instr,
+                             const uint32_t *use_ptr, uint32_t *use_instr) {
+  const uint32_t *site_ptr = blockIdx.y ? use_ptr : def_ptr;
+  uint32_t *site_instr = blockIdx.y ? use_instr : def_instr;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_instr; i += gridDim.x * blockDim.x)
     for (uint32_t s = site_ptr[i]; s < site_ptr[i + 1]; ++s) site_instr[s] = i;
 }
@@ -489,44 +521,43 @@ static void raise_validation(uint32_t err) {
   fail(GPA_E_INVALID, "%s", msg.c_str());
 }
 
-static void sort_sites(gpa_program &p, hipStream_t s, Arena &ar, const uint32_t *site_ptr,
-                       const uint32_t *key, uint32_t n_sites, DBuf<uint32_t> &sorted,
-                       DBuf<uint32_t> &fl_ptr, uint32_t *rank_of) {
+// defs and uses sorted by (function, location, instruction), both sets in
+// the same launches
+static void sort_sites(gpa_program &p, hipStream_t s, Arena &ar) {
   const uint32_t nf = p.n_funcs, nl = p.n_loc;
-  uint32_t *nchunks = ar.get<uint32_t>(nf);
-  uint32_t *cstart = ar.get<uint32_t>(nf);
+  p.def_site_sorted.alloc(p.n_defs);
+  p.use_site_sorted.alloc(p.n_uses);
+  p.fl_def_ptr.alloc((size_t)nf * (nl + 1));
+  p.fl_use_ptr.alloc((size_t)nf * (nl + 1));
+  SiteSets sets;
+  sets.set[0] = SiteSet{p.def_ptr.p, p.def_loc.p, p.fl_def_ptr.p, p.def_site_sorted.p, p.def_rank.p};
+  sets.set[1] = SiteSet{p.use_ptr.p, p.use_loc.p, p.fl_use_ptr.p, p.use_site_sorted.p, p.use_rank.p};
+  uint32_t *nchunks = ar.get<uint32_t>(2 * (size_t)nf);
+  uint32_t *cstart = ar.get<uint32_t>(2 * (size_t)nf);
   unsigned long long *ntot = ar.get<unsigned long long>(1);
-  hipLaunchKernelGGL(k_chunk_count, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf,
-                     p.func_block_begin.p, p.block_begin.p, site_ptr, nchunks);
+  hipLaunchKernelGGL(k_chunk_count, dim3(grid_for(nf, 256), 2), dim3(256), 0, s, nf,
+                     p.func_block_begin.p, p.block_begin.p, sets, nchunks);
   GPA_LAUNCH_CHECK();
-  exclusive_scan_u32(nchunks, cstart, nf, s, ar, ntot);
-  // chunks <= sites / kChunk + one partial chunk per function; the kernels
-  // read the exact count from device memory
-  const uint32_t n_chunks = (uint32_t)(n_sites / kChunk + nf);
-  sorted.alloc(n_sites);
-  fl_ptr.alloc((size_t)nf * (nl + 1));
-  // without sites every list is empty; otherwise k_chunk_bases writes every
-  // list start and each function's closing entry
-  if (n_sites == 0) {
-    GPA_HIP(hipMemsetAsync(fl_ptr.p, 0, sizeof(uint32_t) * fl_ptr.n, s));
-    return;
-  }
+  exclusive_scan_u32(nchunks, cstart, 2 * (size_t)nf, s, ar, ntot);
+  // chunks <= sites / kChunk + one partial chunk per (function, set); the
+  // kernels read the exact count from device memory
+  const uint32_t n_chunks = (uint32_t)((p.n_defs + p.n_uses) / kChunk + 2 * nf);
   SiteChunk *chunks = ar.get<SiteChunk>(n_chunks);
-  hipLaunchKernelGGL(k_chunk_fill, dim3(grid_for(nf, 256)), dim3(256), 0, s, nf,
-                     p.func_block_begin.p, p.block_begin.p, site_ptr, cstart, chunks);
+  hipLaunchKernelGGL(k_chunk_fill, dim3(grid_for(nf, 256), 2), dim3(256), 0, s, nf,
+                     p.func_block_begin.p, p.block_begin.p, sets, cstart, chunks);
   GPA_LAUNCH_CHECK();
   uint32_t *ccnt = ar.get<uint32_t>((size_t)n_chunks * nl);
-  hipLaunchKernelGGL(k_chunk_hist, dim3(n_chunks), dim3(kSortThreads), nl * 4, s, chunks, ntot, key,
+  hipLaunchKernelGGL(k_chunk_hist, dim3(n_chunks), dim3(kSortThreads), nl * 4, s, chunks, ntot, sets,
                      nl, ccnt);
   GPA_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_chunk_bases, dim3(nf), dim3(kSortThreads), 0, s, nf, p.func_block_begin.p,
-                     p.block_begin.p, site_ptr, cstart, nchunks, nl, ccnt, fl_ptr.p);
+  hipLaunchKernelGGL(k_chunk_bases, dim3(nf, 2), dim3(kSortThreads), 0, s, nf, p.func_block_begin.p,
+                     p.block_begin.p, sets, cstart, nchunks, nl, ccnt);
   GPA_LAUNCH_CHECK();
   uint32_t key_bits = 1;
   while ((1u << key_bits) < nl) ++key_bits;
   const size_t lds = (size_t)nl * 4 * (1 + kSortThreads / kWave);
-  hipLaunchKernelGGL(k_chunk_scatter, dim3(n_chunks), dim3(kSortThreads), lds, s, chunks, ntot, key,
-                     nl, key_bits, ccnt, fl_ptr.p, sorted.p, rank_of);
+  hipLaunchKernelGGL(k_chunk_scatter, dim3(n_chunks), dim3(kSortThreads), lds, s, chunks, ntot, sets,
+                     nl, key_bits, ccnt);
   GPA_LAUNCH_CHECK();
 }
 
@@ -591,21 +622,16 @@ void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar) {
 }
 
 void build_sites_and_scopes(gpa_program &p, hipStream_t s, Arena &ar) {
-  const uint32_t n = p.n_instr, nf = p.n_funcs, ns = p.n_scopes;
+  const uint32_t n = p.n_instr, ns = p.n_scopes;
   // sites by (function, location, instruction)
   p.def_instr.alloc(p.n_defs);
   p.use_instr.alloc(p.n_uses);
-  hipLaunchKernelGGL(k_site_instr, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, n, p.def_ptr.p,
-                     p.def_instr.p);
-  hipLaunchKernelGGL(k_site_instr, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, n, p.use_ptr.p,
-                     p.use_instr.p);
+  hipLaunchKernelGGL(k_site_instr, dim3(grid_for(n, 256, 2048), 2), dim3(256), 0, s, n,
+                     p.def_ptr.p, p.def_instr.p, p.use_ptr.p, p.use_instr.p);
   GPA_LAUNCH_CHECK();
   p.def_rank.alloc(p.n_defs);
   p.use_rank.alloc(p.n_uses);
-  sort_sites(p, s, ar, p.def_ptr.p, p.def_loc.p, p.n_defs, p.def_site_sorted, p.fl_def_ptr,
-             p.def_rank.p);
-  sort_sites(p, s, ar, p.use_ptr.p, p.use_loc.p, p.n_uses, p.use_site_sorted, p.fl_use_ptr,
-             p.use_rank.p);
+  sort_sites(p, s, ar);
   p.use_cond.alloc(p.n_uses);
   hipLaunchKernelGGL(k_use_cond, dim3(grid_for(p.n_uses, 256, 4096)), dim3(256), 0, s, p.n_uses,
                      p.use_instr.p, p.use_kind.p, p.guard.p, p.use_cond.p);
