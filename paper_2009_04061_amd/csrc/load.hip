@@ -42,14 +42,14 @@ static const char *kErrText[] = {
 };
 
 // ------------------------------------------------------------ validation
-__global__ void k_val_instr(uint32_t n_instr, uint32_t n_preds, uint32_t n_scopes, uint32_t n_defs,
+__device__ void val_instr_part(uint32_t t0_, uint32_t st_, uint32_t n_instr, uint32_t n_preds, uint32_t n_scopes, uint32_t n_defs,
                             uint32_t n_uses, const uint8_t *op_class, const uint8_t *guard,
                             const uint32_t *def_ptr, const uint32_t *use_ptr,
                             const uint32_t *def_loc, const uint32_t *instr_scope,
                             const uint8_t *scope_kind, uint32_t *err) {
   uint32_t e = 0;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_instr;
-       i += gridDim.x * blockDim.x) {
+  for (uint32_t i = t0_; i < n_instr;
+       i += st_) {
     if (op_class[i] >= GPA_N_OP_CLASSES) e |= kErrOpClass;
     if (guard[i] > 2 * n_preds) e |= kErrGuard;
     if (def_ptr[i] > def_ptr[i + 1] || use_ptr[i] > use_ptr[i + 1] || def_ptr[i + 1] > n_defs ||
@@ -66,10 +66,10 @@ __global__ void k_val_instr(uint32_t n_instr, uint32_t n_preds, uint32_t n_scope
   if (e) atomicOr(err, e);
 }
 
-__global__ void k_val_sites(uint32_t n, const uint32_t *loc, const uint8_t *kind, uint32_t n_loc,
+__device__ void val_sites_part(uint32_t t0_, uint32_t st_, uint32_t n, const uint32_t *loc, const uint8_t *kind, uint32_t n_loc,
                             uint32_t max_kind, uint32_t bit, uint32_t *err) {
   uint32_t e = 0;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+  for (uint32_t i = t0_; i < n; i += st_)
     if (loc[i] >= n_loc || kind[i] > max_kind) e = bit;
   if (e) atomicOr(err, e);
 }
@@ -88,12 +88,12 @@ __global__ void k_val_ends(uint32_t n_instr, uint32_t n_blocks, uint32_t n_funcs
   for (int q = 1; q < 8; ++q) vals[q] = 0;
 }
 
-__global__ void k_val_funcs(uint32_t n_funcs, uint32_t n_scopes, const uint32_t *fbb,
+__device__ void val_funcs_part(uint32_t t0_, uint32_t st_, uint32_t n_funcs, uint32_t n_scopes, const uint32_t *fbb,
                             const uint32_t *func_scope, const uint8_t *scope_kind,
                             const uint8_t *scope_flags, uint32_t *err) {
   uint32_t e = 0;
-  for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < n_funcs;
-       f += gridDim.x * blockDim.x) {
+  for (uint32_t f = t0_; f < n_funcs;
+       f += st_) {
     if (fbb[f] >= fbb[f + 1]) e |= kErrFuncs;
     const uint32_t s = func_scope[f];
     if (s >= n_scopes || scope_kind[s] != GPA_SCOPE_FUNCTION || !(scope_flags[s] & GPA_SF_HAS_CFG))
@@ -102,11 +102,11 @@ __global__ void k_val_funcs(uint32_t n_funcs, uint32_t n_scopes, const uint32_t 
   if (e) atomicOr(err, e);
 }
 
-__global__ void k_val_scopes(uint32_t n_scopes, const uint32_t *parent, const uint8_t *kind,
+__device__ void val_scopes_part(uint32_t t0_, uint32_t st_, uint32_t n_scopes, const uint32_t *parent, const uint8_t *kind,
                              const uint8_t *flags, uint32_t *err) {
   uint32_t e = 0;
-  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_scopes;
-       s += gridDim.x * blockDim.x) {
+  for (uint32_t s = t0_; s < n_scopes;
+       s += st_) {
     const uint32_t p = parent[s];
     if (kind[s] > GPA_SCOPE_LINE) e |= kErrScopes;
     if (p == GPA_NONE) {
@@ -121,13 +121,13 @@ __global__ void k_val_scopes(uint32_t n_scopes, const uint32_t *parent, const ui
 // block structure: block -> function and instruction -> block by binary
 // search over the range starts (always in bounds; the blocks' own check
 // rejects a block_begin that is not strictly increasing)
-__global__ void k_blocks(uint32_t n_funcs, uint32_t n_blocks, uint32_t n_instr, const uint32_t *fbb,
+__device__ void blocks_part(uint32_t t0_, uint32_t st_, uint32_t n_funcs, uint32_t n_blocks, uint32_t n_instr, const uint32_t *fbb,
                          const uint32_t *block_begin, uint32_t *block_of, uint32_t *func_of_block,
                          uint32_t *pred_cnt, uint32_t *err) {
   uint32_t e = 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) pred_cnt[n_blocks] = 0;
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n_blocks + n_instr;
-       k += gridDim.x * blockDim.x) {
+  if (t0_ == 0) pred_cnt[n_blocks] = 0;
+  for (uint32_t k = t0_; k < n_blocks + n_instr;
+       k += st_) {
     if (k < n_blocks) {
       pred_cnt[k] = 0;
       func_of_block[k] = upper_index_u32(fbb, 0, n_funcs, k);
@@ -141,12 +141,12 @@ __global__ void k_blocks(uint32_t n_funcs, uint32_t n_blocks, uint32_t n_instr, 
   if (e) atomicOr(err, e);
 }
 
-__global__ void k_val_succ(uint32_t n_blocks, const uint32_t *succ_ptr, const uint32_t *succ,
+__device__ void val_succ_part(uint32_t t0_, uint32_t st_, uint32_t n_blocks, const uint32_t *succ_ptr, const uint32_t *succ,
                            uint32_t n_succ, const uint32_t *func_of_block, uint32_t *pred_cnt,
                            uint32_t *err) {
   uint32_t e = 0;
-  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_blocks;
-       b += gridDim.x * blockDim.x) {
+  for (uint32_t b = t0_; b < n_blocks;
+       b += st_) {
     const uint32_t e0 = succ_ptr[b], e1 = succ_ptr[b + 1];
     if (e0 > e1 || e1 > n_succ) {
       e |= kErrSucc;
@@ -196,13 +196,13 @@ __global__ void k_sort_pred(uint32_t n_blocks, const uint32_t *pred_ptr, uint32_
 // every instruction's LINE scope lies under its function's scope and under no
 // other CFG function (scope ids are range-checked here: this runs before the
 // other checks' verdict is known)
-__global__ void k_val_instr_scope(uint32_t n_instr, uint32_t n_scopes, const uint32_t *instr_scope,
+__device__ void val_instr_scope_part(uint32_t t0_, uint32_t st_, uint32_t n_instr, uint32_t n_scopes, const uint32_t *instr_scope,
                                   const uint32_t *block_of, const uint32_t *func_of_block,
                                   const uint32_t *func_scope, const uint32_t *parent,
                                   const uint8_t *kind, const uint8_t *flags, uint32_t *err) {
   uint32_t e = 0;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_instr;
-       i += gridDim.x * blockDim.x) {
+  for (uint32_t i = t0_; i < n_instr;
+       i += st_) {
     const uint32_t want = func_scope[func_of_block[block_of[i]]];
     uint32_t s = instr_scope[i];
     uint32_t guard = 0;
@@ -493,12 +493,12 @@ k_roots(uint32_t n_scopes, const uint32_t *parent, uint32_t *roots, uint32_t *n)
 // mx = (largest block count, largest edge count, sum over functions of the
 // squared block count as a 64-bit value in words 2-3)
 // (function bounds are clamped: this runs before the validation verdict)
-__global__ void k_max_func_blocks(uint32_t n_funcs, uint32_t n_blocks, const uint32_t *fbb,
+__device__ void max_func_blocks_part(uint32_t t0_, uint32_t st_, uint32_t n_funcs, uint32_t n_blocks, const uint32_t *fbb,
                                   const uint32_t *succ_ptr, uint32_t *mx) {
   uint32_t m = 0, e = 0;
   unsigned long long sq = 0;
-  for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < n_funcs;
-       f += gridDim.x * blockDim.x) {
+  for (uint32_t f = t0_; f < n_funcs;
+       f += st_) {
     const uint32_t a = min(fbb[f], n_blocks), b = min(fbb[f + 1], n_blocks);
     const uint32_t nb = b - a;
     m = max(m, nb);
@@ -508,6 +508,74 @@ __global__ void k_max_func_blocks(uint32_t n_funcs, uint32_t n_blocks, const uin
   atomicMax(&mx[0], m);
   atomicMax(&mx[1], e);
   if (sq) atomicAdd((unsigned long long *)(mx + 2), sq);
+}
+
+// The checks and maps run as two launches, each grid cut into sections of
+// workgroups, one per check (a section runs the check's grid-stride loop
+// over its own workgroups): first everything that needs only the inputs,
+// then what needs the block maps.
+struct ValArgs {
+  uint32_t n_instr, n_blocks, n_funcs, n_scopes, n_preds, n_defs, n_uses, n_succ, n_loc;
+  const uint8_t *op_class, *guard, *def_kind, *use_kind, *scope_kind, *scope_flags;
+  const uint32_t *def_ptr, *use_ptr, *def_loc, *use_loc, *instr_scope, *fbb, *func_scope,
+      *scope_parent, *block_begin, *succ_ptr, *succ;
+  uint32_t *block_of, *func_of_block, *pred_cnt, *err, *mx;
+};
+constexpr int kValSectionsA = 7, kValSectionsB = 2;
+struct ValSections {
+  uint32_t start[kValSectionsA + 1];   // cumulative workgroup offsets
+};
+
+__device__ __forceinline__ uint32_t val_section(const ValSections &sec, int n, uint32_t &t0,
+                                                uint32_t &st) {
+  uint32_t q = 0;
+  while ((int)q + 1 < n && blockIdx.x >= sec.start[q + 1]) ++q;
+  t0 = (blockIdx.x - sec.start[q]) * blockDim.x + threadIdx.x;
+  st = (sec.start[q + 1] - sec.start[q]) * blockDim.x;
+  return q;
+}
+
+__global__ void k_val_inputs(ValArgs a, ValSections sec) {
+  uint32_t t0, st;
+  switch (val_section(sec, kValSectionsA, t0, st)) {
+    case 0:
+      val_instr_part(t0, st, a.n_instr, a.n_preds, a.n_scopes, a.n_defs, a.n_uses, a.op_class,
+                     a.guard, a.def_ptr, a.use_ptr, a.def_loc, a.instr_scope, a.scope_kind, a.err);
+      break;
+    case 1:
+      val_sites_part(t0, st, a.n_defs, a.def_loc, a.def_kind, a.n_loc, (uint32_t)GPA_DEF_RBAR,
+                     kErrDef, a.err);
+      break;
+    case 2:
+      val_sites_part(t0, st, a.n_uses, a.use_loc, a.use_kind, a.n_loc, (uint32_t)GPA_USE_WAIT,
+                     kErrUse, a.err);
+      break;
+    case 3:
+      val_funcs_part(t0, st, a.n_funcs, a.n_scopes, a.fbb, a.func_scope, a.scope_kind,
+                     a.scope_flags, a.err);
+      break;
+    case 4:
+      val_scopes_part(t0, st, a.n_scopes, a.scope_parent, a.scope_kind, a.scope_flags, a.err);
+      break;
+    case 5:
+      blocks_part(t0, st, a.n_funcs, a.n_blocks, a.n_instr, a.fbb, a.block_begin, a.block_of,
+                  a.func_of_block, a.pred_cnt, a.err);
+      break;
+    default:
+      max_func_blocks_part(t0, st, a.n_funcs, a.n_blocks, a.fbb, a.succ_ptr, a.mx);
+      break;
+  }
+}
+
+__global__ void k_val_maps(ValArgs a, ValSections sec) {
+  uint32_t t0, st;
+  if (val_section(sec, kValSectionsB, t0, st) == 0)
+    val_succ_part(t0, st, a.n_blocks, a.succ_ptr, a.succ, a.n_succ, a.func_of_block, a.pred_cnt,
+                  a.err);
+  else
+    val_instr_scope_part(t0, st, a.n_instr, a.n_scopes, a.instr_scope, a.block_of,
+                         a.func_of_block, a.func_scope, a.scope_parent, a.scope_kind,
+                         a.scope_flags, a.err);
 }
 
 static void raise_validation(uint32_t err) {
@@ -572,33 +640,29 @@ void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar) {
   p.sync_words = vals;
   hipLaunchKernelGGL(k_val_ends, dim3(1), dim3(1), 0, s, n, nb, nf, p.def_ptr.p, p.use_ptr.p,
                      p.block_begin.p, p.succ_ptr.p, p.func_block_begin.p, vals);
-  hipLaunchKernelGGL(k_val_instr, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, n, p.n_preds, ns,
-                     p.n_defs, p.n_uses, p.op_class.p, p.guard.p, p.def_ptr.p, p.use_ptr.p, p.def_loc.p,
-                     p.instr_scope.p, p.scope_kind.p, err);
-  hipLaunchKernelGGL(k_val_sites, dim3(grid_for(p.n_defs, 256, 2048)), dim3(256), 0, s, p.n_defs,
-                     p.def_loc.p, p.def_kind.p, p.n_loc, (uint32_t)GPA_DEF_RBAR, kErrDef, err);
-  hipLaunchKernelGGL(k_val_sites, dim3(grid_for(p.n_uses, 256, 2048)), dim3(256), 0, s, p.n_uses,
-                     p.use_loc.p, p.use_kind.p, p.n_loc, (uint32_t)GPA_USE_WAIT, kErrUse, err);
-  hipLaunchKernelGGL(k_val_funcs, dim3(grid_for(nf, 256, 2048)), dim3(256), 0, s, nf, ns,
-                     p.func_block_begin.p, p.func_scope.p, p.scope_kind.p, p.scope_flags.p, err);
-  hipLaunchKernelGGL(k_val_scopes, dim3(grid_for(ns, 256, 2048)), dim3(256), 0, s, ns,
-                     p.scope_parent.p, p.scope_kind.p, p.scope_flags.p, err);
-  GPA_LAUNCH_CHECK();
   // function and block maps (binary searches, in bounds on any input)
   p.block_of.alloc(n);
   p.func_of_block.alloc(nb);
-  uint32_t *pcnt = ar.get<uint32_t>(nb + 1);   // predecessor counts, cleared by k_blocks
-  hipLaunchKernelGGL(k_blocks, dim3(grid_for((size_t)nb + n, 256, 4096)), dim3(256), 0, s, nf, nb,
-                     n, p.func_block_begin.p, p.block_begin.p, p.block_of.p, p.func_of_block.p,
-                     pcnt, err);
+  uint32_t *pcnt = ar.get<uint32_t>(nb + 1);   // predecessor counts, cleared by blocks_part
+  ValArgs va{n, nb, nf, ns, p.n_preds, p.n_defs, p.n_uses, p.n_succ, p.n_loc,
+             p.op_class.p, p.guard.p, p.def_kind.p, p.use_kind.p, p.scope_kind.p, p.scope_flags.p,
+             p.def_ptr.p, p.use_ptr.p, p.def_loc.p, p.use_loc.p, p.instr_scope.p,
+             p.func_block_begin.p, p.func_scope.p, p.scope_parent.p, p.block_begin.p,
+             p.succ_ptr.p, p.succ.p, p.block_of.p, p.func_of_block.p, pcnt, err, mx};
+  ValSections sa{}, sb{};
+  {
+    const unsigned g[kValSectionsA] = {grid_for(n, 256, 2048), grid_for(p.n_defs, 256, 2048),
+                                       grid_for(p.n_uses, 256, 2048), grid_for(nf, 256, 2048),
+                                       grid_for(ns, 256, 2048),
+                                       grid_for((size_t)nb + n, 256, 4096),
+                                       grid_for(nf, 256, 1024)};
+    for (int q = 0; q < kValSectionsA; ++q) sa.start[q + 1] = sa.start[q] + g[q];
+    const unsigned h2[kValSectionsB] = {grid_for(nb, 256, 2048), grid_for(n, 256, 2048)};
+    for (int q = 0; q < kValSectionsB; ++q) sb.start[q + 1] = sb.start[q] + h2[q];
+  }
+  hipLaunchKernelGGL(k_val_inputs, dim3(sa.start[kValSectionsA]), dim3(256), 0, s, va, sa);
   GPA_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_val_succ, dim3(grid_for(nb, 256, 2048)), dim3(256), 0, s, nb, p.succ_ptr.p,
-                     p.succ.p, p.n_succ, p.func_of_block.p, pcnt, err);
-  hipLaunchKernelGGL(k_val_instr_scope, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, n, ns,
-                     p.instr_scope.p, p.block_of.p, p.func_of_block.p, p.func_scope.p,
-                     p.scope_parent.p, p.scope_kind.p, p.scope_flags.p, err);
-  hipLaunchKernelGGL(k_max_func_blocks, dim3(grid_for(nf, 256, 1024)), dim3(256), 0, s, nf, nb,
-                     p.func_block_begin.p, p.succ_ptr.p, mx);
+  hipLaunchKernelGGL(k_val_maps, dim3(sb.start[kValSectionsB]), dim3(256), 0, s, va, sb);
   GPA_LAUNCH_CHECK();
   uint32_t h[6];
   GPA_HIP(hipMemcpyAsync(h, vals, sizeof(h), hipMemcpyDeviceToHost, s));
