@@ -272,8 +272,11 @@ def main():
                    "gpa_estimate: contributions, scope sums, speedups, top-k"),
         "rd_search": ("hbm", 30.0 * n_instr, "gpa_dataflow: per-use backward searches"),
         "dfs": ("alu", float(n_blocks + n_succ), "CFG depth-first order (k_dfs)"),
-        "dist": ("alu", float(relax),
-                 "walk tables (k_dist_tables): source blocks x sweep entries, shortest + longest"),
+        "dist": ("alu", float(relax) / 2,
+                 "shortest-walk tables (k_dist_tables, block order): source blocks x sweep entries"),
+        "dist_long": ("alu", float(relax) / 2,
+                      "longest G' walk tables (k_dist_tables, DFS order): source blocks x sweep "
+                      "entries"),
     }
     for name, (bound, amount, label) in work.items():
         t = phase_ms.get(name)

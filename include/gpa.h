@@ -211,14 +211,15 @@ gpa_status gpa_advice_topk(const gpa_advice *a, uint32_t k, uint32_t *opt, uint3
 
 /* Instrumentation (for benchmarks and profiling tools).  When enabled, the
  * library records a hipEvent pair around each phase on the stream the phase
- * runs on (the caller's, or for phases 5 and 6 the library's per-device side
- * stream) and accumulates the elapsed device time once the call has
- * synchronized.
+ * runs on (the caller's, or for phases 5, 6 and 12 one of the library's two
+ * per-device side streams) and accumulates the elapsed device time once the
+ * call has synchronized.
  * Phases: 0 sample aggregation, 1 blame, 2 whole program load, 3 advise,
- * 4 reaching definitions and edges, 5 walk tables of the CFGs, 6 depth-first
- * order of the CFGs, 7 the backward searches, 8 descriptor validation and
- * derived CFG structure, 9 definition and use sites and scope structure,
- * 10 def-use edges, 11 edge distances and target scopes.  gpa_timing_read copies
+ * 4 reaching definitions and edges, 5 shortest-walk tables of the CFGs,
+ * 6 depth-first order of the CFGs, 7 the backward searches, 8 descriptor
+ * validation and derived CFG structure, 9 definition and use sites and scope
+ * structure, 10 def-use edges, 11 edge distances and target scopes,
+ * 12 longest-walk tables of the CFGs.  gpa_timing_read copies
  * up to max_phases accumulated milliseconds and call counts (either pointer
  * may be NULL), optionally resets them, and returns the number of phases. */
 void gpa_timing_enable(int on);

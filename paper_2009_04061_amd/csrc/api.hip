@@ -135,16 +135,17 @@ PhaseTimer::~PhaseTimer() {
 // ------------------------------------------------------- side streams
 namespace {
 std::mutex g_smu;
-std::vector<hipStream_t> g_side;   // per device
+std::vector<hipStream_t> g_side;   // per device, two each
 }  // namespace
 
-hipStream_t side_stream() {
+hipStream_t side_stream(int which) {
   int dev = 0;
   GPA_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_smu);
-  if ((size_t)dev >= g_side.size()) g_side.resize((size_t)dev + 1, nullptr);
-  if (!g_side[dev]) GPA_HIP(hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking));
-  return g_side[dev];
+  const size_t k = 2 * (size_t)dev + (which ? 1 : 0);
+  if (k >= g_side.size()) g_side.resize(k + 1, nullptr);
+  if (!g_side[k]) GPA_HIP(hipStreamCreateWithFlags(&g_side[k], hipStreamNonBlocking));
+  return g_side[k];
 }
 
 // a synchronization-only event, destroyed with its scope
@@ -348,26 +349,38 @@ gpa_status gpa_load_program(const gpa_program_desc *d, void *stream, gpa_program
     up(p->scope_kind, d->scope_kind, p->n_scopes);
     up(p->scope_flags, d->scope_flags, p->n_scopes);
     up.flush();
-    const hipStream_t side = side_stream();
-    Event ev_struct, ev_order;   // outlive the arena, whose end waits for both streams
+    const hipStream_t side = side_stream(0), side2 = side_stream(1);
+    // outlive the arena, whose end waits for all three streams
+    Event ev_struct, ev_order, ev_short;
     Arena ar(s);
     ar.add_stream(side);
-    PhaseTimer t_load, t_rd, t_dist, t_dfs, t_search, t_val, t_sites, t_edges, t_targets;
+    ar.add_stream(side2);
+    PhaseTimer t_load, t_rd, t_dist, t_dist_long, t_dfs, t_search, t_val, t_sites, t_edges,
+        t_targets;
     t_load.begin(kPhaseLoad, s);
     t_val.begin(kPhaseValidate, s);
     validate_and_build_structure(*p, s, ar);
     t_val.end(s);
-    // the DFS order, the sweep streams and the walk tables need only the
-    // CFG: they run on the side stream while the sites are sorted and the
-    // reaching definitions and edges are built
+    DistTables tables;
+    prepare_dist_tables(*p, s, ar, tables);
+    // the walk tables need only the CFG: the longest G' tables follow the DFS
+    // order on one side stream, the shortest-walk tables (which any sweep
+    // order settles) run in block order on the other, while the main stream
+    // sorts the sites and builds the reaching definitions and edges
     GPA_HIP(hipEventRecord(ev_struct.e, s));
     GPA_HIP(hipStreamWaitEvent(side, ev_struct.e, 0));
-    SweepPlan plan;
-    DistTables tables;
+    GPA_HIP(hipStreamWaitEvent(side2, ev_struct.e, 0));
+    SweepPlan plan, plan_blocks;
+    uint32_t *block_pos = nullptr;
+    build_block_order_plan(*p, side2, ar, plan_blocks, block_pos);
+    t_dist.begin(kPhaseDist, side2);
+    build_dist_tables(*p, side2, plan_blocks, block_pos, tables, false);
+    t_dist.end(side2);
+    GPA_HIP(hipEventRecord(ev_short.e, side2));
     build_cfg_order(*p, side, ar, plan, t_dfs);
-    t_dist.begin(kPhaseDist, side);
-    build_dist_tables(*p, side, ar, plan, tables);
-    t_dist.end(side);
+    t_dist_long.begin(kPhaseDistLong, side);
+    build_dist_tables(*p, side, plan, p->rpo_pos.p, tables, true);
+    t_dist_long.end(side);
     GPA_HIP(hipEventRecord(ev_order.e, side));
     t_sites.begin(kPhaseSites, s);
     build_sites_and_scopes(*p, s, ar);
@@ -381,6 +394,7 @@ gpa_status gpa_load_program(const gpa_program_desc *d, void *stream, gpa_program
     t_targets.begin(kPhaseTargets, s);
     build_scope_targets(*p, s, ar);
     GPA_HIP(hipStreamWaitEvent(s, ev_order.e, 0));
+    GPA_HIP(hipStreamWaitEvent(s, ev_short.e, 0));
     build_distances(*p, s, ar, tables);
     t_targets.end(s);
     t_load.end(s);
@@ -398,6 +412,7 @@ gpa_status gpa_load_program(const gpa_program_desc *d, void *stream, gpa_program
     t_targets.collect();
     t_rd.collect();
     t_dist.collect();
+    t_dist_long.collect();
     t_dfs.collect();
     t_search.collect();
   });

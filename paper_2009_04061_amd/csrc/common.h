@@ -208,7 +208,7 @@ void build_edges(gpa_program &p, hipStream_t s, Arena &ar);
 // dist.hip
 // Per device, a second stream (default priority, non-blocking) for load work
 // that only needs the CFG and can overlap the reaching definitions.
-hipStream_t side_stream();
+hipStream_t side_stream(int which = 0);   // per device: 0 and 1
 
 // The G' sweep streams the distance kernel reads (built with the DFS order).
 struct SweepPlan {
@@ -217,6 +217,9 @@ struct SweepPlan {
 };
 void build_cfg_order(gpa_program &p, hipStream_t s, Arena &ar, SweepPlan &plan,
                      PhaseTimer &t_dfs);
+// the sweep plan in block order (position = block index within its function)
+void build_block_order_plan(gpa_program &p, hipStream_t s, Arena &ar, SweepPlan &plan,
+                            uint32_t *&pos);
 // Block-to-block walk tables of every function (shortest and longest G'
 // walks from each block to each block of its function), from the CFG alone.
 // per-opcode-class latency bounds, passed to a kernel by value
@@ -229,8 +232,12 @@ struct DistTables {
   uint32_t *sp = nullptr;    // shortest walk lengths, kInf-saturated
   uint32_t *lp = nullptr;    // longest G' walk lengths + 1, 0 = none
 };
-void build_dist_tables(gpa_program &p, hipStream_t s, Arena &ar, const SweepPlan &plan,
-                       DistTables &t);
+// table offsets and storage, before either table is built
+void prepare_dist_tables(gpa_program &p, hipStream_t s, Arena &ar, DistTables &t);
+// the shortest-walk tables (any sweep order: pos and plan in block order) or
+// the longest G' tables (pos = reverse postorder of the DFS, plan from it)
+void build_dist_tables(gpa_program &p, hipStream_t s, const SweepPlan &plan, const uint32_t *pos,
+                       const DistTables &t, bool longest);
 // per edge: dmin, dmax and the latency rule's flag from the tables
 void build_distances(gpa_program &p, hipStream_t s, Arena &ar, const DistTables &t);
 constexpr uint32_t kSmallSeg = 64;   // longest segment one thread sums alone
@@ -247,7 +254,8 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint3
 // the API call that launched it has synchronized its stream.
 enum Phase {
   kPhaseHist = 0, kPhaseBlame, kPhaseLoad, kPhaseAdvise, kPhaseRd, kPhaseDist, kPhaseDfs,
-  kPhaseRdSearch, kPhaseValidate, kPhaseSites, kPhaseEdges, kPhaseTargets, kNumPhases
+  kPhaseRdSearch, kPhaseValidate, kPhaseSites, kPhaseEdges, kPhaseTargets, kPhaseDistLong,
+  kNumPhases
 };
 struct PhaseTimer {
   hipEvent_t a = nullptr, b = nullptr;

@@ -217,13 +217,14 @@ k_dfs(const uint32_t *fbb, const uint32_t *succ_ptr, const uint32_t *succ,
 }
 
 // ------------------------------------------------------------ distances
-// Sweep streams.  For every block w of a function, in the G' order, one entry
+// Sweep streams.  For every block w of a function, in a sweep order (the
+// DFS reverse postorder, whose forward edges are G'; or block order), one entry
 // per predecessor edge v -> w (one entry with v = none for a block without
 // predecessors): v and w as function-local ids, flags for the first and last
 // entry of w and for a retreating edge, and the size of w beside it.  An edge
-// v -> w is retreating exactly when w does not come after v in the order
-// (reverse postorder of the depth-first search).  The retreating edges are
-// also listed on their own, for the convergence test of shortest walks.
+// v -> w is retreating exactly when w does not come after v in the order.
+// The retreating edges are also listed on their own, for the convergence
+// test of shortest walks.
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 constexpr uint32_t kLocalNone = 0x1FFFu;   // local block ids are < 4096
 constexpr uint32_t kEntFirst = 1u << 26, kEntLast = 1u << 27, kEntRet = 1u << 28;
@@ -360,8 +361,9 @@ __device__ void dist_sweep(uint32_t *D, uint32_t Lc, uint32_t col, uint32_t s, u
 }
 
 // Walk tables of a group of L consecutive blocks, one lane per source block:
-// for every block w of the source's function, the shortest walk (y = 0) or
-// the longest G' walk (y = 1) from the source to w, in the sweep table's
+// for every block w of the source's function, the shortest walk
+// (longest_tab = 0, any sweep order) or the longest G' walk (longest_tab = 1,
+// the DFS reverse postorder) from the source to w, in the sweep table's
 // terms (including |w|).  Shortest walks repeat the sweep until no
 // retreating edge can shorten a walk (the sweep order settles every other
 // edge); longest G' walks take one sweep.  The workgroup is one wave; the
@@ -371,10 +373,10 @@ k_dist_tables(uint32_t n_blocks, uint32_t n_funcs, uint32_t L, const uint32_t *f
               const uint32_t *func_of_block, const uint32_t *ent_ptr, const uint32_t *ent,
               const uint32_t *ent_w, const uint32_t *ret_ptr, const uint32_t *rent,
               const uint32_t *rent_w, const uint32_t *rent_e, const uint32_t *rpo_pos,
-              const uint32_t *tab_off, uint32_t *t_sp, uint32_t *t_lp) {
+              const uint32_t *tab_off, uint32_t *t_sp, uint32_t *t_lp, uint32_t longest_tab) {
   extern __shared__ uint32_t D[];   // [blocks of the function + 1][L + 1]
   const unsigned lane = threadIdx.x;
-  const bool longest = blockIdx.y != 0;
+  const bool longest = longest_tab != 0;
   const uint32_t c0 = blockIdx.x * L, c1 = min(c0 + L, n_blocks);
   if (c0 >= n_blocks) return;
   const uint32_t Lc = L + 1;
@@ -387,8 +389,8 @@ k_dist_tables(uint32_t n_blocks, uint32_t n_funcs, uint32_t L, const uint32_t *f
     const bool mine = lane < L && sb >= g0 && sb < g1;
     const uint32_t s = mine ? sb - b0 : 0xFFFFu;
     const uint32_t e_end = ent_ptr[b1];
-    // Nothing before the earliest source (in G' order) is reached without a
-    // retreating edge: the sweeps start there, a later shortest-walk sweep
+    // Nothing before the earliest source (in the sweep order) is reached
+    // without a retreating edge: the sweeps start there, a later shortest-walk sweep
     // at the earliest header whose retreating edge improved a walk.
     uint32_t pmin = mine ? rpo_pos[sb] : 0xFFFFFFFFu;
     for (int d = 32; d > 0; d >>= 1) pmin = min(pmin, (uint32_t)__shfl_xor((int)pmin, d, 64));
@@ -484,6 +486,33 @@ __global__ void k_func_sq(uint32_t n_funcs, const uint32_t *fbb, uint32_t *sq) {
   }
 }
 
+// the sweep streams of every function in the order given by pos (a block's
+// position within its function)
+static void build_sweep_plan(gpa_program &p, hipStream_t s, Arena &ar, const uint32_t *pos,
+                             SweepPlan &plan) {
+  const uint32_t nb = p.n_blocks;
+  uint32_t *cnt = ar.get<uint32_t>((size_t)nb + 1), *rcnt = ar.get<uint32_t>((size_t)nb + 1);
+  plan.ent_ptr = ar.get<uint32_t>((size_t)nb + 1);
+  plan.ret_ptr = ar.get<uint32_t>((size_t)nb + 1);
+  const size_t n_ent = (size_t)p.n_succ + nb;   // upper bound
+  plan.ent = ar.get<uint32_t>(n_ent);
+  plan.ent_w = ar.get<uint32_t>(n_ent);
+  plan.rent = ar.get<uint32_t>(p.n_succ ? p.n_succ : 1);
+  plan.rent_w = ar.get<uint32_t>(p.n_succ ? p.n_succ : 1);
+  plan.rent_e = ar.get<uint32_t>(p.n_succ ? p.n_succ : 1);
+  const uint32_t g = grid_for(nb, 256, 4096);
+  hipLaunchKernelGGL(k_sweep_count, dim3(g), dim3(256), 0, s, nb, p.func_block_begin.p,
+                     p.func_of_block.p, p.pred_ptr.p, p.pred.p, pos, cnt, rcnt);
+  GPA_LAUNCH_CHECK();
+  exclusive_scan_u32(cnt, plan.ent_ptr, (size_t)nb + 1, s, ar);
+  exclusive_scan_u32(rcnt, plan.ret_ptr, (size_t)nb + 1, s, ar);
+  hipLaunchKernelGGL(k_sweep_fill, dim3(g), dim3(256), 0, s, nb, p.func_block_begin.p,
+                     p.func_of_block.p, p.block_begin.p, p.pred_ptr.p, p.pred.p, pos,
+                     plan.ent_ptr, plan.ret_ptr, plan.ent, plan.ent_w, plan.rent, plan.rent_w,
+                     plan.rent_e);
+  GPA_LAUNCH_CHECK();
+}
+
 void build_cfg_order(gpa_program &p, hipStream_t s, Arena &ar, SweepPlan &plan,
                      PhaseTimer &t_dfs) {
   const uint32_t nf = p.n_funcs, nb = p.n_blocks;
@@ -503,33 +532,28 @@ void build_cfg_order(gpa_program &p, hipStream_t s, Arena &ar, SweepPlan &plan,
                      p.succ.p, p.pred_ptr.p, p.pred.p, p.retreat.p, p.rpo_pos.p, p.rpo_order.p);
   GPA_LAUNCH_CHECK();
   t_dfs.end(s);
-  // sweep streams
-  uint32_t *cnt = ar.get<uint32_t>((size_t)nb + 1), *rcnt = ar.get<uint32_t>((size_t)nb + 1);
-  plan.ent_ptr = ar.get<uint32_t>((size_t)nb + 1);
-  plan.ret_ptr = ar.get<uint32_t>((size_t)nb + 1);
-  const size_t n_ent = (size_t)p.n_succ + nb;   // upper bound
-  plan.ent = ar.get<uint32_t>(n_ent);
-  plan.ent_w = ar.get<uint32_t>(n_ent);
-  plan.rent = ar.get<uint32_t>(p.n_succ ? p.n_succ : 1);
-  plan.rent_w = ar.get<uint32_t>(p.n_succ ? p.n_succ : 1);
-  plan.rent_e = ar.get<uint32_t>(p.n_succ ? p.n_succ : 1);
-  const uint32_t g = grid_for(nb, 256, 4096);
-  hipLaunchKernelGGL(k_sweep_count, dim3(g), dim3(256), 0, s, nb, p.func_block_begin.p,
-                     p.func_of_block.p, p.pred_ptr.p, p.pred.p, p.rpo_pos.p, cnt, rcnt);
-  GPA_LAUNCH_CHECK();
-  exclusive_scan_u32(cnt, plan.ent_ptr, (size_t)nb + 1, s, ar);
-  exclusive_scan_u32(rcnt, plan.ret_ptr, (size_t)nb + 1, s, ar);
-  hipLaunchKernelGGL(k_sweep_fill, dim3(g), dim3(256), 0, s, nb, p.func_block_begin.p,
-                     p.func_of_block.p, p.block_begin.p, p.pred_ptr.p, p.pred.p, p.rpo_pos.p,
-                     plan.ent_ptr, plan.ret_ptr, plan.ent, plan.ent_w, plan.rent, plan.rent_w,
-                     plan.rent_e);
-  GPA_LAUNCH_CHECK();
+  build_sweep_plan(p, s, ar, p.rpo_pos.p, plan);
 }
 
-void build_dist_tables(gpa_program &p, hipStream_t s, Arena &ar, const SweepPlan &plan,
-                       DistTables &t) {
-  const uint32_t nf = p.n_funcs, nb = p.n_blocks;
-  const uint32_t max_nb = p.max_func_blocks;
+// position of each block within its function in block order
+__global__ void k_block_pos(uint32_t n_blocks, const uint32_t *fbb, const uint32_t *func_of_block,
+                            uint32_t *pos) {
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < n_blocks;
+       b += gridDim.x * blockDim.x)
+    pos[b] = b - fbb[func_of_block[b]];
+}
+
+void build_block_order_plan(gpa_program &p, hipStream_t s, Arena &ar, SweepPlan &plan,
+                            uint32_t *&pos) {
+  pos = ar.get<uint32_t>(p.n_blocks);
+  hipLaunchKernelGGL(k_block_pos, dim3(grid_for(p.n_blocks, 256, 4096)), dim3(256), 0, s,
+                     p.n_blocks, p.func_block_begin.p, p.func_of_block.p, pos);
+  GPA_LAUNCH_CHECK();
+  build_sweep_plan(p, s, ar, pos, plan);
+}
+
+void prepare_dist_tables(gpa_program &p, hipStream_t s, Arena &ar, DistTables &t) {
+  const uint32_t nf = p.n_funcs;
   if (p.dist_entries >= (1ull << 32))
     fail(GPA_E_UNSUPPORTED, "walk tables of %llu entries; the sum over functions of the squared "
          "block count must stay below 2^32", (unsigned long long)p.dist_entries);
@@ -541,16 +565,22 @@ void build_dist_tables(gpa_program &p, hipStream_t s, Arena &ar, const SweepPlan
                      p.func_block_begin.p, sq);
   GPA_LAUNCH_CHECK();
   exclusive_scan_u32(sq, t.off, nf, s, ar);
+}
+
+void build_dist_tables(gpa_program &p, hipStream_t s, const SweepPlan &plan, const uint32_t *pos,
+                       const DistTables &t, bool longest) {
+  const uint32_t nf = p.n_funcs, nb = p.n_blocks;
+  const uint32_t max_nb = p.max_func_blocks;
   // one table of (blocks + 1) x (L + 1) words per workgroup
   const uint32_t L = std::max<uint32_t>(
       1u, std::min<uint32_t>(63u, kDistLds / (4u * (max_nb + 1)) - 1u));
   const size_t lds = (size_t)4 * (L + 1) * (max_nb + 1);
   GPA_HIP(hipFuncSetAttribute((const void *)k_dist_tables,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_dist_tables, dim3((nb + L - 1) / L, 2), dim3(64), lds, s, nb, nf, L,
+  hipLaunchKernelGGL(k_dist_tables, dim3((nb + L - 1) / L), dim3(64), lds, s, nb, nf, L,
                      p.func_block_begin.p, p.func_of_block.p, plan.ent_ptr, plan.ent, plan.ent_w,
-                     plan.ret_ptr, plan.rent, plan.rent_w, plan.rent_e, p.rpo_pos.p, t.off, t.sp,
-                     t.lp);
+                     plan.ret_ptr, plan.rent, plan.rent_w, plan.rent_e, pos, t.off, t.sp, t.lp,
+                     longest ? 1u : 0u);
   GPA_LAUNCH_CHECK();
 }
 

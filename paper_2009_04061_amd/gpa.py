@@ -63,7 +63,7 @@ EXPORTS = ["gpa_load_program", "gpa_program_free", "gpa_program_get_info", "gpa_
            "gpa_advice_get", "gpa_advice_topk", "gpa_last_error", "gpa_timing_enable",
            "gpa_timing_read"]
 PHASES = ["hist", "blame", "load", "advise", "rd_edges", "dist", "dfs", "rd_search",
-          "validate", "sites", "edges", "targets"]
+          "validate", "sites", "edges", "targets", "dist_long"]
 
 _lib = None
 
