@@ -299,12 +299,13 @@ __global__ void k_sweep_fill(uint32_t n_blocks, const uint32_t *fbb,
 // forwarded (a block is written once per sweep, so at most one slot matches).
 constexpr int kPD = 4;
 
-template <bool kLongest>
-__device__ void dist_sweep(uint32_t *D, uint32_t Lc, uint32_t col, uint32_t s, uint32_t spare_row,
+template <bool kLongest, typename T>
+__device__ void dist_sweep(T *D, uint32_t Lc, uint32_t col, uint32_t s, uint32_t spare_row,
                            const uint32_t *ent, const uint32_t *ent_w, uint32_t e_begin,
                            uint32_t e_end) {
   const unsigned lane = threadIdx.x;
-  const uint32_t none = kLongest ? 0u : kInf;     // "no walk"
+  constexpr uint32_t kTInf = (uint32_t)(T)~0u;   // the entry type's "no walk" for shortest
+  const uint32_t none = kLongest ? 0u : kTInf;
   const uint32_t at_s = kLongest ? 1u : 0u;       // a walk that starts at s
   uint32_t rw[kPD], re[kPD];
 #pragma unroll
@@ -347,10 +348,11 @@ __device__ void dist_sweep(uint32_t *D, uint32_t Lc, uint32_t col, uint32_t s, u
         best = use ? nb_ : best;
         uint32_t e;
         if (kLongest) e = best ? best + bw : 0u;
-        else e = __builtin_elementwise_add_sat(best, bw);
+        else if (sizeof(T) == 4) e = __builtin_elementwise_add_sat(best, bw);
+        else e = min(best + bw, kTInf);   // walks stay below kTInf (checked on the host)
         const bool last = (pk & kEntLast) != 0;
         const uint32_t w = last ? (pk >> 13) & kLocalNone : spare_row;
-        D[w * Lc + col] = e;
+        D[w * Lc + col] = (T)e;
         rw[j % kPD] = last ? w : kLocalNone;
         re[j % kPD] = e;
       }
@@ -368,13 +370,16 @@ __device__ void dist_sweep(uint32_t *D, uint32_t Lc, uint32_t col, uint32_t s, u
 // retreating edge can shorten a walk (the sweep order settles every other
 // edge); longest G' walks take one sweep.  The workgroup is one wave; the
 // table is copied out to the source's row of the function's table.
+template <typename T>
 __global__ void __launch_bounds__(64)
 k_dist_tables(uint32_t n_blocks, uint32_t n_funcs, uint32_t L, const uint32_t *fbb,
               const uint32_t *func_of_block, const uint32_t *ent_ptr, const uint32_t *ent,
               const uint32_t *ent_w, const uint32_t *ret_ptr, const uint32_t *rent,
               const uint32_t *rent_w, const uint32_t *rent_e, const uint32_t *rpo_pos,
               const uint32_t *tab_off, uint32_t *t_sp, uint32_t *t_lp, uint32_t longest_tab) {
-  extern __shared__ uint32_t D[];   // [blocks of the function + 1][L + 1]
+  extern __shared__ uint4 dist_lds[];
+  T *D = (T *)dist_lds;             // [blocks of the function + 1][L + 1]
+  constexpr uint32_t kTInf = (uint32_t)(T)~0u;
   const unsigned lane = threadIdx.x;
   const bool longest = longest_tab != 0;
   const uint32_t c0 = blockIdx.x * L, c1 = min(c0 + L, n_blocks);
@@ -396,17 +401,17 @@ k_dist_tables(uint32_t n_blocks, uint32_t n_funcs, uint32_t L, const uint32_t *f
     for (int d = 32; d > 0; d >>= 1) pmin = min(pmin, (uint32_t)__shfl_xor((int)pmin, d, 64));
     const uint32_t e_src_start = ent_ptr[b0 + pmin];
     __syncthreads();
-    const uint32_t none = longest ? 0u : kInf;
+    const T none = longest ? (T)0 : (T)kTInf;
     for (uint32_t k = lane; k < (nb + 1) * Lc; k += 64) D[k] = none;
     __syncthreads();
     if (longest) {
       // every block is written before any later block reads it
-      dist_sweep<true>(D, Lc, col, s, nb, ent, ent_w, e_src_start, e_end);
+      dist_sweep<true, T>(D, Lc, col, s, nb, ent, ent_w, e_src_start, e_end);
     } else {
       const uint32_t r_begin = ret_ptr[b0], r_end = ret_ptr[b1];
       uint32_t start = e_src_start;
       for (uint32_t sweep = 0; sweep <= nb; ++sweep) {
-        dist_sweep<false>(D, Lc, col, s, nb, ent, ent_w, start, e_end);
+        dist_sweep<false, T>(D, Lc, col, s, nb, ent, ent_w, start, e_end);
         uint32_t restart = 0xFFFFFFFFu;
         for (uint32_t base = r_begin; base < r_end; base += 64) {
           const uint32_t idx = base + lane;
@@ -417,9 +422,9 @@ k_dist_tables(uint32_t n_blocks, uint32_t n_funcs, uint32_t L, const uint32_t *f
           for (uint32_t i = 0; i < cnt; ++i) {
             const uint32_t pk = __builtin_amdgcn_readlane(rp, i);
             const uint32_t u = pk & kLocalNone, h = (pk >> 13) & kLocalNone;
-            const uint32_t cu = (u == s) ? 0u : D[u * Lc + col];
+            const uint32_t cu = (u == s) ? 0u : (uint32_t)D[u * Lc + col];
             const uint32_t bh = __builtin_amdgcn_readlane(rw, i);
-            if (mine && cu != kInf && cu + bh < D[h * Lc + col])
+            if (mine && cu != kTInf && cu + bh < (uint32_t)D[h * Lc + col])
               restart = min(restart, __builtin_amdgcn_readlane(re, i));
           }
         }
@@ -431,11 +436,12 @@ k_dist_tables(uint32_t n_blocks, uint32_t n_funcs, uint32_t L, const uint32_t *f
     }
     __syncthreads();
     // rows (source - b0) of the function's table, nb entries each
-    uint32_t *T = (longest ? t_lp : t_sp) + tab_off[f] + (size_t)(g0 - b0) * nb;
+    uint32_t *Tab = (longest ? t_lp : t_sp) + tab_off[f] + (size_t)(g0 - b0) * nb;
     const uint32_t l0 = g0 - c0, n_out = (g1 - g0) * nb;
     for (uint32_t k = lane; k < n_out; k += 64) {
       const uint32_t r = k / nb, w = k - r * nb;
-      T[k] = D[w * Lc + l0 + r];
+      const uint32_t v = D[w * Lc + l0 + r];
+      Tab[k] = (!longest && v == kTInf) ? kInf : v;
     }
   }
 }
@@ -571,16 +577,28 @@ void build_dist_tables(gpa_program &p, hipStream_t s, const SweepPlan &plan, con
                        const DistTables &t, bool longest) {
   const uint32_t nf = p.n_funcs, nb = p.n_blocks;
   const uint32_t max_nb = p.max_func_blocks;
-  // one table of (blocks + 1) x (L + 1) words per workgroup
+  // one table of (blocks + 1) x (L + 1) entries per workgroup, with L from
+  // the u32 layout; 16-bit entries (half the LDS, so that more of the main
+  // stream's workgroups fit beside) when every walk is shorter than 65,534
+  // instructions: a walk of distinct blocks, or its length plus one, is at
+  // most the instruction count plus one
   const uint32_t L = std::max<uint32_t>(
       1u, std::min<uint32_t>(63u, kDistLds / (4u * (max_nb + 1)) - 1u));
-  const size_t lds = (size_t)4 * (L + 1) * (max_nb + 1);
-  GPA_HIP(hipFuncSetAttribute((const void *)k_dist_tables,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_dist_tables, dim3((nb + L - 1) / L), dim3(64), lds, s, nb, nf, L,
-                     p.func_block_begin.p, p.func_of_block.p, plan.ent_ptr, plan.ent, plan.ent_w,
-                     plan.ret_ptr, plan.rent, plan.rent_w, plan.rent_e, pos, t.off, t.sp, t.lp,
-                     longest ? 1u : 0u);
+  const bool narrow = p.n_instr < 0xFFFEu;
+  const size_t lds = (size_t)(narrow ? 2 : 4) * (L + 1) * (max_nb + 1);
+  const void *kern = narrow ? (const void *)k_dist_tables<uint16_t>
+                            : (const void *)k_dist_tables<uint32_t>;
+  GPA_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  if (narrow)
+    hipLaunchKernelGGL(k_dist_tables<uint16_t>, dim3((nb + L - 1) / L), dim3(64), lds, s, nb, nf,
+                       L, p.func_block_begin.p, p.func_of_block.p, plan.ent_ptr, plan.ent,
+                       plan.ent_w, plan.ret_ptr, plan.rent, plan.rent_w, plan.rent_e, pos, t.off,
+                       t.sp, t.lp, longest ? 1u : 0u);
+  else
+    hipLaunchKernelGGL(k_dist_tables<uint32_t>, dim3((nb + L - 1) / L), dim3(64), lds, s, nb, nf,
+                       L, p.func_block_begin.p, p.func_of_block.p, plan.ent_ptr, plan.ent,
+                       plan.ent_w, plan.ret_ptr, plan.rent, plan.rent_w, plan.rent_e, pos, t.off,
+                       t.sp, t.lp, longest ? 1u : 0u);
   GPA_LAUNCH_CHECK();
 }
 
