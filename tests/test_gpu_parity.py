@@ -144,6 +144,18 @@ def test_large_workload_full_parity():
     assert g["info"]["n_edges"] > 100_000
 
 
+def test_program_past_16_bit_walks():
+    """70,000 instructions in one function: walks can pass 65,533
+    instructions, so the walk tables keep 32-bit entries."""
+    prog = S.gen_program(seed=31, functions=[dict(n_instr=70_000, n_blocks=900, n_loops=40,
+                                                  max_depth=4, kind="kernel")],
+                         n_regs=64, n_preds=4, n_bars=8)
+    n = len(prog["op_class"])
+    assert n >= 0xFFFE
+    rec = S.gen_samples(300_000, n, 1.1, S.stall_mix_small(), seed=31)
+    _both(prog, rec)
+
+
 def test_function_at_block_limit_and_beyond():
     from paper_2009_04061_amd import gpa
     ok = S.gen_program(seed=8, functions=[dict(n_instr=4096 * 2, n_blocks=4096, n_loops=20,
