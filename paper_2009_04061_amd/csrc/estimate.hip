@@ -62,15 +62,28 @@ __global__ void k_instr_contrib(uint32_t n_instr, uint32_t nbl, uint32_t blamabl
 
 // latency samples of global-memory and execution dependency stalls carried
 // by an edge (Loop Unrolling and Code Reordering)
-__global__ void k_edge_contrib(uint64_t n_edges, uint32_t nbl, int s_mem, int s_exec,
-                               const uint32_t *e_src, const uint8_t *op_class, const double *share,
-                               double *ev) {
-  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < n_edges;
-       e += (uint64_t)gridDim.x * blockDim.x) {
-    double v = 0.0;
-    if (s_mem >= 0 && op_class[e_src[e]] == GPA_OP_GLOBAL_LOAD) v += share[(e * nbl + s_mem) * 2 + 1];
-    if (s_exec >= 0) v += share[(e * nbl + s_exec) * 2 + 1];
-    ev[e] = v;
+__device__ __forceinline__ double edge_contrib(uint64_t e, uint32_t nbl, int s_mem, int s_exec,
+                                               const uint32_t *e_src, const uint8_t *op_class,
+                                               const double *share) {
+  double v = 0.0;
+  if (s_mem >= 0 && op_class[e_src[e]] == GPA_OP_GLOBAL_LOAD) v += share[(e * nbl + s_mem) * 2 + 1];
+  if (s_exec >= 0) v += share[(e * nbl + s_exec) * 2 + 1];
+  return v;
+}
+
+// the edge contributions straight into the common-loop and common-scope
+// groupings' orders (edges without a common loop are left out of the first:
+// its size is *n_icl)
+__global__ void k_edge_gathered(uint64_t n_edges, uint32_t nbl, int s_mem, int s_exec,
+                                const uint32_t *e_src, const uint8_t *op_class,
+                                const double *share, const uint32_t *n_icl,
+                                const uint32_t *icl_perm, const uint32_t *lca_perm, double *ev_icl,
+                                double *ev_lca) {
+  const uint64_t ni = min((uint64_t)*n_icl, n_edges);
+  for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n_edges;
+       k += (uint64_t)gridDim.x * blockDim.x) {
+    ev_lca[k] = edge_contrib(lca_perm[k], nbl, s_mem, s_exec, e_src, op_class, share);
+    if (k < ni) ev_icl[k] = edge_contrib(icl_perm[k], nbl, s_mem, s_exec, e_src, op_class, share);
   }
 }
 
@@ -95,23 +108,36 @@ __global__ void k_gather(size_t n, const uint32_t *n_dev, const uint32_t *perm, 
 // longer ones (listed once at load, with their chunk counts) in chunks of
 // kSegChunk by one workgroup each, every thread owning a fixed stride and the
 // reduction a fixed shape, and the chunks then in order.  Either way the
-// result does not depend on scheduling.
+// result does not depend on scheduling.  One launch serves up to two
+// independent sets of segments (grid row y = set).
+struct SegSet {
+  const uint32_t *ptr, *end;          // segment bounds (ptr mode when ptr)
+  const uint32_t *big_list, *big_n;   // the long segments
+  const uint32_t *chunk_start;        // their first chunk
+  uint32_t n_chunks;
+  const double *data;
+  double *out, *partial;
+};
+struct SegSets {
+  SegSet set[2];
+};
+
 template <int W>
-__global__ void k_seg_small(uint32_t n_seg, const uint32_t *ptr, const uint32_t *end,
-                            const double *data, double *out) {
+__global__ void k_seg_small(uint32_t n_seg, SegSets sets) {
+  const SegSet &S = sets.set[blockIdx.y];
   for (uint32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < n_seg;
        l += gridDim.x * blockDim.x) {
-    const uint32_t a = ptr ? ptr[l] : l;
-    const uint32_t b = ptr ? ptr[l + 1] : end[l];
+    const uint32_t a = S.ptr ? S.ptr[l] : l;
+    const uint32_t b = S.ptr ? S.ptr[l + 1] : S.end[l];
     if (b - a > kSmallSeg) continue;
     double v[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) v[q] = 0.0;
     for (uint32_t i = a; i < b; ++i)
 #pragma unroll
-      for (int q = 0; q < W; ++q) v[q] += data[(size_t)i * W + q];
+      for (int q = 0; q < W; ++q) v[q] += S.data[(size_t)i * W + q];
 #pragma unroll
-    for (int q = 0; q < W; ++q) out[(size_t)l * W + q] = v[q];
+    for (int q = 0; q < W; ++q) S.out[(size_t)l * W + q] = v[q];
   }
 }
 
@@ -120,16 +146,16 @@ __global__ void k_seg_small(uint32_t n_seg, const uint32_t *ptr, const uint32_t 
 // waves' sums in a fixed shape), then per segment its chunks in order.
 template <int W>
 __global__ void __launch_bounds__(256)
-k_seg_chunks(const uint32_t *list, const uint32_t *n_list, const uint32_t *chunk_start,
-             uint32_t n_chunks, const uint32_t *ptr, const uint32_t *end, const double *data,
-             double *partial) {
+k_seg_chunks(SegSets sets) {
   __shared__ double red[4][W];
-  const uint32_t nl = *n_list;
-  for (uint32_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
-    const uint32_t j = upper_index_u32(chunk_start, 0, nl, c);
-    const uint32_t l = list[j];
-    const uint32_t a0 = ptr ? ptr[l] : l, b0 = ptr ? ptr[l + 1] : end[l];
-    const uint32_t a = a0 + (c - chunk_start[j]) * kSegChunk, b = min(a + kSegChunk, b0);
+  const SegSet &S = sets.set[blockIdx.y];
+  const uint32_t nl = *S.big_n;
+  for (uint32_t c = blockIdx.x; c < S.n_chunks; c += gridDim.x) {
+    const uint32_t j = upper_index_u32(S.chunk_start, 0, nl, c);
+    const uint32_t l = S.big_list[j];
+    const uint32_t a0 = S.ptr ? S.ptr[l] : l, b0 = S.ptr ? S.ptr[l + 1] : S.end[l];
+    const uint32_t a = a0 + (c - S.chunk_start[j]) * kSegChunk, b = min(a + kSegChunk, b0);
+    const double *data = S.data;
     double v[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) v[q] = 0.0;
@@ -158,44 +184,46 @@ k_seg_chunks(const uint32_t *list, const uint32_t *n_list, const uint32_t *chunk
       for (int q = 0; q < W; ++q) red[w][q] = v[q];
     __syncthreads();
     if (threadIdx.x < (unsigned)W)
-      partial[(size_t)c * W + threadIdx.x] =
+      S.partial[(size_t)c * W + threadIdx.x] =
           (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
     __syncthreads();
   }
 }
 
 template <int W>
-__global__ void k_seg_combine(const uint32_t *list, const uint32_t *n_list,
-                              const uint32_t *chunk_start, uint32_t n_chunks,
-                              const double *partial, double *out) {
-  const uint32_t nl = *n_list;
+__global__ void k_seg_combine(SegSets sets) {
+  const SegSet &S = sets.set[blockIdx.y];
+  const uint32_t nl = *S.big_n;
   for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nl; j += gridDim.x * blockDim.x) {
-    const uint32_t c0 = chunk_start[j], c1 = (j + 1 < nl) ? chunk_start[j + 1] : n_chunks;
+    const uint32_t c0 = S.chunk_start[j], c1 = (j + 1 < nl) ? S.chunk_start[j + 1] : S.n_chunks;
     double v[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) v[q] = 0.0;
     for (uint32_t c = c0; c < c1; ++c)
 #pragma unroll
-      for (int q = 0; q < W; ++q) v[q] += partial[(size_t)c * W + q];
-    const uint32_t l = list[j];
+      for (int q = 0; q < W; ++q) v[q] += S.partial[(size_t)c * W + q];
+    const uint32_t l = S.big_list[j];
 #pragma unroll
-    for (int q = 0; q < W; ++q) out[(size_t)l * W + q] = v[q];
+    for (int q = 0; q < W; ++q) S.out[(size_t)l * W + q] = v[q];
   }
 }
 
+// the sums of n_sets (1 or 2) sets of n_seg segments each
 template <int W>
-void seg_sum(uint32_t n_seg, const uint32_t *ptr, const uint32_t *end, const uint32_t *big_list,
-             const uint32_t *big_n, const uint32_t *chunk_start, uint64_t n_chunks,
-             const double *data, double *out, hipStream_t s, Arena &ar) {
-  hipLaunchKernelGGL(k_seg_small<W>, dim3(grid_for(n_seg, 256, 8192)), dim3(256), 0, s, n_seg, ptr,
-                     end, data, out);
-  if (n_chunks) {
-    double *partial = ar.get<double>((size_t)n_chunks * W);
-    hipLaunchKernelGGL(k_seg_chunks<W>, dim3((unsigned)std::min<uint64_t>(n_chunks, 4096)),
-                       dim3(256), 0, s, big_list, big_n, chunk_start, (uint32_t)n_chunks, ptr, end,
-                       data, partial);
-    hipLaunchKernelGGL(k_seg_combine<W>, dim3(grid_for(n_seg, 256, 1024)), dim3(256), 0, s,
-                       big_list, big_n, chunk_start, (uint32_t)n_chunks, partial, out);
+void seg_sum(uint32_t n_seg, SegSets sets, uint32_t n_sets, hipStream_t s, Arena &ar) {
+  uint64_t max_chunks = 0;
+  for (uint32_t y = 0; y < n_sets; ++y) {
+    SegSet &S = sets.set[y];
+    S.partial = S.n_chunks ? ar.get<double>((size_t)S.n_chunks * W) : nullptr;
+    max_chunks = std::max<uint64_t>(max_chunks, S.n_chunks);
+  }
+  hipLaunchKernelGGL(k_seg_small<W>, dim3(grid_for(n_seg, 256, 8192), n_sets), dim3(256), 0, s,
+                     n_seg, sets);
+  if (max_chunks) {
+    hipLaunchKernelGGL(k_seg_chunks<W>, dim3((unsigned)std::min<uint64_t>(max_chunks, 4096), n_sets),
+                       dim3(256), 0, s, sets);
+    hipLaunchKernelGGL(k_seg_combine<W>, dim3(grid_for(n_seg, 256, 1024), n_sets), dim3(256), 0, s,
+                       sets);
   }
   GPA_LAUNCH_CHECK();
 }
@@ -420,7 +448,6 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint3
   const int s_exec =
       ((bl >> GPA_ST_EXEC_DEP) & 1) ? __builtin_popcount(bl & ((1u << GPA_ST_EXEC_DEP) - 1)) : -1;
   double *iv = ar.get<double>((size_t)n * kNV);
-  double *ev = ar.get<double>(p.n_edges);
   double *own = ar.get<double>((size_t)ns * kNV);
   double *sub = ar.get<double>((size_t)ns * kNV);
   double *iv_g = ar.get<double>((size_t)n * kNV);
@@ -432,24 +459,29 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint3
                      nullptr, p.line_perm, iv, iv_g);
   const uint32_t *big = p.big_list.p;
   const uint32_t *bch = p.big_chunk.p;
-  seg_sum<kNV>(ns, p.line_ptr, nullptr, big, p.big_n.p, bch, p.seg_chunks[0], iv_g, own, s, ar);
-  if (p.n_edges) {
-    hipLaunchKernelGGL(k_edge_contrib, dim3(grid_for(p.n_edges, 256, 8192)), dim3(256), 0, s,
-                       p.n_edges, nbl, s_mem, s_exec, p.e_src.p, p.op_class.p, b.share.p, ev);
-    // edges without a common loop are not in the icl grouping: its size is icl_ptr[ns]
-    hipLaunchKernelGGL(k_gather<1>, dim3(grid_for(p.n_edges, 256, 8192)), dim3(256), 0, s,
-                       (size_t)p.n_edges, p.icl_ptr + ns, p.icl_perm, ev, ev_icl);
-    hipLaunchKernelGGL(k_gather<1>, dim3(grid_for(p.n_edges, 256, 8192)), dim3(256), 0, s,
-                       (size_t)p.n_edges, nullptr, p.lca_perm, ev, ev_lca);
-  }
-  seg_sum<1>(ns, p.icl_ptr, nullptr, big + ns, p.big_n.p + 1, bch + ns, p.seg_chunks[1], ev_icl,
-             own_icl, s, ar);
-  seg_sum<1>(ns, p.lca_ptr, nullptr, big + 2 * (size_t)ns, p.big_n.p + 2, bch + 2 * (size_t)ns,
-             p.seg_chunks[2], ev_lca, own_lca, s, ar);
+  // groupings g (0 line, 1 common loop, 2 common scope, 3 subtree): their
+  // long-segment lists and chunk counts were made at load
+  auto seg_set = [&](int g, const uint32_t *ptr, const uint32_t *end, const double *data,
+                     double *out) {
+    return SegSet{ptr, end, big + (size_t)g * ns, p.big_n.p + g, bch + (size_t)g * ns,
+                  (uint32_t)p.seg_chunks[g], data, out, nullptr};
+  };
+  SegSets line{};
+  line.set[0] = seg_set(0, p.line_ptr, nullptr, iv_g, own);
+  seg_sum<kNV>(ns, line, 1, s, ar);
+  if (p.n_edges)
+    hipLaunchKernelGGL(k_edge_gathered, dim3(grid_for(p.n_edges, 256, 8192)), dim3(256), 0, s,
+                       p.n_edges, nbl, s_mem, s_exec, p.e_src.p, p.op_class.p, b.share.p,
+                       p.icl_ptr + ns, p.icl_perm, p.lca_perm, ev_icl, ev_lca);
+  SegSets edges{};
+  edges.set[0] = seg_set(1, p.icl_ptr, nullptr, ev_icl, own_icl);
+  edges.set[1] = seg_set(2, p.lca_ptr, nullptr, ev_lca, own_lca);
+  seg_sum<1>(ns, edges, 2, s, ar);
   hipLaunchKernelGGL(k_merge_edge_own, dim3(grid_for(ns, 256, 8192)), dim3(256), 0, s, ns, own_icl,
                      own_lca, own);
-  seg_sum<kNV>(ns, nullptr, p.scope_end.p, big + 3 * (size_t)ns, p.big_n.p + 3,
-               bch + 3 * (size_t)ns, p.seg_chunks[3], own, sub, s, ar);
+  SegSets subtree{};
+  subtree.set[0] = seg_set(3, nullptr, p.scope_end.p, own, sub);
+  seg_sum<kNV>(ns, subtree, 1, s, ar);
   GPA_LAUNCH_CHECK();
   a.active.alloc(ns);
   a.matched.alloc((size_t)ns * GPA_N_OPT);
