@@ -276,10 +276,16 @@ struct Cand {
   uint32_t o, l;
 };
 
+// written with non-short-circuit operators so that it compiles to a few
+// compares and mask operations rather than divergent branches
 __device__ __forceinline__ bool better(const Cand &a, const Cand &b) {
-  if (a.s != b.s) return a.s > b.s;
-  if (a.o != b.o) return a.o < b.o;
-  return a.l < b.l;
+  const uint64_t ka = ((uint64_t)a.o << 32) | a.l, kb = ((uint64_t)b.o << 32) | b.l;
+  return (a.s > b.s) | ((a.s == b.s) & (ka < kb));
+}
+
+// the same item (bitwise: a winner is a copy of its owner's head)
+__device__ __forceinline__ bool same(const Cand &a, const Cand &b) {
+  return (__double_as_longlong(a.s) == __double_as_longlong(b.s)) & (a.o == b.o) & (a.l == b.l);
 }
 
 constexpr int kTopK = 16;
@@ -296,11 +302,14 @@ __device__ __forceinline__ Cand cand_none() {
 }
 
 __device__ __forceinline__ void cswap(Cand &a, Cand &b) {
-  if (better(b, a)) {
-    const Cand t = a;
-    a = b;
-    b = t;
-  }
+  const bool sw = better(b, a);
+  const Cand x = a, y = b;
+  a.s = sw ? y.s : x.s;
+  a.o = sw ? y.o : x.o;
+  a.l = sw ? y.l : x.l;
+  b.s = sw ? x.s : y.s;
+  b.o = sw ? x.o : y.o;
+  b.l = sw ? x.l : y.l;
 }
 
 // best first; a bitonic network on 8 with fixed register indices
@@ -319,45 +328,46 @@ __device__ __forceinline__ void sort8(Cand (&a)[kPerThread]) {
       }
 }
 
-// the workgroup's best kTopK of the threads' sorted lists, in order, into out
-__device__ void select_top(Cand (&my)[kPerThread], Cand *out, Cand (*xch)[kTopThreads / kWave],
-                           uint32_t (*xwho)[kTopThreads / kWave]) {
+// the workgroup's best kTopK of the threads' sorted lists, in order, into out.
+// Real items are distinct and the order is total on them, so the round's
+// winner has one owner, found by comparing it with the heads; when the lists
+// are exhausted the winner is the empty candidate and popping an empty head
+// changes nothing.
+__device__ void select_top(Cand (&my)[kPerThread], Cand *out, Cand (*xch)[kTopThreads / kWave]) {
   const unsigned tid = threadIdx.x, w = tid / kWave;
   for (int r = 0; r < kTopK; ++r) {
     Cand c = my[0];
-    uint32_t who = tid;
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) {
       Cand o;
       o.s = __shfl_xor(c.s, d, kWave);
       o.o = (uint32_t)__shfl_xor((int)c.o, d, kWave);
       o.l = (uint32_t)__shfl_xor((int)c.l, d, kWave);
-      const uint32_t ow = (uint32_t)__shfl_xor((int)who, d, kWave);
-      if (better(o, c) || (!better(c, o) && ow < who)) {
-        c = o;
-        who = ow;
-      }
+      const bool take = better(o, c);
+      c.s = take ? o.s : c.s;
+      c.o = take ? o.o : c.o;
+      c.l = take ? o.l : c.l;
     }
-    if (lane_id() == 0) {
-      xch[r & 1][w] = c;
-      xwho[r & 1][w] = who;
-    }
+    if (lane_id() == 0) xch[r & 1][w] = c;
     __syncthreads();
     Cand best = xch[r & 1][0];
-    uint32_t bw = xwho[r & 1][0];
 #pragma unroll
     for (int v = 1; v < kTopThreads / kWave; ++v) {
       const Cand o = xch[r & 1][v];
-      if (better(o, best) || (!better(best, o) && xwho[r & 1][v] < bw)) {
-        best = o;
-        bw = xwho[r & 1][v];
-      }
+      const bool take = better(o, best);
+      best.s = take ? o.s : best.s;
+      best.o = take ? o.o : best.o;
+      best.l = take ? o.l : best.l;
     }
     if (tid == 0) out[r] = best;
-    if (tid == bw) {
+    const bool pop = same(my[0], best);
+    const Cand none = cand_none();
 #pragma unroll
-      for (int i = 0; i < kPerThread - 1; ++i) my[i] = my[i + 1];
-      my[kPerThread - 1] = cand_none();
+    for (int i = 0; i < kPerThread; ++i) {
+      const Cand &nx = i + 1 < kPerThread ? my[i + 1] : none;
+      my[i].s = pop ? nx.s : my[i].s;
+      my[i].o = pop ? nx.o : my[i].o;
+      my[i].l = pop ? nx.l : my[i].l;
     }
   }
 }
@@ -375,7 +385,6 @@ k_topk_chunks(uint32_t n_roots, const uint32_t *roots, const uint32_t *nchunks,
               const uint32_t *chunk_start, const uint32_t *scope_end, const double *speedup,
               Cand *cand) {
   __shared__ Cand xch[2][kTopThreads / kWave];
-  __shared__ uint32_t xwho[2][kTopThreads / kWave];
   const uint32_t c = blockIdx.x;
   const uint32_t total = chunk_start[n_roots - 1] + nchunks[n_roots - 1];
   if (c >= total) return;
@@ -397,7 +406,7 @@ k_topk_chunks(uint32_t n_roots, const uint32_t *roots, const uint32_t *nchunks,
     my[i] = x;
   }
   sort8(my);
-  select_top(my, cand + (size_t)c * kTopK, xch, xwho);
+  select_top(my, cand + (size_t)c * kTopK, xch);
 }
 
 __global__ void __launch_bounds__(kTopThreads)
@@ -405,7 +414,6 @@ k_topk_final(const uint32_t *nchunks, const uint32_t *chunk_start,
              const Cand *cand, uint32_t k, uint32_t *top_opt, uint32_t *top_scope,
              double *top_speed) {
   __shared__ Cand xch[2][kTopThreads / kWave];
-  __shared__ uint32_t xwho[2][kTopThreads / kWave];
   __shared__ Cand best[kTopK];
   const uint32_t ri = blockIdx.x;   // the ri-th kernel root; its row of the output
   const uint32_t n = nchunks[ri] * kTopK;
@@ -429,7 +437,7 @@ k_topk_final(const uint32_t *nchunks, const uint32_t *chunk_start,
     next += kTopChunk - keep;
     __syncthreads();
     sort8(my);
-    select_top(my, best, xch, xwho);
+    select_top(my, best, xch);
     __syncthreads();
   }
   for (uint32_t t = threadIdx.x; t < k; t += kTopThreads) {
