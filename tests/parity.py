@@ -91,8 +91,17 @@ def compare(prog: dict, g: dict, o: dict, k: int = 5):
     top = g["top"]
     osp = oe["speedup"]
     assert np.array_equal(g["roots"], roots), "kernel roots"
+    gsp = np.asarray(est["speedup"])
     for ri, r in enumerate(roots):
         _close(top["top_speed"][ri], oe["top_speed"][r][:k], TOL_SPEEDUP, f"top-k speed root {r}")
+        # the GPU's own row: distinct items, each carrying its own speedup,
+        # in non-increasing order (whatever the oracle's tie order)
+        real = [(int(top["top_opt"][ri, t]), int(top["top_scope"][ri, t]), float(top["top_speed"][ri, t]))
+                for t in range(k) if int(top["top_opt"][ri, t]) != 0xFFFFFFFF]
+        assert len({(o, l) for o, l, _ in real}) == len(real), ("top-k repeats an item", r)
+        for o, l, v in real:
+            assert v == gsp[l, o], ("top-k speed is not the item's", r, o, l)
+        assert all(a[2] >= b[2] for a, b in zip(real, real[1:])), ("top-k order", r)
         for t in range(k):
             go, gs = int(top["top_opt"][ri, t]), int(top["top_scope"][ri, t])
             oo, os_ = int(oe["top_opt"][r, t]), int(oe["top_scope"][r, t])

@@ -12,10 +12,12 @@ from parity import compare, run_gpu
 pytestmark = pytest.mark.gpu
 
 
-def _both(prog, rec, **kw):
-    g = run_gpu(prog, rec, **kw)
-    o = O.run_all(prog, rec)
-    compare(prog, g, o)
+def _both(prog, rec, k=16, **kw):
+    # k = 16, the largest the library takes: kernels with fewer candidates
+    # than k end their rows with empty entries on both sides
+    g = run_gpu(prog, rec, k=k, **kw)
+    o = O.run_all(prog, rec, k=k)
+    compare(prog, g, o, k=k)
     return g, o
 
 
@@ -136,11 +138,12 @@ def test_large_workload_full_parity():
     t = time.time()
     prog, rec = S.workload_large(seed=1)
     print(f"\n  generated in {time.time() - t:.1f}s", flush=True)
-    g = run_gpu(prog, rec)
+    # k = 16, the largest the library takes: every selection round is checked
+    g = run_gpu(prog, rec, k=16)
     print(f"  gpu done at {time.time() - t:.1f}s", flush=True)
-    o = O.run_all(prog, rec)
+    o = O.run_all(prog, rec, k=16)
     print(f"  oracle done at {time.time() - t:.1f}s", flush=True)
-    compare(prog, g, o)
+    compare(prog, g, o, k=16)
     assert g["info"]["n_edges"] > 100_000
 
 
