@@ -26,6 +26,7 @@
 // small launches, but the device-scope fence it needs in every workgroup
 // costs far more on this part.)
 #include <cstdlib>
+#include <type_traits>
 
 #include "common.h"
 #include "devutil.h"
@@ -566,12 +567,17 @@ constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 static_assert(kColdMaxBuckets <= (uint32_t)kHotThreads, "one cold bucket per thread in scans");
 static_assert(kSelSample < 65536u, "16-bit sample counters");
 
-// a hot PC sits in one of its two slots (entry pc | id << 22)
+// a hot PC sits in one of its two slots (entry pc | id << 22), given by two
+// multiplicative hashes of the pc (< 2^17 on this path) taken as 24-bit
+// products, which issue at full rate where a 32-bit multiply takes four
+// cycles (HIP's __umul24 returns int: the product is made unsigned before
+// the shift)
+static_assert(kHotMaxPCs <= (1u << 24), "24-bit hash operands");
 __device__ __forceinline__ uint32_t hot_slot1(uint32_t pc) {
-  return (pc * 0x9E3779B1u) >> (32 - kHotTBits);
+  return (uint32_t)__umul24(pc, 0x9E3779u) >> (32 - kHotTBits);
 }
 __device__ __forceinline__ uint32_t hot_slot2(uint32_t pc) {
-  return (pc * 0x85EBCA6Bu + 0x6A09E667u) >> (32 - kHotTBits);
+  return ((uint32_t)__umul24(pc, 0x85EBCBu) + 0x6A09E667u) >> (32 - kHotTBits);
 }
 __device__ __forceinline__ uint32_t cold_bucket(uint32_t key) { return key >> (5 + kColdShift); }
 __device__ __forceinline__ uint32_t cold_local_bin(uint32_t key) {
@@ -701,8 +707,9 @@ __device__ void sort_cold_tile(uint32_t n_cb, uint64_t base, uint32_t m,
 }
 
 // Workgroup w reads records [w per, min((w + 1) per, n)) in steps of
-// kHotStep (per is a multiple of kHotStep), the loads of the next two steps
-// in flight while a step is counted; its cold keys are appended to cold[]
+// kHotStep (per is even; a last step that is not whole reads its records
+// one by one, clamped), the loads of the next two steps in flight while a
+// step is counted; its cold keys are appended to cold[]
 // from index w per on (one LDS reservation per wave and step), their number
 // to n_cold[w].  Then the workgroup sorts its cold keys by bucket in tiles
 // of kColdTile: tile t's bucket starts go to
@@ -740,26 +747,25 @@ k_hot_pass(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint3
   }
   lds_barrier();
   uint32_t *my_cold = cold + r0;
-  uint32_t my_valid = 0, my_lat = 0;
-  auto step = [&](uint64_t i0, const uint64_t (&cur)[2 * kHotUnroll]) {
+  // the wave's valid and latency records, counted from ballots (uniform)
+  uint32_t w_valid = 0, w_lat = 0;
+  // FULL: a step wholly below r1 (no index check); the table slots are in
+  // range for any pc, so the lookups need no validity branch
+  auto step = [&](auto full, uint64_t i0, const uint64_t (&cur)[2 * kHotUnroll]) {
+    constexpr bool FULL = decltype(full)::value;
     uint32_t cmask = 0;
 #pragma unroll
     for (int q = 0; q < 2 * kHotUnroll; ++q) {
-      const uint64_t i = i0 + 2 * ((uint64_t)(q / 2) * kHotThreads + tid) + (q & 1);
       const uint64_t r = cur[q];
       const uint32_t pc = (uint32_t)r, hi = (uint32_t)(r >> 32);
-      const bool ok = i < r1 && rec_valid(r, n_instr);
-      bool hot = false;
-      if (ok) {
-        const uint32_t e1 = tab[hot_slot1(pc)], e2 = tab[hot_slot2(pc)];
-        const uint32_t e = (e1 & 0x3FFFFFu) == pc ? e1 : e2;   // an empty slot matches no pc
-        if ((e & 0x3FFFFFu) == pc) {
-          hot = true;
-          atomicAdd(&bins[(e >> 22) * 24u + (hi & 0xFFu) * 2u + ((hi >> 8) & 1u)], 1u);
-        }
-      }
-      my_valid += ok ? 1u : 0u;
-      my_lat += ok ? (hi >> 8) & 1u : 0u;
+      bool ok = pc < n_instr && hi < 0x200u && (hi & 0xFFu) < 12u;   // rec_valid
+      if (!FULL) ok = ok && i0 + 2 * ((uint64_t)(q / 2) * kHotThreads + tid) + (q & 1) < r1;
+      const uint32_t e1 = tab[hot_slot1(pc)], e2 = tab[hot_slot2(pc)];
+      const uint32_t e = (e1 & 0x3FFFFFu) == pc ? e1 : e2;   // an empty slot matches no pc
+      const bool hot = ok && (e & 0x3FFFFFu) == pc;
+      if (hot) atomicAdd(&bins[(e >> 22) * 24u + (hi & 0xFFu) * 2u + ((hi >> 8) & 1u)], 1u);
+      w_valid += (uint32_t)__popcll(__ballot(ok));
+      w_lat += (uint32_t)__popcll(__ballot(ok && ((hi >> 8) & 1u)));
       cmask |= (ok && !hot) ? 1u << q : 0u;
     }
     // the step's cold keys: one LDS reservation per wave
@@ -778,26 +784,26 @@ k_hot_pass(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint3
         }
     }
   };
+  constexpr std::true_type kFull{};
+  constexpr std::false_type kPart{};
   for (uint64_t i0 = r0; i0 < rf;) {
     issue(i0 + 2 * kHotStep, vc);
-    step(i0, va);
+    step(kFull, i0, va);
     if ((i0 += kHotStep) >= rf) break;
     issue(i0 + 2 * kHotStep, va);
-    step(i0, vb);
+    step(kFull, i0, vb);
     if ((i0 += kHotStep) >= rf) break;
     issue(i0 + 2 * kHotStep, vb);
-    step(i0, vc);
+    step(kFull, i0, vc);
     i0 += kHotStep;
   }
   if (rf < r1) {
     hot_load<VEC, false>(rec, r1, rf, va);
-    step(rf, va);
+    step(kPart, rf, va);
   }
-  my_valid = wave_sum(my_valid);
-  my_lat = wave_sum(my_lat);
   if (lane == 0) {
-    atomicAdd(&s_valid, my_valid);
-    atomicAdd(&s_lat, my_lat);
+    atomicAdd(&s_valid, w_valid);
+    atomicAdd(&s_lat, w_lat);
   }
   __syncthreads();
   uint32_t *dst = partial + (size_t)blockIdx.x * kHotBins;
@@ -972,9 +978,12 @@ static bool run_hist_hot(const gpa_program &p, const uint64_t *rec, uint64_t n, 
   const char *force = getenv("GPA_HIST_PARTITION");
   if (force && force[0] == '1') return false;
   const uint32_t n_cb = (n_instr + kColdPCs - 1) / kColdPCs;
-  // workgroup ranges: a multiple of kHotStep records each, kHotGrid at most
+  // workgroup ranges: kHotGrid at most, each a multiple of 128 records (even,
+  // so the 16-byte loads stay aligned; finer than a whole step, so that the
+  // grid comes as close to kHotGrid as it can, a range's last step being
+  // partial where it must)
   uint64_t per = (n + kHotGrid - 1) / kHotGrid;
-  per = (per + kHotStep - 1) / kHotStep * kHotStep;
+  per = (per + 2 * kWave - 1) / (2 * kWave) * (2 * kWave);
   const uint32_t G = (uint32_t)((n + per - 1) / per);
   const uint32_t T = (uint32_t)((per + kColdTile - 1) / kColdTile);   // tiles per workgroup
   const uint64_t run_stride = n > kSelSample ? (n - kSelRun) / (kSelSample / kSelRun - 1) : 0;
