@@ -665,21 +665,21 @@ __device__ __forceinline__ void hot_load(const uint64_t *__restrict__ rec, uint6
   }
 }
 
-// m <= kColdTile cold keys at cold[base, base + m) sorted by bucket into
-// cold_sorted at the same indices; the bucket starts (absolute indices) to
-// off[0, n_cb), the end to off[n_cb].  Every thread of the workgroup calls
-// it; it ends on a barrier.
-__device__ void sort_cold_tile(uint32_t n_cb, uint64_t base, uint32_t m,
-                               const uint32_t *__restrict__ cold, uint32_t *__restrict__ cold_sorted,
-                               uint32_t *__restrict__ off, uint32_t *sorted, uint32_t *bc,
-                               uint32_t *scan_tmp) {
+// m <= kColdTile cold keys src[0, m) (in global memory, or in sorted[]
+// itself: every key is in registers before sorted[] is written) sorted by
+// bucket into cold_sorted[base, base + m); the bucket starts (absolute
+// indices) to off[0, n_cb), the end to off[n_cb].  Every thread of the
+// workgroup calls it; it ends on a barrier.
+__device__ void sort_cold_tile(uint32_t n_cb, uint64_t base, uint32_t m, const uint32_t *src,
+                               uint32_t *__restrict__ cold_sorted, uint32_t *__restrict__ off,
+                               uint32_t *sorted, uint32_t *bc, uint32_t *scan_tmp) {
   const unsigned tid = threadIdx.x;
   constexpr uint32_t kPer = kColdTile / kHotThreads;
   uint32_t key[kPer];
 #pragma unroll
   for (uint32_t j = 0; j < kPer; ++j) {
     const uint32_t k = j * kHotThreads + tid;
-    key[j] = k < m ? cold[base + k] : kEmpty;
+    key[j] = k < m ? src[k] : kEmpty;
   }
   for (uint32_t b = tid; b < n_cb; b += kHotThreads) bc[b] = 0;
   __syncthreads();
@@ -709,11 +709,14 @@ __device__ void sort_cold_tile(uint32_t n_cb, uint64_t base, uint32_t m,
 // Workgroup w reads records [w per, min((w + 1) per, n)) in steps of
 // kHotStep (per is even; a last step that is not whole reads its records
 // one by one, clamped), the loads of the next two steps in flight while a
-// step is counted; its cold keys are appended to cold[]
-// from index w per on (one LDS reservation per wave and step), their number
-// to n_cold[w].  Then the workgroup sorts its cold keys by bucket in tiles
-// of kColdTile: tile t's bucket starts go to
-// tile_off[(w T + t) (n_cb + 1) + b] (entry n_cb: the end).
+// step is counted; its cold keys are appended in arrival order (one LDS
+// reservation per wave and step), their number to n_cold[w]: the first
+// kColdTile to the LDS array that the tile sort uses (idle until then), so
+// that the first tile is sorted without a round trip through memory, and
+// the rest to cold[] at their positions from index w per on.  Then the
+// workgroup sorts its cold keys by bucket in tiles of kColdTile: tile t's
+// bucket starts go to tile_off[(w T + t) (n_cb + 1) + b] (entry n_cb: the
+// end).
 template <bool VEC>
 __global__ void __launch_bounds__(kHotThreads)
 k_hot_pass(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint32_t n_cb,
@@ -780,7 +783,10 @@ k_hot_pass(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint3
       for (int q = 0; q < 2 * kHotUnroll; ++q)
         if ((cmask >> q) & 1u) {
           const uint32_t hi = (uint32_t)(cur[q] >> 32);
-          my_cold[pos++] = ((uint32_t)cur[q] << 5) | ((hi & 0xFFu) * 2u + ((hi >> 8) & 1u));
+          const uint32_t key = ((uint32_t)cur[q] << 5) | ((hi & 0xFFu) * 2u + ((hi >> 8) & 1u));
+          if (pos < kColdTile) sorted[pos] = key;
+          else my_cold[pos] = key;
+          ++pos;
         }
     }
   };
@@ -819,9 +825,9 @@ k_hot_pass(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint3
   }
   const uint32_t nc = s_cur;   // the keys were written before the barrier above
   for (uint32_t t = 0; t * kColdTile < nc; ++t)
-    sort_cold_tile(n_cb, r0 + t * kColdTile, min(kColdTile, nc - t * kColdTile), cold,
-                   cold_sorted, tile_off + ((size_t)blockIdx.x * T + t) * (n_cb + 1), sorted, bc,
-                   scan_tmp);
+    sort_cold_tile(n_cb, r0 + t * kColdTile, min(kColdTile, nc - t * kColdTile),
+                   t == 0 ? (const uint32_t *)sorted : my_cold + t * kColdTile, cold_sorted,
+                   tile_off + ((size_t)blockIdx.x * T + t) * (n_cb + 1), sorted, bc, scan_tmp);
 }
 
 // blocks [0, n_cb): the cold bins of one bucket; the next
