@@ -98,6 +98,24 @@ std::mutex g_tmu;
 bool g_timing = false;
 double g_ms[kNumPhases] = {0};
 uint64_t g_calls[kNumPhases] = {0};
+// events are reused, per device: creating and destroying two per timed
+// phase on every call would put host work between the launches it times
+std::map<int, std::vector<hipEvent_t>> g_events;
+
+hipEvent_t take_event(int dev) {
+  {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    auto &v = g_events[dev];
+    if (!v.empty()) {
+      hipEvent_t e = v.back();
+      v.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e = nullptr;
+  GPA_HIP(hipEventCreate(&e));
+  return e;
+}
 }  // namespace
 
 void PhaseTimer::begin(int ph, hipStream_t s) {
@@ -105,9 +123,10 @@ void PhaseTimer::begin(int ph, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_tmu);
     if (!g_timing) return;
   }
+  GPA_HIP(hipGetDevice(&dev));
   phase = ph;
-  GPA_HIP(hipEventCreate(&a));
-  GPA_HIP(hipEventCreate(&b));
+  a = take_event(dev);
+  b = take_event(dev);
   GPA_HIP(hipEventRecord(a, s));
 }
 
@@ -128,8 +147,11 @@ void PhaseTimer::collect() {
 }
 
 PhaseTimer::~PhaseTimer() {
-  if (a) (void)hipEventDestroy(a);
-  if (b) (void)hipEventDestroy(b);
+  // back to the device's pool (an event still pending is simply recorded
+  // again by its next user)
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (a) g_events[dev].push_back(a);
+  if (b) g_events[dev].push_back(b);
 }
 
 // ------------------------------------------------------- side streams

@@ -258,8 +258,8 @@ enum Phase {
   kNumPhases
 };
 struct PhaseTimer {
-  hipEvent_t a = nullptr, b = nullptr;
-  int phase = -1;
+  hipEvent_t a = nullptr, b = nullptr;   // from a per-device pool
+  int phase = -1, dev = 0;
   void begin(int ph, hipStream_t s);
   void end(hipStream_t s);
   void collect();   // after the stream has been synchronized
