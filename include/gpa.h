@@ -21,6 +21,10 @@
  *   - Inputs are borrowed for the duration of the call and copied; handles
  *     own their device memory until the matching *_free call.  A program is
  *     read-only after loading and may back any number of blame handles.
+ *     Blame and advice handles hold a reference to their program: after
+ *     gpa_program_free the program's memory stays until the last blame and
+ *     advice handle made from it is freed, so the handles may be freed in
+ *     any order.
  *   - Copy-out getters write to host buffers; passing NULL for an optional
  *     buffer skips it.
  */
@@ -194,7 +198,10 @@ gpa_status gpa_blame_shares(const gpa_blame *b, double *share);
 gpa_status gpa_blame_table(const gpa_blame *b, double *blamed, double *self_, double *fine);
 
 /* Estimate the speedup of each code optimizer at each scope: Eq. (2) for
- * stall elimination, Eq. (5) for latency hiding (Eq. (4) at a kernel). */
+ * stall elimination, Eq. (5) for latency hiding (Eq. (4) at a kernel).
+ * A kernel without samples gives 1; an optimizer whose matched (or, for
+ * hiding, hidden) samples reach the kernel's total gives +inf, also when
+ * rounding in the share sums puts them a few ulps above it. */
 gpa_status gpa_advise(const gpa_blame *b, void *stream, gpa_advice **out);
 void gpa_advice_free(gpa_advice *a);
 /* active[n_scopes], matched[n_scopes*9], speedup[n_scopes*9],

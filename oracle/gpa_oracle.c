@@ -822,19 +822,21 @@ void orc_estimate(const orc_analysis *a, const uint32_t *C, const double *share,
     add_up(p, matched, ORC_N_OPT, ORC_O_REORDER, lca(p, si, sj), v);
   }
   /* Eq. (2) for stall elimination, Eq. (5) (Eq. (4) at the kernel scope)
-   * for latency hiding; T is the kernel's total */
+   * for latency hiding; T is the kernel's total.  Removing x >= T of the
+   * kernel's T samples gives +inf (the formula would divide by zero, or by
+   * a negative number when rounding in the share sums puts x above T). */
   for (uint32_t s = 0; s < ns; ++s) {
     double T = kernel_T[root_of[s]];
     for (uint32_t o = 0; o < ORC_N_OPT; ++o) {
       double M = matched[(size_t)s * ORC_N_OPT + o];
       double x = (o >= ORC_O_LOOP_UNROLL) ? (active[s] < M ? active[s] : M) : M;
-      double sp = (T == 0.0) ? 1.0 : T / (T - x);
+      double sp = (T == 0.0) ? 1.0 : (x >= T ? INFINITY : T / (T - x));
       speedup[(size_t)s * ORC_N_OPT + o] = sp;
     }
     if (p->scope_parent[s] == ORC_NONE) {
       for (uint32_t h = 0; h < 3; ++h) {
         double M = matched[(size_t)s * ORC_N_OPT + ORC_O_LOOP_UNROLL + h];
-        eq3[(size_t)s * 3 + h] = (T == 0.0) ? 1.0 : T / (T - M);
+        eq3[(size_t)s * 3 + h] = (T == 0.0) ? 1.0 : (M >= T ? INFINITY : T / (T - M));
       }
     }
   }

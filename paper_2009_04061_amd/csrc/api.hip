@@ -279,6 +279,31 @@ static void copy_out(T *host, const DBuf<T> &src, size_t n, hipStream_t s) {
 
 }  // namespace gpa
 
+gpa_blame::gpa_blame(const gpa_program *p) : prog(p) { gpa::program_retain(p); }
+gpa_blame::~gpa_blame() {
+  // the buffers go back to the pool before the program can go
+  counts.release();
+  dtotals.release();
+  share.release();
+  blamed.release();
+  self_.release();
+  fine.release();
+  gpa::program_release(prog);
+}
+gpa_advice::gpa_advice(const gpa_program *p) : prog(p) { gpa::program_retain(p); }
+gpa_advice::~gpa_advice() {
+  active.release();
+  matched.release();
+  speedup.release();
+  kernel_T.release();
+  kernel_L.release();
+  eq3.release();
+  top_opt.release();
+  top_scope.release();
+  top_speed.release();
+  gpa::program_release(prog);
+}
+
 using namespace gpa;
 
 extern "C" {
@@ -449,7 +474,7 @@ gpa_status gpa_load_program(const gpa_program_desc *d, void *stream, gpa_program
   return GPA_OK;
 }
 
-void gpa_program_free(gpa_program *p) { delete p; }
+void gpa_program_free(gpa_program *p) { program_release(p); }
 
 gpa_status gpa_program_get_info(const gpa_program *p, gpa_program_info *info) {
   if (!p || !info) {
@@ -523,8 +548,7 @@ gpa_status gpa_attribute(gpa_program *p, const gpa_sample *samples, uint64_t n,
   gpa_blame *b = nullptr;
   hipStream_t s = (hipStream_t)stream;
   gpa_status st = guarded([&] {
-    b = new gpa_blame();
-    b->prog = p;
+    b = new gpa_blame(p);
     Arena ar(s);
     const gpa_sample *dsamp = samples;
     if (n && !samples_on_device) {
@@ -607,8 +631,7 @@ gpa_status gpa_advise(const gpa_blame *b, void *stream, gpa_advice **out) {
   gpa_advice *a = nullptr;
   hipStream_t s = (hipStream_t)stream;
   gpa_status st = guarded([&] {
-    a = new gpa_advice();
-    a->prog = b->prog;
+    a = new gpa_advice(b->prog);
     Arena ar(s);
     PhaseTimer t_adv;
     t_adv.begin(kPhaseAdvise, s);

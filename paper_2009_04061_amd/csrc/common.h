@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -87,6 +88,9 @@ struct Arena {
 }  // namespace gpa
 
 struct gpa_program {
+  // one reference for the caller's handle and one per blame or advice handle
+  // made from it: the program's memory goes when the last of them is freed
+  std::atomic<int> refs{1};
   // sizes
   uint32_t n_instr = 0, n_blocks = 0, n_funcs = 0, n_scopes = 0;
   uint32_t n_regs = 0, n_preds = 0, n_bars = 0, n_loc = 0;
@@ -149,24 +153,37 @@ struct gpa_program {
 };
 
 struct gpa_blame {
-  const gpa_program *prog = nullptr;
+  const gpa_program *prog = nullptr;   // holds a reference
   uint64_t totals[4] = {0, 0, 0, 0};
   gpa::DBuf<uint32_t> counts;          // [n_instr*24]
   gpa::DBuf<unsigned long long> dtotals;
   gpa::DBuf<double> share;             // [n_edges*n_blamable*2]
   gpa::DBuf<double> blamed, self_;     // [n_instr*24]
   gpa::DBuf<double> fine;              // [n_instr*GPA_N_FINE*2]
+  explicit gpa_blame(const gpa_program *p);
+  ~gpa_blame();
 };
 
 struct gpa_advice {
-  const gpa_program *prog = nullptr;
+  const gpa_program *prog = nullptr;   // holds a reference
   gpa::DBuf<double> active, matched, speedup, kernel_T, kernel_L, eq3;
   gpa::DBuf<uint32_t> top_opt, top_scope;
   gpa::DBuf<double> top_speed;
   uint32_t k = 0;
+  explicit gpa_advice(const gpa_program *p);
+  ~gpa_advice();
 };
 
 namespace gpa {
+
+// reference counting of programs by their blame and advice handles
+inline void program_retain(const gpa_program *p) {
+  const_cast<gpa_program *>(p)->refs.fetch_add(1, std::memory_order_relaxed);
+}
+inline void program_release(const gpa_program *p) {
+  if (p && const_cast<gpa_program *>(p)->refs.fetch_sub(1, std::memory_order_acq_rel) == 1)
+    delete const_cast<gpa_program *>(p);
+}
 
 // ------------------------------------------------------------ device steps
 // scan.hip: exclusive prefix sum of n u32 values into out (out may alias

@@ -238,6 +238,12 @@ __global__ void k_merge_edge_own(uint32_t n_scopes, const double *own_icl, const
   }
 }
 
+// T / (T - y): 1 for an empty kernel; +inf once y reaches T (also when
+// rounding in the share sums puts y a few ulps above T)
+__device__ __forceinline__ double saturating_speedup(double T, double y) {
+  return (T == 0.0) ? 1.0 : (y >= T ? __builtin_huge_val() : T / (T - y));
+}
+
 __global__ void k_speedup(uint32_t n_scopes, const uint32_t *parent, const uint32_t *root_of,
                           const double *sub, double *active, double *matched, double *speedup,
                           double *kernel_T, double *kernel_L, double *eq3) {
@@ -251,14 +257,13 @@ __global__ void k_speedup(uint32_t n_scopes, const uint32_t *parent, const uint3
       const double M = x[o];
       const double y = (o >= GPA_O_LOOP_UNROLLING) ? (A < M ? A : M) : M;
       matched[(size_t)l * GPA_N_OPT + o] = M;
-      speedup[(size_t)l * GPA_N_OPT + o] = (T == 0.0) ? 1.0 : T / (T - y);
+      speedup[(size_t)l * GPA_N_OPT + o] = saturating_speedup(T, y);
     }
     const bool root = parent[l] == GPA_NONE;
     kernel_T[l] = root ? T : 0.0;
     kernel_L[l] = root ? T - A : 0.0;
     for (int h = 0; h < 3; ++h)
-      eq3[(size_t)l * 3 + h] =
-          root ? ((T == 0.0) ? 1.0 : T / (T - x[GPA_O_LOOP_UNROLLING + h])) : 0.0;
+      eq3[(size_t)l * 3 + h] = root ? saturating_speedup(T, x[GPA_O_LOOP_UNROLLING + h]) : 0.0;
   }
 }
 

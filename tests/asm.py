@@ -6,7 +6,10 @@ Syntax, one item per line (``#`` starts a comment)::
       @P0 LDG R0 <- R2 R3 | wbar B0
       IADD R1 <- R0 R5 | wait B0
     loop 0 1                # a LOOP scope over blocks 0..1 (nested by range)
-    func math 3 4           # a FUNCTION scope (math_fn / device_fn) over blocks 3..4
+    func math 3 4           # an inlined FUNCTION scope (math_fn / device_fn) over blocks 3..4
+    cfg device              # the blocks that follow form a function with its
+                            # own CFG (kernel | device | math); a device or
+                            # math function hangs below the latest kernel
 
 Every instruction gets its own LINE scope under the innermost loop (or
 function) holding its block.  ``@Pk`` / ``@!Pk`` set the guard and add a
@@ -34,6 +37,7 @@ def assemble(text: str, n_regs=16, n_preds=4, n_bars=6, arch=None):
     blocks = []     # list of (succs, [instr dicts])
     loops = []
     funcs = []
+    cfgs = [("kernel", 0)]      # (kind, first block) of each function with a CFG
     for raw in text.splitlines():
         line = raw.split("#")[0].strip()
         if not line:
@@ -47,6 +51,14 @@ def assemble(text: str, n_regs=16, n_preds=4, n_bars=6, arch=None):
         if line.startswith("loop"):
             _, a, b = line.split()
             loops.append((int(a), int(b)))
+            continue
+        if line.startswith("cfg"):
+            _, kind = line.split()
+            assert kind in ("kernel", "device", "math"), line
+            if blocks:
+                cfgs.append((kind, len(blocks)))
+            else:
+                cfgs[0] = (kind, 0)
             continue
         if line.startswith("func"):
             _, kind, a, b = line.split()
@@ -101,15 +113,44 @@ def assemble(text: str, n_regs=16, n_preds=4, n_bars=6, arch=None):
     n = len(ins)
     block_begin = np.zeros(nb + 1, np.uint32)
     block_begin[1:] = np.cumsum([len(lst) for _, lst in blocks])
-    # scopes: root, loops / inline functions (nested by block range), one line per instruction
+    # scopes: one FUNCTION per CFG function (a kernel is a root, a device or
+    # math function hangs below the latest kernel), loops and inlined
+    # functions nested by block range inside their CFG function, one line
+    # per instruction
+    nf = len(cfgs)
+    fbb = [b0 for _, b0 in cfgs] + [nb]
+    func_of = np.zeros(nb, np.int64)
+    for f in range(nf):
+        func_of[fbb[f]:fbb[f + 1]] = f
+    parent, kind, flags, key = [], [], [], []
+    fscope = []
+    last_kernel = None
+    for f, (k, b0) in enumerate(cfgs):
+        fl = S.SF_HAS_CFG
+        if k == "kernel":
+            fl |= S.SF_KERNEL_ENTRY
+            par = None
+        else:
+            fl |= S.SF_DEVICE_FN | (S.SF_MATH_FN if k == "math" else 0)
+            assert last_kernel is not None, "a device function needs a kernel before it"
+            par = last_kernel
+        parent.append(par)
+        kind.append(S.SCOPE_FUNCTION)
+        flags.append(fl)
+        key.append(int(block_begin[b0]))
+        fscope.append(len(parent) - 1)
+        if k == "kernel":
+            last_kernel = len(parent) - 1
     regions = [("loop", a, b) for a, b in loops] + [(k, a, b) for k, a, b in funcs]
     regions.sort(key=lambda r: (r[1], -r[2]))
-    parent, kind, flags, key = [None], [S.SCOPE_FUNCTION], [S.SF_KERNEL_ENTRY | S.SF_HAS_CFG], [0]
+    for (_, a, b) in regions:
+        assert func_of[a] == func_of[b], "a region must stay inside one function"
     reg_scope = []
     for (k, a, b) in regions:
         enclosing = [ri for ri, (_, a2, b2) in enumerate(regions[:len(reg_scope)])
                      if a2 <= a and b <= b2]
-        par = 0 if not enclosing else reg_scope[max(enclosing, key=lambda ri: regions[ri][1])]
+        par = (fscope[func_of[a]] if not enclosing
+               else reg_scope[max(enclosing, key=lambda ri: regions[ri][1])])
         parent.append(par)
         if k == "loop":
             kind.append(S.SCOPE_LOOP)
@@ -122,7 +163,8 @@ def assemble(text: str, n_regs=16, n_preds=4, n_bars=6, arch=None):
     instr_scope_tmp = []
     for b in range(nb):
         inner = [ri for ri, (_, a, e) in enumerate(regions) if a <= b <= e]
-        par = 0 if not inner else reg_scope[min(inner, key=lambda ri: regions[ri][2] - regions[ri][1])]
+        par = (fscope[func_of[b]] if not inner
+               else reg_scope[min(inner, key=lambda ri: (regions[ri][2] - regions[ri][1], -ri))])
         for t in range(int(block_begin[b]), int(block_begin[b + 1])):
             parent.append(par)
             kind.append(S.SCOPE_LINE)
@@ -131,11 +173,13 @@ def assemble(text: str, n_regs=16, n_preds=4, n_bars=6, arch=None):
             instr_scope_tmp.append(len(parent) - 1)
     ns = len(parent)
     children = [[] for _ in range(ns)]
-    for s in range(1, ns):
-        children[parent[s]].append(s)
+    roots = []
+    for s in range(ns):
+        (roots if parent[s] is None else children[parent[s]]).append(s)
     for c in children:
         c.sort(key=lambda s: (key[s], kind[s]))
-    order, stack = [], [0]
+    roots.sort(key=lambda s: key[s])
+    order, stack = [], list(reversed(roots))
     while stack:
         s = stack.pop()
         order.append(s)
@@ -163,8 +207,8 @@ def assemble(text: str, n_regs=16, n_preds=4, n_bars=6, arch=None):
         "use_kind": np.array([k for i in ins for _, k in i["uses"]], np.uint8),
         "block_begin": block_begin, "succ_ptr": succ_ptr,
         "succ": np.array([t for s, _ in blocks for t in s], np.uint32),
-        "func_block_begin": np.array([0, nb], np.uint32),
-        "func_scope": np.array([0], np.uint32),
+        "func_block_begin": np.array(fbb, np.uint32),
+        "func_scope": remap[np.array(fscope, np.int64)].astype(np.uint32),
         "instr_scope": remap[np.array(instr_scope_tmp, np.int64)].astype(np.uint32),
         "scope_parent": scope_parent,
         "scope_kind": np.array([kind[o] for o in order], np.uint8),

@@ -303,3 +303,29 @@ def test_histogram_bucket_outgrows_its_estimate(monkeypatch):
     _both(prog, rec)
     monkeypatch.delenv("GPA_HIST_PARTITION")
     _both(prog, rec)
+
+
+def _golden_cases():
+    import json
+    import os
+    gold = os.path.join(os.path.dirname(__file__), "golden")
+    for name in sorted(os.listdir(gold)):
+        with open(os.path.join(gold, name)) as f:
+            g = json.load(f)
+        if "program" in g and "samples" in g:
+            yield name, g["program"], g["samples"]
+        for k, c in enumerate(g.get("cases", [])):
+            yield f"{name}[{k}]", c.get("program", g.get("program")), c["samples"]
+
+
+GOLDEN = list(_golden_cases())
+
+
+@pytest.mark.parametrize("name,text,spec", GOLDEN, ids=[g[0] for g in GOLDEN])
+def test_hand_worked_programs_on_gpu(name, text, spec):
+    """Every hand-worked program of tests/golden (Table 2 rows, Fig. 5 fine
+    classes, Eq. (3), ranking ties, saturated estimates) through the HIP
+    path, element by element against the oracle."""
+    prog = assemble(text)
+    rec = samples([(pc, S.STALL_NAMES.index(st), lam, n) for pc, st, lam, n in spec])
+    _both(prog, rec)

@@ -11,6 +11,7 @@ import os
 import pytest
 
 import test_oracle_bruteforce as TB
+import test_oracle_table2 as T2
 import test_oracle_worked_examples as TW
 from oracle import oracle as O
 
@@ -79,13 +80,68 @@ MUTANTS = [
      "double x = M;",
      [lambda: TW.test_theorem_latency_hiding_bound(1)]),
     ("Eq. 2 sign",
-     "double sp = (T == 0.0) ? 1.0 : T / (T - x);",
-     "double sp = (T == 0.0) ? 1.0 : T / (T + x);",
+     "double sp = (T == 0.0) ? 1.0 : (x >= T ? INFINITY : T / (T - x));",
+     "double sp = (T == 0.0) ? 1.0 : (x >= T ? INFINITY : T / (T + x));",
      [TW.test_eq2_stall_elimination_closed_form]),
     ("subtree sums stop at the scope itself",
      "    if (p->scope_parent[s] == ORC_NONE) return;\n    s = p->scope_parent[s];",
      "    return;",
      [TW.test_nested_scope_actives]),
+    # Table 2 matching rules
+    ("Register Reuse matches global instead of local memory sources",
+     "if (cls == ORC_LOCAL_LOAD || cls == ORC_LOCAL_STORE)\n      add_up(p, matched, ORC_N_OPT, ORC_O_REG_REUSE",
+     "if (cls == ORC_GLOBAL_LOAD)\n      add_up(p, matched, ORC_N_OPT, ORC_O_REG_REUSE",
+     [T2.test_register_reuse_and_memory_fine_classes]),
+    ("Strength Reduction matches plain ALU sources",
+     "if (cls == ORC_FP64 || cls == ORC_LONG_ALU)",
+     "if (cls == ORC_ALU)",
+     [T2.test_strength_reduction_and_execution_fine_classes]),
+    ("Fast Math keyed on the device-function flag",
+     "if (in_function_with(p, s, ORC_SF_MATH)) {",
+     "if (in_function_with(p, s, ORC_SF_DEVICE)) {",
+     [T2.test_fast_math_uses_the_math_flag_and_inlining_skips_inlined_scopes]),
+    ("Warp Balance without the kept synchronization stalls",
+     " +\n               self_[((size_t)j * 12 + ORC_SYNC) * 2] + self_[((size_t)j * 12 + ORC_SYNC) * 2 + 1]);",
+     ");",
+     [T2.test_warp_balance_takes_blamed_and_kept_synchronization_stalls]),
+    ("Function Inlining counts active instead of latency samples",
+     "for (uint32_t r = 0; r < 12; ++r) v += CNT(j, r, 1);",
+     "for (uint32_t r = 0; r < 12; ++r) v += CNT(j, r, 0);",
+     [T2.test_function_inlining_counts_latency_samples_of_called_device_functions]),
+    ("Function Inlining also matches inlined device-function scopes",
+     "in_function_with(p, s, ORC_SF_DEVICE | ORC_SF_CFG)",
+     "in_function_with(p, s, ORC_SF_DEVICE)",
+     [T2.test_fast_math_uses_the_math_flag_and_inlining_skips_inlined_scopes]),
+    ("Loop Unrolling target taken as the lowest common scope",
+     "uint32_t loop = common_loop(p, si, sj, fscope);",
+     "uint32_t loop = lca(p, si, sj);",
+     [T2.test_loop_unrolling_goes_to_the_innermost_common_loop]),
+    # Fig. 5 fine classes
+    ("constant-memory sources put in the local fine class",
+     "if (cls == ORC_CONST_LOAD) return ORC_F_MEM_CONST;",
+     "if (cls == ORC_CONST_LOAD) return ORC_F_MEM_LOCAL;",
+     [T2.test_register_reuse_and_memory_fine_classes]),
+    ("shared-memory sources put in the arithmetic fine class",
+     "if (cls == ORC_SHARED_LOAD) return ORC_F_EXEC_SHARED;",
+     "if (cls == ORC_SHARED_LOAD) return ORC_F_EXEC_ARITH;",
+     [T2.test_strength_reduction_and_execution_fine_classes]),
+    # Eq. (3), ranking, saturation
+    ("Eq. 3 bounded by the active samples like Eq. 4",
+     "eq3[(size_t)s * 3 + h] = (T == 0.0) ? 1.0 : (M >= T ? INFINITY : T / (T - M));",
+     "eq3[(size_t)s * 3 + h] = (T == 0.0) ? 1.0 : T / (T - (active[s] < M ? active[s] : M));",
+     [T2.test_eq3_differs_from_eq4_when_active_samples_bound_the_hiding]),
+    ("ranking ties broken by optimizer descending",
+     "if (x->opt != y->opt) return x->opt < y->opt ? -1 : 1;",
+     "if (x->opt != y->opt) return x->opt > y->opt ? -1 : 1;",
+     [T2.test_ranking_ties_break_by_optimizer_then_scope]),
+    ("ranking ties broken by scope descending",
+     "return (x->scope > y->scope) - (x->scope < y->scope);",
+     "return (x->scope < y->scope) - (x->scope > y->scope);",
+     [T2.test_ranking_ties_break_by_optimizer_then_scope]),
+    ("saturated estimate left to the plain formula",
+     "double sp = (T == 0.0) ? 1.0 : (x >= T ? INFINITY : T / (T - x));",
+     "double sp = (T == 0.0) ? 1.0 : T / (T - x);",
+     [lambda: T2.test_saturated_estimate_is_infinite(1)]),
 ]
 
 
