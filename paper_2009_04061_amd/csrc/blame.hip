@@ -162,22 +162,28 @@ __global__ void k_blame_src(uint32_t n_instr, uint32_t nbl, uint32_t blamable,
 void run_blame(const gpa_program &p, gpa_blame &b, hipStream_t s, Arena &ar) {
   (void)ar;
   const uint32_t n = p.n_instr;
-  const uint32_t nbl = p.n_blamable;
-  b.share.alloc(p.n_edges * nbl * 2);
+  b.share.alloc(p.n_edges * p.n_blamable * 2);
   b.blamed.alloc((size_t)n * 24);
   b.self_.alloc((size_t)n * 24);
   b.fine.alloc((size_t)n * GPA_N_FINE * 2);
+  launch_blame(p, b.counts.p, b.share.p, b.blamed.p, b.self_.p, b.fine.p, s);
+}
+
+void launch_blame(const gpa_program &p, const uint32_t *counts, double *share, double *blamed,
+                  double *self_, double *fine, hipStream_t s) {
+  const uint32_t n = p.n_instr;
+  const uint32_t nbl = p.n_blamable;
   ArchDev a;
   for (int r = 0; r < 12; ++r) a.allowed[r] = p.arch.allowed[r];
   a.blamable = p.arch.blamable;
   a.pad = 0;
   hipLaunchKernelGGL(k_blame_dst, dim3(grid_for(n, 128, 8192)), dim3(128), 0, s, n, nbl, a,
-                     b.counts.p, p.in_ptr.p, p.e_src.p, p.e_flags.p, p.e_dmax.p, p.op_class.p,
-                     b.share.p, b.self_.p);
+                     counts, p.in_ptr.p, p.e_src.p, p.e_flags.p, p.e_dmax.p, p.op_class.p, share,
+                     self_);
   GPA_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_blame_src, dim3(grid_for(n, 128, 8192)), dim3(128), 0, s, n, nbl,
                      (uint32_t)p.arch.blamable, p.out_ptr, p.out_perm, p.e_flags.p,
-                     p.op_class.p, b.share.p, b.blamed.p, b.fine.p);
+                     p.op_class.p, share, blamed, fine);
   GPA_LAUNCH_CHECK();
 }
 

@@ -62,23 +62,41 @@ struct DBuf {
   }
 };
 
-// Per-call scratch: every block is returned to the pool when the arena is
-// destroyed, after the streams the call launched work on have finished (also
-// when the call fails part-way through).
+// Per-call scratch.  Pool mode: every block is returned to the pool when the
+// arena is destroyed, after the streams the call launched work on have
+// finished (also when the call fails part-way through).  Fixed mode: blocks
+// are carved, 256-byte aligned, from a caller-given device region of `cap`
+// bytes; nothing is allocated, synchronized or returned, and a request
+// beyond the region fails with GPA_E_UNSUPPORTED.
 struct Arena {
   std::vector<void *> blocks;
   std::vector<hipStream_t> streams;
+  char *fixed = nullptr;
+  size_t cap = 0, used = 0;
   explicit Arena(hipStream_t s) { streams.push_back(s); }
+  Arena(void *region, size_t bytes) : fixed(static_cast<char *>(region)), cap(bytes) {}
   Arena(const Arena &) = delete;
   Arena &operator=(const Arena &) = delete;
   void add_stream(hipStream_t s) { streams.push_back(s); }
   ~Arena() {
+    if (fixed) return;
     for (hipStream_t s : streams) (void)hipStreamSynchronize(s);
     for (void *b : blocks) dev_free(b);
   }
   template <typename T>
   T *get(size_t count) {
-    void *b = dev_alloc((count ? count : 1) * sizeof(T));
+    const size_t bytes = (count ? count : 1) * sizeof(T);
+    if (fixed) {
+      const size_t at = (used + 255) / 256 * 256;
+      if (at > cap || bytes > cap - at) {
+        set_error("scratch region of %zu bytes is too small (%zu more bytes needed)", cap,
+                  at + bytes - cap);
+        throw Error{GPA_E_UNSUPPORTED};
+      }
+      used = at + bytes;
+      return reinterpret_cast<T *>(fixed + at);
+    }
+    void *b = dev_alloc(bytes);
     blocks.push_back(b);
     return static_cast<T *>(b);
   }
@@ -211,9 +229,15 @@ void group_by_keys(const GroupSpec *spec, int n_groups, DBuf<uint32_t> &ptr,
 void group_by_key(const uint32_t *key, size_t n, uint32_t n_keys, DBuf<uint32_t> &ptr,
                   DBuf<uint32_t> &perm, hipStream_t s, Arena &ar);
 
-// hist.hip
+// hist.hip.  allow_partition = false keeps to the hot-set path (programs of
+// up to hist_hot_max_pcs() instructions; GPA_E_UNSUPPORTED beyond), which
+// issues no memset and no host synchronization.
 void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint32_t *counts,
-              unsigned long long *totals, hipStream_t s, Arena &ar);
+              unsigned long long *totals, hipStream_t s, Arena &ar, bool allow_partition = true);
+uint32_t hist_hot_max_pcs();
+// scratch bytes the hot-set path takes for n records of a program of n_instr
+// instructions (256-byte aligned blocks)
+size_t hist_hot_scratch_bytes(uint32_t n_instr, uint64_t n);
 
 // load.hip
 void validate_and_build_structure(gpa_program &p, hipStream_t s, Arena &ar);
@@ -260,8 +284,11 @@ void build_distances(gpa_program &p, hipStream_t s, Arena &ar, const DistTables 
 constexpr uint32_t kSmallSeg = 64;   // longest segment one thread sums alone
 constexpr uint32_t kSegChunk = 4096; // elements of a longer segment per workgroup
 void build_scope_targets(gpa_program &p, hipStream_t s, Arena &ar);
-// blame.hip
+// blame.hip: run_blame allocates the blame handle's tables and calls
+// launch_blame, which writes caller-given device arrays and allocates nothing
 void run_blame(const gpa_program &p, gpa_blame &b, hipStream_t s, Arena &ar);
+void launch_blame(const gpa_program &p, const uint32_t *counts, double *share, double *blamed,
+                  double *self_, double *fine, hipStream_t s);
 // estimate.hip
 void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint32_t k,
                   hipStream_t s, Arena &ar);

@@ -977,21 +977,46 @@ k_hot_finish(uint32_t n_instr, uint32_t n_cb, uint32_t G, uint32_t T,
 }
 
 // The hot-set path, for programs of at most kHotMaxPCs instructions.
+uint32_t hist_hot_max_pcs() { return kHotMaxPCs; }
+
+// the pass's workgroup ranges: kHotGrid at most, each a multiple of 128
+// records (even, so the 16-byte loads stay aligned; finer than a whole step,
+// so that the grid comes as close to kHotGrid as it can, a range's last step
+// being partial where it must)
+struct HotShape {
+  uint64_t per;
+  uint32_t G, T, n_cb;
+};
+static HotShape hot_shape(uint32_t n_instr, uint64_t n) {
+  HotShape h;
+  h.n_cb = (n_instr + kColdPCs - 1) / kColdPCs;
+  uint64_t per = (n + kHotGrid - 1) / kHotGrid;
+  h.per = (per + 2 * kWave - 1) / (2 * kWave) * (2 * kWave);
+  if (h.per == 0) h.per = 2 * kWave;
+  h.G = (uint32_t)((n + h.per - 1) / h.per);
+  h.T = (uint32_t)((h.per + kColdTile - 1) / kColdTile);   // tiles per workgroup
+  return h;
+}
+
+size_t hist_hot_scratch_bytes(uint32_t n_instr, uint64_t n) {
+  if (n == 0) return 0;
+  const HotShape h = hot_shape(n_instr, n);
+  auto blk = [](size_t bytes) { return (bytes + 255) / 256 * 256; };
+  return blk(4 * kHotT) + blk(4 * kHotH) + blk(4) + blk(4 * (size_t)h.G * kHotBins) +
+         2 * blk(4 * n) + blk(4 * (size_t)h.G * h.T * (h.n_cb + 1)) + blk(4 * (size_t)h.G) +
+         blk(sizeof(TileTotals) * (size_t)h.G);
+}
+
 static bool run_hist_hot(const gpa_program &p, const uint64_t *rec, uint64_t n, bool vec,
-                         uint32_t *counts, unsigned long long *totals, hipStream_t s, Arena &ar) {
+                         uint32_t *counts, unsigned long long *totals, hipStream_t s, Arena &ar,
+                         bool allow_partition) {
   const uint32_t n_instr = p.n_instr;
   if (n_instr > kHotMaxPCs) return false;
   const char *force = getenv("GPA_HIST_PARTITION");
-  if (force && force[0] == '1') return false;
-  const uint32_t n_cb = (n_instr + kColdPCs - 1) / kColdPCs;
-  // workgroup ranges: kHotGrid at most, each a multiple of 128 records (even,
-  // so the 16-byte loads stay aligned; finer than a whole step, so that the
-  // grid comes as close to kHotGrid as it can, a range's last step being
-  // partial where it must)
-  uint64_t per = (n + kHotGrid - 1) / kHotGrid;
-  per = (per + 2 * kWave - 1) / (2 * kWave) * (2 * kWave);
-  const uint32_t G = (uint32_t)((n + per - 1) / per);
-  const uint32_t T = (uint32_t)((per + kColdTile - 1) / kColdTile);   // tiles per workgroup
+  if (allow_partition && force && force[0] == '1') return false;
+  const HotShape hs = hot_shape(n_instr, n);
+  const uint32_t n_cb = hs.n_cb, G = hs.G, T = hs.T;
+  const uint64_t per = hs.per;
   const uint64_t run_stride = n > kSelSample ? (n - kSelRun) / (kSelSample / kSelRun - 1) : 0;
   uint32_t *hot_tab = ar.get<uint32_t>(kHotT);
   uint32_t *hot_pc = ar.get<uint32_t>(kHotH);
@@ -1030,7 +1055,7 @@ __global__ void k_hist_empty(uint32_t *counts, size_t nbins, unsigned long long 
 }
 
 void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint32_t *counts,
-              unsigned long long *totals, hipStream_t s, Arena &ar) {
+              unsigned long long *totals, hipStream_t s, Arena &ar, bool allow_partition) {
   const uint32_t n_instr = p.n_instr;
   const uint32_t n_buckets = (n_instr + kBucketPCs - 1) / kBucketPCs;
   if (n_buckets > kMaxBuckets)
@@ -1044,7 +1069,9 @@ void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint3
   if (n >= 0x40000000ull) fail(GPA_E_UNSUPPORTED, "fewer than 2^30 samples per call are supported");
   const uint64_t *rec = (const uint64_t *)samples;
   const bool vec = ((uintptr_t)samples % 16) == 0;
-  if (run_hist_hot(p, rec, n, vec, counts, totals, s, ar)) return;
+  if (run_hist_hot(p, rec, n, vec, counts, totals, s, ar, allow_partition)) return;
+  if (!allow_partition)
+    fail(GPA_E_UNSUPPORTED, "this path counts programs of up to %u instructions", kHotMaxPCs);
   const uint32_t n_tiles = (uint32_t)((n + kTile - 1) / kTile);
   // bucket regions from a sample of the records
   const uint64_t n_samp =
