@@ -1,27 +1,28 @@
 #!/usr/bin/env python3
-"""Throughput of the GPA hot path on one MI355X.
+"""Throughput of the GPA hot path on one MI355X: batched vs per-profile.
 
-One step is one pass of the whole path over one profile of the large
-single-kernel workload (60,000 instructions in 1,500 blocks, loop depth up to
-5, 255 registers + 7 predicates + 16 barriers, 20M PC-sample records with
-Zipf(1.2) PCs and a memory-dependency-heavy stall mix):
+The headline workload is the whole-application profile: 400 kernels with
+2M instructions in all (log-normal sizes, device functions with their own
+CFG, up to 12k function scopes) and 500M PC-sample records (4 GB) grouped by
+kernel.  Programs are loaded once (the static analysis: reaching
+definitions, edges, distances, target scopes; timed and reported apart), and
+one step is the analysis of every kernel's records:
 
-  load     gpa_load_program: validation, reaching definitions, def-use
-           edges, CFG distances, static pruning and target scopes (Sec. 4);
-  attribute gpa_attribute: sample histogram (Sec. 2.1) and blame with
-           apportioning (Sec. 4.2, Eq. 1);
-  advise   gpa_advise: scope roll-up, estimated speedups (Eqs. 2-5) and the
-           ranked top-k, copied to the host.
+  batched      gpa_attribute_batch + gpa_advise_batch over all 400 kernels
+               (each stage of the histogram, blamer and estimators one launch
+               for the whole batch);
+  per-profile  gpa_attribute + gpa_advise kernel by kernel (host loop).
 
-Inputs are resident in HBM before timing starts.  Three copies of the sample
-records (3 x 160 MB) are used in turn so that no step reads records another
-step left in the 256 MB last-level cache.  `value` is records per second of
-the whole step.  Kernel times come from the library's hipEvent pairs on the
-streams the kernels run on; `roofline` is for the kernel family that takes
-the most time per step, `roofline_hist` for the sample histogram, whose
-traffic field comes from the rocprofv3 counter summary under profiles/ when
-that summary was taken on the current source of the histogram kernels.  The CPU baseline is the oracle (test
-infrastructure) run on the same workload on the host cores.
+`value` is records per second of the batched step, records resident in HBM
+before timing starts.  Beside it, on the same GPU: the per-profile path on
+the same records, the 1,024-profile batch (config 2) both ways, and serving
+(2,000 resident programs, requests of 50k-5M records on a 200 req/s Poisson
+stream, admitted by a 64 GB budget): p50/p99 latency from submit to the
+top-k on the host, against the per-request plain path.  Kernel times come
+from the library's hipEvent pairs on the stream the phases run on;
+`roofline` is for the phase that takes the most time per batched step.  The
+CPU baseline is the oracle (test infrastructure) on a bounded sample of the
+same kernels on the host.
 """
 from __future__ import annotations
 
@@ -40,7 +41,14 @@ HBM_PEAK_GBS = 8000.0
 # 32-bit integer vector issue: 256 CUs x 64 lanes x 2.4 GHz, in Gops/s
 ALU_PEAK_GOPS = 256 * 64 * 2.4e9 / 1e9
 HIST_SOURCE = os.path.join(HERE, "paper_2009_04061_amd", "csrc", "hist.hip")
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "hist_large_traffic.json")
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "hist_batch_wholeapp_traffic.json")
+HIST_KERNELS = ("k_hot_select", "k_hot_pass", "k_hot_finish",
+                "k_hsample", "k_hregions", "k_partition", "k_hplan", "k_count", "k_merge",
+                "k_hoverflow")
+
+
+def log(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
 
 
 def _source_hash(path):
@@ -48,9 +56,10 @@ def _source_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic(n_launches_ref=None):
-    """HBM bytes per histogram pass from the committed counter summary, or
-    None when it is absent or was taken on another version of the kernels."""
+def _traffic():
+    """HBM bytes per batched histogram from the committed counter summary,
+    or None when it is absent or was taken on another version of the
+    kernels."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -61,15 +70,7 @@ def _traffic(n_launches_ref=None):
     return t.get("bytes_per_pass")
 
 
-# the hot-set path (programs up to 2^17 instructions, the large workload) and
-# the partition path beyond it
-HIST_KERNELS = ("k_hot_select", "k_hot_pass", "k_hot_finish",
-                "k_hsample", "k_hregions", "k_partition", "k_hplan", "k_count", "k_merge",
-                "k_hoverflow")
-
-
 def _counter_rows(d):
-    """Rows of the rocprofv3 counter CSV files under directory d."""
     import csv
     import glob
     rows = []
@@ -79,10 +80,11 @@ def _counter_rows(d):
     return rows
 
 
-def summarize_traffic(fetch_dir, write_dir, copy_mb, out_path):
-    """HBM bytes per histogram pass from two rocprofv3 --pmc runs (FETCH_SIZE,
-    then WRITE_SIZE, KiB per dispatch), each scaled by what the same counter
-    reads for the plain device copy of copy_mb MiB in the same run."""
+def summarize_traffic(fetch_dir, write_dir, copy_mb, out_path, steps):
+    """HBM bytes per batched histogram from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
+    same counter reads for the plain device copy of copy_mb MiB in the same
+    run; `steps` histogram passes ran in each (warm-up included)."""
     res = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = [r for r in _counter_rows(d) if r.get("Counter_Name") == counter]
@@ -100,16 +102,14 @@ def summarize_traffic(fetch_dir, write_dir, copy_mb, out_path):
                     per_kernel.setdefault(k, []).append(v)
         if not copy_vals:
             raise SystemExit(f"no copy kernel in the {counter} run")
-        copy_kib = max(copy_vals)   # the large calibration copy
+        copy_kib = max(copy_vals)
         factor = (copy_mb * 1024.0) / copy_kib
-        n_pass = max(len(v) for k, v in per_kernel.items()
-                     if k in ("k_hot_pass", "k_partition", "k_count"))
-        kib = sum(sum(v) for v in per_kernel.values()) / n_pass
+        kib = sum(sum(v) for v in per_kernel.values()) / steps
         res[counter] = {"kib_per_pass_raw": kib, "copy_kib_raw": copy_kib,
                         "scale": factor, "bytes_per_pass": kib * 1024.0 * factor,
-                        "per_kernel_kib_raw": {k: sum(v) / len(v) for k, v in per_kernel.items()}}
-    out = {"kernel": "gpa_hist (sample histogram pass)",
-           "workload": "large single kernel, 20M records",
+                        "per_kernel_kib_raw": {k: sum(v) / steps for k, v in per_kernel.items()}}
+    out = {"kernel": "gpa_hist batched (k_hot_select, k_hot_pass, k_hot_finish)",
+           "workload": "whole application: 400 kernels, 2M instructions, 500M records",
            "source_sha256_16": _source_hash(HIST_SOURCE),
            "bytes_per_pass": res["FETCH_SIZE"]["bytes_per_pass"] +
                              res["WRITE_SIZE"]["bytes_per_pass"],
@@ -119,38 +119,247 @@ def summarize_traffic(fetch_dir, write_dir, copy_mb, out_path):
     print(json.dumps(out, indent=1))
 
 
-def cpu_baseline(prog, rec, seconds):
-    """The oracle on the host: whole steps over the same workload until at
-    least `seconds` of CPU work has been done (at least one step)."""
+def _pct(values, q):
+    v = sorted(values)
+    return v[min(len(v) - 1, int(q * len(v)))]
+
+
+# ------------------------------------------------------------------ pieces
+def upload_records(torch, records, offsets, dev):
+    """All profiles' records in one device buffer, each profile starting on a
+    16-byte boundary; returns the per-profile byte views."""
+    import numpy as np
+    n = np.diff(offsets)
+    starts = np.zeros(len(n) + 1, np.int64)
+    starts[1:] = np.cumsum(n + (n & 1))
+    buf = torch.empty(int(starts[-1]) * 8, dtype=torch.uint8, device=dev)
+    raw = records.view(np.uint8)
+    chunk = 64 << 20
+    for k in range(len(n)):
+        a, b = int(offsets[k]) * 8, int(offsets[k + 1]) * 8
+        s = int(starts[k]) * 8
+        for c in range(a, b, chunk):
+            e = min(b, c + chunk)
+            buf[s + c - a:s + e - a].copy_(torch.from_numpy(raw[c:e]), non_blocking=False)
+    return buf, [buf[int(starts[k]) * 8:(int(starts[k]) + int(n[k])) * 8] for k in range(len(n))]
+
+
+def load_programs(gpa, progs, dev, stream):
+    t0 = time.perf_counter()
+    P = [gpa.Program(gpa.program_to_device(p, dev), stream=stream) for p in progs]
+    return P, time.perf_counter() - t0
+
+
+def batched_step(gpa, P, D, stream):
+    B = gpa.attribute_batch(P, D, stream=stream)
+    A = gpa.advise_batch(B, stream=stream)
+    for a in A:
+        a.close()
+    for b in B:
+        b.close()
+
+
+def per_profile_step(gpa, P, D, stream):
+    for p, d in zip(P, D):
+        b = p.attribute(d, stream=stream)
+        a = b.advise(stream=stream)
+        a.close()
+        b.close()
+
+
+def time_steps(torch, fn, steps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def run_batch_config(torch, gpa, cfg, steps, warmup, dev, stream, per_profile_steps=1):
+    from paper_2009_04061_amd import synth
+    t0 = time.perf_counter()
+    progs, records, offsets = synth.gen_batch(cfg)
+    log(f"config {cfg}: generated {len(progs)} profiles, {int(offsets[-1])} records in "
+        f"{time.perf_counter() - t0:.1f} s")
+    P, load_s = load_programs(gpa, progs, dev, stream)
+    torch.cuda.synchronize()
+    log(f"config {cfg}: loaded {len(P)} programs in {load_s:.2f} s")
+    buf, D = upload_records(torch, records, offsets, dev)
+    torch.cuda.synchronize()
+    n_rec = int(offsets[-1])
+    for _ in range(warmup):
+        batched_step(gpa, P, D, stream)
+    gpa.timing_enable(True)
+    gpa.timing_read(reset=True)
+    t_batch = time_steps(torch, lambda: batched_step(gpa, P, D, stream), steps)
+    ph = gpa.timing_read(reset=True)
+    gpa.timing_enable(False)
+    log(f"config {cfg}: batched step {1e3 * t_batch:.2f} ms")
+    per_profile_step(gpa, P, D, stream)   # warm-up of the plain path
+    t_plain = time_steps(torch, lambda: per_profile_step(gpa, P, D, stream), per_profile_steps)
+    log(f"config {cfg}: per-profile step {1e3 * t_plain:.2f} ms")
+    info = {"instructions": int(sum(len(p["op_class"]) for p in progs)),
+            "edges": int(sum(p.info["n_edges"] for p in P)),
+            "scopes": int(sum(p.info["n_scopes"] for p in P)),
+            "records": n_rec, "profiles": len(P)}
+    out = {"records": n_rec, "t_batch": t_batch, "t_plain": t_plain, "load_s": load_s,
+           "phases": {k: (ms / c if c else None) for k, (ms, c) in ph.items()}, "info": info}
+    return out, progs, records, offsets, P, buf, D
+
+
+def cpu_baseline(progs, records, offsets, seconds):
+    """The oracle on the host over whole kernels of the workload, in order,
+    until at least `seconds` of CPU work is done."""
     from oracle import oracle
     oracle.build(force=False)
-    times = []
-    out = None
     t_all = time.perf_counter()
-    while True:
-        t0 = time.perf_counter()
-        out = oracle.run_all(prog, rec, 5)
-        times.append(time.perf_counter() - t0)
+    n_done = 0
+    k = 0
+    while k < len(progs):
+        oracle.run_all(progs[k], records[offsets[k]:offsets[k + 1]], 5)
+        n_done += int(offsets[k + 1] - offsets[k])
+        k += 1
         if time.perf_counter() - t_all >= seconds:
             break
-    med = statistics.median(times)
-    n = len(rec)
-    return {"value": n / med, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"the whole large workload ({n} records, {len(prog['op_class'])} "
-                      f"instructions), {len(times)} single-thread oracle steps, median "
-                      f"{med:.3f} s"}, out
+    el = time.perf_counter() - t_all
+    return {"value": n_done / el, "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {k} of the {len(progs)} kernels of the whole-application "
+                      f"workload ({n_done} records), single-thread oracle (count, sources, "
+                      f"distances, blame, estimates, top-5 per kernel), {el:.1f} s"}
+
+
+def serving(torch, gpa, dev, seconds, rate, budget, seed=4, n_programs=2000, pool=256):
+    """Config 4: requests on a Poisson stream against resident programs."""
+    import numpy as np
+    from paper_2009_04061_amd import synth
+    specs = synth.serving_specs(seed, n_programs)
+    t0 = time.perf_counter()
+    progs, _, _ = synth.gen_batch(4, specs=specs)
+    log(f"serving: generated {len(progs)} programs in {time.perf_counter() - t0:.1f} s")
+    P, load_s = load_programs(gpa, progs, dev, None)
+    torch.cuda.synchronize()
+    log(f"serving: loaded {len(P)} programs in {load_s:.2f} s")
+    arrive, prog_of, n_of = synth.serving_requests(seed, n_programs, rate, seconds)
+    # the request records: a pool of distinct (program, records) requests in
+    # pinned host memory, drawn on the GPU, used in turn by the stream
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    reqs = []
+    for r in range(min(pool, len(arrive))):
+        p = int(prog_of[r])
+        n = int(n_of[r])
+        d = synth.gen_samples_device(n, len(progs[p]["op_class"]), specs[p]["zipf"],
+                                     specs[p]["stall_mix"], g, device=dev)
+        reqs.append((p, d.cpu().pin_memory()))
+    torch.cuda.synchronize()
+    log(f"serving: {len(reqs)} request buffers, {len(arrive)} arrivals over {seconds} s")
+
+    def open_loop():
+        sv = gpa.Server(budget)
+        lat, pend = [], {}
+        n_rec = 0
+        t_start = time.perf_counter()
+        i = 0
+        while i < len(arrive) or pend:
+            now = time.perf_counter() - t_start
+            while i < len(arrive) and arrive[i] <= now:
+                p, rec = reqs[i % len(reqs)]
+                t = sv.submit(P[p], rec)
+                pend[t] = (time.perf_counter(), rec.numel() // 8)
+                i += 1
+            for t in list(pend):
+                res = sv.poll(t)
+                if res is None:
+                    continue
+                A, _ = res
+                A.topk(5)
+                t_sub, n = pend.pop(t)
+                lat.append(time.perf_counter() - t_sub)
+                n_rec += n
+                A.close()
+            time.sleep(0.0001)
+        el = time.perf_counter() - t_start
+        st = sv.stats()
+        sv.close()
+        return lat, n_rec, el, st
+
+    def saturated(count):
+        sv = gpa.Server(budget)
+        t0 = time.perf_counter()
+        ts = [sv.submit(P[reqs[k % len(reqs)][0]], reqs[k % len(reqs)][1]) for k in range(count)]
+        n_rec = sum(reqs[k % len(reqs)][1].numel() // 8 for k in range(count))
+        left = set(ts)
+        while left:
+            for t in list(left):
+                res = sv.poll(t)
+                if res is not None:
+                    res[0].topk(5)
+                    res[0].close()
+                    left.discard(t)
+            time.sleep(0.0001)
+        el = time.perf_counter() - t0
+        st = sv.stats()
+        sv.close()
+        return n_rec / el, st
+
+    def plain(count):
+        lat = []
+        n_rec = 0
+        t0 = time.perf_counter()
+        for k in range(count):
+            p, rec = reqs[k % len(reqs)]
+            t1 = time.perf_counter()
+            B = P[p].attribute(rec)
+            A = B.advise()
+            A.topk(5)
+            lat.append(time.perf_counter() - t1)
+            n_rec += rec.numel() // 8
+            A.close()
+            B.close()
+        return lat, n_rec / (time.perf_counter() - t0)
+
+    saturated(min(64, len(reqs)))   # warm-up (autotuner buckets, code, pool)
+    plain(8)
+    lat, n_rec, el, st = open_loop()
+    log(f"serving: open loop {len(lat)} requests, p50 {1e3 * _pct(lat, 0.5):.2f} ms, "
+        f"p99 {1e3 * _pct(lat, 0.99):.2f} ms")
+    sat_rate, sat_st = saturated(len(reqs))
+    plat, prate = plain(len(reqs))
+    log(f"serving: saturated {sat_rate:.3g} rec/s, plain {prate:.3g} rec/s")
+    for p in P:
+        p.close()
+    return {
+        "workload": f"{n_programs} resident programs (whole-application size law), Poisson "
+                    f"{rate:g} req/s for {seconds:g} s, 50k-5M records log-uniform, budget "
+                    f"{budget >> 30} GiB; request records from {len(reqs)} distinct "
+                    f"(program, records) buffers in pinned host memory",
+        "requests": len(lat), "programs_load_s": round(load_s, 3),
+        "latency_ms": {"p50": round(1e3 * _pct(lat, 0.5), 3), "p99": round(1e3 * _pct(lat, 0.99), 3),
+                       "max": round(1e3 * max(lat), 3)},
+        "offered_samples_per_s": round(n_rec / el, 1),
+        "saturated_samples_per_s": round(sat_rate, 1),
+        "batches": st["batches"], "max_batch": st["max_batch"],
+        "peak_reserved_bytes": st["peak_reserved"],
+        "plain_path": {"latency_ms": {"p50": round(1e3 * _pct(plat, 0.5), 3),
+                                      "p99": round(1e3 * _pct(plat, 0.99), 3)},
+                       "samples_per_s": round(prate, 1)},
+    }
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="minimum CPU time spent on the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-check", action="store_true",
-                    help="skip the comparison of one step with the oracle")
+    ap.add_argument("--no-config2", action="store_true", help="skip the 1,024-profile batch")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-budget-gib", type=int, default=64)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed steps, run a plain device copy of this many MiB "
                          "(calibrates the HBM byte counters of a profiling run)")
@@ -161,82 +370,27 @@ def main():
 
     if args.traffic_summary:
         summarize_traffic(args.traffic_summary[0], args.traffic_summary[1],
-                          args.copy_mb or 512, TRAFFIC_FILE)
+                          args.copy_mb or 512, TRAFFIC_FILE, args.steps + args.warmup)
         return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the path has no multi-GPU code: one profile is processed by one GPU)",
-              file=sys.stderr)
+              "(nothing in this path uses a second GPU; see the design notes for how it "
+              "would shard)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2009_04061_amd import gpa, synth
+    from paper_2009_04061_amd import gpa
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     gpa.lib()   # fails loudly when the library is not built
-
-    t0 = time.perf_counter()
-    prog, rec = synth.workload_large(seed=1)
-    gen_s = time.perf_counter() - t0
-    n_rec = len(rec)
-    n_instr = len(prog["op_class"])
-    print(f"# workload generated in {gen_s:.1f} s: {n_instr} instructions, {n_rec} records",
-          file=sys.stderr, flush=True)
-
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
-    dprog = gpa.program_to_device(prog, dev)
-    raw = np.ascontiguousarray(rec).view(np.uint8)
-    copies = [torch.from_numpy(raw).to(dev) for _ in range(3)]
-    torch.cuda.synchronize()
 
-    def step(k):
-        with torch.cuda.stream(stream):
-            P = gpa.Program(dprog, stream=stream)
-            B = P.attribute(copies[k % len(copies)], stream=stream)
-            A = B.advise(stream=stream)
-            top = A.topk(5)
-        return P, B, A, top
-
-    lat_adv = []
-    for k in range(args.warmup):
-        P, B, A, _ = step(k)
-        A.close(); B.close(); P.close()
-    torch.cuda.synchronize()
-
-    gpa.timing_enable(True)
-    gpa.timing_read(reset=True)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        P, B, A, _ = step(k)
-        A.close(); B.close(); P.close()
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
-    ph = gpa.timing_read(reset=True)
-    gpa.timing_enable(False)
-
-    # a program kept resident: attribute + advise per profile, and the advise
-    # latency (host clock, from the call to the top-k on the host)
-    P = gpa.Program(dprog, stream=stream)
-    info = dict(P.info)
-    lat_resident = []
-    for k in range(args.steps):
-        t_0 = time.perf_counter()
-        B = P.attribute(copies[k % len(copies)], stream=stream)
-        t_a = time.perf_counter()
-        A = B.advise(stream=stream)
-        A.topk(5)
-        t_1 = time.perf_counter()
-        lat_adv.append(t_1 - t_a)
-        lat_resident.append(t_1 - t_0)
-        A.close(); B.close()
-    P.close()
-
+    c3, progs, records, offsets, P, buf, D = run_batch_config(torch, gpa, 3, args.steps,
+                                                              args.warmup, dev, stream)
     if args.copy_mb:
         a = torch.empty(args.copy_mb << 20, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
@@ -244,84 +398,80 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    n_rec = c3["records"]
+    info = c3["info"]
+    ph = c3["phases"]
+    for p in P:
+        p.close()
+    del buf, D, P
 
-    ms_step = 1e3 * t_total / args.steps
-    value = n_rec * args.steps / t_total
-
-    phase_ms = {name: (ms / c if c else None) for name, (ms, c) in ph.items()}
-    rooflines = {}
-    n_edges, n_scopes, n_blocks = info["n_edges"], info["n_scopes"], info["n_blocks"]
-    n_succ = int(len(prog["succ"]))
-    # walk-table relaxations: every source block against every sweep entry of
-    # its function (one per predecessor edge, one per block without any),
-    # once for shortest and once for longest walks
-    fbb = np.asarray(prog["func_block_begin"], np.int64)
-    n_pred = np.bincount(np.asarray(prog["succ"], np.int64), minlength=n_blocks)
-    ent_per_block = np.maximum(n_pred, 1)
-    ent_cum = np.concatenate([[0], np.cumsum(ent_per_block)])
-    relax = 0
-    for f in range(len(fbb) - 1):
-        nb_f = int(fbb[f + 1] - fbb[f])
-        relax += 2 * nb_f * int(ent_cum[fbb[f + 1]] - ent_cum[fbb[f]])
-    # per-unit algorithmic work of each kernel family
+    # per-unit algorithmic work of each batched phase (design notes, sec. 7)
     work = {
-        "hist": ("hbm", 8.0 * n_rec + 96.0 * n_instr,
-                 "gpa_hist: sample histogram (k_hot_select, k_hot_pass, k_hot_finish)"),
-        "blame": ("hbm", 60.0 * n_edges + 288.0 * n_instr, "gpa_blame: k_blame_dst + k_blame_src"),
-        "advise": ("hbm", 72.0 * n_scopes + 88.0 * n_instr + 8.0 * n_edges,
-                   "gpa_estimate: contributions, scope sums, speedups, top-k"),
-        "rd_search": ("hbm", 30.0 * n_instr, "gpa_dataflow: per-use backward searches"),
-        "dfs": ("alu", float(n_blocks + n_succ), "CFG depth-first order (k_dfs)"),
-        "dist": ("alu", float(relax) / 2,
-                 "shortest-walk tables (k_dist_tables, block order): source blocks x sweep entries"),
-        "dist_long": ("alu", float(relax) / 2,
-                      "longest G' walk tables (k_dist_tables, DFS order): source blocks x sweep "
-                      "entries"),
+        "hist": ("hbm", 8.0 * n_rec + 96.0 * info["instructions"],
+                 "gpa_hist batched: k_hot_select, k_hot_pass, k_hot_finish"),
+        "blame": ("hbm", 60.0 * info["edges"] + 288.0 * info["instructions"],
+                  "gpa_blame batched: k_blame_dst + k_blame_src"),
+        "advise": ("hbm", 72.0 * info["scopes"] + 88.0 * info["instructions"] + 8.0 * info["edges"],
+                   "gpa_estimate batched: contributions, scope sums, speedups, top-k"),
     }
+    rooflines = {}
     for name, (bound, amount, label) in work.items():
-        t = phase_ms.get(name)
+        t = ph.get(name)
         if not t:
             continue
-        if bound == "hbm":
-            achieved, peak, unit = amount / (t * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s"
-        else:
-            achieved, peak, unit = amount / (t * 1e-3) / 1e9, ALU_PEAK_GOPS, "Gops/s"
-        rooflines[name] = {"bound": bound, "kernel": label,
-                           "achieved": float(f"{achieved:.6g}"),
-                           "peak": peak, "unit": unit, "frac": float(f"{achieved / peak:.6g}"),
+        achieved = amount / (t * 1e-3) / 1e9
+        rooflines[name] = {"bound": bound, "kernel": label, "achieved": float(f"{achieved:.6g}"),
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": float(f"{achieved / HBM_PEAK_GBS:.6g}"),
                            "traffic": _traffic() if name == "hist" else None,
                            "algorithmic": amount, "avg_ms": round(t, 5)}
     dominant = max(rooflines, key=lambda k: rooflines[k]["avg_ms"])
-    roofline = dict(rooflines[dominant], name=dominant)
-    roofline_hist = rooflines["hist"]
 
-    checked = None
+    c2 = None
+    if not args.no_config2:
+        r2, *_ = run_batch_config(torch, gpa, 2, max(2, args.steps // 2), 1, dev, stream)
+        c2 = {"workload": "1,024 kernel profiles: instructions log-normal (median 3k, 200-60k), "
+                          "records log-normal (median 200k, 10k-10M), Dirichlet mixes, seed 2",
+              "records": r2["records"], "instructions": r2["info"]["instructions"],
+              "batched_samples_per_s": round(r2["records"] / r2["t_batch"], 1),
+              "per_profile_samples_per_s": round(r2["records"] / r2["t_plain"], 1),
+              "batched_ms_per_step": round(1e3 * r2["t_batch"], 3),
+              "per_profile_ms_per_step": round(1e3 * r2["t_plain"], 3),
+              "speedup": round(r2["t_plain"] / r2["t_batch"], 2),
+              "programs_load_s": round(r2["load_s"], 3)}
+
+    serve = None
+    if not args.no_serving:
+        serve = serving(torch, gpa, dev, args.serve_seconds, args.serve_rate,
+                        args.serve_budget_gib << 30)
+
     base = None
     if not args.no_cpu_baseline:
-        base, oracle_out = cpu_baseline(prog, rec, args.cpu_seconds)
-        if not args.no_check:
-            sys.path.insert(0, os.path.join(HERE, "tests"))
-            from parity import compare, run_gpu   # noqa: E402
-            g = run_gpu(prog, rec, device_inputs=True, k=5)
-            compare(prog, g, oracle_out, k=5)
-            checked = True
+        base = cpu_baseline(progs, records, offsets, args.cpu_seconds)
 
-    a_sorted = sorted(lat_adv)
-    p = lambda q: 1e3 * a_sorted[min(len(a_sorted) - 1, int(q * len(a_sorted)))]
+    value = n_rec / c3["t_batch"]
     line = {
         "metric": "PC samples blamed/s, batched vs per-profile (oracle-exact); p99 advise latency",
         "value": round(value, 1), "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u32+f64", "data": "synthetic",
-        "config": {"workload": "large single kernel: 60k instructions, 1.5k blocks, loop depth "
-                               "<= 5, 255 R + 7 P + 16 B, 20M records, Zipf 1.2, seed 1",
-                   "records": n_rec, "instructions": n_instr, "path": "per-profile"},
-        "phase_ms": {k: (round(v, 4) if v is not None else None) for k, v in phase_ms.items()},
-        "advise_latency_ms": {"p50": round(p(0.5), 4), "p99": round(p(0.99), 4)},
-        "samples_per_s_resident_program": round(n_rec / statistics.median(lat_resident), 1),
-        "oracle_exact": checked,
-        "roofline": roofline,
-        "roofline_hist": roofline_hist,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * c3["t_batch"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32+f64",
+        "data": "synthetic",
+        "config": {"workload": "whole application: 400 kernels, 2M instructions (log-normal "
+                               "sizes), <= 12k function scopes, 500M records (4 GB) grouped by "
+                               "kernel, Zipf 1.1, Dirichlet mixes, seed 3",
+                   "records": n_rec, "instructions": info["instructions"],
+                   "profiles": info["profiles"], "path": "batched, programs resident"},
+        "per_profile_samples_per_s": round(n_rec / c3["t_plain"], 1),
+        "per_profile_ms_per_step": round(1e3 * c3["t_plain"], 3),
+        "batched_vs_per_profile": round(c3["t_plain"] / c3["t_batch"], 2),
+        "programs_load_s": round(c3["load_s"], 3),
+        "samples_per_s_including_load": round(n_rec / (c3["t_batch"] + c3["load_s"]), 1),
+        "phase_ms": {k: (round(v, 4) if v is not None else None) for k, v in ph.items()
+                     if v is not None},
+        "roofline": dict(rooflines[dominant], name=dominant),
+        "roofline_hist": rooflines.get("hist"),
+        "config2": c2,
+        "serving": serve,
         "cpu_baseline": base,
     }
     print(json.dumps(line), flush=True)

@@ -43,7 +43,8 @@ typedef int32_t gpa_status;
 #define GPA_E_INVALID (-1)      /* malformed argument or descriptor */
 #define GPA_E_NOMEM (-2)        /* device or host allocation failed */
 #define GPA_E_DEVICE (-3)       /* a HIP runtime call failed */
-#define GPA_E_STATE (-4)        /* handle used with a mismatching program */
+#define GPA_E_STATE (-4)        /* handle used with a mismatching program, or a server shutting down */
+#define GPA_E_BUSY (-5)         /* a served request is still waiting or running */
 #define GPA_E_UNSUPPORTED (-6)  /* input beyond the limits documented below */
 
 /* ---------------------------------------------------------------------
@@ -216,6 +217,135 @@ gpa_status gpa_advice_get(const gpa_advice *a, double *active, double *matched, 
 gpa_status gpa_advice_topk(const gpa_advice *a, uint32_t k, uint32_t *opt, uint32_t *scope,
                            double *speedup);
 
+/* The advice report (Sec. 3: raw advice as ASCII text; Sec. 7: hotspots as
+ * def and use locations with their distance; Sec. 6: single dependency
+ * coverage).
+ * gpa_program_coverage: the instructions that are single-dependency nodes
+ *   (no use site with two or more sources) before pruning (every reaching
+ *   definition) and after it (sources that survive the dominator rule for
+ *   that use and the latency rule for their edge).
+ * gpa_blame_hotspots: for optimizer `opt` (GPA_O_*) and the kernel root
+ *   with index root_index, the k largest carriers of its matched samples:
+ *   edges (src = def, dst = use, their shortest and longest distance) for
+ *   the blamed-stall and edge optimizers, instructions (src = GPA_NONE, dst
+ *   = the instruction, distances 0) for the others; samples descending,
+ *   ties by src then dst.  *n_out = the number written (<= k).
+ * gpa_report: the whole report as text: coverage, then per kernel its
+ *   optimizers with estimated speedup above 1, best first (at most
+ *   top_optimizers), each with up to `hotspots` hotspots.  *len is the
+ *   buffer size on entry and the size needed (with the final NUL) on
+ *   return; buf may be NULL to ask for the size. */
+typedef struct {
+  uint32_t src, dst, dmin, dmax;
+  double samples;
+} gpa_hotspot;
+gpa_status gpa_program_coverage(const gpa_program *p, uint64_t *single_before,
+                                uint64_t *single_after);
+gpa_status gpa_blame_hotspots(const gpa_blame *b, uint32_t root_index, uint32_t opt, uint32_t k,
+                              gpa_hotspot *out, uint32_t *n_out);
+gpa_status gpa_report(const gpa_advice *a, const gpa_blame *b, uint32_t top_optimizers,
+                      uint32_t hotspots, char *buf, size_t *len);
+
+/* The parallel optimizers of Table 2 and their estimate (Sec. 5.2, Eqs.
+ * (6)-(10)): Block Increase (matched when the grid has fewer blocks than the
+ * device has SMs / CUs) and Thread Increase (matched when the per-SM block
+ * cap, not warps, registers or shared memory, limits residency).  For the
+ * kernel root with index root_index in gpa_program_roots order, from its
+ * samples in `b`, the launch and the device description:
+ *   W     = resident blocks per SM x warps per block / schedulers per SM;
+ *   R_I   = issued samples / all samples of the kernel;
+ *   I     = 1 - (1 - R_I)^W, I_new likewise with W_new    (Eqs. (8), (9));
+ *   C_W   = W_new / W, C_I = I_new / I                     (Eqs. (6), (7));
+ *   S     = C_I / C_W x f                                  (Eq. (10)).
+ * Block Increase: W_new = W x blocks / SMs (the threads spread over one block
+ * per SM); f = 1, or T / (T - pipeline busy - memory throttle - not selected
+ * samples) once W_new < 1.  Thread Increase: W_new = the warps an SM holds
+ * once larger blocks lift the block cap (warp cap, registers, shared
+ * memory, and the grid's warps per SM), over the schedulers; f = C_W, so
+ * S = C_I.  (The paper leaves f and the new configurations open: these are
+ * this library's readings.)  out[0] is Block Increase, out[1] Thread
+ * Increase; speedup = 1 when not matched or when the kernel has no issued
+ * sample.  GPA_E_INVALID for a zero field or threads_per_block above the
+ * device's maximum. */
+typedef struct {
+  uint32_t blocks, threads_per_block;
+  uint32_t regs_per_thread;    /* 32-bit registers per thread; 0 = not limiting */
+  uint32_t shared_per_block;   /* bytes; 0 = not limiting */
+} gpa_launch;
+typedef struct {
+  uint32_t n_sm, schedulers_per_sm, warp_size;
+  uint32_t max_warps_per_sm, max_blocks_per_sm, max_threads_per_block;
+  uint32_t regs_per_sm, shared_per_sm;   /* 32-bit registers; bytes */
+} gpa_device;
+typedef struct {
+  uint32_t matched, pad;
+  double W, W_new, R_I, I, I_new, C_W, C_I, f, speedup;
+} gpa_parallel_estimate;
+gpa_status gpa_parallel_advise(const gpa_blame *b, uint32_t root_index, const gpa_launch *launch,
+                               const gpa_device *device, gpa_parallel_estimate *out);
+
+/* Batching (Sec. 3: every kernel launch context is analyzed on its own, so
+ * many of them can share each device step).  gpa_attribute_batch does for
+ * each entry k what gpa_attribute(progs[k], samples[k], n[k], ...) does,
+ * with one launch of each histogram and blame kernel for the whole batch
+ * (every workgroup takes one entry's share from a device work list), and
+ * returns one blame handle per entry in out[k].  A program may appear in
+ * several entries.  The results are bit for bit those of gpa_attribute.
+ * Entries whose program has more than 2^17 instructions, or whose device
+ * records are not 16-byte aligned, are counted by gpa_attribute's own path
+ * inside the same call.  The records per histogram workgroup are picked by
+ * an autotuner per batch shape (see GPA_BATCH_PER / GPA_AUTOTUNE in the
+ * library's notes).  On failure no handle is returned (all out[k] NULL). */
+gpa_status gpa_attribute_batch(gpa_program *const *progs, const gpa_sample *const *samples,
+                               const uint64_t *n, uint32_t count, int samples_on_device,
+                               void *stream, gpa_blame **out);
+/* gpa_advise for every blame handle of the batch, each estimate stage one
+ * launch over all of them; out[k] as gpa_advise(blames[k]) would return,
+ * bit for bit. */
+gpa_status gpa_advise_batch(const gpa_blame *const *blames, uint32_t count, void *stream,
+                            gpa_advice **out);
+
+/* Serving (Sec. 3: analysis per kernel launch context, so requests against
+ * resident programs are independent).  A server admits submitted requests
+ * in arrival order as long as the device bytes they need (records staged
+ * from the host, histogram scratch, blame and advice tables; an upper
+ * estimate) fit in its budget together with the requests still running,
+ * and runs what has been admitted in batches through the batched kernels of
+ * gpa_attribute_batch / gpa_advise_batch, on two streams of its own so that
+ * consecutive batches overlap on the device; requests that arrive while
+ * others run join the next batch.  A request's results are bit for bit
+ * those of gpa_attribute + gpa_advise on the same records.
+ *
+ * gpa_server_create: budget_bytes > 0; a worker thread is started; the
+ *   server belongs to the device current at creation.
+ * gpa_server_submit: enqueues one request (never blocks on the GPU).  The
+ *   program must be loaded; the server holds a reference to it until the
+ *   request completes.  `samples` (host, or device when samples_on_device)
+ *   is borrowed until the request completes (its ticket polls done or
+ *   failed).  GPA_E_NOMEM, with nothing enqueued, when the request alone
+ *   needs more than the budget; GPA_E_STATE while the server shuts down.
+ * gpa_server_poll: GPA_E_BUSY while the request waits or runs; then once
+ *   GPA_OK with the request's advice (and, when blame is not NULL, its
+ *   blame handle; otherwise the blame is freed), or the request's failure
+ *   status with its message in gpa_last_error; the ticket is forgotten
+ *   after that.  GPA_E_INVALID for an unknown ticket.
+ * gpa_server_free: waits for every submitted request to finish, frees the
+ *   results nobody polled and stops the worker. */
+typedef struct gpa_server gpa_server;
+typedef struct {
+  uint64_t submitted, admitted, completed, failed;
+  uint64_t batches, max_batch;      /* batches launched, most requests in one */
+  uint64_t peak_reserved, reserved, budget;   /* admitted bytes: peak, now; the budget */
+  uint64_t queued, inflight_batches;          /* now */
+} gpa_server_stats;
+gpa_status gpa_server_create(uint64_t budget_bytes, gpa_server **out);
+gpa_status gpa_server_submit(gpa_server *server, gpa_program *p, const gpa_sample *samples,
+                             uint64_t n, int samples_on_device, uint64_t *ticket);
+gpa_status gpa_server_poll(gpa_server *server, uint64_t ticket, gpa_blame **blame,
+                           gpa_advice **advice);
+gpa_status gpa_server_stats_get(gpa_server *server, gpa_server_stats *stats);
+void gpa_server_free(gpa_server *server);
+
 /* Instrumentation (for benchmarks and profiling tools).  When enabled, the
  * library records a hipEvent pair around each phase on the stream the phase
  * runs on (the caller's, or for phases 5, 6 and 12 one of the library's two
@@ -231,6 +361,13 @@ gpa_status gpa_advice_topk(const gpa_advice *a, uint32_t k, uint32_t *opt, uint3
  * may be NULL), optionally resets them, and returns the number of phases. */
 void gpa_timing_enable(int on);
 uint32_t gpa_timing_read(double *ms, uint64_t *calls, uint32_t max_phases, int reset);
+
+/* The library's device memory on the current device: bytes handed out to
+ * live handles and scratch (in_use) and bytes cached for reuse (cached).
+ * Either pointer may be NULL. */
+gpa_status gpa_pool_stats(uint64_t *in_use, uint64_t *cached);
+/* Return the current device's cached blocks to the HIP runtime. */
+gpa_status gpa_pool_trim(void);
 
 /* Thread-local description of the last failure on this thread. */
 const char *gpa_last_error(void);

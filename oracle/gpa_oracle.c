@@ -869,3 +869,211 @@ void orc_estimate(const orc_analysis *a, const uint32_t *C, const double *share,
   free(buf);
 #undef CNT
 }
+
+/* ------------------------------------------------- parallel optimizers */
+/* Sec. 5.2, Eqs. (6)-(10), with the readings the library documents for
+ * the new configurations and the factor f (the paper leaves them open).
+ * launch = {blocks, threads per block, registers per thread (0: none),
+ * shared bytes per block (0: none)}; device = {SMs, schedulers per SM,
+ * warp size, max warps per SM, max blocks per SM, max threads per block,
+ * registers per SM, shared bytes per SM}.  out[11*o + k] for o = 0 (Block
+ * Increase), 1 (Thread Increase): k = 0 matched, 1 W, 2 W_new, 3 R_I, 4 I,
+ * 5 I_new, 6 C_W, 7 C_I, 8 f, 9 speedup, 10 unused. */
+static double orc_issue(double r, double w) { return 1.0 - pow(1.0 - r, w); }
+
+void orc_parallel(const orc_analysis *a, const uint32_t *C, uint32_t root, const uint32_t *launch,
+                  const uint32_t *device, double *out) {
+  const orc_prog *p = &a->c->p;
+  double T = 0.0, issued = 0.0, contention = 0.0;
+  for (uint32_t j = 0; j < p->n_instr; ++j) {
+    if (root_of_scope(p, p->instr_scope[j]) != root) continue;
+    for (uint32_t r = 0; r < 12; ++r) {
+      double v = (double)C[((size_t)j * 12 + r) * 2] + (double)C[((size_t)j * 12 + r) * 2 + 1];
+      T += v;
+      if (r == ORC_SELECTED) issued += v;
+      if (r == ORC_PIPE_BUSY || r == ORC_MEM_THROTTLE || r == ORC_NOT_SELECTED) contention += v;
+    }
+  }
+  uint32_t blocks = launch[0], threads = launch[1], regs = launch[2], shared = launch[3];
+  uint32_t sms = device[0], sched = device[1], warp = device[2], max_warps = device[3];
+  uint32_t max_blocks = device[4], regs_sm = device[6], shared_sm = device[7];
+  /* occupancy: the smallest of the per-SM limits, and of the grid's share */
+  uint32_t wpb = (threads + warp - 1) / warp;
+  uint64_t lim_blocks = max_blocks;
+  uint64_t lim_warps = max_warps / wpb;
+  uint64_t lim_regs = regs ? regs_sm / ((uint64_t)regs * warp * wpb) : UINT64_MAX;
+  uint64_t lim_shared = shared ? shared_sm / shared : UINT64_MAX;
+  uint64_t per_sm = lim_blocks;
+  if (lim_warps < per_sm) per_sm = lim_warps;
+  if (lim_regs < per_sm) per_sm = lim_regs;
+  if (lim_shared < per_sm) per_sm = lim_shared;
+  uint64_t grid_share = ((uint64_t)blocks + sms - 1) / sms;
+  uint64_t resident = per_sm < grid_share ? per_sm : grid_share;
+  double W = (double)resident * wpb / sched;
+  double R = T > 0.0 ? issued / T : 0.0;
+  for (int o = 0; o < 2; ++o) {
+    double *e = out + 11 * o;
+    int matched;
+    double W_new, f;
+    if (o == 0) {
+      /* Block Increase: fewer blocks than SMs; spread over one per SM */
+      matched = blocks < sms;
+      W_new = matched ? W * (double)blocks / sms : W;
+      f = (matched && W_new < 1.0 && T > contention) ? T / (T - contention) : 1.0;
+    } else {
+      /* Thread Increase: the block cap is the binding limit and leaves warps */
+      uint64_t other = lim_warps;
+      if (lim_regs < other) other = lim_regs;
+      if (lim_shared < other) other = lim_shared;
+      uint64_t warps_now = resident * wpb;
+      matched = lim_blocks < other && resident == lim_blocks && warps_now < max_warps;
+      W_new = W;
+      if (matched) {
+        uint64_t hold = max_warps;
+        if (regs && regs_sm / ((uint64_t)regs * warp) < hold) hold = regs_sm / ((uint64_t)regs * warp);
+        if (shared && (uint64_t)shared_sm * wpb / shared < hold) hold = (uint64_t)shared_sm * wpb / shared;
+        uint64_t grid_warps = ((uint64_t)blocks * wpb + sms - 1) / sms;
+        if (grid_warps < hold) hold = grid_warps;
+        if (hold < warps_now) hold = warps_now;
+        W_new = (double)hold / sched;
+      }
+      f = W > 0.0 ? W_new / W : 1.0;
+    }
+    double I = orc_issue(R, W), I_new = orc_issue(R, W_new);
+    double C_W = W > 0.0 ? W_new / W : 1.0;      /* Eq. (6) */
+    double C_I = I > 0.0 ? I_new / I : 1.0;      /* Eq. (7) */
+    e[0] = matched;
+    e[1] = W;
+    e[2] = W_new;
+    e[3] = R;
+    e[4] = I;
+    e[5] = I_new;
+    e[6] = C_W;
+    e[7] = C_I;
+    e[8] = f;
+    e[9] = (matched && T > 0.0 && I > 0.0 && C_W > 0.0) ? (1.0 / C_W) * C_I * f : 1.0;  /* Eq. (10) */
+    e[10] = 0.0;
+  }
+}
+
+/* -------------------------------------------------------------- report */
+/* Single dependency coverage (Sec. 6): an instruction is a single
+ * dependency node when no use site of it has two or more sources; before
+ * pruning all its reaching definitions count, after pruning only those that
+ * survive the dominator rule for that use and the latency rule for their
+ * edge (the opcode rule depends on the stall reason and is left out). */
+void orc_coverage(const orc_analysis *a, uint64_t *before, uint64_t *after) {
+  const orc_prog *p = &a->c->p;
+  uint64_t nb = 0, na = 0;
+  for (uint32_t j = 0; j < p->n_instr; ++j) {
+    int single_before = 1, single_after = 1;
+    for (uint32_t u = p->use_ptr[j]; u < p->use_ptr[j + 1]; ++u) {
+      uint32_t all = a->rd_ptr[u + 1] - a->rd_ptr[u], kept = 0;
+      for (uint32_t q = a->rd_ptr[u]; q < a->rd_ptr[u + 1]; ++q) {
+        if (!a->rd_blk[q]) continue;
+        for (uint32_t e = a->in_ptr[j]; e < a->in_ptr[j + 1]; ++e)
+          if (a->e_src[e] == a->rd_src[q] && (a->e_flags[e] & ORC_E_LAT_KEEP)) ++kept;
+      }
+      if (all > 1) single_before = 0;
+      if (kept > 1) single_after = 0;
+    }
+    nb += (uint64_t)single_before;
+    na += (uint64_t)single_after;
+  }
+  *before = nb;
+  *after = na;
+}
+
+typedef struct {
+  uint32_t src, dst, dmin, dmax;
+  double v;
+} orc_spot;
+
+static int cmp_spot(const void *x, const void *y) {
+  const orc_spot *a = (const orc_spot *)x, *b = (const orc_spot *)y;
+  if (a->v != b->v) return a->v > b->v ? -1 : 1;
+  if (a->src != b->src) return a->src < b->src ? -1 : 1;
+  return (a->dst > b->dst) - (a->dst < b->dst);
+}
+
+/* Hotspots of optimizer `opt` in the kernel rooted at scope `root`: the
+ * edges (src, dst) or instructions (src = ORC_NONE) carrying its matched
+ * samples, Table 2's matching as in orc_estimate, largest first (ties by
+ * src, then dst).  Writes up to k rows of out[5] = {src, dst, dmin, dmax,
+ * samples} and returns how many. */
+uint32_t orc_hotspots(const orc_analysis *a, const uint32_t *C, const double *share,
+                      const double *self_, uint32_t root, uint32_t opt, uint32_t k, double *out) {
+  const orc_prog *p = &a->c->p;
+  uint32_t nbl = popcount32(p->blamable & 0xFFFu);
+  int s_mem = reason_slot(p->blamable, ORC_MEM_DEP);
+  int s_exec = reason_slot(p->blamable, ORC_EXEC_DEP);
+  int s_sync = reason_slot(p->blamable, ORC_SYNC);
+  orc_spot *all = (orc_spot *)xmalloc(sizeof(orc_spot) * ((size_t)a->n_edges + p->n_instr + 1));
+  size_t m = 0;
+#define SH(e, slot, l) ((slot) < 0 ? 0.0 : share[((size_t)(e) * nbl + (uint32_t)(slot)) * 2 + (l)])
+  for (uint64_t e = 0; e < a->n_edges; ++e) {
+    uint32_t i = a->e_src[e], j = a->e_dst[e];
+    if (root_of_scope(p, p->instr_scope[j]) != root) continue;
+    uint8_t ci = p->op_class[i];
+    double v = 0.0;
+    if (opt == ORC_O_REG_REUSE && (ci == ORC_LOCAL_LOAD || ci == ORC_LOCAL_STORE))
+      v = SH(e, s_mem, 0) + SH(e, s_mem, 1);
+    if (opt == ORC_O_STRENGTH && (ci == ORC_FP64 || ci == ORC_LONG_ALU))
+      v = SH(e, s_exec, 0) + SH(e, s_exec, 1);
+    if (opt == ORC_O_WARP_BAL) v = SH(e, s_sync, 0) + SH(e, s_sync, 1);
+    if (opt == ORC_O_LOOP_UNROLL || opt == ORC_O_REORDER) {
+      v = (ci == ORC_GLOBAL_LOAD ? SH(e, s_mem, 1) : 0.0) + SH(e, s_exec, 1);
+      if (opt == ORC_O_LOOP_UNROLL) {
+        uint32_t fscope = p->func_scope[a->c->func_of_block[a->c->block_of[i]]];
+        if (common_loop(p, p->instr_scope[i], p->instr_scope[j], fscope) == ORC_NONE) v = 0.0;
+      }
+    }
+    if (v > 0.0) {
+      all[m].src = i;
+      all[m].dst = j;
+      all[m].dmin = a->e_dmin[e];
+      all[m].dmax = a->e_dmax[e];
+      all[m].v = v;
+      ++m;
+    }
+  }
+#undef SH
+  for (uint32_t j = 0; j < p->n_instr; ++j) {
+    uint32_t s = p->instr_scope[j];
+    if (root_of_scope(p, s) != root) continue;
+    uint8_t cj = p->op_class[j];
+    double v = 0.0;
+    if (opt == ORC_O_FUNC_SPLIT) v = (double)C[((size_t)j * 12 + ORC_INST_FETCH) * 2] +
+                                     (double)C[((size_t)j * 12 + ORC_INST_FETCH) * 2 + 1];
+    if (opt == ORC_O_FAST_MATH && in_function_with(p, s, ORC_SF_MATH))
+      for (uint32_t r = 0; r < 12; ++r)
+        if (r != ORC_SELECTED)
+          v += (double)C[((size_t)j * 12 + r) * 2] + (double)C[((size_t)j * 12 + r) * 2 + 1];
+    if (opt == ORC_O_WARP_BAL)
+      v = self_[((size_t)j * 12 + ORC_SYNC) * 2] + self_[((size_t)j * 12 + ORC_SYNC) * 2 + 1];
+    if (opt == ORC_O_MEM_TRANS && (cj == ORC_GLOBAL_LOAD || cj == ORC_GLOBAL_STORE))
+      v = (double)C[((size_t)j * 12 + ORC_MEM_THROTTLE) * 2] +
+          (double)C[((size_t)j * 12 + ORC_MEM_THROTTLE) * 2 + 1];
+    if (opt == ORC_O_INLINE && (cj == ORC_CALL || in_function_with(p, s, ORC_SF_DEVICE | ORC_SF_CFG)))
+      for (uint32_t r = 0; r < 12; ++r) v += (double)C[((size_t)j * 12 + r) * 2 + 1];
+    if (v > 0.0) {
+      all[m].src = ORC_NONE;
+      all[m].dst = j;
+      all[m].dmin = 0;
+      all[m].dmax = 0;
+      all[m].v = v;
+      ++m;
+    }
+  }
+  qsort(all, m, sizeof(orc_spot), cmp_spot);
+  uint32_t n = (uint32_t)(m < k ? m : k);
+  for (uint32_t t = 0; t < n; ++t) {
+    out[5 * t] = all[t].src;
+    out[5 * t + 1] = all[t].dst;
+    out[5 * t + 2] = all[t].dmin;
+    out[5 * t + 3] = all[t].dmax;
+    out[5 * t + 4] = all[t].v;
+  }
+  free(all);
+  return n;
+}

@@ -111,6 +111,19 @@ void orc_estimate(const orc_analysis *a, const uint32_t *C, const double *share,
                   double *eq3, uint32_t k, uint32_t *top_opt, uint32_t *top_scope,
                   double *top_speed);
 
+/* Parallel optimizers (Sec. 5.2, Eqs. (6)-(10)) for kernel root scope
+ * `root`: launch[4], device[8] and out[22] as documented in gpa_oracle.c. */
+void orc_parallel(const orc_analysis *a, const uint32_t *C, uint32_t root, const uint32_t *launch,
+                  const uint32_t *device, double *out);
+
+/* Single dependency coverage (Sec. 6): instructions with no use site of two
+ * or more sources, before and after pruning. */
+void orc_coverage(const orc_analysis *a, uint64_t *before, uint64_t *after);
+/* Hotspots of one optimizer in one kernel (root scope): up to k rows of
+ * {src, dst, dmin, dmax, samples}; returns the number of rows. */
+uint32_t orc_hotspots(const orc_analysis *a, const uint32_t *C, const double *share,
+                      const double *self_, uint32_t root, uint32_t opt, uint32_t k, double *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -98,6 +98,10 @@ def _load(path):
     L.orc_analysis_edges.argtypes = [vp, vp, vp, vp, vp, vp]
     L.orc_blame.argtypes = [vp, vp, vp, vp, vp, vp]
     L.orc_estimate.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, u32, vp, vp, vp]
+    L.orc_parallel.argtypes = [vp, vp, u32, vp, vp, vp]
+    L.orc_coverage.argtypes = [vp, vp, vp]
+    L.orc_hotspots.argtypes = [vp, vp, vp, vp, u32, u32, u32, vp]
+    L.orc_hotspots.restype = u32
     return L
 
 
@@ -239,6 +243,51 @@ class Program:
                 "speedup": speed.reshape(ns, N_OPT), "root_of": root_of, "kernel_T": kT,
                 "kernel_L": kL, "eq3": eq3.reshape(ns, 3), "top_opt": topo.reshape(ns, k),
                 "top_scope": tops.reshape(ns, k), "top_speed": topv.reshape(ns, k)}
+
+
+PARALLEL_FIELDS = ["matched", "W", "W_new", "R_I", "I", "I_new", "C_W", "C_I", "f", "speedup"]
+LAUNCH_FIELDS = ["blocks", "threads_per_block", "regs_per_thread", "shared_per_block"]
+DEVICE_FIELDS = ["n_sm", "schedulers_per_sm", "warp_size", "max_warps_per_sm",
+                 "max_blocks_per_sm", "max_threads_per_block", "regs_per_sm", "shared_per_sm"]
+
+
+def parallel(P: "Program", C: np.ndarray, root: int, launch: dict, device: dict):
+    """Block Increase and Thread Increase (Sec. 5.2, Eqs. (6)-(10)) for the
+    kernel root scope `root`: two dicts of PARALLEL_FIELDS."""
+    if P._an is None:
+        P.analyze()
+    C = np.ascontiguousarray(C, np.uint32).reshape(-1)
+    la = np.array([launch[f] for f in LAUNCH_FIELDS], np.uint32)
+    de = np.array([device[f] for f in DEVICE_FIELDS], np.uint32)
+    out = np.zeros(22)
+    lib().orc_parallel(P._an, _p(C), int(root), _p(la), _p(de), _p(out))
+    return [{f: float(out[11 * o + k]) for k, f in enumerate(PARALLEL_FIELDS)} for o in (0, 1)]
+
+
+def coverage(P: "Program"):
+    """Single dependency coverage counts (before, after pruning)."""
+    if P._an is None:
+        P.analyze()
+    b = np.zeros(1, np.uint64)
+    a = np.zeros(1, np.uint64)
+    lib().orc_coverage(P._an, _p(b), _p(a))
+    return int(b[0]), int(a[0])
+
+
+def hotspots(P: "Program", C, bl: dict, root: int, opt: int, k: int = 5):
+    """Hotspots of optimizer `opt` in the kernel rooted at scope `root`:
+    list of (src, dst, dmin, dmax, samples)."""
+    if P._an is None:
+        P.analyze()
+    C = np.ascontiguousarray(C, np.uint32).reshape(-1)
+    share = np.ascontiguousarray(bl["share"], np.float64).reshape(-1)
+    if share.size == 0:
+        share = np.zeros(1)
+    self_ = np.ascontiguousarray(bl["self"], np.float64).reshape(-1)
+    out = np.zeros(5 * max(k, 1))
+    n = lib().orc_hotspots(P._an, _p(C), _p(share), _p(self_), int(root), int(opt), int(k), _p(out))
+    rows = out[:5 * n].reshape(n, 5)
+    return [(int(r[0]), int(r[1]), int(r[2]), int(r[3]), float(r[4])) for r in rows]
 
 
 def run_all(prog: dict, records: np.ndarray, k: int = 5) -> dict:

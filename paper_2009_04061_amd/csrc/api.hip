@@ -33,10 +33,21 @@ void fail(gpa_status code, const char *fmt, ...) {
 }
 
 // ------------------------------------------------------------------ pool
+// Per device: free lists by size class, and the bytes handed out and held
+// in the free lists.  A block is returned to the free list of the device it
+// was allocated on.
 namespace {
 std::mutex g_mu;
-std::map<size_t, std::vector<void *>> g_free;   // size class -> cached blocks
-std::unordered_map<void *, size_t> g_class;     // block -> size class
+struct DevPool {
+  std::map<size_t, std::vector<void *>> free;   // size class -> cached blocks
+  uint64_t in_use = 0, cached = 0;
+};
+std::map<int, DevPool> g_pools;
+struct BlockInfo {
+  int dev;
+  size_t cls;
+};
+std::unordered_map<void *, BlockInfo> g_blocks;
 
 size_t size_class(size_t b) {
   if (b <= 4096) return 4096;
@@ -49,30 +60,38 @@ size_t size_class(size_t b) {
   return (b + mb - 1) / mb * mb;
 }
 
-void release_cached_locked() {
-  for (auto &kv : g_free)
+// frees the cached blocks of one device (that device must be current)
+void release_cached_locked(int dev) {
+  DevPool &P = g_pools[dev];
+  for (auto &kv : P.free)
     for (void *p : kv.second) {
       (void)hipFree(p);
-      g_class.erase(p);
+      g_blocks.erase(p);
     }
-  g_free.clear();
+  P.free.clear();
+  P.cached = 0;
 }
 }  // namespace
 
 void *dev_alloc(size_t bytes) {
   const size_t c = size_class(bytes);
+  int dev = 0;
+  GPA_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_free.find(c);
-  if (it != g_free.end() && !it->second.empty()) {
+  DevPool &P = g_pools[dev];
+  auto it = P.free.find(c);
+  if (it != P.free.end() && !it->second.empty()) {
     void *p = it->second.back();
     it->second.pop_back();
+    P.cached -= c;
+    P.in_use += c;
     return p;
   }
   void *p = nullptr;
   hipError_t e = hipMalloc(&p, c);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    release_cached_locked();
+    release_cached_locked(dev);
     e = hipMalloc(&p, c);
   }
   if (e != hipSuccess) {
@@ -80,16 +99,36 @@ void *dev_alloc(size_t bytes) {
     set_error("device allocation of %zu bytes failed: %s", c, hipGetErrorString(e));
     throw Error{GPA_E_NOMEM};
   }
-  g_class[p] = c;
+  g_blocks[p] = BlockInfo{dev, c};
+  P.in_use += c;
   return p;
 }
 
 void dev_free(void *p) {
   if (!p) return;
   std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_class.find(p);
-  if (it == g_class.end()) return;
-  g_free[it->second].push_back(p);
+  auto it = g_blocks.find(p);
+  if (it == g_blocks.end()) return;
+  DevPool &P = g_pools[it->second.dev];
+  P.free[it->second.cls].push_back(p);
+  P.in_use -= it->second.cls;
+  P.cached += it->second.cls;
+}
+
+void pool_stats(uint64_t *in_use, uint64_t *cached) {
+  int dev = 0;
+  GPA_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevPool &P = g_pools[dev];
+  if (in_use) *in_use = P.in_use;
+  if (cached) *cached = P.cached;
+}
+
+void pool_trim() {
+  int dev = 0;
+  GPA_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  release_cached_locked(dev);
 }
 
 // ------------------------------------------------------------- timing
@@ -277,6 +316,41 @@ static void copy_out(T *host, const DBuf<T> &src, size_t n, hipStream_t s) {
   GPA_HIP(hipMemcpyAsync(host, src.p, n * sizeof(T), hipMemcpyDeviceToHost, s));
 }
 
+void enqueue_attribute_batch(gpa_program *const *progs, const gpa_sample *const *ds,
+                             const uint64_t *n, uint32_t count, hipStream_t s, Arena &ar,
+                             gpa_blame **b, unsigned long long *dtot, bool measure_tuning) {
+  PhaseTimer t_hist, t_blame;
+  std::vector<HistEntry> batched;
+  std::vector<uint32_t> single;
+  const char *force = getenv("GPA_HIST_PARTITION");
+  const bool forced = force && force[0] == '1';
+  for (uint32_t k = 0; k < count; ++k) {
+    b[k] = new gpa_blame(progs[k]);
+    b[k]->counts.alloc((size_t)progs[k]->n_instr * 24);
+    const bool fits = n[k] > 0 && progs[k]->n_instr <= hist_hot_max_pcs() && !forced &&
+                      ((uintptr_t)ds[k] % 16) == 0;
+    if (fits) batched.push_back({ds[k], n[k], progs[k]->n_instr, b[k]->counts.p, dtot + 4 * k});
+    else single.push_back(k);
+  }
+  const uint64_t per = batch_records_per_workgroup(batched.data(), (uint32_t)batched.size(), s, ar,
+                                                   measure_tuning);
+  if (measure_tuning) t_hist.begin(kPhaseHist, s);
+  run_hist_batch(batched.data(), (uint32_t)batched.size(), per, s, ar);
+  for (uint32_t k : single) run_hist(*progs[k], ds[k], n[k], b[k]->counts.p, dtot + 4 * k, s, ar);
+  if (measure_tuning) {
+    t_hist.end(s);
+    t_blame.begin(kPhaseBlame, s);
+  }
+  run_blame_batch(progs, b, count, s, ar);
+  if (measure_tuning) {
+    t_blame.end(s);
+    // the caller synchronizes before returning: the timers are read then
+    GPA_HIP(hipStreamSynchronize(s));
+    t_hist.collect();
+    t_blame.collect();
+  }
+}
+
 }  // namespace gpa
 
 gpa_blame::gpa_blame(const gpa_program *p) : prog(p) { gpa::program_retain(p); }
@@ -309,6 +383,14 @@ using namespace gpa;
 extern "C" {
 
 const char *gpa_last_error(void) { return g_err.c_str(); }
+
+gpa_status gpa_pool_stats(uint64_t *in_use, uint64_t *cached) {
+  return guarded([&] { pool_stats(in_use, cached); });
+}
+
+gpa_status gpa_pool_trim(void) {
+  return guarded([&] { pool_trim(); });
+}
 
 void gpa_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(g_tmu);
@@ -443,13 +525,19 @@ gpa_status gpa_load_program(const gpa_program_desc *d, void *stream, gpa_program
     GPA_HIP(hipStreamWaitEvent(s, ev_order.e, 0));
     GPA_HIP(hipStreamWaitEvent(s, ev_short.e, 0));
     build_distances(*p, s, ar, tables);
+    build_topk_plan(*p, s, ar);
     t_targets.end(s);
     t_load.end(s);
     if (p->n_roots_dev)   // not read by an earlier synchronization
       GPA_HIP(hipMemcpyAsync(&p->n_roots, p->n_roots_dev, 4, hipMemcpyDeviceToHost, s));
     GPA_HIP(hipMemcpyAsync(p->seg_chunks, p->big_chunk_tot.p, sizeof(p->seg_chunks),
                            hipMemcpyDeviceToHost, s));
+    unsigned long long tk_total = 0;
+    if (p->tk_total_dev)
+      GPA_HIP(hipMemcpyAsync(&tk_total, p->tk_total_dev, sizeof(tk_total), hipMemcpyDeviceToHost, s));
     GPA_HIP(hipStreamSynchronize(s));
+    p->tk_chunks = (uint32_t)tk_total;
+    p->tk_total_dev = nullptr;   // arena memory, returned with this call
     p->n_roots_dev = nullptr;
     p->sync_words = nullptr;   // arena memory, returned with this call
     t_load.collect();
@@ -580,6 +668,57 @@ gpa_status gpa_attribute(gpa_program *p, const gpa_sample *samples, uint64_t n,
   return GPA_OK;
 }
 
+gpa_status gpa_attribute_batch(gpa_program *const *progs, const gpa_sample *const *samples,
+                               const uint64_t *n, uint32_t count, int samples_on_device,
+                               void *stream, gpa_blame **out) {
+  if (!out || (count && (!progs || !samples || !n))) {
+    set_error("gpa_attribute_batch: NULL argument");
+    return GPA_E_INVALID;
+  }
+  for (uint32_t k = 0; k < count; ++k) {
+    out[k] = nullptr;
+    if (!progs[k] || (n[k] && !samples[k])) {
+      set_error("gpa_attribute_batch: entry %u has a NULL program or sample array", k);
+      return GPA_E_INVALID;
+    }
+    if (n[k] >= 0x40000000ull) {
+      set_error("gpa_attribute_batch: entry %u has 2^30 samples or more", k);
+      return GPA_E_UNSUPPORTED;
+    }
+  }
+  std::vector<gpa_blame *> b(count, nullptr);
+  hipStream_t s = (hipStream_t)stream;
+  gpa_status st = guarded([&] {
+    Arena ar(s);
+    std::vector<const gpa_sample *> dptr(count, nullptr);
+    for (uint32_t k = 0; k < count; ++k) {
+      dptr[k] = samples[k];
+      if (n[k] && !samples_on_device) {
+        gpa_sample *tmp = ar.get<gpa_sample>(n[k]);
+        GPA_HIP(hipMemcpyAsync(tmp, samples[k], n[k] * sizeof(gpa_sample), hipMemcpyHostToDevice, s));
+        dptr[k] = tmp;
+      }
+    }
+    unsigned long long *dtot = ar.get<unsigned long long>((size_t)count * 4);
+    enqueue_attribute_batch(progs, dptr.data(), n, count, s, ar, b.data(), dtot, true);
+    std::vector<unsigned long long> tot((size_t)count * 4);
+    if (count)
+      GPA_HIP(hipMemcpyAsync(tot.data(), dtot, sizeof(unsigned long long) * tot.size(),
+                             hipMemcpyDeviceToHost, s));
+    GPA_HIP(hipStreamSynchronize(s));
+    for (uint32_t k = 0; k < count; ++k)
+      for (int q = 0; q < 4; ++q) b[k]->totals[q] = tot[4 * (size_t)k + q];
+  });
+  if (st != GPA_OK) {
+    if (s) (void)hipStreamSynchronize(s);
+    else (void)hipDeviceSynchronize();
+    for (gpa_blame *x : b) delete x;
+    return st;
+  }
+  for (uint32_t k = 0; k < count; ++k) out[k] = b[k];
+  return GPA_OK;
+}
+
 void gpa_blame_free(gpa_blame *b) { delete b; }
 
 gpa_status gpa_blame_counts(const gpa_blame *b, uint32_t *counts, uint64_t *totals) {
@@ -647,6 +786,41 @@ gpa_status gpa_advise(const gpa_blame *b, void *stream, gpa_advice **out) {
     return st;
   }
   *out = a;
+  return GPA_OK;
+}
+
+gpa_status gpa_advise_batch(const gpa_blame *const *blames, uint32_t count, void *stream,
+                            gpa_advice **out) {
+  if (!out || (count && !blames)) {
+    set_error("gpa_advise_batch: NULL argument");
+    return GPA_E_INVALID;
+  }
+  for (uint32_t k = 0; k < count; ++k) {
+    out[k] = nullptr;
+    if (!blames[k]) {
+      set_error("gpa_advise_batch: entry %u is NULL", k);
+      return GPA_E_INVALID;
+    }
+  }
+  std::vector<gpa_advice *> a(count, nullptr);
+  hipStream_t s = (hipStream_t)stream;
+  gpa_status st = guarded([&] {
+    for (uint32_t k = 0; k < count; ++k) a[k] = new gpa_advice(blames[k]->prog);
+    Arena ar(s);
+    PhaseTimer t_adv;
+    t_adv.begin(kPhaseAdvise, s);
+    run_estimate_batch(blames, a.data(), count, 16, s, ar);
+    t_adv.end(s);
+    GPA_HIP(hipStreamSynchronize(s));
+    t_adv.collect();
+  });
+  if (st != GPA_OK) {
+    if (s) (void)hipStreamSynchronize(s);
+    else (void)hipDeviceSynchronize();
+    for (gpa_advice *x : a) delete x;
+    return st;
+  }
+  for (uint32_t k = 0; k < count; ++k) out[k] = a[k];
   return GPA_OK;
 }
 

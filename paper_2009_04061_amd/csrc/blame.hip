@@ -18,25 +18,48 @@
 
 namespace gpa {
 
-struct ArchDev {
+// One profile's blame: its program's edges and classes, its counts and its
+// output tables.  A launch for one profile takes it by value; a batched
+// launch reads it from a device table per workgroup (a work item names the
+// profile and a tile of kBlameThreads instructions).
+struct BlameArgs {
+  uint32_t n_instr, nbl, blamable;
   uint16_t allowed[12];
-  uint16_t blamable;
-  uint16_t pad;
+  const uint32_t *counts, *in_ptr, *e_src, *e_dmax, *out_ptr, *out_perm;
+  const uint8_t *e_flags, *op_class;
+  double *share, *self_, *blamed, *fine;
 };
+constexpr int kBlameThreads = 128;
+
+// the instructions a thread takes: one per tile in a batched launch, a
+// grid-stride range otherwise
+#define BLAME_ITEM(VAR)                                                          \
+  const BlameArgs &a = BATCH ? many[items[blockIdx.x].entry] : one;              \
+  const uint32_t first_ = (BATCH ? items[blockIdx.x].local : blockIdx.x) * blockDim.x + threadIdx.x; \
+  const uint32_t stride_ = BATCH ? a.n_instr : gridDim.x * blockDim.x;           \
+  for (uint32_t VAR = first_; VAR < a.n_instr; VAR += stride_)
 
 // One thread per destination j.  A first pass over j's incoming edges sums,
 // per blamable reason, the issued-based and the path-only weights of the
 // candidates (in edge order, as Eq. (1) is written); a second pass writes
 // every share slot of those edges.  Reasons are unrolled, so the per-reason
 // sums stay in registers.
-__global__ void k_blame_dst(uint32_t n_instr, uint32_t nbl, ArchDev arch, const uint32_t *counts,
-                            const uint32_t *in_ptr, const uint32_t *e_src, const uint8_t *e_flags,
-                            const uint32_t *e_dmax, const uint8_t *op_class, double *share,
-                            double *self_) {
-  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_instr;
-       j += gridDim.x * blockDim.x) {
+template <bool BATCH>
+__global__ void __launch_bounds__(kBlameThreads)
+k_blame_dst(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *__restrict__ items) {
+  BLAME_ITEM(j) {
+    const uint32_t nbl = a.nbl;
+    const uint32_t *__restrict__ counts = a.counts;
+    const uint32_t *__restrict__ e_src = a.e_src;
+    const uint32_t *__restrict__ e_dmax = a.e_dmax;
+    const uint8_t *__restrict__ e_flags = a.e_flags;
+    const uint8_t *__restrict__ op_class = a.op_class;
+    struct {
+      uint16_t blamable;
+      const uint16_t *allowed;
+    } arch{(uint16_t)a.blamable, a.allowed};
     const uint32_t *C = counts + (size_t)j * 24;
-    const uint32_t e0 = in_ptr[j], e1 = in_ptr[j + 1];
+    const uint32_t e0 = a.in_ptr[j], e1 = a.in_ptr[j + 1];
     double Wi[12], Wp[12];
     bool any[12];
 #pragma unroll
@@ -68,7 +91,7 @@ __global__ void k_blame_dst(uint32_t n_instr, uint32_t nbl, ArchDev arch, const 
       const uint32_t cls = op_class[i];
       const double len = (double)e_dmax[e] + 1.0;
       const double issued = (double)counts[(size_t)i * 24] + (double)counts[(size_t)i * 24 + 1];
-      double *sh = share + (size_t)e * 2 * nbl;
+      double *sh = a.share + (size_t)e * 2 * nbl;
       uint32_t slot = 0;
 #pragma unroll
       for (int r = 0; r < 12; ++r) {
@@ -91,7 +114,7 @@ __global__ void k_blame_dst(uint32_t n_instr, uint32_t nbl, ArchDev arch, const 
 #pragma unroll
       for (int l = 0; l < 2; ++l) {
         const uint32_t S = C[r * 2 + l];
-        self_[(size_t)j * 24 + r * 2 + l] = (S != 0 && (!blam || !any[r])) ? (double)S : 0.0;
+        a.self_[(size_t)j * 24 + r * 2 + l] = (S != 0 && (!blam || !any[r])) ? (double)S : 0.0;
       }
     }
   }
@@ -100,12 +123,18 @@ __global__ void k_blame_dst(uint32_t n_instr, uint32_t nbl, ArchDev arch, const 
 // Sums in edge order; the fine class of a memory dependency or a non-WAR
 // execution dependency depends only on the source's opcode class, so each
 // fine class is one accumulator (no run-time indexing of private arrays).
-__global__ void k_blame_src(uint32_t n_instr, uint32_t nbl, uint32_t blamable,
-                            const uint32_t *out_ptr, const uint32_t *out_perm,
-                            const uint8_t *e_flags, const uint8_t *op_class, const double *share,
-                            double *blamed, double *fine) {
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_instr;
-       i += gridDim.x * blockDim.x) {
+template <bool BATCH>
+__global__ void __launch_bounds__(kBlameThreads)
+k_blame_src(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *__restrict__ items) {
+  BLAME_ITEM(i) {
+    const uint32_t nbl = a.nbl, blamable = a.blamable;
+    const uint32_t *__restrict__ out_ptr = a.out_ptr;
+    const uint32_t *__restrict__ out_perm = a.out_perm;
+    const uint8_t *__restrict__ e_flags = a.e_flags;
+    const uint8_t *__restrict__ op_class = a.op_class;
+    const double *__restrict__ share = a.share;
+    double *__restrict__ blamed = a.blamed;
+    double *__restrict__ fine = a.fine;
     double acc[24];
 #pragma unroll
     for (int q = 0; q < 24; ++q) acc[q] = 0.0;
@@ -169,21 +198,61 @@ void run_blame(const gpa_program &p, gpa_blame &b, hipStream_t s, Arena &ar) {
   launch_blame(p, b.counts.p, b.share.p, b.blamed.p, b.self_.p, b.fine.p, s);
 }
 
+static BlameArgs blame_args(const gpa_program &p, const uint32_t *counts, double *share,
+                            double *blamed, double *self_, double *fine) {
+  BlameArgs a;
+  a.n_instr = p.n_instr;
+  a.nbl = p.n_blamable;
+  a.blamable = p.arch.blamable;
+  for (int r = 0; r < 12; ++r) a.allowed[r] = p.arch.allowed[r];
+  a.counts = counts;
+  a.in_ptr = p.in_ptr.p;
+  a.e_src = p.e_src.p;
+  a.e_dmax = p.e_dmax.p;
+  a.out_ptr = p.out_ptr;
+  a.out_perm = p.out_perm;
+  a.e_flags = p.e_flags.p;
+  a.op_class = p.op_class.p;
+  a.share = share;
+  a.self_ = self_;
+  a.blamed = blamed;
+  a.fine = fine;
+  return a;
+}
+
 void launch_blame(const gpa_program &p, const uint32_t *counts, double *share, double *blamed,
                   double *self_, double *fine, hipStream_t s) {
-  const uint32_t n = p.n_instr;
-  const uint32_t nbl = p.n_blamable;
-  ArchDev a;
-  for (int r = 0; r < 12; ++r) a.allowed[r] = p.arch.allowed[r];
-  a.blamable = p.arch.blamable;
-  a.pad = 0;
-  hipLaunchKernelGGL(k_blame_dst, dim3(grid_for(n, 128, 8192)), dim3(128), 0, s, n, nbl, a,
-                     counts, p.in_ptr.p, p.e_src.p, p.e_flags.p, p.e_dmax.p, p.op_class.p, share,
-                     self_);
+  const BlameArgs a = blame_args(p, counts, share, blamed, self_, fine);
+  const unsigned g = grid_for(p.n_instr, kBlameThreads, 8192);
+  hipLaunchKernelGGL(k_blame_dst<false>, dim3(g), dim3(kBlameThreads), 0, s, a, nullptr, nullptr);
   GPA_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_blame_src, dim3(grid_for(n, 128, 8192)), dim3(128), 0, s, n, nbl,
-                     (uint32_t)p.arch.blamable, p.out_ptr, p.out_perm, p.e_flags.p,
-                     p.op_class.p, share, blamed, fine);
+  hipLaunchKernelGGL(k_blame_src<false>, dim3(g), dim3(kBlameThreads), 0, s, a, nullptr, nullptr);
+  GPA_LAUNCH_CHECK();
+}
+
+void run_blame_batch(const gpa_program *const *progs, gpa_blame *const *b, uint32_t count,
+                     hipStream_t s, Arena &ar) {
+  std::vector<BlameArgs> args(count);
+  std::vector<WorkItem> items;
+  for (uint32_t k = 0; k < count; ++k) {
+    const gpa_program &p = *progs[k];
+    const uint32_t n = p.n_instr;
+    b[k]->share.alloc(p.n_edges * p.n_blamable * 2);
+    b[k]->blamed.alloc((size_t)n * 24);
+    b[k]->self_.alloc((size_t)n * 24);
+    b[k]->fine.alloc((size_t)n * GPA_N_FINE * 2);
+    args[k] = blame_args(p, b[k]->counts.p, b[k]->share.p, b[k]->blamed.p, b[k]->self_.p,
+                         b[k]->fine.p);
+    for (uint32_t t = 0; t * kBlameThreads < n; ++t) items.push_back({k, t});
+  }
+  if (items.empty()) return;
+  const BlameArgs *d_args = ar.upload(args, s);
+  const WorkItem *d_items = ar.upload(items, s);
+  BlameArgs none{};
+  const unsigned g = (unsigned)items.size();
+  hipLaunchKernelGGL(k_blame_dst<true>, dim3(g), dim3(kBlameThreads), 0, s, none, d_args, d_items);
+  GPA_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_blame_src<true>, dim3(g), dim3(kBlameThreads), 0, s, none, d_args, d_items);
   GPA_LAUNCH_CHECK();
 }
 

@@ -36,11 +36,16 @@ struct Error {
 [[noreturn]] void fail(gpa_status code, const char *fmt, ...);
 
 // ------------------------------------------------------------ device memory
-// A caching allocator: freed blocks go back to a per-size-class free list and
-// are reused by later allocations; nothing is returned to the runtime before
-// process exit.  Blocks are 256-byte aligned.
+// A caching allocator, per device: freed blocks go back to their device's
+// per-size-class free list and are reused by later allocations; cached
+// blocks are returned to the runtime when an allocation fails or on
+// pool_trim.  Blocks are 256-byte aligned.
 void *dev_alloc(size_t bytes);
 void dev_free(void *p);
+// bytes of the current device's blocks handed out and cached in free lists
+void pool_stats(uint64_t *in_use, uint64_t *cached);
+// frees the current device's cached blocks
+void pool_trim();
 
 template <typename T>
 struct DBuf {
@@ -71,6 +76,8 @@ struct DBuf {
 struct Arena {
   std::vector<void *> blocks;
   std::vector<hipStream_t> streams;
+  // host staging of uploads, kept until the streams have finished with them
+  std::vector<std::vector<char>> host_blocks;
   char *fixed = nullptr;
   size_t cap = 0, used = 0;
   explicit Arena(hipStream_t s) { streams.push_back(s); }
@@ -78,6 +85,9 @@ struct Arena {
   Arena(const Arena &) = delete;
   Arena &operator=(const Arena &) = delete;
   void add_stream(hipStream_t s) { streams.push_back(s); }
+  // the streams' work that used the blocks is known to be complete (an
+  // event was observed): the destructor returns them without synchronizing
+  void work_done() { streams.clear(); }
   ~Arena() {
     if (fixed) return;
     for (hipStream_t s : streams) (void)hipStreamSynchronize(s);
@@ -99,6 +109,21 @@ struct Arena {
     void *b = dev_alloc(bytes);
     blocks.push_back(b);
     return static_cast<T *>(b);
+  }
+  // a device copy of host data, uploaded on `s` (pool mode only)
+  template <typename T>
+  T *upload(const std::vector<T> &v, hipStream_t s) {
+    T *d = get<T>(v.size());
+    if (v.empty()) return d;
+    host_blocks.emplace_back(reinterpret_cast<const char *>(v.data()),
+                             reinterpret_cast<const char *>(v.data() + v.size()));
+    const hipError_t e =
+        hipMemcpyAsync(d, host_blocks.back().data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+      set_error("upload of %zu bytes failed: %s", sizeof(T) * v.size(), hipGetErrorString(e));
+      throw Error{GPA_E_DEVICE};
+    }
+    return d;
   }
 };
 
@@ -163,6 +188,11 @@ struct gpa_program {
   unsigned long long seg_chunks[4] = {0, 0, 0, 0};
   gpa::DBuf<uint32_t> roots;                   // kernel root scope ids
   uint32_t n_roots = 0;
+  // top-k plan: chunks of (scope, optimizer) items per kernel root, their
+  // starts, and the total (device copy during the load)
+  gpa::DBuf<uint32_t> tk_nch, tk_cst;
+  uint32_t tk_chunks = 0;
+  unsigned long long *tk_total_dev = nullptr;
   uint32_t *n_roots_dev = nullptr;   // during the load: device copy of n_roots
   // during the load: 8 device words read back together at each host
   // synchronization (validation verdict, then the reaching-definition sizes)
@@ -229,12 +259,43 @@ void group_by_keys(const GroupSpec *spec, int n_groups, DBuf<uint32_t> &ptr,
 void group_by_key(const uint32_t *key, size_t n, uint32_t n_keys, DBuf<uint32_t> &ptr,
                   DBuf<uint32_t> &perm, hipStream_t s, Arena &ar);
 
+// A workgroup of a batched launch: the profile it works on and its block
+// index within that profile's grid.
+struct WorkItem {
+  uint32_t entry, local;
+};
+
 // hist.hip.  allow_partition = false keeps to the hot-set path (programs of
 // up to hist_hot_max_pcs() instructions; GPA_E_UNSUPPORTED beyond), which
 // issues no memset and no host synchronization.
 void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint32_t *counts,
               unsigned long long *totals, hipStream_t s, Arena &ar, bool allow_partition = true);
 uint32_t hist_hot_max_pcs();
+// One profile of a batched histogram: n records at `samples` (device, 16-byte
+// aligned) of a program of n_instr <= hist_hot_max_pcs() instructions.
+struct HistEntry {
+  const gpa_sample *samples;
+  uint64_t n;
+  uint32_t n_instr;
+  uint32_t *counts;
+  unsigned long long *totals;
+};
+// The hot-set histogram of many profiles in three launches (selection,
+// pass, finish), each workgroup taking one profile's share; `per` is the
+// records per pass workgroup (rounded up to a multiple of 128, and raised
+// where a profile would need more than 256 workgroups).  Entries must have
+// n > 0.  The counts equal run_hist's for each profile.
+void run_hist_batch(const HistEntry *e, uint32_t count, uint64_t per, hipStream_t s, Arena &ar);
+size_t hist_batch_scratch_bytes(const HistEntry *e, uint32_t count, uint64_t per);
+// The autotuner of the batched histogram: records per pass workgroup for
+// this batch's shape bucket (profile count, total and largest record count,
+// each to a power of two), measured once per bucket and process by timing
+// the candidates on the batch itself (every candidate computes the same
+// counts), then reused.  GPA_BATCH_PER=<records> fixes it; GPA_AUTOTUNE=0
+// takes the default without measuring; so does measure = false (for callers
+// that must not synchronize) when the bucket has not been measured yet.
+uint64_t batch_records_per_workgroup(const HistEntry *e, uint32_t count, hipStream_t s, Arena &ar,
+                                     bool measure = true);
 // scratch bytes the hot-set path takes for n records of a program of n_instr
 // instructions (256-byte aligned blocks)
 size_t hist_hot_scratch_bytes(uint32_t n_instr, uint64_t n);
@@ -289,9 +350,32 @@ void build_scope_targets(gpa_program &p, hipStream_t s, Arena &ar);
 void run_blame(const gpa_program &p, gpa_blame &b, hipStream_t s, Arena &ar);
 void launch_blame(const gpa_program &p, const uint32_t *counts, double *share, double *blamed,
                   double *self_, double *fine, hipStream_t s);
+// The histogram and blame of `count` profiles whose records are on the
+// device at ds[k]: creates b[k] with its tables, totals to dtot[4k..4k+3]
+// (device).  With measure_tuning the autotuner may time candidates, and the
+// call synchronizes s at the end (phase timing); without it nothing
+// synchronizes.
+void enqueue_attribute_batch(gpa_program *const *progs, const gpa_sample *const *ds,
+                             const uint64_t *n, uint32_t count, hipStream_t s, Arena &ar,
+                             gpa_blame **b, unsigned long long *dtot, bool measure_tuning);
+
+// device bytes one request of n records against program p takes from
+// admission to completion (staged records when host_records, histogram
+// scratch, blame and advise tables), an upper estimate
+uint64_t request_device_bytes(const gpa_program &p, uint64_t n, bool host_records);
+
+// the blame of many profiles (their counts already in b[k]->counts) in two
+// launches; allocates each handle's tables
+void run_blame_batch(const gpa_program *const *progs, gpa_blame *const *b, uint32_t count,
+                     hipStream_t s, Arena &ar);
 // estimate.hip
 void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint32_t k,
                   hipStream_t s, Arena &ar);
+// the advise of many profiles, each stage one launch over all of them
+void run_estimate_batch(const gpa_blame *const *b, gpa_advice *const *adv, uint32_t count,
+                        uint32_t k, hipStream_t s, Arena &ar);
+// at load: the top-k chunks of every kernel root (static)
+void build_topk_plan(gpa_program &p, hipStream_t s, Arena &ar);
 
 // Opt-in phase timing with hipEvents on the caller's stream (gpa_timing_*):
 // a phase records an event pair; the pair's elapsed time is accumulated when

@@ -13,29 +13,74 @@
 //   latency hiding     S = T / (T - min(A, M))             (Eq. 5; Eq. 4 at a kernel)
 // Subtree sums are direct sums over the contiguous preorder range of the
 // subtree, never differences of prefix sums.
+//
+// Every kernel takes one profile's EstArgs by value, or, in a batched
+// launch, reads the profile of its work item from a device table; each
+// element is computed by the same code in the same order either way, so a
+// profile's results do not depend on the batch it was advised in.
 #include "common.h"
 #include "devutil.h"
 
 namespace gpa {
 
 constexpr int kNV = 11;  // 9 optimizers, active, total
+constexpr int kEstThreads = 256;
 
-__global__ void k_instr_contrib(uint32_t n_instr, uint32_t nbl, uint32_t blamable,
-                                const uint32_t *counts, const double *blamed, const double *self_,
-                                const uint8_t *op_class, const uint8_t *tags, double *iv) {
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n_instr;
-       k += gridDim.x * blockDim.x) {
-    const uint32_t *C = counts + (size_t)k * 24;
-    const double *Bl = blamed + (size_t)k * 24;
-    const double *Sf = self_ + (size_t)k * 24;
+struct Cand {
+  double s;
+  uint32_t o, l;
+};
+
+// One profile's advise: its program's static groupings, its blame tables,
+// the scratch of the roll-up and the advice's outputs.
+struct EstArgs {
+  uint32_t n_instr, ns, nbl, n_roots, k, tk_chunks;
+  int32_t s_mem, s_exec;
+  uint64_t n_edges;
+  const uint32_t *counts;
+  const double *blamed, *self_, *share;
+  const uint8_t *op_class, *tags;
+  const uint32_t *e_src, *line_ptr, *line_perm, *icl_ptr, *icl_perm, *lca_ptr, *lca_perm;
+  const uint32_t *scope_end, *scope_parent, *root_of, *roots;
+  const uint32_t *big_list, *big_n, *big_chunk;   // 4 groupings x ns
+  uint32_t seg_chunks[4];
+  const uint32_t *tk_nch, *tk_cst;                // top-k chunks per kernel root
+  double *iv_g, *own, *sub, *ev_icl, *ev_lca;
+  double *partial[4];
+  Cand *cand;
+  double *active, *matched, *speedup, *kernel_T, *kernel_L, *eq3;
+  uint32_t *top_opt, *top_scope;
+  double *top_speed;
+};
+
+// a thread's elements: element `local * blockDim.x + threadIdx.x` of a
+// batched launch's profile, a grid-stride range of the one profile otherwise
+#define EST_ITEM(COUNT, VAR)                                                     \
+  const EstArgs &a = BATCH ? many[items[blockIdx.x].entry] : one;                \
+  const uint64_t first_ =                                                        \
+      (uint64_t)(BATCH ? items[blockIdx.x].local : blockIdx.x) * blockDim.x + threadIdx.x; \
+  const uint64_t count_ = (COUNT);                                               \
+  const uint64_t stride_ = BATCH ? count_ : (uint64_t)gridDim.x * blockDim.x;    \
+  for (uint64_t VAR = first_; VAR < count_; VAR += stride_)
+
+// per instruction, in line-grouped order: the contributions to the nine
+// optimizers (the two edge optimizers' come from the edges), active and total
+template <bool BATCH>
+__global__ void __launch_bounds__(kEstThreads)
+k_line_contrib(EstArgs one, const EstArgs *__restrict__ many, const WorkItem *__restrict__ items) {
+  EST_ITEM(a.n_instr, kk) {
+    const uint32_t k = a.line_perm[kk];
+    const uint32_t *C = a.counts + (size_t)k * 24;
+    const double *Bl = a.blamed + (size_t)k * 24;
+    const double *Sf = a.self_ + (size_t)k * 24;
     double act = 0.0, lat = 0.0, stalls = 0.0;
     for (int r = 0; r < 12; ++r) {
       act += (double)C[r * 2];
       lat += (double)C[r * 2 + 1];
       if (r != GPA_ST_SELECTED) stalls += (double)C[r * 2] + (double)C[r * 2 + 1];
     }
-    const uint32_t cls = op_class[k];
-    const uint8_t tg = tags[k];
+    const uint32_t cls = a.op_class[k];
+    const uint8_t tg = a.tags[k];
     double v[kNV];
     v[GPA_O_REGISTER_REUSE] = (cls == GPA_OP_LOCAL_LOAD || cls == GPA_OP_LOCAL_STORE)
                                   ? Bl[GPA_ST_MEM_DEP * 2] + Bl[GPA_ST_MEM_DEP * 2 + 1]
@@ -56,111 +101,159 @@ __global__ void k_instr_contrib(uint32_t n_instr, uint32_t nbl, uint32_t blamabl
     v[GPA_O_FUNCTION_INLINING] = (cls == GPA_OP_CALL || (tg & 2)) ? lat : 0.0;
     v[9] = act;
     v[10] = act + lat;
-    for (int q = 0; q < kNV; ++q) iv[(size_t)k * kNV + q] = v[q];
+    double *dst = a.iv_g + kk * kNV;
+#pragma unroll
+    for (int q = 0; q < kNV; ++q) dst[q] = v[q];
   }
 }
 
 // latency samples of global-memory and execution dependency stalls carried
 // by an edge (Loop Unrolling and Code Reordering)
-__device__ __forceinline__ double edge_contrib(uint64_t e, uint32_t nbl, int s_mem, int s_exec,
-                                               const uint32_t *e_src, const uint8_t *op_class,
-                                               const double *share) {
+__device__ __forceinline__ double edge_contrib(const EstArgs &a, uint64_t e) {
   double v = 0.0;
-  if (s_mem >= 0 && op_class[e_src[e]] == GPA_OP_GLOBAL_LOAD) v += share[(e * nbl + s_mem) * 2 + 1];
-  if (s_exec >= 0) v += share[(e * nbl + s_exec) * 2 + 1];
+  if (a.s_mem >= 0 && a.op_class[a.e_src[e]] == GPA_OP_GLOBAL_LOAD)
+    v += a.share[(e * a.nbl + a.s_mem) * 2 + 1];
+  if (a.s_exec >= 0) v += a.share[(e * a.nbl + a.s_exec) * 2 + 1];
   return v;
 }
 
 // the edge contributions straight into the common-loop and common-scope
 // groupings' orders (edges without a common loop are left out of the first:
-// its size is *n_icl)
-__global__ void k_edge_gathered(uint64_t n_edges, uint32_t nbl, int s_mem, int s_exec,
-                                const uint32_t *e_src, const uint8_t *op_class,
-                                const double *share, const uint32_t *n_icl,
-                                const uint32_t *icl_perm, const uint32_t *lca_perm, double *ev_icl,
-                                double *ev_lca) {
-  const uint64_t ni = min((uint64_t)*n_icl, n_edges);
-  for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n_edges;
-       k += (uint64_t)gridDim.x * blockDim.x) {
-    ev_lca[k] = edge_contrib(lca_perm[k], nbl, s_mem, s_exec, e_src, op_class, share);
-    if (k < ni) ev_icl[k] = edge_contrib(icl_perm[k], nbl, s_mem, s_exec, e_src, op_class, share);
+// its size is icl_ptr[ns])
+template <bool BATCH>
+__global__ void __launch_bounds__(kEstThreads)
+k_edge_contrib(EstArgs one, const EstArgs *__restrict__ many, const WorkItem *__restrict__ items) {
+  EST_ITEM(a.n_edges, k) {
+    const uint64_t ni = min((uint64_t)a.icl_ptr[a.ns], a.n_edges);
+    a.ev_lca[k] = edge_contrib(a, a.lca_perm[k]);
+    if (k < ni) a.ev_icl[k] = edge_contrib(a, a.icl_perm[k]);
   }
 }
 
-// values gathered into group order, so every group is a contiguous range;
-// the grouped count is n, or *n_dev when given (items without a group are
-// left out of the grouping)
-template <int W>
-__global__ void k_gather(size_t n, const uint32_t *n_dev, const uint32_t *perm, const double *src,
-                         double *dst) {
-  if (n_dev) n = min(n, (size_t)*n_dev);
-  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
-       k += (size_t)gridDim.x * blockDim.x) {
-    const double *x = src + (size_t)perm[k] * W;
-#pragma unroll
-    for (int q = 0; q < W; ++q) dst[k * W + q] = x[q];
-  }
-}
-
-// Segmented sums over contiguous ranges [begin(l), end(l)), given either by
-// ptr[l], ptr[l+1] (ptr mode) or by l, end[l] (subtree mode).  A segment of
-// at most kSmallSeg elements is summed by one thread in element order; the
-// longer ones (listed once at load, with their chunk counts) in chunks of
-// kSegChunk by one workgroup each, every thread owning a fixed stride and the
-// reduction a fixed shape, and the chunks then in order.  Either way the
-// result does not depend on scheduling.  One launch serves up to two
-// independent sets of segments (grid row y = set).
-struct SegSet {
+// Segmented sums over contiguous ranges [begin(l), end(l)) of the four
+// groupings g: 0 instructions by line (W = 11, into own), 1 edges by common
+// loop and 2 edges by common scope (W = 1, into own's Loop Unrolling and
+// Code Reordering columns, after grouping 0), 3 scope subtrees (ranges l to
+// scope_end[l] of own, W = 11, into sub).  A segment of at most kSmallSeg
+// elements is summed by one thread in element order; the longer ones
+// (listed once at load, with their chunk counts) in chunks of kSegChunk by
+// one workgroup each, every thread owning a fixed stride and the reduction a
+// fixed shape, and the chunks then in order.  Either way the result does not
+// depend on scheduling.
+struct SegView {
   const uint32_t *ptr, *end;          // segment bounds (ptr mode when ptr)
   const uint32_t *big_list, *big_n;   // the long segments
   const uint32_t *chunk_start;        // their first chunk
-  uint32_t n_chunks;
+  uint32_t n_chunks, out_stride, out_off;
   const double *data;
   double *out, *partial;
 };
-struct SegSets {
-  SegSet set[2];
-};
+
+template <int G>
+__device__ __forceinline__ SegView seg_view(const EstArgs &a) {
+  SegView v;
+  v.ptr = G == 0 ? a.line_ptr : G == 1 ? a.icl_ptr : G == 2 ? a.lca_ptr : nullptr;
+  v.end = G == 3 ? a.scope_end : nullptr;
+  v.big_list = a.big_list + (size_t)G * a.ns;
+  v.big_n = a.big_n + G;
+  v.chunk_start = a.big_chunk + (size_t)G * a.ns;
+  v.n_chunks = a.seg_chunks[G];
+  v.data = G == 0 ? a.iv_g : G == 1 ? a.ev_icl : G == 2 ? a.ev_lca : a.own;
+  v.out = G == 3 ? a.sub : a.own;
+  v.out_stride = (G == 1 || G == 2) ? kNV : 1;
+  v.out_off = G == 1 ? GPA_O_LOOP_UNROLLING : G == 2 ? GPA_O_CODE_REORDERING : 0;
+  v.partial = a.partial[G];
+  return v;
+}
+
+// grid row y picks grouping G0 + y when NG = 2 (the two edge groupings
+// share launches)
+template <int G0, int NG>
+__device__ __forceinline__ SegView pick_view(const EstArgs &a) {
+  if constexpr (NG == 2) {
+    static_assert(G0 == 1, "the edge groupings");
+    // field by field, so that no view is selected as a whole in memory
+    const bool y = blockIdx.y != 0;
+    SegView v;
+    v.ptr = y ? a.lca_ptr : a.icl_ptr;
+    v.end = nullptr;
+    v.big_list = a.big_list + (size_t)(y ? 2 : 1) * a.ns;
+    v.big_n = a.big_n + (y ? 2 : 1);
+    v.chunk_start = a.big_chunk + (size_t)(y ? 2 : 1) * a.ns;
+    v.n_chunks = y ? a.seg_chunks[2] : a.seg_chunks[1];
+    v.out_stride = kNV;
+    v.out_off = y ? GPA_O_CODE_REORDERING : GPA_O_LOOP_UNROLLING;
+    v.data = y ? a.ev_lca : a.ev_icl;
+    v.out = a.own;
+    v.partial = y ? a.partial[2] : a.partial[1];
+    return v;
+  } else {
+    return seg_view<G0>(a);
+  }
+}
+
+// segment l's range: ptr mode for groupings 0-2, subtree mode for 3
+template <int G0>
+__device__ __forceinline__ uint32_t seg_lo(const SegView &S, uint32_t l) {
+  if constexpr (G0 == 3) return l;
+  else return S.ptr[l];
+}
+template <int G0>
+__device__ __forceinline__ uint32_t seg_hi(const SegView &S, uint32_t l) {
+  if constexpr (G0 == 3) return S.end[l];
+  else return S.ptr[l + 1];
+}
 
 template <int W>
-__global__ void k_seg_small(uint32_t n_seg, SegSets sets) {
-  const SegSet &S = sets.set[blockIdx.y];
-  for (uint32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < n_seg;
-       l += gridDim.x * blockDim.x) {
-    const uint32_t a = S.ptr ? S.ptr[l] : l;
-    const uint32_t b = S.ptr ? S.ptr[l + 1] : S.end[l];
-    if (b - a > kSmallSeg) continue;
-    double v[W];
+__device__ __forceinline__ void seg_store(const SegView &S, uint32_t l, const double (&v)[W]) {
+  double *o = S.out + ((size_t)l * W) * S.out_stride + S.out_off;
 #pragma unroll
-    for (int q = 0; q < W; ++q) v[q] = 0.0;
-    for (uint32_t i = a; i < b; ++i)
+  for (int q = 0; q < W; ++q) o[q] = v[q];
+}
+
+template <int W, int G0, int NG, bool BATCH>
+__global__ void __launch_bounds__(kEstThreads)
+k_seg_small(EstArgs one, const EstArgs *__restrict__ many, const WorkItem *__restrict__ items) {
+  EST_ITEM(a.ns, lw) {
+    const uint32_t l = (uint32_t)lw;
+    const SegView S = pick_view<G0, NG>(a);
+    const uint32_t b0 = seg_lo<G0>(S, l), b1 = seg_hi<G0>(S, l);
+    if (b1 - b0 <= kSmallSeg) {
+      double v[W];
 #pragma unroll
-      for (int q = 0; q < W; ++q) v[q] += S.data[(size_t)i * W + q];
+      for (int q = 0; q < W; ++q) v[q] = 0.0;
+      for (uint32_t i = b0; i < b1; ++i)
 #pragma unroll
-    for (int q = 0; q < W; ++q) S.out[(size_t)l * W + q] = v[q];
+        for (int q = 0; q < W; ++q) v[q] += S.data[(size_t)i * W + q];
+      seg_store<W>(S, l, v);
+    }
   }
 }
 
 // Segments longer than kSmallSeg, in chunks of kSegChunk elements: one
 // workgroup per chunk (element order within a thread's stride, then the
 // waves' sums in a fixed shape), then per segment its chunks in order.
-template <int W>
-__global__ void __launch_bounds__(256)
-k_seg_chunks(SegSets sets) {
+template <int W, int G0, int NG, bool BATCH>
+__global__ void __launch_bounds__(kEstThreads)
+k_seg_chunks(EstArgs one, const EstArgs *__restrict__ many, const WorkItem *__restrict__ items) {
+  static_assert(kEstThreads == 256, "four waves");
   __shared__ double red[4][W];
-  const SegSet &S = sets.set[blockIdx.y];
+  const EstArgs &a = BATCH ? many[items[blockIdx.x].entry] : one;
+  const SegView S = pick_view<G0, NG>(a);
   const uint32_t nl = *S.big_n;
-  for (uint32_t c = blockIdx.x; c < S.n_chunks; c += gridDim.x) {
+  const uint32_t c0 = BATCH ? items[blockIdx.x].local : blockIdx.x;
+  const uint32_t cstep = BATCH ? S.n_chunks : gridDim.x;
+  for (uint32_t c = c0; c < S.n_chunks; c += cstep) {
     const uint32_t j = upper_index_u32(S.chunk_start, 0, nl, c);
     const uint32_t l = S.big_list[j];
-    const uint32_t a0 = S.ptr ? S.ptr[l] : l, b0 = S.ptr ? S.ptr[l + 1] : S.end[l];
-    const uint32_t a = a0 + (c - S.chunk_start[j]) * kSegChunk, b = min(a + kSegChunk, b0);
+    const uint32_t a0 = seg_lo<G0>(S, l), b0 = seg_hi<G0>(S, l);
+    const uint32_t lo = a0 + (c - S.chunk_start[j]) * kSegChunk, hi = min(lo + kSegChunk, b0);
     const double *data = S.data;
     double v[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) v[q] = 0.0;
-    uint32_t i = a + threadIdx.x;
-    for (; i + 3 * 256 < b; i += 4 * 256) {
+    uint32_t i = lo + threadIdx.x;
+    for (; i + 3 * 256 < hi; i += 4 * 256) {
       double t0[W], t1[W], t2[W], t3[W];
 #pragma unroll
       for (int q = 0; q < W; ++q) {
@@ -172,7 +265,7 @@ k_seg_chunks(SegSets sets) {
 #pragma unroll
       for (int q = 0; q < W; ++q) v[q] += ((t0[q] + t1[q]) + (t2[q] + t3[q]));
     }
-    for (; i < b; i += 256) {
+    for (; i < hi; i += 256) {
 #pragma unroll
       for (int q = 0; q < W; ++q) v[q] += data[(size_t)i * W + q];
     }
@@ -190,11 +283,14 @@ k_seg_chunks(SegSets sets) {
   }
 }
 
-template <int W>
-__global__ void k_seg_combine(SegSets sets) {
-  const SegSet &S = sets.set[blockIdx.y];
-  const uint32_t nl = *S.big_n;
-  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nl; j += gridDim.x * blockDim.x) {
+template <int W, int G0, int NG, bool BATCH>
+__global__ void __launch_bounds__(kEstThreads)
+k_seg_combine(EstArgs one, const EstArgs *__restrict__ many, const WorkItem *__restrict__ items) {
+  const EstArgs &a0 = BATCH ? many[items[blockIdx.x].entry] : one;
+  const SegView S0 = pick_view<G0, NG>(a0);
+  EST_ITEM(*S0.big_n, jw) {
+    const SegView &S = S0;
+    const uint32_t j = (uint32_t)jw, nl = *S.big_n;
     const uint32_t c0 = S.chunk_start[j], c1 = (j + 1 < nl) ? S.chunk_start[j + 1] : S.n_chunks;
     double v[W];
 #pragma unroll
@@ -202,39 +298,7 @@ __global__ void k_seg_combine(SegSets sets) {
     for (uint32_t c = c0; c < c1; ++c)
 #pragma unroll
       for (int q = 0; q < W; ++q) v[q] += S.partial[(size_t)c * W + q];
-    const uint32_t l = S.big_list[j];
-#pragma unroll
-    for (int q = 0; q < W; ++q) S.out[(size_t)l * W + q] = v[q];
-  }
-}
-
-// the sums of n_sets (1 or 2) sets of n_seg segments each
-template <int W>
-void seg_sum(uint32_t n_seg, SegSets sets, uint32_t n_sets, hipStream_t s, Arena &ar) {
-  uint64_t max_chunks = 0;
-  for (uint32_t y = 0; y < n_sets; ++y) {
-    SegSet &S = sets.set[y];
-    S.partial = S.n_chunks ? ar.get<double>((size_t)S.n_chunks * W) : nullptr;
-    max_chunks = std::max<uint64_t>(max_chunks, S.n_chunks);
-  }
-  hipLaunchKernelGGL(k_seg_small<W>, dim3(grid_for(n_seg, 256, 8192), n_sets), dim3(256), 0, s,
-                     n_seg, sets);
-  if (max_chunks) {
-    hipLaunchKernelGGL(k_seg_chunks<W>, dim3((unsigned)std::min<uint64_t>(max_chunks, 4096), n_sets),
-                       dim3(256), 0, s, sets);
-    hipLaunchKernelGGL(k_seg_combine<W>, dim3(grid_for(n_seg, 256, 1024), n_sets), dim3(256), 0, s,
-                       sets);
-  }
-  GPA_LAUNCH_CHECK();
-}
-
-// own sums of the two edge optimizers, merged into the per-scope vectors
-__global__ void k_merge_edge_own(uint32_t n_scopes, const double *own_icl, const double *own_lca,
-                                 double *own) {
-  for (uint32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < n_scopes;
-       l += gridDim.x * blockDim.x) {
-    own[(size_t)l * kNV + GPA_O_LOOP_UNROLLING] = own_icl[l];
-    own[(size_t)l * kNV + GPA_O_CODE_REORDERING] = own_lca[l];
+    seg_store<W>(S, S.big_list[j], v);
   }
 }
 
@@ -244,26 +308,26 @@ __device__ __forceinline__ double saturating_speedup(double T, double y) {
   return (T == 0.0) ? 1.0 : (y >= T ? __builtin_huge_val() : T / (T - y));
 }
 
-__global__ void k_speedup(uint32_t n_scopes, const uint32_t *parent, const uint32_t *root_of,
-                          const double *sub, double *active, double *matched, double *speedup,
-                          double *kernel_T, double *kernel_L, double *eq3) {
-  for (uint32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < n_scopes;
-       l += gridDim.x * blockDim.x) {
-    const double *x = sub + (size_t)l * kNV;
-    const double T = sub[(size_t)root_of[l] * kNV + 10];
+template <bool BATCH>
+__global__ void __launch_bounds__(kEstThreads)
+k_speedup(EstArgs one, const EstArgs *__restrict__ many, const WorkItem *__restrict__ items) {
+  EST_ITEM(a.ns, lw) {
+    const uint32_t l = (uint32_t)lw;
+    const double *x = a.sub + (size_t)l * kNV;
+    const double T = a.sub[(size_t)a.root_of[l] * kNV + 10];
     const double A = x[9];
-    active[l] = A;
+    a.active[l] = A;
     for (int o = 0; o < GPA_N_OPT; ++o) {
       const double M = x[o];
       const double y = (o >= GPA_O_LOOP_UNROLLING) ? (A < M ? A : M) : M;
-      matched[(size_t)l * GPA_N_OPT + o] = M;
-      speedup[(size_t)l * GPA_N_OPT + o] = saturating_speedup(T, y);
+      a.matched[(size_t)l * GPA_N_OPT + o] = M;
+      a.speedup[(size_t)l * GPA_N_OPT + o] = saturating_speedup(T, y);
     }
-    const bool root = parent[l] == GPA_NONE;
-    kernel_T[l] = root ? T : 0.0;
-    kernel_L[l] = root ? T - A : 0.0;
+    const bool root = a.scope_parent[l] == GPA_NONE;
+    a.kernel_T[l] = root ? T : 0.0;
+    a.kernel_L[l] = root ? T - A : 0.0;
     for (int h = 0; h < 3; ++h)
-      eq3[(size_t)l * 3 + h] = root ? saturating_speedup(T, x[GPA_O_LOOP_UNROLLING + h]) : 0.0;
+      a.eq3[(size_t)l * 3 + h] = root ? saturating_speedup(T, x[GPA_O_LOOP_UNROLLING + h]) : 0.0;
   }
 }
 
@@ -276,11 +340,6 @@ __global__ void k_speedup(uint32_t n_scopes, const uint32_t *parent, const uint3
 // chunks' winners, carrying the best 16 across rounds of kTopChunk.  Order:
 // speedup descending, then optimizer, then scope ascending (a total order,
 // so the result is unique).
-struct Cand {
-  double s;
-  uint32_t o, l;
-};
-
 // written with non-short-circuit operators so that it compiles to a few
 // compares and mask operations rather than divergent branches
 __device__ __forceinline__ bool better(const Cand &a, const Cand &b) {
@@ -377,6 +436,7 @@ __device__ void select_top(Cand (&my)[kPerThread], Cand *out, Cand (*xch)[kTopTh
   }
 }
 
+
 __global__ void k_topk_plan(uint32_t n_roots, const uint32_t *roots, const uint32_t *scope_end,
                             uint32_t *nchunks) {
   for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n_roots; r += gridDim.x * blockDim.x) {
@@ -385,19 +445,19 @@ __global__ void k_topk_plan(uint32_t n_roots, const uint32_t *roots, const uint3
   }
 }
 
+// chunk c of a profile's kernels (c < tk_chunks): the best kTopK of its items
+template <bool BATCH>
 __global__ void __launch_bounds__(kTopThreads)
-k_topk_chunks(uint32_t n_roots, const uint32_t *roots, const uint32_t *nchunks,
-              const uint32_t *chunk_start, const uint32_t *scope_end, const double *speedup,
-              Cand *cand) {
+k_topk_chunks(EstArgs one, const EstArgs *__restrict__ many, const WorkItem *__restrict__ items) {
   __shared__ Cand xch[2][kTopThreads / kWave];
-  const uint32_t c = blockIdx.x;
-  const uint32_t total = chunk_start[n_roots - 1] + nchunks[n_roots - 1];
-  if (c >= total) return;
-  const uint32_t ri = upper_index_u32(chunk_start, 0, n_roots, c);
-  const uint32_t r = roots[ri];
-  const uint64_t n_items = (uint64_t)(scope_end[r] - r) * GPA_N_OPT;
-  const uint64_t base = (uint64_t)(c - chunk_start[ri]) * kTopChunk;
-  const double *sp = speedup + (size_t)r * GPA_N_OPT;
+  const EstArgs &a = BATCH ? many[items[blockIdx.x].entry] : one;
+  const uint32_t c = BATCH ? items[blockIdx.x].local : blockIdx.x;
+  if (c >= a.tk_chunks) return;
+  const uint32_t ri = upper_index_u32(a.tk_cst, 0, a.n_roots, c);
+  const uint32_t r = a.roots[ri];
+  const uint64_t n_items = (uint64_t)(a.scope_end[r] - r) * GPA_N_OPT;
+  const uint64_t base = (uint64_t)(c - a.tk_cst[ri]) * kTopChunk;
+  const double *sp = a.speedup + (size_t)r * GPA_N_OPT;
   Cand my[kPerThread];
 #pragma unroll
   for (int i = 0; i < kPerThread; ++i) {
@@ -411,18 +471,20 @@ k_topk_chunks(uint32_t n_roots, const uint32_t *roots, const uint32_t *nchunks,
     my[i] = x;
   }
   sort8(my);
-  select_top(my, cand + (size_t)c * kTopK, xch);
+  select_top(my, a.cand + (size_t)c * kTopK, xch);
 }
 
+// one workgroup per kernel root (the ri-th, its row of the output)
+template <bool BATCH>
 __global__ void __launch_bounds__(kTopThreads)
-k_topk_final(const uint32_t *nchunks, const uint32_t *chunk_start,
-             const Cand *cand, uint32_t k, uint32_t *top_opt, uint32_t *top_scope,
-             double *top_speed) {
+k_topk_final(EstArgs one, const EstArgs *__restrict__ many, const WorkItem *__restrict__ items) {
   __shared__ Cand xch[2][kTopThreads / kWave];
   __shared__ Cand best[kTopK];
-  const uint32_t ri = blockIdx.x;   // the ri-th kernel root; its row of the output
-  const uint32_t n = nchunks[ri] * kTopK;
-  const Cand *src = cand + (size_t)chunk_start[ri] * kTopK;
+  const EstArgs &a = BATCH ? many[items[blockIdx.x].entry] : one;
+  const uint32_t ri = BATCH ? items[blockIdx.x].local : blockIdx.x;
+  const uint32_t k = a.k;
+  const uint32_t n = a.tk_nch[ri] * kTopK;
+  const Cand *src = a.cand + (size_t)a.tk_cst[ri] * kTopK;
   // round 0 takes kTopChunk candidates; later rounds carry the best kTopK in
   // slots 0 .. kTopK-1 (item 0 of threads 0 .. 15) and take the rest anew
   uint32_t next = 0;
@@ -447,84 +509,215 @@ k_topk_final(const uint32_t *nchunks, const uint32_t *chunk_start,
   }
   for (uint32_t t = threadIdx.x; t < k; t += kTopThreads) {
     const Cand c = t < (uint32_t)kTopK ? best[t] : cand_none();
-    top_opt[(size_t)ri * k + t] = c.o;
-    top_scope[(size_t)ri * k + t] = c.l;
-    top_speed[(size_t)ri * k + t] = c.o == 0xFFFFFFFFu ? 0.0 : c.s;
+    a.top_opt[(size_t)ri * k + t] = c.o;
+    a.top_scope[(size_t)ri * k + t] = c.l;
+    a.top_speed[(size_t)ri * k + t] = c.o == 0xFFFFFFFFu ? 0.0 : c.s;
   }
 }
 
-void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint32_t k,
-                  hipStream_t s, Arena &ar) {
-  const uint32_t n = p.n_instr, ns = p.n_scopes, nbl = p.n_blamable;
-  const uint32_t bl = p.arch.blamable;
-  const int s_mem = ((bl >> GPA_ST_MEM_DEP) & 1) ? __builtin_popcount(bl & ((1u << GPA_ST_MEM_DEP) - 1)) : -1;
-  const int s_exec =
-      ((bl >> GPA_ST_EXEC_DEP) & 1) ? __builtin_popcount(bl & ((1u << GPA_ST_EXEC_DEP) - 1)) : -1;
-  double *iv = ar.get<double>((size_t)n * kNV);
-  double *own = ar.get<double>((size_t)ns * kNV);
-  double *sub = ar.get<double>((size_t)ns * kNV);
-  double *iv_g = ar.get<double>((size_t)n * kNV);
-  double *ev_icl = ar.get<double>(p.n_edges), *ev_lca = ar.get<double>(p.n_edges);
-  double *own_icl = ar.get<double>(ns), *own_lca = ar.get<double>(ns);
-  hipLaunchKernelGGL(k_instr_contrib, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, nbl, bl,
-                     b.counts.p, b.blamed.p, b.self_.p, p.op_class.p, p.instr_tags.p, iv);
-  hipLaunchKernelGGL(k_gather<kNV>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, (size_t)n,
-                     nullptr, p.line_perm, iv, iv_g);
-  const uint32_t *big = p.big_list.p;
-  const uint32_t *bch = p.big_chunk.p;
-  // groupings g (0 line, 1 common loop, 2 common scope, 3 subtree): their
-  // long-segment lists and chunk counts were made at load
-  auto seg_set = [&](int g, const uint32_t *ptr, const uint32_t *end, const double *data,
-                     double *out) {
-    return SegSet{ptr, end, big + (size_t)g * ns, p.big_n.p + g, bch + (size_t)g * ns,
-                  (uint32_t)p.seg_chunks[g], data, out, nullptr};
-  };
-  SegSets line{};
-  line.set[0] = seg_set(0, p.line_ptr, nullptr, iv_g, own);
-  seg_sum<kNV>(ns, line, 1, s, ar);
-  if (p.n_edges)
-    hipLaunchKernelGGL(k_edge_gathered, dim3(grid_for(p.n_edges, 256, 8192)), dim3(256), 0, s,
-                       p.n_edges, nbl, s_mem, s_exec, p.e_src.p, p.op_class.p, b.share.p,
-                       p.icl_ptr + ns, p.icl_perm, p.lca_perm, ev_icl, ev_lca);
-  SegSets edges{};
-  edges.set[0] = seg_set(1, p.icl_ptr, nullptr, ev_icl, own_icl);
-  edges.set[1] = seg_set(2, p.lca_ptr, nullptr, ev_lca, own_lca);
-  seg_sum<1>(ns, edges, 2, s, ar);
-  hipLaunchKernelGGL(k_merge_edge_own, dim3(grid_for(ns, 256, 8192)), dim3(256), 0, s, ns, own_icl,
-                     own_lca, own);
-  SegSets subtree{};
-  subtree.set[0] = seg_set(3, nullptr, p.scope_end.p, own, sub);
-  seg_sum<kNV>(ns, subtree, 1, s, ar);
+// ------------------------------------------------------------------- host
+void build_topk_plan(gpa_program &p, hipStream_t s, Arena &ar) {
+  if (p.n_roots_dev) {
+    p.n_roots = read_scalar(p.n_roots_dev, s);
+    p.n_roots_dev = nullptr;
+  }
+  p.tk_nch.alloc(p.n_roots);
+  p.tk_cst.alloc(p.n_roots);
+  p.tk_total_dev = nullptr;
+  if (p.n_roots == 0) return;
+  hipLaunchKernelGGL(k_topk_plan, dim3(grid_for(p.n_roots, 256, 1024)), dim3(256), 0, s,
+                     p.n_roots, p.roots.p, p.scope_end.p, p.tk_nch.p);
   GPA_LAUNCH_CHECK();
-  a.active.alloc(ns);
-  a.matched.alloc((size_t)ns * GPA_N_OPT);
-  a.speedup.alloc((size_t)ns * GPA_N_OPT);
-  a.kernel_T.alloc(ns);
-  a.kernel_L.alloc(ns);
-  a.eq3.alloc((size_t)ns * 3);
-  hipLaunchKernelGGL(k_speedup, dim3(grid_for(ns, 256, 8192)), dim3(256), 0, s, ns,
-                     p.scope_parent.p, p.root_of.p, sub, a.active.p, a.matched.p, a.speedup.p,
-                     a.kernel_T.p, a.kernel_L.p, a.eq3.p);
-  GPA_LAUNCH_CHECK();
+  p.tk_total_dev = ar.get<unsigned long long>(1);
+  exclusive_scan_u32(p.tk_nch.p, p.tk_cst.p, p.n_roots, s, ar, p.tk_total_dev);
+}
+
+static int reason_slot(uint32_t bl, int r) {
+  return ((bl >> r) & 1) ? __builtin_popcount(bl & ((1u << r) - 1)) : -1;
+}
+
+// the arguments of one profile's advise; scratch from the arena, outputs
+// allocated in the advice handle
+static EstArgs est_args(const gpa_program &p, const gpa_blame &b, gpa_advice &adv, uint32_t k,
+                        Arena &ar) {
+  const uint32_t n = p.n_instr, ns = p.n_scopes;
+  EstArgs a{};
+  a.n_instr = n;
+  a.ns = ns;
+  a.nbl = p.n_blamable;
+  a.n_roots = p.n_roots;
   a.k = k;
+  a.tk_chunks = p.tk_chunks;
+  a.s_mem = reason_slot(p.arch.blamable, GPA_ST_MEM_DEP);
+  a.s_exec = reason_slot(p.arch.blamable, GPA_ST_EXEC_DEP);
+  a.n_edges = p.n_edges;
+  a.counts = b.counts.p;
+  a.blamed = b.blamed.p;
+  a.self_ = b.self_.p;
+  a.share = b.share.p;
+  a.op_class = p.op_class.p;
+  a.tags = p.instr_tags.p;
+  a.e_src = p.e_src.p;
+  a.line_ptr = p.line_ptr;
+  a.line_perm = p.line_perm;
+  a.icl_ptr = p.icl_ptr;
+  a.icl_perm = p.icl_perm;
+  a.lca_ptr = p.lca_ptr;
+  a.lca_perm = p.lca_perm;
+  a.scope_end = p.scope_end.p;
+  a.scope_parent = p.scope_parent.p;
+  a.root_of = p.root_of.p;
+  a.roots = p.roots.p;
+  a.big_list = p.big_list.p;
+  a.big_n = p.big_n.p;
+  a.big_chunk = p.big_chunk.p;
+  for (int g = 0; g < 4; ++g) a.seg_chunks[g] = (uint32_t)p.seg_chunks[g];
+  a.tk_nch = p.tk_nch.p;
+  a.tk_cst = p.tk_cst.p;
+  a.iv_g = ar.get<double>((size_t)n * kNV);
+  a.own = ar.get<double>((size_t)ns * kNV);
+  a.sub = ar.get<double>((size_t)ns * kNV);
+  a.ev_icl = ar.get<double>(p.n_edges);
+  a.ev_lca = ar.get<double>(p.n_edges);
+  for (int g = 0; g < 4; ++g)
+    a.partial[g] = ar.get<double>((size_t)a.seg_chunks[g] * (g == 0 || g == 3 ? kNV : 1));
+  a.cand = ar.get<Cand>((size_t)p.tk_chunks * kTopK);
+  adv.active.alloc(ns);
+  adv.matched.alloc((size_t)ns * GPA_N_OPT);
+  adv.speedup.alloc((size_t)ns * GPA_N_OPT);
+  adv.kernel_T.alloc(ns);
+  adv.kernel_L.alloc(ns);
+  adv.eq3.alloc((size_t)ns * 3);
+  adv.k = k;
   // one row of k per kernel root, in the order of p.roots (ascending scope)
-  a.top_opt.alloc((size_t)p.n_roots * k);
-  a.top_scope.alloc((size_t)p.n_roots * k);
-  a.top_speed.alloc((size_t)p.n_roots * k);
-  if (k) {
-    if (p.n_roots) {
-      uint32_t *nch = ar.get<uint32_t>(p.n_roots), *cst = ar.get<uint32_t>(p.n_roots);
-      hipLaunchKernelGGL(k_topk_plan, dim3(grid_for(p.n_roots, 256, 1024)), dim3(256), 0, s,
-                         p.n_roots, p.roots.p, p.scope_end.p, nch);
-      exclusive_scan_u32(nch, cst, p.n_roots, s, ar);
-      // every scope is in exactly one kernel's subtree: chunks <= items/chunk + roots
-      const uint64_t max_chunks = ((uint64_t)ns * GPA_N_OPT) / kTopChunk + p.n_roots + 1;
-      Cand *cand = ar.get<Cand>(max_chunks * kTopK);
-      hipLaunchKernelGGL(k_topk_chunks, dim3((unsigned)max_chunks), dim3(kTopThreads), 0, s,
-                         p.n_roots, p.roots.p, nch, cst, p.scope_end.p, a.speedup.p, cand);
-      hipLaunchKernelGGL(k_topk_final, dim3(p.n_roots), dim3(kTopThreads), 0, s, nch, cst, cand,
-                         k, a.top_opt.p, a.top_scope.p, a.top_speed.p);
+  adv.top_opt.alloc((size_t)p.n_roots * k);
+  adv.top_scope.alloc((size_t)p.n_roots * k);
+  adv.top_speed.alloc((size_t)p.n_roots * k);
+  a.active = adv.active.p;
+  a.matched = adv.matched.p;
+  a.speedup = adv.speedup.p;
+  a.kernel_T = adv.kernel_T.p;
+  a.kernel_L = adv.kernel_L.p;
+  a.eq3 = adv.eq3.p;
+  a.top_opt = adv.top_opt.p;
+  a.top_scope = adv.top_scope.p;
+  a.top_speed = adv.top_speed.p;
+  return a;
+}
+
+// launches over one profile (BATCH = false: grid-stride, args by value) or
+// over a batch (work lists per stage, args from the device table)
+struct EstLaunch {
+  hipStream_t s;
+  EstArgs one;
+  const EstArgs *many = nullptr;
+  template <typename K>
+  void operator()(K kern, unsigned gx, unsigned gy, const WorkItem *items) {
+    if (gx == 0) return;
+    hipLaunchKernelGGL(kern, dim3(gx, gy), dim3(kEstThreads), 0, s, one, many, items);
+    GPA_LAUNCH_CHECK();
+  }
+};
+
+void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &adv, uint32_t k,
+                  hipStream_t s, Arena &ar) {
+  EstLaunch L{s, est_args(p, b, adv, k, ar)};
+  const EstArgs &a = L.one;
+  const uint32_t n = p.n_instr, ns = p.n_scopes;
+  const unsigned gi = grid_for(n, kEstThreads, 8192), gs = grid_for(ns, kEstThreads, 8192);
+  auto chunks = [](uint32_t c) { return (unsigned)std::min<uint32_t>(c, 4096); };
+  auto combine = [&](uint32_t c) { return c ? grid_for(c, kEstThreads, 1024) : 0u; };
+  L(k_line_contrib<false>, gi, 1, nullptr);
+  L(k_seg_small<kNV, 0, 1, false>, gs, 1, nullptr);
+  L(k_seg_chunks<kNV, 0, 1, false>, chunks(a.seg_chunks[0]), 1, nullptr);
+  L(k_seg_combine<kNV, 0, 1, false>, combine(a.seg_chunks[0]), 1, nullptr);
+  if (p.n_edges) L(k_edge_contrib<false>, grid_for(p.n_edges, kEstThreads, 8192), 1, nullptr);
+  L(k_seg_small<1, 1, 2, false>, gs, 2, nullptr);
+  const uint32_t ce = std::max(a.seg_chunks[1], a.seg_chunks[2]);
+  L(k_seg_chunks<1, 1, 2, false>, chunks(ce), 2, nullptr);
+  L(k_seg_combine<1, 1, 2, false>, combine(ce), 2, nullptr);
+  L(k_seg_small<kNV, 3, 1, false>, gs, 1, nullptr);
+  L(k_seg_chunks<kNV, 3, 1, false>, chunks(a.seg_chunks[3]), 1, nullptr);
+  L(k_seg_combine<kNV, 3, 1, false>, combine(a.seg_chunks[3]), 1, nullptr);
+  L(k_speedup<false>, gs, 1, nullptr);
+  if (k && p.n_roots) {
+    hipLaunchKernelGGL(k_topk_chunks<false>, dim3(std::max(p.tk_chunks, 1u)), dim3(kTopThreads), 0,
+                       s, L.one, nullptr, nullptr);
+    GPA_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_topk_final<false>, dim3(p.n_roots), dim3(kTopThreads), 0, s, L.one,
+                       nullptr, nullptr);
+    GPA_LAUNCH_CHECK();
+  }
+}
+
+void run_estimate_batch(const gpa_blame *const *b, gpa_advice *const *adv, uint32_t count,
+                        uint32_t k, hipStream_t s, Arena &ar) {
+  std::vector<EstArgs> args(count);
+  // work lists, one per stage: instructions, scopes, edges, chunks of each
+  // grouping, long segments, top-k chunks and kernel roots
+  std::vector<WorkItem> w_instr, w_scope, w_edge, w_ch[3], w_cb[3], w_tkc, w_tkf;
+  auto tiles = [](std::vector<WorkItem> &v, uint32_t e, uint64_t n, uint32_t per) {
+    for (uint64_t t = 0; t * per < n; ++t) v.push_back({e, (uint32_t)t});
+  };
+  for (uint32_t e = 0; e < count; ++e) {
+    const gpa_program &p = *b[e]->prog;
+    args[e] = est_args(p, *b[e], *adv[e], k, ar);
+    const EstArgs &a = args[e];
+    tiles(w_instr, e, p.n_instr, kEstThreads);
+    tiles(w_scope, e, p.n_scopes, kEstThreads);
+    tiles(w_edge, e, p.n_edges, kEstThreads);
+    const uint32_t nc[3] = {a.seg_chunks[0], std::max(a.seg_chunks[1], a.seg_chunks[2]),
+                            a.seg_chunks[3]};
+    for (int g = 0; g < 3; ++g) {
+      tiles(w_ch[g], e, nc[g], 1);
+      tiles(w_cb[g], e, nc[g], kEstThreads);   // long segments <= chunks
     }
+    if (k && p.n_roots) {
+      tiles(w_tkc, e, p.tk_chunks, 1);
+      tiles(w_tkf, e, p.n_roots, 1);
+    }
+  }
+  EstLaunch L{s, EstArgs{}, ar.upload(args, s)};
+  auto up = [&](const std::vector<WorkItem> &v) {
+    return std::make_pair(ar.upload(v, s), (unsigned)v.size());
+  };
+  auto [i_instr, n_instr] = up(w_instr);
+  auto [i_scope, n_scope] = up(w_scope);
+  auto [i_edge, n_edge] = up(w_edge);
+  L(k_line_contrib<true>, n_instr, 1, i_instr);
+  L(k_seg_small<kNV, 0, 1, true>, n_scope, 1, i_scope);
+  {
+    auto [ic, nc] = up(w_ch[0]);
+    L(k_seg_chunks<kNV, 0, 1, true>, nc, 1, ic);
+    auto [ib, nb] = up(w_cb[0]);
+    L(k_seg_combine<kNV, 0, 1, true>, nb, 1, ib);
+  }
+  L(k_edge_contrib<true>, n_edge, 1, i_edge);
+  L(k_seg_small<1, 1, 2, true>, n_scope, 2, i_scope);
+  {
+    auto [ic, nc] = up(w_ch[1]);
+    L(k_seg_chunks<1, 1, 2, true>, nc, 2, ic);
+    auto [ib, nb] = up(w_cb[1]);
+    L(k_seg_combine<1, 1, 2, true>, nb, 2, ib);
+  }
+  L(k_seg_small<kNV, 3, 1, true>, n_scope, 1, i_scope);
+  {
+    auto [ic, nc] = up(w_ch[2]);
+    L(k_seg_chunks<kNV, 3, 1, true>, nc, 1, ic);
+    auto [ib, nb] = up(w_cb[2]);
+    L(k_seg_combine<kNV, 3, 1, true>, nb, 1, ib);
+  }
+  L(k_speedup<true>, n_scope, 1, i_scope);
+  auto [i_tkc, n_tkc] = up(w_tkc);
+  auto [i_tkf, n_tkf] = up(w_tkf);
+  if (n_tkc) {
+    hipLaunchKernelGGL(k_topk_chunks<true>, dim3(n_tkc), dim3(kTopThreads), 0, s, EstArgs{},
+                       L.many, i_tkc);
+    GPA_LAUNCH_CHECK();
+  }
+  if (n_tkf) {
+    hipLaunchKernelGGL(k_topk_final<true>, dim3(n_tkf), dim3(kTopThreads), 0, s, EstArgs{},
+                       L.many, i_tkf);
     GPA_LAUNCH_CHECK();
   }
 }

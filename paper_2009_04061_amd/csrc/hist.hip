@@ -26,6 +26,9 @@
 // small launches, but the device-scope fence it needs in every workgroup
 // costs far more on this part.)
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "common.h"
@@ -561,7 +564,6 @@ constexpr uint32_t kSelMin = 3;                  // sampled count that makes a P
 constexpr int kHotUnroll = 4;                    // 16-byte loads per thread per step
 constexpr uint32_t kHotStep = kHotThreads * kHotUnroll * 2;   // records per step
 constexpr uint32_t kHotGrid = 256;               // workgroups of the pass at most
-constexpr uint32_t kHotMergeCols = 64;           // hot bins per merge workgroup
 constexpr uint32_t kMaxRuns = 4096;              // cold runs listed at a time
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 static_assert(kColdMaxBuckets <= (uint32_t)kHotThreads, "one cold bucket per thread in scans");
@@ -587,13 +589,50 @@ __device__ __forceinline__ uint32_t cold_local_bin(uint32_t key) {
 // LDS words of k_hot_select (dynamic): counters and the table
 constexpr size_t kSelLdsWords = kSelCounters / 2 + kHotT;
 
+// Everything one profile's hot-set histogram needs: its records and sizes,
+// the pass's shape, its scratch and its outputs.  A launch for one profile
+// takes it by value; a batched launch reads one per profile from a device
+// table, each workgroup finding its profile and its block index within that
+// profile's grid in a work list.
+struct HotArgs {
+  const uint64_t *rec;
+  uint64_t n, per, run_stride;
+  uint32_t n_instr, n_cb, G, T;
+  uint32_t n_merge, merge_slices;   // hot-bin merge workgroups (0 when G = 1) and their slices
+  uint32_t *hot_tab, *hot_pc, *n_hot, *partial, *cold, *cold_sorted, *tile_off, *n_cold;
+  TileTotals *wtot;
+  uint32_t *counts;
+  unsigned long long *totals;
+};
+
+template <bool BATCH>
+__device__ __forceinline__ void hot_item(const HotArgs &one, const HotArgs *many,
+                                         const WorkItem *items, HotArgs &a, uint32_t &local) {
+  if (BATCH) {
+    const WorkItem it = items[blockIdx.x];
+    a = many[it.entry];
+    local = it.local;
+  } else {
+    a = one;
+    local = blockIdx.x;
+  }
+}
+
 // Sampled record k: k itself when n <= kSelSample, else offset k % kSelRun
 // of run k / kSelRun, the runs run_stride apart
 // ((kSelSample / kSelRun - 1) run_stride + kSelRun <= n).
+template <bool BATCH>
 __global__ void __launch_bounds__(kHotThreads)
-k_hot_select(const uint64_t *__restrict__ rec, uint64_t n, uint64_t run_stride, uint32_t n_instr,
-             uint32_t *__restrict__ hot_tab, uint32_t *__restrict__ hot_pc,
-             uint32_t *__restrict__ n_hot) {
+k_hot_select(HotArgs one, const HotArgs *__restrict__ many, const WorkItem *__restrict__ items) {
+  HotArgs a;
+  uint32_t local;
+  hot_item<BATCH>(one, many, items, a, local);
+  const uint64_t *__restrict__ rec = a.rec;
+  const uint64_t n = a.n, run_stride = a.run_stride;
+  const uint32_t n_instr = a.n_instr;
+  uint32_t *__restrict__ hot_tab = a.hot_tab;
+  uint32_t *__restrict__ hot_pc = a.hot_pc;
+  uint32_t *__restrict__ n_hot = a.n_hot;
   extern __shared__ uint32_t sm[];
   uint32_t *cnt = sm, *tab = cnt + kSelCounters / 2;
   __shared__ uint32_t s_nsel;
@@ -717,13 +756,21 @@ __device__ void sort_cold_tile(uint32_t n_cb, uint64_t base, uint32_t m, const u
 // workgroup sorts its cold keys by bucket in tiles of kColdTile: tile t's
 // bucket starts go to tile_off[(w T + t) (n_cb + 1) + b] (entry n_cb: the
 // end).
-template <bool VEC>
+template <bool VEC, bool BATCH>
 __global__ void __launch_bounds__(kHotThreads)
-k_hot_pass(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint32_t n_cb,
-           uint64_t per, uint32_t T, const uint32_t *__restrict__ hot_tab,
-           uint32_t *__restrict__ partial, uint32_t *__restrict__ cold,
-           uint32_t *__restrict__ cold_sorted, uint32_t *__restrict__ tile_off,
-           uint32_t *__restrict__ n_cold, TileTotals *__restrict__ wtot) {
+k_hot_pass(HotArgs one, const HotArgs *__restrict__ many, const WorkItem *__restrict__ items) {
+  HotArgs a;
+  uint32_t wg;
+  hot_item<BATCH>(one, many, items, a, wg);
+  const uint64_t *__restrict__ rec = a.rec;
+  const uint64_t n = a.n, per = a.per;
+  const uint32_t n_instr = a.n_instr, n_cb = a.n_cb, T = a.T;
+  const uint32_t *__restrict__ hot_tab = a.hot_tab;
+  uint32_t *__restrict__ cold = a.cold;
+  uint32_t *__restrict__ cold_sorted = a.cold_sorted;
+  uint32_t *__restrict__ tile_off = a.tile_off;
+  uint32_t *__restrict__ n_cold = a.n_cold;
+  TileTotals *__restrict__ wtot = a.wtot;
   __shared__ uint32_t bins[kHotBins];
   __shared__ uint32_t tab[kHotT];
   __shared__ uint32_t sorted[kColdTile];
@@ -731,7 +778,7 @@ k_hot_pass(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint3
   __shared__ uint32_t scan_tmp[kHotThreads / kWave + 1];
   __shared__ uint32_t s_cur, s_valid, s_lat;
   const unsigned tid = threadIdx.x, lane = lane_id();
-  const uint64_t r0 = (uint64_t)blockIdx.x * per, r1 = min(r0 + per, n);
+  const uint64_t r0 = (uint64_t)wg * per, r1 = min(r0 + per, n);
   // full steps below rf, then at most one partial step; three register
   // buffers in rotation (the first two issued before the set-up)
   const uint64_t rf = r0 + (r1 - r0) / kHotStep * kHotStep;
@@ -812,34 +859,50 @@ k_hot_pass(const uint64_t *__restrict__ rec, uint64_t n, uint32_t n_instr, uint3
     atomicAdd(&s_lat, w_lat);
   }
   __syncthreads();
-  uint32_t *dst = partial + (size_t)blockIdx.x * kHotBins;
-  for (uint32_t k = tid; k < kHotBins; k += kHotThreads) dst[k] = bins[k];
+  if (a.G == 1) {
+    // the only workgroup: its hot bins are the counts (no merge follows)
+    const uint32_t nh = *a.n_hot;
+    for (uint32_t k = tid; k < nh * 24u; k += kHotThreads)
+      a.counts[(size_t)a.hot_pc[k / 24u] * 24u + k % 24u] = bins[k];
+  } else {
+    uint32_t *dst = a.partial + (size_t)wg * kHotBins;
+    for (uint32_t k = tid; k < kHotBins; k += kHotThreads) dst[k] = bins[k];
+  }
   if (tid == 0) {
     TileTotals t;
     t.valid = s_valid;
     t.latency = s_lat;
     t.dropped = (uint32_t)(r1 - r0) - s_valid;
     t.pad = 0;
-    wtot[blockIdx.x] = t;
-    n_cold[blockIdx.x] = s_cur;
+    wtot[wg] = t;
+    n_cold[wg] = s_cur;
   }
   const uint32_t nc = s_cur;   // the keys were written before the barrier above
   for (uint32_t t = 0; t * kColdTile < nc; ++t)
     sort_cold_tile(n_cb, r0 + t * kColdTile, min(kColdTile, nc - t * kColdTile),
                    t == 0 ? (const uint32_t *)sorted : my_cold + t * kColdTile, cold_sorted,
-                   tile_off + ((size_t)blockIdx.x * T + t) * (n_cb + 1), sorted, bc, scan_tmp);
+                   tile_off + ((size_t)wg * T + t) * (n_cb + 1), sorted, bc, scan_tmp);
 }
 
-// blocks [0, n_cb): the cold bins of one bucket; the next
-// kHotBins / kHotMergeCols: hot bins summed over the pass's workgroups; the
-// last: the totals
+// blocks [0, n_cb): the cold bins of one bucket; the next n_merge: hot bins
+// summed over the pass's workgroups (none when the pass had one workgroup,
+// which wrote its hot bins itself); the last: the totals
+template <bool BATCH>
 __global__ void __launch_bounds__(kHotThreads)
-k_hot_finish(uint32_t n_instr, uint32_t n_cb, uint32_t G, uint32_t T,
-             const uint32_t *__restrict__ hot_pc, const uint32_t *__restrict__ n_hot_p,
-             const uint32_t *__restrict__ partial, const uint32_t *__restrict__ cold_sorted,
-             const uint32_t *__restrict__ tile_off, const uint32_t *__restrict__ n_cold,
-             const TileTotals *__restrict__ wtot, uint32_t *__restrict__ counts,
-             unsigned long long *__restrict__ totals) {
+k_hot_finish(HotArgs one, const HotArgs *__restrict__ many, const WorkItem *__restrict__ items) {
+  HotArgs a;
+  uint32_t bid;
+  hot_item<BATCH>(one, many, items, a, bid);
+  const uint32_t n_instr = a.n_instr, n_cb = a.n_cb, G = a.G, T = a.T;
+  const uint32_t *__restrict__ hot_pc = a.hot_pc;
+  const uint32_t *__restrict__ n_hot_p = a.n_hot;
+  const uint32_t *__restrict__ partial = a.partial;
+  const uint32_t *__restrict__ cold_sorted = a.cold_sorted;
+  const uint32_t *__restrict__ tile_off = a.tile_off;
+  const uint32_t *__restrict__ n_cold = a.n_cold;
+  const TileTotals *__restrict__ wtot = a.wtot;
+  uint32_t *__restrict__ counts = a.counts;
+  unsigned long long *__restrict__ totals = a.totals;
   constexpr uint32_t kWaves = kHotThreads / kWave;
   static_assert(kHotGrid <= (uint32_t)kHotThreads, "one pass workgroup per thread");
   __shared__ __align__(16) uint32_t bins[kColdBins];
@@ -848,9 +911,9 @@ k_hot_finish(uint32_t n_instr, uint32_t n_cb, uint32_t G, uint32_t T,
   __shared__ uint32_t scan_tmp[kHotThreads / kWave + 1];
   const unsigned tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
   const uint32_t n_hot = *n_hot_p;
-  constexpr uint32_t n_merge = kHotBins / kHotMergeCols;
-  if (blockIdx.x < n_cb) {
-    const uint32_t b = blockIdx.x, pc0 = b * kColdPCs;
+  const uint32_t n_merge = a.n_merge;
+  if (bid < n_cb) {
+    const uint32_t b = bid, pc0 = b * kColdPCs;
     const uint32_t npc = min(kColdPCs, n_instr - pc0);
     for (uint32_t k = tid; k < kColdBins; k += kHotThreads) bins[k] = 0;
     if (tid < kColdPCs / 32) hot_mark[tid] = 0;
@@ -928,26 +991,22 @@ k_hot_finish(uint32_t n_instr, uint32_t n_cb, uint32_t G, uint32_t T,
       const uint32_t pl = k / 24u;
       if (!((hot_mark[pl / 32] >> (pl % 32)) & 1u)) counts[(size_t)pc0 * 24u + k] = bins[k];
     }
-  } else if (blockIdx.x < n_cb + n_merge) {
-    // kHotMergeCols hot bins; the pass's workgroups split over kSlices slices
-    constexpr uint32_t kSlices = kHotThreads / kHotMergeCols;
-    const uint32_t c = tid % kHotMergeCols, sl = tid / kHotMergeCols;
-    const uint32_t col = (blockIdx.x - n_cb) * kHotMergeCols + c;
+  } else if (bid < n_cb + n_merge) {
+    // kHotThreads / S hot-bin columns; the pass's workgroups split over S
+    // slices (S a power of two, at most 16, so a thread sums at most
+    // kHotGrid / 16 partials)
+    const uint32_t S = a.merge_slices, cols = kHotThreads / S;
+    const uint32_t c = tid % cols, sl = tid / cols;
+    const uint32_t col = (bid - n_cb) * cols + c;
     const bool live = col < n_hot * 24u;
-    uint32_t v[kHotGrid / kSlices];
-#pragma unroll
-    for (uint32_t u = 0; u < kHotGrid / kSlices; ++u) {
-      const uint32_t w = sl + u * kSlices;
-      v[u] = live && w < G ? partial[(size_t)w * kHotBins + col] : 0u;
-    }
     uint32_t sum = 0;
-#pragma unroll
-    for (uint32_t u = 0; u < kHotGrid / kSlices; ++u) sum += v[u];
-    bins[sl * kHotMergeCols + c] = sum;
+#pragma unroll 4
+    for (uint32_t w = sl; w < G; w += S) sum += live ? partial[(size_t)w * kHotBins + col] : 0u;
+    bins[sl * cols + c] = sum;
     __syncthreads();
     if (sl == 0 && live) {
       uint32_t t = 0;
-      for (uint32_t k = 0; k < kSlices; ++k) t += bins[k * kHotMergeCols + c];
+      for (uint32_t k = 0; k < S; ++k) t += bins[k * cols + c];
       counts[(size_t)hot_pc[col / 24u] * 24u + col % 24u] = t;
     }
   } else {
@@ -982,29 +1041,79 @@ uint32_t hist_hot_max_pcs() { return kHotMaxPCs; }
 // the pass's workgroup ranges: kHotGrid at most, each a multiple of 128
 // records (even, so the 16-byte loads stay aligned; finer than a whole step,
 // so that the grid comes as close to kHotGrid as it can, a range's last step
-// being partial where it must)
+// being partial where it must); per_min, when given, is the least range
 struct HotShape {
-  uint64_t per;
-  uint32_t G, T, n_cb;
+  uint64_t per, run_stride;
+  uint32_t G, T, n_cb, n_merge, merge_slices;
 };
-static HotShape hot_shape(uint32_t n_instr, uint64_t n) {
+static HotShape hot_shape(uint32_t n_instr, uint64_t n, uint64_t per_min = 0) {
   HotShape h;
   h.n_cb = (n_instr + kColdPCs - 1) / kColdPCs;
-  uint64_t per = (n + kHotGrid - 1) / kHotGrid;
+  uint64_t per = std::max<uint64_t>((n + kHotGrid - 1) / kHotGrid, per_min);
   h.per = (per + 2 * kWave - 1) / (2 * kWave) * (2 * kWave);
   if (h.per == 0) h.per = 2 * kWave;
   h.G = (uint32_t)((n + h.per - 1) / h.per);
   h.T = (uint32_t)((h.per + kColdTile - 1) / kColdTile);   // tiles per workgroup
+  h.run_stride = n > kSelSample ? (n - kSelRun) / (kSelSample / kSelRun - 1) : 0;
+  // merge: S slices of the G partials, kHotThreads / S columns per workgroup
+  uint32_t S = 1;
+  while (S < h.G && S < 16) S <<= 1;
+  h.merge_slices = S;
+  const uint32_t cols = kHotThreads / S;
+  const uint32_t live_cols = std::min<uint32_t>(kHotH, n_instr) * 24u;
+  h.n_merge = h.G > 1 ? (live_cols + cols - 1) / cols : 0;
   return h;
+}
+
+static size_t blk256(size_t bytes) { return (bytes + 255) / 256 * 256; }
+
+static size_t hot_scratch(const HotShape &h, uint64_t n) {
+  return blk256(4 * kHotT) + blk256(4 * kHotH) + blk256(4) +
+         blk256(h.G > 1 ? 4 * (size_t)h.G * kHotBins : 4) + 2 * blk256(4 * n) +
+         blk256(4 * (size_t)h.G * h.T * (h.n_cb + 1)) + blk256(4 * (size_t)h.G) +
+         blk256(sizeof(TileTotals) * (size_t)h.G);
 }
 
 size_t hist_hot_scratch_bytes(uint32_t n_instr, uint64_t n) {
   if (n == 0) return 0;
-  const HotShape h = hot_shape(n_instr, n);
-  auto blk = [](size_t bytes) { return (bytes + 255) / 256 * 256; };
-  return blk(4 * kHotT) + blk(4 * kHotH) + blk(4) + blk(4 * (size_t)h.G * kHotBins) +
-         2 * blk(4 * n) + blk(4 * (size_t)h.G * h.T * (h.n_cb + 1)) + blk(4 * (size_t)h.G) +
-         blk(sizeof(TileTotals) * (size_t)h.G);
+  return hot_scratch(hot_shape(n_instr, n), n);
+}
+
+// one profile's arguments, its scratch taken from the arena (in the order
+// hot_scratch counts it)
+static HotArgs hot_args(const HotShape &h, const uint64_t *rec, uint64_t n, uint32_t n_instr,
+                        uint32_t *counts, unsigned long long *totals, Arena &ar) {
+  HotArgs a;
+  a.rec = rec;
+  a.n = n;
+  a.per = h.per;
+  a.run_stride = h.run_stride;
+  a.n_instr = n_instr;
+  a.n_cb = h.n_cb;
+  a.G = h.G;
+  a.T = h.T;
+  a.n_merge = h.n_merge;
+  a.merge_slices = h.merge_slices;
+  a.hot_tab = ar.get<uint32_t>(kHotT);
+  a.hot_pc = ar.get<uint32_t>(kHotH);
+  a.n_hot = ar.get<uint32_t>(1);
+  a.partial = ar.get<uint32_t>(h.G > 1 ? (size_t)h.G * kHotBins : 1);
+  a.cold = ar.get<uint32_t>(n);
+  a.cold_sorted = ar.get<uint32_t>(n);
+  a.tile_off = ar.get<uint32_t>((size_t)h.G * h.T * (h.n_cb + 1));
+  a.n_cold = ar.get<uint32_t>(h.G);
+  a.wtot = ar.get<TileTotals>(h.G);
+  a.counts = counts;
+  a.totals = totals;
+  return a;
+}
+
+static void set_select_lds() {
+  const int lds_sel = (int)(kSelLdsWords * 4);
+  GPA_HIP(hipFuncSetAttribute((const void *)k_hot_select<false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds_sel));
+  GPA_HIP(hipFuncSetAttribute((const void *)k_hot_select<true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds_sel));
 }
 
 static bool run_hist_hot(const gpa_program &p, const uint64_t *rec, uint64_t n, bool vec,
@@ -1015,36 +1124,143 @@ static bool run_hist_hot(const gpa_program &p, const uint64_t *rec, uint64_t n, 
   const char *force = getenv("GPA_HIST_PARTITION");
   if (allow_partition && force && force[0] == '1') return false;
   const HotShape hs = hot_shape(n_instr, n);
-  const uint32_t n_cb = hs.n_cb, G = hs.G, T = hs.T;
-  const uint64_t per = hs.per;
-  const uint64_t run_stride = n > kSelSample ? (n - kSelRun) / (kSelSample / kSelRun - 1) : 0;
-  uint32_t *hot_tab = ar.get<uint32_t>(kHotT);
-  uint32_t *hot_pc = ar.get<uint32_t>(kHotH);
-  uint32_t *n_hot = ar.get<uint32_t>(1);
-  uint32_t *partial = ar.get<uint32_t>((size_t)G * kHotBins);
-  uint32_t *cold = ar.get<uint32_t>(n);
-  uint32_t *cold_sorted = ar.get<uint32_t>(n);
-  uint32_t *tile_off = ar.get<uint32_t>((size_t)G * T * (n_cb + 1));
-  uint32_t *n_cold = ar.get<uint32_t>(G);
-  TileTotals *wtot = ar.get<TileTotals>(G);
-  const size_t lds_sel = kSelLdsWords * 4;
-  GPA_HIP(hipFuncSetAttribute((const void *)k_hot_select,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_sel));
-  hipLaunchKernelGGL(k_hot_select, dim3(1), dim3(kHotThreads), lds_sel, s, rec, n, run_stride,
-                     n_instr, hot_tab, hot_pc, n_hot);
+  const HotArgs a = hot_args(hs, rec, n, n_instr, counts, totals, ar);
+  set_select_lds();
+  hipLaunchKernelGGL(k_hot_select<false>, dim3(1), dim3(kHotThreads), kSelLdsWords * 4, s, a,
+                     nullptr, nullptr);
   GPA_LAUNCH_CHECK();
   if (vec)
-    hipLaunchKernelGGL(k_hot_pass<true>, dim3(G), dim3(kHotThreads), 0, s, rec, n, n_instr, n_cb,
-                       per, T, hot_tab, partial, cold, cold_sorted, tile_off, n_cold, wtot);
+    hipLaunchKernelGGL((k_hot_pass<true, false>), dim3(hs.G), dim3(kHotThreads), 0, s, a, nullptr,
+                       nullptr);
   else
-    hipLaunchKernelGGL(k_hot_pass<false>, dim3(G), dim3(kHotThreads), 0, s, rec, n, n_instr, n_cb,
-                       per, T, hot_tab, partial, cold, cold_sorted, tile_off, n_cold, wtot);
+    hipLaunchKernelGGL((k_hot_pass<false, false>), dim3(hs.G), dim3(kHotThreads), 0, s, a,
+                       nullptr, nullptr);
   GPA_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_hot_finish, dim3(n_cb + kHotBins / kHotMergeCols + 1), dim3(kHotThreads), 0,
-                     s, n_instr, n_cb, G, T, hot_pc, n_hot, partial, cold_sorted, tile_off, n_cold,
-                     wtot, counts, totals);
+  hipLaunchKernelGGL(k_hot_finish<false>, dim3(hs.n_cb + hs.n_merge + 1), dim3(kHotThreads), 0, s,
+                     a, nullptr, nullptr);
   GPA_LAUNCH_CHECK();
   return true;
+}
+
+size_t hist_batch_scratch_bytes(const HistEntry *e, uint32_t count, uint64_t per) {
+  size_t total = 0, items = 0;
+  for (uint32_t k = 0; k < count; ++k) {
+    const HotShape h = hot_shape(e[k].n_instr, e[k].n, per);
+    total += hot_scratch(h, e[k].n);
+    items += 1 + h.G + h.n_cb + h.n_merge + 1;
+  }
+  return total + blk256(sizeof(HotArgs) * (size_t)count) + blk256(sizeof(WorkItem) * items);
+}
+
+void run_hist_batch(const HistEntry *e, uint32_t count, uint64_t per, hipStream_t s, Arena &ar) {
+  if (count == 0) return;
+  std::vector<HotArgs> args(count);
+  std::vector<WorkItem> sel, pass, fin;
+  sel.reserve(count);
+  for (uint32_t k = 0; k < count; ++k) {
+    if (e[k].n == 0 || e[k].n_instr > kHotMaxPCs || ((uintptr_t)e[k].samples % 16) != 0)
+      fail(GPA_E_INVALID, "batched histogram entry %u: n > 0, at most %u instructions and "
+           "16-byte aligned records are required", k, kHotMaxPCs);
+    const HotShape h = hot_shape(e[k].n_instr, e[k].n, per);
+    args[k] = hot_args(h, (const uint64_t *)e[k].samples, e[k].n, e[k].n_instr, e[k].counts,
+                       e[k].totals, ar);
+    sel.push_back({k, 0});
+    for (uint32_t w = 0; w < h.G; ++w) pass.push_back({k, w});
+    for (uint32_t b = 0; b < h.n_cb + h.n_merge + 1; ++b) fin.push_back({k, b});
+  }
+  std::vector<WorkItem> all(sel);
+  all.insert(all.end(), pass.begin(), pass.end());
+  all.insert(all.end(), fin.begin(), fin.end());
+  const HotArgs *d_args = ar.upload(args, s);
+  const WorkItem *d_items = ar.upload(all, s);
+  HotArgs none{};
+  set_select_lds();
+  hipLaunchKernelGGL(k_hot_select<true>, dim3((unsigned)sel.size()), dim3(kHotThreads),
+                     kSelLdsWords * 4, s, none, d_args, d_items);
+  GPA_LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_hot_pass<true, true>), dim3((unsigned)pass.size()), dim3(kHotThreads), 0, s,
+                     none, d_args, d_items + sel.size());
+  GPA_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_hot_finish<true>, dim3((unsigned)fin.size()), dim3(kHotThreads), 0, s, none,
+                     d_args, d_items + sel.size() + pass.size());
+  GPA_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------- autotuner
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<uint32_t, uint32_t, uint32_t>, uint64_t> g_tuned;
+constexpr uint64_t kPerCandidates[] = {32768, 65536, 131072, 262144, 524288};
+constexpr uint64_t kPerDefault = 131072;
+
+uint32_t log2_bucket(uint64_t v) {
+  uint32_t b = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++b;
+  }
+  return b;
+}
+}  // namespace
+
+uint64_t batch_records_per_workgroup(const HistEntry *e, uint32_t count, hipStream_t s, Arena &ar,
+                                     bool measure) {
+  (void)ar;
+  if (const char *f = getenv("GPA_BATCH_PER")) {
+    const unsigned long long v = strtoull(f, nullptr, 10);
+    if (v) return v;
+  }
+  if (count == 0) return kPerDefault;
+  uint64_t total = 0, largest = 0;
+  for (uint32_t k = 0; k < count; ++k) {
+    total += e[k].n;
+    largest = std::max(largest, e[k].n);
+  }
+  const auto key = std::make_tuple(log2_bucket(count), log2_bucket(total), log2_bucket(largest));
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) return it->second;
+  }
+  const char *at = getenv("GPA_AUTOTUNE");
+  if (!measure || (at && at[0] == '0')) return kPerDefault;
+  hipEvent_t a = nullptr, b = nullptr;
+  GPA_HIP(hipEventCreate(&a));
+  GPA_HIP(hipEventCreate(&b));
+  uint64_t best = kPerDefault;
+  float best_ms = 0.f;
+  bool have = false;
+  try {
+    // the first candidate runs twice: its first run pays for cold code and caches
+    for (int rep = 0; rep < 2; ++rep) {
+      for (uint64_t per : kPerCandidates) {
+        if (rep == 1 && per != kPerCandidates[0]) continue;
+        Arena trial(s);   // each candidate's scratch goes back to the pool after it
+        GPA_HIP(hipEventRecord(a, s));
+        run_hist_batch(e, count, per, s, trial);
+        GPA_HIP(hipEventRecord(b, s));
+        GPA_HIP(hipEventSynchronize(b));
+        float ms = 0.f;
+        GPA_HIP(hipEventElapsedTime(&ms, a, b));
+        if (rep == 1 || per != kPerCandidates[0]) {
+          if (!have || ms < best_ms) {
+            best_ms = ms;
+            best = per;
+            have = true;
+          }
+        }
+      }
+    }
+  } catch (...) {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    throw;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[key] = best;
+  return best;
 }
 
 __global__ void k_hist_empty(uint32_t *counts, size_t nbins, unsigned long long *totals) {

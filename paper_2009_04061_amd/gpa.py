@@ -21,7 +21,8 @@ NONE = 0xFFFFFFFF
 
 GPA_OK = 0
 STATUS = {0: "GPA_OK", -1: "GPA_E_INVALID", -2: "GPA_E_NOMEM", -3: "GPA_E_DEVICE",
-          -4: "GPA_E_STATE", -6: "GPA_E_UNSUPPORTED"}
+          -4: "GPA_E_STATE", -5: "GPA_E_BUSY", -6: "GPA_E_UNSUPPORTED"}
+GPA_E_BUSY = -5
 
 
 class GpaError(RuntimeError):
@@ -55,13 +56,44 @@ class ProgramInfo(ct.Structure):
                 ("n_roots", ct.c_uint32)]
 
 
+class Launch(ct.Structure):
+    _fields_ = [("blocks", ct.c_uint32), ("threads_per_block", ct.c_uint32),
+                ("regs_per_thread", ct.c_uint32), ("shared_per_block", ct.c_uint32)]
+
+
+class Device(ct.Structure):
+    _fields_ = [(f, ct.c_uint32) for f in
+                ("n_sm", "schedulers_per_sm", "warp_size", "max_warps_per_sm",
+                 "max_blocks_per_sm", "max_threads_per_block", "regs_per_sm", "shared_per_sm")]
+
+
+class ParallelEstimate(ct.Structure):
+    _fields_ = [("matched", ct.c_uint32), ("pad", ct.c_uint32)] + \
+               [(f, ct.c_double) for f in ("W", "W_new", "R_I", "I", "I_new", "C_W", "C_I", "f",
+                                          "speedup")]
+
+
+class Hotspot(ct.Structure):
+    _fields_ = [("src", ct.c_uint32), ("dst", ct.c_uint32), ("dmin", ct.c_uint32),
+                ("dmax", ct.c_uint32), ("samples", ct.c_double)]
+
+
+class ServerStats(ct.Structure):
+    _fields_ = [(f, ct.c_uint64) for f in
+                ("submitted", "admitted", "completed", "failed", "batches", "max_batch",
+                 "peak_reserved", "reserved", "budget", "queued", "inflight_batches")]
+
+
 # every entry point declared in include/gpa.h
 EXPORTS = ["gpa_load_program", "gpa_program_free", "gpa_program_get_info", "gpa_program_roots",
            "gpa_program_rd",
            "gpa_program_edges", "gpa_attribute", "gpa_blame_free", "gpa_blame_counts",
            "gpa_blame_shares", "gpa_blame_table", "gpa_advise", "gpa_advice_free",
            "gpa_advice_get", "gpa_advice_topk", "gpa_last_error", "gpa_timing_enable",
-           "gpa_timing_read"]
+           "gpa_timing_read", "gpa_attribute_batch",
+           "gpa_advise_batch", "gpa_pool_stats", "gpa_pool_trim", "gpa_server_create",
+           "gpa_server_submit", "gpa_server_poll", "gpa_server_stats_get", "gpa_server_free",
+           "gpa_parallel_advise", "gpa_program_coverage", "gpa_blame_hotspots", "gpa_report"]
 PHASES = ["hist", "blame", "load", "advise", "rd_edges", "dist", "dfs", "rd_search",
           "validate", "sites", "edges", "targets", "dist_long"]
 
@@ -100,6 +132,29 @@ def lib():
         L.gpa_timing_enable.restype = None
         L.gpa_timing_read.argtypes = [vp, vp, u32, i32]
         L.gpa_timing_read.restype = u32
+        L.gpa_attribute_batch.argtypes = [vp, vp, vp, u32, i32, vp, vp]
+        L.gpa_attribute_batch.restype = ct.c_int32
+        L.gpa_advise_batch.argtypes = [vp, u32, vp, vp]
+        L.gpa_advise_batch.restype = ct.c_int32
+        L.gpa_parallel_advise.argtypes = [vp, u32, ct.POINTER(Launch), ct.POINTER(Device),
+                                          ct.POINTER(ParallelEstimate)]
+        L.gpa_parallel_advise.restype = ct.c_int32
+        L.gpa_program_coverage.argtypes = [vp, vp, vp]
+        L.gpa_blame_hotspots.argtypes = [vp, u32, u32, u32, vp, vp]
+        L.gpa_report.argtypes = [vp, vp, u32, u32, vp, ct.POINTER(ct.c_size_t)]
+        for name in ("gpa_program_coverage", "gpa_blame_hotspots", "gpa_report"):
+            getattr(L, name).restype = ct.c_int32
+        L.gpa_pool_stats.argtypes = [vp, vp]
+        L.gpa_pool_trim.argtypes = []
+        L.gpa_server_create.argtypes = [u64, pp]
+        L.gpa_server_submit.argtypes = [vp, vp, vp, u64, i32, ct.POINTER(ct.c_uint64)]
+        L.gpa_server_poll.argtypes = [vp, u64, pp, pp]
+        L.gpa_server_stats_get.argtypes = [vp, ct.POINTER(ServerStats)]
+        L.gpa_server_free.argtypes = [vp]
+        L.gpa_server_free.restype = None
+        for name in ("gpa_pool_stats", "gpa_pool_trim", "gpa_server_create", "gpa_server_submit",
+                     "gpa_server_poll", "gpa_server_stats_get"):
+            getattr(L, name).restype = ct.c_int32
         L.gpa_last_error.argtypes = []
         L.gpa_last_error.restype = ct.c_char_p
         for name in ("gpa_load_program", "gpa_program_get_info", "gpa_program_rd",
@@ -245,6 +300,12 @@ class Program:
         return {"src": src[:ne], "dst": dst[:ne], "flags": flags[:ne], "dmin": dmin[:ne],
                 "dmax": dmax[:ne], "n_edges": ne}
 
+    def coverage(self):
+        """(single-dependency instructions before pruning, after pruning)."""
+        a, b = ct.c_uint64(), ct.c_uint64()
+        _check(lib().gpa_program_coverage(self.handle, ct.byref(a), ct.byref(b)))
+        return int(a.value), int(b.value)
+
     def attribute(self, samples, stream=None) -> "Blame":
         """`samples`: a numpy array of the 8-byte sample dtype (host), or a
         CUDA tensor whose bytes are the records (device)."""
@@ -260,6 +321,42 @@ class Program:
         _check(L.gpa_attribute(self.handle, ptr if n else None, n, on_dev, _stream(stream),
                                ct.byref(h)))
         return Blame(self, h)
+
+def _records(samples):
+    """(pointer, record count, on-device flag) of a sample array."""
+    if isinstance(samples, np.ndarray):
+        a = np.ascontiguousarray(samples)
+        return a.ctypes.data, a.nbytes // 8, 0, a
+    n = samples.numel() * samples.element_size() // 8
+    return samples.data_ptr(), n, int(samples.is_cuda), samples
+
+
+def attribute_batch(programs, samples, stream=None):
+    """gpa_attribute_batch over (programs[k], samples[k]); all sample arrays
+    on the host (numpy) or all on the device (CUDA tensors)."""
+    count = len(programs)
+    if len(samples) != count:
+        raise ValueError("one sample array per program")
+    recs = [_records(x) for x in samples]
+    on_dev = {r[2] for r in recs}
+    if len(on_dev) > 1:
+        raise ValueError("sample arrays must all be host or all be device arrays")
+    progs = (ct.c_void_p * max(count, 1))(*[p.handle for p in programs])
+    ptrs = (ct.c_void_p * max(count, 1))(*[r[0] if r[1] else None for r in recs])
+    ns = (ct.c_uint64 * max(count, 1))(*[r[1] for r in recs])
+    out = (ct.c_void_p * max(count, 1))()
+    _check(lib().gpa_attribute_batch(progs, ptrs, ns, count, on_dev.pop() if count else 1,
+                                     _stream(stream), out))
+    return [Blame(programs[k], ct.c_void_p(out[k])) for k in range(count)]
+
+
+def advise_batch(blames, stream=None):
+    """gpa_advise_batch over the blame handles."""
+    count = len(blames)
+    hs = (ct.c_void_p * max(count, 1))(*[b.handle for b in blames])
+    out = (ct.c_void_p * max(count, 1))()
+    _check(lib().gpa_advise_batch(hs, count, _stream(stream), out))
+    return [Advice(blames[k], ct.c_void_p(out[k])) for k in range(count)]
 
 
 class Blame:
@@ -297,6 +394,25 @@ class Blame:
         _check(lib().gpa_blame_table(self.handle, b.ctypes.data, s.ctypes.data, f.ctypes.data))
         return {"blamed": b.reshape(n, 12, 2), "self": s.reshape(n, 12, 2),
                 "fine": f.reshape(n, N_FINE, 2)}
+
+    def parallel(self, root_index: int, launch: dict, device: dict):
+        """gpa_parallel_advise: [Block Increase, Thread Increase] for the
+        kernel root with index root_index (Program.roots() order)."""
+        la = Launch(**{f: int(launch[f]) for f, _ in Launch._fields_})
+        de = Device(**{f: int(device[f]) for f, _ in Device._fields_})
+        out = (ParallelEstimate * 2)()
+        _check(lib().gpa_parallel_advise(self.handle, int(root_index), ct.byref(la), ct.byref(de),
+                                         out))
+        return [{f: float(getattr(o, f)) for f, _ in ParallelEstimate._fields_ if f != "pad"}
+                for o in out]
+
+    def hotspots(self, root_index: int, opt: int, k: int = 5):
+        """gpa_blame_hotspots: list of (src, dst, dmin, dmax, samples)."""
+        out = (Hotspot * max(k, 1))()
+        n = ct.c_uint32()
+        _check(lib().gpa_blame_hotspots(self.handle, int(root_index), int(opt), int(k), out,
+                                        ct.byref(n)))
+        return [(o.src, o.dst, o.dmin, o.dmax, o.samples) for o in out[:n.value]]
 
     def advise(self, stream=None) -> "Advice":
         h = ct.c_void_p()
@@ -337,3 +453,81 @@ class Advice:
         _check(lib().gpa_advice_topk(self.handle, k, o.ctypes.data, s.ctypes.data, v.ctypes.data))
         return {"top_opt": o.reshape(ns, k), "top_scope": s.reshape(ns, k),
                 "top_speed": v.reshape(ns, k)}
+
+
+def pool_stats():
+    """(bytes handed out, bytes cached) of the library's device pool."""
+    a, b = ct.c_uint64(), ct.c_uint64()
+    _check(lib().gpa_pool_stats(ct.byref(a), ct.byref(b)))
+    return int(a.value), int(b.value)
+
+
+def pool_trim():
+    _check(lib().gpa_pool_trim())
+
+
+class Server:
+    """gpa_server_*: requests against resident programs, admitted by device
+    bytes and run in batches by the library's worker thread."""
+
+    def __init__(self, budget_bytes: int):
+        self.handle = ct.c_void_p()
+        _check(lib().gpa_server_create(int(budget_bytes), ct.byref(self.handle)))
+        self._borrowed = {}    # ticket -> (program, samples): kept alive until polled
+
+    def submit(self, program: Program, samples) -> int:
+        ptr, n, on_dev, keep = _records(samples)
+        t = ct.c_uint64()
+        _check(lib().gpa_server_submit(self.handle, program.handle, ptr if n else None, n, on_dev,
+                                       ct.byref(t)))
+        self._borrowed[t.value] = (program, keep)
+        return t.value
+
+    def poll(self, ticket: int, want_blame: bool = False):
+        """None while the request waits or runs; then (Advice, Blame or None)."""
+        b, a = ct.c_void_p(), ct.c_void_p()
+        st = lib().gpa_server_poll(self.handle, ticket, ct.byref(b) if want_blame else None,
+                                   ct.byref(a))
+        if st == GPA_E_BUSY:
+            return None
+        prog, _ = self._borrowed.pop(ticket, (None, None))
+        _check(st)
+        blame = Blame(prog, b) if want_blame else _Detached(prog)
+        return Advice(blame, a), (blame if want_blame else None)
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib().gpa_server_stats_get(self.handle, ct.byref(s)))
+        return {f: int(getattr(s, f)) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gpa_server_free(self.handle)
+            self.handle = None
+            self._borrowed.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Detached:
+    """Stands in for a blame handle the server already freed (an Advice only
+    needs its program)."""
+
+    def __init__(self, prog):
+        self.prog = prog
+        self.handle = None
+
+
+def report(advice: "Advice", blame: "Blame", top_optimizers: int = 5, hotspots: int = 5) -> str:
+    """gpa_report: the advice as text."""
+    n = ct.c_size_t(0)
+    _check(lib().gpa_report(advice.handle, blame.handle, top_optimizers, hotspots, None,
+                            ct.byref(n)))
+    buf = ct.create_string_buffer(n.value)
+    _check(lib().gpa_report(advice.handle, blame.handle, top_optimizers, hotspots, buf,
+                            ct.byref(n)))
+    return buf.value.decode()

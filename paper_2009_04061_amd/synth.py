@@ -19,6 +19,8 @@ nothing when the sample was taken).
 """
 from __future__ import annotations
 
+import bisect
+
 import numpy as np
 
 # ---------------------------------------------------------------- encodings
@@ -219,11 +221,32 @@ def _build_cfg(rng, nb, loops, branch_frac):
 
 
 # ------------------------------------------------------------ instructions
+class _Uniform:
+    """Uniform draws taken from the generator in blocks (one numpy call per
+    block instead of one per decision)."""
+
+    def __init__(self, rng, block=1 << 16):
+        self.rng, self.block = rng, block
+        self.buf, self.i = [], 0
+
+    def u(self):
+        if self.i == len(self.buf):
+            self.buf, self.i = self.rng.random(self.block).tolist(), 0
+        v = self.buf[self.i]
+        self.i += 1
+        return v
+
+    def below(self, k):
+        """An integer uniform in [0, k)."""
+        return min(int(self.u() * k), k - 1)
+
+
 class _Emitter:
     """Accumulates one function's instructions, defs and uses."""
 
     def __init__(self, rng, n_regs, n_preds, n_bars):
         self.rng = rng
+        self.U = _Uniform(rng)
         self.n_regs, self.n_preds, self.n_bars = n_regs, n_preds, n_bars
         self.op, self.guard = [], []
         self.defs, self.uses = [], []
@@ -242,13 +265,13 @@ class _Emitter:
 
     def pick_reg(self):
         if self.def_regs:
-            return self.def_regs[int(self.rng.integers(len(self.def_regs)))]
-        return int(self.rng.integers(self.n_regs))      # live-in
+            return self.def_regs[self.U.below(len(self.def_regs))]
+        return self.U.below(self.n_regs)      # live-in
 
     def pick_pred(self):
         if self.def_preds:
-            return self.def_preds[int(self.rng.integers(len(self.def_preds)))]
-        return int(self.rng.integers(self.n_preds))
+            return self.def_preds[self.U.below(len(self.def_preds))]
+        return self.U.below(self.n_preds)
 
     def emit(self, op, guard, def_regs=(), def_pred=None, use_regs=(), use_preds=(),
              wbar=None, rbar=None, guard_use=None):
@@ -298,6 +321,10 @@ class _Emitter:
 def _gen_function_body(rng, em: _Emitter, block_sizes, kind, op_mix, guard_frac, pair_frac,
                        pred_def_frac=0.12):
     p = _mix_array(op_mix)
+    cdf = np.cumsum(p)
+    cdf[-1] = 1.0
+    cdf = cdf.tolist()
+    U = em.U
     n_regs, n_preds, n_bars = em.n_regs, em.n_preds, em.n_bars
     for b, size in enumerate(block_sizes):
         forced_pair = None           # (register, guard) of a pending complementary def
@@ -306,7 +333,7 @@ def _gen_function_body(rng, em: _Emitter, block_sizes, kind, op_mix, guard_frac,
             if last and kind[b] in ("cond", "jump"):
                 if kind[b] == "cond":
                     pk = em.pick_pred()
-                    g = guard_literal(pk, bool(rng.random() < 0.5))
+                    g = guard_literal(pk, U.u() < 0.5)
                     em.emit(OP_BRANCH, g, guard_use=pk)
                 else:
                     em.emit(OP_BRANCH, 0)
@@ -318,58 +345,58 @@ def _gen_function_body(rng, em: _Emitter, block_sizes, kind, op_mix, guard_frac,
                 em.emit(OP_ALU, g, def_regs=[r], use_regs=[em.pick_reg()],
                         guard_use=(g - 1) // 2)
                 continue
-            op = int(rng.choice(N_OP_CLASSES, p=p))
+            op = min(bisect.bisect_right(cdf, U.u()), N_OP_CLASSES - 1)
             g = 0
             gpred = None
-            if rng.random() < guard_frac:
-                gpred = int(rng.integers(n_preds))
-                g = guard_literal(gpred, bool(rng.random() < 0.5))
+            if U.u() < guard_frac:
+                gpred = U.below(n_preds)
+                g = guard_literal(gpred, U.u() < 0.5)
             if op == OP_ALU:
-                if rng.random() < pred_def_frac:
-                    em.emit(op, g, def_pred=int(rng.integers(n_preds)),
+                if U.u() < pred_def_frac:
+                    em.emit(op, g, def_pred=U.below(n_preds),
                             use_regs=[em.pick_reg(), em.pick_reg()], guard_use=gpred)
                 else:
-                    r = int(rng.integers(n_regs))
+                    r = U.below(n_regs)
                     # a complementary-guarded redefinition right after this one
                     room = (k + 1 < size - 1) or (k + 1 < size and kind[b] not in ("cond", "jump"))
-                    if room and rng.random() < pair_frac:
+                    if room and U.u() < pair_frac:
                         if g == 0:
-                            gpred = int(rng.integers(n_preds))
-                            g = guard_literal(gpred, bool(rng.random() < 0.5))
+                            gpred = U.below(n_preds)
+                            g = guard_literal(gpred, U.u() < 0.5)
                         comp = g + 1 if g % 2 == 1 else g - 1
                         forced_pair = (r, comp)
                     em.emit(op, g, def_regs=[r], use_regs=[em.pick_reg(), em.pick_reg()],
                             guard_use=gpred)
             elif op == OP_FP64:
-                r = 2 * int(rng.integers(n_regs // 2))
+                r = 2 * U.below(n_regs // 2)
                 em.emit(op, g, def_regs=[r, r + 1], use_regs=[em.pick_reg(), em.pick_reg()],
                         guard_use=gpred)
             elif op == OP_LONG_ALU:
-                em.emit(op, g, def_regs=[int(rng.integers(n_regs))], use_regs=[em.pick_reg()],
+                em.emit(op, g, def_regs=[U.below(n_regs)], use_regs=[em.pick_reg()],
                         guard_use=gpred)
             elif op in (OP_GLOBAL_LOAD, OP_SHARED_LOAD, OP_LOCAL_LOAD, OP_CONST_LOAD):
-                if op == OP_GLOBAL_LOAD and rng.random() < 0.25:
-                    r = 2 * int(rng.integers(n_regs // 2))
+                if op == OP_GLOBAL_LOAD and U.u() < 0.25:
+                    r = 2 * U.below(n_regs // 2)
                     dr = [r, r + 1]
                 else:
-                    dr = [int(rng.integers(n_regs))]
+                    dr = [U.below(n_regs)]
                 ur = [em.pick_reg(), em.pick_reg()] if op == OP_GLOBAL_LOAD else [em.pick_reg()]
-                wb = int(rng.integers(n_bars))
+                wb = U.below(n_bars)
                 em.emit(op, g, def_regs=dr, use_regs=ur, wbar=wb, guard_use=gpred)
                 for r in dr:
                     em.pending_load[r] = wb
             elif op in (OP_GLOBAL_STORE, OP_SHARED_STORE, OP_LOCAL_STORE):
                 addr = [em.pick_reg(), em.pick_reg()] if op == OP_GLOBAL_STORE else [em.pick_reg()]
                 data = em.pick_reg()
-                rb = int(rng.integers(n_bars))
+                rb = U.below(n_bars)
                 em.emit(op, g, use_regs=addr + [data], rbar=rb, guard_use=gpred)
                 em.pending_store[data] = rb
             elif op == OP_BRANCH:
                 # a surplus branch draw: a non-terminating control instruction
                 em.emit(op, g, use_preds=[em.pick_pred()], guard_use=gpred)
             elif op == OP_BARRIER:
-                if rng.random() < 0.5:
-                    wb = int(rng.integers(n_bars))
+                if U.u() < 0.5:
+                    wb = U.below(n_bars)
                     em.emit(op, g, wbar=wb, guard_use=gpred)
                     em.pending_bar = wb
                 else:
@@ -413,7 +440,8 @@ class _ScopeTree:
         return order, remap
 
 
-def _function_scopes(rng, tree, fscope, block_sizes, loops, base, instr_scope, inline_frac=0.0):
+def _function_scopes(rng, tree, fscope, block_sizes, loops, base, instr_scope, inline_frac=0.0,
+                     math_frac=0.5):
     """Loop scopes mirroring the loop nest and line scopes of 1-8 consecutive
     instructions inside one block; optionally an inlined FUNCTION scope
     (math or device) wrapping a line."""
@@ -439,7 +467,7 @@ def _function_scopes(rng, tree, fscope, block_sizes, loops, base, instr_scope, i
             pos = int(first[b]) + k
             line_parent = parent
             if inline_frac > 0 and rng.random() < inline_frac:
-                fl = SF_MATH_FN if rng.random() < 0.5 else SF_DEVICE_FN
+                fl = SF_MATH_FN if rng.random() < math_frac else SF_DEVICE_FN
                 line_parent = tree.add(parent, SCOPE_FUNCTION, fl, pos)
             sid = tree.add(line_parent, SCOPE_LINE, 0, pos)
             instr_scope[pos - base:pos - base + n] = sid
@@ -456,7 +484,7 @@ def _split_blocks(rng, n_instr, nb, min_size=2):
 
 def gen_program(seed=0, functions=None, n_regs=64, n_preds=8, n_bars=2,
                 guard_frac=0.10, pair_frac=0.03, branch_frac=0.25, inline_frac=0.0,
-                op_mix=None, rng=None):
+                op_mix=None, rng=None, math_frac=0.5):
     """Generate one program.
 
     ``functions`` is a list of dicts with keys ``n_instr``, ``n_blocks``,
@@ -495,7 +523,7 @@ def gen_program(seed=0, functions=None, n_regs=64, n_preds=8, n_bars=2,
             fl = SF_HAS_CFG | SF_DEVICE_FN | (SF_MATH_FN if kind_f == "math" else 0)
             fs = tree.add(current_root, SCOPE_FUNCTION, fl, base)
         iscope = np.zeros(n, np.int64)
-        _function_scopes(rng, tree, fs, sizes, loops, base, iscope, inline_frac)
+        _function_scopes(rng, tree, fs, sizes, loops, base, iscope, inline_frac, math_frac)
         instr_scope_parts.append(iscope)
         base_b = len(block_begin) - 1
         for b in range(nb):
@@ -548,7 +576,7 @@ def gen_program(seed=0, functions=None, n_regs=64, n_preds=8, n_bars=2,
 
 # ----------------------------------------------------------------- samples
 def gen_samples(n, n_instr, zipf_s, stall_mix, seed=0, rng=None, pc_base=0,
-                latency_frac=0.5, perm=None):
+                latency_frac=0.5, perm=None, out=None):
     """``n`` records with pc ~ Zipf(s) over ranks mapped through a seeded
     permutation of the instructions, stall reason i.i.d. from ``stall_mix``
     and the latency bit ~ Bernoulli(latency_frac) except for SELECTED and
@@ -559,7 +587,10 @@ def gen_samples(n, n_instr, zipf_s, stall_mix, seed=0, rng=None, pc_base=0,
     cdf /= cdf[-1]
     if perm is None:
         perm = rng.permutation(n_instr).astype(np.uint32)
-    rec = np.zeros(n, SAMPLE_DTYPE)
+    rec = np.zeros(n, SAMPLE_DTYPE) if out is None else out
+    if out is not None:
+        assert len(out) == n and out.dtype == SAMPLE_DTYPE
+        rec["reserved"] = 0
     chunk = 1 << 22
     mix_cdf = np.cumsum(np.asarray(stall_mix, np.float64))
     mix_cdf /= mix_cdf[-1]
@@ -642,3 +673,247 @@ def workload_multi(seed=5, n_kernels=3, n_samples=300_000):
         hi = int(bb[fbb[2 * k + 2]])
         segs.append(gen_samples(per, hi - lo, 1.1, stall_mix_small(), rng=rng, pc_base=lo))
     return prog, np.concatenate(segs)
+
+
+# ------------------------------------------------------- batched workloads
+def _lognormal(rng, n, median, sigma, lo, hi):
+    return np.clip(np.exp(np.log(median) + sigma * rng.standard_normal(n)), lo, hi)
+
+
+def _dirichlet_around(rng, mean, concentration_per_category=2.0):
+    """A mix drawn from Dirichlet(alpha) with E = mean and total concentration
+    `concentration_per_category` times the number of nonzero categories."""
+    mean = np.asarray(mean, np.float64)
+    nz = mean > 0
+    alpha = concentration_per_category * nz.sum() * mean[nz]
+    out = np.zeros_like(mean)
+    out[nz] = rng.dirichlet(alpha)
+    return out
+
+
+def batch_profile_specs(config: int, seed: int | None = None):
+    """Per-profile generation specs of the batched workloads (everything a
+    profile's program and records are drawn from; each profile has its own
+    seed, so a profile does not depend on how the batch is generated).
+
+    config 2: 1,024 kernel profiles; instructions log-normal (median 3k,
+      sigma 1, clipped to 200-60k), records log-normal (median 200k, sigma 1,
+      clipped to 10k-10M); opcode and stall mixes Dirichlet around the
+      plain-path mixes (concentration 2 per category); Zipf(1.1) PCs.
+    config 3: 400 kernels of one application, the same instruction law
+      rescaled to 2M instructions in all, and 500M records in all split in
+      proportion to log-normal weights (grouped by kernel).
+    Both: one FUNCTION scope per about 170 instructions, a tenth of them
+    device functions with their own CFG, the rest inlined function scopes
+    (2% of all function scopes flagged math)."""
+    if config not in (2, 3):
+        raise ValueError("batched workloads are configs 2 and 3")
+    seed = config if seed is None else seed
+    rng = np.random.default_rng([seed, 77])
+    if config == 2:
+        count = 1024
+        n_instr = _lognormal(rng, count, 3000, 1.0, 200, 60_000).astype(np.int64)
+        n_rec = _lognormal(rng, count, 200_000, 1.0, 10_000, 10_000_000).astype(np.int64)
+    else:
+        count = 400
+        w = _lognormal(rng, count, 3000, 1.0, 200, 60_000)
+        n_instr = np.clip(np.round(w * (2_000_000 / w.sum())), 200, 60_000).astype(np.int64)
+        n_instr[-1] += 2_000_000 - int(n_instr.sum())          # exactly 2M in all
+        n_instr = np.clip(n_instr, 200, 60_000)
+        r = _lognormal(rng, count, 200_000, 1.0, 10_000, 10_000_000)
+        n_rec = np.maximum(np.round(r * (500_000_000 / r.sum())), 10_000).astype(np.int64)
+        n_rec[-1] += 500_000_000 - int(n_rec.sum())
+    stall0 = stall_mix_small()
+    op0 = _mix_array(BASE_OP_MIX)
+    seeds = np.random.SeedSequence([seed, 2024]).spawn(count)
+    specs = []
+    for k in range(count):
+        op_mix = _dirichlet_around(rng, op0)
+        stall_mix = _dirichlet_around(rng, stall0)
+        specs.append(dict(index=k, seed=seeds[k], n_instr=int(n_instr[k]), n_rec=int(n_rec[k]),
+                          op_mix={c: float(op_mix[c]) for c in range(N_OP_CLASSES) if op_mix[c] > 0},
+                          stall_mix=stall_mix, zipf=1.1))
+    return specs
+
+
+def gen_profile_program(spec):
+    """The program of one batched profile: a kernel plus device functions
+    with their own CFG (a tenth of its function scopes) and inlined function
+    scopes, about 45 instructions per block, loops of depth up to 4."""
+    rng = np.random.default_rng(spec["seed"])
+    n = spec["n_instr"]
+    n_fscopes = max(1, round(n / 170))
+    n_dev = int(round(0.1 * n_fscopes))
+    dev_sizes = []
+    rest = n
+    for _ in range(n_dev):
+        m = int(max(40, min(rest // 4, rng.integers(40, max(41, n // 8)))))
+        if rest - m < 100:
+            break
+        dev_sizes.append(m)
+        rest -= m
+    funcs = [dict(n_instr=rest, n_blocks=max(2, min(4096, rest // 45)),
+                  n_loops=max(1, rest // 45 // 15), max_depth=4, kind="kernel")]
+    for m in dev_sizes:
+        funcs.append(dict(n_instr=m, n_blocks=max(2, min(4096, m // 45)), n_loops=max(0, m // 45 // 15),
+                          max_depth=2, kind="device"))
+    n_inl = max(0, n_fscopes - 1 - len(dev_sizes))
+    lines = n / 4.5
+    inline_frac = min(0.5, n_inl / lines) if lines else 0.0
+    regs = 64 if n < 10_000 else (128 if n < 30_000 else 255)
+    return gen_program(functions=funcs, n_regs=regs, n_preds=7, n_bars=6, inline_frac=inline_frac,
+                       math_frac=0.02, op_mix=spec["op_mix"], rng=rng)
+
+
+def gen_profile(spec, out=None):
+    """One batched profile: (program, records).  `out`, when given, is an
+    array of spec['n_rec'] records to fill (and is returned)."""
+    prog = gen_profile_program(spec)
+    rng = np.random.default_rng([spec["seed"].entropy, 1] + list(spec["seed"].spawn_key))
+    rec = gen_samples(spec["n_rec"], len(prog["op_class"]), spec["zipf"], spec["stall_mix"],
+                      rng=rng, out=out)
+    return prog, rec
+
+
+def _worker_main(job_file, shm_name, total, out_file):
+    """Entry point of one generator worker process (see gen_batch)."""
+    import pickle
+    from multiprocessing import shared_memory
+    with open(job_file, "rb") as f:
+        jobs = pickle.load(f)
+    shm = shared_memory.SharedMemory(name=shm_name)
+    # the creating process owns the segment: this process's resource tracker
+    # must not remove it when this process ends
+    from multiprocessing import resource_tracker
+    resource_tracker.unregister(shm._name, "shared_memory")
+    progs = {}
+    try:
+        view = np.ndarray((total,), SAMPLE_DTYPE, buffer=shm.buf)
+        for spec, offset in jobs:
+            progs[spec["index"]], _ = gen_profile(spec, out=view[offset:offset + spec["n_rec"]])
+        del view
+    finally:
+        shm.close()
+    with open(out_file, "wb") as f:
+        pickle.dump(progs, f, protocol=pickle.HIGHEST_PROTOCOL)
+
+
+def gen_batch(config: int, seed: int | None = None, workers: int | None = None, specs=None):
+    """All profiles of a batched workload: (programs, records, offsets);
+    profile k's records are records[offsets[k]:offsets[k+1]].  Profiles are
+    generated by up to 16 worker processes (fresh Python interpreters started
+    as child processes; none when workers <= 1), which write the records
+    into shared memory; each profile depends only on its own spec."""
+    import os
+    import pickle
+    import subprocess
+    import sys
+    import tempfile
+    specs = specs if specs is not None else batch_profile_specs(config, seed)
+    sizes = np.array([s["n_rec"] for s in specs], np.int64)
+    offsets = np.concatenate([[0], np.cumsum(sizes)])
+    total = int(offsets[-1])
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    workers = max(1, min(workers, len(specs)))
+    progs = [None] * len(specs)
+    if workers <= 1:
+        records = np.empty(total, SAMPLE_DTYPE)
+        for k, s in enumerate(specs):
+            progs[k], _ = gen_profile(s, out=records[offsets[k]:offsets[k + 1]])
+        return progs, records, offsets
+    from multiprocessing import shared_memory
+    # largest first onto the least loaded worker
+    cost = [s["n_rec"] + 200 * s["n_instr"] for s in specs]
+    groups = [[] for _ in range(workers)]
+    load = [0] * workers
+    for k in sorted(range(len(specs)), key=lambda k: -cost[k]):
+        w = load.index(min(load))
+        groups[w].append((specs[k], int(offsets[k])))
+        load[w] += cost[k]
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ)
+    env["PYTHONPATH"] = root + (os.pathsep + env["PYTHONPATH"] if env.get("PYTHONPATH") else "")
+    env["OMP_NUM_THREADS"] = "1"
+    shm = shared_memory.SharedMemory(create=True, size=max(8, total * 8))
+    try:
+        with tempfile.TemporaryDirectory() as td:
+            procs = []
+            for w, g in enumerate(groups):
+                jf, of = os.path.join(td, f"jobs{w}.pkl"), os.path.join(td, f"progs{w}.pkl")
+                with open(jf, "wb") as f:
+                    pickle.dump(g, f, protocol=pickle.HIGHEST_PROTOCOL)
+                code = ("import sys; from paper_2009_04061_amd.synth import _worker_main; "
+                        "_worker_main(sys.argv[1], sys.argv[2], int(sys.argv[3]), sys.argv[4])")
+                procs.append((subprocess.Popen([sys.executable, "-c", code, jf, shm.name,
+                                                str(total), of], cwd=root, env=env), of))
+            failed = [p.wait() for p, _ in procs]
+            if any(failed):
+                raise RuntimeError(f"generator workers failed: exit codes {failed}")
+            for _, of in procs:
+                with open(of, "rb") as f:
+                    for k, prog in pickle.load(f).items():
+                        progs[k] = prog
+        records = np.empty(total, SAMPLE_DTYPE)
+        records[:] = np.ndarray((total,), SAMPLE_DTYPE, buffer=shm.buf)
+    finally:
+        shm.close()
+        shm.unlink()
+    return progs, records, offsets
+
+
+def gen_samples_device(n, n_instr, zipf_s, stall_mix, generator, perm=None,
+                       latency_frac=0.5, device="cuda"):
+    """Records drawn like gen_samples, but on the GPU with torch (a seeded
+    torch.Generator on the device): for the serving workload, whose requests
+    are too many to draw on the host.  Returns a uint8 tensor of 8n bytes."""
+    import torch
+    ranks = torch.arange(1, n_instr + 1, dtype=torch.float64, device=device)
+    cdf = torch.cumsum(ranks ** (-float(zipf_s)), 0)
+    cdf /= cdf[-1].clone()
+    if perm is None:
+        perm = torch.randperm(n_instr, generator=generator, device=device)
+    mix = torch.as_tensor(np.cumsum(np.asarray(stall_mix, np.float64)), device=device)
+    mix /= mix[-1].clone()
+    u = torch.rand(n, generator=generator, device=device, dtype=torch.float64)
+    idx = torch.clamp(torch.searchsorted(cdf, u, right=True), max=n_instr - 1)
+    pc = perm[idx].to(torch.int64)
+    u = torch.rand(n, generator=generator, device=device, dtype=torch.float64)
+    st = torch.clamp(torch.searchsorted(mix, u, right=True), max=N_STALLS - 1).to(torch.int64)
+    u = torch.rand(n, generator=generator, device=device, dtype=torch.float64)
+    lam = ((u < latency_frac) & (st != ST_SELECTED) & (st != ST_NOT_SELECTED)).to(torch.int64)
+    packed = pc | (st << 32) | (lam << 40)
+    return packed.view(torch.uint8)
+
+
+def serving_specs(seed: int = 4, n_programs: int = 2000):
+    """Program specs of the serving workload: resident programs with the
+    whole-application instruction law (log-normal, median 3k, sigma 1,
+    clipped 200-60k), built like the batched profiles."""
+    rng = np.random.default_rng([seed, 88])
+    n_instr = _lognormal(rng, n_programs, 3000, 1.0, 200, 60_000).astype(np.int64)
+    stall0 = stall_mix_small()
+    op0 = _mix_array(BASE_OP_MIX)
+    seeds = np.random.SeedSequence([seed, 4242]).spawn(n_programs)
+    specs = []
+    for k in range(n_programs):
+        op_mix = _dirichlet_around(rng, op0)
+        stall_mix = _dirichlet_around(rng, stall0)
+        specs.append(dict(index=k, seed=seeds[k], n_instr=int(n_instr[k]), n_rec=0,
+                          op_mix={c: float(op_mix[c]) for c in range(N_OP_CLASSES) if op_mix[c] > 0},
+                          stall_mix=stall_mix, zipf=1.1))
+    return specs
+
+
+def serving_requests(seed: int, n_programs: int, rate: float, seconds: float,
+                     lo: int = 50_000, hi: int = 5_000_000):
+    """The request stream: Poisson arrivals at `rate` per second over
+    `seconds`, a uniformly chosen program and a log-uniform record count in
+    [lo, hi] each: (arrival times, program indices, record counts)."""
+    rng = np.random.default_rng([seed, 99])
+    gaps = rng.exponential(1.0 / rate, size=int(rate * seconds * 1.5) + 16)
+    t = np.cumsum(gaps)
+    t = t[t < seconds]
+    prog = rng.integers(0, n_programs, size=len(t))
+    n = np.exp(rng.uniform(np.log(lo), np.log(hi), size=len(t))).astype(np.int64)
+    return t, prog, n

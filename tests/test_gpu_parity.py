@@ -315,7 +315,9 @@ def _golden_cases():
         if "program" in g and "samples" in g:
             yield name, g["program"], g["samples"]
         for k, c in enumerate(g.get("cases", [])):
-            yield f"{name}[{k}]", c.get("program", g.get("program")), c["samples"]
+            text = c.get("program", g.get("program"))
+            if text is not None and "samples" in c:
+                yield f"{name}[{k}]", text, c["samples"]
 
 
 GOLDEN = list(_golden_cases())
@@ -329,3 +331,94 @@ def test_hand_worked_programs_on_gpu(name, text, spec):
     prog = assemble(text)
     rec = samples([(pc, S.STALL_NAMES.index(st), lam, n) for pc, st, lam, n in spec])
     _both(prog, rec)
+
+
+def _parallel_close(g, o, where):
+    for key in ("matched", "W", "W_new", "R_I", "I", "I_new", "C_W", "C_I", "f", "speedup"):
+        assert g[key] == pytest.approx(o[key], rel=1e-12, abs=1e-15), (where, key)
+
+
+def test_parallel_estimators_on_gpu():
+    """gpa_parallel_advise against the oracle: the hand-worked launches of
+    tests/golden, and every kernel root of the multi-kernel workload under a
+    few launches and devices."""
+    import json
+    import os
+    from paper_2009_04061_amd import gpa
+    with open(os.path.join(os.path.dirname(__file__), "golden", "parallel_estimators.json")) as f:
+        g = json.load(f)
+    prog = assemble(g["program"])
+    for c in g["cases"]:
+        rec = samples([(pc, S.STALL_NAMES.index(st), lam, n) for pc, st, lam, n in c["samples"]])
+        P = gpa.Program(prog)
+        B = P.attribute(rec)
+        got = B.parallel(0, c["launch"], g["device"])
+        Po = O.Program(prog)
+        C, _ = O.count(Po.n_instr, rec)
+        want = O.parallel(Po, C, 0, c["launch"], g["device"])
+        for k in range(2):
+            _parallel_close(got[k], want[k], (c["name"], k))
+        B.close()
+        P.close()
+    prog, rec = S.workload_multi(seed=9, n_samples=120_000)
+    P = gpa.Program(gpa.program_to_device(prog))
+    B = P.attribute(rec)
+    Po = O.Program(prog)
+    C, _ = O.count(Po.n_instr, rec)
+    mi355x = {"n_sm": 256, "schedulers_per_sm": 4, "warp_size": 64, "max_warps_per_sm": 32,
+              "max_blocks_per_sm": 32, "max_threads_per_block": 1024, "regs_per_sm": 4 * 512 * 64,
+              "shared_per_sm": 160 * 1024}
+    launches = [dict(blocks=100, threads_per_block=256, regs_per_thread=64, shared_per_block=0),
+                dict(blocks=100000, threads_per_block=64, regs_per_thread=0, shared_per_block=0),
+                dict(blocks=3, threads_per_block=64, regs_per_thread=0, shared_per_block=4096)]
+    for ri, root in enumerate(P.roots()):
+        for li, la in enumerate(launches):
+            got = B.parallel(ri, la, mi355x)
+            want = O.parallel(Po, C, int(root), la, mi355x)
+            for k in range(2):
+                _parallel_close(got[k], want[k], (int(root), li, k))
+    B.close()
+    P.close()
+
+
+def _hotspots_match(got, want, where):
+    assert len(got) == len(want), (where, got, want)
+    for g_, w in zip(got, want):
+        if g_[:4] != w[:4]:
+            # a tie within rounding may order two carriers either way
+            assert abs(g_[4] - w[4]) <= 1e-9 * max(1.0, abs(w[4])), (where, g_, w)
+        assert g_[4] == pytest.approx(w[4], rel=1e-12), (where, g_, w)
+
+
+@pytest.mark.parametrize("which", ["small", "multi", "golden"])
+def test_report_coverage_and_hotspots_on_gpu(which):
+    """Single dependency coverage and every optimizer's top hotspots per
+    kernel against the oracle; the text report is produced."""
+    import json
+    import os
+    from paper_2009_04061_amd import gpa
+    if which == "small":
+        prog, rec = S.workload_small(seed=2, n_samples=150_000)
+    elif which == "multi":
+        prog, rec = S.workload_multi(seed=3, n_samples=150_000)
+    else:
+        with open(os.path.join(os.path.dirname(__file__), "golden", "report_coverage.json")) as f:
+            g = json.load(f)
+        prog = assemble(g["program"])
+        rec = samples([(19, S.ST_MEM_DEP, 1, 7), (18, S.ST_SELECTED, 0, 2)])
+    P = gpa.Program(gpa.program_to_device(prog))
+    B = P.attribute(rec)
+    A = B.advise()
+    Po = O.Program(prog)
+    assert P.coverage() == O.coverage(Po)
+    C, _ = O.count(Po.n_instr, rec)
+    bl = Po.blame(C)
+    for ri, root in enumerate(P.roots()):
+        for opt in range(9):
+            _hotspots_match(B.hotspots(ri, opt, 5), O.hotspots(Po, C, bl, int(root), opt, 5),
+                            (which, int(root), opt))
+    text = gpa.report(A, B, 5, 3)
+    assert "single dependency coverage" in text and text.count("kernel (scope") == len(P.roots())
+    A.close()
+    B.close()
+    P.close()

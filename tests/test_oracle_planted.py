@@ -11,6 +11,8 @@ import os
 import pytest
 
 import test_oracle_bruteforce as TB
+import test_oracle_parallel as TP
+import test_oracle_report as TR
 import test_oracle_table2 as T2
 import test_oracle_worked_examples as TW
 from oracle import oracle as O
@@ -138,6 +140,44 @@ MUTANTS = [
      "return (x->scope > y->scope) - (x->scope < y->scope);",
      "return (x->scope < y->scope) - (x->scope > y->scope);",
      [T2.test_ranking_ties_break_by_optimizer_then_scope]),
+    # parallel optimizers (Sec. 5.2, Eqs. (6)-(10))
+    ("Eq. 8 with the issued ratio in place of its complement",
+     "static double orc_issue(double r, double w) { return 1.0 - pow(1.0 - r, w); }",
+     "static double orc_issue(double r, double w) { return 1.0 - pow(r, w); }",
+     [lambda: TP.test_parallel_estimators_hand_worked(0)]),
+    ("Eq. 10 multiplied by C_W instead of divided",
+     "(1.0 / C_W) * C_I * f : 1.0;",
+     "C_W * C_I * f : 1.0;",
+     [lambda: TP.test_parallel_estimators_hand_worked(0)]),
+    ("resident blocks not bounded by the grid's share",
+     "uint64_t resident = per_sm < grid_share ? per_sm : grid_share;",
+     "uint64_t resident = per_sm;",
+     [lambda: TP.test_parallel_estimators_hand_worked(0)]),
+    ("contention stalls without the not-selected samples",
+     "if (r == ORC_PIPE_BUSY || r == ORC_MEM_THROTTLE || r == ORC_NOT_SELECTED) contention += v;",
+     "if (r == ORC_PIPE_BUSY || r == ORC_MEM_THROTTLE) contention += v;",
+     [lambda: TP.test_parallel_estimators_hand_worked(1)]),
+    ("Thread Increase without its factor",
+     "      f = W > 0.0 ? W_new / W : 1.0;",
+     "      f = 1.0;",
+     [lambda: TP.test_parallel_estimators_hand_worked(2)]),
+    ("Thread Increase matched whatever limits residency",
+     "matched = lim_blocks < other && resident == lim_blocks && warps_now < max_warps;",
+     "matched = resident == lim_blocks && warps_now < max_warps;",
+     [lambda: TP.test_parallel_estimators_hand_worked(3)]),
+    # report layer (Sec. 6 coverage, Sec. 7 hotspots)
+    ("coverage after pruning ignores the latency rule",
+     "if (a->e_src[e] == a->rd_src[q] && (a->e_flags[e] & ORC_E_LAT_KEEP)) ++kept;",
+     "if (a->e_src[e] == a->rd_src[q]) ++kept;",
+     [TR.test_single_dependency_coverage_before_and_after_pruning]),
+    ("hotspots ranked smallest first",
+     "if (a->v != b->v) return a->v > b->v ? -1 : 1;",
+     "if (a->v != b->v) return a->v < b->v ? -1 : 1;",
+     [lambda: TR.test_hotspots_hand_worked(1)]),
+    ("Loop Unrolling hotspots outside any common loop",
+     "        if (common_loop(p, p->instr_scope[i], p->instr_scope[j], fscope) == ORC_NONE) v = 0.0;\n",
+     "",
+     [lambda: TR.test_hotspots_hand_worked(3)]),
     ("saturated estimate left to the plain formula",
      "double sp = (T == 0.0) ? 1.0 : (x >= T ? INFINITY : T / (T - x));",
      "double sp = (T == 0.0) ? 1.0 : T / (T - x);",
