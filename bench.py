@@ -99,9 +99,12 @@ def summarize_traffic(fetch_dir, write_dir, copy_mb, out_path, steps):
                 copy_vals.append(v)
             for k in HIST_KERNELS:
                 if ("gpa::" + k + "(") in name or ("gpa::" + k + "<") in name:
-                    per_kernel.setdefault(k, []).append(v)
+                    per_kernel.setdefault(k, []).append((int(r.get("Dispatch_Id", 0)), v))
         if not copy_vals:
             raise SystemExit(f"no copy kernel in the {counter} run")
+        # the timed steps are the last `steps` dispatches of each kernel (the
+        # warm-up and the autotuner's trial runs come before them)
+        per_kernel = {k: [v for _, v in sorted(dv)[-steps:]] for k, dv in per_kernel.items()}
         copy_kib = max(copy_vals)
         factor = (copy_mb * 1024.0) / copy_kib
         kib = sum(sum(v) for v in per_kernel.values()) / steps
@@ -370,7 +373,7 @@ def main():
 
     if args.traffic_summary:
         summarize_traffic(args.traffic_summary[0], args.traffic_summary[1],
-                          args.copy_mb or 512, TRAFFIC_FILE, args.steps + args.warmup)
+                          args.copy_mb or 512, TRAFFIC_FILE, args.steps)
         return
 
     if args.gpus != 1:
@@ -438,7 +441,8 @@ def main():
               "batched_ms_per_step": round(1e3 * r2["t_batch"], 3),
               "per_profile_ms_per_step": round(1e3 * r2["t_plain"], 3),
               "speedup": round(r2["t_plain"] / r2["t_batch"], 2),
-              "programs_load_s": round(r2["load_s"], 3)}
+              "programs_load_s": round(r2["load_s"], 3),
+              "phase_ms": {k: round(v, 4) for k, v in r2["phases"].items() if v is not None}}
 
     serve = None
     if not args.no_serving:

@@ -100,6 +100,22 @@ PHASES = ["hist", "blame", "load", "advise", "rd_edges", "dist", "dfs", "rd_sear
 _lib = None
 
 
+def _torch_runtime_first():
+    """Bring up torch's HIP runtime before the library is loaded.
+
+    torch ships its own HIP and HSA runtimes, and libgpa.so links the
+    system's; a process that uses both holds two runtimes over one device.
+    The library's runtime then finds the device only when it is loaded after
+    torch's has come up (loaded first, its first call reports that no device
+    is present), so the load order is fixed here."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def lib():
     """Load libgpa.so (built by paper_2009_04061_amd/build.py)."""
     global _lib
@@ -107,6 +123,7 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run paper_2009_04061_amd/build.py "
                               "(there is no fallback path)")
+        _torch_runtime_first()
         L = ct.CDLL(LIB_PATH)
         vp, u32, u64, i32 = ct.c_void_p, ct.c_uint32, ct.c_uint64, ct.c_int
         pp = ct.POINTER(ct.c_void_p)
