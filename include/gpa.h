@@ -299,6 +299,33 @@ gpa_status gpa_parallel_advise(const gpa_blame *b, uint32_t root_index, const gp
 gpa_status gpa_attribute_batch(gpa_program *const *progs, const gpa_sample *const *samples,
                                const uint64_t *n, uint32_t count, int samples_on_device,
                                void *stream, gpa_blame **out);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): what
+ * gpa_attribute computes for one profile, written to caller-given device
+ * arrays, with no allocation of any kind.  The histogram's scratch is a
+ * fixed array of gpa_noalloc_scratch_bytes() bytes inside the library, one
+ * per GPU, held from the library's first use on that GPU until the process
+ * ends.
+ *   samples : device, n records (8-byte aligned; 16-byte alignment is
+ *             faster), borrowed until the stream's work is done;
+ *   counts  : device u32 [n_instr*24], totals: device u64 [4] (as
+ *             gpa_blame_counts); share: device f64 [n_edges*n_blamable*2]
+ *             (may be NULL when that size is 0); blamed, self_: device f64
+ *             [n_instr*24]; fine: device f64 [n_instr*GPA_N_FINE*2] (as
+ *             gpa_blame_shares and gpa_blame_table).  Every element is
+ *             written; nothing needs clearing beforehand.
+ * The call only enqueues work on `stream` and returns; results are ready
+ * when the stream's work is.  All calls on one GPU share its scratch array:
+ * calls that overlap on one GPU (different streams or threads without
+ * ordering between them) race; calls on one stream are ordered.
+ * GPA_E_UNSUPPORTED, before anything is launched, for programs above 2^17
+ * instructions or inputs whose scratch would exceed the fixed size (about
+ * 8 bytes per record plus at most 16 MB: some 23M records). */
+uint64_t gpa_noalloc_scratch_bytes(void);
+gpa_status gpa_attribute_noalloc(const gpa_program *p, const gpa_sample *samples, uint64_t n,
+                                 void *stream, uint32_t *counts, uint64_t *totals, double *share,
+                                 double *blamed, double *self_, double *fine);
+
 /* gpa_advise for every blame handle of the batch, each estimate stage one
  * launch over all of them; out[k] as gpa_advise(blames[k]) would return,
  * bit for bit. */

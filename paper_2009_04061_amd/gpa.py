@@ -93,7 +93,8 @@ EXPORTS = ["gpa_load_program", "gpa_program_free", "gpa_program_get_info", "gpa_
            "gpa_timing_read", "gpa_attribute_batch",
            "gpa_advise_batch", "gpa_pool_stats", "gpa_pool_trim", "gpa_server_create",
            "gpa_server_submit", "gpa_server_poll", "gpa_server_stats_get", "gpa_server_free",
-           "gpa_parallel_advise", "gpa_program_coverage", "gpa_blame_hotspots", "gpa_report"]
+           "gpa_parallel_advise", "gpa_program_coverage", "gpa_blame_hotspots", "gpa_report",
+           "gpa_attribute_noalloc", "gpa_noalloc_scratch_bytes"]
 PHASES = ["hist", "blame", "load", "advise", "rd_edges", "dist", "dfs", "rd_search",
           "validate", "sites", "edges", "targets", "dist_long"]
 
@@ -172,6 +173,10 @@ def lib():
         for name in ("gpa_pool_stats", "gpa_pool_trim", "gpa_server_create", "gpa_server_submit",
                      "gpa_server_poll", "gpa_server_stats_get"):
             getattr(L, name).restype = ct.c_int32
+        L.gpa_noalloc_scratch_bytes.argtypes = []
+        L.gpa_noalloc_scratch_bytes.restype = u64
+        L.gpa_attribute_noalloc.argtypes = [vp, vp, u64, vp, vp, vp, vp, vp, vp, vp]
+        L.gpa_attribute_noalloc.restype = ct.c_int32
         L.gpa_last_error.argtypes = []
         L.gpa_last_error.restype = ct.c_char_p
         for name in ("gpa_load_program", "gpa_program_get_info", "gpa_program_rd",
@@ -338,6 +343,21 @@ class Program:
         _check(L.gpa_attribute(self.handle, ptr if n else None, n, on_dev, _stream(stream),
                                ct.byref(h)))
         return Blame(self, h)
+
+def noalloc_scratch_bytes() -> int:
+    """gpa_noalloc_scratch_bytes: the fixed scratch of gpa_attribute_noalloc."""
+    return int(lib().gpa_noalloc_scratch_bytes())
+
+
+def attribute_noalloc(program, samples, counts, totals, share, blamed, self_, fine, stream=None):
+    """gpa_attribute_noalloc: `samples` and the six outputs are CUDA tensors
+    of the sizes include/gpa.h states; only enqueues work on `stream`."""
+    n = samples.numel() * samples.element_size() // 8
+    _check(lib().gpa_attribute_noalloc(program.handle, samples.data_ptr() if n else None, n,
+                                       _stream(stream), counts.data_ptr(), totals.data_ptr(),
+                                       share.data_ptr() if share is not None else None,
+                                       blamed.data_ptr(), self_.data_ptr(), fine.data_ptr()))
+
 
 def _records(samples):
     """(pointer, record count, on-device flag) of a sample array."""
