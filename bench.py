@@ -171,12 +171,21 @@ def per_profile_step(gpa, P, D, stream):
 
 
 def time_steps(torch, fn, steps):
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        fn()
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
+    """Wall time per step; Python's cyclic garbage collector is paused over
+    the timed steps (a full collection over the workload's host arrays would
+    land inside one of them)."""
+    import gc
+    gc.collect()
+    gc.disable()
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+    finally:
+        gc.enable()
 
 
 def run_batch_config(torch, gpa, cfg, steps, warmup, dev, stream, per_profile_steps=1):

@@ -324,9 +324,13 @@ void enqueue_attribute_batch(gpa_program *const *progs, const gpa_sample *const 
   std::vector<uint32_t> single;
   const char *force = getenv("GPA_HIST_PARTITION");
   const bool forced = force && force[0] == '1';
+  // the tables of every handle of the batch come from one shared set of
+  // pool chunks, returned with the last of the handles
+  auto sh = std::make_shared<SharedBlocks>();
   for (uint32_t k = 0; k < count; ++k) {
     b[k] = new gpa_blame(progs[k]);
-    b[k]->counts.alloc((size_t)progs[k]->n_instr * 24);
+    b[k]->shared = sh;
+    sh->carve(b[k]->counts, (size_t)progs[k]->n_instr * 24);
     const bool fits = n[k] > 0 && progs[k]->n_instr <= hist_hot_max_pcs() && !forced &&
                       ((uintptr_t)ds[k] % 16) == 0;
     if (fits) batched.push_back({ds[k], n[k], progs[k]->n_instr, b[k]->counts.p, dtot + 4 * k});
@@ -341,7 +345,7 @@ void enqueue_attribute_batch(gpa_program *const *progs, const gpa_sample *const 
     t_hist.end(s);
     t_blame.begin(kPhaseBlame, s);
   }
-  run_blame_batch(progs, b, count, s, ar);
+  run_blame_batch(progs, b, count, s, ar, *sh);
   if (measure_tuning) {
     t_blame.end(s);
     // the caller synchronizes before returning: the timers are read then
@@ -362,6 +366,7 @@ gpa_blame::~gpa_blame() {
   blamed.release();
   self_.release();
   fine.release();
+  shared.reset();
   gpa::program_release(prog);
 }
 gpa_advice::gpa_advice(const gpa_program *p) : prog(p) { gpa::program_retain(p); }
@@ -375,6 +380,7 @@ gpa_advice::~gpa_advice() {
   top_opt.release();
   top_scope.release();
   top_speed.release();
+  shared.reset();
   gpa::program_release(prog);
 }
 

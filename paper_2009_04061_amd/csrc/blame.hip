@@ -231,28 +231,37 @@ void launch_blame(const gpa_program &p, const uint32_t *counts, double *share, d
 }
 
 void run_blame_batch(const gpa_program *const *progs, gpa_blame *const *b, uint32_t count,
-                     hipStream_t s, Arena &ar) {
+                     hipStream_t s, Arena &ar, SharedBlocks &sh) {
   std::vector<BlameArgs> args(count);
-  std::vector<WorkItem> items;
+  std::vector<uint32_t> tiles(count);
   for (uint32_t k = 0; k < count; ++k) {
     const gpa_program &p = *progs[k];
     const uint32_t n = p.n_instr;
-    b[k]->share.alloc(p.n_edges * p.n_blamable * 2);
-    b[k]->blamed.alloc((size_t)n * 24);
-    b[k]->self_.alloc((size_t)n * 24);
-    b[k]->fine.alloc((size_t)n * GPA_N_FINE * 2);
+    sh.carve(b[k]->share, p.n_edges * p.n_blamable * 2);
+    sh.carve(b[k]->blamed, (size_t)n * 24);
+    sh.carve(b[k]->self_, (size_t)n * 24);
+    sh.carve(b[k]->fine, (size_t)n * GPA_N_FINE * 2);
     args[k] = blame_args(p, b[k]->counts.p, b[k]->share.p, b[k]->blamed.p, b[k]->self_.p,
                          b[k]->fine.p);
-    for (uint32_t t = 0; t * kBlameThreads < n; ++t) items.push_back({k, t});
+    tiles[k] = (n + kBlameThreads - 1) / kBlameThreads;
   }
-  if (items.empty()) return;
-  const BlameArgs *d_args = ar.upload(args, s);
-  const WorkItem *d_items = ar.upload(items, s);
+  BatchPlan plan(count);
+  const uint32_t q = plan.add(tiles);
+  if (plan.blocks(q) == 0) return;
+  Upload up;
+  const size_t i_args = up.add(args), i_pre = up.add(plan.pre);
+  up.send(ar, s);
+  const BlameArgs *d_args = up.ptr<BlameArgs>(i_args);
+  plan.d_pre = up.ptr<uint32_t>(i_pre);
+  plan.d_items = ar.get<WorkItem>(plan.total_items());
+  plan.expand(s);
   BlameArgs none{};
-  const unsigned g = (unsigned)items.size();
-  hipLaunchKernelGGL(k_blame_dst<true>, dim3(g), dim3(kBlameThreads), 0, s, none, d_args, d_items);
+  const unsigned g = plan.blocks(q);
+  hipLaunchKernelGGL(k_blame_dst<true>, dim3(g), dim3(kBlameThreads), 0, s, none, d_args,
+                     plan.items(q));
   GPA_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_blame_src<true>, dim3(g), dim3(kBlameThreads), 0, s, none, d_args, d_items);
+  hipLaunchKernelGGL(k_blame_src<true>, dim3(g), dim3(kBlameThreads), 0, s, none, d_args,
+                     plan.items(q));
   GPA_LAUNCH_CHECK();
 }
 

@@ -4,9 +4,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdint>
+#include <memory>
 #include <cstdio>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -51,6 +54,7 @@ template <typename T>
 struct DBuf {
   T *p = nullptr;
   size_t n = 0;
+  bool borrowed = false;   // carved from a block someone else returns to the pool
   DBuf() = default;
   DBuf(const DBuf &) = delete;
   DBuf &operator=(const DBuf &) = delete;
@@ -60,10 +64,70 @@ struct DBuf {
     n = count;
     p = static_cast<T *>(dev_alloc((count ? count : 1) * sizeof(T)));
   }
+  void carve(void *q, size_t count) {
+    release();
+    n = count;
+    p = static_cast<T *>(q);
+    borrowed = true;
+  }
   void release() {
-    if (p) dev_free(p);
+    if (p && !borrowed) dev_free(p);
     p = nullptr;
     n = 0;
+    borrowed = false;
+  }
+};
+
+// Pieces of at least 256-byte alignment carved from pool chunks, so that a
+// call making thousands of small tables takes a handful of blocks from the
+// pool.  Chunks grow from 1 MiB, doubling up to kChunkBytes (so a small
+// call leaves little of its last chunk unused); a request of a quarter of
+// kChunkBytes or more gets a block of its own.  Every piece keeps 256 bytes
+// of slack behind it, as a block of its own would.  The chunks are listed
+// in `chunks` for their owner to return.
+constexpr size_t kChunkBytes = (size_t)32 << 20;
+struct ChunkCarver {
+  std::vector<void *> chunks;
+  char *cur = nullptr;
+  size_t left = 0, next = (size_t)1 << 20;
+  void *take(size_t bytes) {
+    const size_t need = ((bytes ? bytes : 1) + 255) / 256 * 256 + 256;
+    if (need >= kChunkBytes / 4) {
+      void *b = dev_alloc(need);
+      chunks.push_back(b);
+      return b;
+    }
+    if (need > left) {
+      while (next < need) next *= 2;
+      void *c = dev_alloc(next);
+      chunks.push_back(c);
+      cur = static_cast<char *>(c);
+      left = next;
+      next = std::min(2 * next, kChunkBytes);
+    }
+    void *q = cur;
+    cur += need;
+    left -= need;
+    return q;
+  }
+  void release() {
+    for (void *c : chunks) dev_free(c);
+    chunks.clear();
+    cur = nullptr;
+    left = 0;
+    next = (size_t)1 << 20;
+  }
+};
+
+// Device memory shared by the handles one batched call returns (their
+// counts, shares, tables, estimates): each handle holds a reference, and the
+// chunks go back to the pool with the last of them.
+struct SharedBlocks {
+  ChunkCarver carver;
+  ~SharedBlocks() { carver.release(); }
+  template <typename T>
+  void carve(DBuf<T> &d, size_t count) {
+    d.carve(carver.take(count * sizeof(T)), count);
   }
 };
 
@@ -74,7 +138,7 @@ struct DBuf {
 // bytes; nothing is allocated, synchronized or returned, and a request
 // beyond the region fails with GPA_E_UNSUPPORTED.
 struct Arena {
-  std::vector<void *> blocks;
+  ChunkCarver carver;
   std::vector<hipStream_t> streams;
   // host staging of uploads, kept until the streams have finished with them
   std::vector<std::vector<char>> host_blocks;
@@ -91,7 +155,7 @@ struct Arena {
   ~Arena() {
     if (fixed) return;
     for (hipStream_t s : streams) (void)hipStreamSynchronize(s);
-    for (void *b : blocks) dev_free(b);
+    carver.release();
   }
   template <typename T>
   T *get(size_t count) {
@@ -106,9 +170,7 @@ struct Arena {
       used = at + bytes;
       return reinterpret_cast<T *>(fixed + at);
     }
-    void *b = dev_alloc(bytes);
-    blocks.push_back(b);
-    return static_cast<T *>(b);
+    return static_cast<T *>(carver.take(bytes));
   }
   // a device copy of host data, uploaded on `s` (pool mode only)
   template <typename T>
@@ -202,6 +264,7 @@ struct gpa_program {
 
 struct gpa_blame {
   const gpa_program *prog = nullptr;   // holds a reference
+  std::shared_ptr<gpa::SharedBlocks> shared;   // the tables' memory, when made by a batched call
   uint64_t totals[4] = {0, 0, 0, 0};
   gpa::DBuf<uint32_t> counts;          // [n_instr*24]
   gpa::DBuf<unsigned long long> dtotals;
@@ -214,6 +277,7 @@ struct gpa_blame {
 
 struct gpa_advice {
   const gpa_program *prog = nullptr;   // holds a reference
+  std::shared_ptr<gpa::SharedBlocks> shared;   // the outputs' memory, when made by a batched call
   gpa::DBuf<double> active, matched, speedup, kernel_T, kernel_L, eq3;
   gpa::DBuf<uint32_t> top_opt, top_scope;
   gpa::DBuf<double> top_speed;
@@ -265,6 +329,63 @@ struct WorkItem {
   uint32_t entry, local;
 };
 
+// The work lists of a batched launch chain, expanded on the device: stage q
+// gives entry e blocks[q][e] workgroups; its items are those of entry 0,
+// then entry 1, and so on.  The host keeps only per-entry counts and their
+// prefix sums; add the stages, place() their tables into the call's one
+// upload, then expand() writes every stage's items in one launch.
+constexpr uint32_t kMaxStages = 16;
+struct StageTable {
+  uint32_t n_stages, count;
+  uint32_t pre_off[kMaxStages];          // offset of stage q's prefix sums (count + 1)
+  uint64_t item_off[kMaxStages + 1];     // offset of stage q's items
+};
+struct BatchPlan {
+  std::vector<uint32_t> pre;
+  StageTable t{};
+  explicit BatchPlan(uint32_t count) { t.count = count; }
+  // a stage; returns its index
+  uint32_t add(const std::vector<uint32_t> &blocks);
+  uint32_t blocks(uint32_t q) const { return (uint32_t)(t.item_off[q + 1] - t.item_off[q]); }
+  uint64_t total_items() const { return t.item_off[t.n_stages]; }
+  // the device prefix sums and items once placed and expanded
+  const uint32_t *d_pre = nullptr;
+  WorkItem *d_items = nullptr;
+  const WorkItem *items(uint32_t q) const { return d_items + t.item_off[q]; }
+  void expand(hipStream_t s);
+};
+
+// One host-to-device copy for a batched call's tables: each part is
+// appended (256-byte aligned) and gets its device address once sent.
+struct Upload {
+  std::vector<char> host;
+  std::vector<size_t> at;
+  char *dev = nullptr;
+  template <typename T>
+  size_t add(const std::vector<T> &v) {
+    const size_t o = (host.size() + 255) / 256 * 256;
+    host.resize(o + sizeof(T) * v.size());
+    if (!v.empty()) memcpy(host.data() + o, v.data(), sizeof(T) * v.size());
+    at.push_back(o);
+    return at.size() - 1;
+  }
+  template <typename T>
+  T *ptr(size_t part) const { return reinterpret_cast<T *>(dev + at[part]); }
+  // copies the parts to one block of the call's arena on `s` (the host
+  // buffer is kept by the arena until the stream is done with it)
+  void send(Arena &ar, hipStream_t s) {
+    dev = ar.get<char>(host.size());
+    if (host.empty()) return;
+    ar.host_blocks.emplace_back(std::move(host));
+    const std::vector<char> &h = ar.host_blocks.back();
+    const hipError_t e = hipMemcpyAsync(dev, h.data(), h.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+      set_error("upload of %zu bytes failed: %s", h.size(), hipGetErrorString(e));
+      throw Error{GPA_E_DEVICE};
+    }
+  }
+};
+
 // hist.hip.  allow_partition = false keeps to the hot-set path (programs of
 // up to hist_hot_max_pcs() instructions; GPA_E_UNSUPPORTED beyond), which
 // issues no memset and no host synchronization.
@@ -286,7 +407,6 @@ struct HistEntry {
 // where a profile would need more than 256 workgroups).  Entries must have
 // n > 0.  The counts equal run_hist's for each profile.
 void run_hist_batch(const HistEntry *e, uint32_t count, uint64_t per, hipStream_t s, Arena &ar);
-size_t hist_batch_scratch_bytes(const HistEntry *e, uint32_t count, uint64_t per);
 // The autotuner of the batched histogram: records per pass workgroup for
 // this batch's shape bucket (profile count, total and largest record count,
 // each to a power of two), measured once per bucket and process by timing
@@ -365,9 +485,9 @@ void enqueue_attribute_batch(gpa_program *const *progs, const gpa_sample *const 
 uint64_t request_device_bytes(const gpa_program &p, uint64_t n, bool host_records);
 
 // the blame of many profiles (their counts already in b[k]->counts) in two
-// launches; allocates each handle's tables
+// launches; each handle's tables are carved from `sh`
 void run_blame_batch(const gpa_program *const *progs, gpa_blame *const *b, uint32_t count,
-                     hipStream_t s, Arena &ar);
+                     hipStream_t s, Arena &ar, SharedBlocks &sh);
 // estimate.hip
 void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint32_t k,
                   hipStream_t s, Arena &ar);

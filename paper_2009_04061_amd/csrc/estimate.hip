@@ -538,8 +538,10 @@ static int reason_slot(uint32_t bl, int r) {
 
 // the arguments of one profile's advise; scratch from the arena, outputs
 // allocated in the advice handle
+// one profile's kernel arguments: scratch from `ar`; the advice's outputs
+// carved from `sh` in a batched call, their own blocks otherwise
 static EstArgs est_args(const gpa_program &p, const gpa_blame &b, gpa_advice &adv, uint32_t k,
-                        Arena &ar) {
+                        Arena &ar, SharedBlocks *sh = nullptr) {
   const uint32_t n = p.n_instr, ns = p.n_scopes;
   EstArgs a{};
   a.n_instr = n;
@@ -582,17 +584,21 @@ static EstArgs est_args(const gpa_program &p, const gpa_blame &b, gpa_advice &ad
   for (int g = 0; g < 4; ++g)
     a.partial[g] = ar.get<double>((size_t)a.seg_chunks[g] * (g == 0 || g == 3 ? kNV : 1));
   a.cand = ar.get<Cand>((size_t)p.tk_chunks * kTopK);
-  adv.active.alloc(ns);
-  adv.matched.alloc((size_t)ns * GPA_N_OPT);
-  adv.speedup.alloc((size_t)ns * GPA_N_OPT);
-  adv.kernel_T.alloc(ns);
-  adv.kernel_L.alloc(ns);
-  adv.eq3.alloc((size_t)ns * 3);
+  auto out = [&](auto &d, size_t count) {
+    if (sh) sh->carve(d, count);
+    else d.alloc(count);
+  };
+  out(adv.active, ns);
+  out(adv.matched, (size_t)ns * GPA_N_OPT);
+  out(adv.speedup, (size_t)ns * GPA_N_OPT);
+  out(adv.kernel_T, ns);
+  out(adv.kernel_L, ns);
+  out(adv.eq3, (size_t)ns * 3);
   adv.k = k;
   // one row of k per kernel root, in the order of p.roots (ascending scope)
-  adv.top_opt.alloc((size_t)p.n_roots * k);
-  adv.top_scope.alloc((size_t)p.n_roots * k);
-  adv.top_speed.alloc((size_t)p.n_roots * k);
+  out(adv.top_opt, (size_t)p.n_roots * k);
+  out(adv.top_scope, (size_t)p.n_roots * k);
+  out(adv.top_speed, (size_t)p.n_roots * k);
   a.active = adv.active.p;
   a.matched = adv.matched.p;
   a.speedup = adv.speedup.p;
@@ -653,71 +659,70 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &adv, uin
 void run_estimate_batch(const gpa_blame *const *b, gpa_advice *const *adv, uint32_t count,
                         uint32_t k, hipStream_t s, Arena &ar) {
   std::vector<EstArgs> args(count);
-  // work lists, one per stage: instructions, scopes, edges, chunks of each
-  // grouping, long segments, top-k chunks and kernel roots
-  std::vector<WorkItem> w_instr, w_scope, w_edge, w_ch[3], w_cb[3], w_tkc, w_tkf;
-  auto tiles = [](std::vector<WorkItem> &v, uint32_t e, uint64_t n, uint32_t per) {
-    for (uint64_t t = 0; t * per < n; ++t) v.push_back({e, (uint32_t)t});
-  };
+  // per-entry workgroups of each stage: instructions, scopes, edges, chunks
+  // of each grouping and their long segments, top-k chunks, kernel roots
+  std::vector<uint32_t> w_instr(count), w_scope(count), w_edge(count), w_ch[3], w_cb[3],
+      w_tkc(count), w_tkf(count);
+  for (int g = 0; g < 3; ++g) {
+    w_ch[g].resize(count);
+    w_cb[g].resize(count);
+  }
+  auto tiles = [](uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); };
+  // the advice outputs of the whole batch share one set of pool chunks
+  auto sh = std::make_shared<SharedBlocks>();
   for (uint32_t e = 0; e < count; ++e) {
     const gpa_program &p = *b[e]->prog;
-    args[e] = est_args(p, *b[e], *adv[e], k, ar);
+    adv[e]->shared = sh;
+    args[e] = est_args(p, *b[e], *adv[e], k, ar, sh.get());
     const EstArgs &a = args[e];
-    tiles(w_instr, e, p.n_instr, kEstThreads);
-    tiles(w_scope, e, p.n_scopes, kEstThreads);
-    tiles(w_edge, e, p.n_edges, kEstThreads);
+    w_instr[e] = tiles(p.n_instr, kEstThreads);
+    w_scope[e] = tiles(p.n_scopes, kEstThreads);
+    w_edge[e] = tiles(p.n_edges, kEstThreads);
     const uint32_t nc[3] = {a.seg_chunks[0], std::max(a.seg_chunks[1], a.seg_chunks[2]),
                             a.seg_chunks[3]};
     for (int g = 0; g < 3; ++g) {
-      tiles(w_ch[g], e, nc[g], 1);
-      tiles(w_cb[g], e, nc[g], kEstThreads);   // long segments <= chunks
+      w_ch[g][e] = nc[g];
+      w_cb[g][e] = tiles(nc[g], kEstThreads);   // long segments <= chunks
     }
-    if (k && p.n_roots) {
-      tiles(w_tkc, e, p.tk_chunks, 1);
-      tiles(w_tkf, e, p.n_roots, 1);
-    }
+    w_tkc[e] = (k && p.n_roots) ? p.tk_chunks : 0u;
+    w_tkf[e] = (k && p.n_roots) ? p.n_roots : 0u;
   }
-  EstLaunch L{s, EstArgs{}, ar.upload(args, s)};
-  auto up = [&](const std::vector<WorkItem> &v) {
-    return std::make_pair(ar.upload(v, s), (unsigned)v.size());
-  };
-  auto [i_instr, n_instr] = up(w_instr);
-  auto [i_scope, n_scope] = up(w_scope);
-  auto [i_edge, n_edge] = up(w_edge);
-  L(k_line_contrib<true>, n_instr, 1, i_instr);
-  L(k_seg_small<kNV, 0, 1, true>, n_scope, 1, i_scope);
-  {
-    auto [ic, nc] = up(w_ch[0]);
-    L(k_seg_chunks<kNV, 0, 1, true>, nc, 1, ic);
-    auto [ib, nb] = up(w_cb[0]);
-    L(k_seg_combine<kNV, 0, 1, true>, nb, 1, ib);
+  BatchPlan plan(count);
+  const uint32_t q_instr = plan.add(w_instr), q_scope = plan.add(w_scope), q_edge = plan.add(w_edge);
+  uint32_t q_ch[3], q_cb[3];
+  for (int g = 0; g < 3; ++g) {
+    q_ch[g] = plan.add(w_ch[g]);
+    q_cb[g] = plan.add(w_cb[g]);
   }
-  L(k_edge_contrib<true>, n_edge, 1, i_edge);
-  L(k_seg_small<1, 1, 2, true>, n_scope, 2, i_scope);
-  {
-    auto [ic, nc] = up(w_ch[1]);
-    L(k_seg_chunks<1, 1, 2, true>, nc, 2, ic);
-    auto [ib, nb] = up(w_cb[1]);
-    L(k_seg_combine<1, 1, 2, true>, nb, 2, ib);
-  }
-  L(k_seg_small<kNV, 3, 1, true>, n_scope, 1, i_scope);
-  {
-    auto [ic, nc] = up(w_ch[2]);
-    L(k_seg_chunks<kNV, 3, 1, true>, nc, 1, ic);
-    auto [ib, nb] = up(w_cb[2]);
-    L(k_seg_combine<kNV, 3, 1, true>, nb, 1, ib);
-  }
-  L(k_speedup<true>, n_scope, 1, i_scope);
-  auto [i_tkc, n_tkc] = up(w_tkc);
-  auto [i_tkf, n_tkf] = up(w_tkf);
-  if (n_tkc) {
-    hipLaunchKernelGGL(k_topk_chunks<true>, dim3(n_tkc), dim3(kTopThreads), 0, s, EstArgs{},
-                       L.many, i_tkc);
+  const uint32_t q_tkc = plan.add(w_tkc), q_tkf = plan.add(w_tkf);
+  Upload up;
+  const size_t i_args = up.add(args), i_pre = up.add(plan.pre);
+  up.send(ar, s);
+  plan.d_pre = up.ptr<uint32_t>(i_pre);
+  plan.d_items = ar.get<WorkItem>(plan.total_items());
+  plan.expand(s);
+  EstLaunch L{s, EstArgs{}, up.ptr<EstArgs>(i_args)};
+  auto run = [&](auto kern, uint32_t q, unsigned gy) { L(kern, plan.blocks(q), gy, plan.items(q)); };
+  run(k_line_contrib<true>, q_instr, 1);
+  run(k_seg_small<kNV, 0, 1, true>, q_scope, 1);
+  run(k_seg_chunks<kNV, 0, 1, true>, q_ch[0], 1);
+  run(k_seg_combine<kNV, 0, 1, true>, q_cb[0], 1);
+  run(k_edge_contrib<true>, q_edge, 1);
+  run(k_seg_small<1, 1, 2, true>, q_scope, 2);
+  run(k_seg_chunks<1, 1, 2, true>, q_ch[1], 2);
+  run(k_seg_combine<1, 1, 2, true>, q_cb[1], 2);
+  run(k_seg_small<kNV, 3, 1, true>, q_scope, 1);
+  run(k_seg_chunks<kNV, 3, 1, true>, q_ch[2], 1);
+  run(k_seg_combine<kNV, 3, 1, true>, q_cb[2], 1);
+  run(k_speedup<true>, q_scope, 1);
+  if (plan.blocks(q_tkc)) {
+    hipLaunchKernelGGL(k_topk_chunks<true>, dim3(plan.blocks(q_tkc)), dim3(kTopThreads), 0, s,
+                       EstArgs{}, L.many, plan.items(q_tkc));
     GPA_LAUNCH_CHECK();
   }
-  if (n_tkf) {
-    hipLaunchKernelGGL(k_topk_final<true>, dim3(n_tkf), dim3(kTopThreads), 0, s, EstArgs{},
-                       L.many, i_tkf);
+  if (plan.blocks(q_tkf)) {
+    hipLaunchKernelGGL(k_topk_final<true>, dim3(plan.blocks(q_tkf)), dim3(kTopThreads), 0, s,
+                       EstArgs{}, L.many, plan.items(q_tkf));
     GPA_LAUNCH_CHECK();
   }
 }

@@ -1142,21 +1142,19 @@ static bool run_hist_hot(const gpa_program &p, const uint64_t *rec, uint64_t n, 
   return true;
 }
 
-size_t hist_batch_scratch_bytes(const HistEntry *e, uint32_t count, uint64_t per) {
-  size_t total = 0, items = 0;
-  for (uint32_t k = 0; k < count; ++k) {
-    const HotShape h = hot_shape(e[k].n_instr, e[k].n, per);
-    total += hot_scratch(h, e[k].n);
-    items += 1 + h.G + h.n_cb + h.n_merge + 1;
-  }
-  return total + blk256(sizeof(HotArgs) * (size_t)count) + blk256(sizeof(WorkItem) * items);
-}
+// A batched histogram ready to launch: its argument table and work lists on
+// the device (uploaded and expanded on the stream).
+struct HistBatch {
+  BatchPlan plan;
+  const HotArgs *d_args = nullptr;
+  uint32_t q_sel = 0, q_pass = 0, q_fin = 0;
+  explicit HistBatch(uint32_t count) : plan(count) {}
+};
 
-void run_hist_batch(const HistEntry *e, uint32_t count, uint64_t per, hipStream_t s, Arena &ar) {
-  if (count == 0) return;
+static void prepare_hist_batch(HistBatch &hb, const HistEntry *e, uint32_t count, uint64_t per,
+                               hipStream_t s, Arena &ar) {
   std::vector<HotArgs> args(count);
-  std::vector<WorkItem> sel, pass, fin;
-  sel.reserve(count);
+  std::vector<uint32_t> n_sel(count, 1u), n_pass(count), n_fin(count);
   for (uint32_t k = 0; k < count; ++k) {
     if (e[k].n == 0 || e[k].n_instr > kHotMaxPCs || ((uintptr_t)e[k].samples % 16) != 0)
       fail(GPA_E_INVALID, "batched histogram entry %u: n > 0, at most %u instructions and "
@@ -1164,26 +1162,40 @@ void run_hist_batch(const HistEntry *e, uint32_t count, uint64_t per, hipStream_
     const HotShape h = hot_shape(e[k].n_instr, e[k].n, per);
     args[k] = hot_args(h, (const uint64_t *)e[k].samples, e[k].n, e[k].n_instr, e[k].counts,
                        e[k].totals, ar);
-    sel.push_back({k, 0});
-    for (uint32_t w = 0; w < h.G; ++w) pass.push_back({k, w});
-    for (uint32_t b = 0; b < h.n_cb + h.n_merge + 1; ++b) fin.push_back({k, b});
+    n_pass[k] = h.G;
+    n_fin[k] = h.n_cb + h.n_merge + 1;
   }
-  std::vector<WorkItem> all(sel);
-  all.insert(all.end(), pass.begin(), pass.end());
-  all.insert(all.end(), fin.begin(), fin.end());
-  const HotArgs *d_args = ar.upload(args, s);
-  const WorkItem *d_items = ar.upload(all, s);
+  hb.q_sel = hb.plan.add(n_sel);
+  hb.q_pass = hb.plan.add(n_pass);
+  hb.q_fin = hb.plan.add(n_fin);
+  Upload up;
+  const size_t i_args = up.add(args), i_pre = up.add(hb.plan.pre);
+  up.send(ar, s);
+  hb.d_args = up.ptr<HotArgs>(i_args);
+  hb.plan.d_pre = up.ptr<uint32_t>(i_pre);
+  hb.plan.d_items = ar.get<WorkItem>(hb.plan.total_items());
+  hb.plan.expand(s);
+}
+
+static void launch_hist_batch(const HistBatch &hb, hipStream_t s) {
   HotArgs none{};
   set_select_lds();
-  hipLaunchKernelGGL(k_hot_select<true>, dim3((unsigned)sel.size()), dim3(kHotThreads),
-                     kSelLdsWords * 4, s, none, d_args, d_items);
+  hipLaunchKernelGGL(k_hot_select<true>, dim3(hb.plan.blocks(hb.q_sel)), dim3(kHotThreads),
+                     kSelLdsWords * 4, s, none, hb.d_args, hb.plan.items(hb.q_sel));
   GPA_LAUNCH_CHECK();
-  hipLaunchKernelGGL((k_hot_pass<true, true>), dim3((unsigned)pass.size()), dim3(kHotThreads), 0, s,
-                     none, d_args, d_items + sel.size());
+  hipLaunchKernelGGL((k_hot_pass<true, true>), dim3(hb.plan.blocks(hb.q_pass)), dim3(kHotThreads),
+                     0, s, none, hb.d_args, hb.plan.items(hb.q_pass));
   GPA_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_hot_finish<true>, dim3((unsigned)fin.size()), dim3(kHotThreads), 0, s, none,
-                     d_args, d_items + sel.size() + pass.size());
+  hipLaunchKernelGGL(k_hot_finish<true>, dim3(hb.plan.blocks(hb.q_fin)), dim3(kHotThreads), 0, s,
+                     none, hb.d_args, hb.plan.items(hb.q_fin));
   GPA_LAUNCH_CHECK();
+}
+
+void run_hist_batch(const HistEntry *e, uint32_t count, uint64_t per, hipStream_t s, Arena &ar) {
+  if (count == 0) return;
+  HistBatch hb(count);
+  prepare_hist_batch(hb, e, count, per, s, ar);
+  launch_hist_batch(hb, s);
 }
 
 // ------------------------------------------------------------- autotuner
@@ -1235,9 +1247,13 @@ uint64_t batch_records_per_workgroup(const HistEntry *e, uint32_t count, hipStre
     for (int rep = 0; rep < 2; ++rep) {
       for (uint64_t per : kPerCandidates) {
         if (rep == 1 && per != kPerCandidates[0]) continue;
-        Arena trial(s);   // each candidate's scratch goes back to the pool after it
+        // each candidate's scratch goes back to the pool after it; only the
+        // three launches are timed, not the host's preparation
+        Arena trial(s);
+        HistBatch hb(count);
+        prepare_hist_batch(hb, e, count, per, s, trial);
         GPA_HIP(hipEventRecord(a, s));
-        run_hist_batch(e, count, per, s, trial);
+        launch_hist_batch(hb, s);
         GPA_HIP(hipEventRecord(b, s));
         GPA_HIP(hipEventSynchronize(b));
         float ms = 0.f;

@@ -1,0 +1,54 @@
+// Work lists of the batched launches, expanded on the device from per-entry
+// block counts: a workgroup of stage q's launch reads one WorkItem (its
+// entry and its block index within that entry's share).
+#include "common.h"
+
+namespace gpa {
+
+uint32_t BatchPlan::add(const std::vector<uint32_t> &blocks) {
+  if (t.n_stages >= kMaxStages) fail(GPA_E_DEVICE, "too many stages in one batched launch chain");
+  if (blocks.size() != t.count) fail(GPA_E_DEVICE, "stage with a wrong number of entries");
+  const uint32_t q = t.n_stages++;
+  t.pre_off[q] = (uint32_t)pre.size();
+  uint64_t run = 0;
+  pre.push_back(0);
+  for (uint32_t b : blocks) {
+    run += b;
+    if (run >= (1ull << 31)) fail(GPA_E_UNSUPPORTED, "a batched launch of 2^31 workgroups or more");
+    pre.push_back((uint32_t)run);
+  }
+  t.item_off[q + 1] = t.item_off[q] + run;
+  return q;
+}
+
+// item i of the concatenated stages: its stage (a short scan of the table),
+// then the entry e with pre[e] <= i' < pre[e + 1] by bisection (entries
+// without blocks have pre[e] == pre[e + 1] and are never chosen)
+__global__ void __launch_bounds__(256) k_expand_items(const uint32_t *__restrict__ pre, StageTable t,
+                                                      WorkItem *__restrict__ items) {
+  const uint64_t total = t.item_off[t.n_stages];
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < total;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t q = 0;
+    while (i >= t.item_off[q + 1]) ++q;
+    const uint32_t li = (uint32_t)(i - t.item_off[q]);
+    const uint32_t *P = pre + t.pre_off[q];
+    uint32_t lo = 0, hi = t.count;   // P[lo] <= li < P[hi]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) / 2;
+      if (P[mid] <= li) lo = mid;
+      else hi = mid;
+    }
+    items[i] = WorkItem{lo, li - P[lo]};
+  }
+}
+
+void BatchPlan::expand(hipStream_t s) {
+  const uint64_t total = total_items();
+  if (total == 0) return;
+  hipLaunchKernelGGL(k_expand_items, dim3(grid_for(total, 256, 4096)), dim3(256), 0, s, d_pre, t,
+                     d_items);
+  GPA_LAUNCH_CHECK();
+}
+
+}  // namespace gpa
