@@ -30,6 +30,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import statistics
 import sys
 import time
@@ -42,9 +43,9 @@ HBM_PEAK_GBS = 8000.0
 ALU_PEAK_GOPS = 256 * 64 * 2.4e9 / 1e9
 HIST_SOURCE = os.path.join(HERE, "paper_2009_04061_amd", "csrc", "hist.hip")
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "hist_batch_wholeapp_traffic.json")
-HIST_KERNELS = ("k_hot_select", "k_hot_pass", "k_hot_finish",
-                "k_hsample", "k_hregions", "k_partition", "k_hplan", "k_count", "k_merge",
-                "k_hoverflow")
+# the batched histogram's kernels: gpa::k_hot_*<..., true> (the last template
+# argument selects the batched instantiation)
+HIST_BATCH_RE = r"gpa::(k_hot_select|k_hot_pass|k_hot_finish)<(?:[^<>]*, )?true>"
 
 
 def log(msg):
@@ -97,9 +98,9 @@ def summarize_traffic(fetch_dir, write_dir, copy_mb, out_path, steps):
             v = float(r["Counter_Value"])
             if "copyBuffer" in name:
                 copy_vals.append(v)
-            for k in HIST_KERNELS:
-                if ("gpa::" + k + "(") in name or ("gpa::" + k + "<") in name:
-                    per_kernel.setdefault(k, []).append((int(r.get("Dispatch_Id", 0)), v))
+            m = re.search(HIST_BATCH_RE, name)
+            if m:
+                per_kernel.setdefault(m.group(1), []).append((int(r.get("Dispatch_Id", 0)), v))
         if not copy_vals:
             raise SystemExit(f"no copy kernel in the {counter} run")
         # the timed steps are the last `steps` dispatches of each kernel (the
@@ -120,6 +121,46 @@ def summarize_traffic(fetch_dir, write_dir, copy_mb, out_path, steps):
     with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))
+
+
+def summarize_kernels(trace_dir, out_path, steps, command):
+    """A markdown table of the batched step's kernels from a rocprofv3
+    --kernel-trace --stats run (CSV output) of this script: per kernel, the
+    dispatches of the last `steps` batched steps of the headline workload
+    and their average duration."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True):
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    batched = {}
+    for r in rows:
+        name = r.get("Kernel_Name", "")
+        m = re.search(r"gpa::(k_\w+)<(?:[^<>]*, )?true>", name)
+        if not m:
+            continue
+        key = name[name.index("gpa::"):].split("(")[0]
+        batched.setdefault(key, []).append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    # the timed steps are each batched kernel's last `steps` dispatches (the
+    # run is made with --no-config2, so no other batch follows them)
+    lines = [f"# Batched step kernels: whole application (400 kernels, 500M records)", "",
+             f"Command: `{command}`", "",
+             "Per kernel: the last {} dispatches (the timed steps); durations from "
+             "the kernel trace.".format(steps), "",
+             "| kernel | dispatches | avg µs | total per step µs |", "|---|---|---|---|"]
+    tot = 0.0
+    for key, v in sorted(batched.items(), key=lambda kv: -sum(e - b for b, e in kv[1][-steps:])):
+        last = sorted(v)[-steps:]
+        d = [(e - b) / 1e3 for b, e in last]
+        avg = sum(d) / len(d)
+        per_step = sum(d) / steps
+        tot += per_step
+        lines.append(f"| `{key}` | {len(last)} | {avg:.1f} | {per_step:.1f} |")
+    lines += ["", f"GPU time of the batched kernels per step: {tot / 1e3:.3f} ms."]
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def _pct(values, q):
@@ -378,11 +419,18 @@ def main():
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="no benchmark: turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) "
                          "of this script with --copy-mb into the traffic summary")
+    ap.add_argument("--kernel-summary", nargs=3, metavar=("TRACE_DIR", "OUT_MD", "COMMAND"),
+                    help="no benchmark: turn a rocprofv3 --kernel-trace run (CSV) of this script "
+                         "with --no-config2 into a markdown table of the batched step's kernels")
     args = ap.parse_args()
 
     if args.traffic_summary:
         summarize_traffic(args.traffic_summary[0], args.traffic_summary[1],
                           args.copy_mb or 512, TRAFFIC_FILE, args.steps)
+        return
+    if args.kernel_summary:
+        summarize_kernels(args.kernel_summary[0], args.kernel_summary[1], args.steps,
+                          args.kernel_summary[2])
         return
 
     if args.gpus != 1:
