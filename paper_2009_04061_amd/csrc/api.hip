@@ -363,9 +363,9 @@ gpa_blame::~gpa_blame() {
   counts.release();
   dtotals.release();
   share.release();
-  blamed.release();
-  self_.release();
-  fine.release();
+  bl.release();
+  fx.release();
+  nocand.release();
   shared.reset();
   gpa::program_release(prog);
 }
@@ -760,9 +760,17 @@ gpa_status gpa_blame_table(const gpa_blame *b, double *blamed, double *self_, do
   return guarded([&] {
     hipStream_t s = nullptr;
     const size_t n = b->prog->n_instr;
-    copy_out(blamed, b->blamed, n * 24, s);
-    copy_out(self_, b->self_, n * 24, s);
-    copy_out(fine, b->fine, n * GPA_N_FINE * 2, s);
+    // the full tables are expanded from the compact ones into scratch
+    Arena ar(s);
+    double *d_blamed = blamed ? ar.get<double>(n * 24) : nullptr;
+    double *d_self = self_ ? ar.get<double>(n * 24) : nullptr;
+    double *d_fine = fine ? ar.get<double>(n * GPA_N_FINE * 2) : nullptr;
+    expand_blame_tables(*b->prog, b->counts.p, b->bl.p, b->fx.p, b->nocand.p, d_blamed, d_self,
+                        d_fine, s);
+    if (blamed && n) GPA_HIP(hipMemcpyAsync(blamed, d_blamed, n * 24 * 8, hipMemcpyDeviceToHost, s));
+    if (self_ && n) GPA_HIP(hipMemcpyAsync(self_, d_self, n * 24 * 8, hipMemcpyDeviceToHost, s));
+    if (fine && n)
+      GPA_HIP(hipMemcpyAsync(fine, d_fine, n * GPA_N_FINE * 2 * 8, hipMemcpyDeviceToHost, s));
     GPA_HIP(hipStreamSynchronize(s));
   });
 }

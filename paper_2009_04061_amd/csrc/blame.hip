@@ -13,6 +13,15 @@
 // k_blame_dst owns one destination and writes its edges' shares; k_blame_src
 // owns one source and sums its outgoing shares in edge order, so every FP64
 // sum has a fixed order and no floating-point atomics are used.
+//
+// The per-instruction results are kept compact on the device: the blamed
+// samples of the blamable reasons only (bl, [n_instr][n_blamable][2]), one
+// bit per blamable reason telling whether its samples stayed on the
+// instruction for want of a candidate (nocand), and the execution-dependency
+// split into WAR and other sources plus the samples of blamable reasons
+// outside the memory / execution / synchronization classes (fx, 6 per
+// instruction).  Everything else of the full tables follows from these and
+// the counts; k_blame_expand writes the full tables when they are asked for.
 #include "common.h"
 #include "devutil.h"
 
@@ -27,7 +36,8 @@ struct BlameArgs {
   uint16_t allowed[12];
   const uint32_t *counts, *in_ptr, *e_src, *e_dmax, *out_ptr, *out_perm;
   const uint8_t *e_flags, *op_class;
-  double *share, *self_, *blamed, *fine;
+  double *share, *bl, *fx;
+  uint16_t *nocand;
 };
 constexpr int kBlameThreads = 128;
 
@@ -108,21 +118,21 @@ k_blame_dst(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *_
         ++slot;
       }
     }
+    uint32_t mask = 0, bit = 0;
 #pragma unroll
     for (int r = 0; r < 12; ++r) {
-      const bool blam = (arch.blamable >> r) & 1u;
-#pragma unroll
-      for (int l = 0; l < 2; ++l) {
-        const uint32_t S = C[r * 2 + l];
-        a.self_[(size_t)j * 24 + r * 2 + l] = (S != 0 && (!blam || !any[r])) ? (double)S : 0.0;
-      }
+      if (!((arch.blamable >> r) & 1u)) continue;
+      mask |= any[r] ? 0u : (1u << bit);
+      ++bit;
     }
+    a.nocand[j] = (uint16_t)mask;
   }
 }
 
-// Sums in edge order; the fine class of a memory dependency or a non-WAR
-// execution dependency depends only on the source's opcode class, so each
-// fine class is one accumulator (no run-time indexing of private arrays).
+// One thread per source i: sums its outgoing shares in edge order, per
+// blamable reason, and the execution-dependency shares split by the WAR flag
+// of the edge (the fine classes of a memory dependency and of a non-WAR
+// execution dependency follow from i's opcode class alone).
 template <bool BATCH>
 __global__ void __launch_bounds__(kBlameThreads)
 k_blame_src(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *__restrict__ items) {
@@ -131,15 +141,11 @@ k_blame_src(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *_
     const uint32_t *__restrict__ out_ptr = a.out_ptr;
     const uint32_t *__restrict__ out_perm = a.out_perm;
     const uint8_t *__restrict__ e_flags = a.e_flags;
-    const uint8_t *__restrict__ op_class = a.op_class;
     const double *__restrict__ share = a.share;
-    double *__restrict__ blamed = a.blamed;
-    double *__restrict__ fine = a.fine;
     double acc[24];
 #pragma unroll
     for (int q = 0; q < 24; ++q) acc[q] = 0.0;
     double war0 = 0.0, war1 = 0.0, nwar0 = 0.0, nwar1 = 0.0, oth0 = 0.0, oth1 = 0.0;
-    const uint32_t cls = op_class[i];
     for (uint32_t k = out_ptr[i]; k < out_ptr[i + 1]; ++k) {
       const uint32_t e = out_perm[k];
       const bool war = (e_flags[e] & GPA_E_WAR) != 0;
@@ -166,25 +172,92 @@ k_blame_src(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *_
         ++slot;
       }
     }
+    double *bl = a.bl + (size_t)i * nbl * 2;
+    uint32_t slot = 0;
 #pragma unroll
-    for (int q = 0; q < 24; ++q) blamed[(size_t)i * 24 + q] = acc[q];
+    for (uint32_t r = 0; r < 12; ++r) {
+      if (!((blamable >> r) & 1u)) continue;
+      bl[slot * 2] = acc[r * 2];
+      bl[slot * 2 + 1] = acc[r * 2 + 1];
+      ++slot;
+    }
+    double *fx = a.fx + (size_t)i * kBlameFx;
+    fx[0] = war0;
+    fx[1] = war1;
+    fx[2] = nwar0;
+    fx[3] = nwar1;
+    fx[4] = oth0;
+    fx[5] = oth1;
+  }
+}
+
+// The full per-instruction tables of the C-ABI from the compact ones, one
+// thread per instruction:
+//   blamed[j][r][l] = bl[j][slot(r)][l] for a blamable r, else 0;
+//   self_[j][r][l]  = C[j][r][l] for a reason that is not blamable or whose
+//                     samples found no candidate, else 0;
+//   fine[j]         = the memory dependency blamed on j in the class of j's
+//                     opcode (local, constant, global), the execution
+//                     dependency split into WAR and the rest (shared-memory
+//                     or arithmetic by j's opcode), synchronization, and the
+//                     other blamable reasons.
+__global__ void __launch_bounds__(256)
+k_blame_expand(uint32_t n_instr, uint32_t nbl, uint32_t blamable, const uint32_t *__restrict__ counts,
+               const uint8_t *__restrict__ op_class, const double *__restrict__ bl_all,
+               const double *__restrict__ fx_all, const uint16_t *__restrict__ nocand,
+               double *__restrict__ blamed, double *__restrict__ self_, double *__restrict__ fine) {
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_instr;
+       j += gridDim.x * blockDim.x) {
+    const uint32_t *C = counts + (size_t)j * 24;
+    const double *bl = bl_all + (size_t)j * nbl * 2;
+    const double *fx = fx_all + (size_t)j * kBlameFx;
+    const uint32_t nc = nocand[j];
+    double mem0 = 0.0, mem1 = 0.0, sync0 = 0.0, sync1 = 0.0;
+    uint32_t slot = 0;
+    for (uint32_t r = 0; r < 12; ++r) {
+      const bool blam = (blamable >> r) & 1u;
+      double b0 = 0.0, b1 = 0.0;
+      bool kept = true;
+      if (blam) {
+        b0 = bl[slot * 2];
+        b1 = bl[slot * 2 + 1];
+        kept = (nc >> slot) & 1u;
+        ++slot;
+      }
+      if (r == GPA_ST_MEM_DEP) {
+        mem0 = b0;
+        mem1 = b1;
+      } else if (r == GPA_ST_SYNC) {
+        sync0 = b0;
+        sync1 = b1;
+      }
+      if (blamed) {
+        blamed[(size_t)j * 24 + r * 2] = b0;
+        blamed[(size_t)j * 24 + r * 2 + 1] = b1;
+      }
+      if (self_) {
+        self_[(size_t)j * 24 + r * 2] = kept ? (double)C[r * 2] : 0.0;
+        self_[(size_t)j * 24 + r * 2 + 1] = kept ? (double)C[r * 2 + 1] : 0.0;
+      }
+    }
+    if (!fine) continue;
+    const uint32_t cls = op_class[j];
     const uint32_t fm = (cls == GPA_OP_LOCAL_LOAD || cls == GPA_OP_LOCAL_STORE) ? GPA_F_MEM_LOCAL
                         : (cls == GPA_OP_CONST_LOAD)                           ? GPA_F_MEM_CONST
                                                                                : GPA_F_MEM_GLOBAL;
-    const uint32_t fx = (cls == GPA_OP_SHARED_LOAD) ? GPA_F_EXEC_SHARED : GPA_F_EXEC_ARITH;
-    double *dst = fine + (size_t)i * GPA_N_FINE * 2;
-#pragma unroll
+    const uint32_t fe = (cls == GPA_OP_SHARED_LOAD) ? GPA_F_EXEC_SHARED : GPA_F_EXEC_ARITH;
+    double *dst = fine + (size_t)j * GPA_N_FINE * 2;
     for (int q = 0; q < GPA_N_FINE * 2; ++q) dst[q] = 0.0;
-    dst[fm * 2] = acc[GPA_ST_MEM_DEP * 2];
-    dst[fm * 2 + 1] = acc[GPA_ST_MEM_DEP * 2 + 1];
-    dst[GPA_F_EXEC_WAR * 2] = war0;
-    dst[GPA_F_EXEC_WAR * 2 + 1] = war1;
-    dst[fx * 2] = nwar0;
-    dst[fx * 2 + 1] = nwar1;
-    dst[GPA_F_SYNC * 2] = acc[GPA_ST_SYNC * 2];
-    dst[GPA_F_SYNC * 2 + 1] = acc[GPA_ST_SYNC * 2 + 1];
-    dst[GPA_F_OTHER * 2] = oth0;
-    dst[GPA_F_OTHER * 2 + 1] = oth1;
+    dst[fm * 2] = mem0;
+    dst[fm * 2 + 1] = mem1;
+    dst[GPA_F_EXEC_WAR * 2] = fx[0];
+    dst[GPA_F_EXEC_WAR * 2 + 1] = fx[1];
+    dst[fe * 2] = fx[2];
+    dst[fe * 2 + 1] = fx[3];
+    dst[GPA_F_SYNC * 2] = sync0;
+    dst[GPA_F_SYNC * 2 + 1] = sync1;
+    dst[GPA_F_OTHER * 2] = fx[4];
+    dst[GPA_F_OTHER * 2 + 1] = fx[5];
   }
 }
 
@@ -192,14 +265,14 @@ void run_blame(const gpa_program &p, gpa_blame &b, hipStream_t s, Arena &ar) {
   (void)ar;
   const uint32_t n = p.n_instr;
   b.share.alloc(p.n_edges * p.n_blamable * 2);
-  b.blamed.alloc((size_t)n * 24);
-  b.self_.alloc((size_t)n * 24);
-  b.fine.alloc((size_t)n * GPA_N_FINE * 2);
-  launch_blame(p, b.counts.p, b.share.p, b.blamed.p, b.self_.p, b.fine.p, s);
+  b.bl.alloc((size_t)n * p.n_blamable * 2);
+  b.fx.alloc((size_t)n * kBlameFx);
+  b.nocand.alloc(n);
+  launch_blame(p, b.counts.p, b.share.p, b.bl.p, b.fx.p, b.nocand.p, s);
 }
 
 static BlameArgs blame_args(const gpa_program &p, const uint32_t *counts, double *share,
-                            double *blamed, double *self_, double *fine) {
+                            double *bl, double *fx, uint16_t *nocand) {
   BlameArgs a;
   a.n_instr = p.n_instr;
   a.nbl = p.n_blamable;
@@ -214,19 +287,29 @@ static BlameArgs blame_args(const gpa_program &p, const uint32_t *counts, double
   a.e_flags = p.e_flags.p;
   a.op_class = p.op_class.p;
   a.share = share;
-  a.self_ = self_;
-  a.blamed = blamed;
-  a.fine = fine;
+  a.bl = bl;
+  a.fx = fx;
+  a.nocand = nocand;
   return a;
 }
 
-void launch_blame(const gpa_program &p, const uint32_t *counts, double *share, double *blamed,
-                  double *self_, double *fine, hipStream_t s) {
-  const BlameArgs a = blame_args(p, counts, share, blamed, self_, fine);
+void launch_blame(const gpa_program &p, const uint32_t *counts, double *share, double *bl,
+                  double *fx, uint16_t *nocand, hipStream_t s) {
+  const BlameArgs a = blame_args(p, counts, share, bl, fx, nocand);
   const unsigned g = grid_for(p.n_instr, kBlameThreads, 8192);
   hipLaunchKernelGGL(k_blame_dst<false>, dim3(g), dim3(kBlameThreads), 0, s, a, nullptr, nullptr);
   GPA_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_blame_src<false>, dim3(g), dim3(kBlameThreads), 0, s, a, nullptr, nullptr);
+  GPA_LAUNCH_CHECK();
+}
+
+void expand_blame_tables(const gpa_program &p, const uint32_t *counts, const double *bl,
+                         const double *fx, const uint16_t *nocand, double *blamed, double *self_,
+                         double *fine, hipStream_t s) {
+  if (p.n_instr == 0) return;
+  hipLaunchKernelGGL(k_blame_expand, dim3(grid_for(p.n_instr, 256, 8192)), dim3(256), 0, s,
+                     p.n_instr, p.n_blamable, (uint32_t)p.arch.blamable, counts, p.op_class.p, bl,
+                     fx, nocand, blamed, self_, fine);
   GPA_LAUNCH_CHECK();
 }
 
@@ -238,11 +321,11 @@ void run_blame_batch(const gpa_program *const *progs, gpa_blame *const *b, uint3
     const gpa_program &p = *progs[k];
     const uint32_t n = p.n_instr;
     sh.carve(b[k]->share, p.n_edges * p.n_blamable * 2);
-    sh.carve(b[k]->blamed, (size_t)n * 24);
-    sh.carve(b[k]->self_, (size_t)n * 24);
-    sh.carve(b[k]->fine, (size_t)n * GPA_N_FINE * 2);
-    args[k] = blame_args(p, b[k]->counts.p, b[k]->share.p, b[k]->blamed.p, b[k]->self_.p,
-                         b[k]->fine.p);
+    sh.carve(b[k]->bl, (size_t)n * p.n_blamable * 2);
+    sh.carve(b[k]->fx, (size_t)n * kBlameFx);
+    sh.carve(b[k]->nocand, n);
+    args[k] = blame_args(p, b[k]->counts.p, b[k]->share.p, b[k]->bl.p, b[k]->fx.p,
+                         b[k]->nocand.p);
     tiles[k] = (n + kBlameThreads - 1) / kBlameThreads;
   }
   BatchPlan plan(count);

@@ -269,8 +269,10 @@ struct gpa_blame {
   gpa::DBuf<uint32_t> counts;          // [n_instr*24]
   gpa::DBuf<unsigned long long> dtotals;
   gpa::DBuf<double> share;             // [n_edges*n_blamable*2]
-  gpa::DBuf<double> blamed, self_;     // [n_instr*24]
-  gpa::DBuf<double> fine;              // [n_instr*GPA_N_FINE*2]
+  // compact per-instruction results (the full tables are expanded on request)
+  gpa::DBuf<double> bl;                // [n_instr*n_blamable*2] blamed, blamable reasons
+  gpa::DBuf<double> fx;                // [n_instr*kBlameFx] WAR / other / rest splits
+  gpa::DBuf<uint16_t> nocand;          // [n_instr] blamable reasons kept for want of a candidate
   explicit gpa_blame(const gpa_program *p);
   ~gpa_blame();
 };
@@ -462,14 +464,22 @@ void build_dist_tables(gpa_program &p, hipStream_t s, const SweepPlan &plan, con
                        const DistTables &t, bool longest);
 // per edge: dmin, dmax and the latency rule's flag from the tables
 void build_distances(gpa_program &p, hipStream_t s, Arena &ar, const DistTables &t);
+// per instruction: execution dependency from WAR and from other sources,
+// other blamable reasons (each for both latency bits)
+constexpr uint32_t kBlameFx = 6;
 constexpr uint32_t kSmallSeg = 64;   // longest segment one thread sums alone
 constexpr uint32_t kSegChunk = 4096; // elements of a longer segment per workgroup
 void build_scope_targets(gpa_program &p, hipStream_t s, Arena &ar);
 // blame.hip: run_blame allocates the blame handle's tables and calls
 // launch_blame, which writes caller-given device arrays and allocates nothing
 void run_blame(const gpa_program &p, gpa_blame &b, hipStream_t s, Arena &ar);
-void launch_blame(const gpa_program &p, const uint32_t *counts, double *share, double *blamed,
-                  double *self_, double *fine, hipStream_t s);
+void launch_blame(const gpa_program &p, const uint32_t *counts, double *share, double *bl,
+                  double *fx, uint16_t *nocand, hipStream_t s);
+// the full tables of the C-ABI (blamed, self_: [n_instr*24]; fine:
+// [n_instr*GPA_N_FINE*2]; any may be NULL) from the compact ones, on s
+void expand_blame_tables(const gpa_program &p, const uint32_t *counts, const double *bl,
+                         const double *fx, const uint16_t *nocand, double *blamed, double *self_,
+                         double *fine, hipStream_t s);
 // The histogram and blame of `count` profiles whose records are on the
 // device at ds[k]: creates b[k] with its tables, totals to dtot[4k..4k+3]
 // (device).  With measure_tuning the autotuner may time candidates, and the

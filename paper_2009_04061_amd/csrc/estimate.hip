@@ -35,10 +35,11 @@ struct Cand {
 // the scratch of the roll-up and the advice's outputs.
 struct EstArgs {
   uint32_t n_instr, ns, nbl, n_roots, k, tk_chunks;
-  int32_t s_mem, s_exec;
+  int32_t s_mem, s_exec, s_sync;   // slots of these reasons among the blamable ones, or -1
   uint64_t n_edges;
   const uint32_t *counts;
-  const double *blamed, *self_, *share;
+  const double *bl, *share;
+  const uint16_t *nocand;
   const uint8_t *op_class, *tags;
   const uint32_t *e_src, *line_ptr, *line_perm, *icl_ptr, *icl_perm, *lca_ptr, *lca_perm;
   const uint32_t *scope_end, *scope_parent, *root_of, *roots;
@@ -71,8 +72,19 @@ k_line_contrib(EstArgs one, const EstArgs *__restrict__ many, const WorkItem *__
   EST_ITEM(a.n_instr, kk) {
     const uint32_t k = a.line_perm[kk];
     const uint32_t *C = a.counts + (size_t)k * 24;
-    const double *Bl = a.blamed + (size_t)k * 24;
-    const double *Sf = a.self_ + (size_t)k * 24;
+    // blamed samples of the three blamable classes and the synchronization
+    // samples kept on k (all of them when synchronization is not blamable,
+    // none when a candidate took them)
+    const double *Bk = a.bl + (size_t)k * a.nbl * 2;
+    const double bm0 = a.s_mem >= 0 ? Bk[a.s_mem * 2] : 0.0;
+    const double bm1 = a.s_mem >= 0 ? Bk[a.s_mem * 2 + 1] : 0.0;
+    const double be0 = a.s_exec >= 0 ? Bk[a.s_exec * 2] : 0.0;
+    const double be1 = a.s_exec >= 0 ? Bk[a.s_exec * 2 + 1] : 0.0;
+    const double bs0 = a.s_sync >= 0 ? Bk[a.s_sync * 2] : 0.0;
+    const double bs1 = a.s_sync >= 0 ? Bk[a.s_sync * 2 + 1] : 0.0;
+    const bool sync_kept = a.s_sync < 0 || ((a.nocand[k] >> a.s_sync) & 1u);
+    const double ks0 = sync_kept ? (double)C[GPA_ST_SYNC * 2] : 0.0;
+    const double ks1 = sync_kept ? (double)C[GPA_ST_SYNC * 2 + 1] : 0.0;
     double act = 0.0, lat = 0.0, stalls = 0.0;
     for (int r = 0; r < 12; ++r) {
       act += (double)C[r * 2];
@@ -83,15 +95,14 @@ k_line_contrib(EstArgs one, const EstArgs *__restrict__ many, const WorkItem *__
     const uint8_t tg = a.tags[k];
     double v[kNV];
     v[GPA_O_REGISTER_REUSE] = (cls == GPA_OP_LOCAL_LOAD || cls == GPA_OP_LOCAL_STORE)
-                                  ? Bl[GPA_ST_MEM_DEP * 2] + Bl[GPA_ST_MEM_DEP * 2 + 1]
+                                  ? bm0 + bm1
                                   : 0.0;
     v[GPA_O_STRENGTH_REDUCTION] = (cls == GPA_OP_FP64 || cls == GPA_OP_LONG_ALU)
-                                      ? Bl[GPA_ST_EXEC_DEP * 2] + Bl[GPA_ST_EXEC_DEP * 2 + 1]
+                                      ? be0 + be1
                                       : 0.0;
     v[GPA_O_FUNCTION_SPLIT] = (double)C[GPA_ST_INST_FETCH * 2] + (double)C[GPA_ST_INST_FETCH * 2 + 1];
     v[GPA_O_FAST_MATH] = (tg & 1) ? stalls : 0.0;
-    v[GPA_O_WARP_BALANCE] = Bl[GPA_ST_SYNC * 2] + Bl[GPA_ST_SYNC * 2 + 1] + Sf[GPA_ST_SYNC * 2] +
-                            Sf[GPA_ST_SYNC * 2 + 1];
+    v[GPA_O_WARP_BALANCE] = bs0 + bs1 + ks0 + ks1;
     v[GPA_O_MEM_TRANSACTION_REDUCTION] =
         (cls == GPA_OP_GLOBAL_LOAD || cls == GPA_OP_GLOBAL_STORE)
             ? (double)C[GPA_ST_MEM_THROTTLE * 2] + (double)C[GPA_ST_MEM_THROTTLE * 2 + 1]
@@ -552,10 +563,11 @@ static EstArgs est_args(const gpa_program &p, const gpa_blame &b, gpa_advice &ad
   a.tk_chunks = p.tk_chunks;
   a.s_mem = reason_slot(p.arch.blamable, GPA_ST_MEM_DEP);
   a.s_exec = reason_slot(p.arch.blamable, GPA_ST_EXEC_DEP);
+  a.s_sync = reason_slot(p.arch.blamable, GPA_ST_SYNC);
   a.n_edges = p.n_edges;
   a.counts = b.counts.p;
-  a.blamed = b.blamed.p;
-  a.self_ = b.self_.p;
+  a.bl = b.bl.p;
+  a.nocand = b.nocand.p;
   a.share = b.share.p;
   a.op_class = p.op_class.p;
   a.tags = p.instr_tags.p;

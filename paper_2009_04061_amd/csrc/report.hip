@@ -77,7 +77,8 @@ struct HostView {
   uint32_t nbl = 0;
   int s_mem = -1, s_exec = -1, s_sync = -1;
   std::vector<uint32_t> counts, e_src, e_dst, e_dmin, e_dmax, e_icl, instr_scope, root_of, roots;
-  std::vector<double> share, self_;
+  std::vector<double> share;
+  std::vector<uint16_t> nocand;
   std::vector<uint8_t> op_class, tags;
 
   explicit HostView(const gpa_blame &b) : p(b.prog) {
@@ -92,7 +93,7 @@ struct HostView {
     s_sync = slot(GPA_ST_SYNC);
     counts = fetch(b.counts, (size_t)P.n_instr * 24);
     share = fetch(b.share, P.n_edges * nbl * 2);
-    self_ = fetch(b.self_, (size_t)P.n_instr * 24);
+    nocand = fetch(b.nocand, P.n_instr);
     e_src = fetch(P.e_src, P.n_edges);
     e_dst = fetch(P.e_dst, P.n_edges);
     e_dmin = fetch(P.e_dmin, P.n_edges);
@@ -108,6 +109,12 @@ struct HostView {
     return slot < 0 ? 0.0 : share[(e * nbl + (uint32_t)slot) * 2 + l];
   }
   uint32_t C(uint32_t j, int r, int l) const { return counts[(size_t)j * 24 + r * 2 + l]; }
+  // synchronization samples kept on j: all of them when synchronization is
+  // not blamable, else those that found no candidate
+  double kept_sync(uint32_t j, int l) const {
+    const bool kept = s_sync < 0 || ((nocand[j] >> s_sync) & 1u);
+    return kept ? (double)C(j, GPA_ST_SYNC, l) : 0.0;
+  }
 
   std::vector<gpa_hotspot> hotspots(uint32_t root_index, uint32_t opt, uint32_t k) const {
     const uint32_t root = roots[root_index];
@@ -155,7 +162,7 @@ struct HostView {
             for (int r = 1; r < 12; ++r) v += (double)C(j, r, 0) + C(j, r, 1);
           break;
         case GPA_O_WARP_BALANCE:
-          v = self_[(size_t)j * 24 + GPA_ST_SYNC * 2] + self_[(size_t)j * 24 + GPA_ST_SYNC * 2 + 1];
+          v = kept_sync(j, 0) + kept_sync(j, 1);
           break;
         case GPA_O_MEM_TRANSACTION_REDUCTION:
           if (cj == GPA_OP_GLOBAL_LOAD || cj == GPA_OP_GLOBAL_STORE)
