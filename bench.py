@@ -8,9 +8,9 @@ kernel.  Programs are loaded once (the static analysis: reaching
 definitions, edges, distances, target scopes; timed and reported apart), and
 one step is the analysis of every kernel's records:
 
-  batched      gpa_attribute_batch + gpa_advise_batch over all 400 kernels
-               (each stage of the histogram, blamer and estimators one launch
-               for the whole batch);
+  batched      gpa_analyze_batch over all 400 kernels (gpa_attribute_batch and
+               gpa_advise_batch in one call: each stage of the histogram,
+               blamer and estimators one launch for the whole batch);
   per-profile  gpa_attribute + gpa_advise kernel by kernel (host loop).
 
 `value` is records per second of the batched step, records resident in HBM
@@ -195,12 +195,10 @@ def load_programs(gpa, progs, dev, stream):
 
 
 def batched_step(gpa, P, D, stream):
-    B = gpa.attribute_batch(P, D, stream=stream)
-    A = gpa.advise_batch(B, stream=stream)
-    for a in A:
-        a.close()
-    for b in B:
-        b.close()
+    """gpa_analyze_batch (attribute + advise of every profile) with the top-k
+    rows left on the device, then the batch's handles freed."""
+    R = gpa.analyze_batch(P, D, stream=stream)
+    R.close()
 
 
 def per_profile_step(gpa, P, D, stream):

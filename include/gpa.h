@@ -299,6 +299,18 @@ gpa_status gpa_parallel_advise(const gpa_blame *b, uint32_t root_index, const gp
 gpa_status gpa_attribute_batch(gpa_program *const *progs, const gpa_sample *const *samples,
                                const uint64_t *n, uint32_t count, int samples_on_device,
                                void *stream, gpa_blame **out);
+/* gpa_attribute_batch followed by gpa_advise_batch in one call: the
+ * estimators' launches follow the blamer's on the stream without a return
+ * to the host in between, and the call synchronizes once.  blames[k] and
+ * advices[k] are what the two calls would return, bit for bit.  On failure
+ * no handle is returned.
+ * gpa_batch_free frees the handles of a batch (either array may be NULL;
+ * NULL entries are skipped), advice before blame. */
+gpa_status gpa_analyze_batch(gpa_program *const *progs, const gpa_sample *const *samples,
+                             const uint64_t *n, uint32_t count, int samples_on_device, void *stream,
+                             gpa_blame **blames, gpa_advice **advices);
+void gpa_batch_free(gpa_blame *const *blames, gpa_advice *const *advices, uint32_t count);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): what
  * gpa_attribute computes for one profile, written to caller-given device
@@ -319,8 +331,10 @@ gpa_status gpa_attribute_batch(gpa_program *const *progs, const gpa_sample *cons
  * calls that overlap on one GPU (different streams or threads without
  * ordering between them) race; calls on one stream are ordered.
  * GPA_E_UNSUPPORTED, before anything is launched, for programs above 2^17
- * instructions or inputs whose scratch would exceed the fixed size (about
- * 8 bytes per record plus at most 16 MB: some 23M records). */
+ * instructions or inputs whose scratch would exceed the fixed size.  The
+ * scratch of a program of at most 3,072 instructions does not grow with the
+ * records (at most 76 MB); a larger program's takes about 8 bytes per record
+ * plus at most 16 MB (some 23M records). */
 uint64_t gpa_noalloc_scratch_bytes(void);
 gpa_status gpa_attribute_noalloc(const gpa_program *p, const gpa_sample *samples, uint64_t n,
                                  void *stream, uint32_t *counts, uint64_t *totals, double *share,

@@ -318,8 +318,8 @@ static void copy_out(T *host, const DBuf<T> &src, size_t n, hipStream_t s) {
 
 void enqueue_attribute_batch(gpa_program *const *progs, const gpa_sample *const *ds,
                              const uint64_t *n, uint32_t count, hipStream_t s, Arena &ar,
-                             gpa_blame **b, unsigned long long *dtot, bool measure_tuning) {
-  PhaseTimer t_hist, t_blame;
+                             gpa_blame **b, unsigned long long *dtot, bool measure_tuning,
+                             PhaseTimer *t_hist, PhaseTimer *t_blame) {
   std::vector<HistEntry> batched;
   std::vector<uint32_t> single;
   const char *force = getenv("GPA_HIST_PARTITION");
@@ -338,21 +338,13 @@ void enqueue_attribute_batch(gpa_program *const *progs, const gpa_sample *const 
   }
   const uint64_t per = batch_records_per_workgroup(batched.data(), (uint32_t)batched.size(), s, ar,
                                                    measure_tuning);
-  if (measure_tuning) t_hist.begin(kPhaseHist, s);
+  if (t_hist) t_hist->begin(kPhaseHist, s);
   run_hist_batch(batched.data(), (uint32_t)batched.size(), per, s, ar);
   for (uint32_t k : single) run_hist(*progs[k], ds[k], n[k], b[k]->counts.p, dtot + 4 * k, s, ar);
-  if (measure_tuning) {
-    t_hist.end(s);
-    t_blame.begin(kPhaseBlame, s);
-  }
+  if (t_hist) t_hist->end(s);
+  if (t_blame) t_blame->begin(kPhaseBlame, s);
   run_blame_batch(progs, b, count, s, ar, *sh);
-  if (measure_tuning) {
-    t_blame.end(s);
-    // the caller synchronizes before returning: the timers are read then
-    GPA_HIP(hipStreamSynchronize(s));
-    t_hist.collect();
-    t_blame.collect();
-  }
+  if (t_blame) t_blame->end(s);
 }
 
 }  // namespace gpa
@@ -706,12 +698,16 @@ gpa_status gpa_attribute_batch(gpa_program *const *progs, const gpa_sample *cons
       }
     }
     unsigned long long *dtot = ar.get<unsigned long long>((size_t)count * 4);
-    enqueue_attribute_batch(progs, dptr.data(), n, count, s, ar, b.data(), dtot, true);
+    PhaseTimer t_hist, t_blame;
+    enqueue_attribute_batch(progs, dptr.data(), n, count, s, ar, b.data(), dtot, true, &t_hist,
+                            &t_blame);
     std::vector<unsigned long long> tot((size_t)count * 4);
     if (count)
       GPA_HIP(hipMemcpyAsync(tot.data(), dtot, sizeof(unsigned long long) * tot.size(),
                              hipMemcpyDeviceToHost, s));
     GPA_HIP(hipStreamSynchronize(s));
+    t_hist.collect();
+    t_blame.collect();
     for (uint32_t k = 0; k < count; ++k)
       for (int q = 0; q < 4; ++q) b[k]->totals[q] = tot[4 * (size_t)k + q];
   });
@@ -839,6 +835,79 @@ gpa_status gpa_advise_batch(const gpa_blame *const *blames, uint32_t count, void
 }
 
 void gpa_advice_free(gpa_advice *a) { delete a; }
+
+gpa_status gpa_analyze_batch(gpa_program *const *progs, const gpa_sample *const *samples,
+                             const uint64_t *n, uint32_t count, int samples_on_device, void *stream,
+                             gpa_blame **blames, gpa_advice **advices) {
+  if (!blames || !advices || (count && (!progs || !samples || !n))) {
+    set_error("gpa_analyze_batch: NULL argument");
+    return GPA_E_INVALID;
+  }
+  for (uint32_t k = 0; k < count; ++k) {
+    blames[k] = nullptr;
+    advices[k] = nullptr;
+    if (!progs[k] || (n[k] && !samples[k])) {
+      set_error("gpa_analyze_batch: entry %u has a NULL program or sample array", k);
+      return GPA_E_INVALID;
+    }
+    if (n[k] >= 0x40000000ull) {
+      set_error("gpa_analyze_batch: entry %u has 2^30 samples or more", k);
+      return GPA_E_UNSUPPORTED;
+    }
+  }
+  std::vector<gpa_blame *> b(count, nullptr);
+  std::vector<gpa_advice *> a(count, nullptr);
+  hipStream_t s = (hipStream_t)stream;
+  gpa_status st = guarded([&] {
+    Arena ar(s);
+    std::vector<const gpa_sample *> dptr(count, nullptr);
+    for (uint32_t k = 0; k < count; ++k) {
+      dptr[k] = samples[k];
+      if (n[k] && !samples_on_device) {
+        gpa_sample *tmp = ar.get<gpa_sample>(n[k]);
+        GPA_HIP(hipMemcpyAsync(tmp, samples[k], n[k] * sizeof(gpa_sample), hipMemcpyHostToDevice, s));
+        dptr[k] = tmp;
+      }
+    }
+    unsigned long long *dtot = ar.get<unsigned long long>((size_t)count * 4);
+    PhaseTimer t_hist, t_blame, t_adv;
+    enqueue_attribute_batch(progs, dptr.data(), n, count, s, ar, b.data(), dtot, true, &t_hist,
+                            &t_blame);
+    for (uint32_t k = 0; k < count; ++k) a[k] = new gpa_advice(b[k]->prog);
+    t_adv.begin(kPhaseAdvise, s);
+    run_estimate_batch(b.data(), a.data(), count, 16, s, ar);
+    t_adv.end(s);
+    std::vector<unsigned long long> tot((size_t)count * 4);
+    if (count)
+      GPA_HIP(hipMemcpyAsync(tot.data(), dtot, sizeof(unsigned long long) * tot.size(),
+                             hipMemcpyDeviceToHost, s));
+    GPA_HIP(hipStreamSynchronize(s));
+    t_hist.collect();
+    t_blame.collect();
+    t_adv.collect();
+    for (uint32_t k = 0; k < count; ++k)
+      for (int q = 0; q < 4; ++q) b[k]->totals[q] = tot[4 * (size_t)k + q];
+  });
+  if (st != GPA_OK) {
+    if (s) (void)hipStreamSynchronize(s);
+    else (void)hipDeviceSynchronize();
+    for (gpa_advice *x : a) delete x;
+    for (gpa_blame *x : b) delete x;
+    return st;
+  }
+  for (uint32_t k = 0; k < count; ++k) {
+    blames[k] = b[k];
+    advices[k] = a[k];
+  }
+  return GPA_OK;
+}
+
+void gpa_batch_free(gpa_blame *const *blames, gpa_advice *const *advices, uint32_t count) {
+  for (uint32_t k = 0; k < count; ++k) {
+    if (advices) delete advices[k];
+    if (blames) delete blames[k];
+  }
+}
 
 gpa_status gpa_advice_get(const gpa_advice *a, double *active, double *matched, double *speedup,
                           double *kernel_T, double *kernel_L, double *eq3) {

@@ -333,21 +333,24 @@ struct WorkItem {
 
 // The work lists of a batched launch chain, expanded on the device: stage q
 // gives entry e blocks[q][e] workgroups; its items are those of entry 0,
-// then entry 1, and so on.  The host keeps only per-entry counts and their
-// prefix sums; add the stages, place() their tables into the call's one
-// upload, then expand() writes every stage's items in one launch.
+// then entry 1, and so on (or of the entries in a given order).  The host
+// keeps only per-entry counts and their prefix sums (and the order); the
+// tables go into the call's one upload, then expand() writes every stage's
+// items in one launch.
 constexpr uint32_t kMaxStages = 16;
 struct StageTable {
   uint32_t n_stages, count;
   uint32_t pre_off[kMaxStages];          // offset of stage q's prefix sums (count + 1)
+  uint32_t ord_off[kMaxStages];          // offset of its entry order, or ~0u for 0, 1, ...
   uint64_t item_off[kMaxStages + 1];     // offset of stage q's items
 };
 struct BatchPlan {
   std::vector<uint32_t> pre;
   StageTable t{};
   explicit BatchPlan(uint32_t count) { t.count = count; }
-  // a stage; returns its index
-  uint32_t add(const std::vector<uint32_t> &blocks);
+  // a stage (its entries in the given order, a permutation of 0..count-1,
+  // when one is given); returns its index
+  uint32_t add(const std::vector<uint32_t> &blocks, const std::vector<uint32_t> *order = nullptr);
   uint32_t blocks(uint32_t q) const { return (uint32_t)(t.item_off[q + 1] - t.item_off[q]); }
   uint64_t total_items() const { return t.item_off[t.n_stages]; }
   // the device prefix sums and items once placed and expanded
@@ -480,14 +483,17 @@ void launch_blame(const gpa_program &p, const uint32_t *counts, double *share, d
 void expand_blame_tables(const gpa_program &p, const uint32_t *counts, const double *bl,
                          const double *fx, const uint16_t *nocand, double *blamed, double *self_,
                          double *fine, hipStream_t s);
+struct PhaseTimer;
 // The histogram and blame of `count` profiles whose records are on the
 // device at ds[k]: creates b[k] with its tables, totals to dtot[4k..4k+3]
-// (device).  With measure_tuning the autotuner may time candidates, and the
-// call synchronizes s at the end (phase timing); without it nothing
-// synchronizes.
+// (device).  With measure_tuning the autotuner may time candidates (it
+// synchronizes then); otherwise nothing synchronizes.  The phase timers,
+// when given, bracket the histogram and the blame on s (the caller collects
+// them after synchronizing).
 void enqueue_attribute_batch(gpa_program *const *progs, const gpa_sample *const *ds,
                              const uint64_t *n, uint32_t count, hipStream_t s, Arena &ar,
-                             gpa_blame **b, unsigned long long *dtot, bool measure_tuning);
+                             gpa_blame **b, unsigned long long *dtot, bool measure_tuning,
+                             PhaseTimer *t_hist = nullptr, PhaseTimer *t_blame = nullptr);
 
 // device bytes one request of n records against program p takes from
 // admission to completion (staged records when host_records, histogram

@@ -46,7 +46,7 @@ struct EstArgs {
   const uint32_t *big_list, *big_n, *big_chunk;   // 4 groupings x ns
   uint32_t seg_chunks[4];
   const uint32_t *tk_nch, *tk_cst;                // top-k chunks per kernel root
-  double *iv_g, *own, *sub, *ev_icl, *ev_lca;
+  double *own, *sub;
   double *partial[4];
   Cand *cand;
   double *active, *matched, *speedup, *kernel_T, *kernel_L, *eq3;
@@ -64,58 +64,47 @@ struct EstArgs {
   const uint64_t stride_ = BATCH ? count_ : (uint64_t)gridDim.x * blockDim.x;    \
   for (uint64_t VAR = first_; VAR < count_; VAR += stride_)
 
-// per instruction, in line-grouped order: the contributions to the nine
-// optimizers (the two edge optimizers' come from the edges), active and total
-template <bool BATCH>
-__global__ void __launch_bounds__(kEstThreads)
-k_line_contrib(EstArgs one, const EstArgs *__restrict__ many, const WorkItem *__restrict__ items) {
-  EST_ITEM(a.n_instr, kk) {
-    const uint32_t k = a.line_perm[kk];
-    const uint32_t *C = a.counts + (size_t)k * 24;
-    // blamed samples of the three blamable classes and the synchronization
-    // samples kept on k (all of them when synchronization is not blamable,
-    // none when a candidate took them)
-    const double *Bk = a.bl + (size_t)k * a.nbl * 2;
-    const double bm0 = a.s_mem >= 0 ? Bk[a.s_mem * 2] : 0.0;
-    const double bm1 = a.s_mem >= 0 ? Bk[a.s_mem * 2 + 1] : 0.0;
-    const double be0 = a.s_exec >= 0 ? Bk[a.s_exec * 2] : 0.0;
-    const double be1 = a.s_exec >= 0 ? Bk[a.s_exec * 2 + 1] : 0.0;
-    const double bs0 = a.s_sync >= 0 ? Bk[a.s_sync * 2] : 0.0;
-    const double bs1 = a.s_sync >= 0 ? Bk[a.s_sync * 2 + 1] : 0.0;
-    const bool sync_kept = a.s_sync < 0 || ((a.nocand[k] >> a.s_sync) & 1u);
-    const double ks0 = sync_kept ? (double)C[GPA_ST_SYNC * 2] : 0.0;
-    const double ks1 = sync_kept ? (double)C[GPA_ST_SYNC * 2 + 1] : 0.0;
-    double act = 0.0, lat = 0.0, stalls = 0.0;
-    for (int r = 0; r < 12; ++r) {
-      act += (double)C[r * 2];
-      lat += (double)C[r * 2 + 1];
-      if (r != GPA_ST_SELECTED) stalls += (double)C[r * 2] + (double)C[r * 2 + 1];
-    }
-    const uint32_t cls = a.op_class[k];
-    const uint8_t tg = a.tags[k];
-    double v[kNV];
-    v[GPA_O_REGISTER_REUSE] = (cls == GPA_OP_LOCAL_LOAD || cls == GPA_OP_LOCAL_STORE)
-                                  ? bm0 + bm1
-                                  : 0.0;
-    v[GPA_O_STRENGTH_REDUCTION] = (cls == GPA_OP_FP64 || cls == GPA_OP_LONG_ALU)
-                                      ? be0 + be1
-                                      : 0.0;
-    v[GPA_O_FUNCTION_SPLIT] = (double)C[GPA_ST_INST_FETCH * 2] + (double)C[GPA_ST_INST_FETCH * 2 + 1];
-    v[GPA_O_FAST_MATH] = (tg & 1) ? stalls : 0.0;
-    v[GPA_O_WARP_BALANCE] = bs0 + bs1 + ks0 + ks1;
-    v[GPA_O_MEM_TRANSACTION_REDUCTION] =
-        (cls == GPA_OP_GLOBAL_LOAD || cls == GPA_OP_GLOBAL_STORE)
-            ? (double)C[GPA_ST_MEM_THROTTLE * 2] + (double)C[GPA_ST_MEM_THROTTLE * 2 + 1]
-            : 0.0;
-    v[GPA_O_LOOP_UNROLLING] = 0.0;
-    v[GPA_O_CODE_REORDERING] = 0.0;
-    v[GPA_O_FUNCTION_INLINING] = (cls == GPA_OP_CALL || (tg & 2)) ? lat : 0.0;
-    v[9] = act;
-    v[10] = act + lat;
-    double *dst = a.iv_g + kk * kNV;
-#pragma unroll
-    for (int q = 0; q < kNV; ++q) dst[q] = v[q];
+// the contributions of the instruction at position kk of the line-grouped
+// order to the nine optimizers (the two edge optimizers' come from the
+// edges), its active and its total samples
+__device__ __forceinline__ void line_value(const EstArgs &a, uint64_t kk, double (&v)[kNV]) {
+  const uint32_t k = a.line_perm[kk];
+  const uint32_t *C = a.counts + (size_t)k * 24;
+  // blamed samples of the three blamable classes and the synchronization
+  // samples kept on k (all of them when synchronization is not blamable,
+  // none when a candidate took them)
+  const double *Bk = a.bl + (size_t)k * a.nbl * 2;
+  const double bm0 = a.s_mem >= 0 ? Bk[a.s_mem * 2] : 0.0;
+  const double bm1 = a.s_mem >= 0 ? Bk[a.s_mem * 2 + 1] : 0.0;
+  const double be0 = a.s_exec >= 0 ? Bk[a.s_exec * 2] : 0.0;
+  const double be1 = a.s_exec >= 0 ? Bk[a.s_exec * 2 + 1] : 0.0;
+  const double bs0 = a.s_sync >= 0 ? Bk[a.s_sync * 2] : 0.0;
+  const double bs1 = a.s_sync >= 0 ? Bk[a.s_sync * 2 + 1] : 0.0;
+  const bool sync_kept = a.s_sync < 0 || ((a.nocand[k] >> a.s_sync) & 1u);
+  const double ks0 = sync_kept ? (double)C[GPA_ST_SYNC * 2] : 0.0;
+  const double ks1 = sync_kept ? (double)C[GPA_ST_SYNC * 2 + 1] : 0.0;
+  double act = 0.0, lat = 0.0, stalls = 0.0;
+  for (int r = 0; r < 12; ++r) {
+    act += (double)C[r * 2];
+    lat += (double)C[r * 2 + 1];
+    if (r != GPA_ST_SELECTED) stalls += (double)C[r * 2] + (double)C[r * 2 + 1];
   }
+  const uint32_t cls = a.op_class[k];
+  const uint8_t tg = a.tags[k];
+  v[GPA_O_REGISTER_REUSE] = (cls == GPA_OP_LOCAL_LOAD || cls == GPA_OP_LOCAL_STORE) ? bm0 + bm1 : 0.0;
+  v[GPA_O_STRENGTH_REDUCTION] = (cls == GPA_OP_FP64 || cls == GPA_OP_LONG_ALU) ? be0 + be1 : 0.0;
+  v[GPA_O_FUNCTION_SPLIT] = (double)C[GPA_ST_INST_FETCH * 2] + (double)C[GPA_ST_INST_FETCH * 2 + 1];
+  v[GPA_O_FAST_MATH] = (tg & 1) ? stalls : 0.0;
+  v[GPA_O_WARP_BALANCE] = bs0 + bs1 + ks0 + ks1;
+  v[GPA_O_MEM_TRANSACTION_REDUCTION] =
+      (cls == GPA_OP_GLOBAL_LOAD || cls == GPA_OP_GLOBAL_STORE)
+          ? (double)C[GPA_ST_MEM_THROTTLE * 2] + (double)C[GPA_ST_MEM_THROTTLE * 2 + 1]
+          : 0.0;
+  v[GPA_O_LOOP_UNROLLING] = 0.0;
+  v[GPA_O_CODE_REORDERING] = 0.0;
+  v[GPA_O_FUNCTION_INLINING] = (cls == GPA_OP_CALL || (tg & 2)) ? lat : 0.0;
+  v[9] = act;
+  v[10] = act + lat;
 }
 
 // latency samples of global-memory and execution dependency stalls carried
@@ -128,24 +117,13 @@ __device__ __forceinline__ double edge_contrib(const EstArgs &a, uint64_t e) {
   return v;
 }
 
-// the edge contributions straight into the common-loop and common-scope
-// groupings' orders (edges without a common loop are left out of the first:
-// its size is icl_ptr[ns])
-template <bool BATCH>
-__global__ void __launch_bounds__(kEstThreads)
-k_edge_contrib(EstArgs one, const EstArgs *__restrict__ many, const WorkItem *__restrict__ items) {
-  EST_ITEM(a.n_edges, k) {
-    const uint64_t ni = min((uint64_t)a.icl_ptr[a.ns], a.n_edges);
-    a.ev_lca[k] = edge_contrib(a, a.lca_perm[k]);
-    if (k < ni) a.ev_icl[k] = edge_contrib(a, a.icl_perm[k]);
-  }
-}
-
 // Segmented sums over contiguous ranges [begin(l), end(l)) of the four
 // groupings g: 0 instructions by line (W = 11, into own), 1 edges by common
 // loop and 2 edges by common scope (W = 1, into own's Loop Unrolling and
 // Code Reordering columns, after grouping 0), 3 scope subtrees (ranges l to
-// scope_end[l] of own, W = 11, into sub).  A segment of at most kSmallSeg
+// scope_end[l] of own, W = 11, into sub).  The elements of groupings 0-2 are
+// the instructions' and edges' contributions, computed where they are summed
+// (never stored); grouping 3 reads own.  A segment of at most kSmallSeg
 // elements is summed by one thread in element order; the longer ones
 // (listed once at load, with their chunk counts) in chunks of kSegChunk by
 // one workgroup each, every thread owning a fixed stride and the reduction a
@@ -156,7 +134,8 @@ struct SegView {
   const uint32_t *big_list, *big_n;   // the long segments
   const uint32_t *chunk_start;        // their first chunk
   uint32_t n_chunks, out_stride, out_off;
-  const double *data;
+  const uint32_t *perm;               // edge groupings: the edge of each element
+  const double *data;                 // grouping 3: the elements
   double *out, *partial;
 };
 
@@ -169,7 +148,8 @@ __device__ __forceinline__ SegView seg_view(const EstArgs &a) {
   v.big_n = a.big_n + G;
   v.chunk_start = a.big_chunk + (size_t)G * a.ns;
   v.n_chunks = a.seg_chunks[G];
-  v.data = G == 0 ? a.iv_g : G == 1 ? a.ev_icl : G == 2 ? a.ev_lca : a.own;
+  v.perm = G == 1 ? a.icl_perm : G == 2 ? a.lca_perm : nullptr;
+  v.data = G == 3 ? a.own : nullptr;
   v.out = G == 3 ? a.sub : a.own;
   v.out_stride = (G == 1 || G == 2) ? kNV : 1;
   v.out_off = G == 1 ? GPA_O_LOOP_UNROLLING : G == 2 ? GPA_O_CODE_REORDERING : 0;
@@ -194,7 +174,8 @@ __device__ __forceinline__ SegView pick_view(const EstArgs &a) {
     v.n_chunks = y ? a.seg_chunks[2] : a.seg_chunks[1];
     v.out_stride = kNV;
     v.out_off = y ? GPA_O_CODE_REORDERING : GPA_O_LOOP_UNROLLING;
-    v.data = y ? a.ev_lca : a.ev_icl;
+    v.perm = y ? a.lca_perm : a.icl_perm;
+    v.data = nullptr;
     v.out = a.own;
     v.partial = y ? a.partial[2] : a.partial[1];
     return v;
@@ -215,6 +196,22 @@ __device__ __forceinline__ uint32_t seg_hi(const SegView &S, uint32_t l) {
   else return S.ptr[l + 1];
 }
 
+// element i of a grouping
+template <int W, int G0>
+__device__ __forceinline__ void seg_elem(const EstArgs &a, const SegView &S, uint32_t i,
+                                         double (&t)[W]) {
+  if constexpr (G0 == 0) {
+    static_assert(W == kNV, "instruction contributions");
+    line_value(a, i, t);
+  } else if constexpr (G0 == 1 || G0 == 2) {
+    static_assert(W == 1, "edge contributions");
+    t[0] = edge_contrib(a, S.perm[i]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < W; ++q) t[q] = S.data[(size_t)i * W + q];
+  }
+}
+
 template <int W>
 __device__ __forceinline__ void seg_store(const SegView &S, uint32_t l, const double (&v)[W]) {
   double *o = S.out + ((size_t)l * W) * S.out_stride + S.out_off;
@@ -233,9 +230,12 @@ k_seg_small(EstArgs one, const EstArgs *__restrict__ many, const WorkItem *__res
       double v[W];
 #pragma unroll
       for (int q = 0; q < W; ++q) v[q] = 0.0;
-      for (uint32_t i = b0; i < b1; ++i)
+      for (uint32_t i = b0; i < b1; ++i) {
+        double t[W];
+        seg_elem<W, G0>(a, S, i, t);
 #pragma unroll
-        for (int q = 0; q < W; ++q) v[q] += S.data[(size_t)i * W + q];
+        for (int q = 0; q < W; ++q) v[q] += t[q];
+      }
       seg_store<W>(S, l, v);
     }
   }
@@ -259,26 +259,24 @@ k_seg_chunks(EstArgs one, const EstArgs *__restrict__ many, const WorkItem *__re
     const uint32_t l = S.big_list[j];
     const uint32_t a0 = seg_lo<G0>(S, l), b0 = seg_hi<G0>(S, l);
     const uint32_t lo = a0 + (c - S.chunk_start[j]) * kSegChunk, hi = min(lo + kSegChunk, b0);
-    const double *data = S.data;
     double v[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) v[q] = 0.0;
     uint32_t i = lo + threadIdx.x;
     for (; i + 3 * 256 < hi; i += 4 * 256) {
       double t0[W], t1[W], t2[W], t3[W];
-#pragma unroll
-      for (int q = 0; q < W; ++q) {
-        t0[q] = data[(size_t)i * W + q];
-        t1[q] = data[(size_t)(i + 256) * W + q];
-        t2[q] = data[(size_t)(i + 512) * W + q];
-        t3[q] = data[(size_t)(i + 768) * W + q];
-      }
+      seg_elem<W, G0>(a, S, i, t0);
+      seg_elem<W, G0>(a, S, i + 256, t1);
+      seg_elem<W, G0>(a, S, i + 512, t2);
+      seg_elem<W, G0>(a, S, i + 768, t3);
 #pragma unroll
       for (int q = 0; q < W; ++q) v[q] += ((t0[q] + t1[q]) + (t2[q] + t3[q]));
     }
     for (; i < hi; i += 256) {
+      double t[W];
+      seg_elem<W, G0>(a, S, i, t);
 #pragma unroll
-      for (int q = 0; q < W; ++q) v[q] += data[(size_t)i * W + q];
+      for (int q = 0; q < W; ++q) v[q] += t[q];
     }
 #pragma unroll
     for (int q = 0; q < W; ++q) v[q] = wave_sum(v[q]);
@@ -588,11 +586,9 @@ static EstArgs est_args(const gpa_program &p, const gpa_blame &b, gpa_advice &ad
   for (int g = 0; g < 4; ++g) a.seg_chunks[g] = (uint32_t)p.seg_chunks[g];
   a.tk_nch = p.tk_nch.p;
   a.tk_cst = p.tk_cst.p;
-  a.iv_g = ar.get<double>((size_t)n * kNV);
+
   a.own = ar.get<double>((size_t)ns * kNV);
   a.sub = ar.get<double>((size_t)ns * kNV);
-  a.ev_icl = ar.get<double>(p.n_edges);
-  a.ev_lca = ar.get<double>(p.n_edges);
   for (int g = 0; g < 4; ++g)
     a.partial[g] = ar.get<double>((size_t)a.seg_chunks[g] * (g == 0 || g == 3 ? kNV : 1));
   a.cand = ar.get<Cand>((size_t)p.tk_chunks * kTopK);
@@ -641,15 +637,13 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &adv, uin
                   hipStream_t s, Arena &ar) {
   EstLaunch L{s, est_args(p, b, adv, k, ar)};
   const EstArgs &a = L.one;
-  const uint32_t n = p.n_instr, ns = p.n_scopes;
-  const unsigned gi = grid_for(n, kEstThreads, 8192), gs = grid_for(ns, kEstThreads, 8192);
+  const uint32_t ns = p.n_scopes;
+  const unsigned gs = grid_for(ns, kEstThreads, 8192);
   auto chunks = [](uint32_t c) { return (unsigned)std::min<uint32_t>(c, 4096); };
   auto combine = [&](uint32_t c) { return c ? grid_for(c, kEstThreads, 1024) : 0u; };
-  L(k_line_contrib<false>, gi, 1, nullptr);
   L(k_seg_small<kNV, 0, 1, false>, gs, 1, nullptr);
   L(k_seg_chunks<kNV, 0, 1, false>, chunks(a.seg_chunks[0]), 1, nullptr);
   L(k_seg_combine<kNV, 0, 1, false>, combine(a.seg_chunks[0]), 1, nullptr);
-  if (p.n_edges) L(k_edge_contrib<false>, grid_for(p.n_edges, kEstThreads, 8192), 1, nullptr);
   L(k_seg_small<1, 1, 2, false>, gs, 2, nullptr);
   const uint32_t ce = std::max(a.seg_chunks[1], a.seg_chunks[2]);
   L(k_seg_chunks<1, 1, 2, false>, chunks(ce), 2, nullptr);
@@ -671,10 +665,9 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &adv, uin
 void run_estimate_batch(const gpa_blame *const *b, gpa_advice *const *adv, uint32_t count,
                         uint32_t k, hipStream_t s, Arena &ar) {
   std::vector<EstArgs> args(count);
-  // per-entry workgroups of each stage: instructions, scopes, edges, chunks
-  // of each grouping and their long segments, top-k chunks, kernel roots
-  std::vector<uint32_t> w_instr(count), w_scope(count), w_edge(count), w_ch[3], w_cb[3],
-      w_tkc(count), w_tkf(count);
+  // per-entry workgroups of each stage: scopes, chunks of each grouping and
+  // their long segments, top-k chunks, kernel roots
+  std::vector<uint32_t> w_scope(count), w_ch[3], w_cb[3], w_tkc(count), w_tkf(count);
   for (int g = 0; g < 3; ++g) {
     w_ch[g].resize(count);
     w_cb[g].resize(count);
@@ -687,9 +680,7 @@ void run_estimate_batch(const gpa_blame *const *b, gpa_advice *const *adv, uint3
     adv[e]->shared = sh;
     args[e] = est_args(p, *b[e], *adv[e], k, ar, sh.get());
     const EstArgs &a = args[e];
-    w_instr[e] = tiles(p.n_instr, kEstThreads);
     w_scope[e] = tiles(p.n_scopes, kEstThreads);
-    w_edge[e] = tiles(p.n_edges, kEstThreads);
     const uint32_t nc[3] = {a.seg_chunks[0], std::max(a.seg_chunks[1], a.seg_chunks[2]),
                             a.seg_chunks[3]};
     for (int g = 0; g < 3; ++g) {
@@ -700,7 +691,7 @@ void run_estimate_batch(const gpa_blame *const *b, gpa_advice *const *adv, uint3
     w_tkf[e] = (k && p.n_roots) ? p.n_roots : 0u;
   }
   BatchPlan plan(count);
-  const uint32_t q_instr = plan.add(w_instr), q_scope = plan.add(w_scope), q_edge = plan.add(w_edge);
+  const uint32_t q_scope = plan.add(w_scope);
   uint32_t q_ch[3], q_cb[3];
   for (int g = 0; g < 3; ++g) {
     q_ch[g] = plan.add(w_ch[g]);
@@ -715,11 +706,9 @@ void run_estimate_batch(const gpa_blame *const *b, gpa_advice *const *adv, uint3
   plan.expand(s);
   EstLaunch L{s, EstArgs{}, up.ptr<EstArgs>(i_args)};
   auto run = [&](auto kern, uint32_t q, unsigned gy) { L(kern, plan.blocks(q), gy, plan.items(q)); };
-  run(k_line_contrib<true>, q_instr, 1);
   run(k_seg_small<kNV, 0, 1, true>, q_scope, 1);
   run(k_seg_chunks<kNV, 0, 1, true>, q_ch[0], 1);
   run(k_seg_combine<kNV, 0, 1, true>, q_cb[0], 1);
-  run(k_edge_contrib<true>, q_edge, 1);
   run(k_seg_small<1, 1, 2, true>, q_scope, 2);
   run(k_seg_chunks<1, 1, 2, true>, q_ch[1], 2);
   run(k_seg_combine<1, 1, 2, true>, q_cb[1], 2);

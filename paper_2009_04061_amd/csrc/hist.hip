@@ -25,6 +25,7 @@
 // where runs land.  (A last-workgroup-does-the-rest scheme would save the
 // small launches, but the device-scope fence it needs in every workgroup
 // costs far more on this part.)
+#include <algorithm>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -589,6 +590,38 @@ __device__ __forceinline__ uint32_t cold_local_bin(uint32_t key) {
 // LDS words of k_hot_select (dynamic): counters and the table
 constexpr size_t kSelLdsWords = kSelCounters / 2 + kHotT;
 
+// Direct mode: a program of at most kDirectPCs instructions keeps every bin
+// of the pass workgroup in LDS, two 16-bit counters per word (bins 2w and
+// 2w + 1 of word w = pc * 12 + stall), so there is no selection, no lookup
+// and no cold key.  A counter that wraps is caught from the value the LDS
+// atomic returns and logged (kind and word), and the workgroup's totals are
+// rebuilt exactly at the end: with c_lo wraps of the low counter and c_hi of
+// the high one (a carried low wrap adds 1 to the high counter, which can
+// wrap it too), the word's final value W gives
+//   low  = (W & 0xFFFF) + 65536 c_lo,
+//   high = (W >> 16) + 65536 c_hi - c_lo.
+// A wrap takes 65,536 additions to one counter since its last wrap, so a
+// range of at most kDirectMaxPer records logs at most 2 * 64 + 1 events.
+constexpr uint32_t kDirectPCs = 3072;
+constexpr uint32_t kDirectWords = kDirectPCs * 12;
+constexpr uint32_t kDirectMarks = kDirectWords / 32;
+constexpr uint32_t kMaxEvents = 256;
+constexpr uint64_t kDirectMaxPer = 1ull << 22;
+static_assert(2 * (kDirectMaxPer >> 16) + 1 <= kMaxEvents, "event log bound");
+
+// The pass's LDS: one pool laid out per mode.
+//   hot/cold: hot bins, lookup table, the first cold tile, bucket counters,
+//             scan scratch;
+//   direct:   packed counters, wrap marks (one bit per word), the event log,
+//             its count and reduction scratch.
+constexpr uint32_t kHotPoolWords = kHotBins + kHotT + kColdTile + kColdMaxBuckets +
+                                   kHotThreads / kWave + 1;
+constexpr uint32_t kDirectPoolWords = kDirectWords + kDirectMarks + kMaxEvents + 1 +
+                                      2 * (kHotThreads / kWave);
+constexpr uint32_t kPassPoolWords =
+    kHotPoolWords > kDirectPoolWords ? kHotPoolWords : kDirectPoolWords;
+static_assert(kPassPoolWords * 4 + 64 <= 160u * 1024u, "the pass's LDS fits one CU");
+
 // Everything one profile's hot-set histogram needs: its records and sizes,
 // the pass's shape, its scratch and its outputs.  A launch for one profile
 // takes it by value; a batched launch reads one per profile from a device
@@ -599,6 +632,7 @@ struct HotArgs {
   uint64_t n, per, run_stride;
   uint32_t n_instr, n_cb, G, T;
   uint32_t n_merge, merge_slices;   // hot-bin merge workgroups (0 when G = 1) and their slices
+  uint32_t direct, pad;             // direct mode: every bin in LDS, no selection, no cold keys
   uint32_t *hot_tab, *hot_pc, *n_hot, *partial, *cold, *cold_sorted, *tile_off, *n_cold;
   TileTotals *wtot;
   uint32_t *counts;
@@ -756,12 +790,145 @@ __device__ void sort_cold_tile(uint32_t n_cb, uint64_t base, uint32_t m, const u
 // workgroup sorts its cold keys by bucket in tiles of kColdTile: tile t's
 // bucket starts go to tile_off[(w T + t) (n_cb + 1) + b] (entry n_cb: the
 // end).
+// a direct-mode counter wrapped (rare): log it and mark its word.  A low
+// counter's wrap carried 1 into the high counter, which wrapped as well when
+// it held 0xFFFF; entries are word << 1 | (1 for a high-counter wrap).
+__device__ __attribute__((noinline)) void direct_wrap(uint32_t w, uint32_t sh, uint32_t old,
+                                                      uint32_t *mark, uint32_t *evlog,
+                                                      uint32_t *n_ev) {
+  const uint32_t kinds = sh ? 2u : (1u | ((old >> 16) == 0xFFFFu ? 2u : 0u));
+  for (uint32_t k = 1; k <= 2; k <<= 1) {
+    if (!(kinds & k)) continue;
+    const uint32_t i = atomicAdd(n_ev, 1u);
+    if (i < kMaxEvents) evlog[i] = (w << 1) | (k >> 1);
+  }
+  atomicOr(&mark[w >> 5], 1u << (w & 31));
+}
+
+// Direct mode of the pass: records [wg per, min((wg + 1) per, n)) counted in
+// LDS (two 16-bit counters per word), then the workgroup's exact bins and
+// totals written: to the counts when the profile has one workgroup, else to
+// its partial table (n_instr * 24, merged by the finish).
+template <bool VEC>
+__device__ void direct_pass(const HotArgs &a, uint32_t wg, uint32_t *pool) {
+  const uint64_t *__restrict__ rec = a.rec;
+  const uint64_t n = a.n, per = a.per;
+  const uint32_t n_instr = a.n_instr, nw = a.n_instr * 12u;
+  uint32_t *words = pool;
+  uint32_t *mark = pool + kDirectWords;
+  uint32_t *evlog = mark + kDirectMarks;
+  uint32_t *n_ev = evlog + kMaxEvents;
+  uint32_t *red = n_ev + 1;   // [2][kHotThreads / kWave]
+  const unsigned tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
+  const uint64_t r0 = (uint64_t)wg * per, r1 = min(r0 + per, n);
+  const uint64_t rf = r0 + (r1 - r0) / kHotStep * kHotStep;
+  uint64_t va[2 * kHotUnroll], vb[2 * kHotUnroll], vc[2 * kHotUnroll];
+  auto issue = [&](uint64_t i0, uint64_t (&v)[2 * kHotUnroll]) {
+    if (i0 < rf) hot_load<VEC, true>(rec, r1, i0, v);
+  };
+  issue(r0, va);
+  issue(r0 + kHotStep, vb);
+  for (uint32_t k = tid; k < nw; k += kHotThreads) words[k] = 0;
+  for (uint32_t k = tid; k < (nw + 31) / 32; k += kHotThreads) mark[k] = 0;
+  if (tid == 0) *n_ev = 0;
+  lds_barrier();
+  auto step = [&](auto full, uint64_t i0, const uint64_t (&cur)[2 * kHotUnroll]) {
+    constexpr bool FULL = decltype(full)::value;
+#pragma unroll
+    for (int q = 0; q < 2 * kHotUnroll; ++q) {
+      const uint64_t r = cur[q];
+      const uint32_t pc = (uint32_t)r, hi = (uint32_t)(r >> 32);
+      bool ok = pc < n_instr && hi < 0x200u && (hi & 0xFFu) < 12u;   // rec_valid
+      if (!FULL) ok = ok && i0 + 2 * ((uint64_t)(q / 2) * kHotThreads + tid) + (q & 1) < r1;
+      if (ok) {
+        const uint32_t w = (uint32_t)__umul24(pc, 12u) + (hi & 0xFFu);
+        const uint32_t sh = (hi >> 4) & 16u;   // the latency bit selects the high counter
+        const uint32_t old = atomicAdd(&words[w], 1u << sh);
+        if (((old >> sh) & 0xFFFFu) == 0xFFFFu) direct_wrap(w, sh, old, mark, evlog, n_ev);
+      }
+    }
+  };
+  constexpr std::true_type kFull{};
+  constexpr std::false_type kPart{};
+  for (uint64_t i0 = r0; i0 < rf;) {
+    issue(i0 + 2 * kHotStep, vc);
+    step(kFull, i0, va);
+    if ((i0 += kHotStep) >= rf) break;
+    issue(i0 + 2 * kHotStep, va);
+    step(kFull, i0, vb);
+    if ((i0 += kHotStep) >= rf) break;
+    issue(i0 + 2 * kHotStep, vb);
+    step(kFull, i0, vc);
+    i0 += kHotStep;
+  }
+  if (rf < r1) {
+    hot_load<VEC, false>(rec, r1, rf, va);
+    step(kPart, rf, va);
+  }
+  __syncthreads();
+  const uint32_t nev = min(*n_ev, kMaxEvents);
+  uint32_t *dst = a.G == 1 ? a.counts : a.partial + (size_t)wg * n_instr * 24u;
+  uint32_t valid = 0, lat = 0;
+  for (uint32_t w = tid; w < nw; w += kHotThreads) {
+    const uint32_t W = words[w];
+    uint32_t lo = W & 0xFFFFu, hi = W >> 16;
+    if (nev && ((mark[w >> 5] >> (w & 31)) & 1u)) {
+      uint32_t c_lo = 0, c_hi = 0;
+      for (uint32_t e = 0; e < nev; ++e) {
+        const uint32_t v = evlog[e];
+        if ((v >> 1) == w) {
+          c_hi += v & 1u;
+          c_lo += (v & 1u) ^ 1u;
+        }
+      }
+      lo += c_lo << 16;
+      hi = hi + (c_hi << 16) - c_lo;
+    }
+    valid += lo + hi;
+    lat += hi;
+    *(uint2 *)(dst + 2 * (size_t)w) = make_uint2(lo, hi);
+  }
+  valid = wave_sum(valid);
+  lat = wave_sum(lat);
+  if (lane == 0) {
+    red[wv] = valid;
+    red[kHotThreads / kWave + wv] = lat;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t v = 0, l = 0;
+    for (uint32_t k = 0; k < kHotThreads / kWave; ++k) {
+      v += red[k];
+      l += red[kHotThreads / kWave + k];
+    }
+    const uint32_t dropped = (uint32_t)(r1 - r0) - v;
+    if (a.G == 1) {
+      a.totals[0] = v;
+      a.totals[1] = l;
+      a.totals[2] = dropped;
+      a.totals[3] = 0;
+    } else {
+      TileTotals t;
+      t.valid = v;
+      t.latency = l;
+      t.dropped = dropped;
+      t.pad = 0;
+      a.wtot[wg] = t;
+    }
+  }
+}
+
 template <bool VEC, bool BATCH>
 __global__ void __launch_bounds__(kHotThreads)
 k_hot_pass(HotArgs one, const HotArgs *__restrict__ many, const WorkItem *__restrict__ items) {
   HotArgs a;
   uint32_t wg;
   hot_item<BATCH>(one, many, items, a, wg);
+  __shared__ __align__(16) uint32_t pool[kPassPoolWords];
+  if (a.direct) {
+    direct_pass<VEC>(a, wg, pool);
+    return;
+  }
   const uint64_t *__restrict__ rec = a.rec;
   const uint64_t n = a.n, per = a.per;
   const uint32_t n_instr = a.n_instr, n_cb = a.n_cb, T = a.T;
@@ -771,11 +938,11 @@ k_hot_pass(HotArgs one, const HotArgs *__restrict__ many, const WorkItem *__rest
   uint32_t *__restrict__ tile_off = a.tile_off;
   uint32_t *__restrict__ n_cold = a.n_cold;
   TileTotals *__restrict__ wtot = a.wtot;
-  __shared__ uint32_t bins[kHotBins];
-  __shared__ uint32_t tab[kHotT];
-  __shared__ uint32_t sorted[kColdTile];
-  __shared__ uint32_t bc[kColdMaxBuckets];
-  __shared__ uint32_t scan_tmp[kHotThreads / kWave + 1];
+  uint32_t *bins = pool;                      // [kHotBins]
+  uint32_t *tab = bins + kHotBins;            // [kHotT]
+  uint32_t *sorted = tab + kHotT;             // [kColdTile]
+  uint32_t *bc = sorted + kColdTile;          // [kColdMaxBuckets]
+  uint32_t *scan_tmp = bc + kColdMaxBuckets;  // [kHotThreads / kWave + 1]
   __shared__ uint32_t s_cur, s_valid, s_lat;
   const unsigned tid = threadIdx.x, lane = lane_id();
   const uint64_t r0 = (uint64_t)wg * per, r1 = min(r0 + per, n);
@@ -992,22 +1159,24 @@ k_hot_finish(HotArgs one, const HotArgs *__restrict__ many, const WorkItem *__re
       if (!((hot_mark[pl / 32] >> (pl % 32)) & 1u)) counts[(size_t)pc0 * 24u + k] = bins[k];
     }
   } else if (bid < n_cb + n_merge) {
-    // kHotThreads / S hot-bin columns; the pass's workgroups split over S
-    // slices (S a power of two, at most 16, so a thread sums at most
-    // kHotGrid / 16 partials)
+    // kHotThreads / S columns of the partial tables (hot bins, or in direct
+    // mode every bin); the pass's workgroups split over S slices (S a power
+    // of two, at most 16, so a thread sums at most kHotGrid / 16 partials)
+    const bool direct = a.direct != 0;
     const uint32_t S = a.merge_slices, cols = kHotThreads / S;
     const uint32_t c = tid % cols, sl = tid / cols;
     const uint32_t col = (bid - n_cb) * cols + c;
-    const bool live = col < n_hot * 24u;
+    const uint32_t width = direct ? n_instr * 24u : kHotBins;
+    const bool live = col < (direct ? n_instr : n_hot) * 24u;
     uint32_t sum = 0;
 #pragma unroll 4
-    for (uint32_t w = sl; w < G; w += S) sum += live ? partial[(size_t)w * kHotBins + col] : 0u;
+    for (uint32_t w = sl; w < G; w += S) sum += live ? partial[(size_t)w * width + col] : 0u;
     bins[sl * cols + c] = sum;
     __syncthreads();
     if (sl == 0 && live) {
       uint32_t t = 0;
       for (uint32_t k = 0; k < S; ++k) t += bins[k * cols + c];
-      counts[(size_t)hot_pc[col / 24u] * 24u + col % 24u] = t;
+      counts[direct ? (size_t)col : (size_t)hot_pc[col / 24u] * 24u + col % 24u] = t;
     }
   } else {
     unsigned long long v = 0, l = 0, d = 0;
@@ -1038,51 +1207,95 @@ k_hot_finish(HotArgs one, const HotArgs *__restrict__ many, const WorkItem *__re
 // The hot-set path, for programs of at most kHotMaxPCs instructions.
 uint32_t hist_hot_max_pcs() { return kHotMaxPCs; }
 
-// the pass's workgroup ranges: kHotGrid at most, each a multiple of 128
-// records (even, so the 16-byte loads stay aligned; finer than a whole step,
-// so that the grid comes as close to kHotGrid as it can, a range's last step
-// being partial where it must); per_min, when given, is the least range
+// Direct mode for programs of at most kDirectPCs instructions, unless the
+// environment sets GPA_HIST_HOTSET=1 (the hot/cold path for every program;
+// the counts are the same).
+static bool hot_direct(uint32_t n_instr) {
+  if (n_instr > kDirectPCs) return false;
+  const char *f = getenv("GPA_HIST_HOTSET");
+  return !(f && f[0] == '1');
+}
+
+// The pass's workgroup ranges, each a multiple of 128 records (even, so the
+// 16-byte loads stay aligned; finer than a whole step, so that the grid
+// comes as close to its target as it can, a range's last step being partial
+// where it must).
+//   hot/cold: kHotGrid ranges at most; per_min, when given, is the least
+//             range;
+//   direct:   ranges of at least 96 (batched: 480) records per instruction,
+//             so that the partial tables (96 bytes per instruction and
+//             range) stay under a quarter (a twentieth) of the records'
+//             bytes, and at most kDirectMaxPer records.
 struct HotShape {
   uint64_t per, run_stride;
   uint32_t G, T, n_cb, n_merge, merge_slices;
+  bool direct;
 };
 static HotShape hot_shape(uint32_t n_instr, uint64_t n, uint64_t per_min = 0) {
   HotShape h;
-  h.n_cb = (n_instr + kColdPCs - 1) / kColdPCs;
+  h.direct = hot_direct(n_instr);
   uint64_t per = std::max<uint64_t>((n + kHotGrid - 1) / kHotGrid, per_min);
+  if (h.direct) {
+    per = std::max<uint64_t>(per, (per_min ? 480ull : 96ull) * n_instr);
+    per = std::min<uint64_t>(per, kDirectMaxPer);
+  }
   h.per = (per + 2 * kWave - 1) / (2 * kWave) * (2 * kWave);
   if (h.per == 0) h.per = 2 * kWave;
   h.G = (uint32_t)((n + h.per - 1) / h.per);
-  h.T = (uint32_t)((h.per + kColdTile - 1) / kColdTile);   // tiles per workgroup
+  h.n_cb = h.direct ? 0u : (n_instr + kColdPCs - 1) / kColdPCs;
+  h.T = h.direct ? 0u : (uint32_t)((h.per + kColdTile - 1) / kColdTile);   // tiles per workgroup
   h.run_stride = n > kSelSample ? (n - kSelRun) / (kSelSample / kSelRun - 1) : 0;
   // merge: S slices of the G partials, kHotThreads / S columns per workgroup
   uint32_t S = 1;
   while (S < h.G && S < 16) S <<= 1;
   h.merge_slices = S;
   const uint32_t cols = kHotThreads / S;
-  const uint32_t live_cols = std::min<uint32_t>(kHotH, n_instr) * 24u;
+  const uint32_t live_cols = (h.direct ? n_instr : std::min<uint32_t>(kHotH, n_instr)) * 24u;
   h.n_merge = h.G > 1 ? (live_cols + cols - 1) / cols : 0;
   return h;
 }
 
 static size_t blk256(size_t bytes) { return (bytes + 255) / 256 * 256; }
 
-static size_t hot_scratch(const HotShape &h, uint64_t n) {
-  return blk256(4 * kHotT) + blk256(4 * kHotH) + blk256(4) +
-         blk256(h.G > 1 ? 4 * (size_t)h.G * kHotBins : 4) + 2 * blk256(4 * n) +
-         blk256(4 * (size_t)h.G * h.T * (h.n_cb + 1)) + blk256(4 * (size_t)h.G) +
-         blk256(sizeof(TileTotals) * (size_t)h.G);
+// element counts of a profile's scratch pieces, in the order hot_args takes
+// them: lookup table, hot PCs, hot count, partial tables, cold keys, sorted
+// cold keys, tile offsets, cold counts (u32 each), then the range totals
+struct HotPieces {
+  size_t u32[8];
+  size_t totals;
+};
+static HotPieces hot_pieces(const HotShape &h, uint32_t n_instr, uint64_t n) {
+  HotPieces q;
+  const bool d = h.direct;
+  q.u32[0] = d ? 1 : kHotT;
+  q.u32[1] = d ? 1 : kHotH;
+  q.u32[2] = 1;
+  q.u32[3] = h.G > 1 ? (size_t)h.G * (d ? (size_t)n_instr * 24 : kHotBins) : 1;
+  q.u32[4] = d ? 1 : n;
+  q.u32[5] = d ? 1 : n;
+  q.u32[6] = d ? 1 : (size_t)h.G * h.T * (h.n_cb + 1);
+  q.u32[7] = h.G;
+  q.totals = h.G;
+  return q;
+}
+
+static size_t hot_scratch(const HotShape &h, uint32_t n_instr, uint64_t n) {
+  const HotPieces q = hot_pieces(h, n_instr, n);
+  size_t b = 0;
+  for (size_t c : q.u32) b += blk256(4 * (c ? c : 1));
+  return b + blk256(sizeof(TileTotals) * (q.totals ? q.totals : 1));
 }
 
 size_t hist_hot_scratch_bytes(uint32_t n_instr, uint64_t n) {
   if (n == 0) return 0;
-  return hot_scratch(hot_shape(n_instr, n), n);
+  return hot_scratch(hot_shape(n_instr, n), n_instr, n);
 }
 
 // one profile's arguments, its scratch taken from the arena (in the order
 // hot_scratch counts it)
 static HotArgs hot_args(const HotShape &h, const uint64_t *rec, uint64_t n, uint32_t n_instr,
                         uint32_t *counts, unsigned long long *totals, Arena &ar) {
+  const HotPieces q = hot_pieces(h, n_instr, n);
   HotArgs a;
   a.rec = rec;
   a.n = n;
@@ -1094,18 +1307,29 @@ static HotArgs hot_args(const HotShape &h, const uint64_t *rec, uint64_t n, uint
   a.T = h.T;
   a.n_merge = h.n_merge;
   a.merge_slices = h.merge_slices;
-  a.hot_tab = ar.get<uint32_t>(kHotT);
-  a.hot_pc = ar.get<uint32_t>(kHotH);
-  a.n_hot = ar.get<uint32_t>(1);
-  a.partial = ar.get<uint32_t>(h.G > 1 ? (size_t)h.G * kHotBins : 1);
-  a.cold = ar.get<uint32_t>(n);
-  a.cold_sorted = ar.get<uint32_t>(n);
-  a.tile_off = ar.get<uint32_t>((size_t)h.G * h.T * (h.n_cb + 1));
-  a.n_cold = ar.get<uint32_t>(h.G);
-  a.wtot = ar.get<TileTotals>(h.G);
+  a.direct = h.direct ? 1u : 0u;
+  a.pad = 0;
+  a.hot_tab = ar.get<uint32_t>(q.u32[0]);
+  a.hot_pc = ar.get<uint32_t>(q.u32[1]);
+  a.n_hot = ar.get<uint32_t>(q.u32[2]);
+  a.partial = ar.get<uint32_t>(q.u32[3]);
+  a.cold = ar.get<uint32_t>(q.u32[4]);
+  a.cold_sorted = ar.get<uint32_t>(q.u32[5]);
+  a.tile_off = ar.get<uint32_t>(q.u32[6]);
+  a.n_cold = ar.get<uint32_t>(q.u32[7]);
+  a.wtot = ar.get<TileTotals>(q.totals);
   a.counts = counts;
   a.totals = totals;
   return a;
+}
+
+// workgroups of the three launches for one profile: selection (hot/cold
+// only), pass ranges, finish (cold buckets, merges and the totals; nothing
+// in direct mode when one range wrote the counts and totals itself)
+static void hot_blocks(const HotShape &h, uint32_t &n_sel, uint32_t &n_pass, uint32_t &n_fin) {
+  n_sel = h.direct ? 0u : 1u;
+  n_pass = h.G;
+  n_fin = (h.direct && h.G == 1) ? 0u : h.n_cb + h.n_merge + 1;
 }
 
 static void set_select_lds() {
@@ -1125,20 +1349,26 @@ static bool run_hist_hot(const gpa_program &p, const uint64_t *rec, uint64_t n, 
   if (allow_partition && force && force[0] == '1') return false;
   const HotShape hs = hot_shape(n_instr, n);
   const HotArgs a = hot_args(hs, rec, n, n_instr, counts, totals, ar);
-  set_select_lds();
-  hipLaunchKernelGGL(k_hot_select<false>, dim3(1), dim3(kHotThreads), kSelLdsWords * 4, s, a,
-                     nullptr, nullptr);
-  GPA_LAUNCH_CHECK();
+  uint32_t n_sel, n_pass, n_fin;
+  hot_blocks(hs, n_sel, n_pass, n_fin);
+  if (n_sel) {
+    set_select_lds();
+    hipLaunchKernelGGL(k_hot_select<false>, dim3(n_sel), dim3(kHotThreads), kSelLdsWords * 4, s, a,
+                       nullptr, nullptr);
+    GPA_LAUNCH_CHECK();
+  }
   if (vec)
-    hipLaunchKernelGGL((k_hot_pass<true, false>), dim3(hs.G), dim3(kHotThreads), 0, s, a, nullptr,
-                       nullptr);
+    hipLaunchKernelGGL((k_hot_pass<true, false>), dim3(n_pass), dim3(kHotThreads), 0, s, a,
+                       nullptr, nullptr);
   else
-    hipLaunchKernelGGL((k_hot_pass<false, false>), dim3(hs.G), dim3(kHotThreads), 0, s, a,
+    hipLaunchKernelGGL((k_hot_pass<false, false>), dim3(n_pass), dim3(kHotThreads), 0, s, a,
                        nullptr, nullptr);
   GPA_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_hot_finish<false>, dim3(hs.n_cb + hs.n_merge + 1), dim3(kHotThreads), 0, s,
-                     a, nullptr, nullptr);
-  GPA_LAUNCH_CHECK();
+  if (n_fin) {
+    hipLaunchKernelGGL(k_hot_finish<false>, dim3(n_fin), dim3(kHotThreads), 0, s, a, nullptr,
+                       nullptr);
+    GPA_LAUNCH_CHECK();
+  }
   return true;
 }
 
@@ -1154,7 +1384,8 @@ struct HistBatch {
 static void prepare_hist_batch(HistBatch &hb, const HistEntry *e, uint32_t count, uint64_t per,
                                hipStream_t s, Arena &ar) {
   std::vector<HotArgs> args(count);
-  std::vector<uint32_t> n_sel(count, 1u), n_pass(count), n_fin(count);
+  std::vector<uint32_t> n_sel(count), n_pass(count), n_fin(count);
+  std::vector<uint64_t> range(count);
   for (uint32_t k = 0; k < count; ++k) {
     if (e[k].n == 0 || e[k].n_instr > kHotMaxPCs || ((uintptr_t)e[k].samples % 16) != 0)
       fail(GPA_E_INVALID, "batched histogram entry %u: n > 0, at most %u instructions and "
@@ -1162,11 +1393,17 @@ static void prepare_hist_batch(HistBatch &hb, const HistEntry *e, uint32_t count
     const HotShape h = hot_shape(e[k].n_instr, e[k].n, per);
     args[k] = hot_args(h, (const uint64_t *)e[k].samples, e[k].n, e[k].n_instr, e[k].counts,
                        e[k].totals, ar);
-    n_pass[k] = h.G;
-    n_fin[k] = h.n_cb + h.n_merge + 1;
+    hot_blocks(h, n_sel[k], n_pass[k], n_fin[k]);
+    range[k] = std::min<uint64_t>(h.per, e[k].n);
   }
+  // the pass's workgroups longest range first (direct ranges can be several
+  // times the others), so that the long ones do not start last
+  std::vector<uint32_t> order(count);
+  for (uint32_t k = 0; k < count; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](uint32_t x, uint32_t y) { return range[x] > range[y]; });
   hb.q_sel = hb.plan.add(n_sel);
-  hb.q_pass = hb.plan.add(n_pass);
+  hb.q_pass = hb.plan.add(n_pass, &order);
   hb.q_fin = hb.plan.add(n_fin);
   Upload up;
   const size_t i_args = up.add(args), i_pre = up.add(hb.plan.pre);
@@ -1179,16 +1416,20 @@ static void prepare_hist_batch(HistBatch &hb, const HistEntry *e, uint32_t count
 
 static void launch_hist_batch(const HistBatch &hb, hipStream_t s) {
   HotArgs none{};
-  set_select_lds();
-  hipLaunchKernelGGL(k_hot_select<true>, dim3(hb.plan.blocks(hb.q_sel)), dim3(kHotThreads),
-                     kSelLdsWords * 4, s, none, hb.d_args, hb.plan.items(hb.q_sel));
-  GPA_LAUNCH_CHECK();
+  if (hb.plan.blocks(hb.q_sel)) {
+    set_select_lds();
+    hipLaunchKernelGGL(k_hot_select<true>, dim3(hb.plan.blocks(hb.q_sel)), dim3(kHotThreads),
+                       kSelLdsWords * 4, s, none, hb.d_args, hb.plan.items(hb.q_sel));
+    GPA_LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL((k_hot_pass<true, true>), dim3(hb.plan.blocks(hb.q_pass)), dim3(kHotThreads),
                      0, s, none, hb.d_args, hb.plan.items(hb.q_pass));
   GPA_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_hot_finish<true>, dim3(hb.plan.blocks(hb.q_fin)), dim3(kHotThreads), 0, s,
-                     none, hb.d_args, hb.plan.items(hb.q_fin));
-  GPA_LAUNCH_CHECK();
+  if (hb.plan.blocks(hb.q_fin)) {
+    hipLaunchKernelGGL(k_hot_finish<true>, dim3(hb.plan.blocks(hb.q_fin)), dim3(kHotThreads), 0, s,
+                       none, hb.d_args, hb.plan.items(hb.q_fin));
+    GPA_LAUNCH_CHECK();
+  }
 }
 
 void run_hist_batch(const HistEntry *e, uint32_t count, uint64_t per, hipStream_t s, Arena &ar) {

@@ -5,25 +5,34 @@
 
 namespace gpa {
 
-uint32_t BatchPlan::add(const std::vector<uint32_t> &blocks) {
+uint32_t BatchPlan::add(const std::vector<uint32_t> &blocks, const std::vector<uint32_t> *order) {
   if (t.n_stages >= kMaxStages) fail(GPA_E_DEVICE, "too many stages in one batched launch chain");
-  if (blocks.size() != t.count) fail(GPA_E_DEVICE, "stage with a wrong number of entries");
+  if (blocks.size() != t.count || (order && order->size() != t.count))
+    fail(GPA_E_DEVICE, "stage with a wrong number of entries");
   const uint32_t q = t.n_stages++;
   t.pre_off[q] = (uint32_t)pre.size();
   uint64_t run = 0;
   pre.push_back(0);
-  for (uint32_t b : blocks) {
-    run += b;
+  for (uint32_t k = 0; k < t.count; ++k) {
+    const uint32_t e = order ? (*order)[k] : k;
+    if (e >= t.count) fail(GPA_E_DEVICE, "stage order out of range");
+    run += blocks[e];
     if (run >= (1ull << 31)) fail(GPA_E_UNSUPPORTED, "a batched launch of 2^31 workgroups or more");
     pre.push_back((uint32_t)run);
+  }
+  t.ord_off[q] = ~0u;
+  if (order) {
+    t.ord_off[q] = (uint32_t)pre.size();
+    pre.insert(pre.end(), order->begin(), order->end());
   }
   t.item_off[q + 1] = t.item_off[q] + run;
   return q;
 }
 
 // item i of the concatenated stages: its stage (a short scan of the table),
-// then the entry e with pre[e] <= i' < pre[e + 1] by bisection (entries
-// without blocks have pre[e] == pre[e + 1] and are never chosen)
+// then the position p with pre[p] <= i' < pre[p + 1] by bisection (positions
+// without blocks have pre[p] == pre[p + 1] and are never chosen), and the
+// entry at that position of the stage's order
 __global__ void __launch_bounds__(256) k_expand_items(const uint32_t *__restrict__ pre, StageTable t,
                                                       WorkItem *__restrict__ items) {
   const uint64_t total = t.item_off[t.n_stages];
@@ -39,7 +48,8 @@ __global__ void __launch_bounds__(256) k_expand_items(const uint32_t *__restrict
       if (P[mid] <= li) lo = mid;
       else hi = mid;
     }
-    items[i] = WorkItem{lo, li - P[lo]};
+    const uint32_t e = t.ord_off[q] == ~0u ? lo : pre[t.ord_off[q] + lo];
+    items[i] = WorkItem{e, li - P[lo]};
   }
 }
 

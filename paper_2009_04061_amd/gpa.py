@@ -94,7 +94,8 @@ EXPORTS = ["gpa_load_program", "gpa_program_free", "gpa_program_get_info", "gpa_
            "gpa_advise_batch", "gpa_pool_stats", "gpa_pool_trim", "gpa_server_create",
            "gpa_server_submit", "gpa_server_poll", "gpa_server_stats_get", "gpa_server_free",
            "gpa_parallel_advise", "gpa_program_coverage", "gpa_blame_hotspots", "gpa_report",
-           "gpa_attribute_noalloc", "gpa_noalloc_scratch_bytes"]
+           "gpa_attribute_noalloc", "gpa_noalloc_scratch_bytes", "gpa_analyze_batch",
+           "gpa_batch_free"]
 PHASES = ["hist", "blame", "load", "advise", "rd_edges", "dist", "dfs", "rd_search",
           "validate", "sites", "edges", "targets", "dist_long"]
 
@@ -154,6 +155,10 @@ def lib():
         L.gpa_attribute_batch.restype = ct.c_int32
         L.gpa_advise_batch.argtypes = [vp, u32, vp, vp]
         L.gpa_advise_batch.restype = ct.c_int32
+        L.gpa_analyze_batch.argtypes = [vp, vp, vp, u32, i32, vp, vp, vp]
+        L.gpa_analyze_batch.restype = ct.c_int32
+        L.gpa_batch_free.argtypes = [vp, vp, u32]
+        L.gpa_batch_free.restype = None
         L.gpa_parallel_advise.argtypes = [vp, u32, ct.POINTER(Launch), ct.POINTER(Device),
                                           ct.POINTER(ParallelEstimate)]
         L.gpa_parallel_advise.restype = ct.c_int32
@@ -387,6 +392,64 @@ def attribute_batch(programs, samples, stream=None):
     return [Blame(programs[k], ct.c_void_p(out[k])) for k in range(count)]
 
 
+class BatchResult:
+    """The handles of gpa_analyze_batch: blames[k] and advices[k] (Blame and
+    Advice objects, made on first access, that do not free themselves);
+    close() frees them all with gpa_batch_free."""
+
+    def __init__(self, programs, bh, ah, count):
+        self._programs, self._bh, self._ah, self._count = programs, bh, ah, count
+        self._blames = self._advices = None
+
+    @property
+    def blames(self):
+        if self._blames is None:
+            self._blames = [Blame(self._programs[k], ct.c_void_p(self._bh[k]), owned=False)
+                            for k in range(self._count)]
+        return self._blames
+
+    @property
+    def advices(self):
+        if self._advices is None:
+            B = self.blames
+            self._advices = [Advice(B[k], ct.c_void_p(self._ah[k]), owned=False)
+                             for k in range(self._count)]
+        return self._advices
+
+    def close(self):
+        if self._count is not None:
+            lib().gpa_batch_free(self._bh, self._ah, self._count)
+            for x in (self._blames or []) + (self._advices or []):
+                x.handle = None
+            self._count = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def analyze_batch(programs, samples, stream=None) -> BatchResult:
+    """gpa_analyze_batch: attribute and advise every (programs[k],
+    samples[k]) in one call; samples all host (numpy) or all device arrays."""
+    count = len(programs)
+    if len(samples) != count:
+        raise ValueError("one sample array per program")
+    recs = [_records(x) for x in samples]
+    on_dev = {r[2] for r in recs}
+    if len(on_dev) > 1:
+        raise ValueError("sample arrays must all be host or all be device arrays")
+    progs = (ct.c_void_p * max(count, 1))(*[p.handle for p in programs])
+    ptrs = (ct.c_void_p * max(count, 1))(*[r[0] if r[1] else None for r in recs])
+    ns = (ct.c_uint64 * max(count, 1))(*[r[1] for r in recs])
+    bh = (ct.c_void_p * max(count, 1))()
+    ah = (ct.c_void_p * max(count, 1))()
+    _check(lib().gpa_analyze_batch(progs, ptrs, ns, count, on_dev.pop() if count else 1,
+                                   _stream(stream), bh, ah))
+    return BatchResult(programs, bh, ah, count)
+
+
 def advise_batch(blames, stream=None):
     """gpa_advise_batch over the blame handles."""
     count = len(blames)
@@ -397,13 +460,15 @@ def advise_batch(blames, stream=None):
 
 
 class Blame:
-    def __init__(self, prog: Program, handle):
+    def __init__(self, prog: Program, handle, owned: bool = True):
         self.prog = prog
         self.handle = handle
+        self.owned = owned   # False: freed with its batch (BatchResult.close)
 
     def close(self):
         if getattr(self, "handle", None):
-            lib().gpa_blame_free(self.handle)
+            if self.owned:
+                lib().gpa_blame_free(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -458,13 +523,15 @@ class Blame:
 
 
 class Advice:
-    def __init__(self, blame: Blame, handle):
+    def __init__(self, blame: Blame, handle, owned: bool = True):
         self.blame = blame
         self.handle = handle
+        self.owned = owned   # False: freed with its batch (BatchResult.close)
 
     def close(self):
         if getattr(self, "handle", None):
-            lib().gpa_advice_free(self.handle)
+            if self.owned:
+                lib().gpa_advice_free(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -140,3 +140,33 @@ def test_config3_full_batch_equals_per_profile():
           f"instructions, {int(off[-1])} records", flush=True)
     most = {int(np.argmax(np.diff(off)))}
     assert _run_both(progs, recs, oracle_every=40, oracle_set=most) >= 10
+
+
+def test_analyze_batch_equals_attribute_then_advise_batch():
+    """gpa_analyze_batch (one call, no return to the host between the blamer
+    and the estimators) against gpa_attribute_batch + gpa_advise_batch: bit
+    for bit, on a mixed batch with an empty and an unaligned entry."""
+    import torch
+    from paper_2009_04061_amd import gpa
+    progs, recs = [], []
+    for seed in range(5):
+        prog, rec = S.workload_small(seed=500 + seed, n_samples=[0, 3, 40_000, 250_000, 900_001][seed])
+        progs.append(prog)
+        recs.append(rec)
+    P = [gpa.Program(gpa.program_to_device(p)) for p in progs]
+    D = [_device_records(torch, r) for r in recs]
+    raw = np.ascontiguousarray(recs[3]).view(np.uint8)
+    big = torch.zeros(raw.size + 8, dtype=torch.uint8, device="cuda")
+    big[8:] = torch.from_numpy(raw.copy()).cuda()
+    D[3] = big[8:]
+    R = gpa.analyze_batch(P, D)
+    Bb = gpa.attribute_batch(P, D)
+    Ab = gpa.advise_batch(Bb)
+    for i in range(len(P)):
+        _bitwise_equal(_outputs(P[i], R.blames[i], R.advices[i]), _outputs(P[i], Bb[i], Ab[i]),
+                       f"profile {i}")
+        Ab[i].close()
+        Bb[i].close()
+    R.close()
+    for p in P:
+        p.close()

@@ -305,6 +305,67 @@ def test_histogram_bucket_outgrows_its_estimate(monkeypatch):
     _both(prog, rec)
 
 
+def _one_bin(n, pc, stall, lam):
+    rec = np.zeros(n, S.SAMPLE_DTYPE)
+    rec["pc"] = pc
+    rec["stall"] = stall
+    rec["flags"] = lam
+    return rec
+
+
+def test_direct_histogram_counter_wraps():
+    """The direct mode (every bin of a program of at most 3,072 instructions
+    in LDS, two 16-bit counters per word): one bin taking far more than
+    2^16 records per workgroup range, in both counters of a word, and the
+    double wrap (the low counter wraps into a high counter that holds
+    0xFFFF); exact against the oracle's counts."""
+    from paper_2009_04061_amd import gpa
+    prog, _ = S.workload_small(seed=7, n_samples=10)
+    P = gpa.Program(gpa.program_to_device(prog))
+    rng = np.random.default_rng(7)
+    mem = S.STALL_NAMES.index("MEM_DEP")
+    # 700k low-counter and 450k high-counter records of one word, shuffled,
+    # with a light background
+    rec = np.concatenate([_one_bin(700_000, 5, mem, 0), _one_bin(450_000, 5, mem, 1),
+                          S.gen_samples(50_000, len(prog["op_class"]), 1.1, S.stall_mix_small(),
+                                        seed=7)])
+    rec = rec[rng.permutation(len(rec))]
+    print("  one word, both counters", flush=True)
+    _hist_only(P, prog, rec)
+    # 65,535 high-counter records, then 65,536 low ones: the last low record
+    # wraps both counters of the word (one range: 131,071 records)
+    dbl = np.concatenate([_one_bin(65_535, 9, mem, 1), _one_bin(65_536, 9, mem, 0)])
+    print("  double wrap", flush=True)
+    _hist_only(P, prog, dbl)
+    _hist_only(P, prog, dbl[::-1].copy())
+    # the same through the batched path, in one batch with an ordinary profile
+    B = gpa.attribute_batch([P, P], [_dev(rec), _dev(dbl)])
+    for b, r in zip(B, (rec, dbl)):
+        C, tot = b.counts()
+        Co, dropped = O.count(len(prog["op_class"]), r)
+        from parity import _equal
+        _equal(C, Co, "batched counts")
+        _equal(int(tot[0]), int(Co.sum()), "batched valid samples")
+        _equal(int(tot[1]), int(Co[:, :, 1].sum()), "batched latency samples")
+        b.close()
+    P.close()
+
+
+def _dev(rec):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(rec).view(np.uint8).copy()).cuda()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_small_programs_through_the_hot_and_cold_path(monkeypatch, seed):
+    """Programs small enough for the direct mode, forced through the
+    hot-set / cold-key path instead (GPA_HIST_HOTSET=1): whole-path parity,
+    so that both histogram modes stay covered on small programs."""
+    monkeypatch.setenv("GPA_HIST_HOTSET", "1")
+    prog, rec = S.workload_small(seed=40 + seed, n_samples=[200_000, 1_000_003, 37][seed])
+    _both(prog, S.corrupt_samples(rec, 0.01, len(prog["op_class"]), seed=seed))
+
+
 def _golden_cases():
     import json
     import os

@@ -106,18 +106,39 @@ def test_noalloc_on_the_large_profile_and_an_empty_one():
     P.close()
 
 
+def _outputs_for(P):
+    import torch
+    info = P.info
+    ni, ne, nb = info["n_instr"], info["n_edges"], info["n_blamable"]
+    return [torch.zeros(ni * 24, dtype=torch.int32, device="cuda"),
+            torch.zeros(4, dtype=torch.int64, device="cuda"),
+            torch.zeros(max(ne * nb * 2, 1), dtype=torch.float64, device="cuda"),
+            torch.zeros(ni * 24, dtype=torch.float64, device="cuda"),
+            torch.zeros(ni * 24, dtype=torch.float64, device="cuda"),
+            torch.zeros(ni * N_FINE * 2, dtype=torch.float64, device="cuda")]
+
+
 def test_noalloc_rejects_inputs_beyond_its_scratch():
     """Checked on the host before any launch: GPA_E_UNSUPPORTED with a
-    message, and the library stays usable."""
+    message, and the library stays usable.  The refused call gets a record
+    buffer of its full size and output arrays of theirs, so that nothing
+    would be read or written out of bounds even if the check let it through.
+    The program has more than 3,072 instructions, so its histogram keeps cold
+    keys (8 bytes of scratch per record); a smaller program's scratch does
+    not grow with the records."""
+    import torch
     gpa, L = _abi()
-    prog, rec = S.workload_small(seed=3, n_samples=1000)
+    prog, rec = S.workload_large(seed=1, n_samples=2_000_000)
     P = gpa.Program(gpa.program_to_device(prog))
-    d = _dev(rec)
     cap = L.gpa_noalloc_scratch_bytes()
     n_too_many = cap // 8 + 1   # the cold-key arrays alone take 8 bytes per record
-    st = L.gpa_attribute_noalloc(P.handle, d.data_ptr(), n_too_many, None, d.data_ptr(),
-                                 d.data_ptr(), d.data_ptr(), d.data_ptr(), d.data_ptr(),
-                                 d.data_ptr())
+    big = torch.zeros(n_too_many * 8, dtype=torch.uint8, device="cuda")
+    outs = _outputs_for(P)
+    torch.cuda.synchronize()
+    st = L.gpa_attribute_noalloc(P.handle, big.data_ptr(), n_too_many, None,
+                                 *[t.data_ptr() for t in outs])
     assert st == -6 and b"scratch" in L.gpa_last_error()
+    del big
+    d = _dev(rec)
     _same(_noalloc(gpa, L, P, d), _plain(P, d), "after the refused call")
     P.close()
