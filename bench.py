@@ -519,6 +519,7 @@ def main():
                                "sizes), <= 12k function scopes, 500M records (4 GB) grouped by "
                                "kernel, Zipf 1.1, Dirichlet mixes, seed 3",
                    "records": n_rec, "instructions": info["instructions"],
+                   "edges": info["edges"], "scopes": info["scopes"],
                    "profiles": info["profiles"], "path": "batched, programs resident"},
         "per_profile_samples_per_s": round(n_rec / c3["t_plain"], 1),
         "per_profile_ms_per_step": round(1e3 * c3["t_plain"], 3),

@@ -338,13 +338,18 @@ void enqueue_attribute_batch(gpa_program *const *progs, const gpa_sample *const 
   }
   const uint64_t per = batch_records_per_workgroup(batched.data(), (uint32_t)batched.size(), s, ar,
                                                    measure_tuning);
-  if (t_hist) t_hist->begin(kPhaseHist, s);
-  run_hist_batch(batched.data(), (uint32_t)batched.size(), per, s, ar);
-  for (uint32_t k : single) run_hist(*progs[k], ds[k], n[k], b[k]->counts.p, dtot + 4 * k, s, ar);
-  if (t_hist) t_hist->end(s);
-  if (t_blame) t_blame->begin(kPhaseBlame, s);
-  run_blame_batch(progs, b, count, s, ar, *sh);
-  if (t_blame) t_blame->end(s);
+  // the phase timer brackets the batched launches; when some entries take
+  // the per-profile histogram, it brackets everything from the batch's
+  // preparation to the last of those
+  if (single.empty()) {
+    run_hist_batch(batched.data(), (uint32_t)batched.size(), per, s, ar, t_hist);
+  } else {
+    if (t_hist) t_hist->begin(kPhaseHist, s);
+    run_hist_batch(batched.data(), (uint32_t)batched.size(), per, s, ar);
+    for (uint32_t k : single) run_hist(*progs[k], ds[k], n[k], b[k]->counts.p, dtot + 4 * k, s, ar);
+    if (t_hist) t_hist->end(s);
+  }
+  run_blame_batch(progs, b, count, s, ar, *sh, t_blame);
 }
 
 }  // namespace gpa
@@ -818,9 +823,7 @@ gpa_status gpa_advise_batch(const gpa_blame *const *blames, uint32_t count, void
     for (uint32_t k = 0; k < count; ++k) a[k] = new gpa_advice(blames[k]->prog);
     Arena ar(s);
     PhaseTimer t_adv;
-    t_adv.begin(kPhaseAdvise, s);
-    run_estimate_batch(blames, a.data(), count, 16, s, ar);
-    t_adv.end(s);
+    run_estimate_batch(blames, a.data(), count, 16, s, ar, &t_adv);
     GPA_HIP(hipStreamSynchronize(s));
     t_adv.collect();
   });
@@ -874,9 +877,7 @@ gpa_status gpa_analyze_batch(gpa_program *const *progs, const gpa_sample *const 
     enqueue_attribute_batch(progs, dptr.data(), n, count, s, ar, b.data(), dtot, true, &t_hist,
                             &t_blame);
     for (uint32_t k = 0; k < count; ++k) a[k] = new gpa_advice(b[k]->prog);
-    t_adv.begin(kPhaseAdvise, s);
-    run_estimate_batch(b.data(), a.data(), count, 16, s, ar);
-    t_adv.end(s);
+    run_estimate_batch(b.data(), a.data(), count, 16, s, ar, &t_adv);
     std::vector<unsigned long long> tot((size_t)count * 4);
     if (count)
       GPA_HIP(hipMemcpyAsync(tot.data(), dtot, sizeof(unsigned long long) * tot.size(),

@@ -314,7 +314,7 @@ void expand_blame_tables(const gpa_program &p, const uint32_t *counts, const dou
 }
 
 void run_blame_batch(const gpa_program *const *progs, gpa_blame *const *b, uint32_t count,
-                     hipStream_t s, Arena &ar, SharedBlocks &sh) {
+                     hipStream_t s, Arena &ar, SharedBlocks &sh, PhaseTimer *t) {
   std::vector<BlameArgs> args(count);
   std::vector<uint32_t> tiles(count);
   for (uint32_t k = 0; k < count; ++k) {
@@ -340,12 +340,14 @@ void run_blame_batch(const gpa_program *const *progs, gpa_blame *const *b, uint3
   plan.expand(s);
   BlameArgs none{};
   const unsigned g = plan.blocks(q);
+  if (t) t->begin(kPhaseBlame, s);
   hipLaunchKernelGGL(k_blame_dst<true>, dim3(g), dim3(kBlameThreads), 0, s, none, d_args,
                      plan.items(q));
   GPA_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_blame_src<true>, dim3(g), dim3(kBlameThreads), 0, s, none, d_args,
                      plan.items(q));
   GPA_LAUNCH_CHECK();
+  if (t) t->end(s);
 }
 
 }  // namespace gpa

@@ -411,7 +411,11 @@ struct HistEntry {
 // records per pass workgroup (rounded up to a multiple of 128, and raised
 // where a profile would need more than 256 workgroups).  Entries must have
 // n > 0.  The counts equal run_hist's for each profile.
-void run_hist_batch(const HistEntry *e, uint32_t count, uint64_t per, hipStream_t s, Arena &ar);
+struct PhaseTimer;
+// (t, when given, brackets the three launches only, not the host's
+// preparation of the argument tables and work lists)
+void run_hist_batch(const HistEntry *e, uint32_t count, uint64_t per, hipStream_t s, Arena &ar,
+                    PhaseTimer *t = nullptr);
 // The autotuner of the batched histogram: records per pass workgroup for
 // this batch's shape bucket (profile count, total and largest record count,
 // each to a power of two), measured once per bucket and process by timing
@@ -503,13 +507,13 @@ uint64_t request_device_bytes(const gpa_program &p, uint64_t n, bool host_record
 // the blame of many profiles (their counts already in b[k]->counts) in two
 // launches; each handle's tables are carved from `sh`
 void run_blame_batch(const gpa_program *const *progs, gpa_blame *const *b, uint32_t count,
-                     hipStream_t s, Arena &ar, SharedBlocks &sh);
+                     hipStream_t s, Arena &ar, SharedBlocks &sh, PhaseTimer *t = nullptr);
 // estimate.hip
 void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &a, uint32_t k,
                   hipStream_t s, Arena &ar);
 // the advise of many profiles, each stage one launch over all of them
 void run_estimate_batch(const gpa_blame *const *b, gpa_advice *const *adv, uint32_t count,
-                        uint32_t k, hipStream_t s, Arena &ar);
+                        uint32_t k, hipStream_t s, Arena &ar, PhaseTimer *t = nullptr);
 // at load: the top-k chunks of every kernel root (static)
 void build_topk_plan(gpa_program &p, hipStream_t s, Arena &ar);
 

@@ -663,7 +663,7 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &adv, uin
 }
 
 void run_estimate_batch(const gpa_blame *const *b, gpa_advice *const *adv, uint32_t count,
-                        uint32_t k, hipStream_t s, Arena &ar) {
+                        uint32_t k, hipStream_t s, Arena &ar, PhaseTimer *t) {
   std::vector<EstArgs> args(count);
   // per-entry workgroups of each stage: scopes, chunks of each grouping and
   // their long segments, top-k chunks, kernel roots
@@ -706,6 +706,7 @@ void run_estimate_batch(const gpa_blame *const *b, gpa_advice *const *adv, uint3
   plan.expand(s);
   EstLaunch L{s, EstArgs{}, up.ptr<EstArgs>(i_args)};
   auto run = [&](auto kern, uint32_t q, unsigned gy) { L(kern, plan.blocks(q), gy, plan.items(q)); };
+  if (t) t->begin(kPhaseAdvise, s);
   run(k_seg_small<kNV, 0, 1, true>, q_scope, 1);
   run(k_seg_chunks<kNV, 0, 1, true>, q_ch[0], 1);
   run(k_seg_combine<kNV, 0, 1, true>, q_cb[0], 1);
@@ -726,6 +727,7 @@ void run_estimate_batch(const gpa_blame *const *b, gpa_advice *const *adv, uint3
                        EstArgs{}, L.many, plan.items(q_tkf));
     GPA_LAUNCH_CHECK();
   }
+  if (t) t->end(s);
 }
 
 }  // namespace gpa

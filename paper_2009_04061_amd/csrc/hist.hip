@@ -1432,11 +1432,14 @@ static void launch_hist_batch(const HistBatch &hb, hipStream_t s) {
   }
 }
 
-void run_hist_batch(const HistEntry *e, uint32_t count, uint64_t per, hipStream_t s, Arena &ar) {
+void run_hist_batch(const HistEntry *e, uint32_t count, uint64_t per, hipStream_t s, Arena &ar,
+                    PhaseTimer *t) {
   if (count == 0) return;
   HistBatch hb(count);
   prepare_hist_batch(hb, e, count, per, s, ar);
+  if (t) t->begin(kPhaseHist, s);
   launch_hist_batch(hb, s);
+  if (t) t->end(s);
 }
 
 // ------------------------------------------------------------- autotuner
