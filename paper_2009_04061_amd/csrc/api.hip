@@ -115,6 +115,41 @@ void dev_free(void *p) {
   P.cached += it->second.cls;
 }
 
+namespace {
+std::mutex g_pin_mu;
+std::multimap<size_t, void *> g_pinned;   // capacity -> free pinned block
+}  // namespace
+
+void *pinned_take(size_t bytes, size_t *cap) {
+  size_t c = 64 << 10;
+  while (c < bytes) c <<= 1;
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    auto it = g_pinned.lower_bound(c);
+    if (it != g_pinned.end() && it->first <= 4 * c) {
+      void *p = it->second;
+      *cap = it->first;
+      g_pinned.erase(it);
+      return p;
+    }
+  }
+  void *p = nullptr;
+  const hipError_t e = hipHostMalloc(&p, c);
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    set_error("pinned host allocation of %zu bytes failed: %s", c, hipGetErrorString(e));
+    throw Error{GPA_E_NOMEM};
+  }
+  *cap = c;
+  return p;
+}
+
+void pinned_give(void *p, size_t cap) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pinned.emplace(cap, p);
+}
+
 void pool_stats(uint64_t *in_use, uint64_t *cached) {
   int dev = 0;
   GPA_HIP(hipGetDevice(&dev));

@@ -22,6 +22,8 @@
 // outside the memory / execution / synchronization classes (fx, 6 per
 // instruction).  Everything else of the full tables follows from these and
 // the counts; k_blame_expand writes the full tables when they are asked for.
+#include <algorithm>
+
 #include "common.h"
 #include "devutil.h"
 
@@ -35,7 +37,7 @@ struct BlameArgs {
   uint32_t n_instr, nbl, blamable;
   uint16_t allowed[12];
   const uint32_t *counts, *in_ptr, *e_src, *e_dmax, *out_ptr, *out_perm;
-  const uint8_t *e_flags, *op_class;
+  const uint8_t *e_flags, *e_cls;
   double *share, *bl, *fx;
   uint16_t *nocand;
 };
@@ -53,78 +55,125 @@ constexpr int kBlameThreads = 128;
 // per blamable reason, the issued-based and the path-only weights of the
 // candidates (in edge order, as Eq. (1) is written); a second pass writes
 // every share slot of those edges.  Reasons are unrolled, so the per-reason
-// sums stay in registers.
-template <bool BATCH>
+// sums stay in registers.  The edges are taken kBlameU at a time, their
+// loads and the gathers of their sources' issued samples issued together;
+// the first kBlameU edges' weights stay in registers for the second pass
+// (most instructions have no more incoming edges than that).
+constexpr uint32_t kBlameU = 4;
+
+struct EdgeW {
+  double wi, wp;    // issued / length, 1 / length
+  uint32_t cls;     // the source's opcode class
+  bool kept;        // survives dominator and latency pruning
+};
+
+// edge e0 + u of j's range [e0, e1) (an edge past the range reads edge e0
+// and is not kept)
+__device__ __forceinline__ EdgeW blame_edge(const BlameArgs &a, uint32_t e0, uint32_t e1,
+                                            uint32_t e) {
+  const bool in = e < e1;
+  const uint32_t x = in ? e : e0;
+  const uint8_t fl = a.e_flags[x];
+  EdgeW w;
+  w.kept = in && (fl & GPA_E_DOM_KEEP) && (fl & GPA_E_LAT_KEEP);
+  w.cls = a.e_cls[x];
+  const uint32_t i = a.e_src[x];
+  const double len = (double)a.e_dmax[x] + 1.0;
+  const double issued = (double)a.counts[(size_t)i * 24] + (double)a.counts[(size_t)i * 24 + 1];
+  w.wi = issued / len;
+  w.wp = 1.0 / len;
+  return w;
+}
+
+// NB: blamable reasons the kernel keeps sums for (the arch's blamable set
+// has at most NB reasons; slot s is the s-th blamable reason ascending)
+template <bool BATCH, int NB>
 __global__ void __launch_bounds__(kBlameThreads)
 k_blame_dst(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *__restrict__ items) {
   BLAME_ITEM(j) {
     const uint32_t nbl = a.nbl;
-    const uint32_t *__restrict__ counts = a.counts;
-    const uint32_t *__restrict__ e_src = a.e_src;
-    const uint32_t *__restrict__ e_dmax = a.e_dmax;
-    const uint8_t *__restrict__ e_flags = a.e_flags;
-    const uint8_t *__restrict__ op_class = a.op_class;
-    struct {
-      uint16_t blamable;
-      const uint16_t *allowed;
-    } arch{(uint16_t)a.blamable, a.allowed};
-    const uint32_t *C = counts + (size_t)j * 24;
-    const uint32_t e0 = a.in_ptr[j], e1 = a.in_ptr[j + 1];
-    double Wi[12], Wp[12];
-    bool any[12];
-#pragma unroll
-    for (int r = 0; r < 12; ++r) {
-      Wi[r] = 0.0;
-      Wp[r] = 0.0;
-      any[r] = false;
-    }
-    for (uint32_t e = e0; e < e1; ++e) {
-      const uint8_t fl = e_flags[e];
-      if (!(fl & GPA_E_DOM_KEEP) || !(fl & GPA_E_LAT_KEEP)) continue;
-      const uint32_t i = e_src[e];
-      const uint32_t cls = op_class[i];
-      const double len = (double)e_dmax[e] + 1.0;
-      const double issued = (double)counts[(size_t)i * 24] + (double)counts[(size_t)i * 24 + 1];
-      const double wi = issued / len, wp = 1.0 / len;
+    // the blamable reasons by slot, and the opcode classes each allows
+    uint32_t rs[NB], allow[NB];
+    {
+      uint32_t s = 0;
 #pragma unroll
       for (int r = 0; r < 12; ++r) {
-        if (!((arch.blamable >> r) & 1u) || !((arch.allowed[r] >> cls) & 1u)) continue;
-        Wi[r] += wi;
-        Wp[r] += wp;
-        any[r] = true;
-      }
-    }
-    for (uint32_t e = e0; e < e1; ++e) {
-      const uint8_t fl = e_flags[e];
-      const bool kept = (fl & GPA_E_DOM_KEEP) && (fl & GPA_E_LAT_KEEP);
-      const uint32_t i = e_src[e];
-      const uint32_t cls = op_class[i];
-      const double len = (double)e_dmax[e] + 1.0;
-      const double issued = (double)counts[(size_t)i * 24] + (double)counts[(size_t)i * 24 + 1];
-      double *sh = a.share + (size_t)e * 2 * nbl;
-      uint32_t slot = 0;
-#pragma unroll
-      for (int r = 0; r < 12; ++r) {
-        if (!((arch.blamable >> r) & 1u)) continue;
-        const bool cand = kept && ((arch.allowed[r] >> cls) & 1u);
-        const bool by_path = (Wi[r] == 0.0);
-        const double w = by_path ? 1.0 / len : issued / len;
-        const double W = by_path ? Wp[r] : Wi[r];
-#pragma unroll
-        for (int l = 0; l < 2; ++l) {
-          const uint32_t S = C[r * 2 + l];
-          sh[slot * 2 + l] = (cand && S != 0) ? (double)S * w / W : 0.0;
+        if (((a.blamable >> r) & 1u) && s < (uint32_t)NB) {
+          rs[s] = (uint32_t)r;
+          allow[s] = a.allowed[r];
+          ++s;
         }
-        ++slot;
+      }
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+        if ((uint32_t)q >= s) {
+          rs[q] = 0;
+          allow[q] = 0;
+        }
+    }
+    const uint32_t *C = a.counts + (size_t)j * 24;
+    const uint32_t e0 = a.in_ptr[j], e1 = a.in_ptr[j + 1];
+    double Wi[NB], Wp[NB];
+    bool any[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      Wi[q] = 0.0;
+      Wp[q] = 0.0;
+      any[q] = false;
+    }
+    EdgeW first[kBlameU];
+    for (uint32_t base = e0; base < e1; base += kBlameU) {
+      EdgeW w[kBlameU];
+#pragma unroll
+      for (uint32_t u = 0; u < kBlameU; ++u) w[u] = blame_edge(a, e0, e1, base + u);
+#pragma unroll
+      for (uint32_t u = 0; u < kBlameU; ++u) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          const bool cand = w[u].kept && ((allow[q] >> w[u].cls) & 1u);
+          Wi[q] = cand ? Wi[q] + w[u].wi : Wi[q];
+          Wp[q] = cand ? Wp[q] + w[u].wp : Wp[q];
+          any[q] = any[q] || cand;
+        }
+      }
+      if (base == e0) {
+#pragma unroll
+        for (uint32_t u = 0; u < kBlameU; ++u) first[u] = w[u];
       }
     }
-    uint32_t mask = 0, bit = 0;
+    for (uint32_t base = e0; base < e1; base += kBlameU) {
+      EdgeW w[kBlameU];
+      if (base == e0) {
 #pragma unroll
-    for (int r = 0; r < 12; ++r) {
-      if (!((arch.blamable >> r) & 1u)) continue;
-      mask |= any[r] ? 0u : (1u << bit);
-      ++bit;
+        for (uint32_t u = 0; u < kBlameU; ++u) w[u] = first[u];
+      } else {
+#pragma unroll
+        for (uint32_t u = 0; u < kBlameU; ++u) w[u] = blame_edge(a, e0, e1, base + u);
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kBlameU; ++u) {
+        const uint32_t e = base + u;
+        if (e >= e1) break;
+        double *sh = a.share + (size_t)e * 2 * nbl;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          if ((uint32_t)q >= nbl) break;
+          const bool cand = w[u].kept && ((allow[q] >> w[u].cls) & 1u);
+          const bool by_path = (Wi[q] == 0.0);
+          const double wt = by_path ? w[u].wp : w[u].wi;
+          const double W = by_path ? Wp[q] : Wi[q];
+#pragma unroll
+          for (int l = 0; l < 2; ++l) {
+            const uint32_t S = C[rs[q] * 2 + l];
+            sh[q * 2 + l] = (cand && S != 0) ? (double)S * wt / W : 0.0;
+          }
+        }
+      }
     }
+    uint32_t mask = 0;
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+      if ((uint32_t)q < nbl && !any[q]) mask |= 1u << q;
     a.nocand[j] = (uint16_t)mask;
   }
 }
@@ -132,54 +181,78 @@ k_blame_dst(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *_
 // One thread per source i: sums its outgoing shares in edge order, per
 // blamable reason, and the execution-dependency shares split by the WAR flag
 // of the edge (the fine classes of a memory dependency and of a non-WAR
-// execution dependency follow from i's opcode class alone).
-template <bool BATCH>
+// execution dependency follow from i's opcode class alone).  The edges are
+// read two at a time (their loads issued together) and summed in order.
+constexpr uint32_t kBlameSrcU = 2;
+
+template <bool BATCH, int NB>
 __global__ void __launch_bounds__(kBlameThreads)
 k_blame_src(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *__restrict__ items) {
   BLAME_ITEM(i) {
-    const uint32_t nbl = a.nbl, blamable = a.blamable;
-    const uint32_t *__restrict__ out_ptr = a.out_ptr;
+    const uint32_t nbl = a.nbl;
     const uint32_t *__restrict__ out_perm = a.out_perm;
     const uint8_t *__restrict__ e_flags = a.e_flags;
     const double *__restrict__ share = a.share;
-    double acc[24];
+    uint32_t rs[NB];   // the blamable reasons by slot
+    {
+      uint32_t sl = 0;
 #pragma unroll
-    for (int q = 0; q < 24; ++q) acc[q] = 0.0;
+      for (int r = 0; r < 12; ++r)
+        if (((a.blamable >> r) & 1u) && sl < (uint32_t)NB) rs[sl++] = (uint32_t)r;
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+        if ((uint32_t)q >= sl) rs[q] = 12;
+    }
+    double acc[2 * NB];
+#pragma unroll
+    for (int q = 0; q < 2 * NB; ++q) acc[q] = 0.0;
     double war0 = 0.0, war1 = 0.0, nwar0 = 0.0, nwar1 = 0.0, oth0 = 0.0, oth1 = 0.0;
-    for (uint32_t k = out_ptr[i]; k < out_ptr[i + 1]; ++k) {
-      const uint32_t e = out_perm[k];
-      const bool war = (e_flags[e] & GPA_E_WAR) != 0;
-      uint32_t slot = 0;
+    const uint32_t k0 = a.out_ptr[i], k1 = a.out_ptr[i + 1];
+    for (uint32_t k = k0; k < k1; k += kBlameSrcU) {
+      double sv[kBlameSrcU][2 * NB];
+      bool war[kBlameSrcU], in[kBlameSrcU];
 #pragma unroll
-      for (uint32_t r = 0; r < 12; ++r) {
-        if (!((blamable >> r) & 1u)) continue;
-        const double s0 = share[((size_t)e * nbl + slot) * 2];
-        const double s1 = share[((size_t)e * nbl + slot) * 2 + 1];
-        acc[r * 2] += s0;
-        acc[r * 2 + 1] += s1;
-        if (r == GPA_ST_EXEC_DEP) {
-          if (war) {
-            war0 += s0;
-            war1 += s1;
-          } else {
-            nwar0 += s0;
-            nwar1 += s1;
-          }
-        } else if (r != GPA_ST_MEM_DEP && r != GPA_ST_SYNC) {
-          oth0 += s0;
-          oth1 += s1;
+      for (uint32_t u = 0; u < kBlameSrcU; ++u) {
+        in[u] = k + u < k1;
+        const uint32_t e = out_perm[in[u] ? k + u : k0];
+        war[u] = (e_flags[e] & GPA_E_WAR) != 0;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          const bool live = (uint32_t)q < nbl;
+          sv[u][2 * q] = live ? share[((size_t)e * nbl + q) * 2] : 0.0;
+          sv[u][2 * q + 1] = live ? share[((size_t)e * nbl + q) * 2 + 1] : 0.0;
         }
-        ++slot;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kBlameSrcU; ++u) {
+        if (!in[u]) continue;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          if ((uint32_t)q >= nbl) continue;
+          const double s0 = sv[u][2 * q], s1 = sv[u][2 * q + 1];
+          acc[2 * q] += s0;
+          acc[2 * q + 1] += s1;
+          if (rs[q] == GPA_ST_EXEC_DEP) {
+            if (war[u]) {
+              war0 += s0;
+              war1 += s1;
+            } else {
+              nwar0 += s0;
+              nwar1 += s1;
+            }
+          } else if (rs[q] != GPA_ST_MEM_DEP && rs[q] != GPA_ST_SYNC) {
+            oth0 += s0;
+            oth1 += s1;
+          }
+        }
       }
     }
     double *bl = a.bl + (size_t)i * nbl * 2;
-    uint32_t slot = 0;
 #pragma unroll
-    for (uint32_t r = 0; r < 12; ++r) {
-      if (!((blamable >> r) & 1u)) continue;
-      bl[slot * 2] = acc[r * 2];
-      bl[slot * 2 + 1] = acc[r * 2 + 1];
-      ++slot;
+    for (int q = 0; q < NB; ++q) {
+      if ((uint32_t)q >= nbl) continue;
+      bl[q * 2] = acc[2 * q];
+      bl[q * 2 + 1] = acc[2 * q + 1];
     }
     double *fx = a.fx + (size_t)i * kBlameFx;
     fx[0] = war0;
@@ -285,7 +358,7 @@ static BlameArgs blame_args(const gpa_program &p, const uint32_t *counts, double
   a.out_ptr = p.out_ptr;
   a.out_perm = p.out_perm;
   a.e_flags = p.e_flags.p;
-  a.op_class = p.op_class.p;
+  a.e_cls = p.e_cls.p;
   a.share = share;
   a.bl = bl;
   a.fx = fx;
@@ -297,9 +370,19 @@ void launch_blame(const gpa_program &p, const uint32_t *counts, double *share, d
                   double *fx, uint16_t *nocand, hipStream_t s) {
   const BlameArgs a = blame_args(p, counts, share, bl, fx, nocand);
   const unsigned g = grid_for(p.n_instr, kBlameThreads, 8192);
-  hipLaunchKernelGGL(k_blame_dst<false>, dim3(g), dim3(kBlameThreads), 0, s, a, nullptr, nullptr);
+  if (p.n_blamable <= 4)
+    hipLaunchKernelGGL((k_blame_dst<false, 4>), dim3(g), dim3(kBlameThreads), 0, s, a, nullptr,
+                       nullptr);
+  else
+    hipLaunchKernelGGL((k_blame_dst<false, 12>), dim3(g), dim3(kBlameThreads), 0, s, a, nullptr,
+                       nullptr);
   GPA_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_blame_src<false>, dim3(g), dim3(kBlameThreads), 0, s, a, nullptr, nullptr);
+  if (p.n_blamable <= 4)
+    hipLaunchKernelGGL((k_blame_src<false, 4>), dim3(g), dim3(kBlameThreads), 0, s, a, nullptr,
+                       nullptr);
+  else
+    hipLaunchKernelGGL((k_blame_src<false, 12>), dim3(g), dim3(kBlameThreads), 0, s, a, nullptr,
+                       nullptr);
   GPA_LAUNCH_CHECK();
 }
 
@@ -341,11 +424,21 @@ void run_blame_batch(const gpa_program *const *progs, gpa_blame *const *b, uint3
   BlameArgs none{};
   const unsigned g = plan.blocks(q);
   if (t) t->begin(kPhaseBlame, s);
-  hipLaunchKernelGGL(k_blame_dst<true>, dim3(g), dim3(kBlameThreads), 0, s, none, d_args,
-                     plan.items(q));
+  uint32_t max_nbl = 0;
+  for (uint32_t k = 0; k < count; ++k) max_nbl = std::max(max_nbl, progs[k]->n_blamable);
+  if (max_nbl <= 4)
+    hipLaunchKernelGGL((k_blame_dst<true, 4>), dim3(g), dim3(kBlameThreads), 0, s, none, d_args,
+                       plan.items(q));
+  else
+    hipLaunchKernelGGL((k_blame_dst<true, 12>), dim3(g), dim3(kBlameThreads), 0, s, none, d_args,
+                       plan.items(q));
   GPA_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_blame_src<true>, dim3(g), dim3(kBlameThreads), 0, s, none, d_args,
-                     plan.items(q));
+  if (max_nbl <= 4)
+    hipLaunchKernelGGL((k_blame_src<true, 4>), dim3(g), dim3(kBlameThreads), 0, s, none, d_args,
+                       plan.items(q));
+  else
+    hipLaunchKernelGGL((k_blame_src<true, 12>), dim3(g), dim3(kBlameThreads), 0, s, none, d_args,
+                       plan.items(q));
   GPA_LAUNCH_CHECK();
   if (t) t->end(s);
 }

@@ -50,6 +50,13 @@ void pool_stats(uint64_t *in_use, uint64_t *cached);
 // frees the current device's cached blocks
 void pool_trim();
 
+// Pinned host staging for uploads (hipHostMalloc), pooled process-wide:
+// a copy from pinned memory is asynchronous, where one from pageable memory
+// can hold the host until the stream has caught up with it.  A block goes
+// back to the pool only when the stream work reading it is complete.
+void *pinned_take(size_t bytes, size_t *cap);
+void pinned_give(void *p, size_t cap);
+
 template <typename T>
 struct DBuf {
   T *p = nullptr;
@@ -140,8 +147,9 @@ struct SharedBlocks {
 struct Arena {
   ChunkCarver carver;
   std::vector<hipStream_t> streams;
-  // host staging of uploads, kept until the streams have finished with them
-  std::vector<std::vector<char>> host_blocks;
+  // pinned host staging of uploads, kept until the streams have finished
+  // with them
+  std::vector<std::pair<void *, size_t>> pinned;
   char *fixed = nullptr;
   size_t cap = 0, used = 0;
   explicit Arena(hipStream_t s) { streams.push_back(s); }
@@ -156,6 +164,14 @@ struct Arena {
     if (fixed) return;
     for (hipStream_t s : streams) (void)hipStreamSynchronize(s);
     carver.release();
+    for (auto &b : pinned) pinned_give(b.first, b.second);
+  }
+  // a pinned staging block of at least `bytes`, returned with the arena
+  void *stage(size_t bytes) {
+    size_t got = 0;
+    void *p = pinned_take(bytes, &got);
+    pinned.emplace_back(p, got);
+    return p;
   }
   template <typename T>
   T *get(size_t count) {
@@ -171,21 +187,6 @@ struct Arena {
       return reinterpret_cast<T *>(fixed + at);
     }
     return static_cast<T *>(carver.take(bytes));
-  }
-  // a device copy of host data, uploaded on `s` (pool mode only)
-  template <typename T>
-  T *upload(const std::vector<T> &v, hipStream_t s) {
-    T *d = get<T>(v.size());
-    if (v.empty()) return d;
-    host_blocks.emplace_back(reinterpret_cast<const char *>(v.data()),
-                             reinterpret_cast<const char *>(v.data() + v.size()));
-    const hipError_t e =
-        hipMemcpyAsync(d, host_blocks.back().data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) {
-      set_error("upload of %zu bytes failed: %s", sizeof(T) * v.size(), hipGetErrorString(e));
-      throw Error{GPA_E_DEVICE};
-    }
-    return d;
   }
 };
 
@@ -223,7 +224,7 @@ struct gpa_program {
   uint64_t n_edges = 0;
   gpa::DBuf<uint32_t> in_ptr;                  // [n_instr+1] edges into j
   gpa::DBuf<uint32_t> e_src, e_dst, e_dmin, e_dmax;
-  gpa::DBuf<uint8_t> e_flags;
+  gpa::DBuf<uint8_t> e_flags, e_cls;           // flags; the source's opcode class
   // stable groupings, built by one sort after the edges: edges by source
   // instruction (out), by common scope (lca), by common loop (icl), and
   // instructions by line scope (line); each view is laid out as if grouped
@@ -381,11 +382,11 @@ struct Upload {
   void send(Arena &ar, hipStream_t s) {
     dev = ar.get<char>(host.size());
     if (host.empty()) return;
-    ar.host_blocks.emplace_back(std::move(host));
-    const std::vector<char> &h = ar.host_blocks.back();
-    const hipError_t e = hipMemcpyAsync(dev, h.data(), h.size(), hipMemcpyHostToDevice, s);
+    void *pin = ar.stage(host.size());
+    memcpy(pin, host.data(), host.size());
+    const hipError_t e = hipMemcpyAsync(dev, pin, host.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) {
-      set_error("upload of %zu bytes failed: %s", h.size(), hipGetErrorString(e));
+      set_error("upload of %zu bytes failed: %s", host.size(), hipGetErrorString(e));
       throw Error{GPA_E_DEVICE};
     }
   }

@@ -617,9 +617,12 @@ __global__ void k_edge_sort(uint32_t n_instr, const uint32_t *use_ptr, const uin
 
 // One edge per (i, j): kept by dominance if any carrying location keeps it,
 // write-after-read if every carrying location is a read barrier of i.
+// The edge's source opcode class is kept beside it (e_cls), so that the
+// blamer reads it with the edge instead of gathering it through the source.
 __global__ void k_edge_fill(uint32_t n_instr, const uint32_t *use_ptr, const uint32_t *rd_ptr,
-                            const uint64_t *items, const uint32_t *in_ptr, uint32_t *e_src,
-                            uint32_t *e_dst, uint8_t *e_flags) {
+                            const uint64_t *items, const uint32_t *in_ptr,
+                            const uint8_t *op_class, uint32_t *e_src, uint32_t *e_dst,
+                            uint8_t *e_flags, uint8_t *e_cls) {
   for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_instr;
        j += gridDim.x * blockDim.x) {
     const uint32_t a = rd_ptr[use_ptr[j]], b = rd_ptr[use_ptr[j + 1]];
@@ -635,6 +638,7 @@ __global__ void k_edge_fill(uint32_t n_instr, const uint32_t *use_ptr, const uin
       }
       e_src[e] = src;
       e_dst[e] = j;
+      e_cls[e] = op_class[src];
       e_flags[e] = (uint8_t)((blk ? GPA_E_DOM_KEEP : 0) | (nonrbar ? 0 : GPA_E_WAR));
       ++e;
     }
@@ -752,8 +756,10 @@ void build_edges(gpa_program &p, hipStream_t s, Arena &ar) {
   p.e_src.alloc(ne);
   p.e_dst.alloc(ne);
   p.e_flags.alloc(ne);
+  p.e_cls.alloc(ne);
   hipLaunchKernelGGL(k_edge_fill, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, p.use_ptr.p,
-                     p.rd_ptr.p, items, p.in_ptr.p, p.e_src.p, p.e_dst.p, p.e_flags.p);
+                     p.rd_ptr.p, items, p.in_ptr.p, p.op_class.p, p.e_src.p, p.e_dst.p,
+                     p.e_flags.p, p.e_cls.p);
   GPA_LAUNCH_CHECK();
   // (the grouping by source instruction is built with the target scopes)
 }

@@ -40,7 +40,7 @@ struct EstArgs {
   const uint32_t *counts;
   const double *bl, *share;
   const uint16_t *nocand;
-  const uint8_t *op_class, *tags;
+  const uint8_t *op_class, *tags, *e_cls;
   const uint32_t *e_src, *line_ptr, *line_perm, *icl_ptr, *icl_perm, *lca_ptr, *lca_perm;
   const uint32_t *scope_end, *scope_parent, *root_of, *roots;
   const uint32_t *big_list, *big_n, *big_chunk;   // 4 groupings x ns
@@ -111,7 +111,7 @@ __device__ __forceinline__ void line_value(const EstArgs &a, uint64_t kk, double
 // by an edge (Loop Unrolling and Code Reordering)
 __device__ __forceinline__ double edge_contrib(const EstArgs &a, uint64_t e) {
   double v = 0.0;
-  if (a.s_mem >= 0 && a.op_class[a.e_src[e]] == GPA_OP_GLOBAL_LOAD)
+  if (a.s_mem >= 0 && a.e_cls[e] == GPA_OP_GLOBAL_LOAD)
     v += a.share[(e * a.nbl + a.s_mem) * 2 + 1];
   if (a.s_exec >= 0) v += a.share[(e * a.nbl + a.s_exec) * 2 + 1];
   return v;
@@ -568,6 +568,7 @@ static EstArgs est_args(const gpa_program &p, const gpa_blame &b, gpa_advice &ad
   a.nocand = b.nocand.p;
   a.share = b.share.p;
   a.op_class = p.op_class.p;
+  a.e_cls = p.e_cls.p;
   a.tags = p.instr_tags.p;
   a.e_src = p.e_src.p;
   a.line_ptr = p.line_ptr;

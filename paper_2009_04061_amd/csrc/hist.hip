@@ -1432,13 +1432,63 @@ static void launch_hist_batch(const HistBatch &hb, hipStream_t s) {
   }
 }
 
+// A large batch is split into two halves of about equal records, each
+// launched on a stream of its own (the caller's and a side stream, joined
+// by events before the call's next work on the caller's stream): one half's
+// latency-bound selection and finish then run beside the other half's
+// streaming pass instead of after it.
+constexpr uint32_t kSplitMinEntries = 8;
+constexpr uint64_t kSplitMinRecords = 1ull << 24;
+
+namespace {
+struct SyncEvent {
+  hipEvent_t e = nullptr;
+  SyncEvent() { GPA_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming)); }
+  ~SyncEvent() {
+    if (e) (void)hipEventDestroy(e);
+  }
+  SyncEvent(const SyncEvent &) = delete;
+  SyncEvent &operator=(const SyncEvent &) = delete;
+};
+}  // namespace
+
 void run_hist_batch(const HistEntry *e, uint32_t count, uint64_t per, hipStream_t s, Arena &ar,
                     PhaseTimer *t) {
   if (count == 0) return;
-  HistBatch hb(count);
-  prepare_hist_batch(hb, e, count, per, s, ar);
+  uint64_t total = 0;
+  for (uint32_t k = 0; k < count; ++k) total += e[k].n;
+  if (count < kSplitMinEntries || total < kSplitMinRecords) {
+    HistBatch hb(count);
+    prepare_hist_batch(hb, e, count, per, s, ar);
+    if (t) t->begin(kPhaseHist, s);
+    launch_hist_batch(hb, s);
+    if (t) t->end(s);
+    return;
+  }
+  // largest first onto the lighter half
+  std::vector<uint32_t> idx(count);
+  for (uint32_t k = 0; k < count; ++k) idx[k] = k;
+  std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return e[x].n > e[y].n; });
+  std::vector<HistEntry> half[2];
+  uint64_t load[2] = {0, 0};
+  for (uint32_t k : idx) {
+    const int h = load[0] <= load[1] ? 0 : 1;
+    half[h].push_back(e[k]);
+    load[h] += e[k].n;
+  }
+  HistBatch h0((uint32_t)half[0].size()), h1((uint32_t)half[1].size());
+  prepare_hist_batch(h0, half[0].data(), (uint32_t)half[0].size(), per, s, ar);
+  prepare_hist_batch(h1, half[1].data(), (uint32_t)half[1].size(), per, s, ar);
+  hipStream_t s2 = side_stream(1);
+  ar.add_stream(s2);
+  SyncEvent fork, join;
   if (t) t->begin(kPhaseHist, s);
-  launch_hist_batch(hb, s);
+  GPA_HIP(hipEventRecord(fork.e, s));
+  GPA_HIP(hipStreamWaitEvent(s2, fork.e, 0));
+  launch_hist_batch(h1, s2);
+  launch_hist_batch(h0, s);
+  GPA_HIP(hipEventRecord(join.e, s2));
+  GPA_HIP(hipStreamWaitEvent(s, join.e, 0));
   if (t) t->end(s);
 }
 

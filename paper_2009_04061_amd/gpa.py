@@ -430,24 +430,38 @@ class BatchResult:
             pass
 
 
-def analyze_batch(programs, samples, stream=None) -> BatchResult:
+class BatchInputs:
+    """The argument arrays of a batched call (program handles, record
+    pointers and counts), marshalled once for a batch that is analyzed
+    repeatedly; the programs and sample arrays must outlive it."""
+
+    def __init__(self, programs, samples):
+        count = len(programs)
+        if len(samples) != count:
+            raise ValueError("one sample array per program")
+        recs = [_records(x) for x in samples]
+        on_dev = {r[2] for r in recs}
+        if len(on_dev) > 1:
+            raise ValueError("sample arrays must all be host or all be device arrays")
+        self.programs, self.count = list(programs), count
+        self.on_dev = on_dev.pop() if count else 1
+        self._keep = [r[3] for r in recs]
+        self.progs = (ct.c_void_p * max(count, 1))(*[p.handle for p in programs])
+        self.ptrs = (ct.c_void_p * max(count, 1))(*[r[0] if r[1] else None for r in recs])
+        self.ns = (ct.c_uint64 * max(count, 1))(*[r[1] for r in recs])
+
+
+def analyze_batch(programs, samples=None, stream=None) -> BatchResult:
     """gpa_analyze_batch: attribute and advise every (programs[k],
-    samples[k]) in one call; samples all host (numpy) or all device arrays."""
-    count = len(programs)
-    if len(samples) != count:
-        raise ValueError("one sample array per program")
-    recs = [_records(x) for x in samples]
-    on_dev = {r[2] for r in recs}
-    if len(on_dev) > 1:
-        raise ValueError("sample arrays must all be host or all be device arrays")
-    progs = (ct.c_void_p * max(count, 1))(*[p.handle for p in programs])
-    ptrs = (ct.c_void_p * max(count, 1))(*[r[0] if r[1] else None for r in recs])
-    ns = (ct.c_uint64 * max(count, 1))(*[r[1] for r in recs])
+    samples[k]) in one call; samples all host (numpy) or all device arrays.
+    `programs` may instead be a BatchInputs (samples then None)."""
+    inp = programs if isinstance(programs, BatchInputs) else BatchInputs(programs, samples)
+    count = inp.count
     bh = (ct.c_void_p * max(count, 1))()
     ah = (ct.c_void_p * max(count, 1))()
-    _check(lib().gpa_analyze_batch(progs, ptrs, ns, count, on_dev.pop() if count else 1,
+    _check(lib().gpa_analyze_batch(inp.progs, inp.ptrs, inp.ns, count, inp.on_dev,
                                    _stream(stream), bh, ah))
-    return BatchResult(programs, bh, ah, count)
+    return BatchResult(inp.programs, bh, ah, count)
 
 
 def advise_batch(blames, stream=None):
