@@ -317,26 +317,29 @@ __device__ __forceinline__ double saturating_speedup(double T, double y) {
   return (T == 0.0) ? 1.0 : (y >= T ? __builtin_huge_val() : T / (T - y));
 }
 
+// One thread per (scope, optimizer), in the output's order (consecutive
+// threads write consecutive elements); the thread of optimizer 0 also writes
+// the scope's active samples, its kernel totals and Eq. (3) at a root.
 template <bool BATCH>
 __global__ void __launch_bounds__(kEstThreads)
 k_speedup(EstArgs one, const EstArgs *__restrict__ many, const WorkItem *__restrict__ items) {
-  EST_ITEM(a.ns, lw) {
-    const uint32_t l = (uint32_t)lw;
+  EST_ITEM((uint64_t)a.ns * GPA_N_OPT, ew) {
+    const uint32_t l = (uint32_t)(ew / GPA_N_OPT), o = (uint32_t)(ew % GPA_N_OPT);
     const double *x = a.sub + (size_t)l * kNV;
     const double T = a.sub[(size_t)a.root_of[l] * kNV + 10];
     const double A = x[9];
-    a.active[l] = A;
-    for (int o = 0; o < GPA_N_OPT; ++o) {
-      const double M = x[o];
-      const double y = (o >= GPA_O_LOOP_UNROLLING) ? (A < M ? A : M) : M;
-      a.matched[(size_t)l * GPA_N_OPT + o] = M;
-      a.speedup[(size_t)l * GPA_N_OPT + o] = saturating_speedup(T, y);
+    const double M = x[o];
+    const double y = (o >= GPA_O_LOOP_UNROLLING) ? (A < M ? A : M) : M;
+    a.matched[ew] = M;
+    a.speedup[ew] = saturating_speedup(T, y);
+    if (o == 0) {
+      a.active[l] = A;
+      const bool root = a.scope_parent[l] == GPA_NONE;
+      a.kernel_T[l] = root ? T : 0.0;
+      a.kernel_L[l] = root ? T - A : 0.0;
+      for (int h = 0; h < 3; ++h)
+        a.eq3[(size_t)l * 3 + h] = root ? saturating_speedup(T, x[GPA_O_LOOP_UNROLLING + h]) : 0.0;
     }
-    const bool root = a.scope_parent[l] == GPA_NONE;
-    a.kernel_T[l] = root ? T : 0.0;
-    a.kernel_L[l] = root ? T - A : 0.0;
-    for (int h = 0; h < 3; ++h)
-      a.eq3[(size_t)l * 3 + h] = root ? saturating_speedup(T, x[GPA_O_LOOP_UNROLLING + h]) : 0.0;
   }
 }
 
@@ -652,7 +655,7 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &adv, uin
   L(k_seg_small<kNV, 3, 1, false>, gs, 1, nullptr);
   L(k_seg_chunks<kNV, 3, 1, false>, chunks(a.seg_chunks[3]), 1, nullptr);
   L(k_seg_combine<kNV, 3, 1, false>, combine(a.seg_chunks[3]), 1, nullptr);
-  L(k_speedup<false>, gs, 1, nullptr);
+  L(k_speedup<false>, grid_for((size_t)ns * GPA_N_OPT, kEstThreads, 8192), 1, nullptr);
   if (k && p.n_roots) {
     hipLaunchKernelGGL(k_topk_chunks<false>, dim3(std::max(p.tk_chunks, 1u)), dim3(kTopThreads), 0,
                        s, L.one, nullptr, nullptr);
@@ -668,7 +671,8 @@ void run_estimate_batch(const gpa_blame *const *b, gpa_advice *const *adv, uint3
   std::vector<EstArgs> args(count);
   // per-entry workgroups of each stage: scopes, chunks of each grouping and
   // their long segments, top-k chunks, kernel roots
-  std::vector<uint32_t> w_scope(count), w_ch[3], w_cb[3], w_tkc(count), w_tkf(count);
+  std::vector<uint32_t> w_scope(count), w_opt(count), w_ch[3], w_cb[3], w_tkc(count),
+      w_tkf(count);
   for (int g = 0; g < 3; ++g) {
     w_ch[g].resize(count);
     w_cb[g].resize(count);
@@ -682,6 +686,7 @@ void run_estimate_batch(const gpa_blame *const *b, gpa_advice *const *adv, uint3
     args[e] = est_args(p, *b[e], *adv[e], k, ar, sh.get());
     const EstArgs &a = args[e];
     w_scope[e] = tiles(p.n_scopes, kEstThreads);
+    w_opt[e] = tiles((uint64_t)p.n_scopes * GPA_N_OPT, kEstThreads);
     const uint32_t nc[3] = {a.seg_chunks[0], std::max(a.seg_chunks[1], a.seg_chunks[2]),
                             a.seg_chunks[3]};
     for (int g = 0; g < 3; ++g) {
@@ -692,7 +697,7 @@ void run_estimate_batch(const gpa_blame *const *b, gpa_advice *const *adv, uint3
     w_tkf[e] = (k && p.n_roots) ? p.n_roots : 0u;
   }
   BatchPlan plan(count);
-  const uint32_t q_scope = plan.add(w_scope);
+  const uint32_t q_scope = plan.add(w_scope), q_opt = plan.add(w_opt);
   uint32_t q_ch[3], q_cb[3];
   for (int g = 0; g < 3; ++g) {
     q_ch[g] = plan.add(w_ch[g]);
@@ -717,7 +722,7 @@ void run_estimate_batch(const gpa_blame *const *b, gpa_advice *const *adv, uint3
   run(k_seg_small<kNV, 3, 1, true>, q_scope, 1);
   run(k_seg_chunks<kNV, 3, 1, true>, q_ch[2], 1);
   run(k_seg_combine<kNV, 3, 1, true>, q_cb[2], 1);
-  run(k_speedup<true>, q_scope, 1);
+  run(k_speedup<true>, q_opt, 1);
   if (plan.blocks(q_tkc)) {
     hipLaunchKernelGGL(k_topk_chunks<true>, dim3(plan.blocks(q_tkc)), dim3(kTopThreads), 0, s,
                        EstArgs{}, L.many, plan.items(q_tkc));
