@@ -93,23 +93,18 @@ k_blame_dst(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *_
   BLAME_ITEM(j) {
     const uint32_t nbl = a.nbl;
     // the blamable reasons by slot, and the opcode classes each allows
+    // (slot q takes the lowest blamable reason left, so every slot has a
+    // fixed register; slots past the set read reason 0 and allow nothing)
     uint32_t rs[NB], allow[NB];
     {
-      uint32_t s = 0;
+      uint32_t m = a.blamable & 0xFFFu;
 #pragma unroll
-      for (int r = 0; r < 12; ++r) {
-        if (((a.blamable >> r) & 1u) && s < (uint32_t)NB) {
-          rs[s] = (uint32_t)r;
-          allow[s] = a.allowed[r];
-          ++s;
-        }
+      for (int q = 0; q < NB; ++q) {
+        const uint32_t r = m ? (uint32_t)__builtin_ctz(m) : 0u;
+        rs[q] = r;
+        allow[q] = m ? a.allowed[r] : 0u;
+        m &= m - 1u;
       }
-#pragma unroll
-      for (int q = 0; q < NB; ++q)
-        if ((uint32_t)q >= s) {
-          rs[q] = 0;
-          allow[q] = 0;
-        }
     }
     const uint32_t *C = a.counts + (size_t)j * 24;
     const uint32_t e0 = a.in_ptr[j], e1 = a.in_ptr[j + 1];
@@ -121,7 +116,10 @@ k_blame_dst(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *_
       Wp[q] = 0.0;
       any[q] = false;
     }
-    EdgeW first[kBlameU];
+    // with the sums of more than four reasons live, the kept edges would
+    // not fit in registers: the second pass then loads them again
+    constexpr bool kKeepFirst = NB <= 4;
+    EdgeW first[kKeepFirst ? kBlameU : 1];
     for (uint32_t base = e0; base < e1; base += kBlameU) {
       EdgeW w[kBlameU];
 #pragma unroll
@@ -136,14 +134,14 @@ k_blame_dst(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *_
           any[q] = any[q] || cand;
         }
       }
-      if (base == e0) {
+      if (kKeepFirst && base == e0) {
 #pragma unroll
         for (uint32_t u = 0; u < kBlameU; ++u) first[u] = w[u];
       }
     }
     for (uint32_t base = e0; base < e1; base += kBlameU) {
       EdgeW w[kBlameU];
-      if (base == e0) {
+      if (kKeepFirst && base == e0) {
 #pragma unroll
         for (uint32_t u = 0; u < kBlameU; ++u) w[u] = first[u];
       } else {
@@ -157,15 +155,16 @@ k_blame_dst(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *_
         double *sh = a.share + (size_t)e * 2 * nbl;
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
-          if ((uint32_t)q >= nbl) break;
-          const bool cand = w[u].kept && ((allow[q] >> w[u].cls) & 1u);
-          const bool by_path = (Wi[q] == 0.0);
-          const double wt = by_path ? w[u].wp : w[u].wi;
-          const double W = by_path ? Wp[q] : Wi[q];
+          if ((uint32_t)q < nbl) {
+            const bool cand = w[u].kept && ((allow[q] >> w[u].cls) & 1u);
+            const bool by_path = (Wi[q] == 0.0);
+            const double wt = by_path ? w[u].wp : w[u].wi;
+            const double W = by_path ? Wp[q] : Wi[q];
 #pragma unroll
-          for (int l = 0; l < 2; ++l) {
-            const uint32_t S = C[rs[q] * 2 + l];
-            sh[q * 2 + l] = (cand && S != 0) ? (double)S * wt / W : 0.0;
+            for (int l = 0; l < 2; ++l) {
+              const uint32_t S = C[rs[q] * 2 + l];
+              sh[q * 2 + l] = (cand && S != 0) ? (double)S * wt / W : 0.0;
+            }
           }
         }
       }
@@ -193,15 +192,14 @@ k_blame_src(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *_
     const uint32_t *__restrict__ out_perm = a.out_perm;
     const uint8_t *__restrict__ e_flags = a.e_flags;
     const double *__restrict__ share = a.share;
-    uint32_t rs[NB];   // the blamable reasons by slot
+    uint32_t rs[NB];   // the blamable reasons by slot (12 past the set)
     {
-      uint32_t sl = 0;
+      uint32_t m = a.blamable & 0xFFFu;
 #pragma unroll
-      for (int r = 0; r < 12; ++r)
-        if (((a.blamable >> r) & 1u) && sl < (uint32_t)NB) rs[sl++] = (uint32_t)r;
-#pragma unroll
-      for (int q = 0; q < NB; ++q)
-        if ((uint32_t)q >= sl) rs[q] = 12;
+      for (int q = 0; q < NB; ++q) {
+        rs[q] = m ? (uint32_t)__builtin_ctz(m) : 12u;
+        m &= m - 1u;
+      }
     }
     double acc[2 * NB];
 #pragma unroll

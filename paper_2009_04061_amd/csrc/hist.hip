@@ -531,12 +531,16 @@ __global__ void k_hoverflow(const uint32_t *__restrict__ ov_keys, const uint32_t
 // ------------------------------------------------------------ hot-set path
 // For programs of up to kHotMaxPCs instructions, a sample of the records
 // picks a hot set of at most kHotH PCs.  One read of the records adds every
-// hot record into a workgroup-private LDS copy of the hot bins and appends
-// every other (cold) record as a 4-byte key to the workgroup's own slice of
-// a key array; no device atomics.  The workgroup then sorts its cold keys by
-// bucket of kColdPCs PCs within tiles, and a last launch sums the hot copies and
-// counts each bucket's cold keys in LDS.  Hot and cold PCs are disjoint, so
-// every bin is written exactly once.
+// hot record into a workgroup-private LDS copy of the hot bins (two 16-bit
+// counters per word, as in the direct mode) and appends every other (cold)
+// record as a 4-byte key to the workgroup's own slice of a key array.  A hot
+// counter that wraps is caught from the atomic's returned value and its
+// 65,536 (less the carry it pushed into its neighbour) added to a
+// per-profile correction array: the only device atomics, at most a few per
+// 2^16 records.  The workgroup then sorts its cold keys by bucket of
+// kColdPCs PCs within tiles, and a last launch sums the packed hot copies
+// with the corrections and counts each bucket's cold keys in LDS.  Hot and
+// cold PCs are disjoint, so every bin is written exactly once.
 //   k_hot_select  one workgroup: 16-bit LDS counters (one per PC, or per
 //                 pair of PCs beyond 65,536) over kSelSample records in
 //                 evenly spread runs; a counter that reaches kSelMin makes
@@ -547,21 +551,27 @@ __global__ void k_hoverflow(const uint32_t *__restrict__ ov_keys, const uint32_t
 //                 then sorts its cold keys by bucket in tiles of kColdTile;
 //   k_hot_finish  cold buckets, hot-bin sums and the totals.
 constexpr int kHotThreads = 1024;
-constexpr uint32_t kHotH = 512;                  // hot PCs at most
-constexpr uint32_t kHotTBits = 11;
+constexpr uint32_t kHotH = 1024;                 // hot PCs at most
+constexpr uint32_t kHotTBits = 12;
 constexpr uint32_t kHotT = 1u << kHotTBits;      // lookup slots (load <= 1/4)
-constexpr uint32_t kHotBins = kHotH * 24;
+constexpr uint32_t kHotBins = kHotH * 24;        // hot bins (the merge's columns)
+constexpr uint32_t kHotWords = kHotH * 12;       // packed: two 16-bit counters per word
 constexpr uint32_t kHotMaxPCs = 1u << 17;        // cold keys pc << 5 | bin fit 22 bits
-static_assert(kHotH <= 512u && kHotMaxPCs <= (1u << 22), "table entries pc | id << 22 below 2^31");
+// table entries: pc | id << kPcBits; the pc field of an empty slot (all
+// ones) is above every pc, and an id field of all ones marks a claim
+constexpr uint32_t kPcBits = 18;
+constexpr uint32_t kPcMask = (1u << kPcBits) - 1;
+constexpr uint32_t kIdClaim = 0xFFFFFFFFu >> kPcBits;
+static_assert(kHotMaxPCs < kPcMask && kHotH < kIdClaim, "table entry fields");
 constexpr uint32_t kColdShift = 8;
 constexpr uint32_t kColdPCs = 1u << kColdShift;  // PCs per cold bucket
 constexpr uint32_t kColdBins = kColdPCs * 24;
 constexpr uint32_t kColdMaxBuckets = kHotMaxPCs / kColdPCs;
 constexpr uint32_t kColdTile = 16384;            // cold keys per sorted tile
-constexpr uint32_t kSelSample = 16384;           // sampled records
+constexpr uint32_t kSelSample = 32768;           // sampled records
 constexpr uint32_t kSelRun = 128;                // records per sampled run
 constexpr uint32_t kSelCounters = 1u << 16;      // 16-bit, two per word
-constexpr uint32_t kSelMin = 3;                  // sampled count that makes a PC hot
+constexpr uint32_t kSelMin = 2;                  // sampled count that makes a PC hot
 constexpr int kHotUnroll = 4;                    // 16-byte loads per thread per step
 constexpr uint32_t kHotStep = kHotThreads * kHotUnroll * 2;   // records per step
 constexpr uint32_t kHotGrid = 256;               // workgroups of the pass at most
@@ -570,7 +580,7 @@ constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 static_assert(kColdMaxBuckets <= (uint32_t)kHotThreads, "one cold bucket per thread in scans");
 static_assert(kSelSample < 65536u, "16-bit sample counters");
 
-// a hot PC sits in one of its two slots (entry pc | id << 22), given by two
+// a hot PC sits in one of its two slots (entry pc | id << kPcBits), given by two
 // multiplicative hashes of the pc (< 2^17 on this path) taken as 24-bit
 // products, which issue at full rate where a 32-bit multiply takes four
 // cycles (HIP's __umul24 returns int: the product is made unsigned before
@@ -614,7 +624,7 @@ static_assert(2 * (kDirectMaxPer >> 16) + 1 <= kMaxEvents, "event log bound");
 //             scan scratch;
 //   direct:   packed counters, wrap marks (one bit per word), the event log,
 //             its count and reduction scratch.
-constexpr uint32_t kHotPoolWords = kHotBins + kHotT + kColdTile + kColdMaxBuckets +
+constexpr uint32_t kHotPoolWords = kHotWords + kHotT + kColdTile + kColdMaxBuckets +
                                    kHotThreads / kWave + 1;
 constexpr uint32_t kDirectPoolWords = kDirectWords + kDirectMarks + kMaxEvents + 1 +
                                       2 * (kHotThreads / kWave);
@@ -634,6 +644,7 @@ struct HotArgs {
   uint32_t n_merge, merge_slices;   // hot-bin merge workgroups (0 when G = 1) and their slices
   uint32_t direct, pad;             // direct mode: every bin in LDS, no selection, no cold keys
   uint32_t *hot_tab, *hot_pc, *n_hot, *partial, *cold, *cold_sorted, *tile_off, *n_cold;
+  uint32_t *corr;   // hot mode: kHotBins wrap corrections, cleared by the selection
   TileTotals *wtot;
   uint32_t *counts;
   unsigned long long *totals;
@@ -672,18 +683,27 @@ k_hot_select(HotArgs one, const HotArgs *__restrict__ many, const WorkItem *__re
   __shared__ uint32_t s_nsel;
   const unsigned tid = threadIdx.x;
   const uint32_t sh = n_instr > kSelCounters ? 1u : 0u;   // counter = pc >> sh
-  constexpr uint32_t kPer = kSelSample / kHotThreads;
+  // the sample in rounds of kPer records per thread (a round's loads issued
+  // together, held in registers)
+  constexpr uint32_t kPer = 16;
+  constexpr uint32_t kRounds = kSelSample / (kPer * kHotThreads);
+  static_assert(kRounds * kPer * kHotThreads == kSelSample, "whole rounds");
   uint64_t r[kPer];
+  auto load = [&](uint32_t round) {
 #pragma unroll
-  for (uint32_t j = 0; j < kPer; ++j) {
-    const uint32_t k = j * kHotThreads + tid;
-    const uint64_t i = n <= kSelSample ? k : (k / kSelRun) * run_stride + k % kSelRun;
-    r[j] = i < n ? rec[i] : ~0ull;
-  }
+    for (uint32_t j = 0; j < kPer; ++j) {
+      const uint32_t k = (round * kPer + j) * kHotThreads + tid;
+      const uint64_t i = n <= kSelSample ? k : (k / kSelRun) * run_stride + k % kSelRun;
+      r[j] = i < n ? rec[i] : ~0ull;
+    }
+  };
+  load(0);
   for (uint32_t k = tid; k < kSelCounters / 2; k += kHotThreads) cnt[k] = 0;
   for (uint32_t k = tid; k < kHotT; k += kHotThreads) tab[k] = kEmpty;
   if (tid == 0) s_nsel = 0;
   __syncthreads();
+  for (uint32_t round = 0; round < kRounds; ++round) {
+  if (round > 0) load(round);
   // a rolled loop: this kernel runs once per call, so its code is fetched
   // cold and a short body costs less than unrolled copies
 #pragma unroll 1
@@ -694,7 +714,7 @@ k_hot_select(HotArgs one, const HotArgs *__restrict__ many, const WorkItem *__re
     if (old + 1 != kSelMin) continue;
     // this sample made counter c reach kSelMin: its PCs become hot
     for (uint32_t pc = c << sh; pc < ((c + 1) << sh) && pc < n_instr; ++pc) {
-      const uint32_t prov = pc | (kHotH << 22);   // claimed, not yet numbered
+      const uint32_t prov = pc | (kIdClaim << kPcBits);   // claimed, not yet numbered
       uint32_t slot = hot_slot1(pc);
       if (atomicCAS(&tab[slot], kEmpty, prov) != kEmpty) {
         slot = hot_slot2(pc);
@@ -703,15 +723,17 @@ k_hot_select(HotArgs one, const HotArgs *__restrict__ many, const WorkItem *__re
       const uint32_t id = atomicAdd(&s_nsel, 1u);
       if (id < kHotH) {
         hot_pc[id] = pc;
-        tab[slot] = pc | (id << 22);
+        tab[slot] = pc | (id << kPcBits);
       } else {
         tab[slot] = kEmpty;   // the hot set is full: stays cold
       }
     }
   }
+  }
   __syncthreads();
   for (uint32_t k = tid; k < kHotT; k += kHotThreads) hot_tab[k] = tab[k];
   if (tid == 0) *n_hot = min(s_nsel, kHotH);
+  for (uint32_t k = tid; k < kHotBins; k += kHotThreads) a.corr[k] = 0;
 }
 
 // one step's records of a thread: FULL steps lie wholly below n (16-byte
@@ -790,6 +812,20 @@ __device__ void sort_cold_tile(uint32_t n_cb, uint64_t base, uint32_t m, const u
 // workgroup sorts its cold keys by bucket in tiles of kColdTile: tile t's
 // bucket starts go to tile_off[(w T + t) (n_cb + 1) + b] (entry n_cb: the
 // end).
+// a hot counter wrapped (rare): the word's low counter is bin 2w of the hot
+// bins, its high counter bin 2w + 1.  A low wrap loses 65,536 from the low
+// counter and pushed a carry into the high one (which also wrapped if it
+// held 0xFFFF); a high wrap loses 65,536 from the high counter.
+__device__ __attribute__((noinline)) void hot_wrap(uint32_t *corr, uint32_t w, uint32_t sh,
+                                                   uint32_t old) {
+  if (sh == 0) {
+    atomicAdd(&corr[2 * w], 65536u);
+    atomicAdd(&corr[2 * w + 1], ((old >> 16) == 0xFFFFu ? 65536u : 0u) - 1u);
+  } else {
+    atomicAdd(&corr[2 * w + 1], 65536u);
+  }
+}
+
 // a direct-mode counter wrapped (rare): log it and mark its word.  A low
 // counter's wrap carried 1 into the high counter, which wrapped as well when
 // it held 0xFFFF; entries are word << 1 | (1 for a high-counter wrap).
@@ -938,8 +974,8 @@ k_hot_pass(HotArgs one, const HotArgs *__restrict__ many, const WorkItem *__rest
   uint32_t *__restrict__ tile_off = a.tile_off;
   uint32_t *__restrict__ n_cold = a.n_cold;
   TileTotals *__restrict__ wtot = a.wtot;
-  uint32_t *bins = pool;                      // [kHotBins]
-  uint32_t *tab = bins + kHotBins;            // [kHotT]
+  uint32_t *bins = pool;                      // [kHotWords] packed hot counters
+  uint32_t *tab = bins + kHotWords;           // [kHotT]
   uint32_t *sorted = tab + kHotT;             // [kColdTile]
   uint32_t *bc = sorted + kColdTile;          // [kColdMaxBuckets]
   uint32_t *scan_tmp = bc + kColdMaxBuckets;  // [kHotThreads / kWave + 1]
@@ -955,7 +991,7 @@ k_hot_pass(HotArgs one, const HotArgs *__restrict__ many, const WorkItem *__rest
   };
   issue(r0, va);
   issue(r0 + kHotStep, vb);
-  for (uint32_t k = tid; k < kHotBins; k += kHotThreads) bins[k] = 0;
+  for (uint32_t k = tid; k < kHotWords; k += kHotThreads) bins[k] = 0;
   for (uint32_t k = tid; k < kHotT; k += kHotThreads) tab[k] = hot_tab[k];
   if (tid == 0) {
     s_cur = 0;
@@ -978,9 +1014,14 @@ k_hot_pass(HotArgs one, const HotArgs *__restrict__ many, const WorkItem *__rest
       bool ok = pc < n_instr && hi < 0x200u && (hi & 0xFFu) < 12u;   // rec_valid
       if (!FULL) ok = ok && i0 + 2 * ((uint64_t)(q / 2) * kHotThreads + tid) + (q & 1) < r1;
       const uint32_t e1 = tab[hot_slot1(pc)], e2 = tab[hot_slot2(pc)];
-      const uint32_t e = (e1 & 0x3FFFFFu) == pc ? e1 : e2;   // an empty slot matches no pc
-      const bool hot = ok && (e & 0x3FFFFFu) == pc;
-      if (hot) atomicAdd(&bins[(e >> 22) * 24u + (hi & 0xFFu) * 2u + ((hi >> 8) & 1u)], 1u);
+      const uint32_t e = (e1 & kPcMask) == pc ? e1 : e2;   // an empty slot matches no pc
+      const bool hot = ok && (e & kPcMask) == pc;
+      if (hot) {
+        const uint32_t w = (e >> kPcBits) * 12u + (hi & 0xFFu);
+        const uint32_t sh = (hi >> 4) & 16u;   // the latency bit selects the high counter
+        const uint32_t old = atomicAdd(&bins[w], 1u << sh);
+        if (((old >> sh) & 0xFFFFu) == 0xFFFFu) hot_wrap(a.corr, w, sh, old);
+      }
       w_valid += (uint32_t)__popcll(__ballot(ok));
       w_lat += (uint32_t)__popcll(__ballot(ok && ((hi >> 8) & 1u)));
       cmask |= (ok && !hot) ? 1u << q : 0u;
@@ -1026,14 +1067,10 @@ k_hot_pass(HotArgs one, const HotArgs *__restrict__ many, const WorkItem *__rest
     atomicAdd(&s_lat, w_lat);
   }
   __syncthreads();
-  if (a.G == 1) {
-    // the only workgroup: its hot bins are the counts (no merge follows)
-    const uint32_t nh = *a.n_hot;
-    for (uint32_t k = tid; k < nh * 24u; k += kHotThreads)
-      a.counts[(size_t)a.hot_pc[k / 24u] * 24u + k % 24u] = bins[k];
-  } else {
-    uint32_t *dst = a.partial + (size_t)wg * kHotBins;
-    for (uint32_t k = tid; k < kHotBins; k += kHotThreads) dst[k] = bins[k];
+  {
+    // the packed hot counters, merged with the corrections by the finish
+    uint32_t *dst = a.partial + (size_t)wg * kHotWords;
+    for (uint32_t k = tid; k < kHotWords; k += kHotThreads) dst[k] = bins[k];
   }
   if (tid == 0) {
     TileTotals t;
@@ -1162,19 +1199,28 @@ k_hot_finish(HotArgs one, const HotArgs *__restrict__ many, const WorkItem *__re
     // kHotThreads / S columns of the partial tables (hot bins, or in direct
     // mode every bin); the pass's workgroups split over S slices (S a power
     // of two, at most 16, so a thread sums at most kHotGrid / 16 partials)
+    // (hot mode: the partials are the packed 16-bit counters, column col
+    // the half col & 1 of word col / 2, plus the column's wrap correction)
     const bool direct = a.direct != 0;
     const uint32_t S = a.merge_slices, cols = kHotThreads / S;
     const uint32_t c = tid % cols, sl = tid / cols;
     const uint32_t col = (bid - n_cb) * cols + c;
-    const uint32_t width = direct ? n_instr * 24u : kHotBins;
     const bool live = col < (direct ? n_instr : n_hot) * 24u;
     uint32_t sum = 0;
+    if (direct) {
+      const uint32_t width = n_instr * 24u;
 #pragma unroll 4
-    for (uint32_t w = sl; w < G; w += S) sum += live ? partial[(size_t)w * width + col] : 0u;
+      for (uint32_t w = sl; w < G; w += S) sum += live ? partial[(size_t)w * width + col] : 0u;
+    } else {
+      const uint32_t word = col >> 1, sh = 16u * (col & 1u);
+#pragma unroll 4
+      for (uint32_t w = sl; w < G; w += S)
+        sum += live ? (partial[(size_t)w * kHotWords + word] >> sh) & 0xFFFFu : 0u;
+    }
     bins[sl * cols + c] = sum;
     __syncthreads();
     if (sl == 0 && live) {
-      uint32_t t = 0;
+      uint32_t t = direct ? 0u : a.corr[col];
       for (uint32_t k = 0; k < S; ++k) t += bins[k * cols + c];
       counts[direct ? (size_t)col : (size_t)hot_pc[col / 24u] * 24u + col % 24u] = t;
     }
@@ -1254,7 +1300,9 @@ static HotShape hot_shape(uint32_t n_instr, uint64_t n, uint64_t per_min = 0) {
   h.merge_slices = S;
   const uint32_t cols = kHotThreads / S;
   const uint32_t live_cols = (h.direct ? n_instr : std::min<uint32_t>(kHotH, n_instr)) * 24u;
-  h.n_merge = h.G > 1 ? (live_cols + cols - 1) / cols : 0;
+  // direct mode merges partials only when there are several; the hot bins
+  // are always merged (packed counters and corrections to exact counts)
+  h.n_merge = (h.G > 1 || !h.direct) ? (live_cols + cols - 1) / cols : 0;
   return h;
 }
 
@@ -1262,9 +1310,10 @@ static size_t blk256(size_t bytes) { return (bytes + 255) / 256 * 256; }
 
 // element counts of a profile's scratch pieces, in the order hot_args takes
 // them: lookup table, hot PCs, hot count, partial tables, cold keys, sorted
-// cold keys, tile offsets, cold counts (u32 each), then the range totals
+// cold keys, tile offsets, cold counts, wrap corrections (u32 each), then
+// the range totals
 struct HotPieces {
-  size_t u32[8];
+  size_t u32[9];
   size_t totals;
 };
 static HotPieces hot_pieces(const HotShape &h, uint32_t n_instr, uint64_t n) {
@@ -1273,11 +1322,12 @@ static HotPieces hot_pieces(const HotShape &h, uint32_t n_instr, uint64_t n) {
   q.u32[0] = d ? 1 : kHotT;
   q.u32[1] = d ? 1 : kHotH;
   q.u32[2] = 1;
-  q.u32[3] = h.G > 1 ? (size_t)h.G * (d ? (size_t)n_instr * 24 : kHotBins) : 1;
+  q.u32[3] = d ? (h.G > 1 ? (size_t)h.G * n_instr * 24 : 1) : (size_t)h.G * kHotWords;
   q.u32[4] = d ? 1 : n;
   q.u32[5] = d ? 1 : n;
   q.u32[6] = d ? 1 : (size_t)h.G * h.T * (h.n_cb + 1);
   q.u32[7] = h.G;
+  q.u32[8] = d ? 1 : kHotBins;
   q.totals = h.G;
   return q;
 }
@@ -1320,6 +1370,7 @@ static HotArgs hot_args(const HotShape &h, const uint64_t *rec, uint64_t n, uint
   a.cold_sorted = ar.get<uint32_t>(q.u32[5]);
   a.tile_off = ar.get<uint32_t>(q.u32[6]);
   a.n_cold = ar.get<uint32_t>(q.u32[7]);
+  a.corr = ar.get<uint32_t>(q.u32[8]);
   a.wtot = ar.get<TileTotals>(q.totals);
   a.counts = counts;
   a.totals = totals;
