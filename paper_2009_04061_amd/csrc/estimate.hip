@@ -227,10 +227,23 @@ k_seg_small(EstArgs one, const EstArgs *__restrict__ many, const WorkItem *__res
     const SegView S = pick_view<G0, NG>(a);
     const uint32_t b0 = seg_lo<G0>(S, l), b1 = seg_hi<G0>(S, l);
     if (b1 - b0 <= kSmallSeg) {
+      // (an instruction's contribution reads 30 values: two at a time)
+      constexpr int kSmallU = G0 == 0 ? 2 : 4;
       double v[W];
 #pragma unroll
       for (int q = 0; q < W; ++q) v[q] = 0.0;
-      for (uint32_t i = b0; i < b1; ++i) {
+      // kSmallU elements' loads issued together, added in element order
+      uint32_t i = b0;
+      for (; i + kSmallU <= b1; i += kSmallU) {
+        double t[kSmallU][W];
+#pragma unroll
+        for (int u = 0; u < kSmallU; ++u) seg_elem<W, G0>(a, S, i + u, t[u]);
+#pragma unroll
+        for (int u = 0; u < kSmallU; ++u)
+#pragma unroll
+          for (int q = 0; q < W; ++q) v[q] += t[u][q];
+      }
+      for (; i < b1; ++i) {
         double t[W];
         seg_elem<W, G0>(a, S, i, t);
 #pragma unroll

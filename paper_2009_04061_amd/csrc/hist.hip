@@ -576,6 +576,10 @@ constexpr int kHotUnroll = 4;                    // 16-byte loads per thread per
 constexpr uint32_t kHotStep = kHotThreads * kHotUnroll * 2;   // records per step
 constexpr uint32_t kHotGrid = 256;               // workgroups of the pass at most
 constexpr uint32_t kMaxRuns = 4096;              // cold runs listed at a time
+constexpr uint32_t kMergeSlice = 16;             // partials one merging thread sums at most
+constexpr uint32_t kMergeWords = 4;              // words one merging thread takes
+static_assert(kHotGrid / kMergeSlice <= (uint32_t)kHotThreads && 2 * kHotThreads <= kColdPCs * 24,
+              "merge slices and their LDS sums");
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 static_assert(kColdMaxBuckets <= (uint32_t)kHotThreads, "one cold bucket per thread in scans");
 static_assert(kSelSample < 65536u, "16-bit sample counters");
@@ -1196,33 +1200,60 @@ k_hot_finish(HotArgs one, const HotArgs *__restrict__ many, const WorkItem *__re
       if (!((hot_mark[pl / 32] >> (pl % 32)) & 1u)) counts[(size_t)pc0 * 24u + k] = bins[k];
     }
   } else if (bid < n_cb + n_merge) {
-    // kHotThreads / S columns of the partial tables (hot bins, or in direct
-    // mode every bin); the pass's workgroups split over S slices (S a power
-    // of two, at most 16, so a thread sums at most kHotGrid / 16 partials)
-    // (hot mode: the partials are the packed 16-bit counters, column col
-    // the half col & 1 of word col / 2, plus the column's wrap correction)
+    // the partial tables merged by word: a thread takes the two counters of
+    // one word of the packed hot bins (or, in direct mode, one (lo, hi)
+    // pair of the exact partials), kMergeWords words kHotThreads / S apart;
+    // the pass's workgroups split over S slices (S a power of two, so that a
+    // slice holds at most kMergeSlice partials), summed across slices in
+    // LDS, and the hot bins' wrap corrections added
     const bool direct = a.direct != 0;
-    const uint32_t S = a.merge_slices, cols = kHotThreads / S;
-    const uint32_t c = tid % cols, sl = tid / cols;
-    const uint32_t col = (bid - n_cb) * cols + c;
-    const bool live = col < (direct ? n_instr : n_hot) * 24u;
-    uint32_t sum = 0;
-    if (direct) {
-      const uint32_t width = n_instr * 24u;
+    const uint32_t S = a.merge_slices, wpb = kHotThreads / S;
+    const uint32_t c = tid % wpb, sl = tid / wpb;
+    const uint32_t n_words = (direct ? n_instr : n_hot) * 12u;
+    const size_t width = direct ? (size_t)n_instr * 24u : (size_t)kHotWords;
+    const uint32_t base = (bid - n_cb) * wpb * kMergeWords;
+    for (uint32_t k = 0; k < kMergeWords; ++k) {
+      const uint32_t word = base + k * wpb + c;
+      const bool live = word < n_words;
+      uint32_t lo = 0, hi = 0;
+      if (live) {
+        if (direct) {
 #pragma unroll 4
-      for (uint32_t w = sl; w < G; w += S) sum += live ? partial[(size_t)w * width + col] : 0u;
-    } else {
-      const uint32_t word = col >> 1, sh = 16u * (col & 1u);
+          for (uint32_t w = sl; w < G; w += S) {
+            const uint2 x = *(const uint2 *)(partial + (size_t)w * width + 2u * word);
+            lo += x.x;
+            hi += x.y;
+          }
+        } else {
 #pragma unroll 4
-      for (uint32_t w = sl; w < G; w += S)
-        sum += live ? (partial[(size_t)w * kHotWords + word] >> sh) & 0xFFFFu : 0u;
-    }
-    bins[sl * cols + c] = sum;
-    __syncthreads();
-    if (sl == 0 && live) {
-      uint32_t t = direct ? 0u : a.corr[col];
-      for (uint32_t k = 0; k < S; ++k) t += bins[k * cols + c];
-      counts[direct ? (size_t)col : (size_t)hot_pc[col / 24u] * 24u + col % 24u] = t;
+          for (uint32_t w = sl; w < G; w += S) {
+            const uint32_t x = partial[(size_t)w * width + word];
+            lo += x & 0xFFFFu;
+            hi += x >> 16;
+          }
+        }
+      }
+      if (S > 1) {
+        bins[sl * wpb + c] = lo;
+        bins[kHotThreads + sl * wpb + c] = hi;
+        __syncthreads();
+        if (sl == 0) {
+          for (uint32_t q = 1; q < S; ++q) {
+            lo += bins[q * wpb + c];
+            hi += bins[kHotThreads + q * wpb + c];
+          }
+        }
+        __syncthreads();
+      }
+      if (sl == 0 && live) {
+        if (direct) {
+          *(uint2 *)(counts + 2u * (size_t)word) = make_uint2(lo, hi);
+        } else {
+          const uint2 cr = *(const uint2 *)(a.corr + 2u * word);
+          const size_t at = (size_t)hot_pc[word / 12u] * 24u + 2u * (word % 12u);
+          *(uint2 *)(counts + at) = make_uint2(lo + cr.x, hi + cr.y);
+        }
+      }
     }
   } else {
     unsigned long long v = 0, l = 0, d = 0;
@@ -1282,7 +1313,9 @@ struct HotShape {
 };
 static HotShape hot_shape(uint32_t n_instr, uint64_t n, uint64_t per_min = 0) {
   HotShape h;
-  h.direct = hot_direct(n_instr);
+  // (a profile of more than kHotGrid ranges of kDirectMaxPer records takes
+  // the hot-set path, whose ranges have no bound)
+  h.direct = hot_direct(n_instr) && n <= (uint64_t)kHotGrid * kDirectMaxPer;
   uint64_t per = std::max<uint64_t>((n + kHotGrid - 1) / kHotGrid, per_min);
   if (h.direct) {
     per = std::max<uint64_t>(per, (per_min ? 960ull : 96ull) * n_instr);
@@ -1291,18 +1324,20 @@ static HotShape hot_shape(uint32_t n_instr, uint64_t n, uint64_t per_min = 0) {
   h.per = (per + 2 * kWave - 1) / (2 * kWave) * (2 * kWave);
   if (h.per == 0) h.per = 2 * kWave;
   h.G = (uint32_t)((n + h.per - 1) / h.per);
+  if (h.G > kHotGrid) fail(GPA_E_DEVICE, "histogram shape: %u ranges", h.G);
   h.n_cb = h.direct ? 0u : (n_instr + kColdPCs - 1) / kColdPCs;
   h.T = h.direct ? 0u : (uint32_t)((h.per + kColdTile - 1) / kColdTile);   // tiles per workgroup
   h.run_stride = n > kSelSample ? (n - kSelRun) / (kSelSample / kSelRun - 1) : 0;
-  // merge: S slices of the G partials, kHotThreads / S columns per workgroup
+  // merge: S slices of at most kMergeSlice of the G partials, kHotThreads / S
+  // threads per slice, kMergeWords words per thread
   uint32_t S = 1;
-  while (S < h.G && S < 16) S <<= 1;
+  while (S * kMergeSlice < h.G) S <<= 1;
   h.merge_slices = S;
-  const uint32_t cols = kHotThreads / S;
-  const uint32_t live_cols = (h.direct ? n_instr : std::min<uint32_t>(kHotH, n_instr)) * 24u;
+  const uint32_t words_per_wg = kHotThreads / S * kMergeWords;
+  const uint32_t live_words = (h.direct ? n_instr : std::min<uint32_t>(kHotH, n_instr)) * 12u;
   // direct mode merges partials only when there are several; the hot bins
   // are always merged (packed counters and corrections to exact counts)
-  h.n_merge = (h.G > 1 || !h.direct) ? (live_cols + cols - 1) / cols : 0;
+  h.n_merge = (h.G > 1 || !h.direct) ? (live_words + words_per_wg - 1) / words_per_wg : 0;
   return h;
 }
 
@@ -1386,12 +1421,21 @@ static void hot_blocks(const HotShape &h, uint32_t &n_sel, uint32_t &n_pass, uin
   n_fin = (h.direct && h.G == 1) ? 0u : h.n_cb + h.n_merge + 1;
 }
 
+// the selection's dynamic LDS limit, set once per device
 static void set_select_lds() {
+  static std::mutex mu;
+  static std::vector<bool> done;
+  int dev = 0;
+  GPA_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  if ((size_t)dev < done.size() && done[dev]) return;
   const int lds_sel = (int)(kSelLdsWords * 4);
   GPA_HIP(hipFuncSetAttribute((const void *)k_hot_select<false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_sel));
   GPA_HIP(hipFuncSetAttribute((const void *)k_hot_select<true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_sel));
+  if (done.size() <= (size_t)dev) done.resize((size_t)dev + 1, false);
+  done[dev] = true;
 }
 
 static bool run_hist_hot(const gpa_program &p, const uint64_t *rec, uint64_t n, bool vec,
@@ -1468,14 +1512,17 @@ static void prepare_hist_batch(HistBatch &hb, const HistEntry *e, uint32_t count
   hb.plan.expand(s);
 }
 
-static void launch_hist_batch(const HistBatch &hb, hipStream_t s) {
+static void launch_hist_select(const HistBatch &hb, hipStream_t s) {
+  if (!hb.plan.blocks(hb.q_sel)) return;
   HotArgs none{};
-  if (hb.plan.blocks(hb.q_sel)) {
-    set_select_lds();
-    hipLaunchKernelGGL(k_hot_select<true>, dim3(hb.plan.blocks(hb.q_sel)), dim3(kHotThreads),
-                       kSelLdsWords * 4, s, none, hb.d_args, hb.plan.items(hb.q_sel));
-    GPA_LAUNCH_CHECK();
-  }
+  set_select_lds();
+  hipLaunchKernelGGL(k_hot_select<true>, dim3(hb.plan.blocks(hb.q_sel)), dim3(kHotThreads),
+                     kSelLdsWords * 4, s, none, hb.d_args, hb.plan.items(hb.q_sel));
+  GPA_LAUNCH_CHECK();
+}
+
+static void launch_hist_pass_finish(const HistBatch &hb, hipStream_t s) {
+  HotArgs none{};
   hipLaunchKernelGGL((k_hot_pass<true, true>), dim3(hb.plan.blocks(hb.q_pass)), dim3(kHotThreads),
                      0, s, none, hb.d_args, hb.plan.items(hb.q_pass));
   GPA_LAUNCH_CHECK();
@@ -1486,63 +1533,14 @@ static void launch_hist_batch(const HistBatch &hb, hipStream_t s) {
   }
 }
 
-// A large batch is split into two halves of about equal records, each
-// launched on a stream of its own (the caller's and a side stream, joined
-// by events before the call's next work on the caller's stream): one half's
-// latency-bound selection and finish then run beside the other half's
-// streaming pass instead of after it.
-constexpr uint32_t kSplitMinEntries = 8;
-constexpr uint64_t kSplitMinRecords = 1ull << 24;
-
-namespace {
-struct SyncEvent {
-  hipEvent_t e = nullptr;
-  SyncEvent() { GPA_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming)); }
-  ~SyncEvent() {
-    if (e) (void)hipEventDestroy(e);
-  }
-  SyncEvent(const SyncEvent &) = delete;
-  SyncEvent &operator=(const SyncEvent &) = delete;
-};
-}  // namespace
-
 void run_hist_batch(const HistEntry *e, uint32_t count, uint64_t per, hipStream_t s, Arena &ar,
                     PhaseTimer *t) {
   if (count == 0) return;
-  uint64_t total = 0;
-  for (uint32_t k = 0; k < count; ++k) total += e[k].n;
-  if (count < kSplitMinEntries || total < kSplitMinRecords) {
-    HistBatch hb(count);
-    prepare_hist_batch(hb, e, count, per, s, ar);
-    if (t) t->begin(kPhaseHist, s);
-    launch_hist_batch(hb, s);
-    if (t) t->end(s);
-    return;
-  }
-  // largest first onto the lighter half
-  std::vector<uint32_t> idx(count);
-  for (uint32_t k = 0; k < count; ++k) idx[k] = k;
-  std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return e[x].n > e[y].n; });
-  std::vector<HistEntry> half[2];
-  uint64_t load[2] = {0, 0};
-  for (uint32_t k : idx) {
-    const int h = load[0] <= load[1] ? 0 : 1;
-    half[h].push_back(e[k]);
-    load[h] += e[k].n;
-  }
-  HistBatch h0((uint32_t)half[0].size()), h1((uint32_t)half[1].size());
-  prepare_hist_batch(h0, half[0].data(), (uint32_t)half[0].size(), per, s, ar);
-  prepare_hist_batch(h1, half[1].data(), (uint32_t)half[1].size(), per, s, ar);
-  hipStream_t s2 = side_stream(1);
-  ar.add_stream(s2);
-  SyncEvent fork, join;
+  HistBatch hb(count);
+  prepare_hist_batch(hb, e, count, per, s, ar);
   if (t) t->begin(kPhaseHist, s);
-  GPA_HIP(hipEventRecord(fork.e, s));
-  GPA_HIP(hipStreamWaitEvent(s2, fork.e, 0));
-  launch_hist_batch(h1, s2);
-  launch_hist_batch(h0, s);
-  GPA_HIP(hipEventRecord(join.e, s2));
-  GPA_HIP(hipStreamWaitEvent(s, join.e, 0));
+  launch_hist_select(hb, s);
+  launch_hist_pass_finish(hb, s);
   if (t) t->end(s);
 }
 
@@ -1601,7 +1599,8 @@ uint64_t batch_records_per_workgroup(const HistEntry *e, uint32_t count, hipStre
         HistBatch hb(count);
         prepare_hist_batch(hb, e, count, per, s, trial);
         GPA_HIP(hipEventRecord(a, s));
-        launch_hist_batch(hb, s);
+        launch_hist_select(hb, s);
+        launch_hist_pass_finish(hb, s);
         GPA_HIP(hipEventRecord(b, s));
         GPA_HIP(hipEventSynchronize(b));
         float ms = 0.f;
