@@ -127,39 +127,66 @@ def summarize_traffic(fetch_dir, write_dir, copy_mb, out_path, steps):
 
 def summarize_kernels(trace_dir, out_path, steps, command):
     """A markdown table of the batched step's kernels from a rocprofv3
-    --kernel-trace --stats run (CSV output) of this script: per kernel, the
-    dispatches of the last `steps` batched steps of the headline workload
-    and their average duration."""
+    --kernel-trace --stats run (CSV output) of this script: every kernel
+    dispatched within the last `steps` batched steps of the headline workload
+    (a step ends with the batched top-k's final kernel), with its average
+    duration and its time per step."""
     import csv
     import glob
     rows = []
     for f in glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True):
         with open(f, newline="") as fh:
             rows.extend(csv.DictReader(fh))
-    batched = {}
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    ends = [int(r["End_Timestamp"]) for r in rows if "gpa::k_topk_final<true>" in r["Kernel_Name"]]
+    if len(ends) < steps + 1:
+        raise SystemExit("fewer batched steps in the trace than asked for")
+    t0, t1 = ends[-steps - 1], ends[-1]
+    per = {}
     for r in rows:
-        name = r.get("Kernel_Name", "")
-        m = re.search(r"gpa::(k_\w+)<(?:[^<>]*, )?true>", name)
-        if not m:
+        b, e = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        if b <= t0 or e > t1:
             continue
-        key = name[name.index("gpa::"):].split("(")[0]
-        batched.setdefault(key, []).append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
-    # the timed steps are each batched kernel's last `steps` dispatches (the
-    # run is made with --no-config2, so no other batch follows them)
-    lines = [f"# Batched step kernels: whole application (400 kernels, 500M records)", "",
+        name = r["Kernel_Name"].split("(")[0]
+        name = name[5:] if name.startswith("void ") else name
+        per.setdefault(name, []).append((e - b) / 1e3)
+    lines = ["# Batched step kernels: whole application (400 kernels, 500M records)", "",
              f"Command: `{command}`", "",
-             "Per kernel: the last {} dispatches (the timed steps); durations from "
-             "the kernel trace.".format(steps), "",
+             f"Every kernel dispatched within the last {steps} batched steps (from the end "
+             "of the step before them to the end of the last); durations from the "
+             "kernel trace.", "",
              "| kernel | dispatches | avg µs | total per step µs |", "|---|---|---|---|"]
     tot = 0.0
-    for key, v in sorted(batched.items(), key=lambda kv: -sum(e - b for b, e in kv[1][-steps:])):
-        last = sorted(v)[-steps:]
-        d = [(e - b) / 1e3 for b, e in last]
-        avg = sum(d) / len(d)
-        per_step = sum(d) / steps
-        tot += per_step
-        lines.append(f"| `{key}` | {len(last)} | {avg:.1f} | {per_step:.1f} |")
-    lines += ["", f"GPU time of the batched kernels per step: {tot / 1e3:.3f} ms."]
+    for name, d in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        step_us = sum(d) / steps
+        tot += step_us
+        lines.append(f"| `{name}` | {len(d)} | {sum(d) / len(d):.1f} | {step_us:.1f} |")
+    lines += ["", f"GPU time of the kernels per step: {tot / 1e3:.3f} ms; span of a step "
+                  f"(wall, under the profiler): {(t1 - t0) / 1e6 / steps:.3f} ms."]
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def kernel_table(trace_dir, out_path, title, command):
+    """A markdown table of every kernel in a rocprofv3 --kernel-trace --stats
+    run (CSV output): dispatches, average and total duration, longest first."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True):
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    per = {}
+    for r in rows:
+        name = r.get("Kernel_Name", "").split("(")[0]
+        if name.startswith("void "):
+            name = name[5:]
+        per.setdefault(name, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    lines = [f"# {title}", "", f"Command: `{command}`", "",
+             "| kernel | dispatches | avg µs | total µs |", "|---|---|---|---|"]
+    for name, d in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"| `{name}` | {len(d)} | {sum(d) / len(d):.1f} | {sum(d):.1f} |")
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -464,6 +491,11 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--no-config1", action="store_true",
                     help="skip the large single-kernel profile (per-profile path)")
+    ap.add_argument("--only-config1", action="store_true",
+                    help="run only the large single-kernel profile and print its figures")
+    ap.add_argument("--kernel-table", nargs=4, metavar=("TRACE_DIR", "OUT_MD", "TITLE", "COMMAND"),
+                    help="write a table of every kernel of a rocprofv3 kernel trace "
+                         "(COMMAND: the run that made the trace)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-budget-gib", type=int, default=64)
@@ -481,6 +513,9 @@ def main():
     if args.traffic_summary:
         summarize_traffic(args.traffic_summary[0], args.traffic_summary[1],
                           args.copy_mb or 512, TRAFFIC_FILE, args.steps)
+        return
+    if args.kernel_table:
+        kernel_table(*args.kernel_table)
         return
     if args.kernel_summary:
         summarize_kernels(args.kernel_summary[0], args.kernel_summary[1], args.steps,
@@ -502,6 +537,10 @@ def main():
     gpa.lib()   # fails loudly when the library is not built
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
+
+    if args.only_config1:
+        print(json.dumps({"config1": run_config1(torch, gpa, dev, stream, args.steps)}), flush=True)
+        return
 
     c3, progs, records, offsets, P, buf, D = run_batch_config(torch, gpa, 3, args.steps,
                                                               args.warmup, dev, stream)

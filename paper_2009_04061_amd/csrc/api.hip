@@ -366,9 +366,11 @@ void enqueue_attribute_batch(gpa_program *const *progs, const gpa_sample *const 
     b[k] = new gpa_blame(progs[k]);
     b[k]->shared = sh;
     sh->carve(b[k]->counts, (size_t)progs[k]->n_instr * 24);
+    sh->carve(b[k]->issued, progs[k]->n_instr);
     const bool fits = n[k] > 0 && progs[k]->n_instr <= hist_hot_max_pcs() && !forced &&
                       ((uintptr_t)ds[k] % 16) == 0;
-    if (fits) batched.push_back({ds[k], n[k], progs[k]->n_instr, b[k]->counts.p, dtot + 4 * k});
+    if (fits)
+      batched.push_back({ds[k], n[k], progs[k]->n_instr, b[k]->counts.p, b[k]->issued.p, dtot + 4 * k});
     else single.push_back(k);
   }
   const uint64_t per = batch_records_per_workgroup(batched.data(), (uint32_t)batched.size(), s, ar,
@@ -381,7 +383,8 @@ void enqueue_attribute_batch(gpa_program *const *progs, const gpa_sample *const 
   } else {
     if (t_hist) t_hist->begin(kPhaseHist, s);
     run_hist_batch(batched.data(), (uint32_t)batched.size(), per, s, ar);
-    for (uint32_t k : single) run_hist(*progs[k], ds[k], n[k], b[k]->counts.p, dtot + 4 * k, s, ar);
+    for (uint32_t k : single)
+      run_hist(*progs[k], ds[k], n[k], b[k]->counts.p, b[k]->issued.p, dtot + 4 * k, s, ar);
     if (t_hist) t_hist->end(s);
   }
   run_blame_batch(progs, b, count, s, ar, *sh, t_blame);
@@ -393,6 +396,7 @@ gpa_blame::gpa_blame(const gpa_program *p) : prog(p) { gpa::program_retain(p); }
 gpa_blame::~gpa_blame() {
   // the buffers go back to the pool before the program can go
   counts.release();
+  issued.release();
   dtotals.release();
   share.release();
   bl.release();
@@ -683,10 +687,11 @@ gpa_status gpa_attribute(gpa_program *p, const gpa_sample *samples, uint64_t n,
       dsamp = tmp;
     }
     b->counts.alloc((size_t)p->n_instr * 24);
+    b->issued.alloc(p->n_instr);
     b->dtotals.alloc(4);
     PhaseTimer t_hist, t_blame;
     t_hist.begin(kPhaseHist, s);
-    run_hist(*p, dsamp, n, b->counts.p, b->dtotals.p, s, ar);
+    run_hist(*p, dsamp, n, b->counts.p, b->issued.p, b->dtotals.p, s, ar);
     t_hist.end(s);
     t_blame.begin(kPhaseBlame, s);
     run_blame(*p, *b, s, ar);

@@ -36,7 +36,7 @@ namespace gpa {
 struct BlameArgs {
   uint32_t n_instr, nbl, blamable;
   uint16_t allowed[12];
-  const uint32_t *counts, *in_ptr, *e_src, *e_dmax, *out_ptr, *out_perm;
+  const uint32_t *counts, *issued, *in_ptr, *e_src, *e_dmax, *out_ptr, *out_perm;
   const uint8_t *e_flags, *e_cls;
   double *share, *bl, *fx;
   uint16_t *nocand;
@@ -79,7 +79,7 @@ __device__ __forceinline__ EdgeW blame_edge(const BlameArgs &a, uint32_t e0, uin
   w.cls = a.e_cls[x];
   const uint32_t i = a.e_src[x];
   const double len = (double)a.e_dmax[x] + 1.0;
-  const double issued = (double)a.counts[(size_t)i * 24] + (double)a.counts[(size_t)i * 24 + 1];
+  const double issued = (double)a.issued[i];
   w.wi = issued / len;
   w.wp = 1.0 / len;
   return w;
@@ -339,17 +339,18 @@ void run_blame(const gpa_program &p, gpa_blame &b, hipStream_t s, Arena &ar) {
   b.bl.alloc((size_t)n * p.n_blamable * 2);
   b.fx.alloc((size_t)n * kBlameFx);
   b.nocand.alloc(n);
-  launch_blame(p, b.counts.p, b.share.p, b.bl.p, b.fx.p, b.nocand.p, s);
+  launch_blame(p, b.counts.p, b.issued.p, b.share.p, b.bl.p, b.fx.p, b.nocand.p, s);
 }
 
-static BlameArgs blame_args(const gpa_program &p, const uint32_t *counts, double *share,
-                            double *bl, double *fx, uint16_t *nocand) {
+static BlameArgs blame_args(const gpa_program &p, const uint32_t *counts, const uint32_t *issued,
+                            double *share, double *bl, double *fx, uint16_t *nocand) {
   BlameArgs a;
   a.n_instr = p.n_instr;
   a.nbl = p.n_blamable;
   a.blamable = p.arch.blamable;
   for (int r = 0; r < 12; ++r) a.allowed[r] = p.arch.allowed[r];
   a.counts = counts;
+  a.issued = issued;
   a.in_ptr = p.in_ptr.p;
   a.e_src = p.e_src.p;
   a.e_dmax = p.e_dmax.p;
@@ -364,9 +365,9 @@ static BlameArgs blame_args(const gpa_program &p, const uint32_t *counts, double
   return a;
 }
 
-void launch_blame(const gpa_program &p, const uint32_t *counts, double *share, double *bl,
-                  double *fx, uint16_t *nocand, hipStream_t s) {
-  const BlameArgs a = blame_args(p, counts, share, bl, fx, nocand);
+void launch_blame(const gpa_program &p, const uint32_t *counts, const uint32_t *issued,
+                  double *share, double *bl, double *fx, uint16_t *nocand, hipStream_t s) {
+  const BlameArgs a = blame_args(p, counts, issued, share, bl, fx, nocand);
   const unsigned g = grid_for(p.n_instr, kBlameThreads, 8192);
   if (p.n_blamable <= 4)
     hipLaunchKernelGGL((k_blame_dst<false, 4>), dim3(g), dim3(kBlameThreads), 0, s, a, nullptr,
@@ -405,7 +406,7 @@ void run_blame_batch(const gpa_program *const *progs, gpa_blame *const *b, uint3
     sh.carve(b[k]->bl, (size_t)n * p.n_blamable * 2);
     sh.carve(b[k]->fx, (size_t)n * kBlameFx);
     sh.carve(b[k]->nocand, n);
-    args[k] = blame_args(p, b[k]->counts.p, b[k]->share.p, b[k]->bl.p, b[k]->fx.p,
+    args[k] = blame_args(p, b[k]->counts.p, b[k]->issued.p, b[k]->share.p, b[k]->bl.p, b[k]->fx.p,
                          b[k]->nocand.p);
     tiles[k] = (n + kBlameThreads - 1) / kBlameThreads;
   }
@@ -414,11 +415,8 @@ void run_blame_batch(const gpa_program *const *progs, gpa_blame *const *b, uint3
   if (plan.blocks(q) == 0) return;
   Upload up;
   const size_t i_args = up.add(args), i_pre = up.add(plan.pre);
-  up.send(ar, s);
+  send_plan_beside(up, i_pre, plan, ar, s);
   const BlameArgs *d_args = up.ptr<BlameArgs>(i_args);
-  plan.d_pre = up.ptr<uint32_t>(i_pre);
-  plan.d_items = ar.get<WorkItem>(plan.total_items());
-  plan.expand(s);
   BlameArgs none{};
   const unsigned g = plan.blocks(q);
   if (t) t->begin(kPhaseBlame, s);

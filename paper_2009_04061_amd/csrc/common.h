@@ -268,6 +268,7 @@ struct gpa_blame {
   std::shared_ptr<gpa::SharedBlocks> shared;   // the tables' memory, when made by a batched call
   uint64_t totals[4] = {0, 0, 0, 0};
   gpa::DBuf<uint32_t> counts;          // [n_instr*24]
+  gpa::DBuf<uint32_t> issued;          // [n_instr] issued samples (SELECTED, both latency bits)
   gpa::DBuf<unsigned long long> dtotals;
   gpa::DBuf<double> share;             // [n_edges*n_blamable*2]
   // compact per-instruction results (the full tables are expanded on request)
@@ -392,11 +393,20 @@ struct Upload {
   }
 };
 
+// plan.hip: sends `up` (whose part i_pre is plan.pre) and expands the plan's
+// work list on a side stream, and makes `s` wait for both (an event), so
+// that the copy and the expansion overlap what `s` is still running; the
+// side stream joins the arena's streams.
+void send_plan_beside(Upload &up, size_t i_pre, BatchPlan &plan, Arena &ar, hipStream_t s);
+
 // hist.hip.  allow_partition = false keeps to the hot-set path (programs of
 // up to hist_hot_max_pcs() instructions; GPA_E_UNSUPPORTED beyond), which
 // issues no memset and no host synchronization.
+// Besides the counts, every path writes issued[i] = C[i][SELECTED][0] +
+// C[i][SELECTED][1], the sum the blamer gathers per source.
 void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint32_t *counts,
-              unsigned long long *totals, hipStream_t s, Arena &ar, bool allow_partition = true);
+              uint32_t *issued, unsigned long long *totals, hipStream_t s, Arena &ar,
+              bool allow_partition = true);
 uint32_t hist_hot_max_pcs();
 // One profile of a batched histogram: n records at `samples` (device, 16-byte
 // aligned) of a program of n_instr <= hist_hot_max_pcs() instructions.
@@ -405,6 +415,7 @@ struct HistEntry {
   uint64_t n;
   uint32_t n_instr;
   uint32_t *counts;
+  uint32_t *issued;   // [n_instr]: the issued (SELECTED) samples, both latency bits
   unsigned long long *totals;
 };
 // The hot-set histogram of many profiles in three launches (selection,
@@ -481,8 +492,8 @@ void build_scope_targets(gpa_program &p, hipStream_t s, Arena &ar);
 // blame.hip: run_blame allocates the blame handle's tables and calls
 // launch_blame, which writes caller-given device arrays and allocates nothing
 void run_blame(const gpa_program &p, gpa_blame &b, hipStream_t s, Arena &ar);
-void launch_blame(const gpa_program &p, const uint32_t *counts, double *share, double *bl,
-                  double *fx, uint16_t *nocand, hipStream_t s);
+void launch_blame(const gpa_program &p, const uint32_t *counts, const uint32_t *issued,
+                  double *share, double *bl, double *fx, uint16_t *nocand, hipStream_t s);
 // the full tables of the C-ABI (blamed, self_: [n_instr*24]; fine:
 // [n_instr*GPA_N_FINE*2]; any may be NULL) from the compact ones, on s
 void expand_blame_tables(const gpa_program &p, const uint32_t *counts, const double *bl,

@@ -719,10 +719,7 @@ void run_estimate_batch(const gpa_blame *const *b, gpa_advice *const *adv, uint3
   const uint32_t q_tkc = plan.add(w_tkc), q_tkf = plan.add(w_tkf);
   Upload up;
   const size_t i_args = up.add(args), i_pre = up.add(plan.pre);
-  up.send(ar, s);
-  plan.d_pre = up.ptr<uint32_t>(i_pre);
-  plan.d_items = ar.get<WorkItem>(plan.total_items());
-  plan.expand(s);
+  send_plan_beside(up, i_pre, plan, ar, s);
   EstLaunch L{s, EstArgs{}, up.ptr<EstArgs>(i_args)};
   auto run = [&](auto kern, uint32_t q, unsigned gy) { L(kern, plan.blocks(q), gy, plan.items(q)); };
   if (t) t->begin(kPhaseAdvise, s);

@@ -650,7 +650,7 @@ struct HotArgs {
   uint32_t *hot_tab, *hot_pc, *n_hot, *partial, *cold, *cold_sorted, *tile_off, *n_cold;
   uint32_t *corr;   // hot mode: kHotBins wrap corrections, cleared by the selection
   TileTotals *wtot;
-  uint32_t *counts;
+  uint32_t *counts, *issued;
   unsigned long long *totals;
 };
 
@@ -927,6 +927,7 @@ __device__ void direct_pass(const HotArgs &a, uint32_t wg, uint32_t *pool) {
     valid += lo + hi;
     lat += hi;
     *(uint2 *)(dst + 2 * (size_t)w) = make_uint2(lo, hi);
+    if (a.G == 1 && w % 12u == GPA_ST_SELECTED) a.issued[w / 12u] = lo + hi;
   }
   valid = wave_sum(valid);
   lat = wave_sum(lat);
@@ -1197,7 +1198,10 @@ k_hot_finish(HotArgs one, const HotArgs *__restrict__ many, const WorkItem *__re
     __syncthreads();   // the hot marks (and the cleared bins when there are no runs)
     for (uint32_t k = tid; k < npc * 24u; k += kHotThreads) {
       const uint32_t pl = k / 24u;
-      if (!((hot_mark[pl / 32] >> (pl % 32)) & 1u)) counts[(size_t)pc0 * 24u + k] = bins[k];
+      if (!((hot_mark[pl / 32] >> (pl % 32)) & 1u)) {
+        counts[(size_t)pc0 * 24u + k] = bins[k];
+        if (k % 24u == 2 * GPA_ST_SELECTED) a.issued[pc0 + pl] = bins[k] + bins[k + 1];
+      }
     }
   } else if (bid < n_cb + n_merge) {
     // the partial tables merged by word: a thread takes the two counters of
@@ -1248,10 +1252,12 @@ k_hot_finish(HotArgs one, const HotArgs *__restrict__ many, const WorkItem *__re
       if (sl == 0 && live) {
         if (direct) {
           *(uint2 *)(counts + 2u * (size_t)word) = make_uint2(lo, hi);
+          if (word % 12u == GPA_ST_SELECTED) a.issued[word / 12u] = lo + hi;
         } else {
           const uint2 cr = *(const uint2 *)(a.corr + 2u * word);
           const size_t at = (size_t)hot_pc[word / 12u] * 24u + 2u * (word % 12u);
           *(uint2 *)(counts + at) = make_uint2(lo + cr.x, hi + cr.y);
+          if (word % 12u == GPA_ST_SELECTED) a.issued[at / 24u] = lo + cr.x + hi + cr.y;
         }
       }
     }
@@ -1382,7 +1388,8 @@ size_t hist_hot_scratch_bytes(uint32_t n_instr, uint64_t n) {
 // one profile's arguments, its scratch taken from the arena (in the order
 // hot_scratch counts it)
 static HotArgs hot_args(const HotShape &h, const uint64_t *rec, uint64_t n, uint32_t n_instr,
-                        uint32_t *counts, unsigned long long *totals, Arena &ar) {
+                        uint32_t *counts, uint32_t *issued, unsigned long long *totals,
+                        Arena &ar) {
   const HotPieces q = hot_pieces(h, n_instr, n);
   HotArgs a;
   a.rec = rec;
@@ -1408,6 +1415,7 @@ static HotArgs hot_args(const HotShape &h, const uint64_t *rec, uint64_t n, uint
   a.corr = ar.get<uint32_t>(q.u32[8]);
   a.wtot = ar.get<TileTotals>(q.totals);
   a.counts = counts;
+  a.issued = issued;
   a.totals = totals;
   return a;
 }
@@ -1439,14 +1447,14 @@ static void set_select_lds() {
 }
 
 static bool run_hist_hot(const gpa_program &p, const uint64_t *rec, uint64_t n, bool vec,
-                         uint32_t *counts, unsigned long long *totals, hipStream_t s, Arena &ar,
-                         bool allow_partition) {
+                         uint32_t *counts, uint32_t *issued, unsigned long long *totals,
+                         hipStream_t s, Arena &ar, bool allow_partition) {
   const uint32_t n_instr = p.n_instr;
   if (n_instr > kHotMaxPCs) return false;
   const char *force = getenv("GPA_HIST_PARTITION");
   if (allow_partition && force && force[0] == '1') return false;
   const HotShape hs = hot_shape(n_instr, n);
-  const HotArgs a = hot_args(hs, rec, n, n_instr, counts, totals, ar);
+  const HotArgs a = hot_args(hs, rec, n, n_instr, counts, issued, totals, ar);
   uint32_t n_sel, n_pass, n_fin;
   hot_blocks(hs, n_sel, n_pass, n_fin);
   if (n_sel) {
@@ -1490,7 +1498,7 @@ static void prepare_hist_batch(HistBatch &hb, const HistEntry *e, uint32_t count
            "16-byte aligned records are required", k, kHotMaxPCs);
     const HotShape h = hot_shape(e[k].n_instr, e[k].n, per);
     args[k] = hot_args(h, (const uint64_t *)e[k].samples, e[k].n, e[k].n_instr, e[k].counts,
-                       e[k].totals, ar);
+                       e[k].issued, e[k].totals, ar);
     hot_blocks(h, n_sel[k], n_pass[k], n_fin[k]);
     range[k] = std::min<uint64_t>(h.per, e[k].n);
   }
@@ -1626,29 +1634,41 @@ uint64_t batch_records_per_workgroup(const HistEntry *e, uint32_t count, hipStre
   return best;
 }
 
-__global__ void k_hist_empty(uint32_t *counts, size_t nbins, unsigned long long *totals) {
-  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < nbins;
-       k += (size_t)gridDim.x * blockDim.x)
+__global__ void k_hist_empty(uint32_t *counts, uint32_t *issued, uint32_t n_instr,
+                             unsigned long long *totals) {
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < (size_t)n_instr * 24;
+       k += (size_t)gridDim.x * blockDim.x) {
     counts[k] = 0;
+    if (k < n_instr) issued[k] = 0;
+  }
   if (blockIdx.x == 0 && threadIdx.x < 4) totals[threadIdx.x] = 0;
 }
 
+// the issued samples from finished counts (the partition path)
+__global__ void k_issued(const uint32_t *__restrict__ counts, uint32_t n_instr,
+                         uint32_t *__restrict__ issued) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_instr; i += gridDim.x * blockDim.x)
+    issued[i] = counts[(size_t)i * 24 + 2 * GPA_ST_SELECTED] +
+                counts[(size_t)i * 24 + 2 * GPA_ST_SELECTED + 1];
+}
+
 void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint32_t *counts,
-              unsigned long long *totals, hipStream_t s, Arena &ar, bool allow_partition) {
+              uint32_t *issued, unsigned long long *totals, hipStream_t s, Arena &ar,
+              bool allow_partition) {
   const uint32_t n_instr = p.n_instr;
   const uint32_t n_buckets = (n_instr + kBucketPCs - 1) / kBucketPCs;
   if (n_buckets > kMaxBuckets)
     fail(GPA_E_UNSUPPORTED, "histogram supports up to %d instructions", kMaxBuckets * kBucketPCs);
   if (n == 0) {
     hipLaunchKernelGGL(k_hist_empty, dim3(grid_for((size_t)n_instr * 24, 256, 4096)), dim3(256), 0,
-                       s, counts, (size_t)n_instr * 24, totals);
+                       s, counts, issued, n_instr, totals);
     GPA_LAUNCH_CHECK();
     return;
   }
   if (n >= 0x40000000ull) fail(GPA_E_UNSUPPORTED, "fewer than 2^30 samples per call are supported");
   const uint64_t *rec = (const uint64_t *)samples;
   const bool vec = ((uintptr_t)samples % 16) == 0;
-  if (run_hist_hot(p, rec, n, vec, counts, totals, s, ar, allow_partition)) return;
+  if (run_hist_hot(p, rec, n, vec, counts, issued, totals, s, ar, allow_partition)) return;
   if (!allow_partition)
     fail(GPA_E_UNSUPPORTED, "this path counts programs of up to %u instructions", kHotMaxPCs);
   const uint32_t n_tiles = (uint32_t)((n + kTile - 1) / kTile);
@@ -1711,6 +1731,9 @@ void run_hist(const gpa_program &p, const gpa_sample *samples, uint64_t n, uint3
                      s, partial, items, item_start, n_instr, counts);
   GPA_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_hoverflow, dim3(256), dim3(256), 0, s, ov_keys, ov_count, counts);
+  GPA_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_issued, dim3(grid_for(n_instr, 256, 4096)), dim3(256), 0, s, counts, n_instr,
+                     issued);
   GPA_LAUNCH_CHECK();
 }
 

@@ -66,12 +66,13 @@ gpa_status gpa_attribute_noalloc(const gpa_program *p, const gpa_sample *samples
               "has %u)", hist_hot_max_pcs(), p->n_instr);
     return GPA_E_UNSUPPORTED;
   }
-  // the histogram's scratch, then the blamer's compact tables (expanded into
-  // the caller's full tables at the end), each piece 256-byte aligned
+  // the issued samples, the histogram's scratch, then the blamer's compact
+  // tables (expanded into the caller's full tables at the end), each piece
+  // 256-byte aligned
   auto blk = [](size_t bytes) { return (bytes + 255) / 256 * 256; };
   const size_t ni = p->n_instr;
-  const size_t need = hist_hot_scratch_bytes(p->n_instr, n) + blk(ni * p->n_blamable * 2 * 8) +
-                      blk(ni * kBlameFx * 8) + blk(ni * 2) + 256;
+  const size_t need = blk(ni * 4) + hist_hot_scratch_bytes(p->n_instr, n) +
+                      blk(ni * p->n_blamable * 2 * 8) + blk(ni * kBlameFx * 8) + blk(ni * 2) + 256;
   if (need > kScratchBytes) {
     set_error("gpa_attribute_noalloc: %llu records of a %u-instruction program need %zu bytes of "
               "scratch, more than the fixed %zu", (unsigned long long)n, p->n_instr, need,
@@ -81,12 +82,13 @@ gpa_status gpa_attribute_noalloc(const gpa_program *p, const gpa_sample *samples
   hipStream_t s = (hipStream_t)stream;
   try {
     Arena ar(scratch_on_current_device(), kScratchBytes);
-    run_hist(*p, samples, n, counts, reinterpret_cast<unsigned long long *>(totals), s, ar,
+    uint32_t *issued = ar.get<uint32_t>(ni);
+    run_hist(*p, samples, n, counts, issued, reinterpret_cast<unsigned long long *>(totals), s, ar,
              /*allow_partition=*/false);
     double *bl = ar.get<double>(ni * p->n_blamable * 2);
     double *fx = ar.get<double>(ni * kBlameFx);
     uint16_t *nocand = ar.get<uint16_t>(ni);
-    launch_blame(*p, counts, share, bl, fx, nocand, s);
+    launch_blame(*p, counts, issued, share, bl, fx, nocand, s);
     expand_blame_tables(*p, counts, bl, fx, nocand, blamed, self_, fine, s);
   } catch (const Error &e) {
     return e.code;

@@ -61,4 +61,19 @@ void BatchPlan::expand(hipStream_t s) {
   GPA_LAUNCH_CHECK();
 }
 
+void send_plan_beside(Upload &up, size_t i_pre, BatchPlan &plan, Arena &ar, hipStream_t s) {
+  const hipStream_t c = side_stream(1);
+  ar.add_stream(c);
+  up.send(ar, c);
+  plan.d_pre = up.ptr<uint32_t>(i_pre);
+  plan.d_items = ar.get<WorkItem>(plan.total_items());
+  plan.expand(c);
+  hipEvent_t e = nullptr;
+  GPA_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  const hipError_t r1 = hipEventRecord(e, c);
+  const hipError_t r2 = r1 == hipSuccess ? hipStreamWaitEvent(s, e, 0) : r1;
+  (void)hipEventDestroy(e);
+  GPA_HIP(r2);
+}
+
 }  // namespace gpa
