@@ -36,7 +36,7 @@ namespace gpa {
 struct BlameArgs {
   uint32_t n_instr, nbl, blamable;
   uint16_t allowed[12];
-  const uint32_t *counts, *issued, *in_ptr, *e_src, *e_dmax, *out_ptr, *out_perm;
+  const uint32_t *counts, *issued, *in_ptr, *e_src, *e_dst, *e_dmax, *out_ptr, *out_perm;
   const uint8_t *e_flags, *e_cls;
   double *share, *bl, *fx;
   uint16_t *nocand;
@@ -51,15 +51,20 @@ constexpr int kBlameThreads = 128;
   const uint32_t stride_ = BATCH ? a.n_instr : gridDim.x * blockDim.x;           \
   for (uint32_t VAR = first_; VAR < a.n_instr; VAR += stride_)
 
-// One thread per destination j.  A first pass over j's incoming edges sums,
-// per blamable reason, the issued-based and the path-only weights of the
-// candidates (in edge order, as Eq. (1) is written); a second pass writes
-// every share slot of those edges.  Reasons are unrolled, so the per-reason
-// sums stay in registers.  The edges are taken kBlameU at a time, their
-// loads and the gathers of their sources' issued samples issued together;
-// the first kBlameU edges' weights stay in registers for the second pass
-// (most instructions have no more incoming edges than that).
-constexpr uint32_t kBlameU = 4;
+// One wave per tile of 64 consecutive destinations; lane l owns destination
+// j = d0 + l.  The tile's in-edges (contiguous: edges are sorted by
+// destination) are read 64 at a time by all lanes, coalesced, each lane one
+// edge with its source's issued samples.
+//   Pass 1: every owner takes the weights of its own edges in the chunk from
+//   the lanes holding them (cross-lane reads), in edge order, and sums, per
+//   blamable reason, the issued-based and the path-only weights of the
+//   candidates (as Eq. (1) is written; the same additions in the same order
+//   as a loop over j's edges).
+//   Pass 2: each lane takes one edge again, its owner's sums and counts from
+//   the owner lane, and writes the edge's share slots (consecutive lanes,
+//   consecutive edges).
+// Reasons are unrolled, so the per-reason sums stay in registers.
+constexpr uint32_t kTileWaves = 4;   // tiles (waves) per workgroup
 
 struct EdgeW {
   double wi, wp;    // issued / length, 1 / length
@@ -67,8 +72,8 @@ struct EdgeW {
   bool kept;        // survives dominator and latency pruning
 };
 
-// edge e0 + u of j's range [e0, e1) (an edge past the range reads edge e0
-// and is not kept)
+// edge e of the range [e0, e1) (an edge past the range reads edge e0 and
+// is not kept)
 __device__ __forceinline__ EdgeW blame_edge(const BlameArgs &a, uint32_t e0, uint32_t e1,
                                             uint32_t e) {
   const bool in = e < e1;
@@ -88,26 +93,36 @@ __device__ __forceinline__ EdgeW blame_edge(const BlameArgs &a, uint32_t e0, uin
 // NB: blamable reasons the kernel keeps sums for (the arch's blamable set
 // has at most NB reasons; slot s is the s-th blamable reason ascending)
 template <bool BATCH, int NB>
-__global__ void __launch_bounds__(kBlameThreads)
+__global__ void __launch_bounds__(kWave * kTileWaves)
 k_blame_dst(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *__restrict__ items) {
-  BLAME_ITEM(j) {
-    const uint32_t nbl = a.nbl;
-    // the blamable reasons by slot, and the opcode classes each allows
-    // (slot q takes the lowest blamable reason left, so every slot has a
-    // fixed register; slots past the set read reason 0 and allow nothing)
-    uint32_t rs[NB], allow[NB];
-    {
-      uint32_t m = a.blamable & 0xFFFu;
+  const BlameArgs &a = BATCH ? many[items[blockIdx.x].entry] : one;
+  const uint32_t lane = threadIdx.x % kWave;
+  const uint32_t n = a.n_instr, nbl = a.nbl;
+  const uint32_t n_tiles = (n + kWave - 1) / kWave;
+  // a batched workgroup takes its kTileWaves tiles once; otherwise a grid
+  // stride over the tiles
+  const uint32_t t0 = (BATCH ? items[blockIdx.x].local : blockIdx.x) * kTileWaves +
+                      threadIdx.x / kWave;
+  const uint32_t t_step = BATCH ? n_tiles : gridDim.x * kTileWaves;
+  // the blamable reasons by slot, and the opcode classes each allows (slot
+  // q takes the lowest blamable reason left, so every slot has a fixed
+  // register; slots past the set read reason 0 and allow nothing)
+  uint32_t rs[NB], allow[NB];
+  {
+    uint32_t m = a.blamable & 0xFFFu;
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const uint32_t r = m ? (uint32_t)__builtin_ctz(m) : 0u;
-        rs[q] = r;
-        allow[q] = m ? a.allowed[r] : 0u;
-        m &= m - 1u;
-      }
+    for (int q = 0; q < NB; ++q) {
+      const uint32_t r = m ? (uint32_t)__builtin_ctz(m) : 0u;
+      rs[q] = r;
+      allow[q] = m ? a.allowed[r] : 0u;
+      m &= m - 1u;
     }
-    const uint32_t *C = a.counts + (size_t)j * 24;
-    const uint32_t e0 = a.in_ptr[j], e1 = a.in_ptr[j + 1];
+  }
+  for (uint32_t t = t0; t < n_tiles; t += t_step) {
+    const uint32_t d0 = t * kWave, j = d0 + lane;
+    const bool own = j < n;
+    const uint32_t e0 = own ? a.in_ptr[j] : 0u, e1 = own ? a.in_ptr[j + 1] : 0u;
+    const uint32_t E0 = a.in_ptr[d0], E1 = a.in_ptr[min(d0 + kWave, n)];
     double Wi[NB], Wp[NB];
     bool any[NB];
 #pragma unroll
@@ -116,64 +131,66 @@ k_blame_dst(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *_
       Wp[q] = 0.0;
       any[q] = false;
     }
-    // with the sums of more than four reasons live, the kept edges would
-    // not fit in registers: the second pass then loads them again
-    constexpr bool kKeepFirst = NB <= 4;
-    EdgeW first[kKeepFirst ? kBlameU : 1];
-    for (uint32_t base = e0; base < e1; base += kBlameU) {
-      EdgeW w[kBlameU];
+    // pass 1
+    for (uint32_t base = E0; base < E1; base += kWave) {
+      const EdgeW w = blame_edge(a, E0, E1, base + lane);
+      const uint32_t packed = (w.kept ? 1u : 0u) | (w.cls << 1);
+      const uint32_t lo = max(e0, base), hi = min(e1, base + kWave);
+      const uint32_t cnt = hi > lo ? hi - lo : 0u;
+      const uint32_t rounds = wave_max_u32(cnt);
+      for (uint32_t k = 0; k < rounds; ++k) {
+        const int from = (int)(k < cnt ? lo - base + k : lane);
+        const double wi = __shfl(w.wi, from, kWave), wp = __shfl(w.wp, from, kWave);
+        const uint32_t pk = (uint32_t)__shfl((int)packed, from, kWave);
+        if (k < cnt) {
+          const bool kept = (pk & 1u) != 0;
+          const uint32_t cls = pk >> 1;
 #pragma unroll
-      for (uint32_t u = 0; u < kBlameU; ++u) w[u] = blame_edge(a, e0, e1, base + u);
-#pragma unroll
-      for (uint32_t u = 0; u < kBlameU; ++u) {
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-          const bool cand = w[u].kept && ((allow[q] >> w[u].cls) & 1u);
-          Wi[q] = cand ? Wi[q] + w[u].wi : Wi[q];
-          Wp[q] = cand ? Wp[q] + w[u].wp : Wp[q];
-          any[q] = any[q] || cand;
-        }
-      }
-      if (kKeepFirst && base == e0) {
-#pragma unroll
-        for (uint32_t u = 0; u < kBlameU; ++u) first[u] = w[u];
-      }
-    }
-    for (uint32_t base = e0; base < e1; base += kBlameU) {
-      EdgeW w[kBlameU];
-      if (kKeepFirst && base == e0) {
-#pragma unroll
-        for (uint32_t u = 0; u < kBlameU; ++u) w[u] = first[u];
-      } else {
-#pragma unroll
-        for (uint32_t u = 0; u < kBlameU; ++u) w[u] = blame_edge(a, e0, e1, base + u);
-      }
-#pragma unroll
-      for (uint32_t u = 0; u < kBlameU; ++u) {
-        const uint32_t e = base + u;
-        if (e >= e1) break;
-        double *sh = a.share + (size_t)e * 2 * nbl;
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-          if ((uint32_t)q < nbl) {
-            const bool cand = w[u].kept && ((allow[q] >> w[u].cls) & 1u);
-            const bool by_path = (Wi[q] == 0.0);
-            const double wt = by_path ? w[u].wp : w[u].wi;
-            const double W = by_path ? Wp[q] : Wi[q];
-#pragma unroll
-            for (int l = 0; l < 2; ++l) {
-              const uint32_t S = C[rs[q] * 2 + l];
-              sh[q * 2 + l] = (cand && S != 0) ? (double)S * wt / W : 0.0;
-            }
+          for (int q = 0; q < NB; ++q) {
+            const bool cand = kept && ((allow[q] >> cls) & 1u);
+            Wi[q] = cand ? Wi[q] + wi : Wi[q];
+            Wp[q] = cand ? Wp[q] + wp : Wp[q];
+            any[q] = any[q] || cand;
           }
         }
       }
     }
-    uint32_t mask = 0;
+    // the owner's samples of the blamable reasons
+    uint32_t S[NB][2];
 #pragma unroll
     for (int q = 0; q < NB; ++q)
-      if ((uint32_t)q < nbl && !any[q]) mask |= 1u << q;
-    a.nocand[j] = (uint16_t)mask;
+#pragma unroll
+      for (int l = 0; l < 2; ++l)
+        S[q][l] = (own && (uint32_t)q < nbl) ? a.counts[(size_t)j * 24 + rs[q] * 2 + l] : 0u;
+    // pass 2
+    for (uint32_t base = E0; base < E1; base += kWave) {
+      const uint32_t e = base + lane;
+      const bool in = e < E1;
+      const EdgeW w = blame_edge(a, E0, E1, e);
+      const int o = (int)(in ? a.e_dst[e] - d0 : lane);   // the owner lane
+      double *sh = a.share + (size_t)(in ? e : 0u) * 2 * nbl;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const double wiq = __shfl(Wi[q], o, kWave), wpq = __shfl(Wp[q], o, kWave);
+        const uint32_t s0 = (uint32_t)__shfl((int)S[q][0], o, kWave);
+        const uint32_t s1 = (uint32_t)__shfl((int)S[q][1], o, kWave);
+        if (in && (uint32_t)q < nbl) {
+          const bool cand = w.kept && ((allow[q] >> w.cls) & 1u);
+          const bool by_path = (wiq == 0.0);
+          const double wt = by_path ? w.wp : w.wi;
+          const double W = by_path ? wpq : wiq;
+          sh[q * 2] = (cand && s0 != 0) ? (double)s0 * wt / W : 0.0;
+          sh[q * 2 + 1] = (cand && s1 != 0) ? (double)s1 * wt / W : 0.0;
+        }
+      }
+    }
+    if (own) {
+      uint32_t mask = 0;
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+        if ((uint32_t)q < nbl && !any[q]) mask |= 1u << q;
+      a.nocand[j] = (uint16_t)mask;
+    }
   }
 }
 
@@ -353,6 +370,7 @@ static BlameArgs blame_args(const gpa_program &p, const uint32_t *counts, const 
   a.issued = issued;
   a.in_ptr = p.in_ptr.p;
   a.e_src = p.e_src.p;
+  a.e_dst = p.e_dst.p;
   a.e_dmax = p.e_dmax.p;
   a.out_ptr = p.out_ptr;
   a.out_perm = p.out_perm;
@@ -369,12 +387,13 @@ void launch_blame(const gpa_program &p, const uint32_t *counts, const uint32_t *
                   double *share, double *bl, double *fx, uint16_t *nocand, hipStream_t s) {
   const BlameArgs a = blame_args(p, counts, issued, share, bl, fx, nocand);
   const unsigned g = grid_for(p.n_instr, kBlameThreads, 8192);
+  const unsigned gd = grid_for(p.n_instr, kWave * kTileWaves, 8192);
   if (p.n_blamable <= 4)
-    hipLaunchKernelGGL((k_blame_dst<false, 4>), dim3(g), dim3(kBlameThreads), 0, s, a, nullptr,
-                       nullptr);
+    hipLaunchKernelGGL((k_blame_dst<false, 4>), dim3(gd), dim3(kWave * kTileWaves), 0, s, a,
+                       nullptr, nullptr);
   else
-    hipLaunchKernelGGL((k_blame_dst<false, 12>), dim3(g), dim3(kBlameThreads), 0, s, a, nullptr,
-                       nullptr);
+    hipLaunchKernelGGL((k_blame_dst<false, 12>), dim3(gd), dim3(kWave * kTileWaves), 0, s, a,
+                       nullptr, nullptr);
   GPA_LAUNCH_CHECK();
   if (p.n_blamable <= 4)
     hipLaunchKernelGGL((k_blame_src<false, 4>), dim3(g), dim3(kBlameThreads), 0, s, a, nullptr,
@@ -398,7 +417,7 @@ void expand_blame_tables(const gpa_program &p, const uint32_t *counts, const dou
 void run_blame_batch(const gpa_program *const *progs, gpa_blame *const *b, uint32_t count,
                      hipStream_t s, Arena &ar, SharedBlocks &sh, PhaseTimer *t) {
   std::vector<BlameArgs> args(count);
-  std::vector<uint32_t> tiles(count);
+  std::vector<uint32_t> tiles(count), dst_groups(count);
   for (uint32_t k = 0; k < count; ++k) {
     const gpa_program &p = *progs[k];
     const uint32_t n = p.n_instr;
@@ -409,9 +428,10 @@ void run_blame_batch(const gpa_program *const *progs, gpa_blame *const *b, uint3
     args[k] = blame_args(p, b[k]->counts.p, b[k]->issued.p, b[k]->share.p, b[k]->bl.p, b[k]->fx.p,
                          b[k]->nocand.p);
     tiles[k] = (n + kBlameThreads - 1) / kBlameThreads;
+    dst_groups[k] = (n + kWave * kTileWaves - 1) / (kWave * kTileWaves);
   }
   BatchPlan plan(count);
-  const uint32_t q = plan.add(tiles);
+  const uint32_t q = plan.add(tiles), qd = plan.add(dst_groups);
   if (plan.blocks(q) == 0) return;
   Upload up;
   const size_t i_args = up.add(args), i_pre = up.add(plan.pre);
@@ -422,12 +442,13 @@ void run_blame_batch(const gpa_program *const *progs, gpa_blame *const *b, uint3
   if (t) t->begin(kPhaseBlame, s);
   uint32_t max_nbl = 0;
   for (uint32_t k = 0; k < count; ++k) max_nbl = std::max(max_nbl, progs[k]->n_blamable);
+  const unsigned gd = plan.blocks(qd);
   if (max_nbl <= 4)
-    hipLaunchKernelGGL((k_blame_dst<true, 4>), dim3(g), dim3(kBlameThreads), 0, s, none, d_args,
-                       plan.items(q));
+    hipLaunchKernelGGL((k_blame_dst<true, 4>), dim3(gd), dim3(kWave * kTileWaves), 0, s, none,
+                       d_args, plan.items(qd));
   else
-    hipLaunchKernelGGL((k_blame_dst<true, 12>), dim3(g), dim3(kBlameThreads), 0, s, none, d_args,
-                       plan.items(q));
+    hipLaunchKernelGGL((k_blame_dst<true, 12>), dim3(gd), dim3(kWave * kTileWaves), 0, s, none,
+                       d_args, plan.items(qd));
   GPA_LAUNCH_CHECK();
   if (max_nbl <= 4)
     hipLaunchKernelGGL((k_blame_src<true, 4>), dim3(g), dim3(kBlameThreads), 0, s, none, d_args,
