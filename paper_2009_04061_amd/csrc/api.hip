@@ -746,10 +746,14 @@ gpa_status gpa_attribute_batch(gpa_program *const *progs, const gpa_sample *cons
     PhaseTimer t_hist, t_blame;
     enqueue_attribute_batch(progs, dptr.data(), n, count, s, ar, b.data(), dtot, true, &t_hist,
                             &t_blame);
-    std::vector<unsigned long long> tot((size_t)count * 4);
-    if (count)
-      GPA_HIP(hipMemcpyAsync(tot.data(), dtot, sizeof(unsigned long long) * tot.size(),
-                             hipMemcpyDeviceToHost, s));
+    // the totals come back through pinned staging (a direct DMA, no
+    // pageable bounce), returned with the arena
+    unsigned long long *tot = nullptr;
+    if (count) {
+      const size_t bytes = sizeof(unsigned long long) * 4 * (size_t)count;
+      tot = static_cast<unsigned long long *>(ar.stage(bytes));
+      GPA_HIP(hipMemcpyAsync(tot, dtot, bytes, hipMemcpyDeviceToHost, s));
+    }
     GPA_HIP(hipStreamSynchronize(s));
     t_hist.collect();
     t_blame.collect();
@@ -918,10 +922,14 @@ gpa_status gpa_analyze_batch(gpa_program *const *progs, const gpa_sample *const 
                             &t_blame);
     for (uint32_t k = 0; k < count; ++k) a[k] = new gpa_advice(b[k]->prog);
     run_estimate_batch(b.data(), a.data(), count, 16, s, ar, &t_adv);
-    std::vector<unsigned long long> tot((size_t)count * 4);
-    if (count)
-      GPA_HIP(hipMemcpyAsync(tot.data(), dtot, sizeof(unsigned long long) * tot.size(),
-                             hipMemcpyDeviceToHost, s));
+    // the totals come back through pinned staging (a direct DMA, no
+    // pageable bounce), returned with the arena
+    unsigned long long *tot = nullptr;
+    if (count) {
+      const size_t bytes = sizeof(unsigned long long) * 4 * (size_t)count;
+      tot = static_cast<unsigned long long *>(ar.stage(bytes));
+      GPA_HIP(hipMemcpyAsync(tot, dtot, bytes, hipMemcpyDeviceToHost, s));
+    }
     GPA_HIP(hipStreamSynchronize(s));
     t_hist.collect();
     t_blame.collect();
