@@ -119,6 +119,31 @@ def test_long_backward_searches():
     _both(prog, rec)
 
 
+def _hub_program(k):
+    """One block defines R5 and branches to k blocks, each reading R5 and
+    defining R0; they join in a block that reads R0.  The join's use has k
+    incoming edges and R5's def k + 1 outgoing ones, so with k > 64 one
+    destination's (and one source's) edges span several 64-edge chunks of
+    the blamer's wave tiles."""
+    lines = ["block 0 -> " + " ".join(str(i) for i in range(1, k + 1)), "  MOV R5 <- R1", "  BRA"]
+    for i in range(1, k + 1):
+        lines += [f"block {i} -> {k + 1}", "  MOV R0 <- R5", "  BRA"]
+    lines += [f"block {k + 1} ->", "  IADD R2 <- R0 R3", "  IADD R4 <- R2 R5"]
+    return assemble("\n".join(lines) + "\n")
+
+
+@pytest.mark.parametrize("k", [63, 64, 65, 150])
+def test_high_in_and_out_degree(k):
+    prog = _hub_program(k)
+    o = O.Program(prog)
+    a = o.analyze()
+    n = len(prog["op_class"])
+    assert np.bincount(a["dst"], minlength=n).max() == k
+    assert np.bincount(a["src"], minlength=n).max() == k + 1
+    rec = S.gen_samples(50_000, n, 0.5, S.stall_mix_small(), seed=k)
+    _both(prog, rec)
+
+
 def test_deterministic_bitwise():
     prog, rec = S.workload_multi(seed=3, n_samples=60_000)
     a = run_gpu(prog, rec)
