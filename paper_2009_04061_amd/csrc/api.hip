@@ -399,6 +399,7 @@ gpa_blame::~gpa_blame() {
   issued.release();
   dtotals.release();
   share.release();
+  ec.release();
   bl.release();
   fx.release();
   nocand.release();

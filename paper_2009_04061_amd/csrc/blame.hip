@@ -10,9 +10,11 @@
 // candidate the samples stay on j, as do all samples of other reasons; the
 // rule applies the same way to latency samples.
 //
-// k_blame_dst owns one destination and writes its edges' shares; k_blame_src
-// owns one source and sums its outgoing shares in edge order, so every FP64
-// sum has a fixed order and no floating-point atomics are used.
+// k_blame_dst takes the destinations by wave tiles, each lane owning one
+// destination's sums, and writes every edge's shares (and its estimator
+// contribution); k_blame_src owns one source per thread and sums its
+// outgoing shares in edge order.  Every FP64 sum has a fixed order and no
+// floating-point atomics are used.
 //
 // The per-instruction results are kept compact on the device: the blamed
 // samples of the blamable reasons only (bl, [n_instr][n_blamable][2]), one
@@ -38,7 +40,7 @@ struct BlameArgs {
   uint16_t allowed[12];
   const uint32_t *counts, *issued, *in_ptr, *e_src, *e_dst, *e_dmax, *out_ptr, *out_perm;
   const uint8_t *e_flags, *e_cls;
-  double *share, *bl, *fx;
+  double *share, *ec, *bl, *fx;   // ec may be null
   uint16_t *nocand;
 };
 constexpr int kBlameThreads = 128;
@@ -169,6 +171,9 @@ k_blame_dst(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *_
       const EdgeW w = blame_edge(a, E0, E1, e);
       const int o = (int)(in ? a.e_dst[e] - d0 : lane);   // the owner lane
       double *sh = a.share + (size_t)(in ? e : 0u) * 2 * nbl;
+      // the edge's estimator contribution: its latency samples of an
+      // execution dependency and, from a global load, of a memory dependency
+      double ecv = 0.0;
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         const double wiq = __shfl(Wi[q], o, kWave), wpq = __shfl(Wp[q], o, kWave);
@@ -180,9 +185,13 @@ k_blame_dst(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *_
           const double wt = by_path ? w.wp : w.wi;
           const double W = by_path ? wpq : wiq;
           sh[q * 2] = (cand && s0 != 0) ? (double)s0 * wt / W : 0.0;
-          sh[q * 2 + 1] = (cand && s1 != 0) ? (double)s1 * wt / W : 0.0;
+          const double v1 = (cand && s1 != 0) ? (double)s1 * wt / W : 0.0;
+          sh[q * 2 + 1] = v1;
+          if (rs[q] == GPA_ST_EXEC_DEP || (rs[q] == GPA_ST_MEM_DEP && w.cls == GPA_OP_GLOBAL_LOAD))
+            ecv += v1;
         }
       }
+      if (in && a.ec) a.ec[e] = ecv;
     }
     if (own) {
       uint32_t mask = 0;
@@ -353,14 +362,16 @@ void run_blame(const gpa_program &p, gpa_blame &b, hipStream_t s, Arena &ar) {
   (void)ar;
   const uint32_t n = p.n_instr;
   b.share.alloc(p.n_edges * p.n_blamable * 2);
+  b.ec.alloc(p.n_edges);
   b.bl.alloc((size_t)n * p.n_blamable * 2);
   b.fx.alloc((size_t)n * kBlameFx);
   b.nocand.alloc(n);
-  launch_blame(p, b.counts.p, b.issued.p, b.share.p, b.bl.p, b.fx.p, b.nocand.p, s);
+  launch_blame(p, b.counts.p, b.issued.p, b.share.p, b.ec.p, b.bl.p, b.fx.p, b.nocand.p, s);
 }
 
 static BlameArgs blame_args(const gpa_program &p, const uint32_t *counts, const uint32_t *issued,
-                            double *share, double *bl, double *fx, uint16_t *nocand) {
+                            double *share, double *ec, double *bl, double *fx,
+                            uint16_t *nocand) {
   BlameArgs a;
   a.n_instr = p.n_instr;
   a.nbl = p.n_blamable;
@@ -377,6 +388,7 @@ static BlameArgs blame_args(const gpa_program &p, const uint32_t *counts, const 
   a.e_flags = p.e_flags.p;
   a.e_cls = p.e_cls.p;
   a.share = share;
+  a.ec = ec;
   a.bl = bl;
   a.fx = fx;
   a.nocand = nocand;
@@ -384,8 +396,9 @@ static BlameArgs blame_args(const gpa_program &p, const uint32_t *counts, const 
 }
 
 void launch_blame(const gpa_program &p, const uint32_t *counts, const uint32_t *issued,
-                  double *share, double *bl, double *fx, uint16_t *nocand, hipStream_t s) {
-  const BlameArgs a = blame_args(p, counts, issued, share, bl, fx, nocand);
+                  double *share, double *ec, double *bl, double *fx, uint16_t *nocand,
+                  hipStream_t s) {
+  const BlameArgs a = blame_args(p, counts, issued, share, ec, bl, fx, nocand);
   const unsigned g = grid_for(p.n_instr, kBlameThreads, 8192);
   const unsigned gd = grid_for(p.n_instr, kWave * kTileWaves, 8192);
   if (p.n_blamable <= 4)
@@ -422,11 +435,12 @@ void run_blame_batch(const gpa_program *const *progs, gpa_blame *const *b, uint3
     const gpa_program &p = *progs[k];
     const uint32_t n = p.n_instr;
     sh.carve(b[k]->share, p.n_edges * p.n_blamable * 2);
+    sh.carve(b[k]->ec, p.n_edges);
     sh.carve(b[k]->bl, (size_t)n * p.n_blamable * 2);
     sh.carve(b[k]->fx, (size_t)n * kBlameFx);
     sh.carve(b[k]->nocand, n);
-    args[k] = blame_args(p, b[k]->counts.p, b[k]->issued.p, b[k]->share.p, b[k]->bl.p, b[k]->fx.p,
-                         b[k]->nocand.p);
+    args[k] = blame_args(p, b[k]->counts.p, b[k]->issued.p, b[k]->share.p, b[k]->ec.p, b[k]->bl.p,
+                         b[k]->fx.p, b[k]->nocand.p);
     tiles[k] = (n + kBlameThreads - 1) / kBlameThreads;
     dst_groups[k] = (n + kWave * kTileWaves - 1) / (kWave * kTileWaves);
   }

@@ -271,6 +271,9 @@ struct gpa_blame {
   gpa::DBuf<uint32_t> issued;          // [n_instr] issued samples (SELECTED, both latency bits)
   gpa::DBuf<unsigned long long> dtotals;
   gpa::DBuf<double> share;             // [n_edges*n_blamable*2]
+  // [n_edges] each edge's latency samples of global-memory and execution
+  // dependencies (its Loop Unrolling and Code Reordering contribution)
+  gpa::DBuf<double> ec;
   // compact per-instruction results (the full tables are expanded on request)
   gpa::DBuf<double> bl;                // [n_instr*n_blamable*2] blamed, blamable reasons
   gpa::DBuf<double> fx;                // [n_instr*kBlameFx] WAR / other / rest splits
@@ -492,8 +495,10 @@ void build_scope_targets(gpa_program &p, hipStream_t s, Arena &ar);
 // blame.hip: run_blame allocates the blame handle's tables and calls
 // launch_blame, which writes caller-given device arrays and allocates nothing
 void run_blame(const gpa_program &p, gpa_blame &b, hipStream_t s, Arena &ar);
+// (ec may be NULL: the edges' estimator contributions are then not written)
 void launch_blame(const gpa_program &p, const uint32_t *counts, const uint32_t *issued,
-                  double *share, double *bl, double *fx, uint16_t *nocand, hipStream_t s);
+                  double *share, double *ec, double *bl, double *fx, uint16_t *nocand,
+                  hipStream_t s);
 // the full tables of the C-ABI (blamed, self_: [n_instr*24]; fine:
 // [n_instr*GPA_N_FINE*2]; any may be NULL) from the compact ones, on s
 void expand_blame_tables(const gpa_program &p, const uint32_t *counts, const double *bl,

@@ -38,9 +38,9 @@ struct EstArgs {
   int32_t s_mem, s_exec, s_sync;   // slots of these reasons among the blamable ones, or -1
   uint64_t n_edges;
   const uint32_t *counts;
-  const double *bl, *share;
+  const double *bl, *ec;
   const uint16_t *nocand;
-  const uint8_t *op_class, *tags, *e_cls;
+  const uint8_t *op_class, *tags;
   const uint32_t *e_src, *line_ptr, *line_perm, *icl_ptr, *icl_perm, *lca_ptr, *lca_perm;
   const uint32_t *scope_end, *scope_parent, *root_of, *roots;
   const uint32_t *big_list, *big_n, *big_chunk;   // 4 groupings x ns
@@ -109,13 +109,10 @@ __device__ __forceinline__ void line_value(const EstArgs &a, uint64_t kk, double
 
 // latency samples of global-memory and execution dependency stalls carried
 // by an edge (Loop Unrolling and Code Reordering)
-__device__ __forceinline__ double edge_contrib(const EstArgs &a, uint64_t e) {
-  double v = 0.0;
-  if (a.s_mem >= 0 && a.e_cls[e] == GPA_OP_GLOBAL_LOAD)
-    v += a.share[(e * a.nbl + a.s_mem) * 2 + 1];
-  if (a.s_exec >= 0) v += a.share[(e * a.nbl + a.s_exec) * 2 + 1];
-  return v;
-}
+// (written by the blamer with the shares: the latency-bit share of an
+// execution dependency plus, from a global load, that of a memory
+// dependency; two non-negative terms, so their order does not matter)
+__device__ __forceinline__ double edge_contrib(const EstArgs &a, uint64_t e) { return a.ec[e]; }
 
 // Segmented sums over contiguous ranges [begin(l), end(l)) of the four
 // groupings g: 0 instructions by line (W = 11, into own), 1 edges by common
@@ -631,9 +628,8 @@ static EstArgs est_args(const gpa_program &p, const gpa_blame &b, gpa_advice &ad
   a.counts = b.counts.p;
   a.bl = b.bl.p;
   a.nocand = b.nocand.p;
-  a.share = b.share.p;
+  a.ec = b.ec.p;
   a.op_class = p.op_class.p;
-  a.e_cls = p.e_cls.p;
   a.tags = p.instr_tags.p;
   a.e_src = p.e_src.p;
   a.line_ptr = p.line_ptr;

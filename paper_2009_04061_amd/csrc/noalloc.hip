@@ -88,7 +88,7 @@ gpa_status gpa_attribute_noalloc(const gpa_program *p, const gpa_sample *samples
     double *bl = ar.get<double>(ni * p->n_blamable * 2);
     double *fx = ar.get<double>(ni * kBlameFx);
     uint16_t *nocand = ar.get<uint16_t>(ni);
-    launch_blame(*p, counts, issued, share, bl, fx, nocand, s);
+    launch_blame(*p, counts, issued, share, nullptr, bl, fx, nocand, s);
     expand_blame_tables(*p, counts, bl, fx, nocand, blamed, self_, fine, s);
   } catch (const Error &e) {
     return e.code;

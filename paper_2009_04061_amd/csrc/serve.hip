@@ -31,7 +31,7 @@ uint64_t request_device_bytes(const gpa_program &p, uint64_t n, bool host_record
          : 0;
   if (p.n_instr > hist_hot_max_pcs()) b += 8 * n + 16 * n;   // the partition path's payloads
   b += 100 * ni + 32;                                         // counts, issued, totals
-  b += 16 * ne * p.n_blamable + ni * (16 * p.n_blamable + 8 * kBlameFx + 2);   // shares, tables
+  b += 16 * ne * p.n_blamable + 8 * ne + ni * (16 * p.n_blamable + 8 * kBlameFx + 2);   // shares, tables
   b += 88 * ni + 2 * 88 * ns + 16 * ne;                       // advise scratch
   b += 88 * ns * 2 + 8 * (uint64_t)p.tk_chunks * 16 * 2;      // chunk partials, top-k candidates
   b += 8 * ns * 23 + 16 * 16 * (uint64_t)p.n_roots;           // advice outputs
