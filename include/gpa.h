@@ -334,7 +334,8 @@ void gpa_batch_free(gpa_blame *const *blames, gpa_advice *const *advices, uint32
  * instructions or inputs whose scratch would exceed the fixed size.  The
  * scratch of a program of at most 3,072 instructions does not grow with the
  * records (at most 76 MB); a larger program's takes about 8 bytes per record
- * plus at most 16 MB (some 23M records). */
+ * plus 13 MB to 26 MB with the program's size (some 23M records for a
+ * program of 3,073 instructions, 21M for one of 2^17). */
 uint64_t gpa_noalloc_scratch_bytes(void);
 gpa_status gpa_attribute_noalloc(const gpa_program *p, const gpa_sample *samples, uint64_t n,
                                  void *stream, uint32_t *counts, uint64_t *totals, double *share,
