@@ -400,17 +400,20 @@ def serving(torch, gpa, dev, seconds, rate, budget, seed=4, n_programs=2000, poo
                 t = sv.submit(P[p], rec)
                 pend[t] = (time.perf_counter(), rec.numel() // 8)
                 i += 1
-            for t in list(pend):
-                res = sv.poll(t)
-                if res is None:
-                    continue
-                A, _ = res
-                A.topk(5)
-                t_sub, n = pend.pop(t)
-                lat.append(time.perf_counter() - t_sub)
-                n_rec += n
-                A.close()
-            time.sleep(0.0001)
+            # block until a request finishes or the next one arrives
+            due = (arrive[i] - (time.perf_counter() - t_start)) if i < len(arrive) else 1.0
+            if not pend:
+                time.sleep(max(due, 0.0))
+                continue
+            t = sv.wait(max(due, 0.0))
+            if t is None or t not in pend:
+                continue
+            A, _ = sv.poll(t)
+            A.topk(5)
+            t_sub, n = pend.pop(t)
+            lat.append(time.perf_counter() - t_sub)
+            n_rec += n
+            A.close()
         el = time.perf_counter() - t_start
         st = sv.stats()
         sv.close()
@@ -423,13 +426,13 @@ def serving(torch, gpa, dev, seconds, rate, budget, seed=4, n_programs=2000, poo
         n_rec = sum(reqs[k % len(reqs)][1].numel() // 8 for k in range(count))
         left = set(ts)
         while left:
-            for t in list(left):
-                res = sv.poll(t)
-                if res is not None:
-                    res[0].topk(5)
-                    res[0].close()
-                    left.discard(t)
-            time.sleep(0.0001)
+            t = sv.wait(60.0)
+            if t is None or t not in left:
+                continue
+            A, _ = sv.poll(t)
+            A.topk(5)
+            A.close()
+            left.discard(t)
         el = time.perf_counter() - t0
         st = sv.stats()
         sv.close()

@@ -371,6 +371,12 @@ gpa_status gpa_advise_batch(const gpa_blame *const *blames, uint32_t count, void
  *   blame handle; otherwise the blame is freed), or the request's failure
  *   status with its message in gpa_last_error; the ticket is forgotten
  *   after that.  GPA_E_INVALID for an unknown ticket.
+ * gpa_server_wait: blocks until a request has finished that no wait has
+ *   returned yet and no poll has collected, then returns GPA_OK with its
+ *   ticket (finished requests come back in the order they finished; poll
+ *   then collects the results without waiting); GPA_E_BUSY when none
+ *   finishes within timeout_us microseconds.  For callers that would
+ *   otherwise poll in a loop: the caller wakes when a batch completes.
  * gpa_server_free: waits for every submitted request to finish, frees the
  *   results nobody polled and stops the worker. */
 typedef struct gpa_server gpa_server;
@@ -385,6 +391,7 @@ gpa_status gpa_server_submit(gpa_server *server, gpa_program *p, const gpa_sampl
                              uint64_t n, int samples_on_device, uint64_t *ticket);
 gpa_status gpa_server_poll(gpa_server *server, uint64_t ticket, gpa_blame **blame,
                            gpa_advice **advice);
+gpa_status gpa_server_wait(gpa_server *server, uint64_t timeout_us, uint64_t *ticket);
 gpa_status gpa_server_stats_get(gpa_server *server, gpa_server_stats *stats);
 void gpa_server_free(gpa_server *server);
 

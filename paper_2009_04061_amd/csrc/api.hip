@@ -392,6 +392,14 @@ void enqueue_attribute_batch(gpa_program *const *progs, const gpa_sample *const 
 
 }  // namespace gpa
 
+void *gpa_blame::operator new(size_t n) {
+  if (n != sizeof(gpa_blame)) return ::operator new(n);
+  return gpa::handle_alloc<sizeof(gpa_blame)>();
+}
+void gpa_blame::operator delete(void *p, size_t n) {
+  if (n != sizeof(gpa_blame)) ::operator delete(p);
+  else gpa::handle_free<sizeof(gpa_blame)>(p);
+}
 gpa_blame::gpa_blame(const gpa_program *p) : prog(p) { gpa::program_retain(p); }
 gpa_blame::~gpa_blame() {
   // the buffers go back to the pool before the program can go
@@ -405,6 +413,14 @@ gpa_blame::~gpa_blame() {
   nocand.release();
   shared.reset();
   gpa::program_release(prog);
+}
+void *gpa_advice::operator new(size_t n) {
+  if (n != sizeof(gpa_advice)) return ::operator new(n);
+  return gpa::handle_alloc<sizeof(gpa_advice)>();
+}
+void gpa_advice::operator delete(void *p, size_t n) {
+  if (n != sizeof(gpa_advice)) ::operator delete(p);
+  else gpa::handle_free<sizeof(gpa_advice)>(p);
 }
 gpa_advice::gpa_advice(const gpa_program *p) : prog(p) { gpa::program_retain(p); }
 gpa_advice::~gpa_advice() {

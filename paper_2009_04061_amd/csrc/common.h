@@ -263,7 +263,45 @@ struct gpa_program {
   hipStream_t stream = nullptr;
 };
 
+namespace gpa {
+// Blame and advice handles come from a small per-thread cache of fixed-size
+// blocks: a batched call makes and frees hundreds of them, and the heap's
+// small allocations cost more host time than the call's launches.  A block
+// freed on another thread joins that thread's cache; each cache keeps at
+// most kHandleCache blocks and returns them to the heap when its thread
+// ends.
+constexpr size_t kHandleCache = 8192;
+template <size_t Size>
+struct HandleCache {
+  std::vector<void *> free;
+  ~HandleCache() {
+    for (void *p : free) ::operator delete(p);
+  }
+  static HandleCache &mine() {
+    thread_local HandleCache c;
+    return c;
+  }
+};
+template <size_t Size>
+void *handle_alloc() {
+  HandleCache<Size> &c = HandleCache<Size>::mine();
+  if (c.free.empty()) return ::operator new(Size);
+  void *p = c.free.back();
+  c.free.pop_back();
+  return p;
+}
+template <size_t Size>
+void handle_free(void *p) {
+  if (!p) return;
+  HandleCache<Size> &c = HandleCache<Size>::mine();
+  if (c.free.size() < kHandleCache) c.free.push_back(p);
+  else ::operator delete(p);
+}
+}  // namespace gpa
+
 struct gpa_blame {
+  static void *operator new(size_t n);
+  static void operator delete(void *p, size_t n);
   const gpa_program *prog = nullptr;   // holds a reference
   std::shared_ptr<gpa::SharedBlocks> shared;   // the tables' memory, when made by a batched call
   uint64_t totals[4] = {0, 0, 0, 0};
@@ -283,6 +321,8 @@ struct gpa_blame {
 };
 
 struct gpa_advice {
+  static void *operator new(size_t n);
+  static void operator delete(void *p, size_t n);
   const gpa_program *prog = nullptr;   // holds a reference
   std::shared_ptr<gpa::SharedBlocks> shared;   // the outputs' memory, when made by a batched call
   gpa::DBuf<double> active, matched, speedup, kernel_T, kernel_L, eq3;

@@ -86,6 +86,8 @@ struct gpa_server {
   std::deque<Request *> pending;
   std::vector<Batch *> inflight;
   std::unordered_map<uint64_t, Request *> live;
+  std::deque<uint64_t> done_q;            // tickets finished since the last waits, in order
+  std::condition_variable done_cv;        // signalled when done_q grows
   std::vector<hipEvent_t> free_events;
   std::vector<unsigned long long *> free_tot;   // pinned buffers of kMaxBatch * 4
   gpa_server_stats stats{};
@@ -157,8 +159,10 @@ void complete_batch(gpa_server *sv, Batch *bt, gpa_status st, const std::string 
       sv->stats.failed += 1;
     }
     sv->reserved -= r->bytes;
+    sv->done_q.push_back(r->ticket);
     gpa::program_release(r->prog);
   }
+  sv->done_cv.notify_all();
   if (bt->ar) bt->ar->work_done();
   bt->ar.reset();
   sv->free_events.push_back(bt->done);
@@ -351,6 +355,28 @@ gpa_status gpa_server_poll(gpa_server *sv, uint64_t ticket, gpa_blame **blame,
   }
   delete r;
   return st;
+}
+
+gpa_status gpa_server_wait(gpa_server *sv, uint64_t timeout_us, uint64_t *ticket) {
+  if (!sv || !ticket) {
+    set_error("gpa_server_wait: NULL argument");
+    return GPA_E_INVALID;
+  }
+  std::unique_lock<std::mutex> lk(sv->mu);
+  const auto until = std::chrono::steady_clock::now() + std::chrono::microseconds(timeout_us);
+  for (;;) {
+    // tickets already collected by a poll are skipped
+    while (!sv->done_q.empty() && !sv->live.count(sv->done_q.front())) sv->done_q.pop_front();
+    if (!sv->done_q.empty()) {
+      *ticket = sv->done_q.front();
+      sv->done_q.pop_front();
+      return GPA_OK;
+    }
+    if (sv->done_cv.wait_until(lk, until) == std::cv_status::timeout) {
+      while (!sv->done_q.empty() && !sv->live.count(sv->done_q.front())) sv->done_q.pop_front();
+      if (sv->done_q.empty()) return GPA_E_BUSY;
+    }
+  }
 }
 
 gpa_status gpa_server_stats_get(gpa_server *sv, gpa_server_stats *st) {

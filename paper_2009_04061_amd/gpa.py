@@ -92,7 +92,8 @@ EXPORTS = ["gpa_load_program", "gpa_program_free", "gpa_program_get_info", "gpa_
            "gpa_advice_get", "gpa_advice_topk", "gpa_last_error", "gpa_timing_enable",
            "gpa_timing_read", "gpa_attribute_batch",
            "gpa_advise_batch", "gpa_pool_stats", "gpa_pool_trim", "gpa_server_create",
-           "gpa_server_submit", "gpa_server_poll", "gpa_server_stats_get", "gpa_server_free",
+           "gpa_server_submit", "gpa_server_poll", "gpa_server_wait", "gpa_server_stats_get",
+           "gpa_server_free",
            "gpa_parallel_advise", "gpa_program_coverage", "gpa_blame_hotspots", "gpa_report",
            "gpa_attribute_noalloc", "gpa_noalloc_scratch_bytes", "gpa_analyze_batch",
            "gpa_batch_free"]
@@ -172,11 +173,12 @@ def lib():
         L.gpa_server_create.argtypes = [u64, pp]
         L.gpa_server_submit.argtypes = [vp, vp, vp, u64, i32, ct.POINTER(ct.c_uint64)]
         L.gpa_server_poll.argtypes = [vp, u64, pp, pp]
+        L.gpa_server_wait.argtypes = [vp, u64, ct.POINTER(ct.c_uint64)]
         L.gpa_server_stats_get.argtypes = [vp, ct.POINTER(ServerStats)]
         L.gpa_server_free.argtypes = [vp]
         L.gpa_server_free.restype = None
         for name in ("gpa_pool_stats", "gpa_pool_trim", "gpa_server_create", "gpa_server_submit",
-                     "gpa_server_poll", "gpa_server_stats_get"):
+                     "gpa_server_poll", "gpa_server_wait", "gpa_server_stats_get"):
             getattr(L, name).restype = ct.c_int32
         L.gpa_noalloc_scratch_bytes.argtypes = []
         L.gpa_noalloc_scratch_bytes.restype = u64
@@ -612,6 +614,16 @@ class Server:
         _check(st)
         blame = Blame(prog, b) if want_blame else _Detached(prog)
         return Advice(blame, a), (blame if want_blame else None)
+
+    def wait(self, timeout_s: float):
+        """gpa_server_wait: the ticket of the next finished request (its
+        results then poll without waiting), or None after timeout_s."""
+        t = ct.c_uint64()
+        st = lib().gpa_server_wait(self.handle, max(0, int(timeout_s * 1e6)), ct.byref(t))
+        if st == GPA_E_BUSY:
+            return None
+        _check(st)
+        return t.value
 
     def stats(self) -> dict:
         s = ServerStats()

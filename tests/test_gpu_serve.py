@@ -93,6 +93,37 @@ def test_each_result_is_the_same_alone_and_in_the_mix():
     sv.close()
 
 
+def test_wait_returns_each_finished_request_once():
+    """gpa_server_wait hands out every finished ticket once, in finishing
+    order; its results then poll at once; a ticket collected by a poll first
+    is never handed out; an idle server's wait times out."""
+    from paper_2009_04061_amd import gpa
+    progs = _programs(3, seed=2)
+    P = [gpa.Program(gpa.program_to_device(p)) for p in progs]
+    sv = gpa.Server(64 << 30)
+    assert sv.wait(0.001) is None
+    recs = [S.gen_samples(20_000 + 3_000 * r, len(progs[r % 3]["op_class"]), 1.1,
+                          S.stall_mix_small(), seed=3000 + r) for r in range(12)]
+    tickets = [sv.submit(P[r % 3], rec) for r, rec in enumerate(recs)]
+    seen = []
+    while len(seen) < len(tickets):
+        t = sv.wait(60.0)
+        assert t is not None, "no request finished within a minute"
+        seen.append(t)
+        r = sv.poll(t)
+        assert r is not None, "a waited-for ticket did not poll at once"
+        r[0].close()
+    assert sorted(seen) == sorted(tickets)
+    assert sv.wait(0.001) is None
+    # collected by polling, never handed out by a wait
+    t = sv.submit(P[0], recs[0])
+    done = _wait(sv, [t])
+    done[t][0].close()
+    done[t][1].close()
+    assert sv.wait(0.01) is None
+    sv.close()
+
+
 def test_tiny_budget_queues_requests_and_refuses_oversize_ones():
     from paper_2009_04061_amd import gpa
     progs = _programs(3, seed=1)
