@@ -16,6 +16,7 @@ import numpy as np
 RTOL_FP = 1e-12
 RTOL_SUM = 1e-10
 TOL_SPEEDUP = 1e-9
+N_STALLS, N_OP_CLASSES = 12, 13
 
 
 def run_gpu(prog: dict, rec: np.ndarray, device_inputs: bool = True, k: int = 5):
@@ -37,6 +38,21 @@ def run_gpu(prog: dict, rec: np.ndarray, device_inputs: bool = True, k: int = 5)
     B.close()
     P.close()
     return out
+
+
+def with_blamable(prog, mask, seed):
+    """The program with another architecture's blamable set: each reason
+    newly blamable allows a random set of opcode classes (one allows none,
+    so its samples find no candidate)."""
+    p = dict(prog)
+    al = np.array(prog["allowed"], np.uint16).copy()
+    rng = np.random.default_rng([seed, mask])
+    fresh = [r for r in range(N_STALLS) if (mask >> r) & 1 and not (prog["blamable"] >> r) & 1]
+    for i, r in enumerate(fresh):
+        al[r] = 0 if i == 0 else int(rng.integers(1, 1 << N_OP_CLASSES))
+    p["allowed"] = al
+    p["blamable"] = mask
+    return p
 
 
 def _close(a, b, rtol, what):

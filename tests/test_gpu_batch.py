@@ -10,7 +10,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2009_04061_amd import synth as S
-from parity import compare
+from parity import compare, with_blamable
 
 pytestmark = pytest.mark.gpu
 
@@ -90,6 +90,18 @@ def test_small_mixed_batch_equals_per_profile_and_oracle():
         recs.append(S.corrupt_samples(rec, 0.01, n, seed=seed) if seed % 3 == 0 else rec)
     progs.append(progs[4])
     recs.append(S.gen_samples(90_000, len(progs[4]["op_class"]), 1.2, S.stall_mix_small(), seed=99))
+    assert _run_both(progs, recs, oracle_every=1) == len(progs)
+
+
+def test_batch_of_mixed_blamable_sets():
+    """Profiles whose architectures blame none, one, three and eleven
+    reasons: the batch takes the twelve-slot blamer for all of them and
+    must give what the four-slot one gives each profile alone."""
+    progs, recs = [], []
+    for i, mask in enumerate([None, 0, 1 << S.ST_SYNC, 0xFFE]):
+        prog, rec = S.workload_small(seed=20 + i, n_samples=50_000)
+        progs.append(prog if mask is None else with_blamable(prog, mask, seed=i))
+        recs.append(rec)
     assert _run_both(progs, recs, oracle_every=1) == len(progs)
 
 

@@ -7,7 +7,7 @@ import brute as B
 from asm import assemble, samples
 from oracle import oracle as O
 from paper_2009_04061_amd import synth as S
-from parity import compare, run_gpu
+from parity import compare, run_gpu, with_blamable
 
 pytestmark = pytest.mark.gpu
 
@@ -142,6 +142,16 @@ def test_high_in_and_out_degree(k):
     assert np.bincount(a["src"], minlength=n).max() == k + 1
     rec = S.gen_samples(50_000, n, 0.5, S.stall_mix_small(), seed=k)
     _both(prog, rec)
+
+
+# no blamable reason; one (the four-slot kernels); eleven and all twelve
+# (the twelve-slot kernels, with the issued reason itself blamable)
+@pytest.mark.parametrize("mask", [0, 1 << S.ST_SYNC, 0xFFE, 0xFFF])
+def test_blamable_sets_of_other_architectures(mask):
+    prog, rec = S.workload_small(seed=5, n_samples=80_000)
+    p = with_blamable(prog, mask, seed=5)
+    g, _ = _both(p, rec)
+    assert g["info"]["n_blamable"] == bin(mask).count("1")
 
 
 def test_deterministic_bitwise():
