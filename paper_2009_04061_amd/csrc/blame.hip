@@ -67,6 +67,9 @@ constexpr int kBlameThreads = 128;
 //   consecutive edges).
 // Reasons are unrolled, so the per-reason sums stay in registers.
 constexpr uint32_t kTileWaves = 4;   // tiles (waves) per workgroup
+// destinations per wave tile on the one-profile path and in a batch
+constexpr uint32_t kDstTileOne = 16;
+constexpr uint32_t kDstTileBatch = 32;
 
 struct EdgeW {
   double wi, wp;    // issued / length, 1 / length
@@ -93,14 +96,17 @@ __device__ __forceinline__ EdgeW blame_edge(const BlameArgs &a, uint32_t e0, uin
 }
 
 // NB: blamable reasons the kernel keeps sums for (the arch's blamable set
-// has at most NB reasons; slot s is the s-th blamable reason ascending)
-template <bool BATCH, int NB>
+// has at most NB reasons; slot s is the s-th blamable reason ascending);
+// TW: destinations per wave tile (at most kWave; the owners are lanes
+// [0, TW), every lane takes edges)
+template <bool BATCH, int NB, uint32_t TW>
 __global__ void __launch_bounds__(kWave * kTileWaves)
 k_blame_dst(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *__restrict__ items) {
+  static_assert(TW >= 1 && TW <= kWave, "tile width");
   const BlameArgs &a = BATCH ? many[items[blockIdx.x].entry] : one;
   const uint32_t lane = threadIdx.x % kWave;
   const uint32_t n = a.n_instr, nbl = a.nbl;
-  const uint32_t n_tiles = (n + kWave - 1) / kWave;
+  const uint32_t n_tiles = (n + TW - 1) / TW;
   // a batched workgroup takes its kTileWaves tiles once; otherwise a grid
   // stride over the tiles
   const uint32_t t0 = (BATCH ? items[blockIdx.x].local : blockIdx.x) * kTileWaves +
@@ -121,10 +127,10 @@ k_blame_dst(BlameArgs one, const BlameArgs *__restrict__ many, const WorkItem *_
     }
   }
   for (uint32_t t = t0; t < n_tiles; t += t_step) {
-    const uint32_t d0 = t * kWave, j = d0 + lane;
-    const bool own = j < n;
+    const uint32_t d0 = t * TW, j = d0 + lane;
+    const bool own = lane < TW && j < n;
     const uint32_t e0 = own ? a.in_ptr[j] : 0u, e1 = own ? a.in_ptr[j + 1] : 0u;
-    const uint32_t E0 = a.in_ptr[d0], E1 = a.in_ptr[min(d0 + kWave, n)];
+    const uint32_t E0 = a.in_ptr[d0], E1 = a.in_ptr[min(d0 + TW, n)];
     double Wi[NB], Wp[NB];
     bool any[NB];
 #pragma unroll
@@ -400,13 +406,14 @@ void launch_blame(const gpa_program &p, const uint32_t *counts, const uint32_t *
                   hipStream_t s) {
   const BlameArgs a = blame_args(p, counts, issued, share, ec, bl, fx, nocand);
   const unsigned g = grid_for(p.n_instr, kBlameThreads, 8192);
-  const unsigned gd = grid_for(p.n_instr, kWave * kTileWaves, 8192);
+  const unsigned gd = grid_for((p.n_instr + kDstTileOne - 1) / kDstTileOne, kTileWaves, 8192);
+  const dim3 bd(kWave * kTileWaves);
   if (p.n_blamable <= 4)
-    hipLaunchKernelGGL((k_blame_dst<false, 4>), dim3(gd), dim3(kWave * kTileWaves), 0, s, a,
-                       nullptr, nullptr);
+    hipLaunchKernelGGL((k_blame_dst<false, 4, kDstTileOne>), dim3(gd), bd, 0, s, a, nullptr,
+                       nullptr);
   else
-    hipLaunchKernelGGL((k_blame_dst<false, 12>), dim3(gd), dim3(kWave * kTileWaves), 0, s, a,
-                       nullptr, nullptr);
+    hipLaunchKernelGGL((k_blame_dst<false, 12, kDstTileOne>), dim3(gd), bd, 0, s, a, nullptr,
+                       nullptr);
   GPA_LAUNCH_CHECK();
   if (p.n_blamable <= 4)
     hipLaunchKernelGGL((k_blame_src<false, 4>), dim3(g), dim3(kBlameThreads), 0, s, a, nullptr,
@@ -442,7 +449,7 @@ void run_blame_batch(const gpa_program *const *progs, gpa_blame *const *b, uint3
     args[k] = blame_args(p, b[k]->counts.p, b[k]->issued.p, b[k]->share.p, b[k]->ec.p, b[k]->bl.p,
                          b[k]->fx.p, b[k]->nocand.p);
     tiles[k] = (n + kBlameThreads - 1) / kBlameThreads;
-    dst_groups[k] = (n + kWave * kTileWaves - 1) / (kWave * kTileWaves);
+    dst_groups[k] = ((n + kDstTileBatch - 1) / kDstTileBatch + kTileWaves - 1) / kTileWaves;
   }
   BatchPlan plan(count);
   const uint32_t q = plan.add(tiles), qd = plan.add(dst_groups);
@@ -457,12 +464,13 @@ void run_blame_batch(const gpa_program *const *progs, gpa_blame *const *b, uint3
   uint32_t max_nbl = 0;
   for (uint32_t k = 0; k < count; ++k) max_nbl = std::max(max_nbl, progs[k]->n_blamable);
   const unsigned gd = plan.blocks(qd);
+  const dim3 bd(kWave * kTileWaves);
   if (max_nbl <= 4)
-    hipLaunchKernelGGL((k_blame_dst<true, 4>), dim3(gd), dim3(kWave * kTileWaves), 0, s, none,
-                       d_args, plan.items(qd));
+    hipLaunchKernelGGL((k_blame_dst<true, 4, kDstTileBatch>), dim3(gd), bd, 0, s, none, d_args,
+                       plan.items(qd));
   else
-    hipLaunchKernelGGL((k_blame_dst<true, 12>), dim3(gd), dim3(kWave * kTileWaves), 0, s, none,
-                       d_args, plan.items(qd));
+    hipLaunchKernelGGL((k_blame_dst<true, 12, kDstTileBatch>), dim3(gd), bd, 0, s, none, d_args,
+                       plan.items(qd));
   GPA_LAUNCH_CHECK();
   if (max_nbl <= 4)
     hipLaunchKernelGGL((k_blame_src<true, 4>), dim3(g), dim3(kBlameThreads), 0, s, none, d_args,

@@ -25,6 +25,9 @@ namespace gpa {
 
 constexpr int kNV = 11;  // 9 optimizers, active, total
 constexpr int kEstThreads = 256;
+// scopes per wave tile of the line sums on the one-profile path (a batch
+// takes 64)
+constexpr uint32_t kLineTileOne = 16;
 
 struct Cand {
   double s;
@@ -252,30 +255,31 @@ k_seg_small(EstArgs one, const EstArgs *__restrict__ many, const WorkItem *__res
 }
 
 // Grouping 0 (instructions by line), segments of at most kSmallSeg
-// elements: one wave per tile of 64 consecutive scopes (lane l owns scope
-// l0 + l).  The tile's elements are contiguous in the line-grouped order and
+// elements: one wave per tile of TW <= 64 consecutive scopes (lane l < TW
+// owns scope l0 + l).  The tile's elements are contiguous in the line-grouped order and
 // are computed 64 at a time by all lanes (their count rows read coalesced);
 // each owner then adds its own elements, taken across lanes, in element
 // order: the same additions in the same order as a loop over them.  (The
 // elements of the longer segments, summed by k_seg_chunks, are computed
 // here too and not used; lines that long are rare.)
-template <bool BATCH>
+template <bool BATCH, uint32_t TW>
 __global__ void __launch_bounds__(kEstThreads)
 k_line_tiles(EstArgs one, const EstArgs *__restrict__ many, const WorkItem *__restrict__ items) {
+  static_assert(TW >= 1 && TW <= kWave, "tile width");
   constexpr uint32_t kWaves = kEstThreads / kWave;
   const EstArgs &a = BATCH ? many[items[blockIdx.x].entry] : one;
   const uint32_t lane = threadIdx.x % kWave;
-  const uint32_t ns = a.ns, n_tiles = (ns + kWave - 1) / kWave;
+  const uint32_t ns = a.ns, n_tiles = (ns + TW - 1) / TW;
   const uint32_t t0 = (BATCH ? items[blockIdx.x].local : blockIdx.x) * kWaves +
                       threadIdx.x / kWave;
   const uint32_t t_step = BATCH ? n_tiles : gridDim.x * kWaves;
   const SegView S = seg_view<0>(a);
   for (uint32_t t = t0; t < n_tiles; t += t_step) {
-    const uint32_t l0 = t * kWave, l = l0 + lane;
-    const bool own = l < ns;
+    const uint32_t l0 = t * TW, l = l0 + lane;
+    const bool own = lane < TW && l < ns;
     const uint32_t b0 = own ? S.ptr[l] : 0u, b1 = own ? S.ptr[l + 1] : 0u;
     const bool mine = own && b1 - b0 <= kSmallSeg;
-    const uint32_t P0 = S.ptr[l0], P1 = S.ptr[min(l0 + kWave, ns)];
+    const uint32_t P0 = S.ptr[l0], P1 = S.ptr[min(l0 + TW, ns)];
     double v[kNV];
 #pragma unroll
     for (int q = 0; q < kNV; ++q) v[q] = 0.0;
@@ -703,7 +707,8 @@ void run_estimate(const gpa_program &p, const gpa_blame &b, gpa_advice &adv, uin
   const unsigned gs = grid_for(ns, kEstThreads, 8192);
   auto chunks = [](uint32_t c) { return (unsigned)std::min<uint32_t>(c, 4096); };
   auto combine = [&](uint32_t c) { return c ? grid_for(c, kEstThreads, 1024) : 0u; };
-  L(k_line_tiles<false>, gs, 1, nullptr);
+  L(k_line_tiles<false, kLineTileOne>,
+    grid_for((ns + kLineTileOne - 1) / kLineTileOne, kEstThreads / kWave, 8192), 1, nullptr);
   L(k_seg_chunks<kNV, 0, 1, false>, chunks(a.seg_chunks[0]), 1, nullptr);
   L(k_seg_combine<kNV, 0, 1, false>, combine(a.seg_chunks[0]), 1, nullptr);
   L(k_seg_small<1, 1, 2, false>, gs, 2, nullptr);
@@ -768,7 +773,7 @@ void run_estimate_batch(const gpa_blame *const *b, gpa_advice *const *adv, uint3
   EstLaunch L{s, EstArgs{}, up.ptr<EstArgs>(i_args)};
   auto run = [&](auto kern, uint32_t q, unsigned gy) { L(kern, plan.blocks(q), gy, plan.items(q)); };
   if (t) t->begin(kPhaseAdvise, s);
-  run(k_line_tiles<true>, q_scope, 1);
+  run(k_line_tiles<true, kWave>, q_scope, 1);
   run(k_seg_chunks<kNV, 0, 1, true>, q_ch[0], 1);
   run(k_seg_combine<kNV, 0, 1, true>, q_cb[0], 1);
   run(k_seg_small<1, 1, 2, true>, q_scope, 2);
