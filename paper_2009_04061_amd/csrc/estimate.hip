@@ -409,8 +409,9 @@ k_speedup(EstArgs one, const EstArgs *__restrict__ many, const WorkItem *__restr
 // ------------------------------------------------------------------ top-k
 // Two stages: a workgroup takes kTopChunk of one kernel's (scope, optimizer)
 // items, 8 per thread kept sorted in registers, and picks its best 16 in 16
-// rounds, each round selecting the best head over the workgroup (wave
-// shuffles, then one exchange of the 4 wave winners in LDS) and popping it
+// rounds, each round selecting the best head over the workgroup (DPP moves
+// within rows and lane reads across them, then one exchange of the 4 wave
+// winners in LDS) and popping it
 // from its owner; one workgroup per kernel then does the same over its
 // chunks' winners, carrying the best 16 across rounds of kTopChunk.  Order:
 // speedup descending, then optimizer, then scope ascending (a total order,
@@ -467,6 +468,57 @@ __device__ __forceinline__ void sort8(Cand (&a)[kPerThread]) {
       }
 }
 
+// c becomes the better of itself and the candidate that DPP control CTRL
+// brings from another lane of its row of 16 (every lane of the wave active)
+template <int CTRL>
+__device__ __forceinline__ void take_dpp(Cand &c) {
+  const uint64_t sb = (uint64_t)__double_as_longlong(c.s);
+  const uint32_t lo =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)sb, CTRL, 0xF, 0xF, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(sb >> 32), CTRL, 0xF, 0xF, false);
+  Cand o;
+  o.s = __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+  o.o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c.o, CTRL, 0xF, 0xF, false);
+  o.l = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c.l, CTRL, 0xF, 0xF, false);
+  const bool take = better(o, c);
+  c.s = take ? o.s : c.s;
+  c.o = take ? o.o : c.o;
+  c.l = take ? o.l : c.l;
+}
+
+__device__ __forceinline__ Cand lane_cand(const Cand &c, int lane) {
+  const uint64_t sb = (uint64_t)__double_as_longlong(c.s);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sb, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(sb >> 32), lane);
+  Cand r;
+  r.s = __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+  r.o = (uint32_t)__builtin_amdgcn_readlane((int)c.o, lane);
+  r.l = (uint32_t)__builtin_amdgcn_readlane((int)c.l, lane);
+  return r;
+}
+
+// the best of the wave's candidates, the same in every lane: within each row
+// of 16 lanes by exchanges with the lane at xor 1, xor 2, the mirror in 8 and
+// the mirror in 16 (after which every lane of a row holds the row's best),
+// then the four rows' winners read from lanes 0, 16, 32, 48
+__device__ __forceinline__ Cand wave_best(Cand c) {
+  take_dpp<0xB1>(c);    // quad_perm [1, 0, 3, 2]
+  take_dpp<0x4E>(c);    // quad_perm [2, 3, 0, 1]
+  take_dpp<0x141>(c);   // row_half_mirror
+  take_dpp<0x140>(c);   // row_mirror
+  Cand b = lane_cand(c, 0);
+#pragma unroll
+  for (int r = 1; r < kWave / 16; ++r) {
+    const Cand o = lane_cand(c, 16 * r);
+    const bool take = better(o, b);
+    b.s = take ? o.s : b.s;
+    b.o = take ? o.o : b.o;
+    b.l = take ? o.l : b.l;
+  }
+  return b;
+}
+
 // the workgroup's best kTopK of the threads' sorted lists, in order, into out.
 // Real items are distinct and the order is total on them, so the round's
 // winner has one owner, found by comparing it with the heads; when the lists
@@ -475,18 +527,7 @@ __device__ __forceinline__ void sort8(Cand (&a)[kPerThread]) {
 __device__ void select_top(Cand (&my)[kPerThread], Cand *out, Cand (*xch)[kTopThreads / kWave]) {
   const unsigned tid = threadIdx.x, w = tid / kWave;
   for (int r = 0; r < kTopK; ++r) {
-    Cand c = my[0];
-#pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) {
-      Cand o;
-      o.s = __shfl_xor(c.s, d, kWave);
-      o.o = (uint32_t)__shfl_xor((int)c.o, d, kWave);
-      o.l = (uint32_t)__shfl_xor((int)c.l, d, kWave);
-      const bool take = better(o, c);
-      c.s = take ? o.s : c.s;
-      c.o = take ? o.o : c.o;
-      c.l = take ? o.l : c.l;
-    }
+    const Cand c = wave_best(my[0]);
     if (lane_id() == 0) xch[r & 1][w] = c;
     __syncthreads();
     Cand best = xch[r & 1][0];
