@@ -53,8 +53,9 @@ constexpr int kBlameThreads = 128;
   const uint32_t stride_ = BATCH ? a.n_instr : gridDim.x * blockDim.x;           \
   for (uint32_t VAR = first_; VAR < a.n_instr; VAR += stride_)
 
-// One wave per tile of 64 consecutive destinations; lane l owns destination
-// j = d0 + l.  The tile's in-edges (contiguous: edges are sorted by
+// One wave per tile of TW <= 64 consecutive destinations; lane l < TW owns
+// destination j = d0 + l (narrow tiles give one profile more waves).  The
+// tile's in-edges (contiguous: edges are sorted by
 // destination) are read 64 at a time by all lanes, coalesced, each lane one
 // edge with its source's issued samples.
 //   Pass 1: every owner takes the weights of its own edges in the chunk from
